@@ -1,0 +1,165 @@
+/*
+ * mrcm.h -- C ABI of the MI355X (gfx950) MRCM-OS hot path.
+ *
+ * The library solves single-phase Darcy flow (u = -K grad p, div u = f,
+ * p = g or u.n = z on the boundary; paper Section 2, equations eq1a-eq1d) on
+ * a uniform Cartesian grid with the oversampled Multiscale Robin Coupled
+ * Method with smoothing of Zhou, Guiraldello and Pereira (arXiv 2404.13811):
+ *
+ *   mrcm_build_basis      Algorithm 1, Steps 1-2 (+ the particular problems of
+ *                         Step 4): batched local factorisations on the
+ *                         oversampled boxes and on the subdomains, the seed
+ *                         solves that define the informed spaces (equation
+ *                         informed_space) and the multiscale basis functions.
+ *   mrcm_solve_interface  Steps 3-5: interface system (equations int_ujump,
+ *                         int_pjump) assembled on the device, solved in FP64
+ *                         on the device, MRCM-O solution assembled.
+ *   mrcm_smooth           Steps 6-7 / Section 3: colored Robin re-solves on
+ *                         the oversampled boxes with cached factors.
+ *   mrcm_get_pressure / mrcm_get_flux   outputs.
+ *
+ * Conventions
+ *   - Cells are numbered x fastest; axis 0 = x.  A grid has ncell[0..dim-1]
+ *     cells of size h (cubic).  Domain sides are 0..2*dim-1 =
+ *     (-x, +x, -y, +y, -z, +z); boundary values of side s are given per face
+ *     in the x-fastest order of the cells that touch that side.
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *     tensor's data_ptr) owned by the caller, FP64, contiguous.  Inputs are
+ *     copied into library workspace during the call, so the caller may free
+ *     or reuse them afterwards.  Outputs are written by work enqueued on the
+ *     context's stream; synchronise that stream before reading them.
+ *   - The library owns all workspace (factors, basis functions, interface
+ *     system); it is released by mrcm_destroy.
+ *   - Every function returns an mrcm_status and never aborts; on failure
+ *     mrcm_last_error() holds a human-readable message.
+ *   - Call order: create -> set_* -> build_basis -> solve_interface ->
+ *     smooth* -> get_*.  A set_* call after build_basis invalidates the
+ *     basis; a call made too early returns MRCM_ESTATE.
+ *   - One context per stream; contexts share no state.  Calls on one context
+ *     must not overlap in time (not thread-safe per context).
+ */
+#ifndef MRCM_H
+#define MRCM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrcm_ctx mrcm_ctx;
+
+typedef enum {
+  MRCM_OK = 0,
+  MRCM_EINVAL = 1,     /* bad argument (null pointer, bad size, K <= 0, ...)  */
+  MRCM_ENOMEM = 2,     /* device allocation failed                            */
+  MRCM_EDEVICE = 3,    /* a HIP call or kernel launch failed                  */
+  MRCM_ESTATE = 4,     /* call out of order                                   */
+  MRCM_ENOTPD = 5,     /* a local factorisation met a non-positive pivot      */
+  MRCM_ENOCONV = 6,    /* iterative refinement did not reach its tolerance    */
+  MRCM_EINCOMPAT = 7,  /* pure-Neumann problem with non-zero net source       */
+  MRCM_ESINGULAR = 8   /* interface system singular (zero pivot)              */
+} mrcm_status;
+
+/* Interface spaces M_H = V_H and seed family of Lambda_H^i (paper Section 2:
+ * piecewise constant or piecewise linear per coarse interface).  FINE uses
+ * one indicator per fine face (the setting of Proposition 2); it exists to
+ * test the path against the fine-grid solution. */
+typedef enum { MRCM_SPACE_CONST = 0, MRCM_SPACE_LINEAR = 1, MRCM_SPACE_FINE = 2 } mrcm_space;
+
+/* Robin parameter: ALPHA -> beta = alpha * H / K_H per face (paper, equation
+ * after genRobin; H = subdomain width along the face normal, K_H = harmonic
+ * mean of the two adjacent cells); CONST -> beta = the given value. */
+typedef enum { MRCM_BETA_ALPHA = 0, MRCM_BETA_CONST = 1 } mrcm_beta_mode;
+
+/* FP64: local factors and solves in FP64.  FP32_REFINE: local factors and
+ * solves in FP32, corrected by FP64 iterative refinement with the residual
+ * evaluated from K in FP64 until ||r|| <= tol * ||b|| per right-hand side. */
+typedef enum { MRCM_FP64 = 0, MRCM_FP32_REFINE = 1 } mrcm_precision;
+
+typedef enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 } mrcm_bc_type;
+
+typedef struct {
+  int n_subdomains;        /* m                                              */
+  int n_boxes;             /* oversampled boxes (= m)                        */
+  int n_unknowns;          /* interface unknowns sum_i dim Lambda_H^i        */
+  int band_kl, band_ku;    /* bandwidths of the interface system             */
+  int n_local_solves;      /* right-hand sides solved so far                 */
+  int refine_max_iters;    /* largest refinement count of any solve          */
+  double refine_max_resid; /* largest final ||r||/||b|| of any refined solve */
+  double ms_basis, ms_interface, ms_smooth;  /* device time of the last calls */
+  double bytes_factor;     /* bytes of cached local factors                  */
+} mrcm_stats;
+
+/* Create a context for a dim-dimensional grid (dim = 2 or 3) of
+ * ncell[0..dim-1] cells of size h.  stream: a hipStream_t (NULL = default
+ * stream) on which all work of this context is enqueued.
+ * Errors: MRCM_EINVAL (dim, ncell or h out of range, out == NULL),
+ * MRCM_EDEVICE. */
+mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_ctx** out);
+
+/* log K per cell (N values, x fastest; paper eq1a, scalar K).  Copied.
+ * Errors: MRCM_EINVAL on NULL; non-finite values are detected at
+ * mrcm_build_basis (MRCM_EINVAL). */
+mrcm_status mrcm_set_permeability(mrcm_ctx* ctx, const double* logk_dev);
+
+/* Source density f per cell (eq1b; N values) or NULL for f = 0.  Copied. */
+mrcm_status mrcm_set_source(mrcm_ctx* ctx, const double* f_dev);
+
+/* Boundary condition of domain side `side` (0..2*dim-1): pressure g (eq. for
+ * p on the pressure boundary) or outward normal velocity z (eq1d), one value
+ * per boundary face, or val_dev == NULL for zero.  Default: Neumann, z = 0. */
+mrcm_status mrcm_set_bc(mrcm_ctx* ctx, int side, mrcm_bc_type type, const double* val_dev);
+
+/* Non-overlapping partition into boxes of sub[a] cells per axis (ncell[a]
+ * must be a multiple of sub[a]) and oversampling width `overlap` cells,
+ * 0 <= overlap <= min(sub) - 1 (paper Section 2, Figure of the two
+ * partitions; oversampled boxes are clipped to the domain). */
+mrcm_status mrcm_set_partition(mrcm_ctx* ctx, const int* sub, int overlap);
+
+mrcm_status mrcm_set_interface_space(mrcm_ctx* ctx, mrcm_space space);
+
+/* Robin parameters of the basis functions and of the smoothing steps
+ * (Algorithm 1: Step 6 is needed only when they differ). Values > 0. */
+mrcm_status mrcm_set_robin(mrcm_ctx* ctx, mrcm_beta_mode mode, double mbf, double smooth);
+
+/* Precision of the local factorisations and solves.  tol > 0 and
+ * max_refine >= 0 are used by MRCM_FP32_REFINE only. */
+mrcm_status mrcm_set_precision(mrcm_ctx* ctx, mrcm_precision prec, double tol, int max_refine);
+
+/* Algorithm 1, Steps 1-2 and the particular problems of Step 4.
+ * Errors: MRCM_ESTATE (inputs missing), MRCM_EINVAL (bad K),
+ * MRCM_EINCOMPAT, MRCM_ENOTPD, MRCM_ENOCONV, MRCM_ENOMEM, MRCM_EDEVICE. */
+mrcm_status mrcm_build_basis(mrcm_ctx* ctx);
+
+/* Steps 3-5: interface system and MRCM-O solution (resets smoothing).
+ * Errors: MRCM_ESTATE, MRCM_ESINGULAR, MRCM_EDEVICE. */
+mrcm_status mrcm_solve_interface(mrcm_ctx* ctx);
+
+/* Steps 6-7: nsteps >= 0 further smoothing steps on the current solution
+ * (re-entrant: smooth(a); smooth(b) equals smooth(a + b)). */
+mrcm_status mrcm_smooth(mrcm_ctx* ctx, int nsteps);
+
+/* Pressure per cell (N values); shifted to zero mean when no side carries a
+ * pressure condition. */
+mrcm_status mrcm_get_pressure(mrcm_ctx* ctx, double* p_dev);
+
+/* Outward normal velocity on every face of every cell, N x 2*dim values,
+ * cell-major (face order -x, +x, -y, +y, -z, +z).  A face on the skeleton
+ * carries the value of the subdomain owning the cell (the normal flux is
+ * double-valued there). */
+mrcm_status mrcm_get_flux(mrcm_ctx* ctx, double* flux_dev);
+
+/* Interface unknowns X (n_unknowns values, subdomain-major, seeds of each
+ * subdomain in side order), device pointer.  For tests. */
+mrcm_status mrcm_get_coefficients(mrcm_ctx* ctx, double* x_dev);
+
+mrcm_status mrcm_get_stats(mrcm_ctx* ctx, mrcm_stats* out);
+
+/* Message of the last failure on this context (never NULL). */
+const char* mrcm_last_error(const mrcm_ctx* ctx);
+
+mrcm_status mrcm_destroy(mrcm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRCM_H */

@@ -1,0 +1,16 @@
+"""MI355X-native MRCM-OS hot path (arXiv 2404.13811).
+
+Python binding of the C ABI declared in ``include/mrcm.h``: one function per
+C entry point with the same name, marshalling torch device tensors to raw
+pointers.  Every numerical step runs in the HIP kernels of ``libmrcm.so``;
+there is no CPU path.
+"""
+from .api import (MRCMError, Context, create, set_permeability, set_source, set_bc,
+                  set_partition, set_interface_space, set_robin, set_precision, build_basis,
+                  solve_interface, smooth, get_pressure, get_flux, get_coefficients, get_stats,
+                  destroy, solve_workload, SPACE, PRECISION)
+
+__all__ = ["MRCMError", "Context", "create", "set_permeability", "set_source", "set_bc",
+           "set_partition", "set_interface_space", "set_robin", "set_precision", "build_basis",
+           "solve_interface", "smooth", "get_pressure", "get_flux", "get_coefficients",
+           "get_stats", "destroy", "solve_workload", "SPACE", "PRECISION"]

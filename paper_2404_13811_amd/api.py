@@ -1,0 +1,176 @@
+"""Thin binding of the C ABI (argument marshalling only).
+
+Arrays are torch tensors on the GPU, float64, contiguous; the library copies
+inputs and writes outputs on the current torch stream.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+SPACE = {"const": 0, "linear": 1, "fine": 2}
+PRECISION = {"fp64": 0, "fp32_refine": 1}
+BETA = {"alpha": 0, "const": 1}
+BC = {"N": 0, "D": 1}
+
+
+class MRCMError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__("%s -> %s: %s" % (fn, _lib.STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Context:
+    def __init__(self, handle, dim, ncell):
+        self.handle = handle
+        self.dim = dim
+        self.ncell = tuple(ncell)
+
+    @property
+    def ncells(self):
+        n = 1
+        for v in self.ncell:
+            n *= v
+        return n
+
+
+def _check(ctx, fn, st):
+    if st != 0:
+        lib = _lib.load()
+        msg = lib.mrcm_last_error(ctx.handle if ctx is not None else None)
+        raise MRCMError(fn, st, msg.decode() if msg else "")
+
+
+def _dev(t, n=None):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError("expected %d values, got %d" % (n, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def create(dim, ncell, h, stream=None):
+    lib = _lib.load()
+    arr = (ctypes.c_int * 3)(*(list(ncell) + [1] * (3 - len(ncell))))
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    out = ctypes.c_void_p()
+    st = lib.mrcm_create(int(dim), arr, float(h), ctypes.c_void_p(s), ctypes.byref(out))
+    if st != 0:
+        raise MRCMError("mrcm_create", st, "")
+    return Context(out, dim, ncell)
+
+
+def set_permeability(ctx, logk):
+    _check(ctx, "mrcm_set_permeability", _lib.load().mrcm_set_permeability(ctx.handle, _dev(logk, ctx.ncells)))
+
+
+def set_source(ctx, f):
+    _check(ctx, "mrcm_set_source", _lib.load().mrcm_set_source(ctx.handle, _dev(f, ctx.ncells)))
+
+
+def set_bc(ctx, side, kind, values=None):
+    k = BC[kind] if isinstance(kind, str) else int(kind)
+    _check(ctx, "mrcm_set_bc", _lib.load().mrcm_set_bc(ctx.handle, int(side), k, _dev(values)))
+
+
+def set_partition(ctx, sub, overlap):
+    arr = (ctypes.c_int * 3)(*(list(sub) + [1] * (3 - len(sub))))
+    _check(ctx, "mrcm_set_partition", _lib.load().mrcm_set_partition(ctx.handle, arr, int(overlap)))
+
+
+def set_interface_space(ctx, space):
+    s = SPACE[space] if isinstance(space, str) else int(space)
+    _check(ctx, "mrcm_set_interface_space", _lib.load().mrcm_set_interface_space(ctx.handle, s))
+
+
+def set_robin(ctx, mode, mbf, smooth_value):
+    m = BETA[mode] if isinstance(mode, str) else int(mode)
+    _check(ctx, "mrcm_set_robin", _lib.load().mrcm_set_robin(ctx.handle, m, float(mbf), float(smooth_value)))
+
+
+def set_precision(ctx, precision, tol=1e-12, max_refine=30):
+    p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    _check(ctx, "mrcm_set_precision", _lib.load().mrcm_set_precision(ctx.handle, p, float(tol), int(max_refine)))
+
+
+def build_basis(ctx):
+    _check(ctx, "mrcm_build_basis", _lib.load().mrcm_build_basis(ctx.handle))
+
+
+def solve_interface(ctx):
+    _check(ctx, "mrcm_solve_interface", _lib.load().mrcm_solve_interface(ctx.handle))
+
+
+def smooth(ctx, nsteps):
+    _check(ctx, "mrcm_smooth", _lib.load().mrcm_smooth(ctx.handle, int(nsteps)))
+
+
+def get_pressure(ctx, out=None):
+    if out is None:
+        out = torch.empty(ctx.ncells, dtype=torch.float64, device="cuda")
+    _check(ctx, "mrcm_get_pressure", _lib.load().mrcm_get_pressure(ctx.handle, _dev(out, ctx.ncells)))
+    return out
+
+
+def get_flux(ctx, out=None):
+    n = ctx.ncells * 2 * ctx.dim
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(ctx, "mrcm_get_flux", _lib.load().mrcm_get_flux(ctx.handle, _dev(out, n)))
+    return out
+
+
+def get_stats(ctx):
+    st = _lib.Stats()
+    _check(ctx, "mrcm_get_stats", _lib.load().mrcm_get_stats(ctx.handle, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def get_coefficients(ctx, out=None):
+    n = get_stats(ctx)["n_unknowns"]
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    _check(ctx, "mrcm_get_coefficients", _lib.load().mrcm_get_coefficients(ctx.handle, _dev(out)))
+    return out[:n]
+
+
+def destroy(ctx):
+    if ctx.handle:
+        _lib.load().mrcm_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def configure(ctx, wl, precision="fp64", tol=1e-12, max_refine=30):
+    """Pass a workload record (inputs.Workload) through the set_* calls."""
+    dev = "cuda"
+    set_permeability(ctx, torch.as_tensor(wl.logk.ravel(), dtype=torch.float64, device=dev).contiguous())
+    src = wl.source.ravel()
+    set_source(ctx, torch.as_tensor(src, dtype=torch.float64, device=dev).contiguous() if src.any() else None)
+    for side, (kind, vals) in enumerate(zip(wl.bc_type, wl.bc_value)):
+        set_bc(ctx, side, kind, torch.as_tensor(vals, dtype=torch.float64, device=dev).contiguous())
+    set_partition(ctx, wl.sub, wl.overlap)
+    set_interface_space(ctx, wl.space)
+    set_robin(ctx, wl.beta_mode, wl.beta_mbf, wl.beta_smooth)
+    set_precision(ctx, precision, tol, max_refine)
+
+
+def solve_workload(wl, precision="fp64", nsmooth=None, tol=1e-12, max_refine=30, keep=False):
+    """Full MRCM-OS solve of a workload; returns (pressure, flux[, ctx])."""
+    ctx = create(wl.dim, wl.ncell, wl.h)
+    try:
+        configure(ctx, wl, precision, tol, max_refine)
+        build_basis(ctx)
+        solve_interface(ctx)
+        smooth(ctx, wl.nsmooth if nsmooth is None else nsmooth)
+        p = get_pressure(ctx)
+        fl = get_flux(ctx)
+    except Exception:
+        destroy(ctx)
+        raise
+    if keep:
+        return p, fl, ctx
+    destroy(ctx)
+    return p, fl

@@ -1,0 +1,661 @@
+// Host runtime of the MRCM-OS library: context state machine, partition
+// planning (subdomains, oversampled boxes, seeds, interfaces, colors),
+// device workspace and the enqueueing of the HIP kernels.  No numerical
+// work happens on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mrcm.h"
+#include "mrcm_internal.h"
+
+using namespace mrcm;
+
+struct mrcm_ctx {
+  int d = 0;
+  int n[3] = {1, 1, 1};
+  double h = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // configuration
+  bool have_k = false, have_part = false;
+  int S[3] = {1, 1, 1};
+  int l = 0;
+  int space = MRCM_SPACE_CONST;
+  int beta_mode = MRCM_BETA_ALPHA;
+  double beta_mbf = 1.0, beta_sm = 1.0;
+  int prec = MRCM_FP64;
+  double tol = 1e-12;
+  int max_refine = 20;
+  int bc_type[6] = {0, 0, 0, 0, 0, 0};
+  int state = 0;  // 0 configured, 1 basis built, 2 solution available
+  bool plan_valid = false;
+
+  // inputs (device)
+  double* logk = nullptr;
+  double* K = nullptr;
+  double* f = nullptr;
+  bool have_f = false;
+  double* bcv = nullptr;
+  int bc_off[6] = {0, 0, 0, 0, 0, 0};
+  int nbcv = 0;
+
+  // plan
+  Geo geo{};
+  std::vector<Box> obox, pbox;
+  std::vector<Seed> seeds, basis;
+  std::vector<int> seed_off;
+  std::vector<Iface> ifc;
+  std::vector<int> members;
+  int member_off[9] = {0};
+  int nX = 0, kl = 0, ku = 0, ldab = 0;
+  long long fac_n = 0, facp_n = 0, scr_n = 0;
+
+  // device plan
+  Box* d_obox = nullptr;
+  Box* d_pbox = nullptr;
+  Seed* d_seeds = nullptr;
+  Seed* d_basis = nullptr;
+  int* d_seed_off = nullptr;
+  Iface* d_ifc = nullptr;
+  int* d_members = nullptr;
+
+  // device workspace
+  double *fac = nullptr, *facs = nullptr, *facp = nullptr, *scr = nullptr;
+  double *Pk = nullptr, *tr_u = nullptr, *tr_phi = nullptr, *tr_beta = nullptr;
+  double *pbar = nullptr, *ubar = nullptr, *pibar = nullptr;
+  double *AB = nullptr, *rhs = nullptr, *X = nullptr;
+  double *p = nullptr, *gflux = nullptr, *partial = nullptr;
+  int* flags = nullptr;
+
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timed_basis = false, timed_iface = false, timed_smooth = false;
+  int n_local_solves = 0;
+};
+
+namespace {
+
+mrcm_status fail(mrcm_ctx* c, mrcm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? MRCM_ENOMEM : MRCM_EDEVICE, "%s: %s", \
+                  #call, hipGetErrorString(e_));                                          \
+  } while (0)
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_plan(mrcm_ctx* c) {
+  dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
+  dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members);
+  dfree(c->fac); dfree(c->facs); dfree(c->facp); dfree(c->scr);
+  dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
+  dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
+  dfree(c->AB); dfree(c->rhs); dfree(c->X); dfree(c->p); dfree(c->gflux); dfree(c->partial);
+  c->plan_valid = false;
+}
+
+int side_faces(const mrcm_ctx* c, const int lo[3], const int hi[3], int a) {
+  int nf = 1;
+  for (int b = 0; b < c->d; ++b)
+    if (b != a) nf *= hi[b] - lo[b];
+  return nf;
+}
+
+void sub_coords(const mrcm_ctx* c, int i, int ic[3]) {
+  int r = i;
+  for (int a = 0; a < 3; ++a) {
+    const int Ma = a < c->d ? c->geo.M[a] : 1;
+    ic[a] = r % Ma;
+    r /= Ma;
+  }
+}
+
+int neighbor(const mrcm_ctx* c, int i, int q) {
+  const int a = q >> 1, s = q & 1;
+  int ic[3];
+  sub_coords(c, i, ic);
+  const int t = ic[a] + (s ? 1 : -1);
+  if (t < 0 || t >= c->geo.M[a]) return -1;
+  int stride = 1;
+  for (int b = 0; b < a; ++b) stride *= c->geo.M[b];
+  return i + (s ? stride : -stride);
+}
+
+// Seed family on side q of box [lo, hi) (window = Omega_i for FINE).
+void family(const mrcm_ctx* c, int q, const int lo[3], const int hi[3], const int wlo[3],
+            const int whi[3], std::vector<Seed>& out) {
+  const int a = q >> 1;
+  if (c->space == MRCM_SPACE_CONST) {
+    out.push_back(Seed{q, 0, 0, 0});
+  } else if (c->space == MRCM_SPACE_LINEAR) {
+    out.push_back(Seed{q, 0, 0, 0});
+    for (int b = 0; b < c->d; ++b)
+      if (b != a) out.push_back(Seed{q, 1, b, 0});
+  } else {
+    // faces of the side whose tangential position lies inside the window
+    const int nf = side_faces(c, lo, hi, a);
+    for (int f = 0; f < nf; ++f) {
+      int r = f;
+      bool keep = true;
+      for (int b = 0; b < c->d; ++b) {
+        if (b == a) continue;
+        const int m = hi[b] - lo[b];
+        const int x = lo[b] + r % m;
+        r /= m;
+        if (x < wlo[b] || x >= whi[b]) keep = false;
+      }
+      if (keep) out.push_back(Seed{q, 2, 0, f});
+    }
+  }
+}
+
+mrcm_status make_plan(mrcm_ctx* c) {
+  free_plan(c);
+  Geo& g = c->geo;
+  g = Geo{};
+  g.d = c->d;
+  g.l = c->l;
+  g.h = c->h;
+  g.area = std::pow(c->h, c->d - 1);
+  g.vol = std::pow(c->h, c->d);
+  g.beta_mode = c->beta_mode == MRCM_BETA_CONST ? 1 : 0;
+  g.ncells = 1;
+  g.nsub = 1;
+  g.neumann = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = a < c->d ? c->n[a] : 1;
+    g.S[a] = a < c->d ? c->S[a] : 1;
+    g.M[a] = g.n[a] / g.S[a];
+    g.ncells *= g.n[a];
+    g.nsub *= g.M[a];
+  }
+  for (int q = 0; q < 6; ++q) {
+    g.bc_type[q] = c->bc_type[q];
+    g.bc_off[q] = c->bc_off[q];
+    if (q < 2 * c->d && c->bc_type[q]) g.neumann = 0;
+  }
+  int off = 0;
+  for (int q = 0; q < 6; ++q) {
+    g.gside_off[q] = off;
+    if (q < 2 * c->d) {
+      int nf = 1;
+      for (int b = 0; b < c->d; ++b)
+        if (b != (q >> 1)) nf *= g.S[b];
+      off += nf;
+    }
+  }
+  g.gstride = off;
+  g.nfaceg = 0;
+
+  const int nsub = g.nsub;
+  c->seeds.clear();
+  c->seed_off.assign(nsub + 1, 0);
+  c->obox.resize(nsub);
+  c->pbox.resize(nsub);
+  long long fac = 0, facp = 0, scr = 0, scrp = 0;
+  for (int i = 0; i < nsub; ++i) {
+    int ic[3];
+    sub_coords(c, i, ic);
+    int wlo[3], whi[3], lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      wlo[a] = ic[a] * g.S[a];
+      whi[a] = wlo[a] + g.S[a];
+      lo[a] = a < c->d ? std::max(wlo[a] - c->l, 0) : 0;
+      hi[a] = a < c->d ? std::min(whi[a] + c->l, g.n[a]) : 1;
+    }
+    c->seed_off[i] = (int)c->seeds.size();
+    for (int q = 0; q < 2 * c->d; ++q)
+      if (neighbor(c, i, q) >= 0) family(c, q, lo, hi, wlo, whi, c->seeds);
+    Box& B = c->obox[i];
+    B = Box{};
+    for (int a = 0; a < 3; ++a) { B.lo[a] = lo[a]; B.hi[a] = hi[a]; }
+    B.sub = i;
+    B.nb = 1;
+    for (int a = 0; a < c->d - 1; ++a) B.nb *= hi[a] - lo[a];
+    B.nblk = hi[c->d - 1] - lo[c->d - 1];
+    B.ncell = B.nb * B.nblk;
+    B.seed0 = c->seed_off[i];
+    B.nrhs = (int)c->seeds.size() - B.seed0;
+    B.fac = fac;
+    fac += (long long)B.nblk * B.nb * B.nb;
+    B.scr = scr;
+    scr += (long long)B.ncell * std::max(B.nrhs, 1);
+    if (B.nb > kMaxBlock)
+      return fail(c, MRCM_EINVAL, "oversampled box block of %d cells exceeds %d", B.nb, kMaxBlock);
+    if (B.nrhs > kMaxRhs)
+      return fail(c, MRCM_EINVAL, "%d seeds on one box exceed %d", B.nrhs, kMaxRhs);
+    Box& P = c->pbox[i];
+    P = Box{};
+    for (int a = 0; a < 3; ++a) { P.lo[a] = wlo[a]; P.hi[a] = whi[a]; }
+    P.sub = i;
+    P.nb = 1;
+    for (int a = 0; a < c->d - 1; ++a) P.nb *= whi[a] - wlo[a];
+    P.nblk = whi[c->d - 1] - wlo[c->d - 1];
+    P.ncell = P.nb * P.nblk;
+    P.nrhs = 1;
+    P.fac = facp;
+    facp += (long long)P.nblk * P.nb * P.nb;
+    P.scr = scrp;
+    scrp += P.ncell;
+    if (P.nb > kMaxBlock)
+      return fail(c, MRCM_EINVAL, "subdomain block of %d cells exceeds %d", P.nb, kMaxBlock);
+  }
+  c->seed_off[nsub] = (int)c->seeds.size();
+  c->nX = c->seed_off[nsub];
+  c->fac_n = fac;
+  c->facp_n = facp;
+  c->scr_n = std::max(scr, scrp);
+
+  // interfaces and their test functions
+  c->ifc.clear();
+  c->basis.clear();
+  int row = 0;
+  c->kl = 0;
+  c->ku = 0;
+  for (int i = 0; i < nsub; ++i) {
+    for (int a = 0; a < c->d; ++a) {
+      const int j = neighbor(c, i, 2 * a + 1);
+      if (j < 0) continue;
+      int ic[3], wlo[3], whi[3];
+      sub_coords(c, i, ic);
+      for (int b = 0; b < 3; ++b) {
+        wlo[b] = ic[b] * g.S[b];
+        whi[b] = wlo[b] + g.S[b];
+      }
+      Iface F;
+      F.i = i;
+      F.j = j;
+      F.axis = a;
+      F.row0 = row;
+      F.basis0 = (int)c->basis.size();
+      family(c, 2 * a + 1, wlo, whi, wlo, whi, c->basis);
+      F.nbasis = (int)c->basis.size() - F.basis0;
+      const int cmin = c->seed_off[i];
+      const int cmax = c->seed_off[j + 1] - 1;
+      for (int r = row; r < row + 2 * F.nbasis; ++r) {
+        c->kl = std::max(c->kl, r - cmin);
+        c->ku = std::max(c->ku, cmax - r);
+      }
+      row += 2 * F.nbasis;
+      c->ifc.push_back(F);
+    }
+  }
+  if (row != c->nX)
+    return fail(c, MRCM_EINVAL,
+                "interface system not square (Proposition 1): %d equations, %d unknowns", row,
+                c->nX);
+  c->ldab = 2 * c->kl + c->ku + 1;
+
+  // colors: parity of the subdomain index per axis
+  c->members.clear();
+  for (int col = 0; col < (1 << c->d); ++col) {
+    c->member_off[col] = (int)c->members.size();
+    for (int i = 0; i < nsub; ++i) {
+      int ic[3];
+      sub_coords(c, i, ic);
+      int cc = 0;
+      for (int a = 0; a < c->d; ++a) cc |= (ic[a] & 1) << a;
+      if (cc == col) c->members.push_back(i);
+    }
+  }
+  c->member_off[1 << c->d] = (int)c->members.size();
+
+  // device allocations
+  auto alloc = [&](auto*& ptr, size_t count) -> mrcm_status {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)&ptr, count * sizeof(T));
+    if (e != hipSuccess) return fail(c, MRCM_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    return MRCM_OK;
+  };
+#define ALLOC(p, n) do { mrcm_status s_ = alloc(p, (size_t)(n)); if (s_) return s_; } while (0)
+  const long long ncell_o = (long long)g.S[0] * g.S[1] * g.S[2];
+  ALLOC(c->d_obox, nsub);
+  ALLOC(c->d_pbox, nsub);
+  ALLOC(c->d_seeds, c->seeds.size());
+  ALLOC(c->d_basis, c->basis.size());
+  ALLOC(c->d_seed_off, nsub + 1);
+  ALLOC(c->d_ifc, c->ifc.size());
+  ALLOC(c->d_members, c->members.size());
+  ALLOC(c->fac, c->fac_n);
+  ALLOC(c->facp, c->facp_n);
+  ALLOC(c->scr, c->scr_n);
+  ALLOC(c->Pk, (long long)c->nX * ncell_o);
+  ALLOC(c->tr_u, (long long)c->nX * g.gstride);
+  ALLOC(c->tr_phi, (long long)c->nX * g.gstride);
+  ALLOC(c->tr_beta, (long long)nsub * g.gstride);
+  ALLOC(c->pbar, (long long)nsub * ncell_o);
+  ALLOC(c->ubar, (long long)nsub * g.gstride);
+  ALLOC(c->pibar, (long long)nsub * g.gstride);
+  ALLOC(c->AB, (long long)c->ldab * std::max(c->nX, 1));
+  ALLOC(c->rhs, c->nX);
+  ALLOC(c->X, c->nX);
+  ALLOC(c->p, g.ncells);
+  ALLOC(c->gflux, (long long)nsub * g.gstride);
+  ALLOC(c->partial, 64);
+#undef ALLOC
+  HIPCHK(c, hipMemcpy(c->d_obox, c->obox.data(), nsub * sizeof(Box), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_pbox, c->pbox.data(), nsub * sizeof(Box), hipMemcpyHostToDevice));
+  if (!c->seeds.empty())
+    HIPCHK(c, hipMemcpy(c->d_seeds, c->seeds.data(), c->seeds.size() * sizeof(Seed), hipMemcpyHostToDevice));
+  if (!c->basis.empty())
+    HIPCHK(c, hipMemcpy(c->d_basis, c->basis.data(), c->basis.size() * sizeof(Seed), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_seed_off, c->seed_off.data(), (nsub + 1) * sizeof(int), hipMemcpyHostToDevice));
+  if (!c->ifc.empty())
+    HIPCHK(c, hipMemcpy(c->d_ifc, c->ifc.data(), c->ifc.size() * sizeof(Iface), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_members, c->members.data(), c->members.size() * sizeof(int), hipMemcpyHostToDevice));
+  c->plan_valid = true;
+  return MRCM_OK;
+}
+
+mrcm_status check_flags(mrcm_ctx* c) {
+  int fl = 0;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&fl, c->flags, sizeof(int), hipMemcpyDeviceToHost));
+  if (fl & kFlagBadK) return fail(c, MRCM_EINVAL, "permeability must be finite and positive");
+  if (fl & kFlagNotPD) return fail(c, MRCM_ENOTPD, "local factorisation met a non-positive pivot");
+  if (fl & kFlagSingular) return fail(c, MRCM_ESINGULAR, "interface system is singular");
+  if (fl & kFlagNoConv) return fail(c, MRCM_ENOCONV, "iterative refinement did not converge");
+  return MRCM_OK;
+}
+
+void invalidate(mrcm_ctx* c, bool geometry) {
+  c->state = 0;
+  if (geometry) c->plan_valid = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_ctx** out) {
+  if (!out) return MRCM_EINVAL;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return MRCM_EINVAL;
+  if (!ncell || !(h > 0.0) || !std::isfinite(h)) return MRCM_EINVAL;
+  long long N = 1;
+  for (int a = 0; a < dim; ++a) {
+    if (ncell[a] <= 0) return MRCM_EINVAL;
+    N *= ncell[a];
+  }
+  if (N > (1LL << 31) - 1) return MRCM_EINVAL;
+  mrcm_ctx* c = new (std::nothrow) mrcm_ctx();
+  if (!c) return MRCM_ENOMEM;
+  c->d = dim;
+  for (int a = 0; a < dim; ++a) c->n[a] = ncell[a];
+  c->h = h;
+  c->stream = (hipStream_t)stream;
+  // boundary value layout: per side, faces x-fastest over the other axes
+  int off = 0;
+  for (int q = 0; q < 2 * dim; ++q) {
+    c->bc_off[q] = off;
+    int nf = 1;
+    for (int b = 0; b < dim; ++b)
+      if (b != (q >> 1)) nf *= ncell[b];
+    off += nf;
+  }
+  c->nbcv = off;
+  hipError_t e = hipMalloc((void**)&c->logk, N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->K, N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->f, N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
+  for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  if (e == hipSuccess) e = launch_fill(c->bcv, 0.0, off, c->stream);
+  if (e == hipSuccess) e = launch_fill(c->f, 0.0, N, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    mrcm_destroy(c);
+    return e == hipErrorOutOfMemory ? MRCM_ENOMEM : MRCM_EDEVICE;
+  }
+  *out = c;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_permeability(mrcm_ctx* c, const double* logk_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (!logk_dev) return fail(c, MRCM_EINVAL, "logk is NULL");
+  const long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+  HIPCHK(c, hipMemcpyAsync(c->logk, logk_dev, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->have_k = true;
+  invalidate(c, false);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_source(mrcm_ctx* c, const double* f_dev) {
+  if (!c) return MRCM_EINVAL;
+  const long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+  if (f_dev) {
+    HIPCHK(c, hipMemcpyAsync(c->f, f_dev, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    HIPCHK(c, launch_fill(c->f, 0.0, N, c->stream));
+  }
+  c->have_f = f_dev != nullptr;
+  invalidate(c, false);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_bc(mrcm_ctx* c, int side, mrcm_bc_type type, const double* val_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (side < 0 || side >= 2 * c->d) return fail(c, MRCM_EINVAL, "side %d out of range", side);
+  if (type != MRCM_BC_NEUMANN && type != MRCM_BC_DIRICHLET) return fail(c, MRCM_EINVAL, "bad bc type");
+  int nf = 1;
+  for (int b = 0; b < c->d; ++b)
+    if (b != (side >> 1)) nf *= c->n[b];
+  if (val_dev) {
+    HIPCHK(c, hipMemcpyAsync(c->bcv + c->bc_off[side], val_dev, nf * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    HIPCHK(c, launch_fill(c->bcv + c->bc_off[side], 0.0, nf, c->stream));
+  }
+  const bool changed = c->bc_type[side] != (int)type;
+  c->bc_type[side] = (int)type;
+  invalidate(c, changed);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_partition(mrcm_ctx* c, const int* sub, int overlap) {
+  if (!c) return MRCM_EINVAL;
+  if (!sub) return fail(c, MRCM_EINVAL, "sub is NULL");
+  int smin = 1 << 30;
+  for (int a = 0; a < c->d; ++a) {
+    if (sub[a] <= 0 || c->n[a] % sub[a])
+      return fail(c, MRCM_EINVAL, "axis %d: %d cells not a multiple of subdomain size %d", a, c->n[a], sub[a]);
+    smin = std::min(smin, sub[a]);
+  }
+  if (overlap < 0 || overlap > smin - 1)
+    return fail(c, MRCM_EINVAL, "overlap must satisfy 0 <= l <= min(sub) - 1");
+  for (int a = 0; a < c->d; ++a) c->S[a] = sub[a];
+  c->l = overlap;
+  c->have_part = true;
+  invalidate(c, true);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_interface_space(mrcm_ctx* c, mrcm_space space) {
+  if (!c) return MRCM_EINVAL;
+  if (space < MRCM_SPACE_CONST || space > MRCM_SPACE_FINE) return fail(c, MRCM_EINVAL, "bad space");
+  c->space = space;
+  invalidate(c, true);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_robin(mrcm_ctx* c, mrcm_beta_mode mode, double mbf, double smooth) {
+  if (!c) return MRCM_EINVAL;
+  if (mode != MRCM_BETA_ALPHA && mode != MRCM_BETA_CONST) return fail(c, MRCM_EINVAL, "bad beta mode");
+  if (!(mbf > 0.0) || !(smooth > 0.0) || !std::isfinite(mbf) || !std::isfinite(smooth))
+    return fail(c, MRCM_EINVAL, "Robin parameters must be positive and finite");
+  c->beta_mode = mode;
+  c->beta_mbf = mbf;
+  c->beta_sm = smooth;
+  invalidate(c, false);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_precision(mrcm_ctx* c, mrcm_precision prec, double tol, int max_refine) {
+  if (!c) return MRCM_EINVAL;
+  if (prec != MRCM_FP64 && prec != MRCM_FP32_REFINE) return fail(c, MRCM_EINVAL, "bad precision");
+  if (prec == MRCM_FP32_REFINE && (!(tol > 0.0) || max_refine < 0))
+    return fail(c, MRCM_EINVAL, "refinement needs tol > 0 and max_refine >= 0");
+  c->prec = prec;
+  c->tol = tol;
+  c->max_refine = max_refine;
+  invalidate(c, false);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_build_basis(mrcm_ctx* c) {
+  if (!c) return MRCM_EINVAL;
+  if (!c->have_k) return fail(c, MRCM_ESTATE, "permeability not set");
+  if (!c->have_part) return fail(c, MRCM_ESTATE, "partition not set");
+  if (!c->plan_valid) {
+    mrcm_status st = make_plan(c);
+    if (st) return st;
+  }
+  if (c->prec == MRCM_FP32_REFINE) return fail(c, MRCM_EINVAL, "FP32 refinement not available yet");
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipEventRecord(c->ev[0], s));
+  HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
+  HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
+  HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
+                         c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
+  HIPCHK(c, launch_particular(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
+                              c->facp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
+  HIPCHK(c, hipEventRecord(c->ev[1], s));
+  c->timed_basis = true;
+  c->n_local_solves = c->nX + c->geo.nsub;
+  c->state = 1;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
+  if (!c) return MRCM_EINVAL;
+  if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipEventRecord(c->ev[2], s));
+  HIPCHK(c, launch_fill(c->AB, 0.0, (long long)c->ldab * c->nX, s));
+  HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->d_seed_off,
+                           c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab,
+                           c->kl, c->ku, c->rhs, s));
+  if (c->nX > 0) {
+    hipError_t e = launch_bandlu_solve(c->AB, c->ldab, c->nX, c->kl, c->ku, c->rhs, c->X, nullptr,
+                                       c->flags, s);
+    if (e == hipErrorInvalidValue)
+      return fail(c, MRCM_EINVAL, "interface band (kl=%d, ku=%d) too wide for the LDS window", c->kl, c->ku);
+    HIPCHK(c, e);
+  }
+  HIPCHK(c, launch_combine(c->geo, c->d_seed_off, c->X, c->Pk, c->tr_u, c->pbar, c->ubar, c->p,
+                           c->gflux, s));
+  HIPCHK(c, hipEventRecord(c->ev[3], s));
+  c->timed_iface = true;
+  c->state = 2;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
+  if (!c) return MRCM_EINVAL;
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "interface not solved");
+  if (nsteps < 0) return fail(c, MRCM_EINVAL, "nsteps < 0");
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipEventRecord(c->ev[4], s));
+  if (nsteps > 0 && c->beta_sm != c->beta_mbf && !c->facs) {
+    return fail(c, MRCM_EINVAL, "distinct smoothing Robin parameter not available yet");
+  }
+  const double* fac = c->fac;
+  for (int st = 0; st < nsteps; ++st) {
+    for (int col = 0; col < (1 << c->d); ++col) {
+      const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
+      HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+                              c->beta_sm, fac, nullptr, nullptr, c->scr, c->p, c->gflux, c->prec,
+                              c->tol, c->max_refine, nullptr, nullptr, c->flags, s));
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->ev[5], s));
+  c->timed_smooth = true;
+  c->n_local_solves += nsteps * c->geo.nsub;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_get_pressure(mrcm_ctx* c, double* p_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (!p_dev) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  HIPCHK(c, launch_pressure_out(c->geo, c->p, p_dev, c->partial, c->stream));
+  return check_flags(c);
+}
+
+mrcm_status mrcm_get_flux(mrcm_ctx* c, double* flux_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (!flux_dev) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  HIPCHK(c, launch_flux_out(c->geo, c->K, c->p, c->gflux, c->bcv, flux_dev, c->stream));
+  return check_flags(c);
+}
+
+mrcm_status mrcm_get_coefficients(mrcm_ctx* c, double* x_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (!x_dev) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  if (c->nX > 0)
+    HIPCHK(c, hipMemcpyAsync(x_dev, c->X, c->nX * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return check_flags(c);
+}
+
+mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
+  if (!c) return MRCM_EINVAL;
+  if (!out) return fail(c, MRCM_EINVAL, "output is NULL");
+  std::memset(out, 0, sizeof *out);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->n_subdomains = c->geo.nsub;
+  out->n_boxes = c->geo.nsub;
+  out->n_unknowns = c->nX;
+  out->band_kl = c->kl;
+  out->band_ku = c->ku;
+  out->n_local_solves = c->n_local_solves;
+  out->bytes_factor = (double)(c->fac_n + c->facp_n) * sizeof(double);
+  float ms = 0.f;
+  if (c->timed_basis && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_basis = ms;
+  if (c->timed_iface && hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out->ms_interface = ms;
+  if (c->timed_smooth && hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) out->ms_smooth = ms;
+  return check_flags(c);
+}
+
+const char* mrcm_last_error(const mrcm_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+mrcm_status mrcm_destroy(mrcm_ctx* c) {
+  if (!c) return MRCM_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  free_plan(c);
+  dfree(c->logk); dfree(c->K); dfree(c->f); dfree(c->bcv); dfree(c->flags);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return MRCM_OK;
+}
+
+}  // extern "C"

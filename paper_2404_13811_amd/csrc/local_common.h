@@ -1,0 +1,126 @@
+// Device helpers for the local two-point-flux problems on boxes of cells.
+//
+// The lowest-order Raviart-Thomas discretisation with midpoint/trapezoid
+// quadrature on uniform Cartesian cells reduces to a cell-centred system in
+// the pressure (paper Section 2, remark after the local problems):
+//   interior face   |e| u = T (p_c - p_c'),  T = |e| K_H / h, K_H harmonic mean
+//   Robin face      |e| u = T^R (p_c - lam), T^R = |e| / (h / (2 K_c) + beta)
+//   Dirichlet face  |e| u = 2 K_c |e| / h (p_c - g)
+//   Neumann face    |e| u = |e| z
+// and mass balance per cell gives A p = b.  Cells of a box are numbered x
+// fastest; the dense blocks of the block-tridiagonal matrix are the cells
+// sharing the last-axis coordinate (lines in 2-D, planes in 3-D).
+#pragma once
+#include "mrcm_internal.h"
+
+namespace mrcm {
+
+__device__ __forceinline__ int gcell(const Geo& g, const int c[3]) {
+  return c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
+}
+
+__device__ __forceinline__ double kharm(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// Robin parameter on the face between cells c (inside) and o (outside),
+// normal along axis a (paper: beta = alpha H / K_H, or a constant).
+__device__ __forceinline__ double robin_beta(const Geo& g, int a, double kc, double ko, double beta) {
+  if (g.beta_mode == 1) return beta;
+  return beta * (g.S[a] * g.h) / kharm(kc, ko);
+}
+
+__device__ __forceinline__ double robin_T(const Geo& g, double kc, double b) {
+  return g.area / (g.h / (2.0 * kc) + b);
+}
+
+// Local coordinates of box cell `loc` (box order).
+__device__ __forceinline__ void box_local(const Box& B, int loc, int u[3]) {
+  int m0 = B.hi[0] - B.lo[0], m1 = B.hi[1] - B.lo[1];
+  u[0] = loc % m0;
+  int r = loc / m0;
+  u[1] = r % m1;
+  u[2] = r / m1;
+}
+
+// Face kinds of a box cell face.
+enum { kFaceInterior = 0, kFaceRobin = 1, kFaceDir = 2, kFaceNeu = 3 };
+
+__device__ __forceinline__ int face_kind(const Geo& g, const Box& B, const int c[3], int a, int s) {
+  int t = c[a] + (s ? 1 : -1);
+  if (t < 0 || t >= g.n[a]) return g.bc_type[2 * a + s] ? kFaceDir : kFaceNeu;
+  if (t < B.lo[a] || t >= B.hi[a]) return kFaceRobin;
+  return kFaceInterior;
+}
+
+// Index of a boundary face of domain side (a, s) touched by global cell c.
+__device__ __forceinline__ int bface_index(const Geo& g, const int c[3], int a) {
+  int idx = 0, mult = 1;
+  for (int b = 0; b < g.d; ++b) {
+    if (b == a) continue;
+    idx += c[b] * mult;
+    mult *= g.n[b];
+  }
+  return idx;
+}
+
+// Index of the face of side q of box [lo, hi) touched by global cell c
+// (x-fastest over the tangential axes).
+__device__ __forceinline__ int side_face_index(const Geo& g, const int lo[3], const int hi[3],
+                                               const int c[3], int a) {
+  int idx = 0, mult = 1;
+  for (int b = 0; b < g.d; ++b) {
+    if (b == a) continue;
+    idx += (c[b] - lo[b]) * mult;
+    mult *= (hi[b] - lo[b]);
+  }
+  return idx;
+}
+
+// Value of a seed (or interface test function) on the face of side
+// `sd.side` of box [lo, hi) touched by global cell c.
+__device__ __forceinline__ double seed_value(const Geo& g, const Seed& sd, const int lo[3],
+                                             const int hi[3], const int c[3]) {
+  const int a = sd.side >> 1;
+  if (sd.kind == 0) return 1.0;
+  if (sd.kind == 1) {
+    const int b = sd.axis;
+    const int m = hi[b] - lo[b];
+    return (2.0 * (c[b] - lo[b]) + 1.0) / m - 1.0;
+  }
+  return side_face_index(g, lo, hi, c, a) == sd.face ? 1.0 : 0.0;
+}
+
+// Diagonal of A for a box cell and the couplings to its +axis in-box
+// neighbours (T > 0; zero when the neighbour is outside the box).
+struct CellCoef {
+  double diag;
+  double tp[3];
+};
+
+__device__ __forceinline__ CellCoef cell_coef(const Geo& g, const Box& B, const double* K,
+                                              const int c[3], double beta) {
+  CellCoef r;
+  r.diag = 0.0;
+  r.tp[0] = r.tp[1] = r.tp[2] = 0.0;
+  const int ci = gcell(g, c);
+  const double kc = K[ci];
+  for (int a = 0; a < g.d; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      int o[3] = {c[0], c[1], c[2]};
+      o[a] += s ? 1 : -1;
+      const int kind = face_kind(g, B, c, a, s);
+      if (kind == kFaceInterior) {
+        const double T = g.area * kharm(kc, K[gcell(g, o)]) / g.h;
+        r.diag += T;
+        if (s) r.tp[a] = T;
+      } else if (kind == kFaceRobin) {
+        const double b = robin_beta(g, a, kc, K[gcell(g, o)], beta);
+        r.diag += robin_T(g, kc, b);
+      } else if (kind == kFaceDir) {
+        r.diag += 2.0 * kc * g.area / g.h;
+      }
+    }
+  }
+  return r;
+}
+
+}  // namespace mrcm

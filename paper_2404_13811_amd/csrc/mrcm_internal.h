@@ -1,0 +1,114 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the MRCM-OS library.  Nothing here is part of the public ABI (mrcm.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mrcm {
+
+constexpr int kMaxBlock = 64;       // largest dense block (cells of one line / plane)
+constexpr int kLocalThreads = 256;  // threads per local-solve workgroup
+constexpr int kMaxRhs = 64;         // right-hand sides per box in one launch
+
+// Flags raised by kernels (bit mask in device memory).
+enum : int { kFlagNotPD = 1, kFlagSingular = 2, kFlagNoConv = 4, kFlagBadK = 8, kFlagBandOverflow = 16 };
+
+// Geometry and discretisation parameters, passed to every kernel by value.
+struct Geo {
+  int d;
+  int n[3];        // cells per axis (1 for unused axes)
+  int S[3];        // cells per subdomain per axis
+  int M[3];        // subdomains per axis
+  int l;           // oversampling width
+  int nsub;
+  int ncells;
+  int bc_type[6];  // 0 Neumann, 1 Dirichlet
+  int bc_off[6];   // offset of each side's face values in the bc array
+  int beta_mode;   // 0 alpha, 1 constant
+  int neumann;     // no pressure boundary anywhere
+  int nfaceg;      // faces per Gamma side (S^(d-1)), same for every side when S is cubic
+  int gside_off[6];// offset of side q within one subdomain's Gamma-face block
+  int gstride;     // faces per subdomain over all 2d sides
+  double h, area, vol;
+};
+
+// One local box: an oversampled region (basis functions, smoothing) or a
+// subdomain (particular problem).  Cells are ordered x fastest; blocks are
+// the cells sharing the last-axis coordinate.
+struct Box {
+  int lo[3], hi[3];
+  int sub;
+  int nb, nblk, ncell;
+  int nrhs;
+  int seed0;          // first global seed index (basis boxes)
+  long long fac;      // element offset of the cached block inverses
+  long long scr;      // element offset of this box's right-hand-side scratch
+};
+
+// Seed Robin data on one side of an oversampled box, and (with the same
+// encoding, measured on the subdomain) a test function of M_H / V_H.
+struct Seed {
+  int side;   // 0..2d-1
+  int kind;   // 0 constant, 1 linear along tangential axis `axis`, 2 fine indicator
+  int axis;
+  int face;   // fine: face index on the side (x-fastest over tangential axes)
+};
+
+// A coarse interface Gamma_ij, i < j, normal along `axis`.
+struct Iface {
+  int i, j, axis;
+  int row0;     // first row of its 2p equations
+  int nbasis;   // p
+  int basis0;   // index of its first test function in the basis array
+};
+
+// ---------------------------------------------------------------- launchers
+// local problems (local.hip)
+hipError_t launch_exp(const double* logk, double* K, int n, int* flags, hipStream_t s);
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
+hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s);
+hipError_t launch_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
+                        const double* K, double beta, double* fac, double* scr,
+                        double* Pk, double* tr_u, double* tr_phi, double* tr_beta,
+                        int* flags, hipStream_t s);
+hipError_t launch_particular(const Geo& g, const Box* boxes, int nbox, const double* K,
+                             const double* f, const double* bcv, double beta, double* fac,
+                             double* scr, double* pbar, double* ubar, double* pibar,
+                             int* flags, hipStream_t s);
+hipError_t launch_factor32(const Geo& g, const Box* boxes, int nbox, const double* K,
+                           double beta, float* fac32, double* dscale, int* flags, hipStream_t s);
+hipError_t launch_basis32(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
+                          const double* K, double beta, const float* fac32, const double* dscale,
+                          double* scr, double* Pk, double* tr_u, double* tr_phi, double* tr_beta,
+                          double tol, int max_refine, int* iters, double* resid, int* flags,
+                          hipStream_t s);
+hipError_t launch_particular32(const Geo& g, const Box* boxes, int nbox, const double* K,
+                               const double* f, const double* bcv, double beta,
+                               const float* fac32, const double* dscale, double* scr,
+                               double* pbar, double* ubar, double* pibar, double tol,
+                               int max_refine, int* iters, double* resid, int* flags,
+                               hipStream_t s);
+hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int nmem,
+                         const double* K, const double* f, const double* bcv, double beta,
+                         const double* fac, const float* fac32, const double* dscale,
+                         double* scr, double* p, double* gflux, int precision, double tol,
+                         int max_refine, int* iters, double* resid, int* flags, hipStream_t s);
+
+// interface system (iface.hip)
+hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,
+                          const int* seed_off, const double* tr_u, const double* tr_phi,
+                          const double* tr_beta, const double* ubar, const double* pibar,
+                          double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s);
+hipError_t launch_bandlu_solve(double* AB, int ldab, int n, int kl, int ku, double* rhs,
+                               double* x, int* ipiv, int* flags, hipStream_t s);
+hipError_t launch_combine(const Geo& g, const int* seed_off, const double* X, const double* Pk,
+                          const double* tr_u, const double* pbar, const double* ubar,
+                          double* p, double* gflux, hipStream_t s);
+
+// outputs (outputs.hip)
+hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,
+                               hipStream_t s);
+hipError_t launch_flux_out(const Geo& g, const double* K, const double* p, const double* gflux,
+                           const double* bcv, double* out, hipStream_t s);
+
+}  // namespace mrcm

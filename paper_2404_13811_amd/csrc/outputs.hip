@@ -1,0 +1,97 @@
+// Outputs of the MRCM-OS solve: cell pressures (zero mean when no side
+// carries a pressure condition) and outward normal velocities on every face
+// of every cell, with skeleton faces carrying the owning subdomain's value.
+#include "local_common.h"
+
+namespace mrcm {
+namespace {
+
+constexpr int RED = 256;
+
+// Deterministic two-pass mean: fixed partition into blocks, fixed tree.
+__global__ void k_partial_sum(const double* __restrict__ p, int n, double* __restrict__ partial) {
+  __shared__ double s[RED];
+  double acc = 0.0;
+  for (int i = blockIdx.x * RED + threadIdx.x; i < n; i += gridDim.x * RED) acc += p[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = RED / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ void k_shift_copy(const double* __restrict__ p, int n, const double* __restrict__ partial,
+                             int npart, int shift, double* __restrict__ out) {
+  __shared__ double mean;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    if (shift)
+      for (int k = 0; k < npart; ++k) acc += partial[k];
+    mean = acc / n;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = p[i] - mean;
+}
+
+__global__ void k_flux_out(Geo g, const double* __restrict__ K, const double* __restrict__ p,
+                           const double* __restrict__ gflux, const double* __restrict__ bcv,
+                           double* __restrict__ out) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= g.ncells) return;
+  int c[3];
+  c[0] = ci % g.n[0];
+  c[1] = (ci / g.n[0]) % g.n[1];
+  c[2] = ci / (g.n[0] * g.n[1]);
+  const double kc = K[ci];
+  int own[3];
+  for (int a = 0; a < 3; ++a) own[a] = (a < g.d) ? c[a] / g.S[a] : 0;
+  const int sub = own[0] + g.M[0] * (own[1] + (g.d == 3 ? g.M[1] * own[2] : 0));
+  for (int a = 0; a < g.d; ++a)
+    for (int s = 0; s < 2; ++s) {
+      const int q = 2 * a + s;
+      int o[3] = {c[0], c[1], c[2]};
+      o[a] += s ? 1 : -1;
+      double u;
+      if (o[a] < 0 || o[a] >= g.n[a]) {
+        const double val = bcv[g.bc_off[q] + bface_index(g, c, a)];
+        u = g.bc_type[q] ? 2.0 * kc * g.area / g.h * (p[ci] - val) / g.area : val;
+      } else if (o[a] / g.S[a] == own[a]) {
+        const int oi = gcell(g, o);
+        u = g.area * kharm(kc, K[oi]) / g.h * (p[ci] - p[oi]) / g.area;
+      } else {
+        int lo[3], hi[3];
+        for (int b = 0; b < 3; ++b) {
+          lo[b] = (b < g.d) ? own[b] * g.S[b] : 0;
+          hi[b] = (b < g.d) ? lo[b] + g.S[b] : 1;
+        }
+        const int t = side_face_index(g, lo, hi, c, a);
+        u = gflux[(long long)sub * g.gstride + g.gside_off[q] + t];
+      }
+      out[(long long)ci * (2 * g.d) + q] = u;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,
+                               hipStream_t s) {
+  const int n = g.ncells;
+  const int npart = 64;
+  if (g.neumann)
+    hipLaunchKernelGGL(k_partial_sum, dim3(npart), dim3(RED), 0, s, p, n, partial);
+  hipLaunchKernelGGL(k_shift_copy, dim3((n + 255) / 256), dim3(256), 0, s, p, n, partial, npart,
+                     g.neumann, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_out(const Geo& g, const double* K, const double* p, const double* gflux,
+                           const double* bcv, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_flux_out, dim3((g.ncells + 255) / 256), dim3(256), 0, s, g, K, p, gflux, bcv,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

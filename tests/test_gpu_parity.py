@@ -1,0 +1,70 @@
+"""GPU FP64 path vs the CPU oracle, element by element (relative L2 <= 1e-10
+in pressure and flux, the bar for the FP64 form)."""
+import sys
+
+import numpy as np
+import pytest
+
+from inputs import make_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check(wl, nsmooth=None, tol=TOL):
+    from gpu_util import gpu_solve, oracle_solve, rel
+    print("case", wl.name, wl.ncell, wl.sub, "l=%d" % wl.overlap, wl.space, "ns", nsmooth, flush=True)
+    p, fl, X, st = gpu_solve(wl, nsmooth=nsmooth)
+    rp, rf, rX, _ = oracle_solve(wl, nsmooth=nsmooth)
+    ep, ef = rel(p, rp), rel(fl, rf)
+    print("  rel L2 p %.3e flux %.3e  (nX %d kl %d ku %d)" % (ep, ef, st["n_unknowns"], st["band_kl"], st["band_ku"]), flush=True)
+    assert ep <= tol and ef <= tol
+    return p, fl, X, rX
+
+
+def _small(**kw):
+    return make_workload("c1", scale=2).with_(beta_mode="alpha", beta_mbf=1.0, beta_smooth=1.0,
+                                               sub=(8, 8)).with_(**kw)
+
+
+@pytest.mark.parametrize("overlap", [0, 1, 2, 3])
+@pytest.mark.parametrize("space", ["const", "linear"])
+def test_small_mrcm_o(space, overlap):
+    _, _, X, rX = _check(_small(space=space, overlap=overlap), nsmooth=0)
+    assert np.linalg.norm(X - rX) <= 1e-9 * np.linalg.norm(rX)
+
+
+@pytest.mark.parametrize("overlap", [0, 2, 3])
+def test_small_with_smoothing(overlap):
+    _check(_small(space="linear", overlap=overlap), nsmooth=3)
+
+
+@pytest.mark.parametrize("overlap", [0, 1, 2])
+def test_fine_spaces_prop2(overlap):
+    _check(_small(space="fine", overlap=overlap), nsmooth=0)
+
+
+def test_c1_full():
+    _check(make_workload("c1"))
+
+
+@pytest.mark.parametrize("overlap", [0, 2, 4])
+def test_c2_scaled_pure_neumann(overlap):
+    _check(make_workload("c2", scale=4, overlap=overlap))
+
+
+@pytest.mark.parametrize("overlap", [0, 2, 4])
+def test_c2_full(overlap):
+    _check(make_workload("c2", overlap=overlap))
+
+
+def test_three_dimensional_small():
+    _check(make_workload("c4", scale=8), nsmooth=1)
