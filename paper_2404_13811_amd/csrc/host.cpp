@@ -56,7 +56,7 @@ struct mrcm_ctx {
   std::vector<int> members;
   int member_off[9] = {0};
   int nX = 0, kl = 0, ku = 0, ldab = 0;
-  long long fac_n = 0, facp_n = 0, scr_n = 0;
+  long long fac_n = 0, facp_n = 0, scr_n = 0, scro_n = 0, scrp_n = 0;
 
   // device plan
   Box* d_obox = nullptr;
@@ -69,6 +69,8 @@ struct mrcm_ctx {
 
   // device workspace
   double *fac = nullptr, *facs = nullptr, *facp = nullptr, *scr = nullptr;
+  double *tco = nullptr, *tcp = nullptr;  // block couplings of the boxes / subdomains
+  bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
   double *Pk = nullptr, *tr_u = nullptr, *tr_phi = nullptr, *tr_beta = nullptr;
   double *pbar = nullptr, *ubar = nullptr, *pibar = nullptr;
   double *AB = nullptr, *rhs = nullptr, *X = nullptr;
@@ -109,7 +111,7 @@ void dfree(T*& p) {
 void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
   dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members);
-  dfree(c->fac); dfree(c->facs); dfree(c->facp); dfree(c->scr);
+  dfree(c->fac); dfree(c->facs); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
   dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
   dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
   dfree(c->AB); dfree(c->rhs); dfree(c->X); dfree(c->p); dfree(c->gflux); dfree(c->partial);
@@ -267,6 +269,11 @@ mrcm_status make_plan(mrcm_ctx* c) {
   c->fac_n = fac;
   c->facp_n = facp;
   c->scr_n = std::max(scr, scrp);
+  c->scro_n = scr;
+  c->scrp_n = scrp;
+  c->wave = c->d == 2;
+  for (int i = 0; i < nsub; ++i)
+    if (c->obox[i].nb > 32 || c->pbox[i].nb > 32) c->wave = false;
 
   // interfaces and their test functions
   c->ifc.clear();
@@ -342,6 +349,8 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->fac, c->fac_n);
   ALLOC(c->facp, c->facp_n);
   ALLOC(c->scr, c->scr_n);
+  ALLOC(c->tco, c->scro_n);
+  ALLOC(c->tcp, c->scrp_n);
   ALLOC(c->Pk, (long long)c->nX * ncell_o);
   ALLOC(c->tr_u, (long long)c->nX * g.gstride);
   ALLOC(c->tr_phi, (long long)c->nX * g.gstride);
@@ -539,10 +548,17 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   HIPCHK(c, hipEventRecord(c->ev[0], s));
   HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
-  HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
-                         c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
-  HIPCHK(c, launch_particular(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
-                              c->facp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
+  if (c->wave) {
+    HIPCHK(c, launch_basis_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
+                             c->tco, c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
+    HIPCHK(c, launch_particular_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
+                                  c->facp, c->tcp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
+  } else {
+    HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
+                           c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
+    HIPCHK(c, launch_particular(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
+                                c->facp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
+  }
   HIPCHK(c, hipEventRecord(c->ev[1], s));
   c->timed_basis = true;
   c->n_local_solves = c->nX + c->geo.nsub;
@@ -587,9 +603,14 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   for (int st = 0; st < nsteps; ++st) {
     for (int col = 0; col < (1 << c->d); ++col) {
       const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
-      HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
-                              c->beta_sm, fac, nullptr, nullptr, c->scr, c->p, c->gflux, c->prec,
-                              c->tol, c->max_refine, nullptr, nullptr, c->flags, s));
+      if (c->wave) {
+        HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f,
+                                  c->bcv, c->beta_sm, fac, c->tco, c->scr, c->p, c->gflux, s));
+      } else {
+        HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+                                c->beta_sm, fac, nullptr, nullptr, c->scr, c->p, c->gflux, c->prec,
+                                c->tol, c->max_refine, nullptr, nullptr, c->flags, s));
+      }
     }
   }
   HIPCHK(c, hipEventRecord(c->ev[5], s));

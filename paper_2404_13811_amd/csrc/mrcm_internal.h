@@ -94,6 +94,20 @@ hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int
                          double* scr, double* p, double* gflux, int precision, double tol,
                          int max_refine, int* iters, double* resid, int* flags, hipStream_t s);
 
+// one-wavefront-per-box 2-D kernels (local_wave.hip), blocks of <= 32 cells
+hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
+                          const double* K, double beta, double* fac, double* tcoup, double* scr,
+                          double* Pk, double* tr_u, double* tr_phi, double* tr_beta, int* flags,
+                          hipStream_t s);
+hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const double* K,
+                               const double* f, const double* bcv, double beta, double* fac,
+                               double* tcoup, double* scr, double* pbar, double* ubar,
+                               double* pibar, int* flags, hipStream_t s);
+hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
+                           const double* K, const double* f, const double* bcv, double beta,
+                           const double* fac, const double* tcoup, double* scr, double* p,
+                           double* gflux, hipStream_t s);
+
 // interface system (iface.hip)
 hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,
                           const int* seed_off, const double* tr_u, const double* tr_phi,
