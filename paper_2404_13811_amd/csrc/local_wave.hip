@@ -6,11 +6,10 @@
 // line is shorter): lane L holds rows 16h .. 16h+15 of column c, with
 // c = L & 31 and h = L >> 5, so all 64 lanes carry work.
 //
-// The block inverse is computed by in-place Gauss-Jordan elimination.  For
-// an SPD matrix, after pivots 0..k-1 have been processed the pivot column
-// k equals row k with the sign flipped on the processed rows, so each step
-// only needs row k broadcast (one LDS write by the lanes that hold it, then
-// broadcast reads): no cross-lane reduction and no barrier beyond the wave.
+// The block inverse is computed by in-place Gauss-Jordan elimination (no
+// pivoting: the pivots of an SPD matrix are positive).  Each step broadcasts
+// pivot row and column through LDS; no cross-lane reduction and no barrier
+// beyond the single wave.
 //
 // Solves use the block LDL^T recurrences of the block-tridiagonal matrix
 // (see local.hip): forward w_j = W_j (b_j + t_{j-1} .* w_{j-1}), backward
@@ -26,6 +25,7 @@ constexpr int HB = 16;
 
 struct WaveSmem {
   double row[2][NBW];
+  double col[2][NBW];
   double z[kMaxRhs][NBW];
   double diag[NBW], tx[NBW], tprev[NBW], tnext[NBW];
   int flag;
@@ -86,7 +86,9 @@ __device__ __forceinline__ void wbuild(int nb, bool first, const WaveSmem& sm, d
   }
 }
 
-// In-place Gauss-Jordan inversion of the block held in w.
+// In-place Gauss-Jordan inversion of the block held in w.  Each step
+// publishes pivot row k (one element per lane of the owning half) and pivot
+// column k (the 16 registers of the two lanes holding column k) to LDS.
 __device__ __forceinline__ void wgj(int nb, WaveSmem& sm, double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
@@ -94,18 +96,22 @@ __device__ __forceinline__ void wgj(int nb, WaveSmem& sm, double w[HB]) {
   for (int k = 0; k < NBW; ++k) {
     if (k >= nb) break;
     double* rk = sm.row[k & 1];
+    double* ck = sm.col[k & 1];
     if (h == (k >> 4)) rk[c] = w[k & 15];
+    if (c == k) {
+#pragma unroll
+      for (int i = 0; i < HB; ++i) ck[HB * h + i] = w[i];
+    }
     wsync();
     const double a = rk[c];
     const double piv = rk[k];
     if (!(piv > 0.0) && L == 0) sm.flag |= kFlagNotPD;
     const double ip = 1.0 / piv;
-    const double f = (c == k) ? (-1.0 - ip) : -(a * ip);
+    const double f = -(a * ip);
 #pragma unroll
     for (int i = 0; i < HB; ++i) {
-      const int r = HB * h + i;
-      const double v = rk[r];
-      w[i] = fma(f, (r < k) ? -v : v, w[i]);
+      const double v = ck[HB * h + i];
+      w[i] = (c == k) ? -v * ip : fma(f, v, w[i]);
     }
     if (h == (k >> 4)) w[k & 15] = (c == k) ? ip : a * ip;
   }
