@@ -313,7 +313,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
     return fail(c, MRCM_EINVAL,
                 "interface system not square (Proposition 1): %d equations, %d unknowns", row,
                 c->nX);
-  c->ldab = 2 * c->kl + c->ku + 1;
+  c->ldab = c->kl + c->ku + 1;  // row-band width (input rows, then U rows)
 
   // colors: parity of the subdomain index per axis
   c->members.clear();
@@ -358,7 +358,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->pbar, (long long)nsub * ncell_o);
   ALLOC(c->ubar, (long long)nsub * g.gstride);
   ALLOC(c->pibar, (long long)nsub * g.gstride);
-  ALLOC(c->AB, (long long)c->ldab * std::max(c->nX, 1));
+  ALLOC(c->AB, 2LL * c->ldab * std::max(c->nX, 1));
   ALLOC(c->rhs, c->nX);
   ALLOC(c->X, c->nX);
   ALLOC(c->p, g.ncells);
