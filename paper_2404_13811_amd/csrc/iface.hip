@@ -109,6 +109,9 @@ __global__ void k_moments(Geo g, const Iface* __restrict__ ifc, const Seed* __re
 
 constexpr int LU_THREADS = 1024;
 
+// x in [0, 2m) -> x mod m, without an integer division.
+__device__ __forceinline__ int wrap(int x, int m) { return x >= m ? x - m : x; }
+
 // Unblocked variant: the active (kl+1) x (kl+ku+1) window lives in LDS.
 __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict__ RB, int n,
                                                        int kl, int ku,
@@ -119,14 +122,13 @@ __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict_
   const int R = kl + 1;
   const int CW = kl + ku + 1;
   const int WI = kl + ku + 1;
-  double* win = smem;              // R * CW
+  double* win = smem;              // R * CW, slot (i mod R, c mod CW)
   double* zr = win + R * CW;       // R
   double* lm = zr + R;             // R (multipliers)
   __shared__ int s_piv;
   __shared__ int s_flag;
   const int tid = threadIdx.x;
   if (tid == 0) s_flag = 0;
-  auto W = [&](int i, int c) -> double& { return win[(i % R) * CW + (c % CW)]; };
   auto orig = [&](int i, int c) -> double {
     if (c < 0 || c >= n || i < 0 || i >= n) return 0.0;
     const int t = c - i + kl;
@@ -134,18 +136,19 @@ __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict_
     return RB[(long long)i * WI + t];
   };
   for (int e = tid; e < R * CW; e += LU_THREADS) {
-    const int i = e / CW, c = e % CW;
-    W(i, c) = orig(i, c);
+    const int i = e / CW, c = e - (e / CW) * CW;
+    win[i * CW + c] = orig(i, c);
   }
-  for (int i = tid; i < R; i += LU_THREADS) zr[i % R] = (i < n) ? rhs[i] : 0.0;
+  for (int i = tid; i < R; i += LU_THREADS) zr[i] = (i < n) ? rhs[i] : 0.0;
   __syncthreads();
+  int jr = 0, jc = 0;  // slots of row j and column j
   for (int j = 0; j < n; ++j) {
     const int km = min(kl, n - 1 - j);
     if (tid < 64) {
       double best = -1.0;
       int bi = j;
       for (int t = tid; t <= km; t += 64) {
-        const double v = fabs(W(j + t, j));
+        const double v = fabs(win[wrap(jr + t, R) * CW + jc]);
         if (v > best) { best = v; bi = j + t; }
       }
       for (int off = 32; off > 0; off >>= 1) {
@@ -160,52 +163,68 @@ __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict_
     }
     __syncthreads();
     const int pr = s_piv;
+    const int prs = wrap(jr + (pr - j), R);
     if (pr != j) {
       for (int c = tid; c < CW; c += LU_THREADS) {
-        const double a = W(j, j + c);
-        W(j, j + c) = W(pr, j + c);
-        W(pr, j + c) = a;
+        const int cs = wrap(jc + c, CW);
+        const double a = win[jr * CW + cs];
+        win[jr * CW + cs] = win[prs * CW + cs];
+        win[prs * CW + cs] = a;
       }
       if (tid == 0) {
-        const double a = zr[j % R];
-        zr[j % R] = zr[pr % R];
-        zr[pr % R] = a;
+        const double a = zr[jr];
+        zr[jr] = zr[prs];
+        zr[prs] = a;
       }
     }
     __syncthreads();
-    const double piv = W(j, j);
-    for (int i = 1 + tid; i <= km; i += LU_THREADS) lm[i] = (piv != 0.0) ? W(j + i, j) / piv : 0.0;
+    const double piv = win[jr * CW + jc];
+    for (int i = 1 + tid; i <= km; i += LU_THREADS)
+      lm[i] = (piv != 0.0) ? win[wrap(jr + i, R) * CW + jc] / piv : 0.0;
     __syncthreads();
     const int ncols = CW - 1;
     for (int e = tid; e < km * (ncols + 1); e += LU_THREADS) {
-      const int i = 1 + e / (ncols + 1), c = e % (ncols + 1);
-      if (c < ncols) W(j + i, j + 1 + c) -= lm[i] * W(j, j + 1 + c);
-      else zr[(j + i) % R] -= lm[i] * zr[j % R];
+      const int ii = e / (ncols + 1), c = e - ii * (ncols + 1);
+      const int i = 1 + ii;
+      const int rs = wrap(jr + i, R);
+      if (c < ncols) {
+        const int cs = wrap(jc + 1 + c, CW);
+        win[rs * CW + cs] -= lm[i] * win[jr * CW + cs];
+      } else {
+        zr[rs] -= lm[i] * zr[jr];
+      }
     }
-    for (int c = tid; c < CW; c += LU_THREADS) UR[(long long)j * CW + c] = (j + c < n) ? W(j, j + c) : 0.0;
+    for (int c = tid; c < CW; c += LU_THREADS)
+      UR[(long long)j * CW + c] = (j + c < n) ? win[jr * CW + wrap(jc + c, CW)] : 0.0;
     __syncthreads();
-    if (tid == 0) x[j] = zr[j % R];
+    if (tid == 0) x[j] = zr[jr];
+    // slide: row j's slot takes row j + kl + 1, column j's slot column j + CW
     const int nr = j + kl + 1;
-    for (int c = tid; c < CW; c += LU_THREADS) W(nr, j + 1 + c) = (nr < n) ? orig(nr, j + 1 + c) : 0.0;
-    if (tid == 0) zr[nr % R] = (nr < n) ? rhs[nr] : 0.0;
-    for (int i = 1 + tid; i <= kl; i += LU_THREADS) W(j + i, j + CW) = 0.0;
+    for (int c = tid; c < CW; c += LU_THREADS)
+      win[jr * CW + wrap(jc + 1 + c, CW)] = (nr < n) ? orig(nr, j + 1 + c) : 0.0;
+    if (tid == 0) zr[jr] = (nr < n) ? rhs[nr] : 0.0;
+    for (int i = 1 + tid; i <= kl; i += LU_THREADS) win[wrap(jr + i, R) * CW + jc] = 0.0;
     __syncthreads();
+    jr = wrap(jr + 1, R);
+    jc = wrap(jc + 1, CW);
   }
   double* xs = smem;
   __syncthreads();
   if (tid < 64) {
+    int js = (n - 1) % CW;
     for (int j = n - 1; j >= 0; --j) {
       double acc = 0.0;
       for (int c = 1 + tid; c < CW; c += 64)
-        if (j + c < n) acc += UR[(long long)j * CW + c] * xs[(j + c) % CW];
+        if (j + c < n) acc += UR[(long long)j * CW + c] * xs[wrap(js + c, CW)];
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
       const double v = (x[j] - acc) / UR[(long long)j * CW];
       if (tid == 0) {
-        xs[j % CW] = v;
+        xs[js] = v;
         x[j] = v;
       }
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
+      js = (js == 0) ? CW - 1 : js - 1;
     }
   }
   __syncthreads();
@@ -213,12 +232,13 @@ __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict_
 }
 
 // Blocked variant: panels of BNB columns.  Window rows [j0, j0+H) and
-// columns [j0, j0+WC) live in LDS (circular slots), H = BNB + kl,
+// columns [j0, j0+WC) live in LDS in circular slots, H = BNB + kl,
 // WC = BNB + kl + ku.  Per panel: wave 0 factors the H x BNB panel with
 // partial pivoting in registers; all threads apply the row interchanges and
 // the unit-lower triangular solve to their columns (U12), then the
 // register-tiled rank-BNB update of the trailing window, then the window
-// slides by BNB rows / columns (next rows prefetched into registers).
+// slides by BNB rows / columns (the entering rows are prefetched into
+// registers at the start of the panel).
 constexpr int BNB = 16;
 constexpr int BT = 256;
 constexpr int PF = 16;  // prefetched values per thread
@@ -237,12 +257,11 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
   double* win = smem;            // H * LDW
   double* zr = win + H * LDW;    // H
   double* swp = zr + H;          // 2 * BNB
-  __shared__ int piv[BNB];
+  __shared__ int piv[BNB];       // pivot row offsets (relative to j0)
   __shared__ int s_flag;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   if (tid == 0) s_flag = 0;
-  auto WIN = [&](int i, int c) -> double& { return win[(i % H) * LDW + (c % WC)]; };
   auto orig = [&](int i, int c) -> double {
     if (c < 0 || c >= n || i < 0 || i >= n) return 0.0;
     const int t = c - i + kl;
@@ -250,14 +269,17 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
     return RB[(long long)i * WI + t];
   };
   for (int e = tid; e < H * WC; e += BT) {
-    const int i = e / WC, c = e % WC;
-    WIN(i, c) = orig(i, c);
+    const int i = e / WC, c = e - (e / WC) * WC;
+    win[i * LDW + c] = orig(i, c);
   }
-  for (int i = tid; i < H; i += BT) zr[i % H] = (i < n) ? rhs[i] : 0.0;
+  for (int i = tid; i < H; i += BT) zr[i] = (i < n) ? rhs[i] : 0.0;
   __syncthreads();
+  int j0h = 0, j0w = 0;  // slots of row j0 and column j0
   for (int j0 = 0; j0 < n; j0 += BNB) {
     const int nbp = min(BNB, n - j0);
-    const int j1 = j0 + nbp;  // next panel start
+    const int j1 = j0 + nbp;
+    auto RS = [&](int t) { return wrap(j0h + t, H); };          // slot of row j0 + t, t < H
+    auto CS = [&](int t) { int v = j0w + t; v = wrap(v, WC); return wrap(v, WC); };  // column j0 + t
     // prefetch the rows entering the window after this panel
     double pf[PF];
     const int npf = nbp * WC;
@@ -267,32 +289,33 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
       const int e = tid + q * BT;
       pf[q] = 0.0;
       if (use_pf && e < npf) {
-        const int r = j0 + H + e / WC;
-        const int c = j1 + e % WC;
-        pf[q] = orig(r, c);
+        const int rr = e / WC;
+        pf[q] = orig(j0 + H + rr, j1 + (e - rr * WC));
       }
     }
     // (A) panel factorisation by wave 0
     if (tid < 64) {
-      const int r0 = j0 + lane, r1 = j0 + lane + 64;
-      const bool v0 = lane < H && r0 < n;
-      const bool v1 = lane + 64 < H && r1 < n;
+      const int t0 = lane, t1 = lane + 64;  // row offsets from j0
+      const bool v0 = t0 < H && j0 + t0 < n;
+      const bool v1 = t1 < H && j0 + t1 < n;
+      const int s0 = v0 ? RS(t0) : 0, s1 = v1 ? RS(t1) : 0;
       double a0[BNB], a1[BNB];
 #pragma unroll
       for (int c = 0; c < BNB; ++c) {
-        a0[c] = (v0 && c < nbp) ? WIN(r0, j0 + c) : 0.0;
-        a1[c] = (v1 && c < nbp) ? WIN(r1, j0 + c) : 0.0;
+        const int cs = CS(c);
+        a0[c] = (v0 && c < nbp) ? win[s0 * LDW + cs] : 0.0;
+        a1[c] = (v1 && c < nbp) ? win[s1 * LDW + cs] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < BNB; ++k) {
         if (k >= nbp) break;
-        const int lim = min(j0 + k + kl, n - 1);
+        const int lim = min(k + kl, n - 1 - j0);
         double best = -1.0;
         int bi = 0x7fffffff;
-        if (v0 && r0 >= j0 + k && r0 <= lim) { best = fabs(a0[k]); bi = r0; }
-        if (v1 && r1 >= j0 + k && r1 <= lim) {
+        if (v0 && t0 >= k && t0 <= lim) { best = fabs(a0[k]); bi = t0; }
+        if (v1 && t1 >= k && t1 <= lim) {
           const double t = fabs(a1[k]);
-          if (t > best) { best = t; bi = r1; }
+          if (t > best) { best = t; bi = t1; }
         }
         for (int off = 32; off > 0; off >>= 1) {
           const double ob = __shfl_xor(best, off);
@@ -304,46 +327,44 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
           piv[k] = p;
           if (!(best > 0.0)) s_flag |= kFlagSingular;
         }
-        // exchange rows j0+k (lane k, first slot) and p through LDS
-        const int rk = j0 + k;
-        if (r0 == rk) {
+        if (t0 == k) {
 #pragma unroll
           for (int c = 0; c < BNB; ++c) swp[c] = a0[c];
         }
-        if (v0 && r0 == p) {
+        if (v0 && t0 == p) {
 #pragma unroll
           for (int c = 0; c < BNB; ++c) swp[BNB + c] = a0[c];
         }
-        if (v1 && r1 == p) {
+        if (v1 && t1 == p) {
 #pragma unroll
           for (int c = 0; c < BNB; ++c) swp[BNB + c] = a1[c];
         }
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
-        if (p != rk) {
-          if (r0 == rk) {
+        if (p != k) {
+          if (t0 == k) {
 #pragma unroll
             for (int c = 0; c < BNB; ++c) a0[c] = swp[BNB + c];
           }
-          if (v0 && r0 == p) {
+          if (v0 && t0 == p) {
 #pragma unroll
             for (int c = 0; c < BNB; ++c) a0[c] = swp[c];
           }
-          if (v1 && r1 == p) {
+          if (v1 && t1 == p) {
 #pragma unroll
             for (int c = 0; c < BNB; ++c) a1[c] = swp[c];
           }
         }
         const double pk = swp[BNB + k];
         const double ip = (pk != 0.0) ? 1.0 / pk : 0.0;
-        if (v0 && r0 > rk) {
+        if (v0 && t0 > k) {
           const double l = a0[k] * ip;
           a0[k] = l;
 #pragma unroll
           for (int c = 0; c < BNB; ++c)
             if (c > k) a0[c] -= l * swp[BNB + c];
         }
-        if (v1 && r1 > rk) {
+        if (v1 && t1 > k) {
           const double l = a1[k] * ip;
           a1[k] = l;
 #pragma unroll
@@ -356,8 +377,9 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
 #pragma unroll
       for (int c = 0; c < BNB; ++c) {
         if (c < nbp) {
-          if (v0) WIN(r0, j0 + c) = a0[c];
-          if (v1) WIN(r1, j0 + c) = a1[c];
+          const int cs = CS(c);
+          if (v0) win[s0 * LDW + cs] = a0[c];
+          if (v1) win[s1 * LDW + cs] = a1[c];
         }
       }
     }
@@ -365,33 +387,28 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
     // (B)+(C) interchanges and unit-lower solve on the columns right of the panel (+ rhs)
     const int ncr = WC - nbp;  // columns j1 .. j0+WC-1
     for (int cc = tid; cc <= ncr; cc += BT) {
+      double* col;
+      int stride;
       if (cc < ncr) {
-        const int c = j1 + cc;
-        for (int k = 0; k < nbp; ++k) {
-          const int p = piv[k];
-          if (p != j0 + k) {
-            const double a = WIN(j0 + k, c);
-            WIN(j0 + k, c) = WIN(p, c);
-            WIN(p, c) = a;
-          }
-        }
-        for (int k = 0; k < nbp; ++k) {
-          const double a = WIN(j0 + k, c);
-          for (int i = k + 1; i < nbp; ++i) WIN(j0 + i, c) -= WIN(j0 + i, j0 + k) * a;
-        }
+        col = win + CS(nbp + cc);
+        stride = LDW;
       } else {
-        for (int k = 0; k < nbp; ++k) {
-          const int p = piv[k];
-          if (p != j0 + k) {
-            const double a = zr[(j0 + k) % H];
-            zr[(j0 + k) % H] = zr[p % H];
-            zr[p % H] = a;
-          }
+        col = zr;
+        stride = 1;
+      }
+      for (int k = 0; k < nbp; ++k) {
+        const int p = piv[k];
+        if (p != k) {
+          const int a = RS(k) * stride, b = RS(p) * stride;
+          const double t = col[a];
+          col[a] = col[b];
+          col[b] = t;
         }
-        for (int k = 0; k < nbp; ++k) {
-          const double a = zr[(j0 + k) % H];
-          for (int i = k + 1; i < nbp; ++i) zr[(j0 + i) % H] -= WIN(j0 + i, j0 + k) * a;
-        }
+      }
+      for (int k = 0; k < nbp; ++k) {
+        const double a = col[RS(k) * stride];
+        const int ck = CS(k);
+        for (int i = k + 1; i < nbp; ++i) col[RS(i) * stride] -= win[RS(i) * LDW + ck] * a;
       }
     }
     __syncthreads();
@@ -401,21 +418,26 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
       const int nc = ncr + 1;  // + rhs
       const int tr = (nr + 3) / 4, tc = (nc + 3) / 4;
       for (int t = tid; t < tr * tc; t += BT) {
-        const int ib = (t / tc) * 4, cb = (t % tc) * 4;
+        const int ti = t / tc;
+        const int ib = ti * 4, cb = (t - ti * tc) * 4;
+        int rs[4], cs[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) rs[a] = (ib + a < nr) ? RS(nbp + ib + a) : -1;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cs[b] = (cb + b < ncr) ? CS(nbp + cb + b) : (cb + b == ncr ? -2 : -1);
         double acc[4][4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
         for (int k = 0; k < nbp; ++k) {
+          const int ck = CS(k), rk = RS(k);
           double lv[4], uv[4];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) lv[a] = (ib + a < nr) ? WIN(j1 + ib + a, j0 + k) : 0.0;
+          for (int a = 0; a < 4; ++a) lv[a] = (rs[a] >= 0) ? win[rs[a] * LDW + ck] : 0.0;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int cc = cb + b;
-            uv[b] = (cc < ncr) ? WIN(j0 + k, j1 + cc) : (cc == ncr ? zr[(j0 + k) % H] : 0.0);
-          }
+          for (int b = 0; b < 4; ++b)
+            uv[b] = (cs[b] >= 0) ? win[rk * LDW + cs[b]] : (cs[b] == -2 ? zr[rk] : 0.0);
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -423,13 +445,11 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          if (ib + a >= nr) continue;
-          const int i = j1 + ib + a;
+          if (rs[a] < 0) continue;
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
-            const int cc = cb + b;
-            if (cc < ncr) WIN(i, j1 + cc) -= acc[a][b];
-            else if (cc == ncr) zr[i % H] -= acc[a][b];
+            if (cs[b] >= 0) win[rs[a] * LDW + cs[b]] -= acc[a][b];
+            else if (cs[b] == -2) zr[rs[a]] -= acc[a][b];
           }
         }
       }
@@ -437,41 +457,52 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
     __syncthreads();
     // (E) U rows and eliminated rhs out
     for (int e = tid; e < nbp * WU; e += BT) {
-      const int r = j0 + e / WU, t = e % WU;
-      UR[(long long)r * WU + t] = (r + t < n) ? WIN(r, r + t) : 0.0;
+      const int r = e / WU, t = e - r * WU;
+      UR[(long long)(j0 + r) * WU + t] = (j0 + r + t < n) ? win[RS(r) * LDW + CS(r + t)] : 0.0;
     }
-    for (int r = j0 + tid; r < j1; r += BT) x[r] = zr[r % H];
+    for (int r = tid; r < nbp; r += BT) x[j0 + r] = zr[RS(r)];
     __syncthreads();
     // (F) slide: retired rows' slots get rows +H, retired columns' slots get columns +WC
     for (int e = tid; e < (H - nbp) * nbp; e += BT) {
-      const int i = j1 + e / nbp, c = j0 + WC + e % nbp;
-      WIN(i, c) = 0.0;
+      const int i = e / nbp, c = e - i * nbp;
+      win[RS(nbp + i) * LDW + CS(WC + c)] = 0.0;
     }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int e = tid + q * BT;
-      if (use_pf && e < npf) WIN(j0 + H + e / WC, j1 + e % WC) = pf[q];
+      if (use_pf && e < npf) {
+        const int rr = e / WC;
+        win[RS(rr) * LDW + CS(nbp + e - rr * WC)] = pf[q];
+      }
     }
     if (!use_pf)
-      for (int e = tid; e < npf; e += BT) WIN(j0 + H + e / WC, j1 + e % WC) = orig(j0 + H + e / WC, j1 + e % WC);
-    for (int r = j0 + H + tid; r < j0 + H + nbp; r += BT) zr[r % H] = (r < n) ? rhs[r] : 0.0;
+      for (int e = tid; e < npf; e += BT) {
+        const int rr = e / WC;
+        win[RS(rr) * LDW + CS(nbp + e - rr * WC)] = orig(j0 + H + rr, j1 + e - rr * WC);
+      }
+    for (int r = tid; r < nbp; r += BT) zr[RS(r)] = (j0 + H + r < n) ? rhs[j0 + H + r] : 0.0;
     __syncthreads();
+    j0h = RS(nbp);
+    j0w = CS(nbp);
   }
   // back substitution, BNB rows at a time: partial sums by all threads,
   // then the triangular BNB x BNB part by wave 0
-  double* xs = smem;            // ring of the last WU + BNB solutions
+  double* xs = smem;            // ring: x_c at slot c mod XR
   const int XR = WU + BNB;
   double* part = smem + XR;     // BNB partial sums
   for (int i0 = ((n - 1) / BNB) * BNB; i0 >= 0; i0 -= BNB) {
     const int nbr = min(BNB, n - i0);
-    // row r = i0 + tid / 16, 16 threads per row over columns >= i0 + nbr
+    const int i0s = i0 % XR;
     {
       const int rr = tid >> 4, sub = tid & 15;
       double acc = 0.0;
       if (rr < nbr) {
         const int r = i0 + rr;
-        for (int t = (i0 + nbr - r) + sub; t < WU; t += 16)
-          if (r + t < n) acc += UR[(long long)r * WU + t] * xs[(r + t) % XR];
+        for (int t = (nbr - rr) + sub; t < WU; t += 16) {
+          int sl = i0s + rr + t;
+          sl = wrap(wrap(sl, XR), XR);
+          if (r + t < n) acc += UR[(long long)r * WU + t] * xs[sl];
+        }
       }
       for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
       if (sub == 0 && rr < nbr) part[rr] = x[i0 + rr] - acc;
@@ -481,11 +512,11 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
       for (int rr = nbr - 1; rr >= 0; --rr) {
         const int r = i0 + rr;
         double acc = 0.0;
-        if (lane > rr && lane < nbr) acc = UR[(long long)r * WU + (lane - rr)] * xs[(i0 + lane) % XR];
+        if (lane > rr && lane < nbr) acc = UR[(long long)r * WU + (lane - rr)] * xs[wrap(i0s + lane, XR)];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
         const double v = (part[rr] - acc) / UR[(long long)r * WU];
         if (lane == 0) {
-          xs[r % XR] = v;
+          xs[wrap(i0s + rr, XR)] = v;
           x[r] = v;
         }
         __builtin_amdgcn_s_waitcnt(0);
