@@ -71,6 +71,7 @@ struct mrcm_ctx {
   double *fac = nullptr, *facs = nullptr, *facp = nullptr, *scr = nullptr;
   double *tco = nullptr, *tcp = nullptr;  // block couplings of the boxes / subdomains
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
+  size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
   double *Pk = nullptr, *tr_u = nullptr, *tr_phi = nullptr, *tr_beta = nullptr;
   double *pbar = nullptr, *ubar = nullptr, *pibar = nullptr;
   double *AB = nullptr, *rhs = nullptr, *X = nullptr;
@@ -272,8 +273,17 @@ mrcm_status make_plan(mrcm_ctx* c) {
   c->scro_n = scr;
   c->scrp_n = scrp;
   c->wave = c->d == 2;
-  for (int i = 0; i < nsub; ++i)
-    if (c->obox[i].nb > 32 || c->pbox[i].nb > 32) c->wave = false;
+  c->lds_basis = c->lds_part = c->lds_smooth = 0;
+  for (int i = 0; i < nsub; ++i) {
+    const Box& B = c->obox[i];
+    const Box& P = c->pbox[i];
+    if (B.nb > 32 || P.nb > 32) c->wave = false;
+    const int bm0 = B.hi[0] - B.lo[0], bm1 = B.hi[1] - B.lo[1];
+    c->lds_basis = std::max(c->lds_basis, wave_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
+    c->lds_smooth = std::max(c->lds_smooth, wave_lds_bytes(bm0, bm1, 1));
+    c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1));
+  }
+  if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024) c->wave = false;
 
   // interfaces and their test functions
   c->ifc.clear();
@@ -550,9 +560,11 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
   if (c->wave) {
     HIPCHK(c, launch_basis_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
-                             c->tco, c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
+                             c->tco, c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags,
+                             c->lds_basis, s));
     HIPCHK(c, launch_particular_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
-                                  c->facp, c->tcp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
+                                  c->facp, c->tcp, c->scr, c->pbar, c->ubar, c->pibar, c->flags,
+                                  c->lds_part, s));
   } else {
     HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
                            c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
@@ -605,7 +617,8 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
       const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
       if (c->wave) {
         HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f,
-                                  c->bcv, c->beta_sm, fac, c->tco, c->scr, c->p, c->gflux, s));
+                                  c->bcv, c->beta_sm, fac, c->tco, c->scr, c->p, c->gflux,
+                                  c->lds_smooth, s));
       } else {
         HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
                                 c->beta_sm, fac, nullptr, nullptr, c->scr, c->p, c->gflux, c->prec,

@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict_
         xs[js] = v;
         x[j] = v;
       }
-      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
       js = (js == 0) ? CW - 1 : js - 1;
     }
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
 #pragma unroll
           for (int c = 0; c < BNB; ++c) swp[BNB + c] = a1[c];
         }
-        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_s_waitcnt(0xC07F);
         __builtin_amdgcn_wave_barrier();
         if (p != k) {
           if (t0 == k) {
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
           for (int c = 0; c < BNB; ++c)
             if (c > k) a1[c] -= l * swp[BNB + c];
         }
-        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_s_waitcnt(0xC07F);
         __builtin_amdgcn_wave_barrier();
       }
 #pragma unroll
@@ -485,13 +485,47 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
     j0h = RS(nbp);
     j0w = CS(nbp);
   }
-  // back substitution, BNB rows at a time: partial sums by all threads,
-  // then the triangular BNB x BNB part by wave 0
+  // back substitution, BNB rows at a time.  The U rows of the block are
+  // staged in LDS (the next block's rows are prefetched into registers
+  // meanwhile); partial sums with the known solutions by all threads, then
+  // the triangular BNB x BNB part by wave 0.
   double* xs = smem;            // ring: x_c at slot c mod XR
   const int XR = WU + BNB;
-  double* part = smem + XR;     // BNB partial sums
-  for (int i0 = ((n - 1) / BNB) * BNB; i0 >= 0; i0 -= BNB) {
+  double* part = xs + XR;       // BNB partial sums
+  double* ub = part + BNB;      // BNB x WU staged U rows
+  const int last = ((n - 1) / BNB) * BNB;
+  const int nub = BNB * WU;
+  const bool pf_ok = nub <= PF * BT;
+  double pu[PF];
+  auto fetch = [&](int i0) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * BT;
+      pu[q] = 0.0;
+      if (e < nub) {
+        const int r = i0 + e / WU;
+        if (r < n) pu[q] = UR[(long long)i0 * WU + e];
+      }
+    }
+  };
+  if (pf_ok) fetch(last);
+  __syncthreads();
+  for (int i0 = last; i0 >= 0; i0 -= BNB) {
     const int nbr = min(BNB, n - i0);
+    if (pf_ok) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int e = tid + q * BT;
+        if (e < nub) ub[e] = pu[q];
+      }
+      if (i0 - BNB >= 0) fetch(i0 - BNB);
+    } else {
+      for (int e = tid; e < nub; e += BT) {
+        const int r = i0 + e / WU;
+        ub[e] = (r < n) ? UR[(long long)i0 * WU + e] : 0.0;
+      }
+    }
+    __syncthreads();
     const int i0s = i0 % XR;
     {
       const int rr = tid >> 4, sub = tid & 15;
@@ -499,9 +533,8 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
       if (rr < nbr) {
         const int r = i0 + rr;
         for (int t = (nbr - rr) + sub; t < WU; t += 16) {
-          int sl = i0s + rr + t;
-          sl = wrap(wrap(sl, XR), XR);
-          if (r + t < n) acc += UR[(long long)r * WU + t] * xs[sl];
+          const int sl = wrap(i0s + rr + t, XR);
+          if (r + t < n) acc += ub[rr * WU + t] * xs[sl];
         }
       }
       for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
@@ -510,18 +543,15 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
     __syncthreads();
     if (tid < 64) {
       for (int rr = nbr - 1; rr >= 0; --rr) {
-        const int r = i0 + rr;
         double acc = 0.0;
-        if (lane > rr && lane < nbr) acc = UR[(long long)r * WU + (lane - rr)] * xs[wrap(i0s + lane, XR)];
+        if (lane > rr && lane < nbr) acc = ub[rr * WU + (lane - rr)] * xs[wrap(i0s + lane, XR)];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        const double v = (part[rr] - acc) / UR[(long long)r * WU];
-        if (lane == 0) {
-          xs[wrap(i0s + rr, XR)] = v;
-          x[r] = v;
-        }
-        __builtin_amdgcn_s_waitcnt(0);
+        const double v = (part[rr] - acc) / ub[rr * WU];
+        if (lane == 0) xs[wrap(i0s + rr, XR)] = v;
+        __builtin_amdgcn_s_waitcnt(0xC07F);
         __builtin_amdgcn_wave_barrier();
       }
+      if (lane < nbr) x[i0 + lane] = xs[wrap(i0s + lane, XR)];
     }
     __syncthreads();
   }
@@ -578,7 +608,7 @@ hipError_t launch_bandlu_solve(double* RB, int ldab, int n, int kl, int ku, doub
   double* UR = RB + (long long)n * (kl + ku + 1);  // U rows follow the input rows
   const size_t maxlds = 160 * 1024 - 256;
   const size_t lds_blk = sizeof(double) * ((size_t)(BNB + kl) * (BNB + kl + ku + 1) + (BNB + kl) + 2 * BNB);
-  const size_t lds_bs = sizeof(double) * ((size_t)(kl + ku + 1) + 2 * BNB);
+  const size_t lds_bs = sizeof(double) * ((size_t)(kl + ku + 1) * (BNB + 1) + 2 * BNB);
   if (kl + BNB <= 128 && std::max(lds_blk, lds_bs) <= maxlds) {
     const size_t lds = std::max(lds_blk, lds_bs);
     if (lds > 64 * 1024) {

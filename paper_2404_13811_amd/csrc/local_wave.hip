@@ -15,6 +15,11 @@
 // (see local.hip): forward w_j = W_j (b_j + t_{j-1} .* w_{j-1}), backward
 // x_j = w_j + W_j (t_j .* x_{j+1}).  A block product is a 16-term dot
 // product per lane followed by one exchange between the two half-waves.
+//
+// Everything a sweep touches between block steps lives in LDS: the box's
+// permeabilities (with a one-cell halo), its diagonal and couplings, and
+// the right-hand sides / solutions.  The cached block inverses are streamed
+// from memory four blocks ahead of their use.
 #include "local_common.h"
 
 namespace mrcm {
@@ -22,56 +27,112 @@ namespace {
 
 constexpr int NBW = 32;
 constexpr int HB = 16;
+constexpr int RING = 4;
 
 struct WaveSmem {
   double row[2][NBW];
   double col[2][NBW];
-  double z[kMaxRhs][NBW];
-  double diag[NBW], tx[NBW], tprev[NBW], tnext[NBW];
   int flag;
+};
+
+// Dynamic LDS carve-up of one box.
+struct BoxLds {
+  double* Kt;   // (m0 + 2) x (m1 + 2) permeabilities, one-cell halo
+  double* Dg;   // ncell diagonal of A
+  double* Tx;   // ncell coupling to the x+1 neighbour (0 at the box edge)
+  double* Tn;   // ncell coupling to the next block (y+1)
+  double* X;    // nrhs x ncell right-hand sides / solutions
+  double* Z;    // nrhs x NBW staging of one block
+  int m0, m1;
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-__device__ __forceinline__ void wsync() { __syncthreads(); }
+// Single-wave synchronisation through LDS: wait for this wave's LDS
+// operations; the wave barrier keeps the compiler from moving memory
+// operations across it.
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) only
+  __builtin_amdgcn_wave_barrier();
+}
 
 __device__ __forceinline__ double half_swap(double v) { return __shfl_xor(v, 32); }
 
-// Global coordinates of in-block cell a of block j (2-D: lines along x).
-__device__ __forceinline__ void wblock_cell(const Box& B, int j, int a, int c[3]) {
-  c[0] = B.lo[0] + a;
-  c[1] = B.lo[1] + j;
-  c[2] = 0;
+__host__ __device__ inline size_t box_lds_doubles(int m0, int m1, int nrhs) {
+  const int nc = m0 * m1;
+  return (size_t)(m0 + 2) * (m1 + 2) + 3 * (size_t)nc + (size_t)nrhs * nc + (size_t)nrhs * NBW;
 }
 
-__device__ __forceinline__ int wcell_loc(const Box& B, const int c[3]) {
-  const int m0 = B.hi[0] - B.lo[0];
-  return (c[0] - B.lo[0]) + m0 * (c[1] - B.lo[1]);
+__device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs) {
+  BoxLds s;
+  s.m0 = B.hi[0] - B.lo[0];
+  s.m1 = B.hi[1] - B.lo[1];
+  const int nc = s.m0 * s.m1;
+  s.Kt = base;
+  s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2);
+  s.Tx = s.Dg + nc;
+  s.Tn = s.Tx + nc;
+  s.X = s.Tn + nc;
+  s.Z = s.X + (size_t)nrhs * nc;
+  return s;
 }
 
-// Block coefficients of block j into LDS: diag, tx (to x+1), tnext (to y+1).
-__device__ __forceinline__ void wload_coefs(const Geo& g, const Box& B, const double* K,
-                                            double beta, int j, WaveSmem& sm) {
+// K at global cell (x, y), which must lie in the box or its halo.
+__device__ __forceinline__ double kat(const BoxLds& s, const Box& B, int x, int y) {
+  return s.Kt[(y - B.lo[1] + 1) * (s.m0 + 2) + (x - B.lo[0] + 1)];
+}
+
+// Load the K tile and the matrix coefficients of the box into LDS.
+__device__ void load_box(const Geo& g, const Box& B, const double* K, double beta, BoxLds& s) {
   const int L = lane_id();
-  if (L < B.nb) {
-    int c[3];
-    wblock_cell(B, j, L, c);
-    CellCoef cc = cell_coef(g, B, K, c, beta);
-    sm.diag[L] = cc.diag;
-    sm.tx[L] = cc.tp[0];
-    sm.tnext[L] = cc.tp[1];
-  } else if (L < NBW) {
-    sm.diag[L] = 1.0;
-    sm.tx[L] = 0.0;
-    sm.tnext[L] = 0.0;
+  const int W2 = s.m0 + 2, H2 = s.m1 + 2;
+  for (int e = L; e < W2 * H2; e += 64) {
+    const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
+    s.Kt[e] = (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K[x + g.n[0] * y] : 1.0;
   }
+  wsync();
+  const int nc = s.m0 * s.m1;
+  for (int loc = L; loc < nc; loc += 64) {
+    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
+    const double kc = kat(s, B, x, y);
+    double diag = 0.0, tx = 0.0, tn = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0);
+        const int oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+        const int t = a == 0 ? ox : oy;
+        if (t < 0 || t >= g.n[a]) {
+          if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area / g.h;
+          continue;
+        }
+        const double ko = kat(s, B, ox, oy);
+        const bool inside = ox >= B.lo[0] && ox < B.hi[0] && oy >= B.lo[1] && oy < B.hi[1];
+        if (inside) {
+          const double T = g.area * kharm(kc, ko) / g.h;
+          diag += T;
+          if (sd) {
+            if (a == 0) tx = T;
+            else tn = T;
+          }
+        } else {
+          diag += robin_T(g, kc, robin_beta(g, a, kc, ko, beta));
+        }
+      }
+    s.Dg[loc] = diag;
+    s.Tx[loc] = tx;
+    s.Tn[loc] = tn;
+  }
+  wsync();
 }
 
 // S_j (column c, my half) into w; w holds W_{j-1} on entry when j > 0.
-__device__ __forceinline__ void wbuild(int nb, bool first, const WaveSmem& sm, double w[HB]) {
+__device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
-  const double tc = sm.tprev[c];
+  const double* D = s.Dg + j * nb;
+  const double* Tx = s.Tx + j * nb;
+  const double* Tp = s.Tn + (j - 1) * nb;
+  const double tc = (j > 0 && c < nb) ? Tp[c] : 0.0;
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
     const int r = HB * h + i;
@@ -79,8 +140,8 @@ __device__ __forceinline__ void wbuild(int nb, bool first, const WaveSmem& sm, d
     if (r >= nb || c >= nb) {
       v = (r == c) ? 1.0 : 0.0;
     } else {
-      v = (r == c) ? sm.diag[c] : (r == c - 1) ? -sm.tx[r] : (r == c + 1) ? -sm.tx[c] : 0.0;
-      if (!first) v -= sm.tprev[r] * tc * w[i];
+      v = (r == c) ? D[c] : (r == c - 1) ? -Tx[r] : (r == c + 1) ? -Tx[c] : 0.0;
+      if (j > 0) v -= Tp[r] * tc * w[i];
     }
     w[i] = v;
   }
@@ -118,11 +179,9 @@ __device__ __forceinline__ void wgj(int nb, WaveSmem& sm, double w[HB]) {
   wsync();
 }
 
-// y_k = W z_k for k < nrhs (z in sm.z), W symmetric held in w.  Result for
-// row r returned in both half-lanes of column r.
+// Row c of W z (W symmetric, my half in w), summed over both halves.
 __device__ __forceinline__ double wgemv_one(const double w[HB], const double* z) {
-  const int L = lane_id();
-  const int h = L >> 5;
+  const int h = lane_id() >> 5;
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < HB; ++i) acc = fma(w[i], z[HB * h + i], acc);
@@ -139,25 +198,58 @@ __device__ __forceinline__ void wload_block(const double* Wj, int nb, double w[H
   }
 }
 
-// Forward sweep fused with the factorisation.  Right-hand sides in S
-// (S[k*ncell + cell]) are overwritten by w_j; inverses written to Wg and
-// couplings t_j (to block j+1) to Tg.
-__device__ void wfactor_forward(const Geo& g, const Box& B, const double* K, double beta,
-                                double* Wg, double* Tg, double* S, int nrhs, WaveSmem& sm) {
+// Forward step of block j for all right-hand sides, inverse in w:
+// X_j <- W_j (X_j + t_{j-1} .* X_{j-1}).
+__device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
+                                         const double w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    double v = 0.0;
+    if (r < nb) {
+      v = s.X[k * ncell + j * nb + r];
+      if (j > 0) v += s.Tn[(j - 1) * nb + r] * s.X[k * ncell + (j - 1) * nb + r];
+    }
+    s.Z[k * NBW + r] = v;
+  }
+  wsync();
+  for (int k = 0; k < nrhs; ++k) {
+    const double y = wgemv_one(w, s.Z + k * NBW);
+    if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] = y;
+  }
+  wsync();
+}
+
+// Backward step of block j: X_j <- X_j + W_j (t_j .* X_{j+1}).
+__device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
+                                         const double w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    s.Z[k * NBW + r] = (r < nb) ? s.Tn[j * nb + r] * s.X[k * ncell + (j + 1) * nb + r] : 0.0;
+  }
+  wsync();
+  for (int k = 0; k < nrhs; ++k) {
+    const double y = wgemv_one(w, s.Z + k * NBW);
+    if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] += y;
+  }
+  wsync();
+}
+
+// Factorisation fused with the forward sweep; inverses to Wg, couplings to Tg.
+__device__ void factor_forward(const Box& B, double* Wg, double* Tg, int nrhs, const BoxLds& s,
+                               WaveSmem& sm) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
   const int nb = B.nb;
+  for (int e = L; e < B.ncell; e += 64) Tg[e] = s.Tn[e];
   double w[HB];
 #pragma unroll
   for (int i = 0; i < HB; ++i) w[i] = 0.0;
   for (int j = 0; j < B.nblk; ++j) {
-    wsync();
-    if (L < NBW) sm.tprev[L] = (j > 0) ? sm.tnext[L] : 0.0;
-    wsync();
-    wload_coefs(g, B, K, beta, j, sm);
-    wsync();
-    if (L < nb) Tg[j * nb + L] = sm.tnext[L];
-    wbuild(nb, j == 0, sm, w);
+    wbuild(nb, j, s, w);
     wgj(nb, sm, w);
     double* Wj = Wg + (long long)j * nb * nb;
 #pragma unroll
@@ -165,80 +257,48 @@ __device__ void wfactor_forward(const Geo& g, const Box& B, const double* K, dou
       const int r = HB * h + i;
       if (r < nb && c < nb) Wj[r * nb + c] = w[i];
     }
-    // forward step for every right-hand side
-    for (int e = L; e < nrhs * NBW; e += 64) {
-      const int k = e / NBW, r = e % NBW;
-      double v = 0.0;
-      if (r < nb) {
-        v = S[(long long)k * B.ncell + j * nb + r];
-        if (j > 0) v += sm.tprev[r] * S[(long long)k * B.ncell + (j - 1) * nb + r];
-      }
-      sm.z[k][r] = v;
-    }
-    wsync();
-    for (int k = 0; k < nrhs; ++k) {
-      const double y = wgemv_one(w, sm.z[k]);
-      if (h == 0 && c < nb) S[(long long)k * B.ncell + j * nb + c] = y;
-    }
+    fwd_step(nb, B.ncell, j, nrhs, s, w);
   }
-  wsync();
 }
 
-// Forward sweep with cached inverses.
-__device__ void wforward(const Box& B, const double* Wg, const double* Tg, double* S, int nrhs,
-                         WaveSmem& sm) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-  const int nb = B.nb;
-  double w[HB], wn[HB];
-  wload_block(Wg, nb, wn);
-  for (int j = 0; j < B.nblk; ++j) {
+// Sweeps with the cached inverses streamed from memory, RING blocks ahead.
+__device__ void forward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
+  const int nb = B.nb, nblk = B.nblk;
+  const long long bs = (long long)nb * nb;
+  double w[RING][HB];
 #pragma unroll
-    for (int i = 0; i < HB; ++i) w[i] = wn[i];
-    if (j + 1 < B.nblk) wload_block(Wg + (long long)(j + 1) * nb * nb, nb, wn);
-    wsync();
-    for (int e = L; e < nrhs * NBW; e += 64) {
-      const int k = e / NBW, r = e % NBW;
-      double v = 0.0;
-      if (r < nb) {
-        v = S[(long long)k * B.ncell + j * nb + r];
-        if (j > 0) v += Tg[(j - 1) * nb + r] * S[(long long)k * B.ncell + (j - 1) * nb + r];
+  for (int q = 0; q < RING; ++q)
+    if (q < nblk) wload_block(Wg + q * bs, nb, w[q]);
+  for (int j0 = 0; j0 < nblk; j0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int j = j0 + q;
+      if (j < nblk) {
+        fwd_step(nb, B.ncell, j, nrhs, s, w[q]);
+        if (j + RING < nblk) wload_block(Wg + (j + RING) * bs, nb, w[q]);
       }
-      sm.z[k][r] = v;
-    }
-    wsync();
-    for (int k = 0; k < nrhs; ++k) {
-      const double y = wgemv_one(w, sm.z[k]);
-      if (h == 0 && c < nb) S[(long long)k * B.ncell + j * nb + c] = y;
     }
   }
-  wsync();
 }
 
-// Backward sweep with cached inverses.
-__device__ void wbackward(const Box& B, const double* Wg, const double* Tg, double* S, int nrhs,
-                          WaveSmem& sm) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-  const int nb = B.nb;
-  double w[HB], wn[HB];
-  if (B.nblk >= 2) wload_block(Wg + (long long)(B.nblk - 2) * nb * nb, nb, wn);
-  for (int j = B.nblk - 2; j >= 0; --j) {
+__device__ void backward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
+  const int nb = B.nb, nblk = B.nblk;
+  const long long bs = (long long)nb * nb;
+  double w[RING][HB];
+  // block j = nblk - 2 - t uses ring slot t % RING
 #pragma unroll
-    for (int i = 0; i < HB; ++i) w[i] = wn[i];
-    if (j >= 1) wload_block(Wg + (long long)(j - 1) * nb * nb, nb, wn);
-    wsync();
-    for (int e = L; e < nrhs * NBW; e += 64) {
-      const int k = e / NBW, r = e % NBW;
-      sm.z[k][r] = (r < nb) ? Tg[j * nb + r] * S[(long long)k * B.ncell + (j + 1) * nb + r] : 0.0;
-    }
-    wsync();
-    for (int k = 0; k < nrhs; ++k) {
-      const double y = wgemv_one(w, sm.z[k]);
-      if (h == 0 && c < nb) S[(long long)k * B.ncell + j * nb + c] += y;
+  for (int q = 0; q < RING; ++q)
+    if (nblk - 2 - q >= 0) wload_block(Wg + (nblk - 2 - q) * bs, nb, w[q]);
+  for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int j = nblk - 2 - (t0 + q);
+      if (j >= 0) {
+        bwd_step(nb, B.ncell, j, nrhs, s, w[q]);
+        if (j - RING >= 0) wload_block(Wg + (j - RING) * bs, nb, w[q]);
+      }
     }
   }
-  wsync();
 }
 
 __device__ __forceinline__ void womega(const Geo& g, int sub, int lo[3], int hi[3]) {
@@ -251,85 +311,112 @@ __device__ __forceinline__ void womega(const Geo& g, int sub, int lo[3], int hi[
   hi[2] = 1;
 }
 
-__device__ __forceinline__ bool win_box(const Box& B, const int c[3]) {
-  return c[0] >= B.lo[0] && c[0] < B.hi[0] && c[1] >= B.lo[1] && c[1] < B.hi[1];
+__device__ __forceinline__ bool win_box(const Box& B, int x, int y) {
+  return x >= B.lo[0] && x < B.hi[0] && y >= B.lo[1] && y < B.hi[1];
 }
 
 __device__ __forceinline__ int wneighbor(const Geo& g, int sub, int q) {
-  const int a = q >> 1, s = q & 1;
+  const int a = q >> 1, sd = q & 1;
   const int ia = (a == 0) ? sub % g.M[0] : sub / g.M[0];
-  const int t = ia + (s ? 1 : -1);
+  const int t = ia + (sd ? 1 : -1);
   if (t < 0 || t >= g.M[a]) return -1;
   const int stride = (a == 0) ? 1 : g.M[0];
-  return sub + (s ? stride : -stride);
+  return sub + (sd ? stride : -stride);
 }
 
-// Inner cell of face t on Gamma side q of Omega = [lo, hi) (2-D).
-__device__ __forceinline__ void wgface(const int lo[3], const int hi[3], int q, int t, int c[3]) {
-  const int a = q >> 1, s = q & 1;
-  c[2] = 0;
+// Inner cell of face t on side q of [lo, hi) (2-D).
+__device__ __forceinline__ void wgface(const int lo[3], const int hi[3], int q, int t, int& x, int& y) {
+  const int a = q >> 1, sd = q & 1;
   if (a == 0) {
-    c[0] = s ? hi[0] - 1 : lo[0];
-    c[1] = lo[1] + t;
+    x = sd ? hi[0] - 1 : lo[0];
+    y = lo[1] + t;
   } else {
-    c[1] = s ? hi[1] - 1 : lo[1];
-    c[0] = lo[0] + t;
+    y = sd ? hi[1] - 1 : lo[1];
+    x = lo[0] + t;
+  }
+}
+
+__device__ __forceinline__ int bloc(const Box& B, const BoxLds& s, int x, int y) {
+  return (x - B.lo[0]) + s.m0 * (y - B.lo[1]);
+}
+
+// Physical right-hand side (source, boundary data) of box B into out.
+__device__ void physical_rhs(const Geo& g, const Box& B, const BoxLds& s, const double* f,
+                             const double* bcv, double* out) {
+  const int nc = s.m0 * s.m1;
+  for (int loc = lane_id(); loc < nc; loc += 64) {
+    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
+    const int ci = x + g.n[0] * y;
+    double b = f[ci] * g.vol;
+    const int c[3] = {x, y, 0};
+    for (int a = 0; a < 2; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int t = c[a] + (sd ? 1 : -1);
+        if (t >= 0 && t < g.n[a]) continue;
+        const int side = 2 * a + sd;
+        const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
+        if (g.bc_type[side]) b += 2.0 * kat(s, B, x, y) * g.area / g.h * val;
+        else b -= g.area * val;
+      }
+    out[loc] = b;
   }
 }
 
 // ------------------------------------------------------------------ kernels
 
+// Steps 1-2: factor the oversampled box, solve every seed, extract
+// u and phi on Gamma_i and the restriction to Omega_i.
 __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ boxes,
                                                 const Seed* __restrict__ seeds,
                                                 const double* __restrict__ K, double beta,
                                                 double* __restrict__ fac,
                                                 double* __restrict__ tcoup,
-                                                double* __restrict__ scr, double* __restrict__ Pk,
+                                                double* __restrict__ Pk,
                                                 double* __restrict__ tr_u,
                                                 double* __restrict__ tr_phi,
                                                 double* __restrict__ tr_beta, int* flags) {
+  extern __shared__ double dsm[];
   __shared__ WaveSmem sm;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
   if (L == 0) sm.flag = 0;
   const int nrhs = B.nrhs;
-  double* S = scr + B.scr;
-  for (long long e = L; e < (long long)nrhs * B.ncell; e += 64) S[e] = 0.0;
+  BoxLds s = carve(dsm, B, nrhs);
+  load_box(g, B, K, beta, s);
+  const int nc = B.ncell;
+  for (int e = L; e < nrhs * nc; e += 64) s.X[e] = 0.0;
   wsync();
   for (int k = 0; k < nrhs; ++k) {
     const Seed sd = seeds[B.seed0 + k];
-    const int a = sd.side >> 1, s = sd.side & 1;
-    const int nf = (a == 0) ? B.hi[1] - B.lo[1] : B.hi[0] - B.lo[0];
+    const int a = sd.side >> 1, so = sd.side & 1;
+    const int nf = (a == 0) ? s.m1 : s.m0;
     for (int t = L; t < nf; t += 64) {
-      int c[3], o[3];
-      if (a == 0) { c[0] = s ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
-      else { c[1] = s ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
+      int c[3];
+      if (a == 0) { c[0] = so ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
+      else { c[1] = so ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
       c[2] = 0;
-      o[0] = c[0]; o[1] = c[1]; o[2] = 0;
-      o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)];
-      const double bt = robin_beta(g, a, kc, K[gcell(g, o)], beta);
-      S[(long long)k * B.ncell + wcell_loc(B, c)] =
-          robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
+      const int ox = c[0] + (a == 0 ? (so ? 1 : -1) : 0), oy = c[1] + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, c[0], c[1]);
+      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+      s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
     }
   }
   wsync();
   double* Wg = fac + B.fac;
-  double* Tg = tcoup + B.scr;  // per-box couplings share the scratch offsets (ncell each)
-  wfactor_forward(g, B, K, beta, Wg, Tg, S, nrhs, sm);
-  wbackward(B, Wg, Tg, S, nrhs, sm);
+  factor_forward(B, Wg, tcoup + B.scr, nrhs, s, sm);
+  backward_cached(B, Wg, nrhs, s);
   int olo[3], ohi[3];
   womega(g, B.sub, olo, ohi);
   const int ncell_o = g.S[0] * g.S[1];
   for (int e = L; e < nrhs * ncell_o; e += 64) {
     const int k = e / ncell_o, t = e % ncell_o;
-    int c[3] = {olo[0] + t % g.S[0], olo[1] + t / g.S[0], 0};
-    Pk[(long long)(B.seed0 + k) * ncell_o + t] = S[(long long)k * B.ncell + wcell_loc(B, c)];
+    Pk[(long long)(B.seed0 + k) * ncell_o + t] =
+        s.X[k * nc + bloc(B, s, olo[0] + t % g.S[0], olo[1] + t / g.S[0])];
   }
   for (int q = 0; q < 4; ++q) {
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
     const bool has = wneighbor(g, B.sub, q) >= 0;
-    const int a = q >> 1, s = q & 1;
+    const int a = q >> 1, so = q & 1;
     for (int e = L; e < nrhs * nf; e += 64) {
       const int k = e / nf, t = e % nf;
       const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
@@ -338,18 +425,18 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
         tr_phi[oidx] = 0.0;
         continue;
       }
-      int c[3], o[3];
-      wgface(olo, ohi, q, t, c);
-      o[0] = c[0]; o[1] = c[1]; o[2] = 0;
-      o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)], ko = K[gcell(g, o)];
-      const double Pc = S[(long long)k * B.ncell + wcell_loc(B, c)];
+      int x, y;
+      wgface(olo, ohi, q, t, x, y);
+      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+      const double Pc = s.X[k * nc + bloc(B, s, x, y)];
       const double bt = robin_beta(g, a, kc, ko, beta);
       double u;
-      if (win_box(B, o)) {
-        u = g.area * kharm(kc, ko) / g.h * (Pc - S[(long long)k * B.ncell + wcell_loc(B, o)]) / g.area;
+      if (win_box(B, ox, oy)) {
+        u = g.area * kharm(kc, ko) / g.h * (Pc - s.X[k * nc + bloc(B, s, ox, oy)]) / g.area;
       } else {
         const Seed sd = seeds[B.seed0 + k];
+        const int c[3] = {x, y, 0};
         const double lam = (sd.side == q) ? seed_value(g, sd, B.lo, B.hi, c) : 0.0;
         u = robin_T(g, kc, bt) * (Pc - lam) / g.area;
       }
@@ -363,52 +450,33 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-__device__ void wphysical_rhs(const Geo& g, const Box& B, const double* K, const double* f,
-                              const double* bcv, double* S) {
-  for (int loc = lane_id(); loc < B.ncell; loc += 64) {
-    const int m0 = B.hi[0] - B.lo[0];
-    int c[3] = {B.lo[0] + loc % m0, B.lo[1] + loc / m0, 0};
-    const int ci = gcell(g, c);
-    double b = f[ci] * g.vol;
-    for (int a = 0; a < 2; ++a)
-      for (int s = 0; s < 2; ++s) {
-        const int t = c[a] + (s ? 1 : -1);
-        if (t >= 0 && t < g.n[a]) continue;
-        const int side = 2 * a + s;
-        const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-        if (g.bc_type[side]) b += 2.0 * K[ci] * g.area / g.h * val;
-        else b -= g.area * val;
-      }
-    S[loc] = b;
-  }
-}
-
+// Step 4: particular problem on Omega_i with zero Robin data on Gamma_i.
 __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restrict__ boxes,
                                                      const double* __restrict__ K,
                                                      const double* __restrict__ f,
                                                      const double* __restrict__ bcv, double beta,
                                                      double* __restrict__ fac,
                                                      double* __restrict__ tcoup,
-                                                     double* __restrict__ scr,
                                                      double* __restrict__ pbar,
                                                      double* __restrict__ ubar,
                                                      double* __restrict__ pibar, int* flags) {
+  extern __shared__ double dsm[];
   __shared__ WaveSmem sm;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
   if (L == 0) sm.flag = 0;
-  double* S = scr + B.scr;
-  wphysical_rhs(g, B, K, f, bcv, S);
+  BoxLds s = carve(dsm, B, 1);
+  load_box(g, B, K, beta, s);
+  physical_rhs(g, B, s, f, bcv, s.X);
   wsync();
   double* Wg = fac + B.fac;
-  double* Tg = tcoup + B.scr;
-  wfactor_forward(g, B, K, beta, Wg, Tg, S, 1, sm);
-  wbackward(B, Wg, Tg, S, 1, sm);
-  for (int t = L; t < B.ncell; t += 64) pbar[(long long)B.sub * B.ncell + t] = S[t];
+  factor_forward(B, Wg, tcoup + B.scr, 1, s, sm);
+  backward_cached(B, Wg, 1, s);
+  for (int t = L; t < B.ncell; t += 64) pbar[(long long)B.sub * B.ncell + t] = s.X[t];
   for (int q = 0; q < 4; ++q) {
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
     const bool has = wneighbor(g, B.sub, q) >= 0;
-    const int a = q >> 1, s = q & 1;
+    const int a = q >> 1, so = q & 1;
     for (int t = L; t < nf; t += 64) {
       const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
       if (!has) {
@@ -416,13 +484,12 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
         pibar[oidx] = 0.0;
         continue;
       }
-      int c[3], o[3];
-      wgface(B.lo, B.hi, q, t, c);
-      o[0] = c[0]; o[1] = c[1]; o[2] = 0;
-      o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)];
-      const double bt = robin_beta(g, a, kc, K[gcell(g, o)], beta);
-      const double u = robin_T(g, kc, bt) * S[wcell_loc(B, c)] / g.area;
+      int x, y;
+      wgface(B.lo, B.hi, q, t, x, y);
+      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, x, y);
+      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+      const double u = robin_T(g, kc, bt) * s.X[bloc(B, s, x, y)] / g.area;
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
     }
@@ -431,30 +498,31 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-// lambda = -beta u.n + pi on a Robin face of box B from the current state.
-__device__ __forceinline__ double wlambda(const Geo& g, const Box& B, const double* K,
+// lambda = -beta u.n + pi on the Robin face of box B at inside cell (x, y),
+// normal along a, side sd, from the current global state (Section 3).
+__device__ __forceinline__ double wlambda(const Geo& g, const Box& B, const BoxLds& s,
                                           const double* p, const double* gflux, double beta,
-                                          const int c[3], int a, int s) {
-  int o[3] = {c[0], c[1], 0};
-  o[a] += s ? 1 : -1;
-  const int ci = gcell(g, c), oi = gcell(g, o);
-  const double kc = K[ci], ko = K[oi];
+                                          int x, int y, int a, int sd) {
+  const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+  const int ci = x + g.n[0] * y, oi = ox + g.n[0] * oy;
+  const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
   const double bt = robin_beta(g, a, kc, ko, beta);
   if (g.l > 0) {
     const double u = g.area * kharm(kc, ko) / g.h * (p[ci] - p[oi]) / g.area;
     const double pi = p[ci] - u * g.h / (2.0 * kc);
     return -bt * u + pi;
   }
-  const int q = 2 * a + s;
+  const int q = 2 * a + sd;
   const int j = wneighbor(g, B.sub, q);
   int jlo[3], jhi[3];
   womega(g, j, jlo, jhi);
-  const int t = (a == 0) ? o[1] - jlo[1] : o[0] - jlo[0];
+  const int t = (a == 0) ? oy - jlo[1] : ox - jlo[0];
   const double uj = gflux[(long long)j * g.gstride + g.gside_off[q ^ 1] + t];
   const double pij = p[oi] - uj * g.h / (2.0 * ko);
   return bt * uj + pij;
 }
 
+// Steps 6-7: one color phase of the smoothing sweep.
 __global__ void __launch_bounds__(64) k_smooth_w(Geo g, const Box* __restrict__ boxes,
                                                  const int* __restrict__ members,
                                                  const double* __restrict__ K,
@@ -462,101 +530,130 @@ __global__ void __launch_bounds__(64) k_smooth_w(Geo g, const Box* __restrict__ 
                                                  const double* __restrict__ bcv, double beta,
                                                  const double* __restrict__ fac,
                                                  const double* __restrict__ tcoup,
-                                                 double* __restrict__ scr, double* __restrict__ p,
+                                                 double* __restrict__ p,
                                                  double* __restrict__ gflux) {
-  __shared__ WaveSmem sm;
+  extern __shared__ double dsm[];
   const Box B = boxes[members[blockIdx.x]];
   const int L = lane_id();
-  double* S = scr + B.scr;
-  const int m0 = B.hi[0] - B.lo[0];
-  for (int loc = L; loc < B.ncell; loc += 64) {
-    int c[3] = {B.lo[0] + loc % m0, B.lo[1] + loc / m0, 0};
-    const int ci = gcell(g, c);
-    const double kc = K[ci];
+  BoxLds s = carve(dsm, B, 1);
+  const int nc = B.ncell;
+  // K tile and couplings (the factor's diagonal is not needed here)
+  {
+    const int W2 = s.m0 + 2, H2 = s.m1 + 2;
+    for (int e = L; e < W2 * H2; e += 64) {
+      const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
+      s.Kt[e] = (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K[x + g.n[0] * y] : 1.0;
+    }
+    const double* Tg = tcoup + B.scr;
+    for (int e = L; e < nc; e += 64) s.Tn[e] = Tg[e];
+  }
+  wsync();
+  for (int loc = L; loc < nc; loc += 64) {
+    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
+    const int ci = x + g.n[0] * y;
+    const double kc = kat(s, B, x, y);
     double b = f[ci] * g.vol;
+    const int c[3] = {x, y, 0};
     for (int a = 0; a < 2; ++a)
-      for (int s = 0; s < 2; ++s) {
-        const int kind = face_kind(g, B, c, a, s);
+      for (int sd = 0; sd < 2; ++sd) {
+        const int kind = face_kind(g, B, c, a, sd);
         if (kind == kFaceInterior) continue;
-        const int side = 2 * a + s;
+        const int side = 2 * a + sd;
         if (kind == kFaceRobin) {
-          int o[3] = {c[0], c[1], 0};
-          o[a] += s ? 1 : -1;
-          const double bt = robin_beta(g, a, kc, K[gcell(g, o)], beta);
-          b += robin_T(g, kc, bt) * wlambda(g, B, K, p, gflux, beta, c, a, s);
+          const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+          const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+          b += robin_T(g, kc, bt) * wlambda(g, B, s, p, gflux, beta, x, y, a, sd);
         } else {
           const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
           if (kind == kFaceDir) b += 2.0 * kc * g.area / g.h * val;
           else b -= g.area * val;
         }
       }
-    S[loc] = b;
+    s.X[loc] = b;
   }
   wsync();
   const double* Wg = fac + B.fac;
-  const double* Tg = tcoup + B.scr;
-  wforward(B, Wg, Tg, S, 1, sm);
-  wbackward(B, Wg, Tg, S, 1, sm);
+  forward_cached(B, Wg, 1, s);
+  backward_cached(B, Wg, 1, s);
   int olo[3], ohi[3];
   womega(g, B.sub, olo, ohi);
   for (int q = 0; q < 4; ++q) {
     if (wneighbor(g, B.sub, q) < 0) continue;
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
-    const int a = q >> 1, s = q & 1;
+    const int a = q >> 1, so = q & 1;
     for (int t = L; t < nf; t += 64) {
-      int c[3], o[3];
-      wgface(olo, ohi, q, t, c);
-      o[0] = c[0]; o[1] = c[1]; o[2] = 0;
-      o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)], ko = K[gcell(g, o)];
-      const double xc = S[wcell_loc(B, c)];
+      int x, y;
+      wgface(olo, ohi, q, t, x, y);
+      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+      const double xc = s.X[bloc(B, s, x, y)];
       double u;
-      if (win_box(B, o)) {
-        u = g.area * kharm(kc, ko) / g.h * (xc - S[wcell_loc(B, o)]) / g.area;
+      if (win_box(B, ox, oy)) {
+        u = g.area * kharm(kc, ko) / g.h * (xc - s.X[bloc(B, s, ox, oy)]) / g.area;
       } else {
-        const double lam = wlambda(g, B, K, p, gflux, beta, c, a, s);
+        const double lam = wlambda(g, B, s, p, gflux, beta, x, y, a, so);
         u = robin_T(g, kc, robin_beta(g, a, kc, ko, beta)) * (xc - lam) / g.area;
       }
       gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
     }
   }
-  wsync();
   const int ncell_o = g.S[0] * g.S[1];
   for (int t = L; t < ncell_o; t += 64) {
-    int c[3] = {olo[0] + t % g.S[0], olo[1] + t / g.S[0], 0};
-    p[gcell(g, c)] = S[wcell_loc(B, c)];
+    const int x = olo[0] + t % g.S[0], y = olo[1] + t / g.S[0];
+    p[x + g.n[0] * y] = s.X[bloc(B, s, x, y)];
   }
+}
+
+template <typename KF>
+hipError_t set_lds(KF kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+  return hipSuccess;
 }
 
 }  // namespace
 
+size_t wave_lds_bytes(int m0, int m1, int nrhs) {
+  return sizeof(double) * box_lds_doubles(m0, m1, nrhs);
+}
+
 hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                           const double* K, double beta, double* fac, double* tcoup, double* scr,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, int* flags,
-                          hipStream_t s) {
+                          size_t lds, hipStream_t s) {
+  (void)scr;
   if (nbox <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_basis_w, dim3(nbox), dim3(64), 0, s, g, boxes, seeds, K, beta, fac, tcoup,
-                     scr, Pk, tr_u, tr_phi, tr_beta, flags);
+  hipError_t e = set_lds(k_basis_w, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_basis_w, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac, tcoup,
+                     Pk, tr_u, tr_phi, tr_beta, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const double* K,
                                const double* f, const double* bcv, double beta, double* fac,
                                double* tcoup, double* scr, double* pbar, double* ubar,
-                               double* pibar, int* flags, hipStream_t s) {
+                               double* pibar, int* flags, size_t lds, hipStream_t s) {
+  (void)scr;
   if (nbox <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_particular_w, dim3(nbox), dim3(64), 0, s, g, boxes, K, f, bcv, beta, fac,
-                     tcoup, scr, pbar, ubar, pibar, flags);
+  hipError_t e = set_lds(k_particular_w, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_particular_w, dim3(nbox), dim3(64), lds, s, g, boxes, K, f, bcv, beta, fac,
+                     tcoup, pbar, ubar, pibar, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* tcoup, double* scr, double* p,
-                           double* gflux, hipStream_t s) {
+                           double* gflux, size_t lds, hipStream_t s) {
+  (void)scr;
   if (nmem <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_smooth_w, dim3(nmem), dim3(64), 0, s, g, boxes, members, K, f, bcv, beta,
-                     fac, tcoup, scr, p, gflux);
+  hipError_t e = set_lds(k_smooth_w, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_smooth_w, dim3(nmem), dim3(64), lds, s, g, boxes, members, K, f, bcv, beta,
+                     fac, tcoup, p, gflux);
   return hipGetLastError();
 }
 

@@ -95,18 +95,19 @@ hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int
                          int max_refine, int* iters, double* resid, int* flags, hipStream_t s);
 
 // one-wavefront-per-box 2-D kernels (local_wave.hip), blocks of <= 32 cells
+size_t wave_lds_bytes(int m0, int m1, int nrhs);
 hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                           const double* K, double beta, double* fac, double* tcoup, double* scr,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, int* flags,
-                          hipStream_t s);
+                          size_t lds, hipStream_t s);
 hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const double* K,
                                const double* f, const double* bcv, double beta, double* fac,
                                double* tcoup, double* scr, double* pbar, double* ubar,
-                               double* pibar, int* flags, hipStream_t s);
+                               double* pibar, int* flags, size_t lds, hipStream_t s);
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* tcoup, double* scr, double* p,
-                           double* gflux, hipStream_t s);
+                           double* gflux, size_t lds, hipStream_t s);
 
 // interface system (iface.hip)
 hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,
