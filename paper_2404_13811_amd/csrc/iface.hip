@@ -231,14 +231,71 @@ __global__ void __launch_bounds__(LU_THREADS) k_bandlu(const double* __restrict_
   if (tid == 0 && s_flag) atomicOr(flags, s_flag);
 }
 
+// Wave-wide maximum of a 64-bit key (all lanes receive it), using DPP
+// quad permutations and row rotations within rows of 16 lanes, then the
+// gfx950 permlane16/permlane32 swaps across rows.
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v & 0xffffffffu), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long k) {
+  k = umax64(k, dpp64<0xB1>(k));   // quad_perm(1,0,3,2)
+  k = umax64(k, dpp64<0x4E>(k));   // quad_perm(2,3,0,1)
+  k = umax64(k, dpp64<0x124>(k));  // row_ror:4
+  k = umax64(k, dpp64<0x128>(k));  // row_ror:8
+  {
+    const int lo = (int)(unsigned)(k & 0xffffffffu), hi = (int)(unsigned)(k >> 32);
+    const auto l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    k = umax64(((unsigned long long)(unsigned)h2[0] << 32) | (unsigned)l2[0],
+               ((unsigned long long)(unsigned)h2[1] << 32) | (unsigned)l2[1]);
+  }
+  {
+    const int lo = (int)(unsigned)(k & 0xffffffffu), hi = (int)(unsigned)(k >> 32);
+    const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    k = umax64(((unsigned long long)(unsigned)h2[0] << 32) | (unsigned)l2[0],
+               ((unsigned long long)(unsigned)h2[1] << 32) | (unsigned)l2[1]);
+  }
+  return k;
+}
+
+// Pivot key: |v| (non-negative, so its bit pattern orders like the value)
+// with the low 11 mantissa bits replaced by 2047 - row offset, so that the
+// maximum picks the largest magnitude and, among equal truncated
+// magnitudes, the smallest row.  Non-candidates use key 0.
+__device__ __forceinline__ unsigned long long pivot_key(double v, int t) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+  return (b & ~0x7FFull) | (unsigned long long)(2047 - t);
+}
+
+// Broadcast lane `src` (wave-uniform) of a double to all lanes.
+__device__ __forceinline__ double bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Blocked variant: panels of BNB columns.  Window rows [j0, j0+H) and
 // columns [j0, j0+WC) live in LDS in circular slots, H = BNB + kl,
 // WC = BNB + kl + ku.  Per panel: wave 0 factors the H x BNB panel with
-// partial pivoting in registers; all threads apply the row interchanges and
-// the unit-lower triangular solve to their columns (U12), then the
-// register-tiled rank-BNB update of the trailing window, then the window
-// slides by BNB rows / columns (the entering rows are prefetched into
-// registers at the start of the panel).
+// partial pivoting in registers; every thread then applies the panel's row
+// permutation (as one gather) and the unit-lower triangular solve to one
+// column right of the panel (U12), then the register-tiled rank-BNB update
+// of the trailing window, then the window slides by BNB rows / columns (the
+// entering rows are prefetched into registers at the start of the panel).
 constexpr int BNB = 16;
 constexpr int BT = 256;
 constexpr int PF = 16;  // prefetched values per thread
@@ -258,6 +315,8 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
   double* zr = win + H * LDW;    // H
   double* swp = zr + H;          // 2 * BNB
   __shared__ int piv[BNB];       // pivot row offsets (relative to j0)
+  __shared__ int perm_src[128];  // row permutation of the panel (offsets)
+  __shared__ int mv_pos[2 * BNB], mv_src[2 * BNB];
   __shared__ int s_flag;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -278,7 +337,7 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
   for (int j0 = 0; j0 < n; j0 += BNB) {
     const int nbp = min(BNB, n - j0);
     const int j1 = j0 + nbp;
-    auto RS = [&](int t) { return wrap(j0h + t, H); };          // slot of row j0 + t, t < H
+    auto RS = [&](int t) { return wrap(j0h + t, H); };  // slot of row j0 + t, t < H
     auto CS = [&](int t) { int v = j0w + t; v = wrap(v, WC); return wrap(v, WC); };  // column j0 + t
     // prefetch the rows entering the window after this panel
     double pf[PF];
@@ -310,23 +369,13 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
       for (int k = 0; k < BNB; ++k) {
         if (k >= nbp) break;
         const int lim = min(k + kl, n - 1 - j0);
-        double best = -1.0;
-        int bi = 0x7fffffff;
-        if (v0 && t0 >= k && t0 <= lim) { best = fabs(a0[k]); bi = t0; }
-        if (v1 && t1 >= k && t1 <= lim) {
-          const double t = fabs(a1[k]);
-          if (t > best) { best = t; bi = t1; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ob = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        const int p = bi;
-        if (lane == 0) {
-          piv[k] = p;
-          if (!(best > 0.0)) s_flag |= kFlagSingular;
-        }
+        unsigned long long key = 0;
+        if (v0 && t0 >= k && t0 <= lim) key = pivot_key(a0[k], t0);
+        if (v1 && t1 >= k && t1 <= lim) key = umax64(key, pivot_key(a1[k], t1));
+        key = wave_max_key(key);
+        const int p = 2047 - (int)(key & 0x7FFull);
+        if (lane == 0) piv[k] = p;
+        // exchange rows k and p through LDS; the pivot row lands in swp[BNB..]
         if (t0 == k) {
 #pragma unroll
           for (int c = 0; c < BNB; ++c) swp[c] = a0[c];
@@ -339,8 +388,7 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
 #pragma unroll
           for (int c = 0; c < BNB; ++c) swp[BNB + c] = a1[c];
         }
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
         if (p != k) {
           if (t0 == k) {
 #pragma unroll
@@ -356,6 +404,7 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
           }
         }
         const double pk = swp[BNB + k];
+        if (lane == 0 && !(pk != 0.0)) s_flag |= kFlagSingular;
         const double ip = (pk != 0.0) ? 1.0 / pk : 0.0;
         if (v0 && t0 > k) {
           const double l = a0[k] * ip;
@@ -371,8 +420,7 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
           for (int c = 0; c < BNB; ++c)
             if (c > k) a1[c] -= l * swp[BNB + c];
         }
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
       }
 #pragma unroll
       for (int c = 0; c < BNB; ++c) {
@@ -382,9 +430,28 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
           if (v1) win[s1 * LDW + cs] = a1[c];
         }
       }
+      // net row permutation of the panel: position t takes row perm_src[t]
+      if (t0 < H) perm_src[t0] = t0;
+      if (t1 < H) perm_src[t1] = t1;
+      wave_lds_sync();
+      if (lane == 0) {
+        for (int k = 0; k < nbp; ++k) {
+          const int p = piv[k];
+          const int tmp = perm_src[k];
+          perm_src[k] = perm_src[p];
+          perm_src[p] = tmp;
+        }
+      }
+      wave_lds_sync();
+      if (lane < 2 * BNB) {
+        const int pos = (lane < BNB) ? lane : piv[lane - BNB];
+        const bool ok = (lane < BNB) ? lane < nbp : (lane - BNB) < nbp;
+        mv_pos[lane] = ok ? pos : -1;
+        mv_src[lane] = ok ? perm_src[pos] : -1;
+      }
     }
     __syncthreads();
-    // (B)+(C) interchanges and unit-lower solve on the columns right of the panel (+ rhs)
+    // (B)+(C) permutation and unit-lower solve on each column right of the panel (+ rhs)
     const int ncr = WC - nbp;  // columns j1 .. j0+WC-1
     for (int cc = tid; cc <= ncr; cc += BT) {
       double* col;
@@ -396,20 +463,25 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
         col = zr;
         stride = 1;
       }
-      for (int k = 0; k < nbp; ++k) {
-        const int p = piv[k];
-        if (p != k) {
-          const int a = RS(k) * stride, b = RS(p) * stride;
-          const double t = col[a];
-          col[a] = col[b];
-          col[b] = t;
-        }
-      }
-      for (int k = 0; k < nbp; ++k) {
-        const double a = col[RS(k) * stride];
+      double mv[2 * BNB];
+#pragma unroll
+      for (int q = 0; q < 2 * BNB; ++q) mv[q] = (mv_src[q] >= 0) ? col[RS(mv_src[q]) * stride] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 2 * BNB; ++q)
+        if (mv_src[q] >= 0 && mv_src[q] != mv_pos[q]) col[RS(mv_pos[q]) * stride] = mv[q];
+      double u[BNB];
+#pragma unroll
+      for (int k = 0; k < BNB; ++k) u[k] = (k < nbp) ? col[RS(k) * stride] : 0.0;
+#pragma unroll
+      for (int k = 0; k < BNB; ++k) {
         const int ck = CS(k);
-        for (int i = k + 1; i < nbp; ++i) col[RS(i) * stride] -= win[RS(i) * LDW + ck] * a;
+#pragma unroll
+        for (int i = k + 1; i < BNB; ++i)
+          if (i < nbp) u[i] -= win[RS(i) * LDW + ck] * u[k];
       }
+#pragma unroll
+      for (int k = 0; k < BNB; ++k)
+        if (k < nbp) col[RS(k) * stride] = u[k];
     }
     __syncthreads();
     // (D) trailing update, rows [j1, j0+H), columns [j1, j0+WC) and the rhs column
@@ -488,7 +560,8 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
   // back substitution, BNB rows at a time.  The U rows of the block are
   // staged in LDS (the next block's rows are prefetched into registers
   // meanwhile); partial sums with the known solutions by all threads, then
-  // the triangular BNB x BNB part by wave 0.
+  // the triangular BNB x BNB part by wave 0, column by column: lane r keeps
+  // its running right-hand side and x_c is broadcast with readlane.
   double* xs = smem;            // ring: x_c at slot c mod XR
   const int XR = WU + BNB;
   double* part = xs + XR;       // BNB partial sums
@@ -542,16 +615,18 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
     }
     __syncthreads();
     if (tid < 64) {
-      for (int rr = nbr - 1; rr >= 0; --rr) {
-        double acc = 0.0;
-        if (lane > rr && lane < nbr) acc = ub[rr * WU + (lane - rr)] * xs[wrap(i0s + lane, XR)];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        const double v = (part[rr] - acc) / ub[rr * WU];
-        if (lane == 0) xs[wrap(i0s + rr, XR)] = v;
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        __builtin_amdgcn_wave_barrier();
+      double rsd = (lane < nbr) ? part[lane] : 0.0;
+      double xv = 0.0;
+      for (int c = nbr - 1; c >= 0; --c) {
+        const double xc_local = (lane == c) ? rsd / ub[c * WU] : 0.0;
+        const double xc = bcast(xc_local, c);
+        if (lane == c) xv = xc;
+        if (lane < c) rsd -= ub[lane * WU + (c - lane)] * xc;
       }
-      if (lane < nbr) x[i0 + lane] = xs[wrap(i0s + lane, XR)];
+      if (lane < nbr) {
+        xs[wrap(i0s + lane, XR)] = xv;
+        x[i0 + lane] = xv;
+      }
     }
     __syncthreads();
   }
