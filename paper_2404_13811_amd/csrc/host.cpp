@@ -72,6 +72,10 @@ struct mrcm_ctx {
   double *tco = nullptr, *tcp = nullptr;  // block couplings of the boxes / subdomains
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
   size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
+  size_t lds32_basis = 0, lds32_part = 0, lds32_smooth = 0;
+  float *fac32 = nullptr, *facp32 = nullptr;
+  int* d_iters = nullptr;
+  unsigned long long* d_resid = nullptr;
   double *Pk = nullptr, *tr_u = nullptr, *tr_phi = nullptr, *tr_beta = nullptr;
   double *pbar = nullptr, *ubar = nullptr, *pibar = nullptr;
   double *AB = nullptr, *rhs = nullptr, *X = nullptr;
@@ -113,6 +117,7 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
   dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members);
   dfree(c->fac); dfree(c->facs); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
+  dfree(c->fac32); dfree(c->facp32); dfree(c->d_iters); dfree(c->d_resid);
   dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
   dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
   dfree(c->AB); dfree(c->rhs); dfree(c->X); dfree(c->p); dfree(c->gflux); dfree(c->partial);
@@ -282,6 +287,9 @@ mrcm_status make_plan(mrcm_ctx* c) {
     c->lds_basis = std::max(c->lds_basis, wave_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
     c->lds_smooth = std::max(c->lds_smooth, wave_lds_bytes(bm0, bm1, 1));
     c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1));
+    c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0));
+    c->lds32_smooth = std::max(c->lds32_smooth, wave32_lds_bytes(bm0, bm1, 1, 1));
+    c->lds32_part = std::max(c->lds32_part, wave32_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, 1));
   }
   if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024) c->wave = false;
 
@@ -361,6 +369,10 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->scr, c->scr_n);
   ALLOC(c->tco, c->scro_n);
   ALLOC(c->tcp, c->scrp_n);
+  ALLOC(c->fac32, c->fac_n);
+  ALLOC(c->facp32, c->facp_n);
+  ALLOC(c->d_iters, 1);
+  ALLOC(c->d_resid, 1);
   ALLOC(c->Pk, (long long)c->nX * ncell_o);
   ALLOC(c->tr_u, (long long)c->nX * g.gstride);
   ALLOC(c->tr_phi, (long long)c->nX * g.gstride);
@@ -553,12 +565,24 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     mrcm_status st = make_plan(c);
     if (st) return st;
   }
-  if (c->prec == MRCM_FP32_REFINE) return fail(c, MRCM_EINVAL, "FP32 refinement not available yet");
+  const bool r32 = c->prec == MRCM_FP32_REFINE;
+  if (r32 && (!c->wave || c->lds32_basis > 150 * 1024))
+    return fail(c, MRCM_EINVAL, "FP32 refinement is available for 2-D boxes with lines of <= 32 cells");
   hipStream_t s = c->stream;
   HIPCHK(c, hipEventRecord(c->ev[0], s));
   HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
-  if (c->wave) {
+  if (r32) {
+    HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
+    HIPCHK(c, launch_basis32_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf,
+                               c->fac32, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->tol,
+                               c->max_refine, c->d_iters, c->d_resid, c->flags, c->lds32_basis, s));
+    HIPCHK(c, launch_particular32_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv,
+                                    c->beta_mbf, c->facp32, c->pbar, c->ubar, c->pibar, c->tol,
+                                    c->max_refine, c->d_iters, c->d_resid, c->flags,
+                                    c->lds32_part, s));
+  } else if (c->wave) {
     HIPCHK(c, launch_basis_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
                              c->tco, c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags,
                              c->lds_basis, s));
@@ -615,7 +639,12 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   for (int st = 0; st < nsteps; ++st) {
     for (int col = 0; col < (1 << c->d); ++col) {
       const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
-      if (c->wave) {
+      if (c->prec == MRCM_FP32_REFINE) {
+        HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f,
+                                    c->bcv, c->beta_sm, c->fac32, c->p, c->gflux, c->tol,
+                                    c->max_refine, c->d_iters, c->d_resid, c->flags,
+                                    c->lds32_smooth, s));
+      } else if (c->wave) {
         HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f,
                                   c->bcv, c->beta_sm, fac, c->tco, c->scr, c->p, c->gflux,
                                   c->lds_smooth, s));
@@ -668,7 +697,18 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   out->band_kl = c->kl;
   out->band_ku = c->ku;
   out->n_local_solves = c->n_local_solves;
-  out->bytes_factor = (double)(c->fac_n + c->facp_n) * sizeof(double);
+  out->bytes_factor = (double)(c->fac_n + c->facp_n) *
+                      (c->prec == MRCM_FP32_REFINE ? sizeof(float) : sizeof(double));
+  if (c->plan_valid && c->prec == MRCM_FP32_REFINE) {
+    int it = 0;
+    unsigned long long rb = 0;
+    HIPCHK(c, hipMemcpy(&it, c->d_iters, sizeof it, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&rb, c->d_resid, sizeof rb, hipMemcpyDeviceToHost));
+    out->refine_max_iters = it;
+    double r;
+    std::memcpy(&r, &rb, sizeof r);
+    out->refine_max_resid = r;
+  }
   float ms = 0.f;
   if (c->timed_basis && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_basis = ms;
   if (c->timed_iface && hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out->ms_interface = ms;

@@ -1,0 +1,572 @@
+// FP32 local factorisations and solves with FP64 iterative refinement, for
+// the 2-D boxes handled by the one-wavefront-per-box kernels.
+//
+// The block-tridiagonal factorisation of local_wave.hip is applied in FP32
+// to the symmetrically scaled matrix  A^ = D^-1/2 A D^-1/2  (D = diag A,
+// which removes the permeability contrast from the diagonal), and stored
+// as FP32 block inverses (half the bytes of the FP64 form).  Every local
+// solve is then refined in FP64:
+//     x = 0;  repeat  r = b - A x (FP64, two-point stencil from K in LDS);
+//                     x += D^-1/2 solve32(D^-1/2 r)
+// until the componentwise backward error
+//     max_c |r_c| / (|A| |x| + |b|)_c  <=  tol
+// or max_refine corrections have been applied (flag MRCM_ENOCONV).  The
+// interface system and every reduction stay in FP64.
+#include "wave_common.h"
+
+namespace mrcm {
+namespace {
+
+using namespace wave;
+
+struct WaveSmemF {
+  float row[2][NBW];
+  float col[2][NBW];
+  int flag;
+};
+
+// LDS of one box for the refinement kernels.
+struct BoxR {
+  BoxLds b;     // Kt, Dg, Tx, Tn (FP64); b.X = solution x (nrhs x ncell)
+  double* sd;   // ncell, 1 / sqrt(diag)
+  double* Bv;   // nb_rhs x ncell right-hand sides (not stored for seeds)
+  float* Wf;    // nrhs x ncell FP32 work vectors
+  float* Txf;   // ncell scaled x couplings
+  float* Tnf;   // ncell scaled block couplings
+  float* Zf;    // nrhs x NBW staging
+};
+
+__host__ __device__ inline size_t boxr_bytes(int m0, int m1, int nrhs, int nbrhs) {
+  const size_t nc = (size_t)m0 * m1;
+  const size_t d = (size_t)(m0 + 2) * (m1 + 2) + 3 * nc + nrhs * nc + nc + nbrhs * nc;
+  const size_t f = nrhs * nc + 2 * nc + (size_t)nrhs * NBW;
+  return d * sizeof(double) + f * sizeof(float);
+}
+
+__device__ __forceinline__ BoxR carve_r(double* base, const Box& B, int nrhs, int nbrhs) {
+  BoxR r;
+  r.b.m0 = B.hi[0] - B.lo[0];
+  r.b.m1 = B.hi[1] - B.lo[1];
+  const int nc = r.b.m0 * r.b.m1;
+  r.b.Kt = base;
+  r.b.Dg = r.b.Kt + (r.b.m0 + 2) * (r.b.m1 + 2);
+  r.b.Tx = r.b.Dg + nc;
+  r.b.Tn = r.b.Tx + nc;
+  r.b.X = r.b.Tn + nc;
+  r.sd = r.b.X + (size_t)nrhs * nc;
+  r.Bv = r.sd + nc;
+  r.b.Z = nullptr;
+  float* fb = reinterpret_cast<float*>(r.Bv + (size_t)nbrhs * nc);
+  r.Wf = fb;
+  r.Txf = r.Wf + (size_t)nrhs * nc;
+  r.Tnf = r.Txf + nc;
+  r.Zf = r.Tnf + nc;
+  return r;
+}
+
+// Scale factors and scaled couplings (after load_box).
+__device__ void scale_box(const Box& B, BoxR& R) {
+  const int nc = B.ncell, nb = B.nb;
+  for (int e = lane_id(); e < nc; e += 64) R.sd[e] = 1.0 / sqrt(R.b.Dg[e]);
+  wsync();
+  for (int e = lane_id(); e < nc; e += 64) {
+    const int xl = e % R.b.m0;
+    R.Txf[e] = (xl + 1 < R.b.m0) ? (float)(R.b.Tx[e] * R.sd[e] * R.sd[e + 1]) : 0.0f;
+    R.Tnf[e] = (e + nb < nc) ? (float)(R.b.Tn[e] * R.sd[e] * R.sd[e + nb]) : 0.0f;
+  }
+  wsync();
+}
+
+__device__ __forceinline__ float half_swap_f(float v) { return __shfl_xor(v, 32); }
+
+// Scaled S_j into w (column c, my half), w = W_{j-1} on entry when j > 0.
+__device__ __forceinline__ void wbuild32(int nb, int j, const BoxR& R, float w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const float* Tx = R.Txf + j * nb;
+  const float* Tp = R.Tnf + (j - 1) * nb;
+  const float tc = (j > 0 && c < nb) ? Tp[c] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    float v;
+    if (r >= nb || c >= nb) {
+      v = (r == c) ? 1.0f : 0.0f;
+    } else {
+      v = (r == c) ? 1.0f : (r == c - 1) ? -Tx[r] : (r == c + 1) ? -Tx[c] : 0.0f;
+      if (j > 0) v -= Tp[r] * tc * w[i];
+    }
+    w[i] = v;
+  }
+}
+
+__device__ __forceinline__ void wgj32(int nb, WaveSmemF& sm, float w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+#pragma unroll
+  for (int k = 0; k < NBW; ++k) {
+    if (k >= nb) break;
+    float* rk = sm.row[k & 1];
+    float* ck = sm.col[k & 1];
+    if (h == (k >> 4)) rk[c] = w[k & 15];
+    if (c == k) {
+#pragma unroll
+      for (int i = 0; i < HB; ++i) ck[HB * h + i] = w[i];
+    }
+    wsync();
+    const float a = rk[c];
+    const float piv = rk[k];
+    if (!(piv > 0.0f) && L == 0) sm.flag |= kFlagNotPD;
+    const float ip = 1.0f / piv;
+    const float f = -(a * ip);
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const float v = ck[HB * h + i];
+      w[i] = (c == k) ? -v * ip : fmaf(f, v, w[i]);
+    }
+    if (h == (k >> 4)) w[k & 15] = (c == k) ? ip : a * ip;
+  }
+  wsync();
+}
+
+__device__ __forceinline__ float wgemv32(const float w[HB], const float* z) {
+  const int h = lane_id() >> 5;
+  float acc = 0.0f;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) acc = fmaf(w[i], z[HB * h + i], acc);
+  return acc + half_swap_f(acc);
+}
+
+__device__ __forceinline__ void wload32(const float* Wj, int nb, float w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    w[i] = (r < nb && c < nb) ? Wj[r * nb + c] : 0.0f;
+  }
+}
+
+__device__ __forceinline__ void fwd32(int nb, int nc, int j, int nrhs, const BoxR& R, const float w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    float v = 0.0f;
+    if (r < nb) {
+      v = R.Wf[k * nc + j * nb + r];
+      if (j > 0) v += R.Tnf[(j - 1) * nb + r] * R.Wf[k * nc + (j - 1) * nb + r];
+    }
+    R.Zf[k * NBW + r] = v;
+  }
+  wsync();
+  for (int k = 0; k < nrhs; ++k) {
+    const float y = wgemv32(w, R.Zf + k * NBW);
+    if (h == 0 && c < nb) R.Wf[k * nc + j * nb + c] = y;
+  }
+  wsync();
+}
+
+__device__ __forceinline__ void bwd32(int nb, int nc, int j, int nrhs, const BoxR& R, const float w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    R.Zf[k * NBW + r] = (r < nb) ? R.Tnf[j * nb + r] * R.Wf[k * nc + (j + 1) * nb + r] : 0.0f;
+  }
+  wsync();
+  for (int k = 0; k < nrhs; ++k) {
+    const float y = wgemv32(w, R.Zf + k * NBW);
+    if (h == 0 && c < nb) R.Wf[k * nc + j * nb + c] += y;
+  }
+  wsync();
+}
+
+__device__ void factor32(const Box& B, float* Wg, const BoxR& R, WaveSmemF& sm) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb;
+  float w[HB];
+#pragma unroll
+  for (int i = 0; i < HB; ++i) w[i] = 0.0f;
+  for (int j = 0; j < B.nblk; ++j) {
+    wbuild32(nb, j, R, w);
+    wgj32(nb, sm, w);
+    float* Wj = Wg + (long long)j * nb * nb;
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int r = HB * h + i;
+      if (r < nb && c < nb) Wj[r * nb + c] = w[i];
+    }
+  }
+  wsync();
+}
+
+// FP32 solve of the scaled system on every work vector in R.Wf.
+__device__ void solve32(const Box& B, const float* Wg, int nrhs, const BoxR& R) {
+  const int nb = B.nb, nblk = B.nblk, nc = B.ncell;
+  const long long bs = (long long)nb * nb;
+  {
+    float w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (q < nblk) wload32(Wg + q * bs, nb, w[q]);
+    for (int j0 = 0; j0 < nblk; j0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = j0 + q;
+        if (j < nblk) {
+          fwd32(nb, nc, j, nrhs, R, w[q]);
+          if (j + RING < nblk) wload32(Wg + (j + RING) * bs, nb, w[q]);
+        }
+      }
+    }
+  }
+  {
+    float w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (nblk - 2 - q >= 0) wload32(Wg + (nblk - 2 - q) * bs, nb, w[q]);
+    for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = nblk - 2 - (t0 + q);
+        if (j >= 0) {
+          bwd32(nb, nc, j, nrhs, R, w[q]);
+          if (j - RING >= 0) wload32(Wg + (j - RING) * bs, nb, w[q]);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Right-hand side of seed k at box cell loc (T^R times the seed on its side).
+__device__ __forceinline__ double seed_rhs(const Geo& g, const Box& B, const BoxR& R, const Seed& sd,
+                                           double beta, int loc) {
+  const int x = B.lo[0] + loc % R.b.m0, y = B.lo[1] + loc / R.b.m0;
+  const int a = sd.side >> 1, so = sd.side & 1;
+  const bool on = (a == 0) ? (x == (so ? B.hi[0] - 1 : B.lo[0])) : (y == (so ? B.hi[1] - 1 : B.lo[1]));
+  if (!on) return 0.0;
+  const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+  const double kc = kat(R.b, B, x, y);
+  const double bt = robin_beta(g, a, kc, kat(R.b, B, ox, oy), beta);
+  const int c[3] = {x, y, 0};
+  return robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
+}
+
+// Iterative refinement of nrhs systems A x_k = b_k; b from seeds (if
+// seeds != nullptr) or from R.Bv.  Returns the number of FP32 solves.
+__device__ int refine(const Geo& g, const Box& B, const BoxR& R, const float* Wg, int nrhs,
+                      const Seed* seeds, double beta, double tol, int max_refine, double& omega_out,
+                      WaveSmemF& sm) {
+  const int L = lane_id();
+  const int nc = B.ncell, m0 = R.b.m0, nb = B.nb;
+  for (int e = L; e < nrhs * nc; e += 64) R.b.X[e] = 0.0;
+  wsync();
+  int it = 0;
+  double omega = 0.0;
+  while (true) {
+    // r = b - A x, scaled into the FP32 work vectors; componentwise backward error
+    omega = 0.0;
+    for (int k = 0; k < nrhs; ++k) {
+      const double* x = R.b.X + (size_t)k * nc;
+      double om = 0.0;
+      for (int loc = L; loc < nc; loc += 64) {
+        const double bv = seeds ? seed_rhs(g, B, R, seeds[B.seed0 + k], beta, loc) : R.Bv[loc];
+        const int xl = loc % m0;
+        const double xc = x[loc];
+        double ax = R.b.Dg[loc] * xc, aa = fabs(R.b.Dg[loc] * xc);
+        if (xl > 0) { const double t = R.b.Tx[loc - 1] * x[loc - 1]; ax -= t; aa += fabs(t); }
+        if (xl + 1 < m0) { const double t = R.b.Tx[loc] * x[loc + 1]; ax -= t; aa += fabs(t); }
+        if (loc >= nb) { const double t = R.b.Tn[loc - nb] * x[loc - nb]; ax -= t; aa += fabs(t); }
+        if (loc + nb < nc) { const double t = R.b.Tn[loc] * x[loc + nb]; ax -= t; aa += fabs(t); }
+        const double r = bv - ax;
+        const double den = aa + fabs(bv);
+        if (den > 0.0) om = fmax(om, fabs(r) / den);
+        R.Wf[(size_t)k * nc + loc] = (float)(R.sd[loc] * r);
+      }
+      omega = fmax(omega, wave_max(om));
+    }
+    wsync();
+    if (it > 0 && omega <= tol) break;
+    if (it > max_refine) {
+      if (L == 0) sm.flag |= kFlagNoConv;
+      break;
+    }
+    solve32(B, Wg, nrhs, R);
+    for (int e = L; e < nrhs * nc; e += 64) R.b.X[e] += R.sd[e % nc] * (double)R.Wf[e];
+    wsync();
+    ++it;
+  }
+  omega_out = omega;
+  return it;
+}
+
+__device__ __forceinline__ void record_refine(int it, double omega, int* iters,
+                                              unsigned long long* resid) {
+  if (lane_id() == 0) {
+    atomicMax(iters, it);
+    atomicMax(resid, (unsigned long long)__double_as_longlong(omega));
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void __launch_bounds__(64) k_basis32(Geo g, const Box* __restrict__ boxes,
+                                                const Seed* __restrict__ seeds,
+                                                const double* __restrict__ K, double beta,
+                                                float* __restrict__ fac32,
+                                                double* __restrict__ Pk,
+                                                double* __restrict__ tr_u,
+                                                double* __restrict__ tr_phi,
+                                                double* __restrict__ tr_beta, double tol,
+                                                int max_refine, int* iters,
+                                                unsigned long long* resid, int* flags) {
+  extern __shared__ double dsm[];
+  __shared__ WaveSmemF sm;
+  const Box B = boxes[blockIdx.x];
+  const int L = lane_id();
+  if (L == 0) sm.flag = 0;
+  const int nrhs = B.nrhs;
+  BoxR R = carve_r(dsm, B, max(nrhs, 1), 0);
+  load_box(g, B, K, beta, R.b);
+  scale_box(B, R);
+  float* Wg = fac32 + B.fac;
+  factor32(B, Wg, R, sm);
+  double omega = 0.0;
+  const int it = nrhs > 0 ? refine(g, B, R, Wg, nrhs, seeds, beta, tol, max_refine, omega, sm) : 0;
+  record_refine(it, omega, iters, resid);
+  const BoxLds& s = R.b;
+  const int nc = B.ncell;
+  int olo[3], ohi[3];
+  womega(g, B.sub, olo, ohi);
+  const int ncell_o = g.S[0] * g.S[1];
+  for (int e = L; e < nrhs * ncell_o; e += 64) {
+    const int k = e / ncell_o, t = e % ncell_o;
+    Pk[(long long)(B.seed0 + k) * ncell_o + t] =
+        s.X[k * nc + bloc(B, s, olo[0] + t % g.S[0], olo[1] + t / g.S[0])];
+  }
+  for (int q = 0; q < 4; ++q) {
+    const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
+    const bool has = wneighbor(g, B.sub, q) >= 0;
+    const int a = q >> 1, so = q & 1;
+    for (int e = L; e < nrhs * nf; e += 64) {
+      const int k = e / nf, t = e % nf;
+      const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
+      if (!has) {
+        tr_u[oidx] = 0.0;
+        tr_phi[oidx] = 0.0;
+        continue;
+      }
+      int x, y;
+      wgface(olo, ohi, q, t, x, y);
+      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+      const double Pc = s.X[k * nc + bloc(B, s, x, y)];
+      const double bt = robin_beta(g, a, kc, ko, beta);
+      double u;
+      if (win_box(B, ox, oy)) {
+        u = g.area * kharm(kc, ko) / g.h * (Pc - s.X[k * nc + bloc(B, s, ox, oy)]) / g.area;
+      } else {
+        const Seed sd = seeds[B.seed0 + k];
+        const int c[3] = {x, y, 0};
+        const double lam = (sd.side == q) ? seed_value(g, sd, B.lo, B.hi, c) : 0.0;
+        u = robin_T(g, kc, bt) * (Pc - lam) / g.area;
+      }
+      const double pi = Pc - u * g.h / (2.0 * kc);
+      tr_u[oidx] = u;
+      tr_phi[oidx] = -bt * u + pi;
+      if (k == 0) tr_beta[(long long)B.sub * g.gstride + g.gside_off[q] + t] = bt;
+    }
+  }
+  wsync();
+  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+__global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restrict__ boxes,
+                                                     const double* __restrict__ K,
+                                                     const double* __restrict__ f,
+                                                     const double* __restrict__ bcv, double beta,
+                                                     float* __restrict__ fac32,
+                                                     double* __restrict__ pbar,
+                                                     double* __restrict__ ubar,
+                                                     double* __restrict__ pibar, double tol,
+                                                     int max_refine, int* iters,
+                                                     unsigned long long* resid, int* flags) {
+  extern __shared__ double dsm[];
+  __shared__ WaveSmemF sm;
+  const Box B = boxes[blockIdx.x];
+  const int L = lane_id();
+  if (L == 0) sm.flag = 0;
+  BoxR R = carve_r(dsm, B, 1, 1);
+  load_box(g, B, K, beta, R.b);
+  scale_box(B, R);
+  physical_rhs(g, B, R.b, f, bcv, R.Bv);
+  wsync();
+  float* Wg = fac32 + B.fac;
+  factor32(B, Wg, R, sm);
+  double omega = 0.0;
+  const int it = refine(g, B, R, Wg, 1, nullptr, beta, tol, max_refine, omega, sm);
+  record_refine(it, omega, iters, resid);
+  const BoxLds& s = R.b;
+  for (int t = L; t < B.ncell; t += 64) pbar[(long long)B.sub * B.ncell + t] = s.X[t];
+  for (int q = 0; q < 4; ++q) {
+    const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
+    const bool has = wneighbor(g, B.sub, q) >= 0;
+    const int a = q >> 1, so = q & 1;
+    for (int t = L; t < nf; t += 64) {
+      const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
+      if (!has) {
+        ubar[oidx] = 0.0;
+        pibar[oidx] = 0.0;
+        continue;
+      }
+      int x, y;
+      wgface(B.lo, B.hi, q, t, x, y);
+      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, x, y);
+      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+      const double u = robin_T(g, kc, bt) * s.X[bloc(B, s, x, y)] / g.area;
+      ubar[oidx] = u;
+      pibar[oidx] = bt * u;
+    }
+  }
+  wsync();
+  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+__global__ void __launch_bounds__(64) k_smooth32(Geo g, const Box* __restrict__ boxes,
+                                                 const int* __restrict__ members,
+                                                 const double* __restrict__ K,
+                                                 const double* __restrict__ f,
+                                                 const double* __restrict__ bcv, double beta,
+                                                 const float* __restrict__ fac32,
+                                                 double* __restrict__ p,
+                                                 double* __restrict__ gflux, double tol,
+                                                 int max_refine, int* iters,
+                                                 unsigned long long* resid, int* flags) {
+  extern __shared__ double dsm[];
+  __shared__ WaveSmemF sm;
+  const Box B = boxes[members[blockIdx.x]];
+  const int L = lane_id();
+  if (L == 0) sm.flag = 0;
+  BoxR R = carve_r(dsm, B, 1, 1);
+  load_box(g, B, K, beta, R.b);
+  scale_box(B, R);
+  const BoxLds& s = R.b;
+  const int nc = B.ncell;
+  for (int loc = L; loc < nc; loc += 64) {
+    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
+    const int ci = x + g.n[0] * y;
+    const double kc = kat(s, B, x, y);
+    double b = f[ci] * g.vol;
+    const int c[3] = {x, y, 0};
+    for (int a = 0; a < 2; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int kind = face_kind(g, B, c, a, sd);
+        if (kind == kFaceInterior) continue;
+        const int side = 2 * a + sd;
+        if (kind == kFaceRobin) {
+          const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+          const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+          b += robin_T(g, kc, bt) * wlambda(g, B, s, p, gflux, beta, x, y, a, sd);
+        } else {
+          const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
+          if (kind == kFaceDir) b += 2.0 * kc * g.area / g.h * val;
+          else b -= g.area * val;
+        }
+      }
+    R.Bv[loc] = b;
+  }
+  wsync();
+  double omega = 0.0;
+  const int it = refine(g, B, R, fac32 + B.fac, 1, nullptr, beta, tol, max_refine, omega, sm);
+  record_refine(it, omega, iters, resid);
+  int olo[3], ohi[3];
+  womega(g, B.sub, olo, ohi);
+  for (int q = 0; q < 4; ++q) {
+    if (wneighbor(g, B.sub, q) < 0) continue;
+    const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
+    const int a = q >> 1, so = q & 1;
+    for (int t = L; t < nf; t += 64) {
+      int x, y;
+      wgface(olo, ohi, q, t, x, y);
+      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
+      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+      const double xc = s.X[bloc(B, s, x, y)];
+      double u;
+      if (win_box(B, ox, oy)) {
+        u = g.area * kharm(kc, ko) / g.h * (xc - s.X[bloc(B, s, ox, oy)]) / g.area;
+      } else {
+        const double lam = wlambda(g, B, s, p, gflux, beta, x, y, a, so);
+        u = robin_T(g, kc, robin_beta(g, a, kc, ko, beta)) * (xc - lam) / g.area;
+      }
+      gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
+    }
+  }
+  const int ncell_o = g.S[0] * g.S[1];
+  for (int t = L; t < ncell_o; t += 64) {
+    const int x = olo[0] + t % g.S[0], y = olo[1] + t / g.S[0];
+    p[x + g.n[0] * y] = s.X[bloc(B, s, x, y)];
+  }
+  wsync();
+  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+template <typename KF>
+hipError_t set_lds(KF kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs) { return boxr_bytes(m0, m1, nrhs, nbrhs); }
+
+hipError_t launch_basis32_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
+                            const double* K, double beta, float* fac32, double* Pk, double* tr_u,
+                            double* tr_phi, double* tr_beta, double tol, int max_refine,
+                            int* iters, unsigned long long* resid, int* flags, size_t lds,
+                            hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = set_lds(k_basis32, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_basis32, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac32, Pk,
+                     tr_u, tr_phi, tr_beta, tol, max_refine, iters, resid, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_particular32_w(const Geo& g, const Box* boxes, int nbox, const double* K,
+                                 const double* f, const double* bcv, double beta, float* fac32,
+                                 double* pbar, double* ubar, double* pibar, double tol,
+                                 int max_refine, int* iters, unsigned long long* resid,
+                                 int* flags, size_t lds, hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = set_lds(k_particular32, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_particular32, dim3(nbox), dim3(64), lds, s, g, boxes, K, f, bcv, beta, fac32,
+                     pbar, ubar, pibar, tol, max_refine, iters, resid, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members, int nmem,
+                             const double* K, const double* f, const double* bcv, double beta,
+                             const float* fac32, double* p, double* gflux, double tol,
+                             int max_refine, int* iters, unsigned long long* resid, int* flags,
+                             size_t lds, hipStream_t s) {
+  if (nmem <= 0) return hipSuccess;
+  hipError_t e = set_lds(k_smooth32, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_smooth32, dim3(nmem), dim3(64), lds, s, g, boxes, members, K, f, bcv, beta,
+                     fac32, p, gflux, tol, max_refine, iters, resid, flags);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

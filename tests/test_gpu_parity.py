@@ -68,3 +68,31 @@ def test_c2_full(overlap):
 
 def test_three_dimensional_small():
     _check(make_workload("c4", scale=8), nsmooth=1)
+
+
+# ------------------------------------------------------------ FP32 + refinement
+def _check32(wl, nsmooth=None, tol_flux=1e-6, tol_p=1e-6):
+    from gpu_util import gpu_solve, oracle_solve, rel
+    print("case fp32", wl.name, wl.ncell, "l=%d" % wl.overlap, wl.space, flush=True)
+    p, fl, X, st = gpu_solve(wl, precision="fp32_refine", nsmooth=nsmooth, tol=1e-12, max_refine=30)
+    rp, rf, _, _ = oracle_solve(wl, nsmooth=nsmooth)
+    ep, ef = rel(p, rp), rel(fl, rf)
+    print("  fp32+refine rel L2 p %.3e flux %.3e  refine iters %d backward err %.2e"
+          % (ep, ef, st["refine_max_iters"], st["refine_max_resid"]), flush=True)
+    assert ef <= tol_flux and ep <= tol_p
+    assert st["refine_max_resid"] <= 1e-12
+    return ep, ef
+
+
+@pytest.mark.parametrize("overlap", [0, 2])
+def test_fp32_refine_small(overlap):
+    _check32(_small(space="linear", overlap=overlap), nsmooth=2)
+
+
+def test_fp32_refine_c1():
+    _check32(make_workload("c1"))
+
+
+@pytest.mark.parametrize("overlap", [0, 2, 4])
+def test_fp32_refine_c2_full(overlap):
+    _check32(make_workload("c2", overlap=overlap))
