@@ -297,8 +297,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // of the trailing window, then the window slides by BNB rows / columns (the
 // entering rows are prefetched into registers at the start of the panel).
 constexpr int BNB = 16;
-constexpr int BT = 256;
-constexpr int PF = 16;  // prefetched values per thread
+constexpr int BT = 512;
+constexpr int PF = 8;   // prefetched values per thread
 
 __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict__ RB, int n,
                                                        int kl, int ku,
@@ -375,52 +375,40 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
         key = wave_max_key(key);
         const int p = 2047 - (int)(key & 0x7FFull);
         if (lane == 0) piv[k] = p;
-        // exchange rows k and p through LDS; the pivot row lands in swp[BNB..]
-        if (t0 == k) {
+        // pivot row (lane p & 63, first or second slot) and row k (lane k,
+        // first slot) broadcast with readlane; exchange them in registers
+        const int pl = p & 63;
+        const bool phi = p >= 64;
+        double prow[BNB];
 #pragma unroll
-          for (int c = 0; c < BNB; ++c) swp[c] = a0[c];
-        }
-        if (v0 && t0 == p) {
-#pragma unroll
-          for (int c = 0; c < BNB; ++c) swp[BNB + c] = a0[c];
-        }
-        if (v1 && t1 == p) {
-#pragma unroll
-          for (int c = 0; c < BNB; ++c) swp[BNB + c] = a1[c];
-        }
-        wave_lds_sync();
+        for (int c = 0; c < BNB; ++c) prow[c] = bcast(phi ? a1[c] : a0[c], pl);
         if (p != k) {
-          if (t0 == k) {
+          double krow[BNB];
 #pragma unroll
-            for (int c = 0; c < BNB; ++c) a0[c] = swp[BNB + c];
-          }
-          if (v0 && t0 == p) {
+          for (int c = 0; c < BNB; ++c) krow[c] = bcast(a0[c], k);
+          const bool isk = t0 == k, isp0 = !phi && t0 == p, isp1 = phi && t1 == p;
 #pragma unroll
-            for (int c = 0; c < BNB; ++c) a0[c] = swp[c];
-          }
-          if (v1 && t1 == p) {
-#pragma unroll
-            for (int c = 0; c < BNB; ++c) a1[c] = swp[c];
+          for (int c = 0; c < BNB; ++c) {
+            a0[c] = isk ? prow[c] : (isp0 ? krow[c] : a0[c]);
+            a1[c] = isp1 ? krow[c] : a1[c];
           }
         }
-        const double pk = swp[BNB + k];
+        const double pk = prow[k];
         if (lane == 0 && !(pk != 0.0)) s_flag |= kFlagSingular;
         const double ip = (pk != 0.0) ? 1.0 / pk : 0.0;
-        if (v0 && t0 > k) {
-          const double l = a0[k] * ip;
-          a0[k] = l;
+        {
+          const bool e0 = v0 && t0 > k, e1 = v1 && t1 > k;
+          const double l0 = e0 ? a0[k] * ip : 0.0;
+          const double l1 = e1 ? a1[k] * ip : 0.0;
+          a0[k] = e0 ? l0 : a0[k];
+          a1[k] = e1 ? l1 : a1[k];
 #pragma unroll
           for (int c = 0; c < BNB; ++c)
-            if (c > k) a0[c] -= l * swp[BNB + c];
+            if (c > k) {
+              a0[c] = fma(-l0, prow[c], a0[c]);
+              a1[c] = fma(-l1, prow[c], a1[c]);
+            }
         }
-        if (v1 && t1 > k) {
-          const double l = a1[k] * ip;
-          a1[k] = l;
-#pragma unroll
-          for (int c = 0; c < BNB; ++c)
-            if (c > k) a1[c] -= l * swp[BNB + c];
-        }
-        wave_lds_sync();
       }
 #pragma unroll
       for (int c = 0; c < BNB; ++c) {
@@ -465,65 +453,61 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
       }
       double mv[2 * BNB];
 #pragma unroll
-      for (int q = 0; q < 2 * BNB; ++q) mv[q] = (mv_src[q] >= 0) ? col[RS(mv_src[q]) * stride] : 0.0;
+      for (int q = 0; q < 2 * BNB; ++q) {
+        const int src = __builtin_amdgcn_readfirstlane(mv_src[q]);
+        mv[q] = col[RS(max(src, 0)) * stride];
+      }
 #pragma unroll
-      for (int q = 0; q < 2 * BNB; ++q)
-        if (mv_src[q] >= 0 && mv_src[q] != mv_pos[q]) col[RS(mv_pos[q]) * stride] = mv[q];
+      for (int q = 0; q < 2 * BNB; ++q) {
+        const int src = __builtin_amdgcn_readfirstlane(mv_src[q]);
+        const int pos = __builtin_amdgcn_readfirstlane(mv_pos[q]);
+        if (src >= 0 && src != pos) col[RS(pos) * stride] = mv[q];
+      }
       double u[BNB];
 #pragma unroll
-      for (int k = 0; k < BNB; ++k) u[k] = (k < nbp) ? col[RS(k) * stride] : 0.0;
+      for (int k = 0; k < BNB; ++k) u[k] = col[RS(min(k, nbp - 1)) * stride];
 #pragma unroll
       for (int k = 0; k < BNB; ++k) {
         const int ck = CS(k);
 #pragma unroll
-        for (int i = k + 1; i < BNB; ++i)
-          if (i < nbp) u[i] -= win[RS(i) * LDW + ck] * u[k];
+        for (int i = k + 1; i < BNB; ++i) u[i] -= win[RS(min(i, nbp - 1)) * LDW + ck] * u[k];
       }
 #pragma unroll
       for (int k = 0; k < BNB; ++k)
         if (k < nbp) col[RS(k) * stride] = u[k];
     }
     __syncthreads();
-    // (D) trailing update, rows [j1, j0+H), columns [j1, j0+WC) and the rhs column
+    // (D) trailing update, rows [j1, j0+H), columns [j1, j0+WC) and the rhs
+    // column.  Work items are (strip of 8 rows, column); consecutive threads
+    // take consecutive columns, so the U12 reads and the updates hit distinct
+    // LDS banks and the L21 reads are broadcasts.
     {
       const int nr = H - nbp;
       const int nc = ncr + 1;  // + rhs
-      const int tr = (nr + 3) / 4, tc = (nc + 3) / 4;
-      for (int t = tid; t < tr * tc; t += BT) {
-        const int ti = t / tc;
-        const int ib = ti * 4, cb = (t - ti * tc) * 4;
-        int rs[4], cs[4];
+      const int ns = (nr + 7) / 8;
+      for (int t = tid; t < ns * nc; t += BT) {
+        const int st = t / nc;
+        const int cc = t - st * nc;
+        const int ib = st * 8;
+        const bool isr = (cc == ncr);
+        const double* ubase = isr ? zr : win + CS(nbp + cc);
+        const int ustr = isr ? 1 : LDW;
+        int rs[8];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) rs[a] = (ib + a < nr) ? RS(nbp + ib + a) : -1;
+        for (int a = 0; a < 8; ++a) rs[a] = RS(nbp + min(ib + a, nr - 1));
+        double acc[8];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) cs[b] = (cb + b < ncr) ? CS(nbp + cb + b) : (cb + b == ncr ? -2 : -1);
-        double acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int a = 0; a < 8; ++a) acc[a] = 0.0;
         for (int k = 0; k < nbp; ++k) {
           const int ck = CS(k), rk = RS(k);
-          double lv[4], uv[4];
+          const double uv = ubase[rk * ustr];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) lv[a] = (rs[a] >= 0) ? win[rs[a] * LDW + ck] : 0.0;
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            uv[b] = (cs[b] >= 0) ? win[rk * LDW + cs[b]] : (cs[b] == -2 ? zr[rk] : 0.0);
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(lv[a], uv[b], acc[a][b]);
+          for (int a = 0; a < 8; ++a) acc[a] = fma(win[rs[a] * LDW + ck], uv, acc[a]);
         }
+        double* obase = isr ? zr : win + CS(nbp + cc);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (rs[a] < 0) continue;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            if (cs[b] >= 0) win[rs[a] * LDW + cs[b]] -= acc[a][b];
-            else if (cs[b] == -2) zr[rs[a]] -= acc[a][b];
-          }
-        }
+        for (int a = 0; a < 8; ++a)
+          if (ib + a < nr) obase[rs[a] * ustr] -= acc[a];
       }
     }
     __syncthreads();
