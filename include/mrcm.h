@@ -71,8 +71,11 @@ typedef enum { MRCM_SPACE_CONST = 0, MRCM_SPACE_LINEAR = 1, MRCM_SPACE_FINE = 2 
 typedef enum { MRCM_BETA_ALPHA = 0, MRCM_BETA_CONST = 1 } mrcm_beta_mode;
 
 /* FP64: local factors and solves in FP64.  FP32_REFINE: local factors and
- * solves in FP32, corrected by FP64 iterative refinement with the residual
- * evaluated from K in FP64 until ||r|| <= tol * ||b|| per right-hand side. */
+ * solves in FP32 on the diagonally scaled local matrices, corrected by FP64
+ * iterative refinement with the residual r = b - A x evaluated from K in
+ * FP64 until the componentwise backward error max_c |r_c| / (|A||x| + |b|)_c
+ * is <= tol (at most max_refine corrections; MRCM_ENOCONV otherwise).
+ * Available for 2-D boxes whose lines have at most 32 cells. */
 typedef enum { MRCM_FP64 = 0, MRCM_FP32_REFINE = 1 } mrcm_precision;
 
 typedef enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 } mrcm_bc_type;
@@ -83,10 +86,11 @@ typedef struct {
   int n_unknowns;          /* interface unknowns sum_i dim Lambda_H^i        */
   int band_kl, band_ku;    /* bandwidths of the interface system             */
   int n_local_solves;      /* right-hand sides solved so far                 */
-  int refine_max_iters;    /* largest refinement count of any solve          */
-  double refine_max_resid; /* largest final ||r||/||b|| of any refined solve */
+  int refine_max_iters;    /* most FP32 solves used by one refined system     */
+  double refine_max_resid; /* largest final componentwise backward error      */
   double ms_basis, ms_interface, ms_smooth;  /* device time of the last calls */
   double bytes_factor;     /* bytes of cached local factors                  */
+  double ms_interface_solve; /* device time of the interface factor + solve  */
 } mrcm_stats;
 
 /* Create a context for a dim-dimensional grid (dim = 2 or 3) of

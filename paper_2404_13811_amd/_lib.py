@@ -25,7 +25,8 @@ class Stats(ctypes.Structure):
                 ("band_ku", ctypes.c_int), ("n_local_solves", ctypes.c_int),
                 ("refine_max_iters", ctypes.c_int), ("refine_max_resid", ctypes.c_double),
                 ("ms_basis", ctypes.c_double), ("ms_interface", ctypes.c_double),
-                ("ms_smooth", ctypes.c_double), ("bytes_factor", ctypes.c_double)]
+                ("ms_smooth", ctypes.c_double), ("bytes_factor", ctypes.c_double),
+                ("ms_interface_solve", ctypes.c_double)]
 
 
 _lib = None

@@ -82,7 +82,7 @@ struct mrcm_ctx {
   double *p = nullptr, *gflux = nullptr, *partial = nullptr;
   int* flags = nullptr;
 
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed_basis = false, timed_iface = false, timed_smooth = false;
   int n_local_solves = 0;
 };
@@ -453,7 +453,7 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (e == hipSuccess) e = hipMalloc((void**)&c->f, N * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
-  for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   if (e == hipSuccess) e = launch_fill(c->bcv, 0.0, off, c->stream);
   if (e == hipSuccess) e = launch_fill(c->f, 0.0, N, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -612,11 +612,13 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
                            c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab,
                            c->kl, c->ku, c->rhs, s));
   if (c->nX > 0) {
+    HIPCHK(c, hipEventRecord(c->ev[6], s));
     hipError_t e = launch_bandlu_solve(c->AB, c->ldab, c->nX, c->kl, c->ku, c->rhs, c->X, nullptr,
                                        c->flags, s);
     if (e == hipErrorInvalidValue)
       return fail(c, MRCM_EINVAL, "interface band (kl=%d, ku=%d) too wide for the LDS window", c->kl, c->ku);
     HIPCHK(c, e);
+    HIPCHK(c, hipEventRecord(c->ev[7], s));
   }
   HIPCHK(c, launch_combine(c->geo, c->d_seed_off, c->X, c->Pk, c->tr_u, c->pbar, c->ubar, c->p,
                            c->gflux, s));
@@ -713,6 +715,8 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   if (c->timed_basis && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_basis = ms;
   if (c->timed_iface && hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out->ms_interface = ms;
   if (c->timed_smooth && hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) out->ms_smooth = ms;
+  if (c->timed_iface && c->nX > 0 && hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess)
+    out->ms_interface_solve = ms;
   return check_flags(c);
 }
 
