@@ -21,6 +21,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the CPU baseline (oracle) runs single-threaded
+for _v in ("OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "OMP_NUM_THREADS"):
+    os.environ[_v] = "1"
 
 PEAK_FP64 = 78.6e12  # MI355X dense FP64 (vector and matrix), FLOP/s
 
