@@ -80,6 +80,16 @@ typedef enum { MRCM_FP64 = 0, MRCM_FP32_REFINE = 1 } mrcm_precision;
 
 typedef enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 } mrcm_bc_type;
 
+/* Direct solver of the interface system (Algorithm 1, Step 5), both FP64 on
+ * the device.  BAND_LU: banded LU with partial pivoting in the natural
+ * (interface-major) equation order, one workgroup.  BCR: block cyclic
+ * reduction over the layers of subdomains along the last axis, with the
+ * flux equations of an interface assigned to its lower-indexed subdomain and
+ * the pressure equations to the higher one (square layer blocks, block
+ * tridiagonal system), dense block inverses without pivoting; needs layer
+ * blocks of at most 256 unknowns.  AUTO: BCR when it applies, else BAND_LU. */
+typedef enum { MRCM_IFACE_AUTO = 0, MRCM_IFACE_BAND_LU = 1, MRCM_IFACE_BCR = 2 } mrcm_iface_solver;
+
 typedef struct {
   int n_subdomains;        /* m                                              */
   int n_boxes;             /* oversampled boxes (= m)                        */
@@ -91,6 +101,7 @@ typedef struct {
   double ms_basis, ms_interface, ms_smooth;  /* device time of the last calls */
   double bytes_factor;     /* bytes of cached local factors                  */
   double ms_interface_solve; /* device time of the interface factor + solve  */
+  int interface_solver;    /* MRCM_IFACE_BAND_LU or MRCM_IFACE_BCR in use      */
 } mrcm_stats;
 
 /* Create a context for a dim-dimensional grid (dim = 2 or 3) of
@@ -120,6 +131,11 @@ mrcm_status mrcm_set_bc(mrcm_ctx* ctx, int side, mrcm_bc_type type, const double
 mrcm_status mrcm_set_partition(mrcm_ctx* ctx, const int* sub, int overlap);
 
 mrcm_status mrcm_set_interface_space(mrcm_ctx* ctx, mrcm_space space);
+
+/* Interface solver (default MRCM_IFACE_AUTO).  Errors: MRCM_EINVAL; with
+ * MRCM_IFACE_BCR, mrcm_build_basis fails with MRCM_EINVAL when the layer
+ * blocks are not square or exceed 256 unknowns. */
+mrcm_status mrcm_set_interface_solver(mrcm_ctx* ctx, mrcm_iface_solver solver);
 
 /* Robin parameters of the basis functions and of the smoothing steps
  * (Algorithm 1: Step 6 is needed only when they differ). Values > 0. */

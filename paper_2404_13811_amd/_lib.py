@@ -13,7 +13,8 @@ STATUS = {0: "MRCM_OK", 1: "MRCM_EINVAL", 2: "MRCM_ENOMEM", 3: "MRCM_EDEVICE", 4
           5: "MRCM_ENOTPD", 6: "MRCM_ENOCONV", 7: "MRCM_EINCOMPAT", 8: "MRCM_ESINGULAR"}
 
 SYMBOLS = ("mrcm_create", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_bc",
-           "mrcm_set_partition", "mrcm_set_interface_space", "mrcm_set_robin",
+           "mrcm_set_partition", "mrcm_set_interface_space", "mrcm_set_interface_solver",
+           "mrcm_set_robin",
            "mrcm_set_precision", "mrcm_build_basis", "mrcm_solve_interface", "mrcm_smooth",
            "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_coefficients", "mrcm_get_stats",
            "mrcm_last_error", "mrcm_destroy")
@@ -26,7 +27,7 @@ class Stats(ctypes.Structure):
                 ("refine_max_iters", ctypes.c_int), ("refine_max_resid", ctypes.c_double),
                 ("ms_basis", ctypes.c_double), ("ms_interface", ctypes.c_double),
                 ("ms_smooth", ctypes.c_double), ("bytes_factor", ctypes.c_double),
-                ("ms_interface_solve", ctypes.c_double)]
+                ("ms_interface_solve", ctypes.c_double), ("interface_solver", ctypes.c_int)]
 
 
 _lib = None
@@ -47,6 +48,7 @@ def load():
         "mrcm_set_bc": [vp, i, i, vp],
         "mrcm_set_partition": [vp, ip, i],
         "mrcm_set_interface_space": [vp, i],
+        "mrcm_set_interface_solver": [vp, i],
         "mrcm_set_robin": [vp, i, d, d],
         "mrcm_set_precision": [vp, i, d, i],
         "mrcm_build_basis": [vp],

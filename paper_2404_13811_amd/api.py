@@ -12,6 +12,7 @@ from . import _lib
 SPACE = {"const": 0, "linear": 1, "fine": 2}
 PRECISION = {"fp64": 0, "fp32_refine": 1}
 BETA = {"alpha": 0, "const": 1}
+IFACE_SOLVER = {"auto": 0, "band_lu": 1, "bcr": 2}
 BC = {"N": 0, "D": 1}
 
 
@@ -86,6 +87,11 @@ def set_interface_space(ctx, space):
     _check(ctx, "mrcm_set_interface_space", _lib.load().mrcm_set_interface_space(ctx.handle, s))
 
 
+def set_interface_solver(ctx, solver):
+    v = IFACE_SOLVER[solver] if isinstance(solver, str) else int(solver)
+    _check(ctx, "mrcm_set_interface_solver", _lib.load().mrcm_set_interface_solver(ctx.handle, v))
+
+
 def set_robin(ctx, mode, mbf, smooth_value):
     m = BETA[mode] if isinstance(mode, str) else int(mode)
     _check(ctx, "mrcm_set_robin", _lib.load().mrcm_set_robin(ctx.handle, m, float(mbf), float(smooth_value)))
@@ -143,7 +149,7 @@ def destroy(ctx):
         ctx.handle = None
 
 
-def configure(ctx, wl, precision="fp64", tol=1e-12, max_refine=30):
+def configure(ctx, wl, precision="fp64", tol=1e-12, max_refine=30, solver="auto"):
     """Pass a workload record (inputs.Workload) through the set_* calls."""
     dev = "cuda"
     set_permeability(ctx, torch.as_tensor(wl.logk.ravel(), dtype=torch.float64, device=dev).contiguous())
@@ -155,13 +161,15 @@ def configure(ctx, wl, precision="fp64", tol=1e-12, max_refine=30):
     set_interface_space(ctx, wl.space)
     set_robin(ctx, wl.beta_mode, wl.beta_mbf, wl.beta_smooth)
     set_precision(ctx, precision, tol, max_refine)
+    set_interface_solver(ctx, solver)
 
 
-def solve_workload(wl, precision="fp64", nsmooth=None, tol=1e-12, max_refine=30, keep=False):
+def solve_workload(wl, precision="fp64", nsmooth=None, tol=1e-12, max_refine=30, keep=False,
+                   solver="auto"):
     """Full MRCM-OS solve of a workload; returns (pressure, flux[, ctx])."""
     ctx = create(wl.dim, wl.ncell, wl.h)
     try:
-        configure(ctx, wl, precision, tol, max_refine)
+        configure(ctx, wl, precision, tol, max_refine, solver)
         build_basis(ctx)
         solve_interface(ctx)
         smooth(ctx, wl.nsmooth if nsmooth is None else nsmooth)

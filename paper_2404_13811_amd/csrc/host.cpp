@@ -32,6 +32,7 @@ struct mrcm_ctx {
   int beta_mode = MRCM_BETA_ALPHA;
   double beta_mbf = 1.0, beta_sm = 1.0;
   int prec = MRCM_FP64;
+  int iface_solver = MRCM_IFACE_AUTO;
   double tol = 1e-12;
   int max_refine = 20;
   int bc_type[6] = {0, 0, 0, 0, 0, 0};
@@ -82,6 +83,21 @@ struct mrcm_ctx {
   double *p = nullptr, *gflux = nullptr, *partial = nullptr;
   int* flags = nullptr;
 
+  // block cyclic reduction of the interface system over the layers of
+  // subdomains along the last axis (bcr.hip)
+  struct BcrOp {
+    int kind;  // 0 inverses, 1 block products, 2 block-vector products
+    int off, cnt;
+  };
+  bool use_bcr = false;
+  int bcr_M = 0, bcr_bp = 0;
+  std::vector<BcrOp> bcr_ops;
+  int *d_row_lvl = nullptr, *d_row_loc = nullptr, *d_col_lvl = nullptr, *d_col_loc = nullptr;
+  int *d_lsize = nullptr, *d_binv = nullptr;
+  BcrGemm* d_bgemm = nullptr;
+  BcrGemv* d_bgemv = nullptr;
+  double *bpool = nullptr, *bvec = nullptr;
+
   hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed_basis = false, timed_iface = false, timed_smooth = false;
   int n_local_solves = 0;
@@ -121,6 +137,11 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
   dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
   dfree(c->AB); dfree(c->rhs); dfree(c->X); dfree(c->p); dfree(c->gflux); dfree(c->partial);
+  dfree(c->d_row_lvl); dfree(c->d_row_loc); dfree(c->d_col_lvl); dfree(c->d_col_loc);
+  dfree(c->d_lsize); dfree(c->d_binv); dfree(c->d_bgemm); dfree(c->d_bgemv);
+  dfree(c->bpool); dfree(c->bvec);
+  c->use_bcr = false;
+  c->bcr_ops.clear();
   c->plan_valid = false;
 }
 
@@ -177,6 +198,173 @@ void family(const mrcm_ctx* c, int q, const int lo[3], const int hi[3], const in
       if (keep) out.push_back(Seed{q, 2, 0, f});
     }
   }
+}
+
+// Plan of the block cyclic reduction (bcr.hip).  Equations are assigned to
+// subdomains: the flux rows of Gamma_ij to the lower index i, the pressure
+// rows to the higher index j; within a subdomain they follow its Gamma sides
+// in side order, which pairs them with the seeds of the same side.  A layer
+// is the set of subdomains with the same last-axis coordinate; the system is
+// block tridiagonal over layers.  Returns false (band LU is used) when a
+// layer block is not square or exceeds kBcrMaxBlock.
+bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
+              std::vector<int>& col_lvl, std::vector<int>& col_loc, std::vector<int>& lsize,
+              std::vector<int>& inv, std::vector<BcrGemm>& gemm, std::vector<BcrGemv>& gemv) {
+  const Geo& g = c->geo;
+  const int d = c->d, nsub = g.nsub, n = c->nX;
+  const int M = g.M[d - 1];
+  const int P = nsub / M;  // subdomains per layer (contiguous indices)
+  std::vector<int> ifc_of(3 * nsub, -1);
+  for (size_t k = 0; k < c->ifc.size(); ++k) ifc_of[3 * c->ifc[k].i + c->ifc[k].axis] = (int)k;
+  row_lvl.assign(n, -1);
+  row_loc.assign(n, -1);
+  col_lvl.assign(n, -1);
+  col_loc.assign(n, -1);
+  std::vector<int> rows(M, 0), cols(M, 0);
+  for (int i = 0; i < nsub; ++i) {
+    const int k = i / P;
+    for (int cc = c->seed_off[i]; cc < c->seed_off[i + 1]; ++cc) {
+      col_lvl[cc] = k;
+      col_loc[cc] = cols[k]++;
+    }
+    for (int q = 0; q < 2 * d; ++q) {
+      const int j = neighbor(c, i, q);
+      if (j < 0) continue;
+      const int a = q >> 1;
+      const bool lower = q & 1;  // i is the lower index of the interface
+      const int f = ifc_of[3 * (lower ? i : j) + a];
+      if (f < 0) return false;
+      const Iface& F = c->ifc[f];
+      const int r0 = F.row0 + (lower ? 0 : F.nbasis);
+      for (int mu = 0; mu < F.nbasis; ++mu) {
+        row_lvl[r0 + mu] = k;
+        row_loc[r0 + mu] = rows[k]++;
+      }
+    }
+  }
+  int bp = 0;
+  for (int k = 0; k < M; ++k) {
+    if (rows[k] != cols[k]) return false;
+    bp = std::max(bp, rows[k]);
+  }
+  for (int r = 0; r < n; ++r)
+    if (row_lvl[r] < 0) return false;
+  bp = (bp + 31) / 32 * 32;  // tile of the block products
+  if (bp == 0 || bp > kBcrMaxBlock) return false;
+  lsize = rows;
+  c->bcr_M = M;
+  c->bcr_bp = bp;
+
+  // schedule; block slots: D_k = k, L_k = M+k, U_k = 2M+k, then F_k = 3M+k,
+  // G_k = 4M+k for the layers eliminated at some level; vectors: r_k = k,
+  // g_k = M+k, x_k = 2M+k.  A reduced L_j / U_j is written to the slot of
+  // the eliminated neighbour's L / U, which is no longer read.
+  std::vector<int> dsl(M), lsl(M), usl(M);
+  for (int k = 0; k < M; ++k) {
+    dsl[k] = k;
+    lsl[k] = M + k;
+    usl[k] = 2 * M + k;
+  }
+  auto F = [&](int k) { return 3 * M + k; };
+  auto G = [&](int k) { return 4 * M + k; };
+  auto rv = [&](int k) { return k; };
+  auto gv = [&](int k) { return M + k; };
+  auto xv = [&](int k) { return 2 * M + k; };
+  auto op = [&](int kind, int off, int cnt) {
+    if (cnt > 0) c->bcr_ops.push_back(mrcm_ctx::BcrOp{kind, off, cnt});
+  };
+  std::vector<std::vector<BcrGemv>> back;
+  std::vector<int> idx(M);
+  for (int k = 0; k < M; ++k) idx[k] = k;
+  c->bcr_ops.clear();
+  while (idx.size() > 1) {
+    const int L = (int)idx.size();
+    // eliminated layers (odd positions): E_k = D_k^{-1}, F_k, G_k, g_k
+    int o = (int)inv.size();
+    for (int t = 1; t < L; t += 2) inv.push_back(dsl[idx[t]]);
+    op(0, o, (int)inv.size() - o);
+    o = (int)gemm.size();
+    for (int t = 1; t < L; t += 2) {
+      const int k = idx[t];
+      gemm.push_back(BcrGemm{F(k), -1, dsl[k], lsl[k], -1, -1, 1.0, 0.0});
+      if (t + 1 < L) gemm.push_back(BcrGemm{G(k), -1, dsl[k], usl[k], -1, -1, 1.0, 0.0});
+    }
+    op(1, o, (int)gemm.size() - o);
+    o = (int)gemv.size();
+    for (int t = 1; t < L; t += 2) {
+      const int k = idx[t];
+      gemv.push_back(BcrGemv{gv(k), -1, dsl[k], rv(k), -1, -1, 1.0, 0.0});
+    }
+    op(2, o, (int)gemv.size() - o);
+    // kept layers (even positions)
+    std::vector<int> nl(M, -1), nu(M, -1);
+    o = (int)gemm.size();
+    const int ov = (int)gemv.size();
+    for (int t = 0; t < L; t += 2) {
+      const int j = idx[t];
+      const bool hl = t > 0, hr = t + 1 < L;
+      const int km = hl ? idx[t - 1] : -1, kp = hr ? idx[t + 1] : -1;
+      BcrGemm Dt{dsl[j], dsl[j], -1, -1, -1, -1, -1.0, -1.0};
+      BcrGemv Rt{rv(j), rv(j), -1, -1, -1, -1, -1.0, -1.0};
+      if (hl) {
+        Dt.a1 = lsl[j];
+        Dt.b1 = G(km);
+        Rt.a1 = lsl[j];
+        Rt.x1 = gv(km);
+      }
+      if (hr) {
+        (hl ? Dt.a2 : Dt.a1) = usl[j];
+        (hl ? Dt.b2 : Dt.b1) = F(kp);
+        (hl ? Rt.a2 : Rt.a1) = usl[j];
+        (hl ? Rt.x2 : Rt.x1) = gv(kp);
+      }
+      gemm.push_back(Dt);
+      gemv.push_back(Rt);
+      if (hl && t - 1 > 0) {
+        gemm.push_back(BcrGemm{lsl[km], -1, lsl[j], F(km), -1, -1, -1.0, 0.0});
+        nl[j] = lsl[km];
+      }
+      if (hr && t + 2 < L) {
+        gemm.push_back(BcrGemm{usl[kp], -1, usl[j], G(kp), -1, -1, -1.0, 0.0});
+        nu[j] = usl[kp];
+      }
+    }
+    op(1, o, (int)gemm.size() - o);
+    op(2, ov, (int)gemv.size() - ov);
+    // back substitution of this level, replayed in reverse order
+    std::vector<BcrGemv> bk;
+    for (int t = 1; t < L; t += 2) {
+      const int k = idx[t];
+      BcrGemv B{xv(k), gv(k), F(k), xv(idx[t - 1]), -1, -1, -1.0, -1.0};
+      if (t + 1 < L) {
+        B.a2 = G(k);
+        B.x2 = xv(idx[t + 1]);
+      }
+      bk.push_back(B);
+    }
+    back.push_back(bk);
+    std::vector<int> keep;
+    for (int t = 0; t < L; t += 2) {
+      const int j = idx[t];
+      lsl[j] = nl[j];
+      usl[j] = nu[j];
+      keep.push_back(j);
+    }
+    idx.swap(keep);
+  }
+  const int k0 = idx[0];
+  int o = (int)inv.size();
+  inv.push_back(dsl[k0]);
+  op(0, o, 1);
+  o = (int)gemv.size();
+  gemv.push_back(BcrGemv{xv(k0), -1, dsl[k0], rv(k0), -1, -1, 1.0, 0.0});
+  op(2, o, 1);
+  for (int lv = (int)back.size() - 1; lv >= 0; --lv) {
+    o = (int)gemv.size();
+    for (const auto& B : back[lv]) gemv.push_back(B);
+    op(2, o, (int)back[lv].size());
+  }
+  return true;
 }
 
 mrcm_status make_plan(mrcm_ctx* c) {
@@ -386,7 +574,6 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->p, g.ncells);
   ALLOC(c->gflux, (long long)nsub * g.gstride);
   ALLOC(c->partial, 64);
-#undef ALLOC
   HIPCHK(c, hipMemcpy(c->d_obox, c->obox.data(), nsub * sizeof(Box), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_pbox, c->pbox.data(), nsub * sizeof(Box), hipMemcpyHostToDevice));
   if (!c->seeds.empty())
@@ -397,7 +584,66 @@ mrcm_status make_plan(mrcm_ctx* c) {
   if (!c->ifc.empty())
     HIPCHK(c, hipMemcpy(c->d_ifc, c->ifc.data(), c->ifc.size() * sizeof(Iface), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_members, c->members.data(), c->members.size() * sizeof(int), hipMemcpyHostToDevice));
+
+  // interface solver
+  c->use_bcr = false;
+  if (c->nX > 0 && c->iface_solver != MRCM_IFACE_BAND_LU) {
+    std::vector<int> rl, ro, cl, co, ls, inv;
+    std::vector<BcrGemm> gm;
+    std::vector<BcrGemv> gv;
+    const bool ok = bcr_plan(c, rl, ro, cl, co, ls, inv, gm, gv);
+    if (!ok && c->iface_solver == MRCM_IFACE_BCR)
+      return fail(c, MRCM_EINVAL,
+                  "block cyclic reduction needs square layer blocks of at most %d unknowns",
+                  kBcrMaxBlock);
+    if (ok) {
+      const int M = c->bcr_M;
+      const long long bs = (long long)c->bcr_bp * c->bcr_bp;
+      ALLOC(c->d_row_lvl, c->nX);
+      ALLOC(c->d_row_loc, c->nX);
+      ALLOC(c->d_col_lvl, c->nX);
+      ALLOC(c->d_col_loc, c->nX);
+      ALLOC(c->d_lsize, M);
+      ALLOC(c->d_binv, inv.size());
+      ALLOC(c->d_bgemm, gm.size());
+      ALLOC(c->d_bgemv, gv.size());
+      ALLOC(c->bpool, 5LL * M * bs);
+      ALLOC(c->bvec, 3LL * M * c->bcr_bp);
+      auto up = [&](void* dst, const void* src, size_t bytes) {
+        return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+      };
+      HIPCHK(c, up(c->d_row_lvl, rl.data(), rl.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_row_loc, ro.data(), ro.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_col_lvl, cl.data(), cl.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_col_loc, co.data(), co.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_lsize, ls.data(), ls.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_binv, inv.data(), inv.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_bgemm, gm.data(), gm.size() * sizeof(BcrGemm)));
+      HIPCHK(c, up(c->d_bgemv, gv.data(), gv.size() * sizeof(BcrGemv)));
+      c->use_bcr = true;
+    }
+  }
+#undef ALLOC
   c->plan_valid = true;
+  return MRCM_OK;
+}
+
+mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
+  const int M = c->bcr_M, bp = c->bcr_bp;
+  const long long bs = (long long)bp * bp;
+  HIPCHK(c, launch_fill(c->bpool, 0.0, 3LL * M * bs, s));
+  HIPCHK(c, launch_fill(c->bvec, 0.0, (long long)M * bp, s));
+  HIPCHK(c, launch_bcr_scatter(c->AB, c->rhs, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
+                               c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, c->d_lsize, s));
+  for (const auto& o : c->bcr_ops) {
+    if (o.kind == 0)
+      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, bp, c->flags, s));
+    else if (o.kind == 1)
+      HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, bp, s));
+    else
+      HIPCHK(c, launch_bcr_gemv(c->bpool, c->bvec, c->d_bgemv + o.off, o.cnt, bp, s));
+  }
+  HIPCHK(c, launch_bcr_gather(c->bvec + 2LL * M * bp, c->d_col_lvl, c->d_col_loc, c->nX, bp, c->X, s));
   return MRCM_OK;
 }
 
@@ -525,6 +771,14 @@ mrcm_status mrcm_set_partition(mrcm_ctx* c, const int* sub, int overlap) {
   return MRCM_OK;
 }
 
+mrcm_status mrcm_set_interface_solver(mrcm_ctx* c, mrcm_iface_solver solver) {
+  if (!c) return MRCM_EINVAL;
+  if (solver < MRCM_IFACE_AUTO || solver > MRCM_IFACE_BCR) return fail(c, MRCM_EINVAL, "bad interface solver");
+  c->iface_solver = solver;
+  invalidate(c, true);
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_set_interface_space(mrcm_ctx* c, mrcm_space space) {
   if (!c) return MRCM_EINVAL;
   if (space < MRCM_SPACE_CONST || space > MRCM_SPACE_FINE) return fail(c, MRCM_EINVAL, "bad space");
@@ -613,11 +867,17 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
                            c->kl, c->ku, c->rhs, s));
   if (c->nX > 0) {
     HIPCHK(c, hipEventRecord(c->ev[6], s));
-    hipError_t e = launch_bandlu_solve(c->AB, c->ldab, c->nX, c->kl, c->ku, c->rhs, c->X, nullptr,
-                                       c->flags, s);
-    if (e == hipErrorInvalidValue)
-      return fail(c, MRCM_EINVAL, "interface band (kl=%d, ku=%d) too wide for the LDS window", c->kl, c->ku);
-    HIPCHK(c, e);
+    if (c->use_bcr) {
+      mrcm_status st = bcr_solve(c, s);
+      if (st) return st;
+    } else {
+      hipError_t e = launch_bandlu_solve(c->AB, c->ldab, c->nX, c->kl, c->ku, c->rhs, c->X,
+                                         nullptr, c->flags, s);
+      if (e == hipErrorInvalidValue)
+        return fail(c, MRCM_EINVAL, "interface band (kl=%d, ku=%d) too wide for the LDS window",
+                    c->kl, c->ku);
+      HIPCHK(c, e);
+    }
     HIPCHK(c, hipEventRecord(c->ev[7], s));
   }
   HIPCHK(c, launch_combine(c->geo, c->d_seed_off, c->X, c->Pk, c->tr_u, c->pbar, c->ubar, c->p,
@@ -698,6 +958,7 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   out->n_unknowns = c->nX;
   out->band_kl = c->kl;
   out->band_ku = c->ku;
+  out->interface_solver = c->use_bcr ? MRCM_IFACE_BCR : MRCM_IFACE_BAND_LU;
   out->n_local_solves = c->n_local_solves;
   out->bytes_factor = (double)(c->fac_n + c->facp_n) *
                       (c->prec == MRCM_FP32_REFINE ? sizeof(float) : sizeof(double));

@@ -62,6 +62,18 @@ struct Iface {
   int basis0;   // index of its first test function in the basis array
 };
 
+// One batched block product of the cyclic reduction: block c of the pool :=
+// [block c0] + al1 * a1 * b1 [+ al2 * a2 * b2]  (an index < 0 drops a term).
+struct BcrGemm {
+  int c, c0, a1, b1, a2, b2;
+  double al1, al2;
+};
+// Vector form: vector y := [vector y0] + al1 * block a1 * vector x1 [+ ...].
+struct BcrGemv {
+  int y, y0, a1, x1, a2, x2;
+  double al1, al2;
+};
+
 // ---------------------------------------------------------------- launchers
 // local problems (local.hip)
 hipError_t launch_exp(const double* logk, double* K, int n, int* flags, hipStream_t s);
@@ -137,6 +149,19 @@ hipError_t launch_bandlu_solve(double* AB, int ldab, int n, int kl, int ku, doub
 hipError_t launch_combine(const Geo& g, const int* seed_off, const double* X, const double* Pk,
                           const double* tr_u, const double* pbar, const double* ubar,
                           double* p, double* gflux, hipStream_t s);
+
+// block cyclic reduction of the interface system (bcr.hip)
+constexpr int kBcrMaxBlock = 256;
+hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl, int ku,
+                              const int* row_lvl, const int* row_loc, const int* col_lvl,
+                              const int* col_loc, int M, int bp, double* pool, double* vec,
+                              const int* lsize, hipStream_t s);
+hipError_t launch_bcr_inv(double* pool, const int* blk, int nblk, int bp, int* flags, hipStream_t s);
+hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int bp, hipStream_t s);
+hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks, int ntask, int bp,
+                           hipStream_t s);
+hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* col_loc, int n, int bp,
+                             double* X, hipStream_t s);
 
 // outputs (outputs.hip)
 hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,

@@ -19,13 +19,21 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _check(wl, nsmooth=None, tol=TOL):
+SOLVER_NAME = {1: "band_lu", 2: "bcr"}
+
+
+def _check(wl, nsmooth=None, tol=TOL, solver="auto"):
     from gpu_util import gpu_solve, oracle_solve, rel
-    print("case", wl.name, wl.ncell, wl.sub, "l=%d" % wl.overlap, wl.space, "ns", nsmooth, flush=True)
-    p, fl, X, st = gpu_solve(wl, nsmooth=nsmooth)
+    print("case", wl.name, wl.ncell, wl.sub, "l=%d" % wl.overlap, wl.space, "ns", nsmooth,
+          "solver", solver, flush=True)
+    p, fl, X, st = gpu_solve(wl, nsmooth=nsmooth, solver=solver)
     rp, rf, rX, _ = oracle_solve(wl, nsmooth=nsmooth)
     ep, ef = rel(p, rp), rel(fl, rf)
-    print("  rel L2 p %.3e flux %.3e  (nX %d kl %d ku %d)" % (ep, ef, st["n_unknowns"], st["band_kl"], st["band_ku"]), flush=True)
+    used = SOLVER_NAME[st["interface_solver"]]
+    print("  rel L2 p %.3e flux %.3e  (nX %d kl %d ku %d, interface solver %s)"
+          % (ep, ef, st["n_unknowns"], st["band_kl"], st["band_ku"], used), flush=True)
+    if solver != "auto":
+        assert used == solver
     assert ep <= tol and ef <= tol
     return p, fl, X, rX
 
@@ -64,6 +72,27 @@ def test_c2_scaled_pure_neumann(overlap):
 @pytest.mark.parametrize("overlap", [0, 2, 4])
 def test_c2_full(overlap):
     _check(make_workload("c2", overlap=overlap))
+
+
+# The two interface solvers on the same systems (the natural-order banded LU
+# and the block cyclic reduction over subdomain layers).
+@pytest.mark.parametrize("solver", ["band_lu", "bcr"])
+@pytest.mark.parametrize("case", ["small_linear_l2", "small_const_l0", "c1", "c2_scaled_l2",
+                                  "c2_full_l0", "c2_full_l4", "c5", "c3_scaled"])
+def test_interface_solvers(case, solver):
+    wl = {
+        "small_linear_l2": lambda: _small(space="linear", overlap=2),
+        "small_const_l0": lambda: _small(space="const", overlap=0),
+        "c1": lambda: make_workload("c1"),
+        "c2_scaled_l2": lambda: make_workload("c2", scale=4, overlap=2),
+        "c2_full_l0": lambda: make_workload("c2", overlap=0),
+        "c2_full_l4": lambda: make_workload("c2", overlap=4),
+        "c5": lambda: make_workload("c5"),
+        "c3_scaled": lambda: make_workload("c3", scale=4),
+    }[case]()
+    ns = 0 if case.startswith("small") else None
+    _, _, X, rX = _check(wl, nsmooth=ns, solver=solver)
+    assert np.linalg.norm(X - rX) <= 1e-9 * np.linalg.norm(rX)
 
 
 def test_three_dimensional_small():
