@@ -473,10 +473,10 @@ mrcm_status make_plan(mrcm_ctx* c) {
     if (B.nb > 32 || P.nb > 32) c->wave = false;
     const int bm0 = B.hi[0] - B.lo[0], bm1 = B.hi[1] - B.lo[1];
     c->lds_basis = std::max(c->lds_basis, wave_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
-    c->lds_smooth = std::max(c->lds_smooth, wave_lds_bytes(bm0, bm1, 1));
+    c->lds_smooth = std::max(c->lds_smooth, wave_smooth_lds_bytes(bm0, bm1));
     c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1));
     c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0));
-    c->lds32_smooth = std::max(c->lds32_smooth, wave32_lds_bytes(bm0, bm1, 1, 1));
+    c->lds32_smooth = std::max(c->lds32_smooth, wave32_smooth_lds_bytes(bm0, bm1));
     c->lds32_part = std::max(c->lds32_part, wave32_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, 1));
   }
   if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024) c->wave = false;
@@ -820,7 +820,8 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     if (st) return st;
   }
   const bool r32 = c->prec == MRCM_FP32_REFINE;
-  if (r32 && (!c->wave || c->lds32_basis > 150 * 1024))
+  if (r32 && (!c->wave || c->lds32_basis > 150 * 1024 || c->lds32_smooth > 150 * 1024 ||
+              c->lds32_part > 150 * 1024))
     return fail(c, MRCM_EINVAL, "FP32 refinement is available for 2-D boxes with lines of <= 32 cells");
   hipStream_t s = c->stream;
   HIPCHK(c, hipEventRecord(c->ev[0], s));

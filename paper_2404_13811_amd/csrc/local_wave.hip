@@ -36,15 +36,6 @@ __device__ __forceinline__ double wgemv_one(const double w[HB], const double* z)
   return acc + half_swap(acc);
 }
 
-__device__ __forceinline__ void wload_block(const double* Wj, int nb, double w[HB]) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-#pragma unroll
-  for (int i = 0; i < HB; ++i) {
-    const int r = HB * h + i;
-    w[i] = (r < nb && c < nb) ? Wj[r * nb + c] : 0.0;
-  }
-}
 
 // Forward step of block j for all right-hand sides, inverse in w:
 // X_j <- W_j (X_j + t_{j-1} .* X_{j-1}).
@@ -52,6 +43,7 @@ __device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, con
                                          const double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  #pragma unroll 1
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     double v = 0.0;
@@ -74,6 +66,7 @@ __device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, con
                                          const double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  #pragma unroll 1
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     s.Z[k * NBW + r] = (r < nb) ? s.Tn[j * nb + r] * s.X[k * ncell + (j + 1) * nb + r] : 0.0;
@@ -87,7 +80,7 @@ __device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, con
 }
 
 // Factorisation fused with the forward sweep; inverses to Wg, couplings to Tg.
-__device__ void factor_forward(const Box& B, double* Wg, double* Tg, int nrhs, const BoxLds& s,
+__device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double* Tg, int nrhs, const BoxLds& s,
                                WaveSmem& sm) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
@@ -110,43 +103,128 @@ __device__ void factor_forward(const Box& B, double* Wg, double* Tg, int nrhs, c
 }
 
 // Sweeps with the cached inverses streamed from memory, RING blocks ahead.
-__device__ void forward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
+__device__ __forceinline__ void forward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
   const int nb = B.nb, nblk = B.nblk;
   const long long bs = (long long)nb * nb;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
   double w[RING][HB];
 #pragma unroll
   for (int q = 0; q < RING; ++q)
-    if (q < nblk) wload_block(Wg + q * bs, nb, w[q]);
+    if (q < nblk) wload_block(src, q, w[q]);
   for (int j0 = 0; j0 < nblk; j0 += RING) {
 #pragma unroll
     for (int q = 0; q < RING; ++q) {
       const int j = j0 + q;
       if (j < nblk) {
         fwd_step(nb, B.ncell, j, nrhs, s, w[q]);
-        if (j + RING < nblk) wload_block(Wg + (j + RING) * bs, nb, w[q]);
+        if (j + RING < nblk) wload_block(src, (j + RING), w[q]);
       }
     }
   }
 }
 
-__device__ void backward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
+__device__ __forceinline__ void backward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
   const int nb = B.nb, nblk = B.nblk;
   const long long bs = (long long)nb * nb;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
   double w[RING][HB];
   // block j = nblk - 2 - t uses ring slot t % RING
 #pragma unroll
   for (int q = 0; q < RING; ++q)
-    if (nblk - 2 - q >= 0) wload_block(Wg + (nblk - 2 - q) * bs, nb, w[q]);
+    if (nblk - 2 - q >= 0) wload_block(src, (nblk - 2 - q), w[q]);
   for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
 #pragma unroll
     for (int q = 0; q < RING; ++q) {
       const int j = nblk - 2 - (t0 + q);
       if (j >= 0) {
         bwd_step(nb, B.ncell, j, nrhs, s, w[q]);
-        if (j - RING >= 0) wload_block(Wg + (j - RING) * bs, nb, w[q]);
+        if (j - RING >= 0) wload_block(src, (j - RING), w[q]);
       }
     }
   }
+}
+
+// W_j z for the block staged in z (LDS): lane (c, h) sums its 16 rows with
+// two accumulators; half_sum completes the column.
+__device__ __forceinline__ double wgemv2(const double w[HB], const double* z) {
+  const int h = lane_id() >> 5;
+  const double2* z2 = reinterpret_cast<const double2*>(z + HB * h);
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < HB / 2; ++i) {
+    const double2 v = z2[i];
+    a0 = fma(w[2 * i], v.x, a0);
+    a1 = fma(w[2 * i + 1], v.y, a1);
+  }
+  return half_sum(a0 + a1);
+}
+
+// Forward and backward sweeps of one right-hand side in s.X with the cached
+// inverses.  The value of the previous block stays in registers (every lane
+// of column c holds it), so a block step is one LDS write of the staged
+// vector, the 16-term products and one half-wave exchange.  z points to
+// 2 x NBW doubles of LDS (alternating buffers).
+__device__ __forceinline__ void sweep1(const Box& B, const double* Wg, const BoxLds& s, double* z) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb, nblk = B.nblk;
+  const bool cv = c < nb;
+  const long long bs = (long long)nb * nb;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  {
+    double w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (q < nblk) wload_block(src, q, w[q]);
+    double y = 0.0;
+    double xn = cv ? s.X[c] : 0.0, tp = 0.0;
+    for (int j0 = 0; j0 < nblk; j0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = j0 + q;
+        if (j < nblk) {
+          double* zb = z + (j & 1) * NBW;
+          if (h == 0) zb[c] = cv ? fma(tp, y, xn) : 0.0;
+          __builtin_amdgcn_wave_barrier();
+          const bool more = j + 1 < nblk;
+          xn = (more && cv) ? s.X[(j + 1) * nb + c] : 0.0;
+          tp = (more && cv) ? s.Tn[j * nb + c] : 0.0;
+          y = wgemv2(w[q], zb);
+          if (h == 0 && cv) s.X[j * nb + c] = y;
+          if (j + RING < nblk) wload_block(src, (j + RING), w[q]);
+        }
+      }
+    }
+  }
+  {
+    double w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (nblk - 2 - q >= 0) wload_block(src, (nblk - 2 - q), w[q]);
+    // x_{nblk-1} = w_{nblk-1} is final; every lane of column c reads it
+    __builtin_amdgcn_wave_barrier();
+    double xnext = cv ? s.X[(nblk - 1) * nb + c] : 0.0;
+    double tj = (nblk >= 2 && cv) ? s.Tn[(nblk - 2) * nb + c] : 0.0;
+    double wj = (nblk >= 2 && cv) ? s.X[(nblk - 2) * nb + c] : 0.0;
+    for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = nblk - 2 - (t0 + q);
+        if (j >= 0) {
+          double* zb = z + (j & 1) * NBW;
+          if (h == 0) zb[c] = cv ? tj * xnext : 0.0;
+          __builtin_amdgcn_wave_barrier();
+          const double wcur = wj;
+          tj = (j >= 1 && cv) ? s.Tn[(j - 1) * nb + c] : 0.0;
+          wj = (j >= 1 && cv) ? s.X[(j - 1) * nb + c] : 0.0;
+          xnext = wcur + wgemv2(w[q], zb);
+          if (h == 0 && cv) s.X[j * nb + c] = xnext;
+          if (j - RING >= 0) wload_block(src, (j - RING), w[q]);
+        }
+      }
+    }
+  }
+  wsync();
 }
 
 // ------------------------------------------------------------------ kernels
@@ -177,6 +255,7 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
     const Seed sd = seeds[B.seed0 + k];
     const int a = sd.side >> 1, so = sd.side & 1;
     const int nf = (a == 0) ? s.m1 : s.m0;
+    #pragma unroll 1
     for (int t = L; t < nf; t += 64) {
       int c[3];
       if (a == 0) { c[0] = so ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
@@ -195,6 +274,7 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
   int olo[3], ohi[3];
   womega(g, B.sub, olo, ohi);
   const int ncell_o = g.S[0] * g.S[1];
+  #pragma unroll 1
   for (int e = L; e < nrhs * ncell_o; e += 64) {
     const int k = e / ncell_o, t = e % ncell_o;
     Pk[(long long)(B.seed0 + k) * ncell_o + t] =
@@ -204,6 +284,7 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
     const bool has = wneighbor(g, B.sub, q) >= 0;
     const int a = q >> 1, so = q & 1;
+    #pragma unroll 1
     for (int e = L; e < nrhs * nf; e += 64) {
       const int k = e / nf, t = e % nf;
       const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
@@ -264,6 +345,7 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
     const bool has = wneighbor(g, B.sub, q) >= 0;
     const int a = q >> 1, so = q & 1;
+    #pragma unroll 1
     for (int t = L; t < nf; t += 64) {
       const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
       if (!has) {
@@ -285,8 +367,12 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-// Steps 6-7: one color phase of the smoothing sweep.
-__global__ void __launch_bounds__(64) k_smooth_w(Geo g, const Box* __restrict__ boxes,
+// Steps 6-7: one color phase of the smoothing sweep.  Four waves per box
+// stage the box's data, build the right-hand side and write the outputs; the
+// first wave runs the block sweeps.
+constexpr int kSmoothThreads = 256;
+
+__global__ void __launch_bounds__(kSmoothThreads) k_smooth_w(Geo g, const Box* __restrict__ boxes,
                                                  const int* __restrict__ members,
                                                  const double* __restrict__ K,
                                                  const double* __restrict__ f,
@@ -295,76 +381,16 @@ __global__ void __launch_bounds__(64) k_smooth_w(Geo g, const Box* __restrict__ 
                                                  const double* __restrict__ tcoup,
                                                  double* __restrict__ p,
                                                  double* __restrict__ gflux) {
+  constexpr int NT = kSmoothThreads;
   extern __shared__ double dsm[];
   const Box B = boxes[members[blockIdx.x]];
-  const int L = lane_id();
-  BoxLds s = carve(dsm, B, 1);
-  const int nc = B.ncell;
-  // K tile and couplings (the factor's diagonal is not needed here)
-  {
-    const int W2 = s.m0 + 2, H2 = s.m1 + 2;
-    for (int e = L; e < W2 * H2; e += 64) {
-      const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
-      s.Kt[e] = (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K[x + g.n[0] * y] : 1.0;
-    }
-    const double* Tg = tcoup + B.scr;
-    for (int e = L; e < nc; e += 64) s.Tn[e] = Tg[e];
-  }
-  wsync();
-  for (int loc = L; loc < nc; loc += 64) {
-    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
-    const int ci = x + g.n[0] * y;
-    const double kc = kat(s, B, x, y);
-    double b = f[ci] * g.vol;
-    const int c[3] = {x, y, 0};
-    for (int a = 0; a < 2; ++a)
-      for (int sd = 0; sd < 2; ++sd) {
-        const int kind = face_kind(g, B, c, a, sd);
-        if (kind == kFaceInterior) continue;
-        const int side = 2 * a + sd;
-        if (kind == kFaceRobin) {
-          const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
-          const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
-          b += robin_T(g, kc, bt) * wlambda(g, B, s, p, gflux, beta, x, y, a, sd);
-        } else {
-          const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-          if (kind == kFaceDir) b += 2.0 * kc * g.area / g.h * val;
-          else b -= g.area * val;
-        }
-      }
-    s.X[loc] = b;
-  }
-  wsync();
-  const double* Wg = fac + B.fac;
-  forward_cached(B, Wg, 1, s);
-  backward_cached(B, Wg, 1, s);
-  int olo[3], ohi[3];
-  womega(g, B.sub, olo, ohi);
-  for (int q = 0; q < 4; ++q) {
-    if (wneighbor(g, B.sub, q) < 0) continue;
-    const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
-    const int a = q >> 1, so = q & 1;
-    for (int t = L; t < nf; t += 64) {
-      int x, y;
-      wgface(olo, ohi, q, t, x, y);
-      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
-      const double xc = s.X[bloc(B, s, x, y)];
-      double u;
-      if (win_box(B, ox, oy)) {
-        u = g.area * kharm(kc, ko) / g.h * (xc - s.X[bloc(B, s, ox, oy)]) / g.area;
-      } else {
-        const double lam = wlambda(g, B, s, p, gflux, beta, x, y, a, so);
-        u = robin_T(g, kc, robin_beta(g, a, kc, ko, beta)) * (xc - lam) / g.area;
-      }
-      gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
-    }
-  }
-  const int ncell_o = g.S[0] * g.S[1];
-  for (int t = L; t < ncell_o; t += 64) {
-    const int x = olo[0] + t % g.S[0], y = olo[1] + t / g.S[0];
-    p[x + g.n[0] * y] = s.X[bloc(B, s, x, y)];
-  }
+  SmoothLds r = carve_smooth(dsm, B);
+  stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
+  __syncthreads();
+  smooth_rhs<NT>(g, B, r, beta, r.b.X);
+  if (threadIdx.x < 64) sweep1(B, fac + B.fac, r.b, r.b.Z);
+  __syncthreads();
+  smooth_out<NT>(g, B, r, r.b.X, beta, p, gflux);
 }
 
 template <typename KF>
@@ -380,6 +406,8 @@ hipError_t set_lds(KF kern, size_t bytes) {
 size_t wave_lds_bytes(int m0, int m1, int nrhs) {
   return sizeof(double) * box_lds_doubles(m0, m1, nrhs);
 }
+
+size_t wave_smooth_lds_bytes(int m0, int m1) { return sizeof(double) * smooth_lds_doubles(m0, m1); }
 
 hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                           const double* K, double beta, double* fac, double* tcoup, double* scr,
@@ -415,7 +443,7 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
   if (nmem <= 0) return hipSuccess;
   hipError_t e = set_lds(k_smooth_w, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_smooth_w, dim3(nmem), dim3(64), lds, s, g, boxes, members, K, f, bcv, beta,
+  hipLaunchKernelGGL(k_smooth_w, dim3(nmem), dim3(kSmoothThreads), lds, s, g, boxes, members, K, f, bcv, beta,
                      fac, tcoup, p, gflux);
   return hipGetLastError();
 }

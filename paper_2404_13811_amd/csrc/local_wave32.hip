@@ -39,7 +39,7 @@ struct BoxR {
 __host__ __device__ inline size_t boxr_bytes(int m0, int m1, int nrhs, int nbrhs) {
   const size_t nc = (size_t)m0 * m1;
   const size_t d = (size_t)(m0 + 2) * (m1 + 2) + 3 * nc + nrhs * nc + nc + nbrhs * nc;
-  const size_t f = nrhs * nc + 2 * nc + (size_t)nrhs * NBW;
+  const size_t f = nrhs * nc + 2 * nc + (size_t)(nrhs < 2 ? 2 : nrhs) * NBW;
   return d * sizeof(double) + f * sizeof(float);
 }
 
@@ -65,16 +65,20 @@ __device__ __forceinline__ BoxR carve_r(double* base, const Box& B, int nrhs, in
 }
 
 // Scale factors and scaled couplings (after load_box).
-__device__ void scale_box(const Box& B, BoxR& R) {
+template <int NT = 64>
+__device__ __forceinline__ void scale_box(const Box& B, BoxR& R) {
   const int nc = B.ncell, nb = B.nb;
-  for (int e = lane_id(); e < nc; e += 64) R.sd[e] = 1.0 / sqrt(R.b.Dg[e]);
-  wsync();
-  for (int e = lane_id(); e < nc; e += 64) {
+  const int tid = threadIdx.x % NT;
+#pragma unroll 1
+  for (int e = tid; e < nc; e += NT) R.sd[e] = rcp_d(sqrt(R.b.Dg[e]));
+  bsync<NT>();
+#pragma unroll 1
+  for (int e = tid; e < nc; e += NT) {
     const int xl = e % R.b.m0;
     R.Txf[e] = (xl + 1 < R.b.m0) ? (float)(R.b.Tx[e] * R.sd[e] * R.sd[e + 1]) : 0.0f;
     R.Tnf[e] = (e + nb < nc) ? (float)(R.b.Tn[e] * R.sd[e] * R.sd[e + nb]) : 0.0f;
   }
-  wsync();
+  bsync<NT>();
 }
 
 __device__ __forceinline__ float half_swap_f(float v) { return __shfl_xor(v, 32); }
@@ -137,19 +141,11 @@ __device__ __forceinline__ float wgemv32(const float w[HB], const float* z) {
   return acc + half_swap_f(acc);
 }
 
-__device__ __forceinline__ void wload32(const float* Wj, int nb, float w[HB]) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-#pragma unroll
-  for (int i = 0; i < HB; ++i) {
-    const int r = HB * h + i;
-    w[i] = (r < nb && c < nb) ? Wj[r * nb + c] : 0.0f;
-  }
-}
 
 __device__ __forceinline__ void fwd32(int nb, int nc, int j, int nrhs, const BoxR& R, const float w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  #pragma unroll 1
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     float v = 0.0f;
@@ -170,6 +166,7 @@ __device__ __forceinline__ void fwd32(int nb, int nc, int j, int nrhs, const Box
 __device__ __forceinline__ void bwd32(int nb, int nc, int j, int nrhs, const BoxR& R, const float w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  #pragma unroll 1
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     R.Zf[k * NBW + r] = (r < nb) ? R.Tnf[j * nb + r] * R.Wf[k * nc + (j + 1) * nb + r] : 0.0f;
@@ -182,7 +179,7 @@ __device__ __forceinline__ void bwd32(int nb, int nc, int j, int nrhs, const Box
   wsync();
 }
 
-__device__ void factor32(const Box& B, float* Wg, const BoxR& R, WaveSmemF& sm) {
+__device__ __forceinline__ void factor32(const Box& B, float* Wg, const BoxR& R, WaveSmemF& sm) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
   const int nb = B.nb;
@@ -203,21 +200,22 @@ __device__ void factor32(const Box& B, float* Wg, const BoxR& R, WaveSmemF& sm) 
 }
 
 // FP32 solve of the scaled system on every work vector in R.Wf.
-__device__ void solve32(const Box& B, const float* Wg, int nrhs, const BoxR& R) {
+__device__ __forceinline__ void solve32(const Box& B, const float* Wg, int nrhs, const BoxR& R) {
   const int nb = B.nb, nblk = B.nblk, nc = B.ncell;
   const long long bs = (long long)nb * nb;
+  const BlockSrc<float> src = block_src(Wg, nb, nblk);
   {
     float w[RING][HB];
 #pragma unroll
     for (int q = 0; q < RING; ++q)
-      if (q < nblk) wload32(Wg + q * bs, nb, w[q]);
+      if (q < nblk) wload_block(src, q, w[q]);
     for (int j0 = 0; j0 < nblk; j0 += RING) {
 #pragma unroll
       for (int q = 0; q < RING; ++q) {
         const int j = j0 + q;
         if (j < nblk) {
           fwd32(nb, nc, j, nrhs, R, w[q]);
-          if (j + RING < nblk) wload32(Wg + (j + RING) * bs, nb, w[q]);
+          if (j + RING < nblk) wload_block(src, (j + RING), w[q]);
         }
       }
     }
@@ -226,22 +224,127 @@ __device__ void solve32(const Box& B, const float* Wg, int nrhs, const BoxR& R) 
     float w[RING][HB];
 #pragma unroll
     for (int q = 0; q < RING; ++q)
-      if (nblk - 2 - q >= 0) wload32(Wg + (nblk - 2 - q) * bs, nb, w[q]);
+      if (nblk - 2 - q >= 0) wload_block(src, (nblk - 2 - q), w[q]);
     for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
 #pragma unroll
       for (int q = 0; q < RING; ++q) {
         const int j = nblk - 2 - (t0 + q);
         if (j >= 0) {
           bwd32(nb, nc, j, nrhs, R, w[q]);
-          if (j - RING >= 0) wload32(Wg + (j - RING) * bs, nb, w[q]);
+          if (j - RING >= 0) wload_block(src, (j - RING), w[q]);
         }
       }
     }
   }
 }
 
+// Single right-hand side in R.Wf: forward and backward sweeps with the
+// previous block's values kept in registers (as the FP64 sweep).
+__device__ __forceinline__ float wgemv2f(const float w[HB], const float* z) {
+  const int h = lane_id() >> 5;
+  const float4* z4 = reinterpret_cast<const float4*>(z + HB * h);
+  float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < HB / 4; ++i) {
+    const float4 v = z4[i];
+    a0 = fmaf(w[4 * i], v.x, a0);
+    a1 = fmaf(w[4 * i + 1], v.y, a1);
+    a0 = fmaf(w[4 * i + 2], v.z, a0);
+    a1 = fmaf(w[4 * i + 3], v.w, a1);
+  }
+  return half_sum_f(a0 + a1);
+}
+
+__device__ __forceinline__ void sweep1f(const Box& B, const float* Wg, const BoxR& R) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb, nblk = B.nblk;
+  const bool cv = c < nb;
+  const long long bs = (long long)nb * nb;
+  const BlockSrc<float> src = block_src(Wg, nb, nblk);
+  float* X = R.Wf;
+  const float* Tn = R.Tnf;
+  float* z = R.Zf;
+  {
+    float w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (q < nblk) wload_block(src, q, w[q]);
+    float y = 0.0f, xn = cv ? X[c] : 0.0f, tp = 0.0f;
+    for (int j0 = 0; j0 < nblk; j0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = j0 + q;
+        if (j < nblk) {
+          float* zb = z + (j & 1) * NBW;
+          if (h == 0) zb[c] = cv ? fmaf(tp, y, xn) : 0.0f;
+          __builtin_amdgcn_wave_barrier();
+          const bool more = j + 1 < nblk;
+          xn = (more && cv) ? X[(j + 1) * nb + c] : 0.0f;
+          tp = (more && cv) ? Tn[j * nb + c] : 0.0f;
+          y = wgemv2f(w[q], zb);
+          if (h == 0 && cv) X[j * nb + c] = y;
+          if (j + RING < nblk) wload_block(src, (j + RING), w[q]);
+        }
+      }
+    }
+  }
+  {
+    float w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (nblk - 2 - q >= 0) wload_block(src, (nblk - 2 - q), w[q]);
+    __builtin_amdgcn_wave_barrier();
+    float xnext = cv ? X[(nblk - 1) * nb + c] : 0.0f;
+    float tj = (nblk >= 2 && cv) ? Tn[(nblk - 2) * nb + c] : 0.0f;
+    float wj = (nblk >= 2 && cv) ? X[(nblk - 2) * nb + c] : 0.0f;
+    for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = nblk - 2 - (t0 + q);
+        if (j >= 0) {
+          float* zb = z + (j & 1) * NBW;
+          if (h == 0) zb[c] = cv ? tj * xnext : 0.0f;
+          __builtin_amdgcn_wave_barrier();
+          const float wcur = wj;
+          tj = (j >= 1 && cv) ? Tn[(j - 1) * nb + c] : 0.0f;
+          wj = (j >= 1 && cv) ? X[(j - 1) * nb + c] : 0.0f;
+          xnext = wcur + wgemv2f(w[q], zb);
+          if (h == 0 && cv) X[j * nb + c] = xnext;
+          if (j - RING >= 0) wload_block(src, (j - RING), w[q]);
+        }
+      }
+    }
+  }
+  wsync();
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over the wave of non-negative values: quad and row steps by DPP,
+// then the row pairs and the half-waves by lane swaps (no LDS).
 __device__ __forceinline__ double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  v = fmax(v, dpp_d<0xB1>(v));   // quad_perm(1,0,3,2)
+  v = fmax(v, dpp_d<0x4E>(v));   // quad_perm(2,3,0,1)
+  v = fmax(v, dpp_d<0x124>(v));  // row_ror:4
+  v = fmax(v, dpp_d<0x128>(v));  // row_ror:8
+  {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const auto l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    v = fmax(__hiloint2double(h2[0], l2[0]), __hiloint2double(h2[1], l2[1]));
+  }
+  {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    v = fmax(__hiloint2double(h2[0], l2[0]), __hiloint2double(h2[1], l2[1]));
+  }
   return v;
 }
 
@@ -261,7 +364,8 @@ __device__ __forceinline__ double seed_rhs(const Geo& g, const Box& B, const Box
 
 // Iterative refinement of nrhs systems A x_k = b_k; b from seeds (if
 // seeds != nullptr) or from R.Bv.  Returns the number of FP32 solves.
-__device__ int refine(const Geo& g, const Box& B, const BoxR& R, const float* Wg, int nrhs,
+template <bool ONE>
+__device__ __forceinline__ int refine(const Geo& g, const Box& B, const BoxR& R, const float* Wg, int nrhs,
                       const Seed* seeds, double beta, double tol, int max_refine, double& omega_out,
                       WaveSmemF& sm) {
   const int L = lane_id();
@@ -276,6 +380,7 @@ __device__ int refine(const Geo& g, const Box& B, const BoxR& R, const float* Wg
     for (int k = 0; k < nrhs; ++k) {
       const double* x = R.b.X + (size_t)k * nc;
       double om = 0.0;
+      #pragma unroll 1
       for (int loc = L; loc < nc; loc += 64) {
         const double bv = seeds ? seed_rhs(g, B, R, seeds[B.seed0 + k], beta, loc) : R.Bv[loc];
         const int xl = loc % m0;
@@ -298,7 +403,8 @@ __device__ int refine(const Geo& g, const Box& B, const BoxR& R, const float* Wg
       if (L == 0) sm.flag |= kFlagNoConv;
       break;
     }
-    solve32(B, Wg, nrhs, R);
+    if (ONE) sweep1f(B, Wg, R);
+    else solve32(B, Wg, nrhs, R);
     for (int e = L; e < nrhs * nc; e += 64) R.b.X[e] += R.sd[e % nc] * (double)R.Wf[e];
     wsync();
     ++it;
@@ -339,13 +445,14 @@ __global__ void __launch_bounds__(64) k_basis32(Geo g, const Box* __restrict__ b
   float* Wg = fac32 + B.fac;
   factor32(B, Wg, R, sm);
   double omega = 0.0;
-  const int it = nrhs > 0 ? refine(g, B, R, Wg, nrhs, seeds, beta, tol, max_refine, omega, sm) : 0;
+  const int it = nrhs > 0 ? refine<false>(g, B, R, Wg, nrhs, seeds, beta, tol, max_refine, omega, sm) : 0;
   record_refine(it, omega, iters, resid);
   const BoxLds& s = R.b;
   const int nc = B.ncell;
   int olo[3], ohi[3];
   womega(g, B.sub, olo, ohi);
   const int ncell_o = g.S[0] * g.S[1];
+  #pragma unroll 1
   for (int e = L; e < nrhs * ncell_o; e += 64) {
     const int k = e / ncell_o, t = e % ncell_o;
     Pk[(long long)(B.seed0 + k) * ncell_o + t] =
@@ -355,6 +462,7 @@ __global__ void __launch_bounds__(64) k_basis32(Geo g, const Box* __restrict__ b
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
     const bool has = wneighbor(g, B.sub, q) >= 0;
     const int a = q >> 1, so = q & 1;
+    #pragma unroll 1
     for (int e = L; e < nrhs * nf; e += 64) {
       const int k = e / nf, t = e % nf;
       const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
@@ -411,7 +519,7 @@ __global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restric
   float* Wg = fac32 + B.fac;
   factor32(B, Wg, R, sm);
   double omega = 0.0;
-  const int it = refine(g, B, R, Wg, 1, nullptr, beta, tol, max_refine, omega, sm);
+  const int it = refine<true>(g, B, R, Wg, 1, nullptr, beta, tol, max_refine, omega, sm);
   record_refine(it, omega, iters, resid);
   const BoxLds& s = R.b;
   for (int t = L; t < B.ncell; t += 64) pbar[(long long)B.sub * B.ncell + t] = s.X[t];
@@ -419,6 +527,7 @@ __global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restric
     const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
     const bool has = wneighbor(g, B.sub, q) >= 0;
     const int a = q >> 1, so = q & 1;
+    #pragma unroll 1
     for (int t = L; t < nf; t += 64) {
       const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
       if (!has) {
@@ -440,7 +549,14 @@ __global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restric
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-__global__ void __launch_bounds__(64) k_smooth32(Geo g, const Box* __restrict__ boxes,
+__host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1) {
+  const size_t nc = (size_t)m0 * m1;
+  return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW);
+}
+
+constexpr int kSmooth32Threads = 256;
+
+__global__ void __launch_bounds__(kSmooth32Threads) k_smooth32(Geo g, const Box* __restrict__ boxes,
                                                  const int* __restrict__ members,
                                                  const double* __restrict__ K,
                                                  const double* __restrict__ f,
@@ -450,72 +566,35 @@ __global__ void __launch_bounds__(64) k_smooth32(Geo g, const Box* __restrict__ 
                                                  double* __restrict__ gflux, double tol,
                                                  int max_refine, int* iters,
                                                  unsigned long long* resid, int* flags) {
+  constexpr int NT = kSmooth32Threads;
   extern __shared__ double dsm[];
   __shared__ WaveSmemF sm;
   const Box B = boxes[members[blockIdx.x]];
-  const int L = lane_id();
-  if (L == 0) sm.flag = 0;
-  BoxR R = carve_r(dsm, B, 1, 1);
-  load_box(g, B, K, beta, R.b);
-  scale_box(B, R);
-  const BoxLds& s = R.b;
+  if (threadIdx.x == 0) sm.flag = 0;
+  SmoothLds r = carve_smooth(dsm, B);
   const int nc = B.ncell;
-  for (int loc = L; loc < nc; loc += 64) {
-    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
-    const int ci = x + g.n[0] * y;
-    const double kc = kat(s, B, x, y);
-    double b = f[ci] * g.vol;
-    const int c[3] = {x, y, 0};
-    for (int a = 0; a < 2; ++a)
-      for (int sd = 0; sd < 2; ++sd) {
-        const int kind = face_kind(g, B, c, a, sd);
-        if (kind == kFaceInterior) continue;
-        const int side = 2 * a + sd;
-        if (kind == kFaceRobin) {
-          const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
-          const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
-          b += robin_T(g, kc, bt) * wlambda(g, B, s, p, gflux, beta, x, y, a, sd);
-        } else {
-          const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-          if (kind == kFaceDir) b += 2.0 * kc * g.area / g.h * val;
-          else b -= g.area * val;
-        }
-      }
-    R.Bv[loc] = b;
+  BoxR R;
+  R.b = r.b;
+  R.sd = r.b.Z + 2 * NBW;
+  R.Bv = R.sd + nc;
+  float* fb = reinterpret_cast<float*>(R.Bv + nc);
+  R.Wf = fb;
+  R.Txf = R.Wf + nc;
+  R.Tnf = R.Txf + nc;
+  R.Zf = R.Tnf + nc;
+  stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, nullptr);
+  __syncthreads();
+  smooth_rhs<NT>(g, B, r, beta, R.Bv);
+  coef_box<NT>(g, B, beta, R.b);
+  scale_box<NT>(B, R);
+  if (threadIdx.x < 64) {
+    double omega = 0.0;
+    const int it = refine<true>(g, B, R, fac32 + B.fac, 1, nullptr, beta, tol, max_refine, omega, sm);
+    record_refine(it, omega, iters, resid);
   }
-  wsync();
-  double omega = 0.0;
-  const int it = refine(g, B, R, fac32 + B.fac, 1, nullptr, beta, tol, max_refine, omega, sm);
-  record_refine(it, omega, iters, resid);
-  int olo[3], ohi[3];
-  womega(g, B.sub, olo, ohi);
-  for (int q = 0; q < 4; ++q) {
-    if (wneighbor(g, B.sub, q) < 0) continue;
-    const int nf = (q >> 1) == 0 ? g.S[1] : g.S[0];
-    const int a = q >> 1, so = q & 1;
-    for (int t = L; t < nf; t += 64) {
-      int x, y;
-      wgface(olo, ohi, q, t, x, y);
-      const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
-      const double xc = s.X[bloc(B, s, x, y)];
-      double u;
-      if (win_box(B, ox, oy)) {
-        u = g.area * kharm(kc, ko) / g.h * (xc - s.X[bloc(B, s, ox, oy)]) / g.area;
-      } else {
-        const double lam = wlambda(g, B, s, p, gflux, beta, x, y, a, so);
-        u = robin_T(g, kc, robin_beta(g, a, kc, ko, beta)) * (xc - lam) / g.area;
-      }
-      gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
-    }
-  }
-  const int ncell_o = g.S[0] * g.S[1];
-  for (int t = L; t < ncell_o; t += 64) {
-    const int x = olo[0] + t % g.S[0], y = olo[1] + t / g.S[0];
-    p[x + g.n[0] * y] = s.X[bloc(B, s, x, y)];
-  }
-  wsync();
-  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
+  __syncthreads();
+  smooth_out<NT>(g, B, r, R.b.X, beta, p, gflux);
+  if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
 template <typename KF>
@@ -529,6 +608,8 @@ hipError_t set_lds(KF kern, size_t bytes) {
 }  // namespace
 
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs) { return boxr_bytes(m0, m1, nrhs, nbrhs); }
+
+size_t wave32_smooth_lds_bytes(int m0, int m1) { return smooth32_lds_bytes(m0, m1); }
 
 hipError_t launch_basis32_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                             const double* K, double beta, float* fac32, double* Pk, double* tr_u,
@@ -564,7 +645,7 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members,
   if (nmem <= 0) return hipSuccess;
   hipError_t e = set_lds(k_smooth32, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_smooth32, dim3(nmem), dim3(64), lds, s, g, boxes, members, K, f, bcv, beta,
+  hipLaunchKernelGGL(k_smooth32, dim3(nmem), dim3(kSmooth32Threads), lds, s, g, boxes, members, K, f, bcv, beta,
                      fac32, p, gflux, tol, max_refine, iters, resid, flags);
   return hipGetLastError();
 }

@@ -108,6 +108,7 @@ hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int
 
 // one-wavefront-per-box 2-D kernels (local_wave.hip), blocks of <= 32 cells
 size_t wave_lds_bytes(int m0, int m1, int nrhs);
+size_t wave_smooth_lds_bytes(int m0, int m1);
 hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                           const double* K, double beta, double* fac, double* tcoup, double* scr,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, int* flags,
@@ -123,6 +124,7 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);
+size_t wave32_smooth_lds_bytes(int m0, int m1);
 hipError_t launch_basis32_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                             const double* K, double beta, float* fac32, double* Pk, double* tr_u,
                             double* tr_phi, double* tr_beta, double tol, int max_refine,

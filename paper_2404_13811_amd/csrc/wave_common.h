@@ -39,7 +39,110 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Synchronisation of the NT threads working on one box (NT = 64: one wave).
+template <int NT>
+__device__ __forceinline__ void bsync() {
+  if (NT == 64) wsync();
+  else __syncthreads();
+}
+
 __device__ __forceinline__ double half_swap(double v) { return __shfl_xor(v, 32); }
+
+// v(lane c) + v(lane c + 32) in every lane of column c, by two half-wave
+// swaps of the 32-bit words (no LDS); both halves add in the same order.
+__device__ __forceinline__ double half_sum(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+
+__device__ __forceinline__ float half_sum_f(float v) {
+  const int u = __float_as_int(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __int_as_float(a[0]) + __int_as_float(a[1]);
+}
+
+// Cached block inverses of one box (nblk row-major nb x nb blocks) read
+// through a buffer resource: per lane the byte offsets of its 16 entries
+// (row 16h + i, column c) within a block, and the buffer size for the padding
+// entries, which the range check turns into zeros; the block index goes into
+// the scalar offset.
+template <typename T>
+struct BlockSrc {
+  __amdgpu_buffer_rsrc_t rs;
+  int off[HB];
+  int bbytes;
+};
+
+template <typename T>
+__device__ __forceinline__ BlockSrc<T> block_src(const T* Wg, int nb, int nblk) {
+  BlockSrc<T> b;
+  const int bytes = nblk * nb * nb * (int)sizeof(T);
+  b.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Wg), (short)0, bytes, 0x00020000);
+  const int c = threadIdx.x & 31, h = (threadIdx.x >> 5) & 1;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    b.off[i] = (r < nb && c < nb) ? (r * nb + c) * (int)sizeof(T) : bytes;
+  }
+  b.bbytes = nb * nb * (int)sizeof(T);
+  return b;
+}
+
+__device__ __forceinline__ void wload_block(const BlockSrc<double>& b, int j, double w[HB]) {
+#pragma unroll
+  for (int i = 0; i < HB; ++i)
+    w[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.rs, b.off[i], j * b.bbytes, 0));
+}
+
+__device__ __forceinline__ void wload_block(const BlockSrc<float>& b, int j, float w[HB]) {
+#pragma unroll
+  for (int i = 0; i < HB; ++i)
+    w[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rs, b.off[i], j * b.bbytes, 0));
+}
+
+// dst[e] = *addr(e, fill) for e < n (or `fill` where addr returns nullptr),
+// by NT threads with CH loads each in flight before any of them is waited for.
+template <int CH, int NT = 64, typename AddrFn>
+__device__ __forceinline__ void gather(double* dst, int n, AddrFn addr) {
+  const int L = threadIdx.x % NT;
+#pragma unroll 1
+  for (int e0 = 0; e0 < n; e0 += NT * CH) {
+    double v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = e0 + u * NT + L;
+      double fill = 0.0;
+      const double* a = (e < n) ? addr(e, fill) : nullptr;
+      v[u] = a ? *a : fill;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = e0 + u * NT + L;
+      if (e < n) dst[e] = v[u];
+    }
+  }
+}
+
+// 1/x from the hardware estimate refined by two Newton steps (x normal).
+__device__ __forceinline__ double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Robin coefficients of the face between box cell c (K = kc) and the
+// outside cell o (K = ko): beta (paper: alpha H / K_H, or a constant) and
+// T^R = |e| / (h / (2 K_c) + beta), with reciprocals in place of divisions.
+__device__ __forceinline__ void robin_face(const Geo& g, int a, double kc, double ko, double beta,
+                                           double& bt, double& TR) {
+  const double Ha = (a == 0 ? g.S[0] : g.S[1]) * g.h;
+  bt = g.beta_mode == 1 ? beta : beta * Ha * (kc + ko) * rcp_d(2.0 * kc * ko);
+  TR = g.area * 2.0 * kc * rcp_d(g.h + 2.0 * kc * bt);
+}
 
 __host__ __device__ inline size_t box_lds_doubles(int m0, int m1, int nrhs) {
   const int nc = m0 * m1;
@@ -65,47 +168,63 @@ __device__ __forceinline__ double kat(const BoxLds& s, const Box& B, int x, int 
   return s.Kt[(y - B.lo[1] + 1) * (s.m0 + 2) + (x - B.lo[0] + 1)];
 }
 
+template <int NT = 64>
+__device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta, BoxLds& s);
+
 // Load the K tile and the matrix coefficients of the box into LDS.
-__device__ void load_box(const Geo& g, const Box& B, const double* K, double beta, BoxLds& s) {
+__device__ __forceinline__ void load_box(const Geo& g, const Box& B, const double* K, double beta, BoxLds& s) {
   const int L = lane_id();
   const int W2 = s.m0 + 2, H2 = s.m1 + 2;
-  for (int e = L; e < W2 * H2; e += 64) {
+  gather<16>(s.Kt, W2 * H2, [&](int e, double& fill) -> const double* {
     const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
-    s.Kt[e] = (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K[x + g.n[0] * y] : 1.0;
-  }
+    fill = 1.0;
+    return (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K + x + g.n[0] * y : nullptr;
+  });
   wsync();
+  coef_box(g, B, beta, s);
+}
+
+// Diagonal and couplings of the box matrix from the K tile in LDS.
+template <int NT>
+__device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta, BoxLds& s) {
   const int nc = s.m0 * s.m1;
-  for (int loc = L; loc < nc; loc += 64) {
+  const double ih = rcp_d(g.h);
+#pragma unroll 1
+  for (int loc = threadIdx.x % NT; loc < nc; loc += NT) {
     const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
     const double kc = kat(s, B, x, y);
     double diag = 0.0, tx = 0.0, tn = 0.0;
+#pragma unroll
     for (int a = 0; a < 2; ++a)
+#pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0);
         const int oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
         const int t = a == 0 ? ox : oy;
         if (t < 0 || t >= g.n[a]) {
-          if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area / g.h;
+          if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area * ih;
           continue;
         }
         const double ko = kat(s, B, ox, oy);
         const bool inside = ox >= B.lo[0] && ox < B.hi[0] && oy >= B.lo[1] && oy < B.hi[1];
         if (inside) {
-          const double T = g.area * kharm(kc, ko) / g.h;
+          const double T = g.area * 2.0 * kc * ko * rcp_d(kc + ko) * ih;
           diag += T;
           if (sd) {
             if (a == 0) tx = T;
             else tn = T;
           }
         } else {
-          diag += robin_T(g, kc, robin_beta(g, a, kc, ko, beta));
+          double bt, TR;
+          robin_face(g, a, kc, ko, beta, bt, TR);
+          diag += TR;
         }
       }
     s.Dg[loc] = diag;
     s.Tx[loc] = tx;
     s.Tn[loc] = tn;
   }
-  wsync();
+  bsync<NT>();
 }
 
 // S_j (column c, my half) into w; w holds W_{j-1} on entry when j > 0.
@@ -188,13 +307,9 @@ __device__ __forceinline__ int wneighbor(const Geo& g, int sub, int q) {
 // Inner cell of face t on side q of [lo, hi) (2-D).
 __device__ __forceinline__ void wgface(const int lo[3], const int hi[3], int q, int t, int& x, int& y) {
   const int a = q >> 1, sd = q & 1;
-  if (a == 0) {
-    x = sd ? hi[0] - 1 : lo[0];
-    y = lo[1] + t;
-  } else {
-    y = sd ? hi[1] - 1 : lo[1];
-    x = lo[0] + t;
-  }
+  const int xe = sd ? hi[0] - 1 : lo[0], ye = sd ? hi[1] - 1 : lo[1];
+  x = a == 0 ? xe : lo[0] + t;
+  y = a == 0 ? lo[1] + t : ye;
 }
 
 __device__ __forceinline__ int bloc(const Box& B, const BoxLds& s, int x, int y) {
@@ -202,9 +317,10 @@ __device__ __forceinline__ int bloc(const Box& B, const BoxLds& s, int x, int y)
 }
 
 // Physical right-hand side (source, boundary data) of box B into out.
-__device__ void physical_rhs(const Geo& g, const Box& B, const BoxLds& s, const double* f,
+__device__ __forceinline__ void physical_rhs(const Geo& g, const Box& B, const BoxLds& s, const double* f,
                              const double* bcv, double* out) {
   const int nc = s.m0 * s.m1;
+  #pragma unroll 1
   for (int loc = lane_id(); loc < nc; loc += 64) {
     const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
     const int ci = x + g.n[0] * y;
@@ -247,6 +363,216 @@ __device__ __forceinline__ double wlambda(const Geo& g, const Box& B, const BoxL
   return bt * uj + pij;
 }
 
+
+// ----------------------------------------------------------------- smoothing
+// LDS of a smoothing box: the K and p tiles with a one-cell halo, the source,
+// the block couplings, the neighbours' Gamma fluxes on the box sides (used
+// when the boxes do not overlap) and the boundary data of the box sides on
+// the domain boundary, all gathered in one pass; then the matrix
+// coefficients, the solution vector and the block staging.
+struct SmoothLds {
+  BoxLds b;    // Kt, Dg, Tx, Tn, X, Z (Z: 2 x NBW)
+  double* P;   // (m0 + 2) x (m1 + 2) pressure tile
+  double* F;   // ncell source density
+  double* GF;  // 2 (m0 + m1): neighbour flux per face of each box side
+  double* BC;  // 2 (m0 + m1): boundary value per face of each box side
+};
+
+__host__ __device__ inline size_t smooth_lds_doubles(int m0, int m1) {
+  const size_t nc = (size_t)m0 * m1, nt = (size_t)(m0 + 2) * (m1 + 2);
+  return 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 2 * NBW;
+}
+
+__device__ __forceinline__ int side_off(const BoxLds& s, int q) {
+  // faces of side q are numbered along the tangential axis
+  return q == 0 ? 0 : q == 1 ? s.m1 : q == 2 ? 2 * s.m1 : 2 * s.m1 + s.m0;
+}
+
+// Gather order: [Kt | P | F | Tn | GF | BC] contiguous from `base`.
+__device__ __forceinline__ SmoothLds carve_smooth(double* base, const Box& B) {
+  SmoothLds r;
+  BoxLds& s = r.b;
+  s.m0 = B.hi[0] - B.lo[0];
+  s.m1 = B.hi[1] - B.lo[1];
+  const int nc = s.m0 * s.m1, nt = (s.m0 + 2) * (s.m1 + 2), ns = 2 * (s.m0 + s.m1);
+  s.Kt = base;
+  r.P = s.Kt + nt;
+  r.F = r.P + nt;
+  s.Tn = r.F + nc;
+  r.GF = s.Tn + nc;
+  r.BC = r.GF + ns;
+  s.Dg = r.BC + ns;
+  s.Tx = s.Dg + nc;
+  s.X = s.Tx + nc;
+  s.Z = s.X + nc;
+  return r;
+}
+
+// One gather for everything the smoothing solve of box B reads from memory.
+// The block couplings come from tcoup (cached by the factorisation) unless
+// it is null (then they are left to coef_box).
+template <int NT>
+__device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const SmoothLds& r,
+                                             const double* K, const double* p, const double* f,
+                                             const double* gflux, const double* bcv,
+                                             const double* tcoup) {
+  const BoxLds& s = r.b;
+  const int m0 = s.m0, m1 = s.m1, W2 = m0 + 2;
+  const int nc = m0 * m1, nt = W2 * (m1 + 2), ns = 2 * (m0 + m1);
+  const int n0 = g.n[0], n1 = g.n[1];
+  const int lo0 = B.lo[0], lo1 = B.lo[1];
+  const double* tg = tcoup ? tcoup + B.scr : nullptr;
+  gather<64 * 16 / NT, NT>(s.Kt, 2 * nt + 2 * nc, [&](int e, double& fill) -> const double* {
+    if (e < 2 * nt) {
+      const bool isk = e < nt;
+      const int u = isk ? e : e - nt;
+      const int y = lo1 - 1 + u / W2, x = lo0 - 1 + (u - (u / W2) * W2);
+      fill = isk ? 1.0 : 0.0;
+      if (x < 0 || x >= n0 || y < 0 || y >= n1) return nullptr;
+      return (isk ? K : p) + x + n0 * y;
+    }
+    e -= 2 * nt;
+    if (e < nc) return f + (lo0 + e % m0) + n0 * (lo1 + e / m0);
+    e -= nc;
+    return tg ? tg + e : nullptr;
+  });
+  // per side q: a box side on the domain boundary reads its boundary values;
+  // with non-overlapping boxes an interior side reads the neighbour's flux
+  const int Mx = g.M[0];
+  const int isub = B.sub % Mx, jsub = B.sub / Mx;
+  gather<64 * 4 / NT < 1 ? 1 : 64 * 4 / NT, NT>(r.GF, 2 * ns, [&](int e, double& fill) -> const double* {
+    fill = 0.0;
+    const bool isgf = e < ns;
+    const int u = isgf ? e : e - ns;
+    const int q = u < 2 * m1 ? (u < m1 ? 0 : 1) : (u < 2 * m1 + m0 ? 2 : 3);
+    const int t = u - (q == 0 ? 0 : q == 1 ? m1 : q == 2 ? 2 * m1 : 2 * m1 + m0);
+    const int a = q >> 1, sd = q & 1;
+    const int x = a == 0 ? (sd ? B.hi[0] - 1 : lo0) : lo0 + t;
+    const int y = a == 1 ? (sd ? B.hi[1] - 1 : lo1) : lo1 + t;
+    const int o = (a == 0 ? x : y) + (sd ? 1 : -1);
+    const bool dom = o < 0 || o >= (a == 0 ? n0 : n1);
+    if (!isgf) {
+      if (!dom) return nullptr;
+      const int off = q == 0 ? g.bc_off[0] : q == 1 ? g.bc_off[1] : q == 2 ? g.bc_off[2] : g.bc_off[3];
+      return bcv + off + (a == 0 ? y : x);
+    }
+    if (dom || g.l > 0) return nullptr;
+    // neighbour across side q and the face's position on its opposite side
+    const int j = B.sub + (a == 0 ? (sd ? 1 : -1) : (sd ? Mx : -Mx));
+    const int go = q == 0 ? g.gside_off[1] : q == 1 ? g.gside_off[0] : q == 2 ? g.gside_off[3] : g.gside_off[2];
+    const int tj = a == 0 ? y - jsub * g.S[1] : x - isub * g.S[0];
+    return gflux + (long long)j * g.gstride + go + tj;
+  });
+}
+
+// K and p at a cell of the box or its halo.
+__device__ __forceinline__ int tile_at(const BoxLds& s, const Box& B, int x, int y) {
+  return (y - B.lo[1] + 1) * (s.m0 + 2) + (x - B.lo[0] + 1);
+}
+
+// lambda on the face of box cell (x, y) normal to a on side sd of the box,
+// from the staged state (Section 3; the neighbour's flux and trace when the
+// boxes do not overlap).  bt is the face's beta.
+__device__ __forceinline__ double lambda_s(const Geo& g, const Box& B, const SmoothLds& r,
+                                           double bt, int x, int y, int a, int sd) {
+  const BoxLds& s = r.b;
+  const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+  const int ti = tile_at(s, B, x, y), to = tile_at(s, B, ox, oy);
+  const double kc = s.Kt[ti], ko = s.Kt[to];
+  if (g.l > 0) {
+    // u = K_H (p_c - p_o) / h, pi = p_c - u h / (2 K_c)
+    const double u = 2.0 * kc * ko * rcp_d(kc + ko) * (r.P[ti] - r.P[to]) * rcp_d(g.h);
+    const double pi = r.P[ti] - u * g.h * 0.5 * rcp_d(kc);
+    return -bt * u + pi;
+  }
+  const int q = 2 * a + sd;
+  const double uj = r.GF[side_off(s, q) + (a == 0 ? y - B.lo[1] : x - B.lo[0])];
+  const double pij = r.P[to] - uj * g.h * 0.5 * rcp_d(ko);
+  return bt * uj + pij;
+}
+
+// Right-hand side of the smoothing problem of box B into out (LDS), by NT
+// threads: the source on every cell, then the faces of the box sides (x
+// sides, then y sides, so that no cell is updated twice at once).
+template <int NT>
+__device__ __forceinline__ void smooth_rhs(const Geo& g, const Box& B, const SmoothLds& r,
+                                           double beta, double* out) {
+  const BoxLds& s = r.b;
+  const int nc = s.m0 * s.m1;
+  const int tid = threadIdx.x % NT;
+#pragma unroll 1
+  for (int loc = tid; loc < nc; loc += NT) out[loc] = r.F[loc] * g.vol;
+  bsync<NT>();
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int nf = a == 0 ? s.m1 : s.m0;
+#pragma unroll 1
+    for (int u = tid; u < 2 * nf; u += NT) {
+      const int sd = u >= nf, t = u - (sd ? nf : 0);
+      const int x = a == 0 ? (sd ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
+      const int y = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
+      const int c[3] = {x, y, 0};
+      const int kind = face_kind(g, B, c, a, sd);
+      const double kc = s.Kt[tile_at(s, B, x, y)];
+      double add;
+      if (kind == kFaceRobin) {
+        const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+        double bt, TR;
+        robin_face(g, a, kc, s.Kt[tile_at(s, B, ox, oy)], beta, bt, TR);
+        add = TR * lambda_s(g, B, r, bt, x, y, a, sd);
+      } else {
+        const double val = r.BC[side_off(s, 2 * a + sd) + t];
+        add = kind == kFaceDir ? 2.0 * kc * g.area / g.h * val : -g.area * val;
+      }
+      out[bloc(B, s, x, y)] += add;
+    }
+    bsync<NT>();
+  }
+}
+
+// Smoothing outputs of box B from its solution x (LDS), by NT threads: p on
+// Omega_i and Omega_i's own Gamma fluxes (TPFA of the new pressure; the
+// Robin formula with the staged lambda when the boxes do not overlap).
+template <int NT, typename T>
+__device__ __forceinline__ void smooth_out(const Geo& g, const Box& B, const SmoothLds& r, const T* x,
+                                           double beta, double* p, double* gflux) {
+  const BoxLds& s = r.b;
+  const int tid = threadIdx.x % NT;
+  int olo[3], ohi[3];
+  womega(g, B.sub, olo, ohi);
+  const int nfx = g.S[1], nfy = g.S[0];
+#pragma unroll 1
+  for (int u = tid; u < 2 * (nfx + nfy); u += NT) {
+    const int q = u < 2 * nfx ? (u < nfx ? 0 : 1) : (u < 2 * nfx + nfy ? 2 : 3);
+    const int t = u - (q == 0 ? 0 : q == 1 ? nfx : q == 2 ? 2 * nfx : 2 * nfx + nfy);
+    const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
+    const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
+    if (!has) continue;
+    const int a = q >> 1, so = q & 1;
+    int cx, cy;
+    wgface(olo, ohi, q, t, cx, cy);
+    const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
+    const double kc = s.Kt[tile_at(s, B, cx, cy)], ko = s.Kt[tile_at(s, B, ox, oy)];
+    const double xc = x[bloc(B, s, cx, cy)];
+    double v;
+    if (win_box(B, ox, oy)) {
+      v = 2.0 * kc * ko * rcp_d(kc + ko) * (xc - x[bloc(B, s, ox, oy)]) * rcp_d(g.h);
+    } else {
+      double bt, TR;
+      robin_face(g, a, kc, ko, beta, bt, TR);
+      const double lam = lambda_s(g, B, r, bt, cx, cy, a, so);
+      v = TR * (xc - lam) * rcp_d(g.area);
+    }
+    const int go = q == 0 ? g.gside_off[0] : q == 1 ? g.gside_off[1] : q == 2 ? g.gside_off[2] : g.gside_off[3];
+    gflux[(long long)B.sub * g.gstride + go + t] = v;
+  }
+  const int ncell_o = g.S[0] * g.S[1];
+#pragma unroll 1
+  for (int t = tid; t < ncell_o; t += NT) {
+    const int cx = olo[0] + t % g.S[0], cy = olo[1] + t / g.S[0];
+    p[cx + g.n[0] * cy] = x[bloc(B, s, cx, cy)];
+  }
+}
 
 }  // namespace wave
 }  // namespace mrcm
