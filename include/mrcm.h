@@ -102,6 +102,8 @@ typedef struct {
   double bytes_factor;     /* bytes of cached local factors                  */
   double ms_interface_solve; /* device time of the interface factor + solve  */
   int interface_solver;    /* MRCM_IFACE_BAND_LU or MRCM_IFACE_BCR in use      */
+  int n_smooth_launches;   /* colour-phase launches of the last mrcm_smooth    */
+  double ms_basis_kernel;  /* device time of the seed-solve kernel alone       */
 } mrcm_stats;
 
 /* Create a context for a dim-dimensional grid (dim = 2 or 3) of

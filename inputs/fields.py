@@ -8,7 +8,7 @@ every consumer.
   covariance ``sigma2 * exp(-sum_a (r_a / ell_a)^2)``, sampled by circulant
   embedding on a torus twice the domain size (negative spectral weights are
   clipped to zero).  Stands in for the heterogeneous benchmark field of the
-  paper (Section 4), which is not available.
+  paper (Section 5), which is not available.
 * ``channel_logk``: binary channelised field (background 1, channels
   ``contrast``), sinusoidal channel centrelines along x.
 * ``layered_logk``: anisotropic Gaussian field clipped to a contrast bound.

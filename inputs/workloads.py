@@ -4,7 +4,7 @@ Each workload is a plain record of arrays and parameters.  Sides of the domain
 are numbered 0..2d-1 as (-x, +x, -y, +y, -z, +z); boundary values are given per
 boundary face, in the x-fastest order of the cells adjacent to that side.
 
-Recipes (synthetic stand-ins for the paper's fields, Section 4):
+Recipes (synthetic stand-ins for the paper's fields, Section 5):
 
 * ``c1``: 64x64 unit square, 4x4 subdomains of 16x16 cells, overlap 2,
   piecewise-constant interface spaces, constant Robin parameter 1, Gaussian
@@ -136,7 +136,7 @@ def make_workload(name, scale=1, overlap=None, space=None, seed=None,
         w = Workload("c5", 2, ncell, h, y, np.zeros_like(y), tuple(types), vals,
                      (16, 16), 2, "const", "alpha", 1.0, 1.0, 5)
     elif name == "homog":
-        # constant K, f = 8 pi^2 cos(2 pi x) cos(2 pi y), no flow (Section 4)
+        # constant K, f = 8 pi^2 cos(2 pi x) cos(2 pi y), no flow (Section 5)
         m = max(1, 4 // scale)
         ncell = (20 * m, 20 * m)
         h = 1.0 / ncell[0]

@@ -27,7 +27,8 @@ class Stats(ctypes.Structure):
                 ("refine_max_iters", ctypes.c_int), ("refine_max_resid", ctypes.c_double),
                 ("ms_basis", ctypes.c_double), ("ms_interface", ctypes.c_double),
                 ("ms_smooth", ctypes.c_double), ("bytes_factor", ctypes.c_double),
-                ("ms_interface_solve", ctypes.c_double), ("interface_solver", ctypes.c_int)]
+                ("ms_interface_solve", ctypes.c_double), ("interface_solver", ctypes.c_int),
+                ("n_smooth_launches", ctypes.c_int), ("ms_basis_kernel", ctypes.c_double)]
 
 
 _lib = None

@@ -98,9 +98,11 @@ struct mrcm_ctx {
   BcrGemv* d_bgemv = nullptr;
   double *bpool = nullptr, *bvec = nullptr;
 
-  hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[10] = {nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed_basis = false, timed_iface = false, timed_smooth = false;
   int n_local_solves = 0;
+  int n_smooth_launches = 0;
 };
 
 namespace {
@@ -699,7 +701,7 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (e == hipSuccess) e = hipMalloc((void**)&c->f, N * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
-  for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 10 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   if (e == hipSuccess) e = launch_fill(c->bcv, 0.0, off, c->stream);
   if (e == hipSuccess) e = launch_fill(c->f, 0.0, N, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -830,23 +832,29 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   if (r32) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
+    HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis32_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf,
                                c->fac32, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->tol,
                                c->max_refine, c->d_iters, c->d_resid, c->flags, c->lds32_basis, s));
+    HIPCHK(c, hipEventRecord(c->ev[9], s));
     HIPCHK(c, launch_particular32_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv,
                                     c->beta_mbf, c->facp32, c->pbar, c->ubar, c->pibar, c->tol,
                                     c->max_refine, c->d_iters, c->d_resid, c->flags,
                                     c->lds32_part, s));
   } else if (c->wave) {
+    HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
                              c->tco, c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags,
                              c->lds_basis, s));
+    HIPCHK(c, hipEventRecord(c->ev[9], s));
     HIPCHK(c, launch_particular_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
                                   c->facp, c->tcp, c->scr, c->pbar, c->ubar, c->pibar, c->flags,
                                   c->lds_part, s));
   } else {
+    HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
                            c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
+    HIPCHK(c, hipEventRecord(c->ev[9], s));
     HIPCHK(c, launch_particular(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
                                 c->facp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
   }
@@ -895,6 +903,7 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   if (nsteps < 0) return fail(c, MRCM_EINVAL, "nsteps < 0");
   hipStream_t s = c->stream;
   HIPCHK(c, hipEventRecord(c->ev[4], s));
+  c->n_smooth_launches = nsteps << c->d;
   if (nsteps > 0 && c->beta_sm != c->beta_mbf && !c->facs) {
     return fail(c, MRCM_EINVAL, "distinct smoothing Robin parameter not available yet");
   }
@@ -979,6 +988,9 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   if (c->timed_smooth && hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) out->ms_smooth = ms;
   if (c->timed_iface && c->nX > 0 && hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess)
     out->ms_interface_solve = ms;
+  if (c->timed_basis && hipEventElapsedTime(&ms, c->ev[8], c->ev[9]) == hipSuccess)
+    out->ms_basis_kernel = ms;
+  out->n_smooth_launches = c->n_smooth_launches;
   return check_flags(c);
 }
 

@@ -65,7 +65,7 @@ def test_tpfa_equals_explicit_rt0_mixed_with_all_face_types():
 
 
 def test_fine_solution_converges_second_order_to_analytic():
-    """Homogeneous problem of Section 4: p = cos(2 pi x) cos(2 pi y)."""
+    """Homogeneous problem of Section 5: p = cos(2 pi x) cos(2 pi y)."""
     errs = []
     for n in (16, 32, 64):
         h = 1.0 / n
