@@ -51,28 +51,33 @@ __device__ __forceinline__ int face_kind(const Geo& g, const Box& B, const int c
   return kFaceInterior;
 }
 
+// Element t (0..2) of a 3-array by selects, so that a runtime axis does not
+// force the array into scratch memory.
+__device__ __forceinline__ int pick3(const int v[3], int t) { return t == 0 ? v[0] : t == 1 ? v[1] : v[2]; }
+
+// The tangential axes of a face normal to a (t1 unused in 2-D).
+__device__ __forceinline__ void tangential(int a, int& t0, int& t1) {
+  t0 = a == 0 ? 1 : 0;
+  t1 = a == 2 ? 1 : 2;
+}
+
 // Index of a boundary face of domain side (a, s) touched by global cell c.
 __device__ __forceinline__ int bface_index(const Geo& g, const int c[3], int a) {
-  int idx = 0, mult = 1;
-  for (int b = 0; b < g.d; ++b) {
-    if (b == a) continue;
-    idx += c[b] * mult;
-    mult *= g.n[b];
-  }
-  return idx;
+  int t0, t1;
+  tangential(a, t0, t1);
+  const int i0 = pick3(c, t0);
+  return g.d == 3 ? i0 + pick3(g.n, t0) * pick3(c, t1) : i0;
 }
 
 // Index of the face of side q of box [lo, hi) touched by global cell c
 // (x-fastest over the tangential axes).
 __device__ __forceinline__ int side_face_index(const Geo& g, const int lo[3], const int hi[3],
                                                const int c[3], int a) {
-  int idx = 0, mult = 1;
-  for (int b = 0; b < g.d; ++b) {
-    if (b == a) continue;
-    idx += (c[b] - lo[b]) * mult;
-    mult *= (hi[b] - lo[b]);
-  }
-  return idx;
+  int t0, t1;
+  tangential(a, t0, t1);
+  const int i0 = pick3(c, t0) - pick3(lo, t0);
+  if (g.d != 3) return i0;
+  return i0 + (pick3(hi, t0) - pick3(lo, t0)) * (pick3(c, t1) - pick3(lo, t1));
 }
 
 // Value of a seed (or interface test function) on the face of side
@@ -83,8 +88,8 @@ __device__ __forceinline__ double seed_value(const Geo& g, const Seed& sd, const
   if (sd.kind == 0) return 1.0;
   if (sd.kind == 1) {
     const int b = sd.axis;
-    const int m = hi[b] - lo[b];
-    return (2.0 * (c[b] - lo[b]) + 1.0) / m - 1.0;
+    const int m = pick3(hi, b) - pick3(lo, b);
+    return (2.0 * (pick3(c, b) - pick3(lo, b)) + 1.0) / m - 1.0;
   }
   return side_face_index(g, lo, hi, c, a) == sd.face ? 1.0 : 0.0;
 }

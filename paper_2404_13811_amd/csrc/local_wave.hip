@@ -27,15 +27,22 @@ namespace {
 
 using namespace wave;
 
-// Row c of W z (W symmetric, my half in w), summed over both halves.
-__device__ __forceinline__ double wgemv_one(const double w[HB], const double* z) {
-  const int h = lane_id() >> 5;
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < HB; ++i) acc = fma(w[i], z[HB * h + i], acc);
-  return acc + half_swap(acc);
-}
 
+
+// W_j z for the block staged in z (LDS): lane (c, h) sums its 16 rows with
+// two accumulators; half_sum completes the column.
+__device__ __forceinline__ double wgemv2(const double w[HB], const double* z) {
+  const int h = lane_id() >> 5;
+  const double2* z2 = reinterpret_cast<const double2*>(z + HB * h);
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < HB / 2; ++i) {
+    const double2 v = z2[i];
+    a0 = fma(w[2 * i], v.x, a0);
+    a1 = fma(w[2 * i + 1], v.y, a1);
+  }
+  return half_sum(a0 + a1);
+}
 
 // Forward step of block j for all right-hand sides, inverse in w:
 // X_j <- W_j (X_j + t_{j-1} .* X_{j-1}).
@@ -55,7 +62,7 @@ __device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, con
   }
   wsync();
   for (int k = 0; k < nrhs; ++k) {
-    const double y = wgemv_one(w, s.Z + k * NBW);
+    const double y = wgemv2(w, s.Z + k * NBW);
     if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] = y;
   }
   wsync();
@@ -73,7 +80,7 @@ __device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, con
   }
   wsync();
   for (int k = 0; k < nrhs; ++k) {
-    const double y = wgemv_one(w, s.Z + k * NBW);
+    const double y = wgemv2(w, s.Z + k * NBW);
     if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] += y;
   }
   wsync();
@@ -142,21 +149,6 @@ __device__ __forceinline__ void backward_cached(const Box& B, const double* Wg, 
       }
     }
   }
-}
-
-// W_j z for the block staged in z (LDS): lane (c, h) sums its 16 rows with
-// two accumulators; half_sum completes the column.
-__device__ __forceinline__ double wgemv2(const double w[HB], const double* z) {
-  const int h = lane_id() >> 5;
-  const double2* z2 = reinterpret_cast<const double2*>(z + HB * h);
-  double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-  for (int i = 0; i < HB / 2; ++i) {
-    const double2 v = z2[i];
-    a0 = fma(w[2 * i], v.x, a0);
-    a1 = fma(w[2 * i + 1], v.y, a1);
-  }
-  return half_sum(a0 + a1);
 }
 
 // Forward and backward sweeps of one right-hand side in s.X with the cached
@@ -240,7 +232,7 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
                                                 double* __restrict__ tr_u,
                                                 double* __restrict__ tr_phi,
                                                 double* __restrict__ tr_beta, int* flags) {
-  extern __shared__ double dsm[];
+  extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmem sm;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
@@ -328,7 +320,7 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
                                                      double* __restrict__ pbar,
                                                      double* __restrict__ ubar,
                                                      double* __restrict__ pibar, int* flags) {
-  extern __shared__ double dsm[];
+  extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmem sm;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
@@ -382,7 +374,7 @@ __global__ void __launch_bounds__(kSmoothThreads) k_smooth_w(Geo g, const Box* _
                                                  double* __restrict__ p,
                                                  double* __restrict__ gflux) {
   constexpr int NT = kSmoothThreads;
-  extern __shared__ double dsm[];
+  extern __shared__ __align__(16) double dsm[];
   const Box B = boxes[members[blockIdx.x]];
   SmoothLds r = carve_smooth(dsm, B);
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);

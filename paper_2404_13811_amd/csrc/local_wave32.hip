@@ -19,7 +19,7 @@ namespace {
 
 using namespace wave;
 
-struct WaveSmemF {
+struct __align__(16) WaveSmemF {
   float row[2][NBW];
   float col[2][NBW];
   int flag;
@@ -39,7 +39,7 @@ struct BoxR {
 __host__ __device__ inline size_t boxr_bytes(int m0, int m1, int nrhs, int nbrhs) {
   const size_t nc = (size_t)m0 * m1;
   const size_t d = (size_t)(m0 + 2) * (m1 + 2) + 3 * nc + nrhs * nc + nc + nbrhs * nc;
-  const size_t f = nrhs * nc + 2 * nc + (size_t)(nrhs < 2 ? 2 : nrhs) * NBW;
+  const size_t f = nrhs * nc + 2 * nc + (size_t)(nrhs < 2 ? 2 : nrhs) * NBW + 4;
   return d * sizeof(double) + f * sizeof(float);
 }
 
@@ -60,7 +60,7 @@ __device__ __forceinline__ BoxR carve_r(double* base, const Box& B, int nrhs, in
   r.Wf = fb;
   r.Txf = r.Wf + (size_t)nrhs * nc;
   r.Tnf = r.Txf + nc;
-  r.Zf = r.Tnf + nc;
+  r.Zf = align16(base, r.Tnf + nc);
   return r;
 }
 
@@ -81,65 +81,95 @@ __device__ __forceinline__ void scale_box(const Box& B, BoxR& R) {
   bsync<NT>();
 }
 
-__device__ __forceinline__ float half_swap_f(float v) { return __shfl_xor(v, 32); }
 
-// Scaled S_j into w (column c, my half), w = W_{j-1} on entry when j > 0.
+// Scaled S_j into w (column c, my half), w = W_{j-1} on entry when j > 0
+// (branch-free, as wbuild).
 __device__ __forceinline__ void wbuild32(int nb, int j, const BoxR& R, float w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  const int cc = c < nb ? c : 0;
   const float* Tx = R.Txf + j * nb;
-  const float* Tp = R.Tnf + (j - 1) * nb;
-  const float tc = (j > 0 && c < nb) ? Tp[c] : 0.0f;
+  const float* Tp = R.Tnf + (j - 1) * nb;  // read only when j > 0
+  const float txc = Tx[cc];
+  const float tc = j > 0 ? Tp[cc] : 0.0f;
+  float tr[HB], tpr[HB];
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
     const int r = HB * h + i;
-    float v;
-    if (r >= nb || c >= nb) {
-      v = (r == c) ? 1.0f : 0.0f;
-    } else {
-      v = (r == c) ? 1.0f : (r == c - 1) ? -Tx[r] : (r == c + 1) ? -Tx[c] : 0.0f;
-      if (j > 0) v -= Tp[r] * tc * w[i];
-    }
-    w[i] = v;
+    const int rr = r < nb ? r : 0;
+    tr[i] = Tx[rr];
+    tpr[i] = j > 0 ? Tp[rr] : 0.0f;
+  }
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    const int d = r - c;
+    float v = d == 0 ? 1.0f : d == -1 ? -tr[i] : d == 1 ? -txc : 0.0f;
+    v = fmaf(-tpr[i] * tc, w[i], v);
+    w[i] = (r < nb && c < nb) ? v : (d == 0 ? 1.0f : 0.0f);
   }
 }
 
 __device__ __forceinline__ void wgj32(int nb, WaveSmemF& sm, float w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  for (int k0 = 0; k0 < NBW; k0 += HB) {
+    if (k0 >= nb) break;
+    const bool own_half = h == (k0 >> 4);
 #pragma unroll
-  for (int k = 0; k < NBW; ++k) {
-    if (k >= nb) break;
-    float* rk = sm.row[k & 1];
-    float* ck = sm.col[k & 1];
-    if (h == (k >> 4)) rk[c] = w[k & 15];
-    if (c == k) {
+    for (int kk = 0; kk < HB; ++kk) {
+      const int k = k0 + kk;
+      if (k >= nb) break;
+      float* rk = sm.row[kk & 1];
+      float* ck = sm.col[kk & 1];
+      if (own_half) rk[c] = w[kk];
+      if (c == k) {
+        float4* d = reinterpret_cast<float4*>(ck + HB * h);
 #pragma unroll
-      for (int i = 0; i < HB; ++i) ck[HB * h + i] = w[i];
+        for (int i = 0; i < HB / 4; ++i) d[i] = make_float4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+      }
+      wsync();
+      const float a = rk[c];
+      const float piv = rk[k];
+      if (!(piv > 0.0f) && L == 0) sm.flag |= kFlagNotPD;
+      const float ip = 1.0f / piv;
+      const float f = (c == k) ? 0.0f : -(a * ip);
+      const float4* cs = reinterpret_cast<const float4*>(ck + HB * h);
+#pragma unroll
+      for (int i = 0; i < HB / 4; ++i) {
+        const float4 v = cs[i];
+        w[4 * i] = fmaf(f, v.x, w[4 * i]);
+        w[4 * i + 1] = fmaf(f, v.y, w[4 * i + 1]);
+        w[4 * i + 2] = fmaf(f, v.z, w[4 * i + 2]);
+        w[4 * i + 3] = fmaf(f, v.w, w[4 * i + 3]);
+      }
+      if (c == k) {
+        const float m = -ip;
+#pragma unroll
+        for (int i = 0; i < HB; ++i) w[i] *= m;
+      }
+      if (own_half) w[kk] = (c == k) ? ip : a * ip;
     }
-    wsync();
-    const float a = rk[c];
-    const float piv = rk[k];
-    if (!(piv > 0.0f) && L == 0) sm.flag |= kFlagNotPD;
-    const float ip = 1.0f / piv;
-    const float f = -(a * ip);
-#pragma unroll
-    for (int i = 0; i < HB; ++i) {
-      const float v = ck[HB * h + i];
-      w[i] = (c == k) ? -v * ip : fmaf(f, v, w[i]);
-    }
-    if (h == (k >> 4)) w[k & 15] = (c == k) ? ip : a * ip;
   }
   wsync();
 }
 
-__device__ __forceinline__ float wgemv32(const float w[HB], const float* z) {
+// W_j z with 128-bit LDS reads, two FMA chains and the half-wave swap sum.
+__device__ __forceinline__ float wgemv2f(const float w[HB], const float* z) {
   const int h = lane_id() >> 5;
-  float acc = 0.0f;
+  const float4* z4 = reinterpret_cast<const float4*>(z + HB * h);
+  float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
-  for (int i = 0; i < HB; ++i) acc = fmaf(w[i], z[HB * h + i], acc);
-  return acc + half_swap_f(acc);
+  for (int i = 0; i < HB / 4; ++i) {
+    const float4 v = z4[i];
+    a0 = fmaf(w[4 * i], v.x, a0);
+    a1 = fmaf(w[4 * i + 1], v.y, a1);
+    a0 = fmaf(w[4 * i + 2], v.z, a0);
+    a1 = fmaf(w[4 * i + 3], v.w, a1);
+  }
+  return half_sum_f(a0 + a1);
 }
+
 
 
 __device__ __forceinline__ void fwd32(int nb, int nc, int j, int nrhs, const BoxR& R, const float w[HB]) {
@@ -157,7 +187,7 @@ __device__ __forceinline__ void fwd32(int nb, int nc, int j, int nrhs, const Box
   }
   wsync();
   for (int k = 0; k < nrhs; ++k) {
-    const float y = wgemv32(w, R.Zf + k * NBW);
+    const float y = wgemv2f(w, R.Zf + k * NBW);
     if (h == 0 && c < nb) R.Wf[k * nc + j * nb + c] = y;
   }
   wsync();
@@ -173,7 +203,7 @@ __device__ __forceinline__ void bwd32(int nb, int nc, int j, int nrhs, const Box
   }
   wsync();
   for (int k = 0; k < nrhs; ++k) {
-    const float y = wgemv32(w, R.Zf + k * NBW);
+    const float y = wgemv2f(w, R.Zf + k * NBW);
     if (h == 0 && c < nb) R.Wf[k * nc + j * nb + c] += y;
   }
   wsync();
@@ -240,21 +270,6 @@ __device__ __forceinline__ void solve32(const Box& B, const float* Wg, int nrhs,
 
 // Single right-hand side in R.Wf: forward and backward sweeps with the
 // previous block's values kept in registers (as the FP64 sweep).
-__device__ __forceinline__ float wgemv2f(const float w[HB], const float* z) {
-  const int h = lane_id() >> 5;
-  const float4* z4 = reinterpret_cast<const float4*>(z + HB * h);
-  float a0 = 0.0f, a1 = 0.0f;
-#pragma unroll
-  for (int i = 0; i < HB / 4; ++i) {
-    const float4 v = z4[i];
-    a0 = fmaf(w[4 * i], v.x, a0);
-    a1 = fmaf(w[4 * i + 1], v.y, a1);
-    a0 = fmaf(w[4 * i + 2], v.z, a0);
-    a1 = fmaf(w[4 * i + 3], v.w, a1);
-  }
-  return half_sum_f(a0 + a1);
-}
-
 __device__ __forceinline__ void sweep1f(const Box& B, const float* Wg, const BoxR& R) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
@@ -433,7 +448,7 @@ __global__ void __launch_bounds__(64) k_basis32(Geo g, const Box* __restrict__ b
                                                 double* __restrict__ tr_beta, double tol,
                                                 int max_refine, int* iters,
                                                 unsigned long long* resid, int* flags) {
-  extern __shared__ double dsm[];
+  extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmemF sm;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
@@ -506,7 +521,7 @@ __global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restric
                                                      double* __restrict__ pibar, double tol,
                                                      int max_refine, int* iters,
                                                      unsigned long long* resid, int* flags) {
-  extern __shared__ double dsm[];
+  extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmemF sm;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
@@ -551,7 +566,7 @@ __global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restric
 
 __host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1) {
   const size_t nc = (size_t)m0 * m1;
-  return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW);
+  return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW + 4);
 }
 
 constexpr int kSmooth32Threads = 256;
@@ -567,7 +582,7 @@ __global__ void __launch_bounds__(kSmooth32Threads) k_smooth32(Geo g, const Box*
                                                  int max_refine, int* iters,
                                                  unsigned long long* resid, int* flags) {
   constexpr int NT = kSmooth32Threads;
-  extern __shared__ double dsm[];
+  extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmemF sm;
   const Box B = boxes[members[blockIdx.x]];
   if (threadIdx.x == 0) sm.flag = 0;
@@ -581,7 +596,7 @@ __global__ void __launch_bounds__(kSmooth32Threads) k_smooth32(Geo g, const Box*
   R.Wf = fb;
   R.Txf = R.Wf + nc;
   R.Tnf = R.Txf + nc;
-  R.Zf = R.Tnf + nc;
+  R.Zf = align16(dsm, R.Tnf + nc);
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, nullptr);
   __syncthreads();
   smooth_rhs<NT>(g, B, r, beta, R.Bv);

@@ -12,7 +12,7 @@ constexpr int NBW = 32;
 constexpr int HB = 16;
 constexpr int RING = 4;
 
-struct WaveSmem {
+struct __align__(16) WaveSmem {
   double row[2][NBW];
   double col[2][NBW];
   int flag;
@@ -30,6 +30,17 @@ struct BoxLds {
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// p rounded up to a 16-byte boundary (for 128-bit LDS accesses), measured
+// from a 16-byte aligned base of the same array, so that the pointer keeps
+// its address space.
+template <typename T, typename B>
+__device__ __forceinline__ T* align16(B* base, T* p) {
+  constexpr int q = 16 / sizeof(T);
+  const char* b = reinterpret_cast<const char*>(base);
+  const long long off = (reinterpret_cast<const char*>(p) - b) / (long long)sizeof(T);
+  return reinterpret_cast<T*>(const_cast<char*>(b)) + ((off + q - 1) / q) * q;
+}
 
 // Single-wave synchronisation through LDS: wait for this wave's LDS
 // operations; the wave barrier keeps the compiler from moving memory
@@ -78,28 +89,36 @@ struct BlockSrc {
 template <typename T>
 __device__ __forceinline__ BlockSrc<T> block_src(const T* Wg, int nb, int nblk) {
   BlockSrc<T> b;
-  const int bytes = nblk * nb * nb * (int)sizeof(T);
-  b.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Wg), (short)0, bytes, 0x00020000);
+  // the base and size are wave-uniform: keep them in scalar registers so
+  // that the loads need no per-lane resource
+  const unsigned long long pa = reinterpret_cast<unsigned long long>(Wg);
+  const unsigned plo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)pa);
+  const unsigned phi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(pa >> 32));
+  T* pu = reinterpret_cast<T*>(((unsigned long long)phi << 32) | plo);
+  const int bytes = __builtin_amdgcn_readfirstlane(nblk * nb * nb * (int)sizeof(T));
+  b.rs = __builtin_amdgcn_make_buffer_rsrc(pu, (short)0, bytes, 0x00020000);
   const int c = threadIdx.x & 31, h = (threadIdx.x >> 5) & 1;
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
     const int r = HB * h + i;
     b.off[i] = (r < nb && c < nb) ? (r * nb + c) * (int)sizeof(T) : bytes;
   }
-  b.bbytes = nb * nb * (int)sizeof(T);
+  b.bbytes = __builtin_amdgcn_readfirstlane(nb * nb * (int)sizeof(T));
   return b;
 }
 
 __device__ __forceinline__ void wload_block(const BlockSrc<double>& b, int j, double w[HB]) {
 #pragma unroll
   for (int i = 0; i < HB; ++i)
-    w[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.rs, b.off[i], j * b.bbytes, 0));
+    w[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+        b.rs, b.off[i], __builtin_amdgcn_readfirstlane(j * b.bbytes), 0));
 }
 
 __device__ __forceinline__ void wload_block(const BlockSrc<float>& b, int j, float w[HB]) {
 #pragma unroll
   for (int i = 0; i < HB; ++i)
-    w[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rs, b.off[i], j * b.bbytes, 0));
+    w[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+        b.rs, b.off[i], __builtin_amdgcn_readfirstlane(j * b.bbytes), 0));
 }
 
 // dst[e] = *addr(e, fill) for e < n (or `fill` where addr returns nullptr),
@@ -146,7 +165,7 @@ __device__ __forceinline__ void robin_face(const Geo& g, int a, double kc, doubl
 
 __host__ __device__ inline size_t box_lds_doubles(int m0, int m1, int nrhs) {
   const int nc = m0 * m1;
-  return (size_t)(m0 + 2) * (m1 + 2) + 3 * (size_t)nc + (size_t)nrhs * nc + (size_t)nrhs * NBW;
+  return (size_t)(m0 + 2) * (m1 + 2) + 3 * (size_t)nc + (size_t)nrhs * nc + (size_t)nrhs * NBW + 2;
 }
 
 __device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs) {
@@ -159,7 +178,7 @@ __device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs) {
   s.Tx = s.Dg + nc;
   s.Tn = s.Tx + nc;
   s.X = s.Tn + nc;
-  s.Z = s.X + (size_t)nrhs * nc;
+  s.Z = align16(base, s.X + (size_t)nrhs * nc);
   return s;
 }
 
@@ -228,55 +247,81 @@ __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta
 }
 
 // S_j (column c, my half) into w; w holds W_{j-1} on entry when j > 0.
+// Branch-free: every LDS read is unconditional (the addresses stay inside
+// the box arrays) and selects pick the tridiagonal entries, so the reads of
+// a block issue back to back.
 __device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  const int cc = c < nb ? c : 0;
   const double* D = s.Dg + j * nb;
   const double* Tx = s.Tx + j * nb;
-  const double* Tp = s.Tn + (j - 1) * nb;
-  const double tc = (j > 0 && c < nb) ? Tp[c] : 0.0;
+  const double* Tp = s.Tn + (j - 1) * nb;  // read only when j > 0
+  const double dc = D[cc], txc = Tx[cc];
+  const double tc = j > 0 ? Tp[cc] : 0.0;
+  double tr[HB], tpr[HB];
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
     const int r = HB * h + i;
-    double v;
-    if (r >= nb || c >= nb) {
-      v = (r == c) ? 1.0 : 0.0;
-    } else {
-      v = (r == c) ? D[c] : (r == c - 1) ? -Tx[r] : (r == c + 1) ? -Tx[c] : 0.0;
-      if (j > 0) v -= Tp[r] * tc * w[i];
-    }
-    w[i] = v;
+    const int rr = r < nb ? r : 0;
+    tr[i] = Tx[rr];
+    tpr[i] = j > 0 ? Tp[rr] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    const int d = r - c;
+    double v = d == 0 ? dc : d == -1 ? -tr[i] : d == 1 ? -txc : 0.0;
+    v = fma(-tpr[i] * tc, w[i], v);
+    w[i] = (r < nb && c < nb) ? v : (d == 0 ? 1.0 : 0.0);
   }
 }
 
 // In-place Gauss-Jordan inversion of the block held in w.  Each step
 // publishes pivot row k (one element per lane of the owning half) and pivot
 // column k (the 16 registers of the two lanes holding column k) to LDS.
+// Every lane applies the rank-1 update; the two lanes of column k (which
+// hold the pivot column itself, left unchanged by a zero multiplier) then
+// scale it to -v / pivot, and the owning half rewrites row k.
 __device__ __forceinline__ void wgj(int nb, WaveSmem& sm, double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  // pivots in two halves of 16 so that the register index kk is static
+  for (int k0 = 0; k0 < NBW; k0 += HB) {
+    if (k0 >= nb) break;
+    const bool own_half = h == (k0 >> 4);
 #pragma unroll
-  for (int k = 0; k < NBW; ++k) {
-    if (k >= nb) break;
-    double* rk = sm.row[k & 1];
-    double* ck = sm.col[k & 1];
-    if (h == (k >> 4)) rk[c] = w[k & 15];
-    if (c == k) {
+    for (int kk = 0; kk < HB; ++kk) {
+      const int k = k0 + kk;
+      if (k >= nb) break;
+      double* rk = sm.row[kk & 1];
+      double* ck = sm.col[kk & 1];
+      if (own_half) rk[c] = w[kk];
+      if (c == k) {
+        double2* d = reinterpret_cast<double2*>(ck + HB * h);
 #pragma unroll
-      for (int i = 0; i < HB; ++i) ck[HB * h + i] = w[i];
+        for (int i = 0; i < HB / 2; ++i) d[i] = make_double2(w[2 * i], w[2 * i + 1]);
+      }
+      wsync();
+      const double a = rk[c];
+      const double piv = rk[k];
+      if (!(piv > 0.0) && L == 0) sm.flag |= kFlagNotPD;
+      const double ip = rcp_d(piv);
+      const double f = (c == k) ? 0.0 : -(a * ip);
+      const double2* cs = reinterpret_cast<const double2*>(ck + HB * h);
+#pragma unroll
+      for (int i = 0; i < HB / 2; ++i) {
+        const double2 v = cs[i];
+        w[2 * i] = fma(f, v.x, w[2 * i]);
+        w[2 * i + 1] = fma(f, v.y, w[2 * i + 1]);
+      }
+      if (c == k) {
+        const double m = -ip;
+#pragma unroll
+        for (int i = 0; i < HB; ++i) w[i] *= m;
+      }
+      if (own_half) w[kk] = (c == k) ? ip : a * ip;
     }
-    wsync();
-    const double a = rk[c];
-    const double piv = rk[k];
-    if (!(piv > 0.0) && L == 0) sm.flag |= kFlagNotPD;
-    const double ip = 1.0 / piv;
-    const double f = -(a * ip);
-#pragma unroll
-    for (int i = 0; i < HB; ++i) {
-      const double v = ck[HB * h + i];
-      w[i] = (c == k) ? -v * ip : fma(f, v, w[i]);
-    }
-    if (h == (k >> 4)) w[k & 15] = (c == k) ? ip : a * ip;
   }
   wsync();
 }
@@ -380,7 +425,7 @@ struct SmoothLds {
 
 __host__ __device__ inline size_t smooth_lds_doubles(int m0, int m1) {
   const size_t nc = (size_t)m0 * m1, nt = (size_t)(m0 + 2) * (m1 + 2);
-  return 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 2 * NBW;
+  return 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 2 * NBW + 2;
 }
 
 __device__ __forceinline__ int side_off(const BoxLds& s, int q) {
@@ -404,7 +449,7 @@ __device__ __forceinline__ SmoothLds carve_smooth(double* base, const Box& B) {
   s.Dg = r.BC + ns;
   s.Tx = s.Dg + nc;
   s.X = s.Tx + nc;
-  s.Z = s.X + nc;
+  s.Z = align16(base, s.X + nc);
   return r;
 }
 
