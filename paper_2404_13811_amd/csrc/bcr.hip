@@ -24,7 +24,9 @@ namespace {
 // ------------------------------------------------------------------ inverse
 // In-place Gauss-Jordan inversion of one bp x bp block per workgroup; each
 // thread holds an 8 x 8 tile in registers; the pivot row and column go
-// through LDS (double buffered: one barrier per pivot).  The generic update
+// through LDS (double buffered: one barrier per pivot), interleaved so that
+// the 16-byte pieces read by neighbouring threads are adjacent (no bank
+// conflicts).  The generic update
 // is a rank-1 FMA on every tile; the owners of the pivot row / column then
 // overwrite those entries (uniform per unrolled pivot, so no selects).
 constexpr int IT = 8;
@@ -40,12 +42,13 @@ __device__ __forceinline__ double recip(double x) {
 }
 
 template <int NT>
-__global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool, const int* __restrict__ blk,
-                                                int bp, int* flags) {
-  __shared__ double rowb[2][kBcrMaxBlock];
-  __shared__ double colb[2][kBcrMaxBlock];
+__global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool,
+                                                const long long* __restrict__ offs, int bp, int ld,
+                                                int* flags) {
+  __shared__ __align__(16) double rowb[2][kBcrInvMax];
+  __shared__ __align__(16) double colb[2][kBcrInvMax];
   __shared__ double ipb[2];
-  double* A = pool + (long long)blk[blockIdx.x] * bp * bp;
+  double* A = pool + offs[blockIdx.x];
   const int nt = bp / IT;  // tiles per dimension
   const int t = threadIdx.x;
   const bool act = t < nt * nt;
@@ -55,7 +58,7 @@ __global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool, const
   if (act) {
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-      const double2* src = reinterpret_cast<const double2*>(A + (long long)(r0 + i) * bp + c0);
+      const double2* src = reinterpret_cast<const double2*>(A + (long long)(r0 + i) * ld + c0);
 #pragma unroll
       for (int j = 0; j < IT / 2; ++j) {
         const double2 v = src[j];
@@ -72,9 +75,9 @@ __global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool, const
       double* rk = rowb[kk & 1];
       double* ck = colb[kk & 1];
       if (own_r) {
-        double2* d = reinterpret_cast<double2*>(rk + c0);
+        double2* d = reinterpret_cast<double2*>(rk);
 #pragma unroll
-        for (int j = 0; j < IT / 2; ++j) d[j] = make_double2(w[kk][2 * j], w[kk][2 * j + 1]);
+        for (int j = 0; j < IT / 2; ++j) d[j * nt + tc] = make_double2(w[kk][2 * j], w[kk][2 * j + 1]);
         if (own_c) {
           const double piv = w[kk][kk];
           bad |= !(piv != 0.0);
@@ -82,19 +85,19 @@ __global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool, const
         }
       }
       if (own_c) {
-        double2* d = reinterpret_cast<double2*>(ck + r0);
+        double2* d = reinterpret_cast<double2*>(ck);
 #pragma unroll
-        for (int i = 0; i < IT / 2; ++i) d[i] = make_double2(w[2 * i][kk], w[2 * i + 1][kk]);
+        for (int i = 0; i < IT / 2; ++i) d[i * nt + tr] = make_double2(w[2 * i][kk], w[2 * i + 1][kk]);
       }
       __syncthreads();
       if (!act) continue;
       const double ip = ipb[kk & 1];
       double rv[IT], cv[IT];
-      const double2* rs = reinterpret_cast<const double2*>(rk + c0);
-      const double2* cs = reinterpret_cast<const double2*>(ck + r0);
+      const double2* rs = reinterpret_cast<const double2*>(rk);
+      const double2* cs = reinterpret_cast<const double2*>(ck);
 #pragma unroll
       for (int j = 0; j < IT / 2; ++j) {
-        const double2 a = rs[j], b = cs[j];
+        const double2 a = rs[j * nt + tc], b = cs[j * nt + tr];
         rv[2 * j] = a.x;
         rv[2 * j + 1] = a.y;
         cv[2 * j] = -b.x * ip;
@@ -118,7 +121,7 @@ __global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool, const
   if (act) {
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-      double2* dst = reinterpret_cast<double2*>(A + (long long)(r0 + i) * bp + c0);
+      double2* dst = reinterpret_cast<double2*>(A + (long long)(r0 + i) * ld + c0);
 #pragma unroll
       for (int j = 0; j < IT / 2; ++j) dst[j] = make_double2(w[i][2 * j], w[i][2 * j + 1]);
     }
@@ -127,34 +130,36 @@ __global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool, const
 }
 
 // ------------------------------------------------------------------ products
-// C = [C0] + al1 A1 B1 + al2 A2 B2 for a batch of tasks.  One workgroup of
-// 256 threads per 32 x 32 output tile; the whole 32 x bp strip of A
-// (transposed, k-major) and bp x 32 strip of B are staged in LDS with all
-// global loads of a chunk in flight before the stores; each thread computes
-// a 2 x 2 set of outputs.
+// C = [C0] + al1 A1 B1 + al2 A2 B2 for a batch of tasks; the operands are
+// n x n matrices at element offsets in the pool with leading dimension ld
+// (whole blocks, or quarters of a block in the two-by-two inverse).  One
+// workgroup of 256 threads per 32 x 32 output tile; the whole 32 x n strip
+// of A (transposed, k-major) and n x 32 strip of B are staged in LDS with
+// all global loads of a chunk in flight before the stores; each thread
+// computes a 2 x 2 set of outputs.
 constexpr int GT = 32, GCH = 16;
 
 __device__ __forceinline__ void stage_strips(const double* __restrict__ A, const double* __restrict__ B,
-                                             double al, int bp, int tr0, int tc0, double* As,
+                                             double al, int n, int ld, int tr0, int tc0, double* As,
                                              double* Bs) {
   // As[k * GT + r] = al * A[tr0 + r][k];  Bs[k * GT + c] = B[k][tc0 + c]
-  const int n = GT * bp;  // elements per strip
-  for (int e0 = 0; e0 < n; e0 += 256 * GCH) {
+  const int cnt = GT * n;  // elements per strip
+  for (int e0 = 0; e0 < cnt; e0 += 256 * GCH) {
     double va[GCH], vb[GCH];
 #pragma unroll
     for (int u = 0; u < GCH; ++u) {
       const int e = e0 + u * 256 + threadIdx.x;
-      const bool ok = e < n;
-      const int ra = e / bp, ka = e - (e / bp) * bp;  // A row-major: consecutive k
-      const int kb = e >> 5, cb = e & 31;             // B: 32 consecutive columns
-      va[u] = ok ? A[(long long)(tr0 + ra) * bp + ka] : 0.0;
-      vb[u] = ok ? B[(long long)kb * bp + tc0 + cb] : 0.0;
+      const bool ok = e < cnt;
+      const int ra = e / n, ka = e - (e / n) * n;  // A row-major: consecutive k
+      const int kb = e >> 5, cb = e & 31;          // B: 32 consecutive columns
+      va[u] = ok ? A[(long long)(tr0 + ra) * ld + ka] : 0.0;
+      vb[u] = ok ? B[(long long)kb * ld + tc0 + cb] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < GCH; ++u) {
       const int e = e0 + u * 256 + threadIdx.x;
-      if (e < n) {
-        const int ra = e / bp, ka = e - (e / bp) * bp;
+      if (e < cnt) {
+        const int ra = e / n, ka = e - (e / n) * n;
         As[ka * GT + ra] = al * va[u];
         Bs[e] = vb[u];
       }
@@ -163,26 +168,25 @@ __device__ __forceinline__ void stage_strips(const double* __restrict__ A, const
 }
 
 __global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
-                                                  const BcrGemm* __restrict__ tasks, int bp) {
+                                                  const BcrGemm* __restrict__ tasks, int n, int ld) {
   extern __shared__ double smem[];
-  double* As = smem;            // bp x GT
-  double* Bs = smem + bp * GT;  // bp x GT
-  const int ntile = bp / GT;
+  double* As = smem;           // n x GT
+  double* Bs = smem + n * GT;  // n x GT
+  const int ntile = n / GT;
   const int task = blockIdx.x / (ntile * ntile);
   const int tile = blockIdx.x - task * ntile * ntile;
   const BcrGemm T = tasks[task];
-  const long long bs = (long long)bp * bp;
   const int tr0 = (tile / ntile) * GT, tc0 = (tile % ntile) * GT;
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
   for (int term = 0; term < 2; ++term) {
-    const int ai = term ? T.a2 : T.a1, bi = term ? T.b2 : T.b1;
+    const long long ai = term ? T.a2 : T.a1, bi = term ? T.b2 : T.b1;
     if (ai < 0) continue;
     if (term) __syncthreads();
-    stage_strips(pool + ai * bs, pool + bi * bs, term ? T.al2 : T.al1, bp, tr0, tc0, As, Bs);
+    stage_strips(pool + ai, pool + bi, term ? T.al2 : T.al1, n, ld, tr0, tc0, As, Bs);
     __syncthreads();
 #pragma unroll 8
-    for (int k = 0; k < bp; ++k) {
+    for (int k = 0; k < n; ++k) {
       const double a0 = As[k * GT + ty], a1 = As[k * GT + ty + 16];
       const double b0 = Bs[k * GT + tx], b1 = Bs[k * GT + tx + 16];
       acc00 = fma(a0, b0, acc00);
@@ -191,19 +195,20 @@ __global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
       acc11 = fma(a1, b1, acc11);
     }
   }
-  double* C = pool + T.c * bs;
-  const double* C0 = T.c0 >= 0 ? pool + T.c0 * bs : nullptr;
-  const int r_0 = tr0 + ty, r_1 = r_0 + 16, c_0 = tc0 + tx, c_1 = c_0 + 16;
+  double* C = pool + T.c;
+  const double* C0 = T.c0 >= 0 ? pool + T.c0 : nullptr;
+  const long long r_0 = tr0 + ty, r_1 = r_0 + 16;
+  const int c_0 = tc0 + tx, c_1 = c_0 + 16;
   if (C0) {
-    acc00 += C0[r_0 * bp + c_0];
-    acc01 += C0[r_0 * bp + c_1];
-    acc10 += C0[r_1 * bp + c_0];
-    acc11 += C0[r_1 * bp + c_1];
+    acc00 += C0[r_0 * ld + c_0];
+    acc01 += C0[r_0 * ld + c_1];
+    acc10 += C0[r_1 * ld + c_0];
+    acc11 += C0[r_1 * ld + c_1];
   }
-  C[r_0 * bp + c_0] = acc00;
-  C[r_0 * bp + c_1] = acc01;
-  C[r_1 * bp + c_0] = acc10;
-  C[r_1 * bp + c_1] = acc11;
+  C[r_0 * ld + c_0] = acc00;
+  C[r_0 * ld + c_1] = acc01;
+  C[r_1 * ld + c_0] = acc10;
+  C[r_1 * ld + c_1] = acc11;
 }
 
 // y = [y0] + al1 A1 x1 + al2 A2 x2.  Workgroup (task, group of 16 rows);
@@ -280,28 +285,25 @@ __global__ void k_bcr_gather(const double* __restrict__ xv, const int* __restric
 
 }  // namespace
 
-hipError_t launch_bcr_inv(double* pool, const int* blk, int nblk, int bp, int* flags, hipStream_t s) {
+hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
+                          hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
-  if (bp % IT || bp > kBcrMaxBlock) return hipErrorInvalidValue;
-  const int nt = (bp / IT) * (bp / IT);
-  if (nt <= 256)
-    hipLaunchKernelGGL(k_bcr_inv<256>, dim3(nblk), dim3(256), 0, s, pool, blk, bp, flags);
-  else
-    hipLaunchKernelGGL(k_bcr_inv<1024>, dim3(nblk), dim3(1024), 0, s, pool, blk, bp, flags);
+  if (n % IT || n > kBcrInvMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bcr_inv<256>, dim3(nblk), dim3(256), 0, s, pool, offs, n, ld, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int bp, hipStream_t s) {
+hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n, int ld, hipStream_t s) {
   if (ntask <= 0) return hipSuccess;
-  if (bp % GT || bp > kBcrMaxBlock) return hipErrorInvalidValue;
-  const int ntile = bp / GT;
-  const size_t lds = 2 * sizeof(double) * (size_t)bp * GT;
+  if (n % GT || n > kBcrMaxBlock) return hipErrorInvalidValue;
+  const int ntile = n / GT;
+  const size_t lds = 2 * sizeof(double) * (size_t)n * GT;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_bcr_gemm,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_bcr_gemm, dim3(ntask * ntile * ntile), dim3(256), lds, s, pool, tasks, bp);
+  hipLaunchKernelGGL(k_bcr_gemm, dim3(ntask * ntile * ntile), dim3(256), lds, s, pool, tasks, n, ld);
   return hipGetLastError();
 }
 

@@ -88,12 +88,14 @@ struct mrcm_ctx {
   struct BcrOp {
     int kind;  // 0 inverses, 1 block products, 2 block-vector products
     int off, cnt;
+    int n, ld;  // operand size and leading dimension (kinds 0 and 1)
   };
   bool use_bcr = false;
   int bcr_M = 0, bcr_bp = 0;
   std::vector<BcrOp> bcr_ops;
   int *d_row_lvl = nullptr, *d_row_loc = nullptr, *d_col_lvl = nullptr, *d_col_loc = nullptr;
-  int *d_lsize = nullptr, *d_binv = nullptr;
+  int* d_lsize = nullptr;
+  long long* d_binv = nullptr;
   BcrGemm* d_bgemm = nullptr;
   BcrGemv* d_bgemv = nullptr;
   double *bpool = nullptr, *bvec = nullptr;
@@ -211,7 +213,8 @@ void family(const mrcm_ctx* c, int q, const int lo[3], const int hi[3], const in
 // layer block is not square or exceeds kBcrMaxBlock.
 bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
               std::vector<int>& col_lvl, std::vector<int>& col_loc, std::vector<int>& lsize,
-              std::vector<int>& inv, std::vector<BcrGemm>& gemm, std::vector<BcrGemv>& gemv) {
+              std::vector<long long>& inv, std::vector<BcrGemm>& gemm,
+              std::vector<BcrGemv>& gemv) {
   const Geo& g = c->geo;
   const int d = c->d, nsub = g.nsub, n = c->nX;
   const int M = g.M[d - 1];
@@ -251,7 +254,9 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
   }
   for (int r = 0; r < n; ++r)
     if (row_lvl[r] < 0) return false;
-  bp = (bp + 31) / 32 * 32;  // tile of the block products
+  // tile of the block products; above kBcrInvMax the inverse works on
+  // halves, which must be tiles too
+  bp = bp <= kBcrInvMax ? (bp + 31) / 32 * 32 : (bp + 63) / 64 * 64;
   if (bp == 0 || bp > kBcrMaxBlock) return false;
   lsize = rows;
   c->bcr_M = M;
@@ -272,8 +277,61 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
   auto rv = [&](int k) { return k; };
   auto gv = [&](int k) { return M + k; };
   auto xv = [&](int k) { return 2 * M + k; };
-  auto op = [&](int kind, int off, int cnt) {
-    if (cnt > 0) c->bcr_ops.push_back(mrcm_ctx::BcrOp{kind, off, cnt});
+  const long long bs = (long long)bp * bp;
+  auto op = [&](int kind, int off, int cnt, int nn = 0, int ld = 0) {
+    if (cnt > 0) c->bcr_ops.push_back(mrcm_ctx::BcrOp{kind, off, cnt, nn, ld});
+  };
+  // a product task on whole blocks (slots < 0 drop a term)
+  auto GM = [&](int cs, int c0, int a1, int b1, int a2, int b2, double al1, double al2) {
+    auto o = [&](int slot) { return slot < 0 ? -1LL : slot * bs; };
+    return BcrGemm{o(cs), o(c0), o(a1), o(b1), o(a2), o(b2), al1, al2};
+  };
+  // In-place inverses of the blocks in slots `blk`.  Up to kBcrInvMax one
+  // Gauss-Jordan workgroup per block; above, the two-by-two form
+  //   [A B; C D]^-1 = [A' - B' T2, B'; C', S^-1],  A' = A^-1, T1 = A' B,
+  //   T2 = C A', S = D - C T1, B' = -T1 S^-1, C' = -S^-1 T2,
+  // with T1 and T2 in the scratch slots s1 and s2 (quarters, ld = bp).
+  auto inverses = [&](const std::vector<int>& blk, const std::vector<int>& s1,
+                      const std::vector<int>& s2) {
+    const int nb = (int)blk.size();
+    if (nb == 0) return;
+    if (bp <= kBcrInvMax) {
+      const int o = (int)inv.size();
+      for (int b : blk) inv.push_back(b * bs);
+      op(0, o, nb, bp, bp);
+      return;
+    }
+    const int hh = bp / 2;
+    auto A = [&](int i) { return blk[i] * bs; };
+    auto B = [&](int i) { return blk[i] * bs + hh; };
+    auto C = [&](int i) { return blk[i] * bs + (long long)hh * bp; };
+    auto D = [&](int i) { return blk[i] * bs + (long long)hh * bp + hh; };
+    auto T1 = [&](int i) { return s1[i] * bs; };
+    auto T2 = [&](int i) { return s2[i] * bs; };
+    int o = (int)inv.size();
+    for (int i = 0; i < nb; ++i) inv.push_back(A(i));
+    op(0, o, nb, hh, bp);
+    o = (int)gemm.size();
+    for (int i = 0; i < nb; ++i) {
+      gemm.push_back(BcrGemm{T1(i), -1, A(i), B(i), -1, -1, 1.0, 0.0});
+      gemm.push_back(BcrGemm{T2(i), -1, C(i), A(i), -1, -1, 1.0, 0.0});
+    }
+    op(1, o, 2 * nb, hh, bp);
+    o = (int)gemm.size();
+    for (int i = 0; i < nb; ++i) gemm.push_back(BcrGemm{D(i), D(i), C(i), T1(i), -1, -1, -1.0, 0.0});
+    op(1, o, nb, hh, bp);
+    o = (int)inv.size();
+    for (int i = 0; i < nb; ++i) inv.push_back(D(i));
+    op(0, o, nb, hh, bp);
+    o = (int)gemm.size();
+    for (int i = 0; i < nb; ++i) {
+      gemm.push_back(BcrGemm{B(i), -1, T1(i), D(i), -1, -1, -1.0, 0.0});
+      gemm.push_back(BcrGemm{C(i), -1, D(i), T2(i), -1, -1, -1.0, 0.0});
+    }
+    op(1, o, 2 * nb, hh, bp);
+    o = (int)gemm.size();
+    for (int i = 0; i < nb; ++i) gemm.push_back(BcrGemm{A(i), A(i), B(i), T2(i), -1, -1, -1.0, 0.0});
+    op(1, o, nb, hh, bp);
   };
   std::vector<std::vector<BcrGemv>> back;
   std::vector<int> idx(M);
@@ -282,16 +340,23 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
   while (idx.size() > 1) {
     const int L = (int)idx.size();
     // eliminated layers (odd positions): E_k = D_k^{-1}, F_k, G_k, g_k
-    int o = (int)inv.size();
-    for (int t = 1; t < L; t += 2) inv.push_back(dsl[idx[t]]);
-    op(0, o, (int)inv.size() - o);
-    o = (int)gemm.size();
+    // (the F and G slots of k are free until then: scratch of the inverse)
+    {
+      std::vector<int> blk, s1, s2;
+      for (int t = 1; t < L; t += 2) {
+        blk.push_back(dsl[idx[t]]);
+        s1.push_back(F(idx[t]));
+        s2.push_back(G(idx[t]));
+      }
+      inverses(blk, s1, s2);
+    }
+    int o = (int)gemm.size();
     for (int t = 1; t < L; t += 2) {
       const int k = idx[t];
-      gemm.push_back(BcrGemm{F(k), -1, dsl[k], lsl[k], -1, -1, 1.0, 0.0});
-      if (t + 1 < L) gemm.push_back(BcrGemm{G(k), -1, dsl[k], usl[k], -1, -1, 1.0, 0.0});
+      gemm.push_back(GM(F(k), -1, dsl[k], lsl[k], -1, -1, 1.0, 0.0));
+      if (t + 1 < L) gemm.push_back(GM(G(k), -1, dsl[k], usl[k], -1, -1, 1.0, 0.0));
     }
-    op(1, o, (int)gemm.size() - o);
+    op(1, o, (int)gemm.size() - o, bp, bp);
     o = (int)gemv.size();
     for (int t = 1; t < L; t += 2) {
       const int k = idx[t];
@@ -306,32 +371,32 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
       const int j = idx[t];
       const bool hl = t > 0, hr = t + 1 < L;
       const int km = hl ? idx[t - 1] : -1, kp = hr ? idx[t + 1] : -1;
-      BcrGemm Dt{dsl[j], dsl[j], -1, -1, -1, -1, -1.0, -1.0};
+      BcrGemm Dt = GM(dsl[j], dsl[j], -1, -1, -1, -1, -1.0, -1.0);
       BcrGemv Rt{rv(j), rv(j), -1, -1, -1, -1, -1.0, -1.0};
       if (hl) {
-        Dt.a1 = lsl[j];
-        Dt.b1 = G(km);
+        Dt.a1 = lsl[j] * bs;
+        Dt.b1 = G(km) * bs;
         Rt.a1 = lsl[j];
         Rt.x1 = gv(km);
       }
       if (hr) {
-        (hl ? Dt.a2 : Dt.a1) = usl[j];
-        (hl ? Dt.b2 : Dt.b1) = F(kp);
+        (hl ? Dt.a2 : Dt.a1) = usl[j] * bs;
+        (hl ? Dt.b2 : Dt.b1) = F(kp) * bs;
         (hl ? Rt.a2 : Rt.a1) = usl[j];
         (hl ? Rt.x2 : Rt.x1) = gv(kp);
       }
       gemm.push_back(Dt);
       gemv.push_back(Rt);
       if (hl && t - 1 > 0) {
-        gemm.push_back(BcrGemm{lsl[km], -1, lsl[j], F(km), -1, -1, -1.0, 0.0});
+        gemm.push_back(GM(lsl[km], -1, lsl[j], F(km), -1, -1, -1.0, 0.0));
         nl[j] = lsl[km];
       }
       if (hr && t + 2 < L) {
-        gemm.push_back(BcrGemm{usl[kp], -1, usl[j], G(kp), -1, -1, -1.0, 0.0});
+        gemm.push_back(GM(usl[kp], -1, usl[j], G(kp), -1, -1, -1.0, 0.0));
         nu[j] = usl[kp];
       }
     }
-    op(1, o, (int)gemm.size() - o);
+    op(1, o, (int)gemm.size() - o, bp, bp);
     op(2, ov, (int)gemv.size() - ov);
     // back substitution of this level, replayed in reverse order
     std::vector<BcrGemv> bk;
@@ -355,10 +420,8 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
     idx.swap(keep);
   }
   const int k0 = idx[0];
-  int o = (int)inv.size();
-  inv.push_back(dsl[k0]);
-  op(0, o, 1);
-  o = (int)gemv.size();
+  inverses({dsl[k0]}, {F(k0)}, {G(k0)});
+  int o = (int)gemv.size();
   gemv.push_back(BcrGemv{xv(k0), -1, dsl[k0], rv(k0), -1, -1, 1.0, 0.0});
   op(2, o, 1);
   for (int lv = (int)back.size() - 1; lv >= 0; --lv) {
@@ -590,7 +653,8 @@ mrcm_status make_plan(mrcm_ctx* c) {
   // interface solver
   c->use_bcr = false;
   if (c->nX > 0 && c->iface_solver != MRCM_IFACE_BAND_LU) {
-    std::vector<int> rl, ro, cl, co, ls, inv;
+    std::vector<int> rl, ro, cl, co, ls;
+    std::vector<long long> inv;
     std::vector<BcrGemm> gm;
     std::vector<BcrGemv> gv;
     const bool ok = bcr_plan(c, rl, ro, cl, co, ls, inv, gm, gv);
@@ -619,7 +683,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
       HIPCHK(c, up(c->d_col_lvl, cl.data(), cl.size() * sizeof(int)));
       HIPCHK(c, up(c->d_col_loc, co.data(), co.size() * sizeof(int)));
       HIPCHK(c, up(c->d_lsize, ls.data(), ls.size() * sizeof(int)));
-      HIPCHK(c, up(c->d_binv, inv.data(), inv.size() * sizeof(int)));
+      HIPCHK(c, up(c->d_binv, inv.data(), inv.size() * sizeof(long long)));
       HIPCHK(c, up(c->d_bgemm, gm.data(), gm.size() * sizeof(BcrGemm)));
       HIPCHK(c, up(c->d_bgemv, gv.data(), gv.size() * sizeof(BcrGemv)));
       c->use_bcr = true;
@@ -639,9 +703,9 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
                                c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, c->d_lsize, s));
   for (const auto& o : c->bcr_ops) {
     if (o.kind == 0)
-      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, bp, c->flags, s));
+      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, o.n, o.ld, c->flags, s));
     else if (o.kind == 1)
-      HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, bp, s));
+      HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, o.n, o.ld, s));
     else
       HIPCHK(c, launch_bcr_gemv(c->bpool, c->bvec, c->d_bgemv + o.off, o.cnt, bp, s));
   }

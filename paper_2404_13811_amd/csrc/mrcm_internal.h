@@ -62,10 +62,11 @@ struct Iface {
   int basis0;   // index of its first test function in the basis array
 };
 
-// One batched block product of the cyclic reduction: block c of the pool :=
-// [block c0] + al1 * a1 * b1 [+ al2 * a2 * b2]  (an index < 0 drops a term).
+// One batched product of the cyclic reduction: the matrix at pool offset c
+// := [matrix at c0] + al1 * a1 * b1 [+ al2 * a2 * b2]  (element offsets of
+// n x n operands with the launch's leading dimension; < 0 drops a term).
 struct BcrGemm {
-  int c, c0, a1, b1, a2, b2;
+  long long c, c0, a1, b1, a2, b2;
   double al1, al2;
 };
 // Vector form: vector y := [vector y0] + al1 * block a1 * vector x1 [+ ...].
@@ -153,13 +154,15 @@ hipError_t launch_combine(const Geo& g, const int* seed_off, const double* X, co
                           double* p, double* gflux, hipStream_t s);
 
 // block cyclic reduction of the interface system (bcr.hip)
-constexpr int kBcrMaxBlock = 256;
+constexpr int kBcrMaxBlock = 256;  // layer block (two-by-two inverse above kBcrInvMax)
+constexpr int kBcrInvMax = 128;    // largest block one Gauss-Jordan workgroup inverts
 hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl, int ku,
                               const int* row_lvl, const int* row_loc, const int* col_lvl,
                               const int* col_loc, int M, int bp, double* pool, double* vec,
                               const int* lsize, hipStream_t s);
-hipError_t launch_bcr_inv(double* pool, const int* blk, int nblk, int bp, int* flags, hipStream_t s);
-hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int bp, hipStream_t s);
+hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
+                          hipStream_t s);
+hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n, int ld, hipStream_t s);
 hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks, int ntask, int bp,
                            hipStream_t s);
 hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* col_loc, int n, int bp,

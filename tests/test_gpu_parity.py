@@ -95,6 +95,15 @@ def test_interface_solvers(case, solver):
     assert np.linalg.norm(X - rX) <= 1e-9 * np.linalg.norm(rX)
 
 
+# Layer blocks above 128 unknowns (32 subdomains of 8 x 8 per layer, linear
+# spaces: 248 unknowns) use the two-by-two block inverse.
+@pytest.mark.parametrize("overlap", [0, 2])
+def test_bcr_large_layer_blocks(overlap):
+    wl = make_workload("c2", overlap=overlap).with_(sub=(8, 8))
+    _, _, X, rX = _check(wl, nsmooth=2, solver="bcr")
+    assert np.linalg.norm(X - rX) <= 1e-9 * np.linalg.norm(rX)
+
+
 def test_three_dimensional_small():
     _check(make_workload("c4", scale=8), nsmooth=1)
 
