@@ -104,6 +104,9 @@ typedef struct {
   int interface_solver;    /* MRCM_IFACE_BAND_LU or MRCM_IFACE_BCR in use      */
   int n_smooth_launches;   /* colour-phase launches of the last mrcm_smooth    */
   double ms_basis_kernel;  /* device time of the seed-solve kernel alone       */
+  int smooth_threads;      /* threads per box of the smoothing kernels         */
+  int smooth_graph;        /* 1: sweeps replay a captured graph                */
+  double ms_autotune;      /* device time of the last smoothing autotune       */
 } mrcm_stats;
 
 /* Create a context for a dim-dimensional grid (dim = 2 or 3) of
@@ -159,6 +162,16 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* ctx);
 /* Steps 6-7: nsteps >= 0 further smoothing steps on the current solution
  * (re-entrant: smooth(a); smooth(b) equals smooth(a + b)). */
 mrcm_status mrcm_smooth(mrcm_ctx* ctx, int nsteps);
+
+/* Execution of the smoothing sweeps (Steps 6-7).  use_graph != 0 (default):
+ * one sweep (the 2^dim colour phases) is captured into a HIP graph at the
+ * first mrcm_smooth after a configuration change and replayed per step on
+ * the context's stream.  threads_per_box: 64, 128 or 256 threads per
+ * oversampled box, or 0 (default) to time the three on one sweep over a copy
+ * of the current state and keep the fastest (done once per configuration,
+ * outside the timed region of mrcm_smooth).  The choice does not change the
+ * results.  Errors: MRCM_EINVAL. */
+mrcm_status mrcm_set_smoothing(mrcm_ctx* ctx, int use_graph, int threads_per_box);
 
 /* Pressure per cell (N values); shifted to zero mean when no side carries a
  * pressure condition. */

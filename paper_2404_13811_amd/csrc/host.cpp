@@ -100,8 +100,19 @@ struct mrcm_ctx {
   BcrGemv* d_bgemv = nullptr;
   double *bpool = nullptr, *bvec = nullptr;
 
-  hipEvent_t ev[10] = {nullptr, nullptr, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, nullptr};
+  // smoothing execution: threads per box (0 = autotune on first use), the
+  // chosen value, and the captured sweep graph
+  int smooth_nt_req = 0, smooth_nt = 0;
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double* p_tune = nullptr;
+  double* gflux_tune = nullptr;
+  double ms_autotune = 0.0;
+
+  hipEvent_t ev[12] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed_basis = false, timed_iface = false, timed_smooth = false;
   int n_local_solves = 0;
   int n_smooth_launches = 0;
@@ -133,6 +144,8 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+void drop_graph(mrcm_ctx* c);
+
 void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
   dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members);
@@ -144,6 +157,9 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->d_row_lvl); dfree(c->d_row_loc); dfree(c->d_col_lvl); dfree(c->d_col_loc);
   dfree(c->d_lsize); dfree(c->d_binv); dfree(c->d_bgemm); dfree(c->d_bgemv);
   dfree(c->bpool); dfree(c->bvec);
+  dfree(c->p_tune); dfree(c->gflux_tune);
+  drop_graph(c);
+  c->smooth_nt = 0;
   c->use_bcr = false;
   c->bcr_ops.clear();
   c->plan_valid = false;
@@ -724,9 +740,20 @@ mrcm_status check_flags(mrcm_ctx* c) {
   return MRCM_OK;
 }
 
+void drop_graph(mrcm_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
 void invalidate(mrcm_ctx* c, bool geometry) {
   c->state = 0;
-  if (geometry) c->plan_valid = false;
+  drop_graph(c);
+  if (geometry) {
+    c->plan_valid = false;
+    c->smooth_nt = 0;
+  }
 }
 
 }  // namespace
@@ -765,7 +792,7 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (e == hipSuccess) e = hipMalloc((void**)&c->f, N * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
-  for (int k = 0; k < 10 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   if (e == hipSuccess) e = launch_fill(c->bcv, 0.0, off, c->stream);
   if (e == hipSuccess) e = launch_fill(c->f, 0.0, N, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -961,34 +988,133 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   return MRCM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One smoothing sweep: the 2^d colour phases, in increasing colour order.
+mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux) {
+  for (int col = 0; col < (1 << c->d); ++col) {
+    const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
+    if (c->prec == MRCM_FP32_REFINE) {
+      HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+                                  c->beta_sm, c->fac32, p, gflux, c->tol, c->max_refine,
+                                  c->d_iters, c->d_resid, c->flags, c->lds32_smooth, nt, s));
+    } else if (c->wave) {
+      HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+                                c->beta_sm, c->fac, c->tco, c->scr, p, gflux, c->lds_smooth, nt,
+                                s));
+    } else {
+      HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+                              c->beta_sm, c->fac, nullptr, nullptr, c->scr, p, gflux, c->prec,
+                              c->tol, c->max_refine, nullptr, nullptr, c->flags, s));
+    }
+  }
+  return MRCM_OK;
+}
+
+// Threads per box of the smoothing kernels: the requested value, or the
+// fastest of 64, 128 and 256 over timed sweeps on copies of the current
+// state (the variants give identical results).
+mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
+  if (c->smooth_nt) return MRCM_OK;
+  if (c->smooth_nt_req || !(c->wave || c->prec == MRCM_FP32_REFINE)) {
+    c->smooth_nt = c->smooth_nt_req ? c->smooth_nt_req : 256;
+    return MRCM_OK;
+  }
+  const size_t np = (size_t)c->geo.ncells, ng = (size_t)c->geo.nsub * c->geo.gstride;
+  if (!c->p_tune) HIPCHK(c, hipMalloc((void**)&c->p_tune, np * sizeof(double)));
+  if (!c->gflux_tune) HIPCHK(c, hipMalloc((void**)&c->gflux_tune, std::max<size_t>(ng, 1) * sizeof(double)));
+  HIPCHK(c, hipMemcpyAsync(c->p_tune, c->p, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->gflux_tune, c->gflux, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipEventRecord(c->ev[10], s));
+  float best = 0.f;
+  int best_nt = 256;
+  for (int nt : {64, 128, 256}) {
+    mrcm_status st = sweep(c, s, nt, c->p_tune, c->gflux_tune);  // warm-up
+    if (st) return st;
+    HIPCHK(c, hipEventRecord(c->ev[4], s));
+    for (int r = 0; r < 3; ++r) {
+      st = sweep(c, s, nt, c->p_tune, c->gflux_tune);
+      if (st) return st;
+    }
+    HIPCHK(c, hipEventRecord(c->ev[5], s));
+    HIPCHK(c, hipEventSynchronize(c->ev[5]));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+    if (nt == 64 || ms < best) {
+      best = ms;
+      best_nt = nt;
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->ev[11], s));
+  HIPCHK(c, hipEventSynchronize(c->ev[11]));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev[10], c->ev[11]));
+  c->ms_autotune = ms;
+  c->smooth_nt = best_nt;
+  return MRCM_OK;
+}
+
+// Capture one sweep into a graph (on a private stream), replayed by
+// mrcm_smooth on the context's stream.
+mrcm_status capture_sweep(mrcm_ctx* c) {
+  if (c->graph_exec) return MRCM_OK;
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  mrcm_status st = sweep(c, c->cap_stream, c->smooth_nt, c->p, c->gflux);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+  if (st) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return st;
+  }
+  HIPCHK(c, e);
+  c->graph = gr;
+  HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  return MRCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrcm_status mrcm_set_smoothing(mrcm_ctx* c, int use_graph, int threads_per_box) {
+  if (!c) return MRCM_EINVAL;
+  if (threads_per_box != 0 && threads_per_box != 64 && threads_per_box != 128 &&
+      threads_per_box != 256)
+    return fail(c, MRCM_EINVAL, "threads per box must be 0 (autotune), 64, 128 or 256");
+  c->use_graph = use_graph != 0;
+  c->smooth_nt_req = threads_per_box;
+  c->smooth_nt = 0;
+  drop_graph(c);
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   if (!c) return MRCM_EINVAL;
   if (c->state < 2) return fail(c, MRCM_ESTATE, "interface not solved");
   if (nsteps < 0) return fail(c, MRCM_EINVAL, "nsteps < 0");
-  hipStream_t s = c->stream;
-  HIPCHK(c, hipEventRecord(c->ev[4], s));
-  c->n_smooth_launches = nsteps << c->d;
   if (nsteps > 0 && c->beta_sm != c->beta_mbf && !c->facs) {
     return fail(c, MRCM_EINVAL, "distinct smoothing Robin parameter not available yet");
   }
-  const double* fac = c->fac;
-  for (int st = 0; st < nsteps; ++st) {
-    for (int col = 0; col < (1 << c->d); ++col) {
-      const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
-      if (c->prec == MRCM_FP32_REFINE) {
-        HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f,
-                                    c->bcv, c->beta_sm, c->fac32, c->p, c->gflux, c->tol,
-                                    c->max_refine, c->d_iters, c->d_resid, c->flags,
-                                    c->lds32_smooth, s));
-      } else if (c->wave) {
-        HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f,
-                                  c->bcv, c->beta_sm, fac, c->tco, c->scr, c->p, c->gflux,
-                                  c->lds_smooth, s));
-      } else {
-        HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
-                                c->beta_sm, fac, nullptr, nullptr, c->scr, c->p, c->gflux, c->prec,
-                                c->tol, c->max_refine, nullptr, nullptr, c->flags, s));
-      }
+  hipStream_t s = c->stream;
+  if (nsteps > 0) {
+    mrcm_status st = tune_smoothing(c, s);
+    if (st) return st;
+    if (c->use_graph) {
+      st = capture_sweep(c);
+      if (st) return st;
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->ev[4], s));
+  c->n_smooth_launches = nsteps << c->d;
+  for (int step = 0; step < nsteps; ++step) {
+    if (c->use_graph) {
+      HIPCHK(c, hipGraphLaunch(c->graph_exec, s));
+    } else {
+      mrcm_status st = sweep(c, s, c->smooth_nt, c->p, c->gflux);
+      if (st) return st;
     }
   }
   HIPCHK(c, hipEventRecord(c->ev[5], s));
@@ -1055,6 +1181,9 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   if (c->timed_basis && hipEventElapsedTime(&ms, c->ev[8], c->ev[9]) == hipSuccess)
     out->ms_basis_kernel = ms;
   out->n_smooth_launches = c->n_smooth_launches;
+  out->smooth_threads = c->smooth_nt;
+  out->smooth_graph = c->use_graph ? 1 : 0;
+  out->ms_autotune = c->ms_autotune;
   return check_flags(c);
 }
 
@@ -1067,6 +1196,7 @@ mrcm_status mrcm_destroy(mrcm_ctx* c) {
   if (!c) return MRCM_EINVAL;
   (void)hipStreamSynchronize(c->stream);
   free_plan(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dfree(c->logk); dfree(c->K); dfree(c->f); dfree(c->bcv); dfree(c->flags);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);

@@ -359,12 +359,12 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-// Steps 6-7: one color phase of the smoothing sweep.  Four waves per box
-// stage the box's data, build the right-hand side and write the outputs; the
-// first wave runs the block sweeps.
-constexpr int kSmoothThreads = 256;
-
-__global__ void __launch_bounds__(kSmoothThreads) k_smooth_w(Geo g, const Box* __restrict__ boxes,
+// Steps 6-7: one color phase of the smoothing sweep.  NT threads per box
+// (64, 128 or 256, chosen by the autotuner) stage the box's data, build the
+// right-hand side and write the outputs; the first wave runs the block
+// sweeps.  The result does not depend on NT.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ boxes,
                                                  const int* __restrict__ members,
                                                  const double* __restrict__ K,
                                                  const double* __restrict__ f,
@@ -373,15 +373,14 @@ __global__ void __launch_bounds__(kSmoothThreads) k_smooth_w(Geo g, const Box* _
                                                  const double* __restrict__ tcoup,
                                                  double* __restrict__ p,
                                                  double* __restrict__ gflux) {
-  constexpr int NT = kSmoothThreads;
   extern __shared__ __align__(16) double dsm[];
   const Box B = boxes[members[blockIdx.x]];
   SmoothLds r = carve_smooth(dsm, B);
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
-  __syncthreads();
+  bsync<NT>();
   smooth_rhs<NT>(g, B, r, beta, r.b.X);
   if (threadIdx.x < 64) sweep1(B, fac + B.fac, r.b, r.b.Z);
-  __syncthreads();
+  bsync<NT>();
   smooth_out<NT>(g, B, r, r.b.X, beta, p, gflux);
 }
 
@@ -430,13 +429,25 @@ hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const d
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* tcoup, double* scr, double* p,
-                           double* gflux, size_t lds, hipStream_t s) {
+                           double* gflux, size_t lds, int nt, hipStream_t s) {
   (void)scr;
   if (nmem <= 0) return hipSuccess;
-  hipError_t e = set_lds(k_smooth_w, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_smooth_w, dim3(nmem), dim3(kSmoothThreads), lds, s, g, boxes, members, K, f, bcv, beta,
-                     fac, tcoup, p, gflux);
+  hipError_t e;
+#define MRCM_SMOOTH_NT(N)                                                                     \
+  e = set_lds(k_smooth_w<N>, lds);                                                            \
+  if (e != hipSuccess) return e;                                                              \
+  hipLaunchKernelGGL(k_smooth_w<N>, dim3(nmem), dim3(N), lds, s, g, boxes, members, K, f, bcv, \
+                     beta, fac, tcoup, p, gflux);
+  if (nt == 64) {
+    MRCM_SMOOTH_NT(64)
+  } else if (nt == 128) {
+    MRCM_SMOOTH_NT(128)
+  } else if (nt == 256) {
+    MRCM_SMOOTH_NT(256)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef MRCM_SMOOTH_NT
   return hipGetLastError();
 }
 

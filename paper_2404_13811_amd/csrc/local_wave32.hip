@@ -569,9 +569,8 @@ __host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1) {
   return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW + 4);
 }
 
-constexpr int kSmooth32Threads = 256;
-
-__global__ void __launch_bounds__(kSmooth32Threads) k_smooth32(Geo g, const Box* __restrict__ boxes,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_smooth32(Geo g, const Box* __restrict__ boxes,
                                                  const int* __restrict__ members,
                                                  const double* __restrict__ K,
                                                  const double* __restrict__ f,
@@ -581,7 +580,6 @@ __global__ void __launch_bounds__(kSmooth32Threads) k_smooth32(Geo g, const Box*
                                                  double* __restrict__ gflux, double tol,
                                                  int max_refine, int* iters,
                                                  unsigned long long* resid, int* flags) {
-  constexpr int NT = kSmooth32Threads;
   extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmemF sm;
   const Box B = boxes[members[blockIdx.x]];
@@ -656,12 +654,24 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members,
                              const double* K, const double* f, const double* bcv, double beta,
                              const float* fac32, double* p, double* gflux, double tol,
                              int max_refine, int* iters, unsigned long long* resid, int* flags,
-                             size_t lds, hipStream_t s) {
+                             size_t lds, int nt, hipStream_t s) {
   if (nmem <= 0) return hipSuccess;
-  hipError_t e = set_lds(k_smooth32, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_smooth32, dim3(nmem), dim3(kSmooth32Threads), lds, s, g, boxes, members, K, f, bcv, beta,
-                     fac32, p, gflux, tol, max_refine, iters, resid, flags);
+  hipError_t e;
+#define MRCM_SMOOTH32_NT(N)                                                                     \
+  e = set_lds(k_smooth32<N>, lds);                                                              \
+  if (e != hipSuccess) return e;                                                                \
+  hipLaunchKernelGGL(k_smooth32<N>, dim3(nmem), dim3(N), lds, s, g, boxes, members, K, f, bcv,  \
+                     beta, fac32, p, gflux, tol, max_refine, iters, resid, flags);
+  if (nt == 64) {
+    MRCM_SMOOTH32_NT(64)
+  } else if (nt == 128) {
+    MRCM_SMOOTH32_NT(128)
+  } else if (nt == 256) {
+    MRCM_SMOOTH32_NT(256)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef MRCM_SMOOTH32_NT
   return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const d
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* tcoup, double* scr, double* p,
-                           double* gflux, size_t lds, hipStream_t s);
+                           double* gflux, size_t lds, int nt, hipStream_t s);
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);
@@ -140,7 +140,7 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members,
                              const double* K, const double* f, const double* bcv, double beta,
                              const float* fac32, double* p, double* gflux, double tol,
                              int max_refine, int* iters, unsigned long long* resid, int* flags,
-                             size_t lds, hipStream_t s);
+                             size_t lds, int nt, hipStream_t s);
 
 // interface system (iface.hip)
 hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,

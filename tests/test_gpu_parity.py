@@ -104,6 +104,13 @@ def test_bcr_large_layer_blocks(overlap):
     assert np.linalg.norm(X - rX) <= 1e-9 * np.linalg.norm(rX)
 
 
+# Full-size channel workload: 1024 x 1024 cells, 64 x 64 subdomains,
+# 16128 interface unknowns in 64 layers of up to 256 (about a minute of
+# oracle time).
+def test_c3_full():
+    _check(make_workload("c3"))
+
+
 def test_three_dimensional_small():
     _check(make_workload("c4", scale=8), nsmooth=1)
 
@@ -134,3 +141,44 @@ def test_fp32_refine_c1():
 @pytest.mark.parametrize("overlap", [0, 2, 4])
 def test_fp32_refine_c2_full(overlap):
     _check32(make_workload("c2", overlap=overlap))
+
+
+# ------------------------------------------------- smoothing execution forms
+def _smooth_trace(wl, use_graph, threads, steps, precision="fp64"):
+    """Pressure and flux after each mrcm_smooth call (eager reads between
+    the calls, so graph replays alternate with other device work)."""
+    import torch
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    ctx = m.create(wl.dim, wl.ncell, wl.h)
+    out = []
+    try:
+        api.configure(ctx, wl, precision, tol=1e-12, max_refine=30)
+        m.set_smoothing(ctx, use_graph, threads)
+        m.build_basis(ctx)
+        m.solve_interface(ctx)
+        for n in steps:
+            m.smooth(ctx, n)
+            out.append((m.get_pressure(ctx).cpu().numpy(), m.get_flux(ctx).cpu().numpy()))
+        st = m.get_stats(ctx)
+        torch.cuda.synchronize()
+    finally:
+        m.destroy(ctx)
+    return out, st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_smoothing_graph_and_thread_variants_agree_exactly(precision):
+    """Every threads-per-box variant and every graph replay gives results
+    bit-identical to plain launches after the same number of steps."""
+    wl = make_workload("c2", scale=4, overlap=2)
+    steps = [2, 1, 2, 1]
+    ref, _ = _smooth_trace(wl, False, 64, steps, precision)
+    for use_graph, threads in [(False, 128), (False, 256), (True, 0), (True, 64)]:
+        got, st = _smooth_trace(wl, use_graph, threads, steps, precision)
+        print("graph", use_graph, "threads", threads, "->", st["smooth_threads"],
+              "autotune ms %.3f" % st["ms_autotune"], flush=True)
+        assert st["smooth_graph"] == int(use_graph)
+        assert st["smooth_threads"] in (64, 128, 256)
+        for (p, fl), (rp, rf) in zip(got, ref):
+            assert np.array_equal(p, rp) and np.array_equal(fl, rf)
