@@ -187,6 +187,29 @@ mrcm_status mrcm_get_flux(mrcm_ctx* ctx, double* flux_dev);
  * subdomain in side order), device pointer.  For tests. */
 mrcm_status mrcm_get_coefficients(mrcm_ctx* ctx, double* x_dev);
 
+/* Reverse mode (gradient of a function of the outputs with respect to
+ * log K).  mrcm_set_checkpointing(ctx, 1) before the mrcm_smooth calls makes
+ * them keep the state (pressure and Gamma fluxes) before every colour phase
+ * (device memory: one copy of both per phase; smoothing then runs as plain
+ * launches).  Default off. */
+mrcm_status mrcm_set_checkpointing(mrcm_ctx* ctx, int on);
+
+/* dJ/dlog K (N values) of J(pressure, flux) at the current solution, given
+ * dJdp = dJ/d(mrcm_get_pressure output) (N values, or NULL for zero) and
+ * dJdflux = dJ/d(mrcm_get_flux output) (N x 2*dim values, or NULL).  The
+ * vector-Jacobian product of the whole discrete map (basis, particular
+ * problems, interface system, MRCM-O assembly, smoothing sweeps, outputs),
+ * computed on the device by the reverse of each step: adjoint local solves
+ * with the cached FP64 factors (the local matrices are symmetric), the
+ * transposed interface system by the same cyclic reduction, the smoothing
+ * phases in reverse order recomputed from the checkpoints.  Device pointers.
+ * Requirements: MRCM_FP64, 2-D boxes whose lines have <= 32 cells, the block
+ * cyclic reduction interface solver, equal Robin parameters in both stages,
+ * checkpointing on for every smoothing step since the last
+ * mrcm_solve_interface.  Errors: MRCM_EINVAL, MRCM_ESTATE, MRCM_EDEVICE. */
+mrcm_status mrcm_adjoint(mrcm_ctx* ctx, const double* dJdp_dev, const double* dJdflux_dev,
+                         double* dJdlogK_dev);
+
 mrcm_status mrcm_get_stats(mrcm_ctx* ctx, mrcm_stats* out);
 
 /* Message of the last failure on this context (never NULL). */

@@ -14,7 +14,7 @@ STATUS = {0: "MRCM_OK", 1: "MRCM_EINVAL", 2: "MRCM_ENOMEM", 3: "MRCM_EDEVICE", 4
 
 SYMBOLS = ("mrcm_create", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_bc",
            "mrcm_set_partition", "mrcm_set_interface_space", "mrcm_set_interface_solver",
-           "mrcm_set_robin", "mrcm_set_smoothing",
+           "mrcm_set_robin", "mrcm_set_smoothing", "mrcm_set_checkpointing", "mrcm_adjoint",
            "mrcm_set_precision", "mrcm_build_basis", "mrcm_solve_interface", "mrcm_smooth",
            "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_coefficients", "mrcm_get_stats",
            "mrcm_last_error", "mrcm_destroy")
@@ -54,6 +54,8 @@ def load():
         "mrcm_set_interface_solver": [vp, i],
         "mrcm_set_robin": [vp, i, d, d],
         "mrcm_set_smoothing": [vp, i, i],
+        "mrcm_set_checkpointing": [vp, i],
+        "mrcm_adjoint": [vp, vp, vp, vp],
         "mrcm_set_precision": [vp, i, d, i],
         "mrcm_build_basis": [vp],
         "mrcm_solve_interface": [vp],

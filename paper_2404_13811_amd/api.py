@@ -140,6 +140,61 @@ def get_stats(ctx):
     return {k: getattr(st, k) for k, _ in st._fields_}
 
 
+def set_checkpointing(ctx, on=True):
+    _check(ctx, "mrcm_set_checkpointing", _lib.load().mrcm_set_checkpointing(ctx.handle, int(bool(on))))
+
+
+def adjoint(ctx, dJdp=None, dJdflux=None, out=None):
+    """dJ/dlog K (device tensor) for the given output adjoints (mrcm_adjoint)."""
+    n = ctx.ncells
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+    gp = None if dJdp is None else dJdp.detach().to(device="cuda", dtype=torch.float64).contiguous()
+    gf = None if dJdflux is None else dJdflux.detach().to(device="cuda", dtype=torch.float64).contiguous()
+    _check(ctx, "mrcm_adjoint", _lib.load().mrcm_adjoint(
+        ctx.handle, _dev(gp, n) if gp is not None else None,
+        _dev(gf, n * 2 * ctx.dim) if gf is not None else None, _dev(out, n)))
+    return out
+
+
+class _SolveFn(torch.autograd.Function):
+    """(pressure, flux) = MRCM-OS(log K); backward = mrcm_adjoint."""
+
+    @staticmethod
+    def forward(actx, logk, wl, nsmooth):
+        ctx = create(wl.dim, wl.ncell, wl.h)
+        try:
+            configure(ctx, wl, "fp64")
+            set_permeability(ctx, logk.detach().to(device="cuda", dtype=torch.float64).contiguous())
+            set_checkpointing(ctx, True)
+            build_basis(ctx)
+            solve_interface(ctx)
+            smooth(ctx, wl.nsmooth if nsmooth is None else nsmooth)
+            p = get_pressure(ctx)
+            fl = get_flux(ctx)
+        except Exception:
+            destroy(ctx)
+            raise
+        actx.mrcm = ctx
+        return p, fl
+
+    @staticmethod
+    def backward(actx, gp, gfl):
+        ctx = actx.mrcm
+        try:
+            g = adjoint(ctx, gp, gfl)
+        finally:
+            destroy(ctx)
+        return g, None, None
+
+
+def solve_differentiable(logk, wl, nsmooth=None):
+    """MRCM-OS pressure and face velocities as differentiable functions of
+    log K (a CUDA float64 tensor of N values); the gradient runs the device
+    adjoint.  The workload record supplies everything else."""
+    return _SolveFn.apply(logk, wl, nsmooth)
+
+
 def get_coefficients(ctx, out=None):
     n = get_stats(ctx)["n_unknowns"]
     if out is None:

@@ -326,6 +326,11 @@ hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl
   return hipGetLastError();
 }
 
+hipError_t launch_bcr_pad(double* pool, const int* lsize, int M, int bp, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcr_pad, dim3(M), dim3(64), 0, s, pool, lsize, bp);
+  return hipGetLastError();
+}
+
 hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* col_loc, int n, int bp,
                              double* X, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -111,6 +111,16 @@ struct mrcm_ctx {
   double* gflux_tune = nullptr;
   double ms_autotune = 0.0;
 
+  // reverse mode: checkpoints of the smoothing state and adjoint workspace
+  bool ckpt = false;
+  double *ck_p = nullptr, *ck_g = nullptr;
+  int ck_cap = 0, n_ck = 0, n_phase = 0;
+  double *a_pb = nullptr, *a_gfb = nullptr, *a_Kb = nullptr, *a_Xb = nullptr, *a_nu = nullptr;
+  double *a_trub = nullptr, *a_trphib = nullptr, *a_trbetab = nullptr, *a_ubarb = nullptr;
+  double *a_pibarb = nullptr, *a_mean = nullptr;
+  int* d_seed_sub = nullptr;
+  size_t lds_adj_smooth = 0, lds_adj_basis = 0, lds_adj_part = 0;
+
   hipEvent_t ev[12] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed_basis = false, timed_iface = false, timed_smooth = false;
@@ -158,6 +168,11 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->d_lsize); dfree(c->d_binv); dfree(c->d_bgemm); dfree(c->d_bgemv);
   dfree(c->bpool); dfree(c->bvec);
   dfree(c->p_tune); dfree(c->gflux_tune);
+  dfree(c->ck_p); dfree(c->ck_g);
+  c->ck_cap = c->n_ck = c->n_phase = 0;
+  dfree(c->a_pb); dfree(c->a_gfb); dfree(c->a_Kb); dfree(c->a_Xb); dfree(c->a_nu);
+  dfree(c->a_trub); dfree(c->a_trphib); dfree(c->a_trbetab); dfree(c->a_ubarb);
+  dfree(c->a_pibarb); dfree(c->a_mean); dfree(c->d_seed_sub);
   drop_graph(c);
   c->smooth_nt = 0;
   c->use_bcr = false;
@@ -548,6 +563,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   c->scrp_n = scrp;
   c->wave = c->d == 2;
   c->lds_basis = c->lds_part = c->lds_smooth = 0;
+  c->lds_adj_smooth = c->lds_adj_basis = c->lds_adj_part = 0;
   for (int i = 0; i < nsub; ++i) {
     const Box& B = c->obox[i];
     const Box& P = c->pbox[i];
@@ -559,6 +575,11 @@ mrcm_status make_plan(mrcm_ctx* c) {
     c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0));
     c->lds32_smooth = std::max(c->lds32_smooth, wave32_smooth_lds_bytes(bm0, bm1));
     c->lds32_part = std::max(c->lds32_part, wave32_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, 1));
+    if (c->d == 2) {
+      c->lds_adj_smooth = std::max(c->lds_adj_smooth, adj_smooth_lds_bytes(bm0, bm1));
+      c->lds_adj_basis = std::max(c->lds_adj_basis, adj_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
+      c->lds_adj_part = std::max(c->lds_adj_part, adj_part_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1]));
+    }
   }
   if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024) c->wave = false;
 
@@ -985,6 +1006,8 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   HIPCHK(c, hipEventRecord(c->ev[3], s));
   c->timed_iface = true;
   c->state = 2;
+  c->n_ck = 0;
+  c->n_phase = 0;
   return MRCM_OK;
 }
 
@@ -993,9 +1016,16 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
 namespace {
 
 // One smoothing sweep: the 2^d colour phases, in increasing colour order.
-mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux) {
+mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, bool ck = false) {
+  const size_t np = (size_t)c->geo.ncells, ng = (size_t)c->geo.nsub * c->geo.gstride;
   for (int col = 0; col < (1 << c->d); ++col) {
     const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
+    if (ck) {
+      // state before this phase, for the reverse pass
+      HIPCHK(c, hipMemcpyAsync(c->ck_p + c->n_ck * np, p, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(c->ck_g + c->n_ck * ng, gflux, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+      ++c->n_ck;
+    }
     if (c->prec == MRCM_FP32_REFINE) {
       HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
                                   c->beta_sm, c->fac32, p, gflux, c->tol, c->max_refine,
@@ -1102,21 +1132,43 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   if (nsteps > 0) {
     mrcm_status st = tune_smoothing(c, s);
     if (st) return st;
-    if (c->use_graph) {
+    if (c->use_graph && !c->ckpt) {
       st = capture_sweep(c);
       if (st) return st;
+    }
+  }
+  if (c->ckpt && nsteps > 0) {
+    // room for the checkpoints of these phases (grown with a copy)
+    const int need = c->n_ck + (nsteps << c->d);
+    if (need > c->ck_cap) {
+      const size_t np = (size_t)c->geo.ncells, ng = (size_t)c->geo.nsub * c->geo.gstride;
+      const int cap = std::max(need, 2 * c->ck_cap);
+      double *np_ = nullptr, *ng_ = nullptr;
+      HIPCHK(c, hipMalloc((void**)&np_, (size_t)cap * np * sizeof(double)));
+      HIPCHK(c, hipMalloc((void**)&ng_, (size_t)cap * std::max<size_t>(ng, 1) * sizeof(double)));
+      if (c->n_ck) {
+        HIPCHK(c, hipMemcpyAsync(np_, c->ck_p, c->n_ck * np * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(ng_, c->ck_g, c->n_ck * ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+      }
+      dfree(c->ck_p);
+      dfree(c->ck_g);
+      c->ck_p = np_;
+      c->ck_g = ng_;
+      c->ck_cap = cap;
     }
   }
   HIPCHK(c, hipEventRecord(c->ev[4], s));
   c->n_smooth_launches = nsteps << c->d;
   for (int step = 0; step < nsteps; ++step) {
-    if (c->use_graph) {
+    if (c->use_graph && !c->ckpt) {
       HIPCHK(c, hipGraphLaunch(c->graph_exec, s));
     } else {
-      mrcm_status st = sweep(c, s, c->smooth_nt, c->p, c->gflux);
+      mrcm_status st = sweep(c, s, c->smooth_nt, c->p, c->gflux, c->ckpt);
       if (st) return st;
     }
   }
+  c->n_phase += nsteps << c->d;
   HIPCHK(c, hipEventRecord(c->ev[5], s));
   c->timed_smooth = true;
   c->n_local_solves += nsteps * c->geo.nsub;
@@ -1145,6 +1197,106 @@ mrcm_status mrcm_get_coefficients(mrcm_ctx* c, double* x_dev) {
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
   if (c->nX > 0)
     HIPCHK(c, hipMemcpyAsync(x_dev, c->X, c->nX * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return check_flags(c);
+}
+
+mrcm_status mrcm_set_checkpointing(mrcm_ctx* c, int on) {
+  if (!c) return MRCM_EINVAL;
+  c->ckpt = on != 0;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux, double* dJdlogK) {
+  if (!c) return MRCM_EINVAL;
+  if (!dJdlogK) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution to differentiate");
+  if (c->prec != MRCM_FP64 || !c->wave || c->d != 2)
+    return fail(c, MRCM_EINVAL, "the adjoint needs the FP64 path on 2-D boxes with lines of <= 32 cells");
+  if (!c->use_bcr)
+    return fail(c, MRCM_EINVAL, "the adjoint needs the block-cyclic-reduction interface solver");
+  if (c->n_ck != c->n_phase)
+    return fail(c, MRCM_ESTATE, "smoothing ran without checkpointing (call mrcm_set_checkpointing first)");
+  if (c->lds_adj_basis > 150 * 1024 || c->lds_adj_smooth > 150 * 1024 || c->lds_adj_part > 150 * 1024)
+    return fail(c, MRCM_EINVAL, "too many seeds per box for the adjoint kernels");
+  if (c->beta_sm != c->beta_mbf)
+    return fail(c, MRCM_EINVAL, "the adjoint needs equal Robin parameters in both stages");
+  const Geo& g = c->geo;
+  hipStream_t s = c->stream;
+  const size_t N = (size_t)g.ncells, ng = std::max<size_t>((size_t)g.nsub * g.gstride, 1);
+  const size_t nX = std::max(c->nX, 1), ntr = (size_t)nX * g.gstride;
+  auto need = [&](double*& p, size_t n) -> mrcm_status {
+    if (!p) HIPCHK(c, hipMalloc((void**)&p, n * sizeof(double)));
+    return MRCM_OK;
+  };
+#define NEED(p, n) do { mrcm_status s_ = need(p, n); if (s_) return s_; } while (0)
+  NEED(c->a_pb, N); NEED(c->a_gfb, ng); NEED(c->a_Kb, N); NEED(c->a_Xb, nX); NEED(c->a_nu, nX);
+  NEED(c->a_trub, ntr); NEED(c->a_trphib, ntr); NEED(c->a_trbetab, ng); NEED(c->a_ubarb, ng);
+  NEED(c->a_pibarb, ng); NEED(c->a_mean, 1);
+#undef NEED
+  if (!c->d_seed_sub) {
+    std::vector<int> ss(nX, 0);
+    for (int i = 0; i < g.nsub; ++i)
+      for (int k = c->seed_off[i]; k < c->seed_off[i + 1]; ++k) ss[k] = i;
+    HIPCHK(c, hipMalloc((void**)&c->d_seed_sub, nX * sizeof(int)));
+    HIPCHK(c, hipMemcpy(c->d_seed_sub, ss.data(), nX * sizeof(int), hipMemcpyHostToDevice));
+  }
+  HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
+  // outputs
+  HIPCHK(c, launch_fill(c->a_gfb, 0.0, (long long)ng, s));
+  HIPCHK(c, launch_adj_out(g, c->K, c->p, c->bcv, dJdp, dJdflux, c->a_mean, c->a_pb, c->a_gfb,
+                           c->a_Kb, s));
+  // smoothing phases, last first
+  const size_t np = N;
+  for (int ph = c->n_ck - 1; ph >= 0; --ph) {
+    const int col = ph % (1 << g.d);
+    const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
+    HIPCHK(c, launch_adj_smooth(g, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+                                c->beta_sm, c->fac, c->tco, c->ck_p + ph * np, c->ck_g + ph * ng,
+                                c->a_pb, c->a_gfb, c->a_Kb, c->lds_adj_smooth, s));
+  }
+  // MRCM-O assembly
+  HIPCHK(c, launch_adj_combine(g, c->d_seed_sub, c->nX, c->X, c->Pk, c->tr_u, c->a_pb, c->a_gfb,
+                               c->a_Xb, c->a_trub, s));
+  // interface system, transposed: G^T nu = Xbar by the same reduction
+  {
+    const int M = c->bcr_M, bp = c->bcr_bp;
+    const long long bs = (long long)bp * bp;
+    HIPCHK(c, launch_fill(c->AB, 0.0, (long long)c->ldab * c->nX, s));
+    HIPCHK(c, launch_moments(g, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->d_seed_off, c->tr_u,
+                             c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab, c->kl, c->ku,
+                             c->rhs, s));
+    HIPCHK(c, launch_fill(c->bpool, 0.0, 3LL * M * bs, s));
+    HIPCHK(c, launch_fill(c->bvec, 0.0, (long long)M * bp, s));
+    HIPCHK(c, launch_bcr_scatter_t(c->AB, c->a_Xb, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
+                                   c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, s));
+    HIPCHK(c, launch_bcr_pad(c->bpool, c->d_lsize, M, bp, s));
+    for (const auto& o : c->bcr_ops) {
+      if (o.kind == 0)
+        HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, o.n, o.ld, c->flags, s));
+      else if (o.kind == 1)
+        HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, o.n, o.ld, s));
+      else
+        HIPCHK(c, launch_bcr_gemv(c->bpool, c->bvec, c->d_bgemv + o.off, o.cnt, bp, s));
+    }
+    HIPCHK(c, launch_bcr_gather_t(c->bvec + 2LL * M * bp, c->d_row_lvl, c->d_row_loc, c->nX, bp,
+                                  c->a_nu, s));
+  }
+  // moments
+  HIPCHK(c, hipMemcpyAsync(c->a_ubarb, c->a_gfb, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, launch_fill(c->a_trphib, 0.0, (long long)ntr, s));
+  HIPCHK(c, launch_fill(c->a_trbetab, 0.0, (long long)ng, s));
+  HIPCHK(c, launch_fill(c->a_pibarb, 0.0, (long long)ng, s));
+  HIPCHK(c, launch_adj_moments(g, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->d_seed_off, c->X,
+                               c->a_nu, c->tr_u, c->tr_beta, c->a_trub, c->a_trphib, c->a_trbetab,
+                               c->a_ubarb, c->a_pibarb, s));
+  // seeds and particular problems
+  HIPCHK(c, launch_adj_basis(g, c->d_obox, g.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac, c->X,
+                             c->a_pb, c->tr_u, c->a_trub, c->a_trphib, c->a_trbetab, c->a_Kb,
+                             c->lds_adj_basis, s));
+  HIPCHK(c, launch_adj_particular(g, c->d_pbox, g.nsub, c->K, c->bcv, c->beta_mbf, c->facp,
+                                  c->pbar, c->a_pb, c->a_ubarb, c->a_pibarb, c->a_Kb,
+                                  c->lds_adj_part, s));
+  HIPCHK(c, launch_adj_logk(c->K, c->a_Kb, g.ncells, dJdlogK, s));
   return check_flags(c);
 }
 

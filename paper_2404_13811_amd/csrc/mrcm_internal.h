@@ -167,6 +167,44 @@ hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks
                            hipStream_t s);
 hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* col_loc, int n, int bp,
                              double* X, hipStream_t s);
+hipError_t launch_bcr_pad(double* pool, const int* lsize, int M, int bp, hipStream_t s);
+
+// adjoint (adjoint.hip): reverse mode of the 2-D FP64 path
+size_t adj_smooth_lds_bytes(int m0, int m1);
+size_t adj_basis_lds_bytes(int m0, int m1, int nrhs);
+size_t adj_part_lds_bytes(int m0, int m1);
+hipError_t launch_adj_out(const Geo& g, const double* K, const double* p, const double* bcv,
+                          const double* dJdp, const double* dJdf, double* meanp, double* pb,
+                          double* gfb, double* Kb, hipStream_t s);
+hipError_t launch_adj_smooth(const Geo& g, const Box* boxes, const int* members, int nmem,
+                             const double* K, const double* f, const double* bcv, double beta,
+                             const double* fac, const double* tcoup, const double* p_in,
+                             const double* gf_in, double* pb, double* gfb, double* Kb, size_t lds,
+                             hipStream_t s);
+hipError_t launch_adj_combine(const Geo& g, const int* seed_sub, int nX, const double* X,
+                              const double* Pk, const double* tr_u, const double* pb,
+                              const double* gfb, double* Xb, double* tr_ub, hipStream_t s);
+hipError_t launch_adj_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,
+                              const int* seed_off, const double* X, const double* nu,
+                              const double* tr_u, const double* tr_beta, double* tr_ub,
+                              double* tr_phib, double* tr_betab, double* ubarb, double* pibarb,
+                              hipStream_t s);
+hipError_t launch_adj_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
+                            const double* K, double beta, const double* fac, const double* X,
+                            const double* pb, const double* tr_u, const double* tr_ub,
+                            const double* tr_phib, const double* tr_betab, double* Kb, size_t lds,
+                            hipStream_t s);
+hipError_t launch_adj_particular(const Geo& g, const Box* boxes, int nbox, const double* K,
+                                 const double* bcv, double beta, const double* fac,
+                                 const double* pbar, const double* pb, const double* ubarb,
+                                 const double* pibarb, double* Kb, size_t lds, hipStream_t s);
+hipError_t launch_adj_logk(const double* K, const double* Kb, int n, double* out, hipStream_t s);
+hipError_t launch_bcr_scatter_t(const double* RB, const double* rhs, int n, int kl, int ku,
+                                const int* row_lvl, const int* row_loc, const int* col_lvl,
+                                const int* col_loc, int M, int bp, double* pool, double* vec,
+                                hipStream_t s);
+hipError_t launch_bcr_gather_t(const double* xv, const int* row_lvl, const int* row_loc, int n, int bp,
+                               double* out, hipStream_t s);
 
 // outputs (outputs.hip)
 hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,

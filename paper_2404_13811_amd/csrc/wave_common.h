@@ -619,5 +619,173 @@ __device__ __forceinline__ void smooth_out(const Geo& g, const Box& B, const Smo
   }
 }
 
+// ------------------------------------------------------------- block sweeps
+// W_j z for the block staged in z (LDS): lane (c, h) sums its 16 rows with
+// two accumulators; half_sum completes the column.
+__device__ __forceinline__ double wgemv2(const double w[HB], const double* z) {
+  const int h = lane_id() >> 5;
+  const double2* z2 = reinterpret_cast<const double2*>(z + HB * h);
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < HB / 2; ++i) {
+    const double2 v = z2[i];
+    a0 = fma(w[2 * i], v.x, a0);
+    a1 = fma(w[2 * i + 1], v.y, a1);
+  }
+  return half_sum(a0 + a1);
+}
+
+// Forward step of block j for all right-hand sides, inverse in w:
+// X_j <- W_j (X_j + t_{j-1} .* X_{j-1}).
+__device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
+                                         const double w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  #pragma unroll 1
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    double v = 0.0;
+    if (r < nb) {
+      v = s.X[k * ncell + j * nb + r];
+      if (j > 0) v += s.Tn[(j - 1) * nb + r] * s.X[k * ncell + (j - 1) * nb + r];
+    }
+    s.Z[k * NBW + r] = v;
+  }
+  wsync();
+  for (int k = 0; k < nrhs; ++k) {
+    const double y = wgemv2(w, s.Z + k * NBW);
+    if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] = y;
+  }
+  wsync();
+}
+
+// Backward step of block j: X_j <- X_j + W_j (t_j .* X_{j+1}).
+__device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
+                                         const double w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  #pragma unroll 1
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    s.Z[k * NBW + r] = (r < nb) ? s.Tn[j * nb + r] * s.X[k * ncell + (j + 1) * nb + r] : 0.0;
+  }
+  wsync();
+  for (int k = 0; k < nrhs; ++k) {
+    const double y = wgemv2(w, s.Z + k * NBW);
+    if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] += y;
+  }
+  wsync();
+}
+
+// Sweeps with the cached inverses streamed from memory, RING blocks ahead.
+__device__ __forceinline__ void forward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
+  const int nb = B.nb, nblk = B.nblk;
+  const long long bs = (long long)nb * nb;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  double w[RING][HB];
+#pragma unroll
+  for (int q = 0; q < RING; ++q)
+    if (q < nblk) wload_block(src, q, w[q]);
+  for (int j0 = 0; j0 < nblk; j0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int j = j0 + q;
+      if (j < nblk) {
+        fwd_step(nb, B.ncell, j, nrhs, s, w[q]);
+        if (j + RING < nblk) wload_block(src, (j + RING), w[q]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void backward_cached(const Box& B, const double* Wg, int nrhs, const BoxLds& s) {
+  const int nb = B.nb, nblk = B.nblk;
+  const long long bs = (long long)nb * nb;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  double w[RING][HB];
+  // block j = nblk - 2 - t uses ring slot t % RING
+#pragma unroll
+  for (int q = 0; q < RING; ++q)
+    if (nblk - 2 - q >= 0) wload_block(src, (nblk - 2 - q), w[q]);
+  for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int j = nblk - 2 - (t0 + q);
+      if (j >= 0) {
+        bwd_step(nb, B.ncell, j, nrhs, s, w[q]);
+        if (j - RING >= 0) wload_block(src, (j - RING), w[q]);
+      }
+    }
+  }
+}
+
+// Forward and backward sweeps of one right-hand side in s.X with the cached
+// inverses.  The value of the previous block stays in registers (every lane
+// of column c holds it), so a block step is one LDS write of the staged
+// vector, the 16-term products and one half-wave exchange.  z points to
+// 2 x NBW doubles of LDS (alternating buffers).
+__device__ __forceinline__ void sweep1(const Box& B, const double* Wg, const BoxLds& s, double* z) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb, nblk = B.nblk;
+  const bool cv = c < nb;
+  const long long bs = (long long)nb * nb;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  {
+    double w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (q < nblk) wload_block(src, q, w[q]);
+    double y = 0.0;
+    double xn = cv ? s.X[c] : 0.0, tp = 0.0;
+    for (int j0 = 0; j0 < nblk; j0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = j0 + q;
+        if (j < nblk) {
+          double* zb = z + (j & 1) * NBW;
+          if (h == 0) zb[c] = cv ? fma(tp, y, xn) : 0.0;
+          __builtin_amdgcn_wave_barrier();
+          const bool more = j + 1 < nblk;
+          xn = (more && cv) ? s.X[(j + 1) * nb + c] : 0.0;
+          tp = (more && cv) ? s.Tn[j * nb + c] : 0.0;
+          y = wgemv2(w[q], zb);
+          if (h == 0 && cv) s.X[j * nb + c] = y;
+          if (j + RING < nblk) wload_block(src, (j + RING), w[q]);
+        }
+      }
+    }
+  }
+  {
+    double w[RING][HB];
+#pragma unroll
+    for (int q = 0; q < RING; ++q)
+      if (nblk - 2 - q >= 0) wload_block(src, (nblk - 2 - q), w[q]);
+    // x_{nblk-1} = w_{nblk-1} is final; every lane of column c reads it
+    __builtin_amdgcn_wave_barrier();
+    double xnext = cv ? s.X[(nblk - 1) * nb + c] : 0.0;
+    double tj = (nblk >= 2 && cv) ? s.Tn[(nblk - 2) * nb + c] : 0.0;
+    double wj = (nblk >= 2 && cv) ? s.X[(nblk - 2) * nb + c] : 0.0;
+    for (int t0 = 0; t0 <= nblk - 2; t0 += RING) {
+#pragma unroll
+      for (int q = 0; q < RING; ++q) {
+        const int j = nblk - 2 - (t0 + q);
+        if (j >= 0) {
+          double* zb = z + (j & 1) * NBW;
+          if (h == 0) zb[c] = cv ? tj * xnext : 0.0;
+          __builtin_amdgcn_wave_barrier();
+          const double wcur = wj;
+          tj = (j >= 1 && cv) ? s.Tn[(j - 1) * nb + c] : 0.0;
+          wj = (j >= 1 && cv) ? s.X[(j - 1) * nb + c] : 0.0;
+          xnext = wcur + wgemv2(w[q], zb);
+          if (h == 0 && cv) s.X[j * nb + c] = xnext;
+          if (j - RING >= 0) wload_block(src, (j - RING), w[q]);
+        }
+      }
+    }
+  }
+  wsync();
+}
+
 }  // namespace wave
 }  // namespace mrcm
