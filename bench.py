@@ -90,6 +90,49 @@ def time_solves(wl, precision, steps, warmup, tol):
     return dt, phases, st, p.cpu().numpy(), fl.cpu().numpy()
 
 
+def time_adjoint(wl, reps):
+    """Forward solve with checkpointing plus mrcm_adjoint (dJ/dlog K of the
+    outflow through the +x side plus a misfit at 16 cells) on one member of
+    the batch workload; device wall time per call."""
+    import numpy as np
+    import torch
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    nx, ny = wl.ncell
+    N = nx * ny
+    obs = torch.as_tensor(np.arange(0, N, N // 16)[:16], device="cuda")
+    fw = torch.zeros(N, 4, dtype=torch.float64, device="cuda")
+    fw[torch.arange(nx - 1, N, nx, device="cuda"), 1] = wl.h
+    fw = fw.reshape(-1)
+    ctx = m.create(wl.dim, wl.ncell, wl.h)
+    api.configure(ctx, wl, "fp64")
+    m.set_checkpointing(ctx, True)
+    grad = torch.empty(N, dtype=torch.float64, device="cuda")
+    tf = ta = 0.0
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.build_basis(ctx)
+        m.solve_interface(ctx)
+        m.smooth(ctx, wl.nsmooth)
+        p = m.get_pressure(ctx)
+        m.get_flux(ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dJdp = torch.zeros_like(p)
+        dJdp[obs] = p[obs] - 0.1
+        m.adjoint(ctx, dJdp, fw, grad)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r:  # the first call builds the plan and allocates
+            tf += (t1 - t0) / reps
+            ta += (t2 - t1) / reps
+    m.destroy(ctx)
+    return {"workload": "c5 member: 256x256 cells, subdomains 16x16, overlap 2, const spaces, 5 smoothing steps",
+            "ms_forward_with_checkpoints": round(tf * 1e3, 4), "ms_gradient": round(ta * 1e3, 4),
+            "gradient_over_forward": round(ta / tf, 3)}
+
+
 def boxes(wl):
     """Oversampled boxes (cells per axis), seeds per box, subdomain cells."""
     import numpy as np
@@ -215,6 +258,7 @@ def main():
             d["err_vs_oracle"] = f["err"]
         return d
 
+    adj = None if args.no_extra else time_adjoint(make_workload("c5"), max(3, args.steps // 4))
     extra = {}
     if not args.no_extra and args.workload == "c2":
         for l in (0, 2, 4):
@@ -245,6 +289,7 @@ def main():
         head: form_summary(H, head),
         other: form_summary(O, other),
         "other_overlaps": extra,
+        "adjoint": adj,
         "roofline": roofline(wl, head, H["phases"], st),
     }
     if cpu is not None:
