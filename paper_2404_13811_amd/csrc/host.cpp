@@ -945,23 +945,19 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
     HIPCHK(c, hipEventRecord(c->ev[8], s));
-    HIPCHK(c, launch_basis32_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf,
-                               c->fac32, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->tol,
-                               c->max_refine, c->d_iters, c->d_resid, c->flags, c->lds32_basis, s));
+    HIPCHK(c, launch_local32_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
+                               c->bcv, c->beta_mbf, c->fac32, c->facp32, c->Pk, c->tr_u, c->tr_phi,
+                               c->tr_beta, c->pbar, c->ubar, c->pibar, c->tol, c->max_refine,
+                               c->d_iters, c->d_resid, c->flags,
+                               std::max(c->lds32_basis, c->lds32_part), s));
     HIPCHK(c, hipEventRecord(c->ev[9], s));
-    HIPCHK(c, launch_particular32_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv,
-                                    c->beta_mbf, c->facp32, c->pbar, c->ubar, c->pibar, c->tol,
-                                    c->max_refine, c->d_iters, c->d_resid, c->flags,
-                                    c->lds32_part, s));
   } else if (c->wave) {
     HIPCHK(c, hipEventRecord(c->ev[8], s));
-    HIPCHK(c, launch_basis_w(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
-                             c->tco, c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags,
-                             c->lds_basis, s));
+    HIPCHK(c, launch_local_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
+                             c->bcv, c->beta_mbf, c->fac, c->tco, c->facp, c->tcp, c->Pk, c->tr_u,
+                             c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->flags,
+                             std::max(c->lds_basis, c->lds_part), s));
     HIPCHK(c, hipEventRecord(c->ev[9], s));
-    HIPCHK(c, launch_particular_w(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
-                                  c->facp, c->tcp, c->scr, c->pbar, c->ubar, c->pibar, c->flags,
-                                  c->lds_part, s));
   } else {
     HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,

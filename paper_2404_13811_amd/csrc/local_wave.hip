@@ -58,20 +58,13 @@ __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double*
 
 // Steps 1-2: factor the oversampled box, solve every seed, extract
 // u and phi on Gamma_i and the restriction to Omega_i.
-__global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ boxes,
-                                                const Seed* __restrict__ seeds,
-                                                const double* __restrict__ K, double beta,
-                                                double* __restrict__ fac,
-                                                double* __restrict__ tcoup,
-                                                double* __restrict__ Pk,
-                                                double* __restrict__ tr_u,
-                                                double* __restrict__ tr_phi,
-                                                double* __restrict__ tr_beta, int* flags) {
-  extern __shared__ __align__(16) double dsm[];
-  __shared__ WaveSmem sm;
-  const Box B = boxes[blockIdx.x];
+__device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
+                                          const double* __restrict__ K, double beta,
+                                          double* __restrict__ fac, double* __restrict__ tcoup,
+                                          double* __restrict__ Pk, double* __restrict__ tr_u,
+                                          double* __restrict__ tr_phi,
+                                          double* __restrict__ tr_beta, double* dsm, WaveSmem& sm) {
   const int L = lane_id();
-  if (L == 0) sm.flag = 0;
   const int nrhs = B.nrhs;
   BoxLds s = carve(dsm, B, nrhs);
   load_box(g, B, K, beta, s);
@@ -141,25 +134,16 @@ __global__ void __launch_bounds__(64) k_basis_w(Geo g, const Box* __restrict__ b
       if (k == 0) tr_beta[(long long)B.sub * g.gstride + g.gside_off[q] + t] = bt;
     }
   }
-  wsync();
-  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
 // Step 4: particular problem on Omega_i with zero Robin data on Gamma_i.
-__global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restrict__ boxes,
-                                                     const double* __restrict__ K,
-                                                     const double* __restrict__ f,
-                                                     const double* __restrict__ bcv, double beta,
-                                                     double* __restrict__ fac,
-                                                     double* __restrict__ tcoup,
-                                                     double* __restrict__ pbar,
-                                                     double* __restrict__ ubar,
-                                                     double* __restrict__ pibar, int* flags) {
-  extern __shared__ __align__(16) double dsm[];
-  __shared__ WaveSmem sm;
-  const Box B = boxes[blockIdx.x];
+__device__ __forceinline__ void particular_box(const Geo& g, const Box& B, const double* __restrict__ K,
+                                               const double* __restrict__ f,
+                                               const double* __restrict__ bcv, double beta,
+                                               double* __restrict__ fac, double* __restrict__ tcoup,
+                                               double* __restrict__ pbar, double* __restrict__ ubar,
+                                               double* __restrict__ pibar, double* dsm, WaveSmem& sm) {
   const int L = lane_id();
-  if (L == 0) sm.flag = 0;
   BoxLds s = carve(dsm, B, 1);
   load_box(g, B, K, beta, s);
   physical_rhs(g, B, s, f, bcv, s.X);
@@ -189,6 +173,41 @@ __global__ void __launch_bounds__(64) k_particular_w(Geo g, const Box* __restric
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
     }
+  }
+}
+
+// Steps 1-2 and 4 in one launch.  Workgroups [0, nbox) handle the
+// oversampled boxes (factor, seeds, traces); workgroups [nbox, 2 nbox) handle
+// the particular problems on the subdomains.  The two sets share nothing, so
+// their waves run side by side instead of one launch after the other.
+__global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ obox,
+                                                const Box* __restrict__ pbox, int nbox,
+                                                const Seed* __restrict__ seeds,
+                                                const double* __restrict__ K,
+                                                const double* __restrict__ f,
+                                                const double* __restrict__ bcv, double beta,
+                                                double* __restrict__ fac,
+                                                double* __restrict__ tcoup,
+                                                double* __restrict__ facp,
+                                                double* __restrict__ tcp,
+                                                double* __restrict__ Pk,
+                                                double* __restrict__ tr_u,
+                                                double* __restrict__ tr_phi,
+                                                double* __restrict__ tr_beta,
+                                                double* __restrict__ pbar,
+                                                double* __restrict__ ubar,
+                                                double* __restrict__ pibar, int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmem sm;
+  const int L = lane_id();
+  if (L == 0) sm.flag = 0;
+  const int b = blockIdx.x;
+  if (b < nbox) {
+    const Box B = obox[b];
+    basis_box(g, B, seeds, K, beta, fac, tcoup, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+  } else {
+    const Box B = pbox[b - nbox];
+    particular_box(g, B, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm);
   }
   wsync();
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
@@ -235,29 +254,17 @@ size_t wave_lds_bytes(int m0, int m1, int nrhs) {
 
 size_t wave_smooth_lds_bytes(int m0, int m1) { return sizeof(double) * smooth_lds_doubles(m0, m1); }
 
-hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
-                          const double* K, double beta, double* fac, double* tcoup, double* scr,
-                          double* Pk, double* tr_u, double* tr_phi, double* tr_beta, int* flags,
-                          size_t lds, hipStream_t s) {
-  (void)scr;
+hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
+                          const Seed* seeds, const double* K, const double* f, const double* bcv,
+                          double beta, double* fac, double* tcoup, double* facp, double* tcp,
+                          double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
+                          double* ubar, double* pibar, int* flags, size_t lds, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
-  hipError_t e = set_lds(k_basis_w, lds);
+  hipError_t e = set_lds(k_local_w, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_basis_w, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac, tcoup,
-                     Pk, tr_u, tr_phi, tr_beta, flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const double* K,
-                               const double* f, const double* bcv, double beta, double* fac,
-                               double* tcoup, double* scr, double* pbar, double* ubar,
-                               double* pibar, int* flags, size_t lds, hipStream_t s) {
-  (void)scr;
-  if (nbox <= 0) return hipSuccess;
-  hipError_t e = set_lds(k_particular_w, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_particular_w, dim3(nbox), dim3(64), lds, s, g, boxes, K, f, bcv, beta, fac,
-                     tcoup, pbar, ubar, pibar, flags);
+  hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(64), lds, s, g, obox, pbox, nbox, seeds, K, f,
+                     bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar,
+                     flags);
   return hipGetLastError();
 }
 

@@ -438,21 +438,15 @@ __device__ __forceinline__ void record_refine(int it, double omega, int* iters,
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void __launch_bounds__(64) k_basis32(Geo g, const Box* __restrict__ boxes,
-                                                const Seed* __restrict__ seeds,
-                                                const double* __restrict__ K, double beta,
-                                                float* __restrict__ fac32,
-                                                double* __restrict__ Pk,
-                                                double* __restrict__ tr_u,
-                                                double* __restrict__ tr_phi,
-                                                double* __restrict__ tr_beta, double tol,
-                                                int max_refine, int* iters,
-                                                unsigned long long* resid, int* flags) {
-  extern __shared__ __align__(16) double dsm[];
-  __shared__ WaveSmemF sm;
-  const Box B = boxes[blockIdx.x];
+// Steps 1-2 on an oversampled box: FP32 factor, seeds refined to tol.
+__device__ __forceinline__ void basis32_box(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
+                                            const double* __restrict__ K, double beta,
+                                            float* __restrict__ fac32, double* __restrict__ Pk,
+                                            double* __restrict__ tr_u, double* __restrict__ tr_phi,
+                                            double* __restrict__ tr_beta, double tol, int max_refine,
+                                            int* iters, unsigned long long* resid, double* dsm,
+                                            WaveSmemF& sm) {
   const int L = lane_id();
-  if (L == 0) sm.flag = 0;
   const int nrhs = B.nrhs;
   BoxR R = carve_r(dsm, B, max(nrhs, 1), 0);
   load_box(g, B, K, beta, R.b);
@@ -507,25 +501,18 @@ __global__ void __launch_bounds__(64) k_basis32(Geo g, const Box* __restrict__ b
       if (k == 0) tr_beta[(long long)B.sub * g.gstride + g.gside_off[q] + t] = bt;
     }
   }
-  wsync();
-  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-__global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restrict__ boxes,
-                                                     const double* __restrict__ K,
-                                                     const double* __restrict__ f,
-                                                     const double* __restrict__ bcv, double beta,
-                                                     float* __restrict__ fac32,
-                                                     double* __restrict__ pbar,
-                                                     double* __restrict__ ubar,
-                                                     double* __restrict__ pibar, double tol,
-                                                     int max_refine, int* iters,
-                                                     unsigned long long* resid, int* flags) {
-  extern __shared__ __align__(16) double dsm[];
-  __shared__ WaveSmemF sm;
-  const Box B = boxes[blockIdx.x];
+// Step 4 on a subdomain: FP32 factor, particular solution refined to tol.
+__device__ __forceinline__ void particular32_box(const Geo& g, const Box& B, const double* __restrict__ K,
+                                                 const double* __restrict__ f,
+                                                 const double* __restrict__ bcv, double beta,
+                                                 float* __restrict__ fac32, double* __restrict__ pbar,
+                                                 double* __restrict__ ubar, double* __restrict__ pibar,
+                                                 double tol, int max_refine, int* iters,
+                                                 unsigned long long* resid, double* dsm,
+                                                 WaveSmemF& sm) {
   const int L = lane_id();
-  if (L == 0) sm.flag = 0;
   BoxR R = carve_r(dsm, B, 1, 1);
   load_box(g, B, K, beta, R.b);
   scale_box(B, R);
@@ -559,6 +546,42 @@ __global__ void __launch_bounds__(64) k_particular32(Geo g, const Box* __restric
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
     }
+  }
+}
+
+// Steps 1-2 and 4 in one launch: workgroups [0, nbox) take the oversampled
+// boxes, workgroups [nbox, 2 nbox) the particular problems.  The two sets are
+// independent and run side by side.
+__global__ void __launch_bounds__(64) k_local32(Geo g, const Box* __restrict__ obox,
+                                                const Box* __restrict__ pbox, int nbox,
+                                                const Seed* __restrict__ seeds,
+                                                const double* __restrict__ K,
+                                                const double* __restrict__ f,
+                                                const double* __restrict__ bcv, double beta,
+                                                float* __restrict__ fac32,
+                                                float* __restrict__ facp32,
+                                                double* __restrict__ Pk,
+                                                double* __restrict__ tr_u,
+                                                double* __restrict__ tr_phi,
+                                                double* __restrict__ tr_beta,
+                                                double* __restrict__ pbar,
+                                                double* __restrict__ ubar,
+                                                double* __restrict__ pibar, double tol,
+                                                int max_refine, int* iters,
+                                                unsigned long long* resid, int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmemF sm;
+  const int L = lane_id();
+  if (L == 0) sm.flag = 0;
+  const int b = blockIdx.x;
+  if (b < nbox) {
+    const Box B = obox[b];
+    basis32_box(g, B, seeds, K, beta, fac32, Pk, tr_u, tr_phi, tr_beta, tol, max_refine, iters,
+                resid, dsm, sm);
+  } else {
+    const Box B = pbox[b - nbox];
+    particular32_box(g, B, K, f, bcv, beta, facp32, pbar, ubar, pibar, tol, max_refine, iters,
+                     resid, dsm, sm);
   }
   wsync();
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
@@ -624,29 +647,18 @@ size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs) { return boxr_bytes
 
 size_t wave32_smooth_lds_bytes(int m0, int m1) { return smooth32_lds_bytes(m0, m1); }
 
-hipError_t launch_basis32_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
-                            const double* K, double beta, float* fac32, double* Pk, double* tr_u,
-                            double* tr_phi, double* tr_beta, double tol, int max_refine,
-                            int* iters, unsigned long long* resid, int* flags, size_t lds,
-                            hipStream_t s) {
+hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
+                            const Seed* seeds, const double* K, const double* f, const double* bcv,
+                            double beta, float* fac32, float* facp32, double* Pk, double* tr_u,
+                            double* tr_phi, double* tr_beta, double* pbar, double* ubar,
+                            double* pibar, double tol, int max_refine, int* iters,
+                            unsigned long long* resid, int* flags, size_t lds, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
-  hipError_t e = set_lds(k_basis32, lds);
+  hipError_t e = set_lds(k_local32, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_basis32, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac32, Pk,
-                     tr_u, tr_phi, tr_beta, tol, max_refine, iters, resid, flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_particular32_w(const Geo& g, const Box* boxes, int nbox, const double* K,
-                                 const double* f, const double* bcv, double beta, float* fac32,
-                                 double* pbar, double* ubar, double* pibar, double tol,
-                                 int max_refine, int* iters, unsigned long long* resid,
-                                 int* flags, size_t lds, hipStream_t s) {
-  if (nbox <= 0) return hipSuccess;
-  hipError_t e = set_lds(k_particular32, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_particular32, dim3(nbox), dim3(64), lds, s, g, boxes, K, f, bcv, beta, fac32,
-                     pbar, ubar, pibar, tol, max_refine, iters, resid, flags);
+  hipLaunchKernelGGL(k_local32, dim3(2 * nbox), dim3(64), lds, s, g, obox, pbox, nbox, seeds, K, f,
+                     bcv, beta, fac32, facp32, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar, tol,
+                     max_refine, iters, resid, flags);
   return hipGetLastError();
 }
 

@@ -110,14 +110,13 @@ hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int
 // one-wavefront-per-box 2-D kernels (local_wave.hip), blocks of <= 32 cells
 size_t wave_lds_bytes(int m0, int m1, int nrhs);
 size_t wave_smooth_lds_bytes(int m0, int m1);
-hipError_t launch_basis_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
-                          const double* K, double beta, double* fac, double* tcoup, double* scr,
-                          double* Pk, double* tr_u, double* tr_phi, double* tr_beta, int* flags,
-                          size_t lds, hipStream_t s);
-hipError_t launch_particular_w(const Geo& g, const Box* boxes, int nbox, const double* K,
-                               const double* f, const double* bcv, double beta, double* fac,
-                               double* tcoup, double* scr, double* pbar, double* ubar,
-                               double* pibar, int* flags, size_t lds, hipStream_t s);
+// Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox) in one
+// launch of 2 nbox workgroups; lds = the larger of the two boxes' needs.
+hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
+                          const Seed* seeds, const double* K, const double* f, const double* bcv,
+                          double beta, double* fac, double* tcoup, double* facp, double* tcp,
+                          double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
+                          double* ubar, double* pibar, int* flags, size_t lds, hipStream_t s);
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* tcoup, double* scr, double* p,
@@ -126,16 +125,12 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);
 size_t wave32_smooth_lds_bytes(int m0, int m1);
-hipError_t launch_basis32_w(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
-                            const double* K, double beta, float* fac32, double* Pk, double* tr_u,
-                            double* tr_phi, double* tr_beta, double tol, int max_refine,
-                            int* iters, unsigned long long* resid, int* flags, size_t lds,
-                            hipStream_t s);
-hipError_t launch_particular32_w(const Geo& g, const Box* boxes, int nbox, const double* K,
-                                 const double* f, const double* bcv, double beta, float* fac32,
-                                 double* pbar, double* ubar, double* pibar, double tol,
-                                 int max_refine, int* iters, unsigned long long* resid,
-                                 int* flags, size_t lds, hipStream_t s);
+hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
+                            const Seed* seeds, const double* K, const double* f, const double* bcv,
+                            double beta, float* fac32, float* facp32, double* Pk, double* tr_u,
+                            double* tr_phi, double* tr_beta, double* pbar, double* ubar,
+                            double* pibar, double tol, int max_refine, int* iters,
+                            unsigned long long* resid, int* flags, size_t lds, hipStream_t s);
 hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
                              const float* fac32, double* p, double* gflux, double tol,
