@@ -19,11 +19,7 @@ namespace {
 
 using namespace wave;
 
-struct __align__(16) WaveSmemF {
-  float row[2][NBW];
-  float col[2][NBW];
-  int flag;
-};
+using WaveSmemF = GjSmem<float>;
 
 // LDS of one box for the refinement kernels.
 struct BoxR {
@@ -110,49 +106,7 @@ __device__ __forceinline__ void wbuild32(int nb, int j, const BoxR& R, float w[H
   }
 }
 
-__device__ __forceinline__ void wgj32(int nb, WaveSmemF& sm, float w[HB]) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-  for (int k0 = 0; k0 < NBW; k0 += HB) {
-    if (k0 >= nb) break;
-    const bool own_half = h == (k0 >> 4);
-#pragma unroll
-    for (int kk = 0; kk < HB; ++kk) {
-      const int k = k0 + kk;
-      if (k >= nb) break;
-      float* rk = sm.row[kk & 1];
-      float* ck = sm.col[kk & 1];
-      if (own_half) rk[c] = w[kk];
-      if (c == k) {
-        float4* d = reinterpret_cast<float4*>(ck + HB * h);
-#pragma unroll
-        for (int i = 0; i < HB / 4; ++i) d[i] = make_float4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
-      }
-      wsync();
-      const float a = rk[c];
-      const float piv = rk[k];
-      if (!(piv > 0.0f) && L == 0) sm.flag |= kFlagNotPD;
-      const float ip = 1.0f / piv;
-      const float f = (c == k) ? 0.0f : -(a * ip);
-      const float4* cs = reinterpret_cast<const float4*>(ck + HB * h);
-#pragma unroll
-      for (int i = 0; i < HB / 4; ++i) {
-        const float4 v = cs[i];
-        w[4 * i] = fmaf(f, v.x, w[4 * i]);
-        w[4 * i + 1] = fmaf(f, v.y, w[4 * i + 1]);
-        w[4 * i + 2] = fmaf(f, v.z, w[4 * i + 2]);
-        w[4 * i + 3] = fmaf(f, v.w, w[4 * i + 3]);
-      }
-      if (c == k) {
-        const float m = -ip;
-#pragma unroll
-        for (int i = 0; i < HB; ++i) w[i] *= m;
-      }
-      if (own_half) w[kk] = (c == k) ? ip : a * ip;
-    }
-  }
-  wsync();
-}
+__device__ __forceinline__ void wgj32(int nb, WaveSmemF& sm, float w[HB]) { wgj_blk<float>(nb, sm, w); }
 
 // W_j z with 128-bit LDS reads, two FMA chains and the half-wave swap sum.
 __device__ __forceinline__ float wgemv2f(const float w[HB], const float* z) {

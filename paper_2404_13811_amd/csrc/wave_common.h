@@ -12,11 +12,17 @@ constexpr int NBW = 32;
 constexpr int HB = 16;
 constexpr int RING = 4;
 
-struct __align__(16) WaveSmem {
-  double row[2][NBW];
-  double col[2][NBW];
+constexpr int GJB = 4;  // pivots per Gauss-Jordan step
+
+// Pivot rows and columns of one Gauss-Jordan step (two alternating buffers):
+// rowb[c * GJB + m] = A[k + m][c], colb[m * NBW + r] = A[r][k + m].
+template <typename T>
+struct __align__(16) GjSmem {
+  T rowb[2][NBW * GJB];
+  T colb[2][GJB * NBW];
   int flag;
 };
+using WaveSmem = GjSmem<double>;
 
 // Dynamic LDS carve-up of one box.
 struct BoxLds {
@@ -277,54 +283,123 @@ __device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[
   }
 }
 
-// In-place Gauss-Jordan inversion of the block held in w.  Each step
-// publishes pivot row k (one element per lane of the owning half) and pivot
-// column k (the 16 registers of the two lanes holding column k) to LDS.
-// Every lane applies the rank-1 update; the two lanes of column k (which
-// hold the pivot column itself, left unchanged by a zero multiplier) then
-// scale it to -v / pivot, and the owning half rewrites row k.
-__device__ __forceinline__ void wgj(int nb, WaveSmem& sm, double w[HB]) {
+__device__ __forceinline__ double rcp_t(double x) { return rcp_d(x); }
+__device__ __forceinline__ float rcp_t(float x) { return 1.0f / x; }
+
+// v = P^{-1} r for a 4 x 4 pivot block P = [[a, b], [e, d]] (2 x 2 blocks),
+// by the block elimination y = a^{-1} r1, E = a^{-1} b, S = d - e E,
+// v2 = S^{-1} (r2 - e y), v1 = y - E v2.  The four pivots of that elimination
+// are P00, det(a) / P00, S00 and det(S) / S00; ok says whether all are > 0.
+template <typename T>
+struct PivBlock {
+  T ai[2][2], E[2][2], e[2][2], si[2][2];
+  bool ok;
+};
+
+template <typename T>
+__device__ __forceinline__ PivBlock<T> piv_block(const T P[GJB][GJB]) {
+  PivBlock<T> q;
+  const T da = P[0][0] * P[1][1] - P[0][1] * P[1][0];
+  const T ia = rcp_t(da);
+  q.ai[0][0] = P[1][1] * ia;
+  q.ai[0][1] = -P[0][1] * ia;
+  q.ai[1][0] = -P[1][0] * ia;
+  q.ai[1][1] = P[0][0] * ia;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      q.E[i][j] = q.ai[i][0] * P[0][2 + j] + q.ai[i][1] * P[1][2 + j];
+      q.e[i][j] = P[2 + i][j];
+    }
+  T S[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) S[i][j] = P[2 + i][2 + j] - (q.e[i][0] * q.E[0][j] + q.e[i][1] * q.E[1][j]);
+  const T ds = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+  const T is = rcp_t(ds);
+  q.si[0][0] = S[1][1] * is;
+  q.si[0][1] = -S[0][1] * is;
+  q.si[1][0] = -S[1][0] * is;
+  q.si[1][1] = S[0][0] * is;
+  q.ok = P[0][0] > T(0) && da > T(0) && S[0][0] > T(0) && ds > T(0);
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ void piv_apply(const PivBlock<T>& q, const T r[GJB], T v[GJB]) {
+  const T y0 = q.ai[0][0] * r[0] + q.ai[0][1] * r[1];
+  const T y1 = q.ai[1][0] * r[0] + q.ai[1][1] * r[1];
+  const T z0 = r[2] - (q.e[0][0] * y0 + q.e[0][1] * y1);
+  const T z1 = r[3] - (q.e[1][0] * y0 + q.e[1][1] * y1);
+  v[2] = q.si[0][0] * z0 + q.si[0][1] * z1;
+  v[3] = q.si[1][0] * z0 + q.si[1][1] * z1;
+  v[0] = y0 - (q.E[0][0] * v[2] + q.E[0][1] * v[3]);
+  v[1] = y1 - (q.E[1][0] * v[2] + q.E[1][1] * v[3]);
+}
+
+// In-place Gauss-Jordan inversion of the block held in w, GJB pivots per
+// step (block Gauss-Jordan without pivoting).  For the pivot set K with
+// block P = A[K][K], rows R = A[K][:] and columns C = A[:][K], one step
+// replaces A[K][j] by P^{-1} A[K][j], A[i][K] by -A[i][K] P^{-1}, A[K][K] by
+// P^{-1} and the rest by A - C P^{-1} R: the result of GJB single pivots.
+// Lane (c, h) forms v = P^{-1} r with r = A[K][c] (or the unit vector of c
+// when c is in K), then updates its 16 rows with the columns C from LDS.
+// The owning half writes the pivot rows and the lanes of the pivot columns
+// write those columns: one LDS round trip per GJB pivots.  Lines shorter than
+// NBW carry identity padding, which a pivot step leaves unchanged.
+template <typename T>
+__device__ __forceinline__ void wgj_blk(int nb, GjSmem<T>& sm, T w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
-  // pivots in two halves of 16 so that the register index kk is static
   for (int k0 = 0; k0 < NBW; k0 += HB) {
     if (k0 >= nb) break;
     const bool own_half = h == (k0 >> 4);
 #pragma unroll
-    for (int kk = 0; kk < HB; ++kk) {
-      const int k = k0 + kk;
+    for (int kb = 0; kb < HB; kb += GJB) {
+      const int k = k0 + kb;
       if (k >= nb) break;
-      double* rk = sm.row[kk & 1];
-      double* ck = sm.col[kk & 1];
-      if (own_half) rk[c] = w[kk];
-      if (c == k) {
-        double2* d = reinterpret_cast<double2*>(ck + HB * h);
+      T* rb = sm.rowb[(kb / GJB) & 1];
+      T* cb = sm.colb[(kb / GJB) & 1];
+      const int ck = c - k;
+      const bool pc = ck >= 0 && ck < GJB;
+      if (own_half) {
 #pragma unroll
-        for (int i = 0; i < HB / 2; ++i) d[i] = make_double2(w[2 * i], w[2 * i + 1]);
+        for (int m = 0; m < GJB; ++m) rb[GJB * c + m] = w[kb + m];
+      }
+      if (pc) {
+#pragma unroll
+        for (int i = 0; i < HB; ++i) cb[ck * NBW + HB * h + i] = w[i];
       }
       wsync();
-      const double a = rk[c];
-      const double piv = rk[k];
-      if (!(piv > 0.0) && L == 0) sm.flag |= kFlagNotPD;
-      const double ip = rcp_d(piv);
-      const double f = (c == k) ? 0.0 : -(a * ip);
-      const double2* cs = reinterpret_cast<const double2*>(ck + HB * h);
+      T P[GJB][GJB], r[GJB], v[GJB];
 #pragma unroll
-      for (int i = 0; i < HB / 2; ++i) {
-        const double2 v = cs[i];
-        w[2 * i] = fma(f, v.x, w[2 * i]);
-        w[2 * i + 1] = fma(f, v.y, w[2 * i + 1]);
-      }
-      if (c == k) {
-        const double m = -ip;
+      for (int j = 0; j < GJB; ++j)
 #pragma unroll
-        for (int i = 0; i < HB; ++i) w[i] *= m;
+        for (int m = 0; m < GJB; ++m) P[m][j] = rb[GJB * (k + j) + m];
+#pragma unroll
+      for (int m = 0; m < GJB; ++m) r[m] = pc ? (ck == m ? T(1) : T(0)) : rb[GJB * c + m];
+      const PivBlock<T> q = piv_block(P);
+      if (!q.ok && L == 0) sm.flag |= kFlagNotPD;
+      piv_apply(q, r, v);
+#pragma unroll
+      for (int i = 0; i < HB; ++i) {
+        T acc = pc ? T(0) : w[i];
+#pragma unroll
+        for (int m = 0; m < GJB; ++m) acc = fma(-cb[m * NBW + HB * h + i], v[m], acc);
+        w[i] = acc;
       }
-      if (own_half) w[kk] = (c == k) ? ip : a * ip;
+      if (own_half) {
+#pragma unroll
+        for (int m = 0; m < GJB; ++m) w[kb + m] = v[m];
+      }
     }
   }
   wsync();
 }
+
+__device__ __forceinline__ void wgj(int nb, WaveSmem& sm, double w[HB]) { wgj_blk<double>(nb, sm, w); }
 
 __device__ __forceinline__ void womega(const Geo& g, int sub, int lo[3], int hi[3]) {
   const int ix = sub % g.M[0], iy = sub / g.M[0];
