@@ -17,113 +17,153 @@
 // factors F, G kept for the back substitution in slots the host schedule
 // assigns) and a pool of 3M vectors [r | g | x].
 #include "mrcm_internal.h"
+#include "pivot4.h"
 
 namespace mrcm {
 namespace {
 
 // ------------------------------------------------------------------ inverse
-// In-place Gauss-Jordan inversion of one bp x bp block per workgroup; each
-// thread holds an 8 x 8 tile in registers; the pivot row and column go
-// through LDS (double buffered: one barrier per pivot), interleaved so that
-// the 16-byte pieces read by neighbouring threads are adjacent (no bank
-// conflicts).  The generic update
-// is a rank-1 FMA on every tile; the owners of the pivot row / column then
-// overwrite those entries (uniform per unrolled pivot, so no selects).
-constexpr int IT = 8;
+// In-place Gauss-Jordan inversion of one n x n block (n <= 128, n % 8 == 0)
+// per workgroup of 512 threads; thread (tr, tc) holds the 8 x 4 tile at rows
+// 8 tr.., columns 4 tc.. in registers.  Pivots are taken four at a time
+// (block Gauss-Jordan without pivoting): for the pivot rows and columns K,
+// with P = A[K][K],
+//   A[K][j] <- P^{-1} A[K][j],   A[i][K] <- -A[i][K] P^{-1},
+//   A[K][K] <- P^{-1},           A[i][j] <- A[i][j] - A[i][K] P^{-1} A[K][j],
+// which equals four scalar pivot steps.  One step:
+//   1. the owners of rows K and of columns K (one tile column) publish them
+//      to LDS (barrier);
+//   2. every thread factors the 4 x 4 block P (closed form, no exchange)
+//      and thread t < n forms column t of R = P^{-1} A~[K][:], where A~
+//      has unit vectors in the columns K (barrier);
+//   3. every thread applies the rank-4 update A[i][j] <- A[i][j] -
+//      A[i][K] R[:, j] to its tile (zero base in the columns K) and the
+//      owners of rows K take R.
+// The LDS buffers alternate between steps, so two barriers per four
+// pivots.  R is stored in 16-byte pieces interleaved over the tile columns
+// so that the update reads are free of bank conflicts.  Two waves per SIMD
+// hide each other's LDS latency.
+constexpr int TR = 8, PB = 4;  // tile rows; pivots per step = tile columns
+constexpr int kInvThreads = 512;
 
-// Reciprocal by the hardware estimate refined with two Newton steps (the
-// pivots are normal numbers; the result is within an ulp of 1/x).
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-template <int NT>
-__global__ void __launch_bounds__(NT) k_bcr_inv(double* __restrict__ pool,
-                                                const long long* __restrict__ offs, int bp, int ld,
-                                                int* flags) {
-  __shared__ __align__(16) double rowb[2][kBcrInvMax];
-  __shared__ __align__(16) double colb[2][kBcrInvMax];
-  __shared__ double ipb[2];
+__global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ pool,
+                                                         const long long* __restrict__ offs, int bp,
+                                                         int ld, int* flags) {
+  __shared__ __align__(16) double rpan[2][PB * kBcrInvMax];  // [m][col] = A[k + m][col]
+  __shared__ __align__(16) double cpan[2][kBcrInvMax * PB];  // [row][m] = A[row][k + m]
+  __shared__ __align__(16) double rpp[2][PB * kBcrInvMax];   // R, interleaved pieces
   double* A = pool + offs[blockIdx.x];
-  const int nt = bp / IT;  // tiles per dimension
+  const int ntr = bp / TR, ntc = bp / PB;  // tiles per column / per row
   const int t = threadIdx.x;
-  const bool act = t < nt * nt;
-  const int tr = act ? t / nt : -1, tc = act ? t - (t / nt) * nt : -1;
-  const int r0 = tr * IT, c0 = tc * IT;
-  double w[IT][IT];
+  const bool act = t < ntr * ntc;
+  const int tr = act ? t / ntc : -1, tc = act ? t - (t / ntc) * ntc : -1;
+  const int r0 = tr * TR, c0 = tc * PB;
+  double w[TR][PB];
   if (act) {
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
+    for (int i = 0; i < TR; ++i) {
       const double2* src = reinterpret_cast<const double2*>(A + (long long)(r0 + i) * ld + c0);
-#pragma unroll
-      for (int j = 0; j < IT / 2; ++j) {
-        const double2 v = src[j];
-        w[i][2 * j] = v.x;
-        w[i][2 * j + 1] = v.y;
-      }
+      const double2 u = src[0], v = src[1];
+      w[i][0] = u.x;
+      w[i][1] = u.y;
+      w[i][2] = v.x;
+      w[i][3] = v.y;
     }
   }
-  int bad = 0;
-  for (int kb = 0; kb < nt; ++kb) {
-    const bool own_r = tr == kb, own_c = tc == kb;
+  bool bad = false;
+  for (int kt = 0; kt < ntr; ++kt) {
+    const bool own_r = tr == kt;
 #pragma unroll
-    for (int kk = 0; kk < IT; ++kk) {
-      double* rk = rowb[kk & 1];
-      double* ck = colb[kk & 1];
+    for (int k2 = 0; k2 < TR; k2 += PB) {
+      const int k = kt * TR + k2;
+      const bool own_c = c0 == k;
+      double* rp = rpan[k2 / PB];
+      double* cp = cpan[k2 / PB];
+      double* rq = rpp[k2 / PB];
       if (own_r) {
-        double2* d = reinterpret_cast<double2*>(rk);
 #pragma unroll
-        for (int j = 0; j < IT / 2; ++j) d[j * nt + tc] = make_double2(w[kk][2 * j], w[kk][2 * j + 1]);
-        if (own_c) {
-          const double piv = w[kk][kk];
-          bad |= !(piv != 0.0);
-          ipb[kk & 1] = recip(piv);
+        for (int m = 0; m < PB; ++m) {
+          double2* d = reinterpret_cast<double2*>(rp + m * kBcrInvMax + c0);
+          d[0] = make_double2(w[k2 + m][0], w[k2 + m][1]);
+          d[1] = make_double2(w[k2 + m][2], w[k2 + m][3]);
         }
       }
       if (own_c) {
-        double2* d = reinterpret_cast<double2*>(ck);
 #pragma unroll
-        for (int i = 0; i < IT / 2; ++i) d[i * nt + tr] = make_double2(w[2 * i][kk], w[2 * i + 1][kk]);
+        for (int i = 0; i < TR; ++i) {
+          double2* d = reinterpret_cast<double2*>(cp + (r0 + i) * PB);
+          d[0] = make_double2(w[i][0], w[i][1]);
+          d[1] = make_double2(w[i][2], w[i][3]);
+        }
       }
       __syncthreads();
-      if (!act) continue;
-      const double ip = ipb[kk & 1];
-      double rv[IT], cv[IT];
-      const double2* rs = reinterpret_cast<const double2*>(rk);
-      const double2* cs = reinterpret_cast<const double2*>(ck);
+      if (t < bp) {
+        double P[PB][PB];
 #pragma unroll
-      for (int j = 0; j < IT / 2; ++j) {
-        const double2 a = rs[j * nt + tc], b = cs[j * nt + tr];
-        rv[2 * j] = a.x;
-        rv[2 * j + 1] = a.y;
-        cv[2 * j] = -b.x * ip;
-        cv[2 * j + 1] = -b.y * ip;
+        for (int m = 0; m < PB; ++m)
+#pragma unroll
+          for (int j = 0; j < PB; ++j) P[m][j] = rp[m * kBcrInvMax + k + j];
+        const PivBlock<double> q = piv_block(P);
+        bad |= !(q.d0 != 0.0 && q.da != 0.0 && q.s0 != 0.0 && q.ds != 0.0);
+        const int ck = t - k;
+        const bool pc = ck >= 0 && ck < PB;
+        double r[PB], v[PB];
+        // unit vector in the pivot columns, formed arithmetically (a select
+        // on a load becomes a branch with its own LDS wait)
+#pragma unroll
+        for (int m = 0; m < PB; ++m)
+          r[m] = fma(rp[m * kBcrInvMax + t], pc ? 0.0 : 1.0, (pc && ck == m) ? 1.0 : 0.0);
+        piv_apply(q, r, v);
+        const int tq = t / PB, jj = (t % PB) / 2, e = t & 1;
+#pragma unroll
+        for (int m = 0; m < PB; ++m) rq[((m * 2 + jj) * ntc + tq) * 2 + e] = v[m];
       }
+      __syncthreads();
+      if (act) {
+        double rv[PB][PB], cv[TR][PB];
+        const double2* q2 = reinterpret_cast<const double2*>(rq);
 #pragma unroll
-      for (int i = 0; i < IT; ++i)
+        for (int m = 0; m < PB; ++m)
 #pragma unroll
-        for (int j = 0; j < IT; ++j) w[i][j] = fma(cv[i], rv[j], w[i][j]);
-      if (own_r) {
+          for (int jj = 0; jj < 2; ++jj) {
+            const double2 x = q2[(m * 2 + jj) * ntc + tc];
+            rv[m][2 * jj] = x.x;
+            rv[m][2 * jj + 1] = x.y;
+          }
 #pragma unroll
-        for (int j = 0; j < IT; ++j) w[kk][j] = rv[j] * ip;
-      }
-      if (own_c) {
+        for (int i = 0; i < TR; ++i) {
+          const double2* s2 = reinterpret_cast<const double2*>(cp + (r0 + i) * PB);
+          const double2 a = s2[0], b = s2[1];
+          cv[i][0] = a.x;
+          cv[i][1] = a.y;
+          cv[i][2] = b.x;
+          cv[i][3] = b.y;
+        }
+        const double base = own_c ? 0.0 : 1.0;
 #pragma unroll
-        for (int i = 0; i < IT; ++i) w[i][kk] = cv[i];
-        if (own_r) w[kk][kk] = ip;
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+          for (int j = 0; j < PB; ++j) {
+            double acc = w[i][j] * base;
+#pragma unroll
+            for (int m = 0; m < PB; ++m) acc = fma(-cv[i][m], rv[m][j], acc);
+            w[i][j] = acc;
+          }
+        if (own_r) {
+#pragma unroll
+          for (int m = 0; m < PB; ++m)
+#pragma unroll
+            for (int j = 0; j < PB; ++j) w[k2 + m][j] = rv[m][j];
+        }
       }
     }
   }
   if (act) {
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
+    for (int i = 0; i < TR; ++i) {
       double2* dst = reinterpret_cast<double2*>(A + (long long)(r0 + i) * ld + c0);
-#pragma unroll
-      for (int j = 0; j < IT / 2; ++j) dst[j] = make_double2(w[i][2 * j], w[i][2 * j + 1]);
+      dst[0] = make_double2(w[i][0], w[i][1]);
+      dst[1] = make_double2(w[i][2], w[i][3]);
     }
   }
   if (bad) atomicOr(flags, kFlagSingular);
@@ -288,8 +328,8 @@ __global__ void k_bcr_gather(const double* __restrict__ xv, const int* __restric
 hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
                           hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
-  if (n % IT || n > kBcrInvMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bcr_inv<256>, dim3(nblk), dim3(256), 0, s, pool, offs, n, ld, flags);
+  if (n % TR || n > kBcrInvMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bcr_inv, dim3(nblk), dim3(kInvThreads), 0, s, pool, offs, n, ld, flags);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 // geometry helpers.  See local_wave.hip for the algorithm.
 #pragma once
 #include "local_common.h"
+#include "pivot4.h"
 
 namespace mrcm {
 namespace wave {
@@ -12,7 +13,7 @@ constexpr int NBW = 32;
 constexpr int HB = 16;
 constexpr int RING = 4;
 
-constexpr int GJB = 4;  // pivots per Gauss-Jordan step
+constexpr int GJB = 4;  // pivots per Gauss-Jordan step (one 4 x 4 pivot block)
 
 // Pivot rows and columns of one Gauss-Jordan step (two alternating buffers):
 // rowb[c * GJB + m] = A[k + m][c], colb[m * NBW + r] = A[r][k + m].
@@ -283,62 +284,6 @@ __device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[
   }
 }
 
-__device__ __forceinline__ double rcp_t(double x) { return rcp_d(x); }
-__device__ __forceinline__ float rcp_t(float x) { return 1.0f / x; }
-
-// v = P^{-1} r for a 4 x 4 pivot block P = [[a, b], [e, d]] (2 x 2 blocks),
-// by the block elimination y = a^{-1} r1, E = a^{-1} b, S = d - e E,
-// v2 = S^{-1} (r2 - e y), v1 = y - E v2.  The four pivots of that elimination
-// are P00, det(a) / P00, S00 and det(S) / S00; ok says whether all are > 0.
-template <typename T>
-struct PivBlock {
-  T ai[2][2], E[2][2], e[2][2], si[2][2];
-  bool ok;
-};
-
-template <typename T>
-__device__ __forceinline__ PivBlock<T> piv_block(const T P[GJB][GJB]) {
-  PivBlock<T> q;
-  const T da = P[0][0] * P[1][1] - P[0][1] * P[1][0];
-  const T ia = rcp_t(da);
-  q.ai[0][0] = P[1][1] * ia;
-  q.ai[0][1] = -P[0][1] * ia;
-  q.ai[1][0] = -P[1][0] * ia;
-  q.ai[1][1] = P[0][0] * ia;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      q.E[i][j] = q.ai[i][0] * P[0][2 + j] + q.ai[i][1] * P[1][2 + j];
-      q.e[i][j] = P[2 + i][j];
-    }
-  T S[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) S[i][j] = P[2 + i][2 + j] - (q.e[i][0] * q.E[0][j] + q.e[i][1] * q.E[1][j]);
-  const T ds = S[0][0] * S[1][1] - S[0][1] * S[1][0];
-  const T is = rcp_t(ds);
-  q.si[0][0] = S[1][1] * is;
-  q.si[0][1] = -S[0][1] * is;
-  q.si[1][0] = -S[1][0] * is;
-  q.si[1][1] = S[0][0] * is;
-  q.ok = P[0][0] > T(0) && da > T(0) && S[0][0] > T(0) && ds > T(0);
-  return q;
-}
-
-template <typename T>
-__device__ __forceinline__ void piv_apply(const PivBlock<T>& q, const T r[GJB], T v[GJB]) {
-  const T y0 = q.ai[0][0] * r[0] + q.ai[0][1] * r[1];
-  const T y1 = q.ai[1][0] * r[0] + q.ai[1][1] * r[1];
-  const T z0 = r[2] - (q.e[0][0] * y0 + q.e[0][1] * y1);
-  const T z1 = r[3] - (q.e[1][0] * y0 + q.e[1][1] * y1);
-  v[2] = q.si[0][0] * z0 + q.si[0][1] * z1;
-  v[3] = q.si[1][0] * z0 + q.si[1][1] * z1;
-  v[0] = y0 - (q.E[0][0] * v[2] + q.E[0][1] * v[3]);
-  v[1] = y1 - (q.E[1][0] * v[2] + q.E[1][1] * v[3]);
-}
-
 // In-place Gauss-Jordan inversion of the block held in w, GJB pivots per
 // step (block Gauss-Jordan without pivoting).  For the pivot set K with
 // block P = A[K][K], rows R = A[K][:] and columns C = A[:][K], one step
@@ -353,6 +298,7 @@ template <typename T>
 __device__ __forceinline__ void wgj_blk(int nb, GjSmem<T>& sm, T w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  bool bad = false;
   for (int k0 = 0; k0 < NBW; k0 += HB) {
     if (k0 >= nb) break;
     const bool own_half = h == (k0 >> 4);
@@ -378,10 +324,13 @@ __device__ __forceinline__ void wgj_blk(int nb, GjSmem<T>& sm, T w[HB]) {
       for (int j = 0; j < GJB; ++j)
 #pragma unroll
         for (int m = 0; m < GJB; ++m) P[m][j] = rb[GJB * (k + j) + m];
+      // r = unit vector (pivot-column lanes) or A[K][c], formed arithmetically:
+      // a select here becomes a branch per load, each with a full LDS wait
 #pragma unroll
-      for (int m = 0; m < GJB; ++m) r[m] = pc ? (ck == m ? T(1) : T(0)) : rb[GJB * c + m];
+      for (int m = 0; m < GJB; ++m)
+        r[m] = fma(rb[GJB * c + m], pc ? T(0) : T(1), (pc && ck == m) ? T(1) : T(0));
       const PivBlock<T> q = piv_block(P);
-      if (!q.ok && L == 0) sm.flag |= kFlagNotPD;
+      bad |= !(q.d0 > T(0) && q.da > T(0) && q.s0 > T(0) && q.ds > T(0));
       piv_apply(q, r, v);
 #pragma unroll
       for (int i = 0; i < HB; ++i) {
@@ -396,6 +345,7 @@ __device__ __forceinline__ void wgj_blk(int nb, GjSmem<T>& sm, T w[HB]) {
       }
     }
   }
+  if (bad && L == 0) sm.flag |= kFlagNotPD;
   wsync();
 }
 
