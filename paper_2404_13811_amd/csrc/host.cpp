@@ -70,6 +70,7 @@ struct mrcm_ctx {
 
   // device workspace
   double *fac = nullptr, *facs = nullptr, *facp = nullptr, *scr = nullptr;
+  double* fact = nullptr;  // twisted-sweep factors (backward inverses, meeting block), fac layout
   double *tco = nullptr, *tcp = nullptr;  // block couplings of the boxes / subdomains
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
   size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
@@ -159,7 +160,7 @@ void drop_graph(mrcm_ctx* c);
 void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
   dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members);
-  dfree(c->fac); dfree(c->facs); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
+  dfree(c->fac); dfree(c->fact); dfree(c->facs); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
   dfree(c->fac32); dfree(c->facp32); dfree(c->d_iters); dfree(c->d_resid);
   dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
   dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
@@ -655,6 +656,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->d_ifc, c->ifc.size());
   ALLOC(c->d_members, c->members.size());
   ALLOC(c->fac, c->fac_n);
+  ALLOC(c->fact, c->fac_n);
   ALLOC(c->facp, c->facp_n);
   ALLOC(c->scr, c->scr_n);
   ALLOC(c->tco, c->scro_n);
@@ -955,8 +957,8 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_local_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
                              c->bcv, c->beta_mbf, c->fac, c->tco, c->facp, c->tcp, c->Pk, c->tr_u,
-                             c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->flags,
-                             std::max(c->lds_basis, c->lds_part), s));
+                             c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->fact,
+                             c->flags, std::max(c->lds_basis, c->lds_part), s));
     HIPCHK(c, hipEventRecord(c->ev[9], s));
   } else {
     HIPCHK(c, hipEventRecord(c->ev[8], s));
@@ -1028,8 +1030,8 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
                                   c->d_iters, c->d_resid, c->flags, c->lds32_smooth, nt, s));
     } else if (c->wave) {
       HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
-                                c->beta_sm, c->fac, c->tco, c->scr, p, gflux, c->lds_smooth, nt,
-                                s));
+                                c->beta_sm, c->fac, c->fact, c->tco, c->scr, p, gflux,
+                                c->lds_smooth, nt, s));
     } else {
       HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
                               c->beta_sm, c->fac, nullptr, nullptr, c->scr, p, gflux, c->prec,

@@ -176,10 +176,70 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B, const
   }
 }
 
+// Factors of the twisted smoothing sweep for the oversampled box B: the
+// backward inverses W'_j = (D_j - t_j W'_{j+1} t_j)^{-1}, j = nblk-1 .. m+1,
+// and the meeting block Z_m = (S_m - t_m W'_{m+1} t_m)^{-1} with S_m the
+// forward Schur complement of block m (its forward chain is recomputed here
+// with the same arithmetic as the basis factorisation).  Each is stored at
+// its block's place in Wt; the blocks before m are not used.
+__device__ __forceinline__ void twist_box(const Geo& g, const Box& B, const double* __restrict__ K,
+                                          double beta, double* __restrict__ Wt, double* dsm,
+                                          WaveSmem& sm) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  BoxLds s = carve(dsm, B, 1);
+  load_box(g, B, K, beta, s);
+  wsync();
+  const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
+  double w[HB];
+#pragma unroll
+  for (int i = 0; i < HB; ++i) w[i] = 0.0;
+  for (int j = 0; j <= m; ++j) {
+    wbuild(nb, j, s, w);
+    if (j < m) wgj(nb, sm, w);
+  }
+  double sm_m[HB];
+#pragma unroll
+  for (int i = 0; i < HB; ++i) sm_m[i] = w[i];
+  for (int j = nblk - 1; j > m; --j) {
+    wbuild_t(nb, j, j < nblk - 1 ? j : -1, s, w);
+    wgj(nb, sm, w);
+    double* Wj = Wt + (long long)j * nb * nb;
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int r = HB * h + i;
+      if (r < nb && c < nb) Wj[r * nb + c] = w[i];
+    }
+  }
+  if (m < nblk - 1) {
+    // S_m - t_m W'_{m+1} t_m (identity padding kept)
+    const double* Tm = s.Tn + m * nb;
+    const double tc = c < nb ? Tm[c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int r = HB * h + i;
+      const double tr = r < nb ? Tm[r] : 0.0;
+      w[i] = (r < nb && c < nb) ? fma(-tr * tc, w[i], sm_m[i]) : sm_m[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < HB; ++i) w[i] = sm_m[i];
+  }
+  wgj(nb, sm, w);
+  double* Zm = Wt + (long long)m * nb * nb;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    if (r < nb && c < nb) Zm[r * nb + c] = w[i];
+  }
+}
+
 // Steps 1-2 and 4 in one launch.  Workgroups [0, nbox) handle the
 // oversampled boxes (factor, seeds, traces); workgroups [nbox, 2 nbox) handle
-// the particular problems on the subdomains.  The two sets share nothing, so
-// their waves run side by side instead of one launch after the other.
+// the particular problems on the subdomains and then, when fact is given,
+// the factors of the twisted smoothing sweep of the same subdomain's
+// oversampled box.  The two sets share nothing, so their waves run side by
+// side instead of one launch after the other.
 __global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ obox,
                                                 const Box* __restrict__ pbox, int nbox,
                                                 const Seed* __restrict__ seeds,
@@ -196,7 +256,8 @@ __global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ o
                                                 double* __restrict__ tr_beta,
                                                 double* __restrict__ pbar,
                                                 double* __restrict__ ubar,
-                                                double* __restrict__ pibar, int* flags) {
+                                                double* __restrict__ pibar,
+                                                double* __restrict__ fact, int* flags) {
   extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmem sm;
   const int L = lane_id();
@@ -208,6 +269,11 @@ __global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ o
   } else {
     const Box B = pbox[b - nbox];
     particular_box(g, B, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm);
+    if (fact) {
+      wsync();
+      const Box O = obox[b - nbox];
+      twist_box(g, O, K, beta, fact + O.fac, dsm, sm);
+    }
   }
   wsync();
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
@@ -215,8 +281,9 @@ __global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ o
 
 // Steps 6-7: one color phase of the smoothing sweep.  NT threads per box
 // (64, 128 or 256, chosen by the autotuner) stage the box's data, build the
-// right-hand side and write the outputs; the first wave runs the block
-// sweeps.  The result does not depend on NT.
+// right-hand side and write the outputs; the box solve is the twisted block
+// sweep, its two halves on the first two waves when NT >= 128.  The result
+// does not depend on NT.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ boxes,
                                                  const int* __restrict__ members,
@@ -224,6 +291,7 @@ __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ 
                                                  const double* __restrict__ f,
                                                  const double* __restrict__ bcv, double beta,
                                                  const double* __restrict__ fac,
+                                                 const double* __restrict__ fact,
                                                  const double* __restrict__ tcoup,
                                                  double* __restrict__ p,
                                                  double* __restrict__ gflux) {
@@ -233,8 +301,8 @@ __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ 
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
   bsync<NT>();
   smooth_rhs<NT>(g, B, r, beta, r.b.X);
-  if (threadIdx.x < 64) sweep1(B, fac + B.fac, r.b, r.b.Z);
   bsync<NT>();
+  sweep_twisted<NT>(B, fac + B.fac, fact + B.fac, r.b, r.b.Z);
   smooth_out<NT>(g, B, r, r.b.X, beta, p, gflux);
 }
 
@@ -258,28 +326,30 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
                           const Seed* seeds, const double* K, const double* f, const double* bcv,
                           double beta, double* fac, double* tcoup, double* facp, double* tcp,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
-                          double* ubar, double* pibar, int* flags, size_t lds, hipStream_t s) {
+                          double* ubar, double* pibar, double* fact, int* flags, size_t lds,
+                          hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
   hipError_t e = set_lds(k_local_w, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(64), lds, s, g, obox, pbox, nbox, seeds, K, f,
                      bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar,
-                     flags);
+                     fact, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
-                           const double* fac, const double* tcoup, double* scr, double* p,
-                           double* gflux, size_t lds, int nt, hipStream_t s) {
+                           const double* fac, const double* fact, const double* tcoup, double* scr,
+                           double* p, double* gflux, size_t lds, int nt, hipStream_t s) {
   (void)scr;
   if (nmem <= 0) return hipSuccess;
+  if (!fact) return hipErrorInvalidValue;
   hipError_t e;
 #define MRCM_SMOOTH_NT(N)                                                                     \
   e = set_lds(k_smooth_w<N>, lds);                                                            \
   if (e != hipSuccess) return e;                                                              \
   hipLaunchKernelGGL(k_smooth_w<N>, dim3(nmem), dim3(N), lds, s, g, boxes, members, K, f, bcv, \
-                     beta, fac, tcoup, p, gflux);
+                     beta, fac, fact, tcoup, p, gflux);
   if (nt == 64) {
     MRCM_SMOOTH_NT(64)
   } else if (nt == 128) {

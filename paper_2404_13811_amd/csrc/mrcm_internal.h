@@ -112,15 +112,18 @@ size_t wave_lds_bytes(int m0, int m1, int nrhs);
 size_t wave_smooth_lds_bytes(int m0, int m1);
 // Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox) in one
 // launch of 2 nbox workgroups; lds = the larger of the two boxes' needs.
+// fact (may be null): factors of the twisted smoothing sweep, same layout
+// as fac.
 hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
                           const Seed* seeds, const double* K, const double* f, const double* bcv,
                           double beta, double* fac, double* tcoup, double* facp, double* tcp,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
-                          double* ubar, double* pibar, int* flags, size_t lds, hipStream_t s);
+                          double* ubar, double* pibar, double* fact, int* flags, size_t lds,
+                          hipStream_t s);
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
-                           const double* fac, const double* tcoup, double* scr, double* p,
-                           double* gflux, size_t lds, int nt, hipStream_t s);
+                           const double* fac, const double* fact, const double* tcoup, double* scr,
+                           double* p, double* gflux, size_t lds, int nt, hipStream_t s);
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);

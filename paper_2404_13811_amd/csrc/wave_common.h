@@ -253,26 +253,30 @@ __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta
   bsync<NT>();
 }
 
-// S_j (column c, my half) into w; w holds W_{j-1} on entry when j > 0.
+// Schur complement of block j (column c, my half) into w: D_j - t W t with
+// the coupling t = Tn row tpi to the previously eliminated block, whose
+// inverse W w holds on entry (tpi < 0: no previous block, S = D_j).  The
+// forward elimination uses tpi = j - 1, the backward one tpi = j.
 // Branch-free: every LDS read is unconditional (the addresses stay inside
 // the box arrays) and selects pick the tridiagonal entries, so the reads of
 // a block issue back to back.
-__device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[HB]) {
+__device__ __forceinline__ void wbuild_t(int nb, int j, int tpi, const BoxLds& s, double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
   const int cc = c < nb ? c : 0;
+  const bool hp = tpi >= 0;
   const double* D = s.Dg + j * nb;
   const double* Tx = s.Tx + j * nb;
-  const double* Tp = s.Tn + (j - 1) * nb;  // read only when j > 0
+  const double* Tp = s.Tn + (hp ? tpi : 0) * nb;
   const double dc = D[cc], txc = Tx[cc];
-  const double tc = j > 0 ? Tp[cc] : 0.0;
+  const double tc = hp ? Tp[cc] : 0.0;
   double tr[HB], tpr[HB];
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
     const int r = HB * h + i;
     const int rr = r < nb ? r : 0;
     tr[i] = Tx[rr];
-    tpr[i] = j > 0 ? Tp[rr] : 0.0;
+    tpr[i] = hp ? Tp[rr] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
@@ -282,6 +286,11 @@ __device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[
     v = fma(-tpr[i] * tc, w[i], v);
     w[i] = (r < nb && c < nb) ? v : (d == 0 ? 1.0 : 0.0);
   }
+}
+
+// S_j of the forward elimination; w holds W_{j-1} on entry when j > 0.
+__device__ __forceinline__ void wbuild(int nb, int j, const BoxLds& s, double w[HB]) {
+  wbuild_t(nb, j, j - 1, s, w);
 }
 
 // In-place Gauss-Jordan inversion of the block held in w, GJB pivots per
@@ -450,7 +459,7 @@ struct SmoothLds {
 
 __host__ __device__ inline size_t smooth_lds_doubles(int m0, int m1) {
   const size_t nc = (size_t)m0 * m1, nt = (size_t)(m0 + 2) * (m1 + 2);
-  return 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 2 * NBW + 2;
+  return 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 4 * NBW + 2;
 }
 
 __device__ __forceinline__ int side_off(const BoxLds& s, int q) {
@@ -810,6 +819,156 @@ __device__ __forceinline__ void sweep1(const Box& B, const double* Wg, const Box
     }
   }
   wsync();
+}
+
+// ---------------------------------------------------------- twisted sweep
+// The block-tridiagonal box system solved from both ends towards the
+// meeting block m = nblk / 2 (a twisted block factorisation):
+//   top:     z_j = W_j (b_j + t_{j-1} z_{j-1}),    j = 0 .. m-1
+//   bottom:  z_j = W'_j (b_j + t_j z_{j+1}),       j = nblk-1 .. m+1
+//   meet:    x_m = Z_m (b_m + t_{m-1} z_{m-1} + t_m z_{m+1})
+//   top:     x_j = z_j + W_j (t_j x_{j+1}),        j = m-1 .. 0
+//   bottom:  x_j = z_j + W'_j (t_{j-1} x_{j-1}),   j = m+1 .. nblk-1
+// with the forward inverses W_j, the backward inverses W'_j =
+// (D_j - t_j W'_{j+1} t_j)^{-1} and Z_m = (S_m - t_m W'_{m+1} t_m)^{-1}, S_m
+// the forward Schur complement of block m.  All of them are symmetric, so
+// the column-per-lane products of sweep1 apply.  The two halves touch
+// disjoint blocks of s.X and may run on two waves at once; each half needs
+// its own 2 x NBW doubles of LDS staging z.
+
+// Forward half (top or bottom); z_j replaces b_j in s.X.
+__device__ __forceinline__ void twist_fwd(const Box& B, const double* Wg, const BoxLds& s, double* z,
+                                          int m, bool bottom) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb, nblk = B.nblk;
+  const bool cv = c < nb;
+  const int cnt = bottom ? nblk - 1 - m : m;
+  if (cnt <= 0) return;
+  const int j0 = bottom ? nblk - 1 : 0, dj = bottom ? -1 : 1;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  double w[RING][HB];
+#pragma unroll
+  for (int q = 0; q < RING; ++q)
+    if (q < cnt) wload_block(src, j0 + dj * q, w[q]);
+  double y = 0.0, tp = 0.0;
+  double xn = cv ? s.X[j0 * nb + c] : 0.0;
+  for (int t0 = 0; t0 < cnt; t0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int t = t0 + q;
+      if (t < cnt) {
+        const int j = j0 + dj * t;
+        double* zb = z + (t & 1) * NBW;
+        if (h == 0) zb[c] = cv ? fma(tp, y, xn) : 0.0;
+        __builtin_amdgcn_wave_barrier();
+        const bool more = t + 1 < cnt;
+        const int jn = j + dj;                // next block of this half
+        const int ti = bottom ? jn : j;       // coupling between j and jn
+        xn = (more && cv) ? s.X[jn * nb + c] : 0.0;
+        tp = (more && cv) ? s.Tn[ti * nb + c] : 0.0;
+        y = wgemv2(w[q], zb);
+        if (h == 0 && cv) s.X[j * nb + c] = y;
+        if (t + RING < cnt) wload_block(src, j0 + dj * (t + RING), w[q]);
+      }
+    }
+  }
+}
+
+// Meeting block: x_m from b_m and the neighbouring z of both halves; Tw
+// holds Z_m at block m.
+__device__ __forceinline__ void twist_mid(const Box& B, const double* Tw, const BoxLds& s, double* z,
+                                          int m) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb, nblk = B.nblk;
+  const bool cv = c < nb;
+  const BlockSrc<double> src = block_src(Tw, nb, nblk);
+  double w[HB];
+  wload_block(src, m, w);
+  double v = 0.0;
+  if (cv) {
+    v = s.X[m * nb + c];
+    if (m > 0) v = fma(s.Tn[(m - 1) * nb + c], s.X[(m - 1) * nb + c], v);
+    if (m + 1 < nblk) v = fma(s.Tn[m * nb + c], s.X[(m + 1) * nb + c], v);
+  }
+  if (h == 0) z[c] = v;
+  __builtin_amdgcn_wave_barrier();
+  const double y = wgemv2(w, z);
+  if (h == 0 && cv) s.X[m * nb + c] = y;
+}
+
+// Back-substitution half (top or bottom), outwards from the meeting block.
+__device__ __forceinline__ void twist_back(const Box& B, const double* Wg, const BoxLds& s, double* z,
+                                           int m, bool bottom) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  const int nb = B.nb, nblk = B.nblk;
+  const bool cv = c < nb;
+  const int cnt = bottom ? nblk - 1 - m : m;
+  if (cnt <= 0) return;
+  const int j0 = bottom ? m + 1 : m - 1, dj = bottom ? 1 : -1;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  double w[RING][HB];
+#pragma unroll
+  for (int q = 0; q < RING; ++q)
+    if (q < cnt) wload_block(src, j0 + dj * q, w[q]);
+  double xnext = cv ? s.X[m * nb + c] : 0.0;  // the solved neighbour of block j0
+  double tj = cv ? s.Tn[(bottom ? j0 - 1 : j0) * nb + c] : 0.0;
+  double wj = cv ? s.X[j0 * nb + c] : 0.0;
+  for (int t0 = 0; t0 < cnt; t0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int t = t0 + q;
+      if (t < cnt) {
+        const int j = j0 + dj * t;
+        double* zb = z + (t & 1) * NBW;
+        if (h == 0) zb[c] = cv ? tj * xnext : 0.0;
+        __builtin_amdgcn_wave_barrier();
+        const double wcur = wj;
+        const bool more = t + 1 < cnt;
+        const int jn = j + dj;
+        tj = (more && cv) ? s.Tn[(bottom ? jn - 1 : jn) * nb + c] : 0.0;
+        wj = (more && cv) ? s.X[jn * nb + c] : 0.0;
+        xnext = wcur + wgemv2(w[q], zb);
+        if (h == 0 && cv) s.X[j * nb + c] = xnext;
+        if (t + RING < cnt) wload_block(src, j0 + dj * (t + RING), w[q]);
+      }
+    }
+  }
+}
+
+// The whole twisted sweep of one right-hand side by the NT threads of a
+// box: with NT >= 128 the two halves run on waves 0 and 1 at once, with
+// NT = 64 one after the other (same arithmetic, same result).  Wf: forward
+// inverses, Wt: backward inverses and Z_m; z: 4 x NBW doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void sweep_twisted(const Box& B, const double* Wf, const double* Wt,
+                                              const BoxLds& s, double* z) {
+  const int wv = threadIdx.x >> 6;
+  const int m = B.nblk / 2;
+  double* za = z;
+  double* zb = z + 2 * NBW;
+  if (NT == 64) {
+    twist_fwd(B, Wf, s, za, m, false);
+    twist_fwd(B, Wt, s, zb, m, true);
+  } else if (wv == 0) {
+    twist_fwd(B, Wf, s, za, m, false);
+  } else if (wv == 1) {
+    twist_fwd(B, Wt, s, zb, m, true);
+  }
+  bsync<NT>();
+  if (wv == 0) twist_mid(B, Wt, s, za, m);
+  bsync<NT>();
+  if (NT == 64) {
+    twist_back(B, Wf, s, za, m, false);
+    twist_back(B, Wt, s, zb, m, true);
+  } else if (wv == 0) {
+    twist_back(B, Wf, s, za, m, false);
+  } else if (wv == 1) {
+    twist_back(B, Wt, s, zb, m, true);
+  }
+  bsync<NT>();
 }
 
 }  // namespace wave
