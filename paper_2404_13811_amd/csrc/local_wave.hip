@@ -297,12 +297,22 @@ __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ 
                                                  double* __restrict__ gflux) {
   extern __shared__ __align__(16) double dsm[];
   const Box B = boxes[members[blockIdx.x]];
+  const double* Wf = fac + B.fac;
+  const double* Wt = fact + B.fac;
+  // factor blocks needed first: in flight while the box data is staged
+  double w[RING][HB], zm[HB];
+  const int wv = threadIdx.x >> 6;
+  if (NT > 64 && wv < 2) {
+    const int m = B.nblk / 2;
+    twist_preload(twist_half(B, wv == 0 ? Wf : Wt, m, wv == 1), w);
+  }
+  if (threadIdx.x < 64) wload_block(block_src(Wt, B.nb, B.nblk), B.nblk / 2, zm);
   SmoothLds r = carve_smooth(dsm, B);
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
   bsync<NT>();
   smooth_rhs<NT>(g, B, r, beta, r.b.X);
   bsync<NT>();
-  sweep_twisted<NT>(B, fac + B.fac, fact + B.fac, r.b, r.b.Z);
+  sweep_twisted<NT>(B, Wf, Wt, r.b, r.b.Z, w, zm);
   smooth_out<NT>(g, B, r, r.b.X, beta, p, gflux);
 }
 

@@ -836,56 +836,78 @@ __device__ __forceinline__ void sweep1(const Box& B, const double* Wg, const Box
 // disjoint blocks of s.X and may run on two waves at once; each half needs
 // its own 2 x NBW doubles of LDS staging z.
 
-// Forward half (top or bottom); z_j replaces b_j in s.X.
-__device__ __forceinline__ void twist_fwd(const Box& B, const double* Wg, const BoxLds& s, double* z,
-                                          int m, bool bottom) {
+// One half of the twisted sweep: block j = j0 + dj * b for the b-th block
+// away from the end (b = 0 .. cnt-1).  The register ring holds block b in
+// slot (b + o) % RING, with o chosen so that the last block of the forward
+// pass sits in slot RING-1: the back pass then finds its first RING blocks
+// in place (slot RING-1-q for its q-th block) and the slot of every block
+// stays a compile-time index.
+struct TwistHalf {
+  BlockSrc<double> src;
+  int cnt, j0, dj, o;
+};
+
+__device__ __forceinline__ TwistHalf twist_half(const Box& B, const double* Wg, int m, bool bottom) {
+  TwistHalf hf;
+  hf.src = block_src(Wg, B.nb, B.nblk);
+  hf.cnt = bottom ? B.nblk - 1 - m : m;
+  hf.j0 = bottom ? B.nblk - 1 : 0;
+  hf.dj = bottom ? -1 : 1;
+  hf.o = hf.cnt > 0 ? (RING - hf.cnt % RING) % RING : 0;
+  return hf;
+}
+
+// First RING blocks of the forward pass into the ring (block b in slot
+// (b + o) % RING).
+__device__ __forceinline__ void twist_preload(const TwistHalf& hf, double w[RING][HB]) {
+#pragma unroll
+  for (int q = 0; q < RING; ++q) {
+    const int b = (q - hf.o + RING) % RING;
+    if (b < hf.cnt) wload_block(hf.src, hf.j0 + hf.dj * b, w[q]);
+  }
+}
+
+// Forward half (ring preloaded); z_j replaces b_j in s.X.
+__device__ __forceinline__ void twist_fwd(const Box& B, const TwistHalf& hf, const BoxLds& s,
+                                          double* z, bool bottom, double w[RING][HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
-  const int nb = B.nb, nblk = B.nblk;
+  const int nb = B.nb;
   const bool cv = c < nb;
-  const int cnt = bottom ? nblk - 1 - m : m;
+  const int cnt = hf.cnt;
   if (cnt <= 0) return;
-  const int j0 = bottom ? nblk - 1 : 0, dj = bottom ? -1 : 1;
-  const BlockSrc<double> src = block_src(Wg, nb, nblk);
-  double w[RING][HB];
-#pragma unroll
-  for (int q = 0; q < RING; ++q)
-    if (q < cnt) wload_block(src, j0 + dj * q, w[q]);
   double y = 0.0, tp = 0.0;
-  double xn = cv ? s.X[j0 * nb + c] : 0.0;
-  for (int t0 = 0; t0 < cnt; t0 += RING) {
+  double xn = cv ? s.X[hf.j0 * nb + c] : 0.0;
+  for (int v0 = 0; v0 < cnt + hf.o; v0 += RING) {
 #pragma unroll
     for (int q = 0; q < RING; ++q) {
-      const int t = t0 + q;
-      if (t < cnt) {
-        const int j = j0 + dj * t;
+      const int t = v0 + q - hf.o;
+      if (t >= 0 && t < cnt) {
+        const int j = hf.j0 + hf.dj * t;
         double* zb = z + (t & 1) * NBW;
         if (h == 0) zb[c] = cv ? fma(tp, y, xn) : 0.0;
         __builtin_amdgcn_wave_barrier();
         const bool more = t + 1 < cnt;
-        const int jn = j + dj;                // next block of this half
+        const int jn = j + hf.dj;             // next block of this half
         const int ti = bottom ? jn : j;       // coupling between j and jn
         xn = (more && cv) ? s.X[jn * nb + c] : 0.0;
         tp = (more && cv) ? s.Tn[ti * nb + c] : 0.0;
         y = wgemv2(w[q], zb);
         if (h == 0 && cv) s.X[j * nb + c] = y;
-        if (t + RING < cnt) wload_block(src, j0 + dj * (t + RING), w[q]);
+        if (t + RING < cnt) wload_block(hf.src, hf.j0 + hf.dj * (t + RING), w[q]);
       }
     }
   }
 }
 
-// Meeting block: x_m from b_m and the neighbouring z of both halves; Tw
-// holds Z_m at block m.
-__device__ __forceinline__ void twist_mid(const Box& B, const double* Tw, const BoxLds& s, double* z,
-                                          int m) {
+// Meeting block: x_m from b_m and the neighbouring z of both halves; zm
+// holds Z_m in the block register layout.
+__device__ __forceinline__ void twist_mid(const Box& B, const double zm[HB], const BoxLds& s,
+                                          double* z, int m) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
   const int nb = B.nb, nblk = B.nblk;
   const bool cv = c < nb;
-  const BlockSrc<double> src = block_src(Tw, nb, nblk);
-  double w[HB];
-  wload_block(src, m, w);
   double v = 0.0;
   if (cv) {
     v = s.X[m * nb + c];
@@ -894,79 +916,93 @@ __device__ __forceinline__ void twist_mid(const Box& B, const double* Tw, const 
   }
   if (h == 0) z[c] = v;
   __builtin_amdgcn_wave_barrier();
-  const double y = wgemv2(w, z);
+  const double y = wgemv2(zm, z);
   if (h == 0 && cv) s.X[m * nb + c] = y;
 }
 
-// Back-substitution half (top or bottom), outwards from the meeting block.
-__device__ __forceinline__ void twist_back(const Box& B, const double* Wg, const BoxLds& s, double* z,
-                                           int m, bool bottom) {
+// Back-substitution half, outwards from the meeting block.  With
+// have_ring the ring is the one the forward pass of this half left behind.
+__device__ __forceinline__ void twist_back(const Box& B, const TwistHalf& hf, const BoxLds& s,
+                                           double* z, int m, bool bottom, bool have_ring,
+                                           double w[RING][HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
-  const int nb = B.nb, nblk = B.nblk;
+  const int nb = B.nb;
   const bool cv = c < nb;
-  const int cnt = bottom ? nblk - 1 - m : m;
+  const int cnt = hf.cnt;
   if (cnt <= 0) return;
-  const int j0 = bottom ? m + 1 : m - 1, dj = bottom ? 1 : -1;
-  const BlockSrc<double> src = block_src(Wg, nb, nblk);
-  double w[RING][HB];
-#pragma unroll
-  for (int q = 0; q < RING; ++q)
-    if (q < cnt) wload_block(src, j0 + dj * q, w[q]);
-  double xnext = cv ? s.X[m * nb + c] : 0.0;  // the solved neighbour of block j0
-  double tj = cv ? s.Tn[(bottom ? j0 - 1 : j0) * nb + c] : 0.0;
-  double wj = cv ? s.X[j0 * nb + c] : 0.0;
-  for (int t0 = 0; t0 < cnt; t0 += RING) {
+  if (!have_ring) {
 #pragma unroll
     for (int q = 0; q < RING; ++q) {
-      const int t = t0 + q;
+      const int b = cnt - 1 - q;
+      if (b >= 0) wload_block(hf.src, hf.j0 + hf.dj * b, w[RING - 1 - q]);
+    }
+  }
+  const int jf = hf.j0 + hf.dj * (cnt - 1);  // first block of the back pass (next to m)
+  double xnext = cv ? s.X[m * nb + c] : 0.0;
+  double tj = cv ? s.Tn[(bottom ? jf - 1 : jf) * nb + c] : 0.0;
+  double wj = cv ? s.X[jf * nb + c] : 0.0;
+  for (int v0 = 0; v0 < cnt; v0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int t = v0 + q;
       if (t < cnt) {
-        const int j = j0 + dj * t;
+        const int b = cnt - 1 - t;
+        const int j = hf.j0 + hf.dj * b;
         double* zb = z + (t & 1) * NBW;
         if (h == 0) zb[c] = cv ? tj * xnext : 0.0;
         __builtin_amdgcn_wave_barrier();
         const double wcur = wj;
         const bool more = t + 1 < cnt;
-        const int jn = j + dj;
+        const int jn = j - hf.dj;             // next block, away from m
         tj = (more && cv) ? s.Tn[(bottom ? jn - 1 : jn) * nb + c] : 0.0;
         wj = (more && cv) ? s.X[jn * nb + c] : 0.0;
-        xnext = wcur + wgemv2(w[q], zb);
+        xnext = wcur + wgemv2(w[RING - 1 - q], zb);
         if (h == 0 && cv) s.X[j * nb + c] = xnext;
-        if (t + RING < cnt) wload_block(src, j0 + dj * (t + RING), w[q]);
+        if (b - RING >= 0) wload_block(hf.src, hf.j0 + hf.dj * (b - RING), w[RING - 1 - q]);
       }
     }
   }
 }
 
 // The whole twisted sweep of one right-hand side by the NT threads of a
-// box: with NT >= 128 the two halves run on waves 0 and 1 at once, with
-// NT = 64 one after the other (same arithmetic, same result).  Wf: forward
-// inverses, Wt: backward inverses and Z_m; z: 4 x NBW doubles of LDS.
+// box.  With NT >= 128 the two halves run on waves 0 and 1 at once, each
+// keeping its ring from the forward into the back pass; the caller has
+// preloaded the ring of its half (twist_preload) and wave 0 the meeting
+// block (zm), before staging, so that their memory latency is hidden.  With
+// NT = 64 one wave runs the halves one after the other and loads as it
+// goes.  The arithmetic is the same in both cases, and so is the result.
+// Wf: forward inverses, Wt: backward inverses and Z_m; z: 4 x NBW doubles.
 template <int NT>
 __device__ __forceinline__ void sweep_twisted(const Box& B, const double* Wf, const double* Wt,
-                                              const BoxLds& s, double* z) {
+                                              const BoxLds& s, double* z, double w[RING][HB],
+                                              const double zm[HB]) {
   const int wv = threadIdx.x >> 6;
   const int m = B.nblk / 2;
   double* za = z;
   double* zb = z + 2 * NBW;
+  const TwistHalf top = twist_half(B, Wf, m, false);
+  const TwistHalf bot = twist_half(B, Wt, m, true);
   if (NT == 64) {
-    twist_fwd(B, Wf, s, za, m, false);
-    twist_fwd(B, Wt, s, zb, m, true);
+    twist_preload(top, w);
+    twist_fwd(B, top, s, za, false, w);
+    twist_preload(bot, w);
+    twist_fwd(B, bot, s, zb, true, w);
   } else if (wv == 0) {
-    twist_fwd(B, Wf, s, za, m, false);
+    twist_fwd(B, top, s, za, false, w);
   } else if (wv == 1) {
-    twist_fwd(B, Wt, s, zb, m, true);
+    twist_fwd(B, bot, s, zb, true, w);
   }
   bsync<NT>();
-  if (wv == 0) twist_mid(B, Wt, s, za, m);
+  if (wv == 0) twist_mid(B, zm, s, za, m);
   bsync<NT>();
   if (NT == 64) {
-    twist_back(B, Wf, s, za, m, false);
-    twist_back(B, Wt, s, zb, m, true);
+    twist_back(B, top, s, za, m, false, false, w);
+    twist_back(B, bot, s, zb, m, true, false, w);
   } else if (wv == 0) {
-    twist_back(B, Wf, s, za, m, false);
+    twist_back(B, top, s, za, m, false, true, w);
   } else if (wv == 1) {
-    twist_back(B, Wt, s, zb, m, true);
+    twist_back(B, bot, s, zb, m, true, true, w);
   }
   bsync<NT>();
 }
