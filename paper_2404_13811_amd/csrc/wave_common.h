@@ -675,7 +675,7 @@ __device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, con
                                          const double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
-  #pragma unroll 1
+  #pragma unroll 4
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     double v = 0.0;
@@ -686,9 +686,14 @@ __device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, con
     s.Z[k * NBW + r] = v;
   }
   wsync();
-  for (int k = 0; k < nrhs; ++k) {
-    const double y = wgemv2(w, s.Z + k * NBW);
-    if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] = y;
+  // four right-hand sides at a time: independent product chains overlap
+  for (int k0 = 0; k0 < nrhs; k0 += 4) {
+    double y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, s.Z + min(k0 + q, nrhs - 1) * NBW);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k0 + q < nrhs && h == 0 && c < nb) s.X[(k0 + q) * ncell + j * nb + c] = y[q];
   }
   wsync();
 }
@@ -698,15 +703,19 @@ __device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, con
                                          const double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
-  #pragma unroll 1
+  #pragma unroll 4
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     s.Z[k * NBW + r] = (r < nb) ? s.Tn[j * nb + r] * s.X[k * ncell + (j + 1) * nb + r] : 0.0;
   }
   wsync();
-  for (int k = 0; k < nrhs; ++k) {
-    const double y = wgemv2(w, s.Z + k * NBW);
-    if (h == 0 && c < nb) s.X[k * ncell + j * nb + c] += y;
+  for (int k0 = 0; k0 < nrhs; k0 += 4) {
+    double y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, s.Z + min(k0 + q, nrhs - 1) * NBW);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k0 + q < nrhs && h == 0 && c < nb) s.X[(k0 + q) * ncell + j * nb + c] += y[q];
   }
   wsync();
 }
