@@ -207,15 +207,12 @@ __device__ __forceinline__ void stage_strips(const double* __restrict__ A, const
   }
 }
 
-__global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
-                                                  const BcrGemm* __restrict__ tasks, int n, int ld) {
-  extern __shared__ double smem[];
+// One 32 x 32 output tile of a product task (tile = row-major tile index).
+__device__ __forceinline__ void gemm_tile(double* pool, const BcrGemm& T, int n, int ld, int tile,
+                                          double* smem) {
   double* As = smem;           // n x GT
   double* Bs = smem + n * GT;  // n x GT
   const int ntile = n / GT;
-  const int task = blockIdx.x / (ntile * ntile);
-  const int tile = blockIdx.x - task * ntile * ntile;
-  const BcrGemm T = tasks[task];
   const int tr0 = (tile / ntile) * GT, tc0 = (tile % ntile) * GT;
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
@@ -251,14 +248,20 @@ __global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
   C[r_1 * ld + c_1] = acc11;
 }
 
+__global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
+                                                  const BcrGemm* __restrict__ tasks, int n, int ld) {
+  extern __shared__ double smem[];
+  const int ntile = n / GT;
+  const int task = blockIdx.x / (ntile * ntile);
+  gemm_tile(pool, tasks[task], n, ld, blockIdx.x - task * ntile * ntile, smem);
+}
+
 // y = [y0] + al1 A1 x1 + al2 A2 x2.  Workgroup (task, group of 16 rows);
 // 16 lanes per row, each with bp/16 independent loads, then a 16-lane sum.
-__global__ void __launch_bounds__(256) k_bcr_gemv(const double* __restrict__ pool,
-                                                  double* __restrict__ vec,
-                                                  const BcrGemv* __restrict__ tasks, int bp) {
-  const BcrGemv T = tasks[blockIdx.x];
+__device__ __forceinline__ void gemv_rows(const double* pool, double* __restrict__ vec, const BcrGemv& T,
+                                          int bp, int rg) {
   const long long bs = (long long)bp * bp;
-  const int r = blockIdx.y * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+  const int r = rg * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
   double acc = 0.0;
 #pragma unroll
   for (int term = 0; term < 2; ++term) {
@@ -278,6 +281,33 @@ __global__ void __launch_bounds__(256) k_bcr_gemv(const double* __restrict__ poo
   if (l == 0) {
     double* y = vec + (long long)T.y * bp;
     y[r] = (T.y0 >= 0 ? vec[(long long)T.y0 * bp + r] : 0.0) + acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bcr_gemv(const double* __restrict__ pool,
+                                                  double* __restrict__ vec,
+                                                  const BcrGemv* __restrict__ tasks, int bp) {
+  gemv_rows(pool, vec, tasks[blockIdx.x], bp, blockIdx.y);
+}
+
+// Block products and block-vector products that do not depend on each
+// other, in one launch: workgroups [0, ngblk) are product tiles, the rest
+// row groups of the vector tasks.  The caller guarantees that no vector
+// task reads a block a product task of the same launch writes.
+__global__ void __launch_bounds__(256) k_bcr_gemm_gemv(double* pool, double* __restrict__ vec,
+                                                       const BcrGemm* __restrict__ gtasks, int ngblk,
+                                                       const BcrGemv* __restrict__ vtasks, int n,
+                                                       int ld, int bp) {
+  extern __shared__ double smem[];
+  const int b = blockIdx.x;
+  if (b < ngblk) {
+    const int ntile = n / GT;
+    const int task = b / (ntile * ntile);
+    gemm_tile(pool, gtasks[task], n, ld, b - task * ntile * ntile, smem);
+  } else {
+    const int rgs = bp / 16;
+    const int i = b - ngblk;
+    gemv_rows(pool, vec, vtasks[i / rgs], bp, i - (i / rgs) * rgs);
   }
 }
 
@@ -344,6 +374,24 @@ hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n,
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_bcr_gemm, dim3(ntask * ntile * ntile), dim3(256), lds, s, pool, tasks, n, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_bcr_gemm_gemv(double* pool, double* vec, const BcrGemm* gtasks, int ngemm,
+                               const BcrGemv* vtasks, int ngemv, int n, int ld, int bp,
+                               hipStream_t s) {
+  if (ngemm <= 0 && ngemv <= 0) return hipSuccess;
+  if (n % GT || n > kBcrMaxBlock || bp % 16) return hipErrorInvalidValue;
+  const int ntile = n / GT;
+  const size_t lds = 2 * sizeof(double) * (size_t)n * GT;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_bcr_gemm_gemv,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int ngblk = ngemm * ntile * ntile;
+  hipLaunchKernelGGL(k_bcr_gemm_gemv, dim3(ngblk + ngemv * (bp / 16)), dim3(256), lds, s, pool, vec,
+                     gtasks, ngblk, vtasks, n, ld, bp);
   return hipGetLastError();
 }
 

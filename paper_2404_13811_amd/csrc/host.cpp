@@ -87,9 +87,11 @@ struct mrcm_ctx {
   // block cyclic reduction of the interface system over the layers of
   // subdomains along the last axis (bcr.hip)
   struct BcrOp {
-    int kind;  // 0 inverses, 1 block products, 2 block-vector products
+    int kind;  // 0 inverses, 1 block products, 2 block-vector products,
+               // 3 independent products (off, cnt) and vector products (off2, cnt2)
     int off, cnt;
-    int n, ld;  // operand size and leading dimension (kinds 0 and 1)
+    int n, ld;  // operand size and leading dimension (kinds 0, 1, 3)
+    int off2 = 0, cnt2 = 0;
   };
   bool use_bcr = false;
   int bcr_M = 0, bcr_bp = 0;
@@ -313,6 +315,15 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
   auto op = [&](int kind, int off, int cnt, int nn = 0, int ld = 0) {
     if (cnt > 0) c->bcr_ops.push_back(mrcm_ctx::BcrOp{kind, off, cnt, nn, ld});
   };
+  // products and vector products that read nothing the other writes
+  auto op_pair = [&](int goff, int gcnt, int voff, int vcnt) {
+    if (gcnt == 0) return op(2, voff, vcnt);
+    if (vcnt == 0) return op(1, goff, gcnt, bp, bp);
+    mrcm_ctx::BcrOp o{3, goff, gcnt, bp, bp};
+    o.off2 = voff;
+    o.cnt2 = vcnt;
+    c->bcr_ops.push_back(o);
+  };
   // a product task on whole blocks (slots < 0 drop a term)
   auto GM = [&](int cs, int c0, int a1, int b1, int a2, int b2, double al1, double al2) {
     auto o = [&](int slot) { return slot < 0 ? -1LL : slot * bs; };
@@ -382,19 +393,20 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
       }
       inverses(blk, s1, s2);
     }
+    // F_k = E_k L_k, G_k = E_k U_k and g_k = E_k r_k read only E, L, U, r:
+    // one launch
     int o = (int)gemm.size();
     for (int t = 1; t < L; t += 2) {
       const int k = idx[t];
       gemm.push_back(GM(F(k), -1, dsl[k], lsl[k], -1, -1, 1.0, 0.0));
       if (t + 1 < L) gemm.push_back(GM(G(k), -1, dsl[k], usl[k], -1, -1, 1.0, 0.0));
     }
-    op(1, o, (int)gemm.size() - o, bp, bp);
-    o = (int)gemv.size();
+    const int ov0 = (int)gemv.size();
     for (int t = 1; t < L; t += 2) {
       const int k = idx[t];
       gemv.push_back(BcrGemv{gv(k), -1, dsl[k], rv(k), -1, -1, 1.0, 0.0});
     }
-    op(2, o, (int)gemv.size() - o);
+    op_pair(o, (int)gemm.size() - o, ov0, (int)gemv.size() - ov0);
     // kept layers (even positions)
     std::vector<int> nl(M, -1), nu(M, -1);
     o = (int)gemm.size();
@@ -428,8 +440,9 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
         nu[j] = usl[kp];
       }
     }
-    op(1, o, (int)gemm.size() - o, bp, bp);
-    op(2, ov, (int)gemv.size() - ov);
+    // the kept-layer products write D_j and the eliminated neighbours' L/U
+    // slots; the vector products read L_j, U_j (kept slots) and g: one launch
+    op_pair(o, (int)gemm.size() - o, ov, (int)gemv.size() - ov);
     // back substitution of this level, replayed in reverse order
     std::vector<BcrGemv> bk;
     for (int t = 1; t < L; t += 2) {
@@ -733,6 +746,22 @@ mrcm_status make_plan(mrcm_ctx* c) {
   return MRCM_OK;
 }
 
+mrcm_status run_bcr_ops(mrcm_ctx* c, hipStream_t s) {
+  const int bp = c->bcr_bp;
+  for (const auto& o : c->bcr_ops) {
+    if (o.kind == 0)
+      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, o.n, o.ld, c->flags, s));
+    else if (o.kind == 1)
+      HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, o.n, o.ld, s));
+    else if (o.kind == 2)
+      HIPCHK(c, launch_bcr_gemv(c->bpool, c->bvec, c->d_bgemv + o.off, o.cnt, bp, s));
+    else
+      HIPCHK(c, launch_bcr_gemm_gemv(c->bpool, c->bvec, c->d_bgemm + o.off, o.cnt,
+                                     c->d_bgemv + o.off2, o.cnt2, o.n, o.ld, bp, s));
+  }
+  return MRCM_OK;
+}
+
 mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
   const int M = c->bcr_M, bp = c->bcr_bp;
   const long long bs = (long long)bp * bp;
@@ -740,13 +769,9 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
   HIPCHK(c, launch_fill(c->bvec, 0.0, (long long)M * bp, s));
   HIPCHK(c, launch_bcr_scatter(c->AB, c->rhs, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
                                c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, c->d_lsize, s));
-  for (const auto& o : c->bcr_ops) {
-    if (o.kind == 0)
-      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, o.n, o.ld, c->flags, s));
-    else if (o.kind == 1)
-      HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, o.n, o.ld, s));
-    else
-      HIPCHK(c, launch_bcr_gemv(c->bpool, c->bvec, c->d_bgemv + o.off, o.cnt, bp, s));
+  {
+    mrcm_status st = run_bcr_ops(c, s);
+    if (st) return st;
   }
   HIPCHK(c, launch_bcr_gather(c->bvec + 2LL * M * bp, c->d_col_lvl, c->d_col_loc, c->nX, bp, c->X, s));
   return MRCM_OK;
@@ -1268,13 +1293,9 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
     HIPCHK(c, launch_bcr_scatter_t(c->AB, c->a_Xb, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
                                    c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, s));
     HIPCHK(c, launch_bcr_pad(c->bpool, c->d_lsize, M, bp, s));
-    for (const auto& o : c->bcr_ops) {
-      if (o.kind == 0)
-        HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, o.n, o.ld, c->flags, s));
-      else if (o.kind == 1)
-        HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, o.n, o.ld, s));
-      else
-        HIPCHK(c, launch_bcr_gemv(c->bpool, c->bvec, c->d_bgemv + o.off, o.cnt, bp, s));
+    {
+      mrcm_status st = run_bcr_ops(c, s);
+      if (st) return st;
     }
     HIPCHK(c, launch_bcr_gather_t(c->bvec + 2LL * M * bp, c->d_row_lvl, c->d_row_loc, c->nX, bp,
                                   c->a_nu, s));

@@ -161,6 +161,11 @@ hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl
 hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
                           hipStream_t s);
 hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n, int ld, hipStream_t s);
+// independent products and block-vector products of one reduction step in
+// one launch (no vector task may read a block the products write)
+hipError_t launch_bcr_gemm_gemv(double* pool, double* vec, const BcrGemm* gtasks, int ngemm,
+                               const BcrGemv* vtasks, int ngemv, int n, int ld, int bp,
+                               hipStream_t s);
 hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks, int ntask, int bp,
                            hipStream_t s);
 hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* col_loc, int n, int bp,
