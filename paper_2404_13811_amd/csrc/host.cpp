@@ -57,6 +57,7 @@ struct mrcm_ctx {
   std::vector<int> members;
   int member_off[9] = {0};
   int nX = 0, kl = 0, ku = 0, ldab = 0;
+  int mom_rows = 0;  // largest number of equation rows of one interface
   long long fac_n = 0, facp_n = 0, scr_n = 0, scro_n = 0, scrp_n = 0;
 
   // device plan
@@ -603,6 +604,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   int row = 0;
   c->kl = 0;
   c->ku = 0;
+  c->mom_rows = 0;
   for (int i = 0; i < nsub; ++i) {
     for (int a = 0; a < c->d; ++a) {
       const int j = neighbor(c, i, 2 * a + 1);
@@ -621,6 +623,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
       F.basis0 = (int)c->basis.size();
       family(c, 2 * a + 1, wlo, whi, wlo, whi, c->basis);
       F.nbasis = (int)c->basis.size() - F.basis0;
+      c->mom_rows = std::max(c->mom_rows, 2 * F.nbasis);
       const int cmin = c->seed_off[i];
       const int cmax = c->seed_off[j + 1] - 1;
       for (int r = row; r < row + 2 * F.nbasis; ++r) {
@@ -1005,8 +1008,10 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
   hipStream_t s = c->stream;
   HIPCHK(c, hipEventRecord(c->ev[2], s));
-  HIPCHK(c, launch_fill(c->AB, 0.0, (long long)c->ldab * c->nX, s));
-  HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->d_seed_off,
+  // the reduction reads the row band only; the banded LU also uses the rest
+  const long long band = (long long)(c->kl + c->ku + 1) * c->nX;
+  HIPCHK(c, launch_fill(c->AB, 0.0, c->use_bcr ? band : (long long)c->ldab * c->nX, s));
+  HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis, c->d_seed_off,
                            c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab,
                            c->kl, c->ku, c->rhs, s));
   if (c->nX > 0) {
@@ -1284,8 +1289,8 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
   {
     const int M = c->bcr_M, bp = c->bcr_bp;
     const long long bs = (long long)bp * bp;
-    HIPCHK(c, launch_fill(c->AB, 0.0, (long long)c->ldab * c->nX, s));
-    HIPCHK(c, launch_moments(g, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->d_seed_off, c->tr_u,
+    HIPCHK(c, launch_fill(c->AB, 0.0, (long long)(c->kl + c->ku + 1) * c->nX, s));
+    HIPCHK(c, launch_moments(g, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis, c->d_seed_off, c->tr_u,
                              c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab, c->kl, c->ku,
                              c->rhs, s));
     HIPCHK(c, launch_fill(c->bpool, 0.0, 3LL * M * bs, s));

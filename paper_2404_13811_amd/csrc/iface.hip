@@ -42,61 +42,81 @@ __device__ __forceinline__ void gface_cell(const int lo[3], const int hi[3], int
   }
 }
 
-// One workgroup per interface; threads over (row, entry) pairs.
-__global__ void k_moments(Geo g, const Iface* __restrict__ ifc, const Seed* __restrict__ basis,
-                          const int* __restrict__ seed_off, const double* __restrict__ tr_u,
-                          const double* __restrict__ tr_phi, const double* __restrict__ tr_beta,
-                          const double* __restrict__ ubar, const double* __restrict__ pibar,
-                          double* __restrict__ AB, int ldab, int kl, int ku,
-                          double* __restrict__ rhs) {
+// One workgroup per (interface, equation row); each entry of the row (one
+// column per seed of the two subdomains, then the right-hand side) is a sum
+// over the interface faces, taken by a group of MG lanes: each lane adds
+// the faces t = lane, lane + MG, ... and the group sums its lanes in a fixed
+// order.  All loads of a round are in flight together.
+constexpr int MG = 16;
+
+__global__ void __launch_bounds__(256) k_moments(Geo g, const Iface* __restrict__ ifc,
+                                                 const Seed* __restrict__ basis,
+                                                 const int* __restrict__ seed_off,
+                                                 const double* __restrict__ tr_u,
+                                                 const double* __restrict__ tr_phi,
+                                                 const double* __restrict__ tr_beta,
+                                                 const double* __restrict__ ubar,
+                                                 const double* __restrict__ pibar,
+                                                 double* __restrict__ AB, int ldab, int kl, int ku,
+                                                 double* __restrict__ rhs) {
   const Iface F = ifc[blockIdx.x];
+  const int rr = blockIdx.y;
+  const int nrow = 2 * F.nbasis;
+  if (rr >= nrow) return;  // uniform over the workgroup
   const int qi = 2 * F.axis + 1, qj = 2 * F.axis;
   const int ni = seed_off[F.i + 1] - seed_off[F.i];
   const int nj = seed_off[F.j + 1] - seed_off[F.j];
   const int per_row = ni + nj + 1;  // entries + rhs
-  const int nrow = 2 * F.nbasis;
   int ilo[3], ihi[3];
   omega_box(g, F.i, ilo, ihi);
   int nf = 1;
   for (int b = 0; b < g.d; ++b)
     if (b != F.axis) nf *= g.S[b];
-  for (int w = threadIdx.x; w < nrow * per_row; w += blockDim.x) {
-    const int rr = w / per_row, e = w % per_row;
-    const int kind = rr / F.nbasis;  // 0 flux, 1 pressure
-    const Seed mu = basis[F.basis0 + rr % F.nbasis];
-    const int row = F.row0 + rr;
+  const int kind = rr / F.nbasis;  // 0 flux, 1 pressure
+  const Seed mu = basis[F.basis0 + rr % F.nbasis];
+  const int row = F.row0 + rr;
+  const int lg = threadIdx.x & (MG - 1), grp = threadIdx.x / MG, ngrp = blockDim.x / MG;
+  for (int e0 = 0; e0 < per_row; e0 += ngrp) {
+    const int e = e0 + grp;
+    const bool valid = e < per_row;
     double acc = 0.0;
     int col = -1;
-    if (e < ni + nj) {
+    if (valid && e < ni + nj) {
       const bool side_i = e < ni;
       const int sub = side_i ? F.i : F.j;
       const int k = side_i ? e : e - ni;
       const int q = side_i ? qi : qj;
-      const double sg = (kind == 1 && !side_i) ? -1.0 : 1.0;
       col = seed_off[sub] + k;
       const long long base = (long long)col * g.gstride + g.gside_off[q];
       const long long bbase = (long long)sub * g.gstride + g.gside_off[q];
-      for (int t = 0; t < nf; ++t) {
+      for (int t = lg; t < nf; t += MG) {
         int c[3];
         gface_cell(ilo, ihi, qi, t, c);
         const double w_t = g.area * seed_value(g, mu, ilo, ihi, c);
         const double v = kind == 0 ? tr_u[base + t] : tr_beta[bbase + t] * tr_u[base + t] + tr_phi[base + t];
         acc += w_t * v;
       }
-      acc *= sg;
-      if (g.neumann && row == 0) acc = (col == 0) ? 1.0 : 0.0;
-      AB[(long long)row * (kl + ku + 1) + (col - row + kl)] = acc;
-    } else {
+      if (kind == 1 && !side_i) acc = -acc;
+    } else if (valid) {
       const long long bi = (long long)F.i * g.gstride + g.gside_off[qi];
       const long long bj = (long long)F.j * g.gstride + g.gside_off[qj];
-      for (int t = 0; t < nf; ++t) {
+      for (int t = lg; t < nf; t += MG) {
         int c[3];
         gface_cell(ilo, ihi, qi, t, c);
         const double w_t = g.area * seed_value(g, mu, ilo, ihi, c);
         const double v = kind == 0 ? ubar[bi + t] + ubar[bj + t] : pibar[bi + t] - pibar[bj + t];
         acc += w_t * v;
       }
-      rhs[row] = (g.neumann && row == 0) ? 0.0 : -acc;
+    }
+#pragma unroll
+    for (int off = MG / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (valid && lg == 0) {
+      if (e < ni + nj) {
+        if (g.neumann && row == 0) acc = (col == 0) ? 1.0 : 0.0;
+        AB[(long long)row * (kl + ku + 1) + (col - row + kl)] = acc;
+      } else {
+        rhs[row] = (g.neumann && row == 0) ? 0.0 : -acc;
+      }
     }
   }
 }
@@ -649,13 +669,13 @@ __global__ void k_combine_u(Geo g, const int* __restrict__ seed_off, const doubl
 
 }  // namespace
 
-hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,
+hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, int nrow_max, const Seed* basis,
                           const int* seed_off, const double* tr_u, const double* tr_phi,
                           const double* tr_beta, const double* ubar, const double* pibar,
                           double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s) {
-  if (nifc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_moments, dim3(nifc), dim3(64), 0, s, g, ifc, basis, seed_off, tr_u, tr_phi,
-                     tr_beta, ubar, pibar, AB, ldab, kl, ku, rhs);
+  if (nifc <= 0 || nrow_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_moments, dim3(nifc, nrow_max), dim3(256), 0, s, g, ifc, basis, seed_off, tr_u,
+                     tr_phi, tr_beta, ubar, pibar, AB, ldab, kl, ku, rhs);
   return hipGetLastError();
 }
 

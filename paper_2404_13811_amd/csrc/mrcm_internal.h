@@ -141,7 +141,7 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members,
                              size_t lds, int nt, hipStream_t s);
 
 // interface system (iface.hip)
-hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, const Seed* basis,
+hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, int nrow_max, const Seed* basis,
                           const int* seed_off, const double* tr_u, const double* tr_phi,
                           const double* tr_beta, const double* ubar, const double* pibar,
                           double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s);
