@@ -339,11 +339,23 @@ __global__ void k_bcr_scatter(const double* __restrict__ RB, const double* __res
   pool[(long long)(kind * M + li) * bs + (long long)ri * bp + rc] = v;
 }
 
-// Identity on the padded diagonal of every D block.
-__global__ void k_bcr_pad(double* __restrict__ pool, const int* __restrict__ lsize, int bp) {
-  const int k = blockIdx.x;
+// Initial state of the reduction in one pass: the 3M blocks [D | L | U] of
+// the pool zero except the identity on the padded diagonal of every D
+// block (rows and columns past the layer's size), and the M right-hand-side
+// vectors zero.  The scatter then writes the nonzeros of the system, none
+// of which fall in the padding.
+__global__ void k_bcr_init(double* __restrict__ pool, double* __restrict__ vec,
+                           const int* __restrict__ lsize, int M, int bp) {
   const long long bs = (long long)bp * bp;
-  for (int r = lsize[k] + threadIdx.x; r < bp; r += blockDim.x) pool[k * bs + (long long)r * bp + r] = 1.0;
+  const long long npool = 3LL * M * bs, nvec = (long long)M * bp;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < npool) {
+    const long long k = e / bs, w = e - k * bs;
+    const int r = (int)(w / bp), cc = (int)(w - (long long)r * bp);
+    pool[e] = (k < M && r == cc && r >= lsize[k]) ? 1.0 : 0.0;
+  } else if (e < npool + nvec) {
+    vec[e - npool] = 0.0;
+  }
 }
 
 // x (layer-major, padded) -> X (unknown order).
@@ -408,14 +420,16 @@ hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl
                               const int* col_loc, int M, int bp, double* pool, double* vec,
                               const int* lsize, hipStream_t s) {
   const long long tot = (long long)n * (kl + ku + 1);
+  (void)lsize;
   hipLaunchKernelGGL(k_bcr_scatter, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, RB, rhs, n,
                      kl, ku, row_lvl, row_loc, col_lvl, col_loc, M, bp, pool, vec);
-  hipLaunchKernelGGL(k_bcr_pad, dim3(M), dim3(64), 0, s, pool, lsize, bp);
   return hipGetLastError();
 }
 
-hipError_t launch_bcr_pad(double* pool, const int* lsize, int M, int bp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcr_pad, dim3(M), dim3(64), 0, s, pool, lsize, bp);
+hipError_t launch_bcr_init(double* pool, double* vec, const int* lsize, int M, int bp, hipStream_t s) {
+  const long long tot = 3LL * M * bp * bp + (long long)M * bp;
+  hipLaunchKernelGGL(k_bcr_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, pool, vec, lsize,
+                     M, bp);
   return hipGetLastError();
 }
 

@@ -117,6 +117,9 @@ struct mrcm_ctx {
 
   // reverse mode: checkpoints of the smoothing state and adjoint workspace
   bool ckpt = false;
+  // error flags: work that can set them bumps epoch; check_flags reads the
+  // flags once per epoch (later output calls add no flag-setting work)
+  long long epoch = 0, checked_epoch = -1;
   double *ck_p = nullptr, *ck_g = nullptr;
   int ck_cap = 0, n_ck = 0, n_phase = 0;
   double *a_pb = nullptr, *a_gfb = nullptr, *a_Kb = nullptr, *a_Xb = nullptr, *a_nu = nullptr;
@@ -768,8 +771,8 @@ mrcm_status run_bcr_ops(mrcm_ctx* c, hipStream_t s) {
 mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
   const int M = c->bcr_M, bp = c->bcr_bp;
   const long long bs = (long long)bp * bp;
-  HIPCHK(c, launch_fill(c->bpool, 0.0, 3LL * M * bs, s));
-  HIPCHK(c, launch_fill(c->bvec, 0.0, (long long)M * bp, s));
+  (void)bs;
+  HIPCHK(c, launch_bcr_init(c->bpool, c->bvec, c->d_lsize, M, bp, s));
   HIPCHK(c, launch_bcr_scatter(c->AB, c->rhs, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
                                c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, c->d_lsize, s));
   {
@@ -781,9 +784,11 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
 }
 
 mrcm_status check_flags(mrcm_ctx* c) {
+  if (c->checked_epoch == c->epoch) return MRCM_OK;
   int fl = 0;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(&fl, c->flags, sizeof(int), hipMemcpyDeviceToHost));
+  if (!fl) c->checked_epoch = c->epoch;
   if (fl & kFlagBadK) return fail(c, MRCM_EINVAL, "permeability must be finite and positive");
   if (fl & kFlagNotPD) return fail(c, MRCM_ENOTPD, "local factorisation met a non-positive pivot");
   if (fl & kFlagSingular) return fail(c, MRCM_ESINGULAR, "interface system is singular");
@@ -957,6 +962,7 @@ mrcm_status mrcm_set_precision(mrcm_ctx* c, mrcm_precision prec, double tol, int
 
 mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   if (!c) return MRCM_EINVAL;
+  ++c->epoch;
   if (!c->have_k) return fail(c, MRCM_ESTATE, "permeability not set");
   if (!c->have_part) return fail(c, MRCM_ESTATE, "partition not set");
   if (!c->plan_valid) {
@@ -1005,6 +1011,7 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
 
 mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   if (!c) return MRCM_EINVAL;
+  ++c->epoch;
   if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
   hipStream_t s = c->stream;
   HIPCHK(c, hipEventRecord(c->ev[2], s));
@@ -1151,6 +1158,7 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* c, int use_graph, int threads_per_box) 
 
 mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   if (!c) return MRCM_EINVAL;
+  ++c->epoch;
   if (c->state < 2) return fail(c, MRCM_ESTATE, "interface not solved");
   if (nsteps < 0) return fail(c, MRCM_EINVAL, "nsteps < 0");
   if (nsteps > 0 && c->beta_sm != c->beta_mbf && !c->facs) {
@@ -1236,6 +1244,7 @@ mrcm_status mrcm_set_checkpointing(mrcm_ctx* c, int on) {
 
 mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux, double* dJdlogK) {
   if (!c) return MRCM_EINVAL;
+  ++c->epoch;
   if (!dJdlogK) return fail(c, MRCM_EINVAL, "output is NULL");
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution to differentiate");
   if (c->prec != MRCM_FP64 || !c->wave || c->d != 2)
@@ -1293,11 +1302,10 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
     HIPCHK(c, launch_moments(g, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis, c->d_seed_off, c->tr_u,
                              c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab, c->kl, c->ku,
                              c->rhs, s));
-    HIPCHK(c, launch_fill(c->bpool, 0.0, 3LL * M * bs, s));
-    HIPCHK(c, launch_fill(c->bvec, 0.0, (long long)M * bp, s));
+    (void)bs;
+    HIPCHK(c, launch_bcr_init(c->bpool, c->bvec, c->d_lsize, M, bp, s));
     HIPCHK(c, launch_bcr_scatter_t(c->AB, c->a_Xb, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
                                    c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, s));
-    HIPCHK(c, launch_bcr_pad(c->bpool, c->d_lsize, M, bp, s));
     {
       mrcm_status st = run_bcr_ops(c, s);
       if (st) return st;

@@ -170,7 +170,8 @@ hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks
                            hipStream_t s);
 hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* col_loc, int n, int bp,
                              double* X, hipStream_t s);
-hipError_t launch_bcr_pad(double* pool, const int* lsize, int M, int bp, hipStream_t s);
+// zero pool and right-hand sides, identity on the padded diagonals of D
+hipError_t launch_bcr_init(double* pool, double* vec, const int* lsize, int M, int bp, hipStream_t s);
 
 // adjoint (adjoint.hip): reverse mode of the 2-D FP64 path
 size_t adj_smooth_lds_bytes(int m0, int m1);
