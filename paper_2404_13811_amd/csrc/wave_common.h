@@ -264,19 +264,20 @@ __device__ __forceinline__ void wbuild_t(int nb, int j, int tpi, const BoxLds& s
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
   const int cc = c < nb ? c : 0;
-  const bool hp = tpi >= 0;
+  // Unconditional, contiguous reads (paired by the compiler); a missing
+  // previous block is a zero factor, not a select on the loads.  Rows past
+  // nb read on into the next LDS array of the box and are discarded below.
+  const double hpf = tpi >= 0 ? 1.0 : 0.0;
   const double* D = s.Dg + j * nb;
   const double* Tx = s.Tx + j * nb;
-  const double* Tp = s.Tn + (hp ? tpi : 0) * nb;
+  const double* Tp = s.Tn + (tpi >= 0 ? tpi : 0) * nb;
   const double dc = D[cc], txc = Tx[cc];
-  const double tc = hp ? Tp[cc] : 0.0;
+  const double tc = Tp[cc] * hpf;
   double tr[HB], tpr[HB];
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
-    const int r = HB * h + i;
-    const int rr = r < nb ? r : 0;
-    tr[i] = Tx[rr];
-    tpr[i] = hp ? Tp[rr] : 0.0;
+    tr[i] = Tx[HB * h + i];
+    tpr[i] = Tp[HB * h + i];
   }
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
