@@ -241,12 +241,13 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
   }
   __syncthreads();
   const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
+  // one pass per side of Omega_i: with a subdomain one cell thick along a,
+  // both sides of that axis add to the same cells
 #pragma unroll 1
-  for (int a = 0; a < 2; ++a) {
+  for (int q = 0; q < 4; ++q) {
+    const int a = q >> 1, so = q & 1;
     const int nf = a == 0 ? g.S[1] : g.S[0];
-    for (int u = tid; u < 2 * nf; u += NT) {
-      const int so = u >= nf, t = u - (so ? nf : 0);
-      const int q = 2 * a + so;
+    for (int t = tid; t < nf; t += NT) {
       const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
       if (!has) continue;
       int cx, cy;
@@ -515,12 +516,13 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
   }
   wsync();
   const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
-  for (int a = 0; a < 2; ++a) {
+  // one pass per side of Omega_i: with a subdomain one cell thick along a,
+  // both sides of that axis add to the same cells
+  for (int q = 0; q < 4; ++q) {
+    const int a = q >> 1, so = q & 1;
     const int nf = a == 0 ? g.S[1] : g.S[0];
-    for (int e = L; e < nrhs * 2 * nf; e += 64) {
-      const int k = e / (2 * nf), u = e % (2 * nf);
-      const int so = u >= nf, t = u - (so ? nf : 0);
-      const int q = 2 * a + so;
+    for (int e = L; e < nrhs * nf; e += 64) {
+      const int k = e / nf, t = e % nf;
       const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
       if (!has) continue;
       const int go = q == 0 ? g.gside_off[0] : q == 1 ? g.gside_off[1] : q == 2 ? g.gside_off[2] : g.gside_off[3];
@@ -614,11 +616,10 @@ __global__ void __launch_bounds__(64) k_adj_particular(Geo g, const Box* __restr
   }
   wsync();
   const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
-  for (int a = 0; a < 2; ++a) {
+  for (int q = 0; q < 4; ++q) {  // one pass per side, as above
+    const int a = q >> 1, so = q & 1;
     const int nf = a == 0 ? g.S[1] : g.S[0];
-    for (int u = L; u < 2 * nf; u += 64) {
-      const int so = u >= nf, t = u - (so ? nf : 0);
-      const int q = 2 * a + so;
+    for (int t = L; t < nf; t += 64) {
       const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
       if (!has) continue;
       const int go = q == 0 ? g.gside_off[0] : q == 1 ? g.gside_off[1] : q == 2 ? g.gside_off[2] : g.gside_off[3];

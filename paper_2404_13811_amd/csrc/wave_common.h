@@ -583,28 +583,39 @@ __device__ __forceinline__ void smooth_rhs(const Geo& g, const Box& B, const Smo
 #pragma unroll 1
   for (int loc = tid; loc < nc; loc += NT) out[loc] = r.F[loc] * g.vol;
   bsync<NT>();
+  // both sides of an axis in one pass, except in a box one cell thick
+  // along that axis, where they add to the same cells: then one pass each
+  auto face = [&](int a, int sd, int t) {
+    const int x = a == 0 ? (sd ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
+    const int y = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
+    const int c[3] = {x, y, 0};
+    const int kind = face_kind(g, B, c, a, sd);
+    const double kc = s.Kt[tile_at(s, B, x, y)];
+    double add;
+    if (kind == kFaceRobin) {
+      const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
+      double bt, TR;
+      robin_face(g, a, kc, s.Kt[tile_at(s, B, ox, oy)], beta, bt, TR);
+      add = TR * lambda_s(g, B, r, bt, x, y, a, sd);
+    } else {
+      const double val = r.BC[side_off(s, 2 * a + sd) + t];
+      add = kind == kFaceDir ? 2.0 * kc * g.area / g.h * val : -g.area * val;
+    }
+    out[bloc(B, s, x, y)] += add;
+  };
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int nf = a == 0 ? s.m1 : s.m0;
+    const int ma = a == 0 ? s.m0 : s.m1;
+    if (ma > 1) {
 #pragma unroll 1
-    for (int u = tid; u < 2 * nf; u += NT) {
-      const int sd = u >= nf, t = u - (sd ? nf : 0);
-      const int x = a == 0 ? (sd ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
-      const int y = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
-      const int c[3] = {x, y, 0};
-      const int kind = face_kind(g, B, c, a, sd);
-      const double kc = s.Kt[tile_at(s, B, x, y)];
-      double add;
-      if (kind == kFaceRobin) {
-        const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
-        double bt, TR;
-        robin_face(g, a, kc, s.Kt[tile_at(s, B, ox, oy)], beta, bt, TR);
-        add = TR * lambda_s(g, B, r, bt, x, y, a, sd);
-      } else {
-        const double val = r.BC[side_off(s, 2 * a + sd) + t];
-        add = kind == kFaceDir ? 2.0 * kc * g.area / g.h * val : -g.area * val;
-      }
-      out[bloc(B, s, x, y)] += add;
+      for (int u = tid; u < 2 * nf; u += NT) face(a, u >= nf, u - (u >= nf ? nf : 0));
+    } else {
+#pragma unroll 1
+      for (int t = tid; t < nf; t += NT) face(a, 0, t);
+      bsync<NT>();
+#pragma unroll 1
+      for (int t = tid; t < nf; t += NT) face(a, 1, t);
     }
     bsync<NT>();
   }

@@ -78,6 +78,10 @@ CASES = {
     "neumann_wells_l0": (lambda: make_workload("c2", scale=8, overlap=0), 2),
     "beta_const": (lambda: make_workload("c1", scale=2), 2),
     "no_smoothing": (lambda: _small(space="linear", overlap=2), 0),
+    # subdomains one and two cells thick: both sides of an axis touch the
+    # same cells in the box right-hand sides and their adjoints
+    "thin_rows_l0": (lambda: _small(space="const", overlap=0, sub=(8, 1)), 2),
+    "thin_rows_l1": (lambda: _small(space="const", overlap=1, sub=(8, 2)), 2),
 }
 
 

@@ -55,6 +55,13 @@ def test_small_with_smoothing(overlap):
     _check(_small(space="linear", overlap=overlap), nsmooth=3)
 
 
+@pytest.mark.parametrize("suby,overlap", [(1, 0), (2, 0), (2, 1), (4, 3)])
+def test_short_boxes_with_smoothing(suby, overlap):
+    # boxes of 1 to 10 lines (truncated ones at the domain edge): the halves
+    # of the two-ended box sweep are empty, one block or a few blocks long
+    _check(_small(space="const", overlap=overlap, sub=(8, suby)), nsmooth=2)
+
+
 @pytest.mark.parametrize("overlap", [0, 1, 2])
 def test_fine_spaces_prop2(overlap):
     _check(_small(space="fine", overlap=overlap), nsmooth=0)
