@@ -42,10 +42,10 @@ FLUX_TOL = 1e-6
 # hash to the value it was taken with; otherwise the traffic is reported null.
 TRAFFIC = {
     # kernel: (source files, sha256 prefix, fetch KiB, write KiB, workload)
-    "k_smooth_w": (("local_wave.hip",), "dc70e40408ca7b7b", 4393.1, 158.0, "c2 overlap 4"),
-    "k_basis_w": (("local_wave.hip",), "dc70e40408ca7b7b", 13216.1, 33022.5, "c2 overlap 4"),
-    "k_smooth32": (("local_wave32.hip",), "c77a018678bfff26", 2695.7, 162.0, "c2 overlap 4"),
-    "k_basis32": (("local_wave32.hip",), "c77a018678bfff26", 8077.0, 18915.0, "c2 overlap 4"),
+    "k_smooth_w": (("local_wave.hip",), "532a8d5acc8389da", 4468.1, 158.0, "c2 overlap 4"),
+    "k_local_w": (("local_wave.hip",), "532a8d5acc8389da", 17812.6, 55513.5, "c2 overlap 4"),
+    "k_smooth32": (("local_wave32.hip",), "3c097b55cb1db6d6", 2701.1, 162.0, "c2 overlap 4"),
+    "k_local32": (("local_wave32.hip",), "3c097b55cb1db6d6", 10265.4, 23795.0, "c2 overlap 4"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -60,7 +60,7 @@ def traffic(kern, wl):
     files, digest, fk, wk, _ = rec
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2404_13811_amd", "csrc")
-    for f in files + ("wave_common.h", "local_common.h", "mrcm_internal.h"):
+    for f in files + ("wave_common.h", "local_common.h", "mrcm_internal.h", "pivot4.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest()[:16] != digest:
@@ -228,15 +228,22 @@ def roofline(wl, form, phases, st):
                 "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic(kern, wl),
                 "work_per_launch": "%.0f bytes" % per_launch,
                 "avg_launch_us": t_smooth_launch * 1e6}
-    # basis kernel: Gauss-Jordan inverse of every line block (nb^3 FMA) and the
-    # forward + backward block products of every seed (2 nb^2 FMA per block)
+    # local kernel (basis boxes, particular problems and, in FP64, the
+    # backward factors of the two-ended smoothing sweep, in one launch):
+    # Gauss-Jordan inverse of every line block (nb^3 FMA) and the forward +
+    # backward block products of every right-hand side (2 nb^2 FMA per block)
     flops = 0.0
     for dims, nseed in bx:
         nb, nblk = dims[0], int(np.prod(dims[1:]))
         flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb * nseed
+        if form != "fp32_refine":
+            flops += 2.0 * nblk * nb ** 3  # backward inverses and meeting block
+    for _ in range(int(np.prod(wl.ncell)) // int(np.prod(S))):
+        nb, nblk = S[0], int(np.prod(S[1:]))
+        flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb
     achieved = flops / t_basis
     peak = PEAK_FP32 if form == "fp32_refine" else PEAK_FP64
-    kern = "k_basis32" if form == "fp32_refine" else "k_basis_w"
+    kern = "k_local32" if form == "fp32_refine" else "k_local_w"
     return {"kernel": kern, "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic(kern, wl),
             "work_per_launch": "%.0f flop" % flops, "avg_launch_us": t_basis * 1e6}
