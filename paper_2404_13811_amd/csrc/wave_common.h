@@ -502,7 +502,13 @@ __device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const S
   const int n0 = g.n[0], n1 = g.n[1];
   const int lo0 = B.lo[0], lo1 = B.lo[1];
   const double* tg = tcoup ? tcoup + B.scr : nullptr;
-  gather<64 * 16 / NT, NT>(s.Kt, 2 * nt + 2 * nc, [&](int e, double& fill) -> const double* {
+  // per side q: a box side on the domain boundary reads its boundary values;
+  // with non-overlapping boxes an interior side reads the neighbour's flux
+  const int Mx = g.M[0];
+  const int isub = B.sub % Mx, jsub = B.sub / Mx;
+  // one gather over the contiguous LDS arrays Kt, P, F, Tn, GF, BC, with
+  // about 12 loads per thread in flight (a 24 x 24 box needs one round)
+  gather<64 * 48 / NT, NT>(s.Kt, 2 * nt + 2 * nc + 2 * ns, [&](int e, double& fill) -> const double* {
     if (e < 2 * nt) {
       const bool isk = e < nt;
       const int u = isk ? e : e - nt;
@@ -514,13 +520,8 @@ __device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const S
     e -= 2 * nt;
     if (e < nc) return f + (lo0 + e % m0) + n0 * (lo1 + e / m0);
     e -= nc;
-    return tg ? tg + e : nullptr;
-  });
-  // per side q: a box side on the domain boundary reads its boundary values;
-  // with non-overlapping boxes an interior side reads the neighbour's flux
-  const int Mx = g.M[0];
-  const int isub = B.sub % Mx, jsub = B.sub / Mx;
-  gather<64 * 4 / NT < 1 ? 1 : 64 * 4 / NT, NT>(r.GF, 2 * ns, [&](int e, double& fill) -> const double* {
+    if (e < nc) return tg ? tg + e : nullptr;
+    e -= nc;
     fill = 0.0;
     const bool isgf = e < ns;
     const int u = isgf ? e : e - ns;
