@@ -24,18 +24,19 @@ namespace {
 
 // ------------------------------------------------------------------ inverse
 // In-place Gauss-Jordan inversion of one n x n block (n <= 128, n % 8 == 0)
-// per workgroup of 512 threads; thread (tr, tc) holds the 8 x 4 tile at rows
-// 8 tr.., columns 4 tc.. in registers.  Pivots are taken four at a time
+// per workgroup of 512 threads; thread (tr, tc) holds the 4 x 8 tile at rows
+// 4 tr.., columns 8 tc.. in registers.  Pivots are taken four at a time
 // (block Gauss-Jordan without pivoting): for the pivot rows and columns K,
 // with P = A[K][K],
 //   A[K][j] <- P^{-1} A[K][j],   A[i][K] <- -A[i][K] P^{-1},
 //   A[K][K] <- P^{-1},           A[i][j] <- A[i][j] - A[i][K] P^{-1} A[K][j],
-// which equals four scalar pivot steps.  One step:
-//   1. the owners of rows K and of columns K (one tile column) publish them
-//      to LDS (barrier);
-//   2. every thread factors the 4 x 4 block P (closed form, no exchange)
-//      and thread t < n forms column t of R = P^{-1} A~[K][:], where A~
-//      has unit vectors in the columns K (barrier);
+// which equals four scalar pivot steps.  The pivot rows of a step are one
+// tile row (16 threads of one wave) and the pivot columns half a tile
+// column, so few LDS store instructions publish them.  One step:
+//   1. the owners of rows K and of columns K publish them (barrier);
+//   2. threads t < n factor the 4 x 4 block P (closed form, no exchange)
+//      and form column t of R = P^{-1} A~[K][:], where A~ has unit vectors
+//      in the columns K (barrier);
 //   3. every thread applies the rank-4 update A[i][j] <- A[i][j] -
 //      A[i][K] R[:, j] to its tile (zero base in the columns K) and the
 //      owners of rows K take R.
@@ -43,7 +44,7 @@ namespace {
 // pivots.  R is stored in 16-byte pieces interleaved over the tile columns
 // so that the update reads are free of bank conflicts.  Two waves per SIMD
 // hide each other's LDS latency.
-constexpr int TR = 8, PB = 4;  // tile rows; pivots per step = tile columns
+constexpr int TR = 4, TC = 8, PB = 4;  // tile rows / columns; pivots per step
 constexpr int kInvThreads = 512;
 
 __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ pool,
@@ -53,30 +54,31 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
   __shared__ __align__(16) double cpan[2][kBcrInvMax * PB];  // [row][m] = A[row][k + m]
   __shared__ __align__(16) double rpp[2][PB * kBcrInvMax];   // R, interleaved pieces
   double* A = pool + offs[blockIdx.x];
-  const int ntr = bp / TR, ntc = bp / PB;  // tiles per column / per row
+  const int ntr = bp / TR, ntc = bp / TC;  // tiles per column / per row
   const int t = threadIdx.x;
   const bool act = t < ntr * ntc;
   const int tr = act ? t / ntc : -1, tc = act ? t - (t / ntc) * ntc : -1;
-  const int r0 = tr * TR, c0 = tc * PB;
-  double w[TR][PB];
+  const int r0 = tr * TR, c0 = tc * TC;
+  double w[TR][TC];
   if (act) {
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
       const double2* src = reinterpret_cast<const double2*>(A + (long long)(r0 + i) * ld + c0);
-      const double2 u = src[0], v = src[1];
-      w[i][0] = u.x;
-      w[i][1] = u.y;
-      w[i][2] = v.x;
-      w[i][3] = v.y;
+#pragma unroll
+      for (int jj = 0; jj < TC / 2; ++jj) {
+        const double2 u = src[jj];
+        w[i][2 * jj] = u.x;
+        w[i][2 * jj + 1] = u.y;
+      }
     }
   }
   bool bad = false;
-  for (int kt = 0; kt < ntr; ++kt) {
-    const bool own_r = tr == kt;
+  for (int kt = 0; kt < ntc; ++kt) {
+    const bool own_c = tc == kt;
 #pragma unroll
-    for (int k2 = 0; k2 < TR; k2 += PB) {
-      const int k = kt * TR + k2;
-      const bool own_c = c0 == k;
+    for (int k2 = 0; k2 < TC; k2 += PB) {
+      const int k = kt * TC + k2;
+      const bool own_r = tr == k / TR;
       double* rp = rpan[k2 / PB];
       double* cp = cpan[k2 / PB];
       double* rq = rpp[k2 / PB];
@@ -84,16 +86,16 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
 #pragma unroll
         for (int m = 0; m < PB; ++m) {
           double2* d = reinterpret_cast<double2*>(rp + m * kBcrInvMax + c0);
-          d[0] = make_double2(w[k2 + m][0], w[k2 + m][1]);
-          d[1] = make_double2(w[k2 + m][2], w[k2 + m][3]);
+#pragma unroll
+          for (int jj = 0; jj < TC / 2; ++jj) d[jj] = make_double2(w[m][2 * jj], w[m][2 * jj + 1]);
         }
       }
       if (own_c) {
 #pragma unroll
         for (int i = 0; i < TR; ++i) {
           double2* d = reinterpret_cast<double2*>(cp + (r0 + i) * PB);
-          d[0] = make_double2(w[i][0], w[i][1]);
-          d[1] = make_double2(w[i][2], w[i][3]);
+          d[0] = make_double2(w[i][k2], w[i][k2 + 1]);
+          d[1] = make_double2(w[i][k2 + 2], w[i][k2 + 3]);
         }
       }
       __syncthreads();
@@ -114,19 +116,19 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
         for (int m = 0; m < PB; ++m)
           r[m] = fma(rp[m * kBcrInvMax + t], pc ? 0.0 : 1.0, (pc && ck == m) ? 1.0 : 0.0);
         piv_apply(q, r, v);
-        const int tq = t / PB, jj = (t % PB) / 2, e = t & 1;
+        const int tq = t / TC, jj = (t % TC) / 2, e = t & 1;
 #pragma unroll
-        for (int m = 0; m < PB; ++m) rq[((m * 2 + jj) * ntc + tq) * 2 + e] = v[m];
+        for (int m = 0; m < PB; ++m) rq[((m * (TC / 2) + jj) * ntc + tq) * 2 + e] = v[m];
       }
       __syncthreads();
       if (act) {
-        double rv[PB][PB], cv[TR][PB];
+        double rv[PB][TC], cv[TR][PB];
         const double2* q2 = reinterpret_cast<const double2*>(rq);
 #pragma unroll
         for (int m = 0; m < PB; ++m)
 #pragma unroll
-          for (int jj = 0; jj < 2; ++jj) {
-            const double2 x = q2[(m * 2 + jj) * ntc + tc];
+          for (int jj = 0; jj < TC / 2; ++jj) {
+            const double2 x = q2[(m * (TC / 2) + jj) * ntc + tc];
             rv[m][2 * jj] = x.x;
             rv[m][2 * jj + 1] = x.y;
           }
@@ -139,12 +141,17 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
           cv[i][2] = b.x;
           cv[i][3] = b.y;
         }
-        const double base = own_c ? 0.0 : 1.0;
+        if (own_c) {
+#pragma unroll
+          for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int m = 0; m < PB; ++m) w[i][k2 + m] = 0.0;
+        }
 #pragma unroll
         for (int i = 0; i < TR; ++i)
 #pragma unroll
-          for (int j = 0; j < PB; ++j) {
-            double acc = w[i][j] * base;
+          for (int j = 0; j < TC; ++j) {
+            double acc = w[i][j];
 #pragma unroll
             for (int m = 0; m < PB; ++m) acc = fma(-cv[i][m], rv[m][j], acc);
             w[i][j] = acc;
@@ -153,7 +160,7 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
 #pragma unroll
           for (int m = 0; m < PB; ++m)
 #pragma unroll
-            for (int j = 0; j < PB; ++j) w[k2 + m][j] = rv[m][j];
+            for (int j = 0; j < TC; ++j) w[m][j] = rv[m][j];
         }
       }
     }
@@ -162,8 +169,8 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
       double2* dst = reinterpret_cast<double2*>(A + (long long)(r0 + i) * ld + c0);
-      dst[0] = make_double2(w[i][0], w[i][1]);
-      dst[1] = make_double2(w[i][2], w[i][3]);
+#pragma unroll
+      for (int jj = 0; jj < TC / 2; ++jj) dst[jj] = make_double2(w[i][2 * jj], w[i][2 * jj + 1]);
     }
   }
   if (bad) atomicOr(flags, kFlagSingular);
@@ -370,7 +377,7 @@ __global__ void k_bcr_gather(const double* __restrict__ xv, const int* __restric
 hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
                           hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
-  if (n % TR || n > kBcrInvMax) return hipErrorInvalidValue;
+  if (n % TC || n > kBcrInvMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_bcr_inv, dim3(nblk), dim3(kInvThreads), 0, s, pool, offs, n, ld, flags);
   return hipGetLastError();
 }
