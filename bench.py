@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--precision", default="best", choices=["best", "fp64", "fp32_refine"])
     ap.add_argument("--tol", type=float, default=1e-12,
                     help="componentwise backward-error tolerance of the refinement")
+    ap.add_argument("--smoothing", default="graph", choices=["graph", "persistent"],
+                    help="smoothing sweeps as a replayed graph of per-colour launches, or all "
+                         "colour phases of a call in one cooperative launch (FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other overlaps")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -85,12 +88,13 @@ def parse():
     return ap.parse_args()
 
 
-def time_solves(wl, precision, steps, warmup, tol):
+def time_solves(wl, precision, steps, warmup, tol, persistent=False):
     import torch
     import paper_2404_13811_amd as m
     from paper_2404_13811_amd import api
     ctx = m.create(wl.dim, wl.ncell, wl.h)
     api.configure(ctx, wl, precision, tol=tol, max_refine=30)
+    m.set_smoothing_persistent(ctx, persistent)
     p = torch.empty(wl.ncells, dtype=torch.float64, device="cuda")
     fl = torch.empty(wl.ncells * 2 * wl.dim, dtype=torch.float64, device="cuda")
 
@@ -204,6 +208,7 @@ def roofline(wl, form, phases, st):
     word = 4 if form == "fp32_refine" else 8
     solves = max(st["refine_max_iters"], 1) if form == "fp32_refine" else 1
     n_launch = max(st["n_smooth_launches"], 1)
+    phases_per_launch = max(st["n_smooth_phases"], 1) / n_launch
     t_smooth_launch = phases["ms_smooth"] / n_launch * 1e-3
     t_basis = phases["ms_basis_kernel"] * 1e-3
     cand = {"basis": t_basis, "smooth": phases["ms_smooth"] * 1e-3}
@@ -220,10 +225,13 @@ def roofline(wl, form, phases, st):
             halo = int(np.prod([d + 2 for d in dims]))
             total += solves * nblk * nb * nb * word + ncb * 8 + 2 * halo * 8 + ncb * 8
             total += int(np.prod(S)) * 8 + 2 * wl.dim * int(np.prod(S[1:])) * 8
-        # every box is solved once per sweep, and a sweep has 2^d launches
-        per_launch = total / (2 ** wl.dim)
+        # every box is solved once per sweep of 2^d colour phases; a launch
+        # runs one phase, or all phases of the call in the persistent form
+        per_launch = total / (2 ** wl.dim) * phases_per_launch
         achieved = per_launch / t_smooth_launch
         kern = "k_smooth32" if form == "fp32_refine" else "k_smooth_w"
+        if st["smooth_persistent"]:
+            kern = "k_smooth_grid"
         return {"kernel": kern, "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic(kern, wl),
                 "work_per_launch": "%.0f bytes" % per_launch,
@@ -277,7 +285,8 @@ def main():
     forms = {}
     for form in ("fp32_refine", "fp64"):
         steps = args.steps if args.precision in ("best", form) else max(3, args.steps // 2)
-        dt, ph, st, p, fl = time_solves(wl, form, steps, args.warmup, args.tol)
+        dt, ph, st, p, fl = time_solves(wl, form, steps, args.warmup, args.tol,
+                                        args.smoothing == "persistent")
         forms[form] = {"dt": dt, "phases": ph, "stats": st, "p": p, "fl": fl, "steps": steps}
     cpu = None
     if not args.no_cpu_baseline:
@@ -323,7 +332,8 @@ def main():
             if l == args.overlap:
                 continue
             w2 = make_workload(args.workload, overlap=l)
-            d3, ph3, _, _, _ = time_solves(w2, head, max(3, args.steps // 2), 2, args.tol)
+            d3, ph3, _, _, _ = time_solves(w2, head, max(3, args.steps // 2), 2, args.tol,
+                                           args.smoothing == "persistent")
             extra["overlap_%d" % l] = {"ms_per_step": round(d3 * 1e3, 4), "value": w2.ncells / d3,
                                        **{k: round(v, 4) for k, v in ph3.items()}}
     line = {
@@ -342,6 +352,8 @@ def main():
         "config": {"workload": "%s: %dx%d cells, subdomains %s, overlap %d, %s spaces, %d smoothing steps"
                    % (args.workload, wl.ncell[0], wl.ncell[1], "x".join(map(str, wl.sub)),
                       wl.overlap, wl.space, wl.nsmooth),
+                   "smoothing": "one cooperative launch per call" if st["smooth_persistent"]
+                   else "graph of per-colour launches",
                    "precision": head, "interface_unknowns": st["n_unknowns"],
                    "interface_solver": {1: "band_lu", 2: "block_cyclic_reduction"}[st["interface_solver"]]},
         head: form_summary(H, head),

@@ -107,6 +107,9 @@ typedef struct {
   int smooth_threads;      /* threads per box of the smoothing kernels         */
   int smooth_graph;        /* 1: sweeps replay a captured graph                */
   double ms_autotune;      /* device time of the last smoothing autotune       */
+  int n_smooth_phases;     /* colour phases run by the last mrcm_smooth        */
+  int smooth_persistent;   /* 1: the last mrcm_smooth ran as one cooperative
+                              launch                                          */
 } mrcm_stats;
 
 /* Create a context for a dim-dimensional grid (dim = 2 or 3) of
@@ -172,6 +175,20 @@ mrcm_status mrcm_smooth(mrcm_ctx* ctx, int nsteps);
  * outside the timed region of mrcm_smooth).  The choice does not change the
  * results.  Errors: MRCM_EINVAL. */
 mrcm_status mrcm_set_smoothing(mrcm_ctx* ctx, int use_graph, int threads_per_box);
+
+/* Persistent form of the smoothing sweeps (Steps 6-7, Algorithm 1's loop
+ * over the colours).  on != 0: each mrcm_smooth runs all its colour phases
+ * in ONE cooperative launch; the workgroups (as many as the device holds at
+ * once, at most max_groups when max_groups > 0, never more than the boxes of
+ * the largest colour) loop over the boxes of a colour and meet at a
+ * device-wide barrier between colours, which removes the launch gaps
+ * between phases.  Applies to MRCM_FP64 contexts using the wave-per-box
+ * kernels (2-D boxes, lines of at most 32 cells) without checkpointing;
+ * otherwise, or when the device has no cooperative launch, mrcm_smooth uses
+ * the per-phase launches of mrcm_set_smoothing.  The threads per box are the
+ * ones mrcm_set_smoothing selects.  Results are bit-identical to the
+ * per-phase form.  Default: off.  Errors: MRCM_EINVAL (max_groups < 0). */
+mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* ctx, int on, int max_groups);
 
 /* Pressure per cell (N values); shifted to zero mean when no side carries a
  * pressure condition. */

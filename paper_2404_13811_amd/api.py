@@ -97,6 +97,11 @@ def set_smoothing(ctx, use_graph=True, threads_per_box=0):
            _lib.load().mrcm_set_smoothing(ctx.handle, int(bool(use_graph)), int(threads_per_box)))
 
 
+def set_smoothing_persistent(ctx, on=True, max_groups=0):
+    _check(ctx, "mrcm_set_smoothing_persistent",
+           _lib.load().mrcm_set_smoothing_persistent(ctx.handle, int(bool(on)), int(max_groups)))
+
+
 def set_robin(ctx, mode, mbf, smooth_value):
     m = BETA[mode] if isinstance(mode, str) else int(mode)
     _check(ctx, "mrcm_set_robin", _lib.load().mrcm_set_robin(ctx.handle, m, float(mbf), float(smooth_value)))

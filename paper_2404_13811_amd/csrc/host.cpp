@@ -108,6 +108,10 @@ struct mrcm_ctx {
   // chosen value, and the captured sweep graph
   int smooth_nt_req = 0, smooth_nt = 0;
   bool use_graph = true;
+  // one cooperative launch per mrcm_smooth call (FP64 wave kernels), with
+  // at most persist_groups workgroups (0 = as many as fit)
+  bool persist = false, persist_used = false;
+  int persist_groups = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -133,6 +137,7 @@ struct mrcm_ctx {
   bool timed_basis = false, timed_iface = false, timed_smooth = false;
   int n_local_solves = 0;
   int n_smooth_launches = 0;
+  int n_smooth_phases = 0;
 };
 
 namespace {
@@ -1156,6 +1161,14 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* c, int use_graph, int threads_per_box) 
   return MRCM_OK;
 }
 
+mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* c, int on, int max_groups) {
+  if (!c) return MRCM_EINVAL;
+  if (max_groups < 0) return fail(c, MRCM_EINVAL, "max_groups < 0");
+  c->persist = on != 0;
+  c->persist_groups = max_groups;
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   if (!c) return MRCM_EINVAL;
   ++c->epoch;
@@ -1194,8 +1207,28 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
       c->ck_cap = cap;
     }
   }
+  const int nphase = nsteps << c->d;
+  const bool try_grid = c->persist && c->wave && c->prec != MRCM_FP32_REFINE && !c->ckpt;
   HIPCHK(c, hipEventRecord(c->ev[4], s));
-  c->n_smooth_launches = nsteps << c->d;
+  c->n_smooth_launches = nphase;
+  c->n_smooth_phases = nphase;
+  c->persist_used = false;
+  if (try_grid && nphase > 0) {
+    SmoothPhases ph;
+    ph.ncol = 1 << c->d;
+    for (int col = 0; col <= ph.ncol; ++col) ph.off[col] = c->member_off[col];
+    const hipError_t e =
+        launch_smooth_grid(c->geo, c->d_obox, c->d_members, ph, nphase, c->K, c->f, c->bcv,
+                           c->beta_sm, c->fac, c->fact, c->tco, c->p, c->gflux, c->lds_smooth,
+                           c->smooth_nt, c->persist_groups, s);
+    if (e == hipSuccess) {
+      c->persist_used = true;
+      c->n_smooth_launches = 1;
+      nsteps = 0;  // all phases done
+    } else if (e != hipErrorNotSupported && e != hipErrorCooperativeLaunchTooLarge) {
+      HIPCHK(c, e);
+    }
+  }
   for (int step = 0; step < nsteps; ++step) {
     if (c->use_graph && !c->ckpt) {
       HIPCHK(c, hipGraphLaunch(c->graph_exec, s));
@@ -1204,10 +1237,10 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
       if (st) return st;
     }
   }
-  c->n_phase += nsteps << c->d;
+  c->n_phase += nphase;
   HIPCHK(c, hipEventRecord(c->ev[5], s));
   c->timed_smooth = true;
-  c->n_local_solves += nsteps * c->geo.nsub;
+  c->n_local_solves += (nphase >> c->d) * c->geo.nsub;
   return MRCM_OK;
 }
 
@@ -1368,6 +1401,8 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   out->smooth_threads = c->smooth_nt;
   out->smooth_graph = c->use_graph ? 1 : 0;
   out->ms_autotune = c->ms_autotune;
+  out->n_smooth_phases = c->n_smooth_phases;
+  out->smooth_persistent = c->persist_used ? 1 : 0;
   return check_flags(c);
 }
 

@@ -22,6 +22,10 @@
 // from memory four blocks ahead of their use.
 #include "wave_common.h"
 
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 namespace mrcm {
 namespace {
 
@@ -279,10 +283,39 @@ __global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ o
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-// Steps 6-7: one color phase of the smoothing sweep.  NT threads per box
-// (64, 128 or 256, chosen by the autotuner) stage the box's data, build the
-// right-hand side and write the outputs; the box solve is the twisted block
-// sweep, its two halves on the first two waves when NT >= 128.  The result
+// Factor blocks a box's smoothing solve needs first (the first ring slots of
+// both halves on waves 0 and 1, the meeting block on wave 0): constant data,
+// loaded early so that their memory latency overlaps other work.
+template <int NT>
+__device__ __forceinline__ void smooth_preload(const Box& B, const double* Wf, const double* Wt,
+                                               double w[RING][HB], double zm[HB]) {
+  const int wv = threadIdx.x >> 6;
+  if (NT > 64 && wv < 2) twist_preload(twist_half(B, wv == 0 ? Wf : Wt, B.nblk / 2, wv == 1), w);
+  if (threadIdx.x < 64) wload_block(block_src(Wt, B.nb, B.nblk), B.nblk / 2, zm);
+}
+
+// Steps 6-7 for one box: stage the box's data, build the right-hand side,
+// solve with the two-ended block sweep (its halves on the first two waves
+// when NT >= 128) and write p on Omega_i and Omega_i's Gamma fluxes.
+template <int NT>
+__device__ __forceinline__ void smooth_box(const Geo& g, const Box& B, const double* __restrict__ K,
+                                           const double* __restrict__ f,
+                                           const double* __restrict__ bcv, double beta,
+                                           const double* Wf, const double* Wt,
+                                           const double* __restrict__ tcoup, double* p,
+                                           double* gflux, double w[RING][HB], const double zm[HB],
+                                           double* dsm) {
+  SmoothLds r = carve_smooth(dsm, B);
+  stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
+  bsync<NT>();
+  smooth_rhs<NT>(g, B, r, beta, r.b.X);
+  bsync<NT>();
+  sweep_twisted<NT>(B, Wf, Wt, r.b, r.b.Z, w, zm);
+  smooth_out<NT>(g, B, r, r.b.X, beta, p, gflux);
+}
+
+// Steps 6-7: one color phase of the smoothing sweep, one workgroup of NT
+// threads (64, 128 or 256, chosen by the autotuner) per box.  The result
 // does not depend on NT.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ boxes,
@@ -297,23 +330,56 @@ __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ 
                                                  double* __restrict__ gflux) {
   extern __shared__ __align__(16) double dsm[];
   const Box B = boxes[members[blockIdx.x]];
-  const double* Wf = fac + B.fac;
-  const double* Wt = fact + B.fac;
-  // factor blocks needed first: in flight while the box data is staged
   double w[RING][HB], zm[HB];
-  const int wv = threadIdx.x >> 6;
-  if (NT > 64 && wv < 2) {
-    const int m = B.nblk / 2;
-    twist_preload(twist_half(B, wv == 0 ? Wf : Wt, m, wv == 1), w);
+  smooth_preload<NT>(B, fac + B.fac, fact + B.fac, w, zm);
+  smooth_box<NT>(g, B, K, f, bcv, beta, fac + B.fac, fact + B.fac, tcoup, p, gflux, w, zm, dsm);
+}
+
+// All colour phases of nphase / ncol smoothing steps in one cooperative
+// launch.  In phase k (colour k % ncol) workgroup b takes boxes b, b + G,
+// b + 2G, ... of that colour (G workgroups, all resident at once), and a
+// grid-wide barrier separates the phases, so that a phase reads the state
+// its predecessors wrote.  After each box a workgroup already loads the
+// first factor blocks of its next box, also across the barrier (factors do
+// not change during smoothing).  Every workgroup passes every barrier.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_smooth_grid(Geo g, const Box* __restrict__ boxes,
+                                                    const int* __restrict__ members,
+                                                    SmoothPhases ph, int nphase,
+                                                    const double* __restrict__ K,
+                                                    const double* __restrict__ f,
+                                                    const double* __restrict__ bcv, double beta,
+                                                    const double* __restrict__ fac,
+                                                    const double* __restrict__ fact,
+                                                    const double* __restrict__ tcoup, double* p,
+                                                    double* gflux) {
+  extern __shared__ __align__(16) double dsm[];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int G = gridDim.x, b0 = blockIdx.x;
+  auto count = [&](int k) { return ph.off[k % ph.ncol + 1] - ph.off[k % ph.ncol]; };
+  auto box_at = [&](int k, int j) { return members[ph.off[k % ph.ncol] + j]; };
+  auto preload = [&](int bi, double w[RING][HB], double zm[HB]) {
+    const Box B = boxes[bi];
+    smooth_preload<NT>(B, fac + B.fac, fact + B.fac, w, zm);
+  };
+  double w[RING][HB], zm[HB];
+  int bi = b0 < count(0) ? box_at(0, b0) : -1;
+  if (bi >= 0) preload(bi, w, zm);
+  for (int k = 0; k < nphase; ++k) {
+    const int n = count(k);
+    const int n1 = k + 1 < nphase ? count(k + 1) : 0;
+    for (int j = b0; j < n; j += G) {
+      const Box B = boxes[bi];
+      smooth_box<NT>(g, B, K, f, bcv, beta, fac + B.fac, fact + B.fac, tcoup, p, gflux, w, zm, dsm);
+      bi = j + G < n ? box_at(k, j + G) : (b0 < n1 ? box_at(k + 1, b0) : -1);
+      if (bi >= 0) preload(bi, w, zm);
+    }
+    if (b0 >= n && b0 < n1) {
+      bi = box_at(k + 1, b0);
+      preload(bi, w, zm);
+    }
+    grid.sync();
   }
-  if (threadIdx.x < 64) wload_block(block_src(Wt, B.nb, B.nblk), B.nblk / 2, zm);
-  SmoothLds r = carve_smooth(dsm, B);
-  stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
-  bsync<NT>();
-  smooth_rhs<NT>(g, B, r, beta, r.b.X);
-  bsync<NT>();
-  sweep_twisted<NT>(B, Wf, Wt, r.b, r.b.Z, w, zm);
-  smooth_out<NT>(g, B, r, r.b.X, beta, p, gflux);
 }
 
 template <typename KF>
@@ -371,6 +437,42 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
   }
 #undef MRCM_SMOOTH_NT
   return hipGetLastError();
+}
+
+hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const int* members,
+                              const SmoothPhases& ph, int nphase, const double* K, const double* f,
+                              const double* bcv, double beta, const double* fac, const double* fact,
+                              const double* tcoup, double* p, double* gflux, size_t lds, int nt,
+                              int max_groups, hipStream_t s) {
+  if (nphase <= 0) return hipSuccess;
+  if (!fact || ph.ncol <= 0 || ph.ncol > 8 || max_groups < 0) return hipErrorInvalidValue;
+  int nbox = 0;
+  for (int c = 0; c < ph.ncol; ++c) nbox = std::max(nbox, ph.off[c + 1] - ph.off[c]);
+  if (nbox <= 0) return hipSuccess;
+  int dev = 0, ncu = 0, coop = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (!coop) return hipErrorNotSupported;
+  Geo gg = g;
+  SmoothPhases pp = ph;
+  void* args[] = {&gg, &boxes, &members, &pp, &nphase, &K, &f, &bcv, &beta, &fac, &fact, &tcoup, &p, &gflux};
+  auto go = [&](auto kern, int N) -> hipError_t {
+    hipError_t r = set_lds(kern, lds);
+    if (r != hipSuccess) return r;
+    int per_cu = 0;
+    r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, N, lds);
+    if (r != hipSuccess) return r;
+    long long grid = std::min<long long>(nbox, (long long)per_cu * ncu);
+    if (max_groups > 0) grid = std::min<long long>(grid, max_groups);
+    if (grid <= 0) return hipErrorCooperativeLaunchTooLarge;
+    return hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)grid), dim3(N), args, lds, s);
+  };
+  if (nt == 64) return go(k_smooth_grid<64>, 64);
+  if (nt == 128) return go(k_smooth_grid<128>, 128);
+  if (nt == 256) return go(k_smooth_grid<256>, 256);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mrcm

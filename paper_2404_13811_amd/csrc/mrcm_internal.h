@@ -124,6 +124,24 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* fact, const double* tcoup, double* scr,
                            double* p, double* gflux, size_t lds, int nt, hipStream_t s);
+// colour phases of the smoothing sweep: boxes of colour c are
+// members[off[c] .. off[c+1])
+struct SmoothPhases {
+  int off[9];
+  int ncol;
+};
+// nphase colour phases (phase k has colour k % ncol) in one cooperative
+// launch with a grid barrier between phases: as many workgroups as fit on
+// the device at once (at most the largest colour's box count, and at most
+// max_groups when that is > 0), each looping over its share of a phase's
+// boxes; hipErrorNotSupported when the device has no cooperative launch,
+// hipErrorCooperativeLaunchTooLarge when not one workgroup fits (nothing is
+// launched in either case)
+hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const int* members,
+                              const SmoothPhases& ph, int nphase, const double* K, const double* f,
+                              const double* bcv, double beta, const double* fac, const double* fact,
+                              const double* tcoup, double* p, double* gflux, size_t lds, int nt,
+                              int max_groups, hipStream_t s);
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);

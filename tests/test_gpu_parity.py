@@ -151,9 +151,10 @@ def test_fp32_refine_c2_full(overlap):
 
 
 # ------------------------------------------------- smoothing execution forms
-def _smooth_trace(wl, use_graph, threads, steps, precision="fp64"):
+def _smooth_trace(wl, use_graph, threads, steps, precision="fp64", persistent=None):
     """Pressure and flux after each mrcm_smooth call (eager reads between
-    the calls, so graph replays alternate with other device work)."""
+    the calls, so graph replays alternate with other device work).
+    persistent: None, or (on, max_groups) for the one-launch form."""
     import torch
     import paper_2404_13811_amd as m
     from paper_2404_13811_amd import api
@@ -162,6 +163,8 @@ def _smooth_trace(wl, use_graph, threads, steps, precision="fp64"):
     try:
         api.configure(ctx, wl, precision, tol=1e-12, max_refine=30)
         m.set_smoothing(ctx, use_graph, threads)
+        if persistent is not None:
+            m.set_smoothing_persistent(ctx, *persistent)
         m.build_basis(ctx)
         m.solve_interface(ctx)
         for n in steps:
@@ -187,5 +190,25 @@ def test_smoothing_graph_and_thread_variants_agree_exactly(precision):
               "autotune ms %.3f" % st["ms_autotune"], flush=True)
         assert st["smooth_graph"] == int(use_graph)
         assert st["smooth_threads"] in (64, 128, 256)
+        for (p, fl), (rp, rf) in zip(got, ref):
+            assert np.array_equal(p, rp) and np.array_equal(fl, rf)
+
+
+@pytest.mark.parametrize("overlap", [2, 0])
+def test_persistent_smoothing_agrees_exactly(overlap):
+    """All colour phases of a call in one cooperative launch (Steps 6-7 with
+    a device-wide barrier between colours) give results bit-identical to
+    one launch per phase, also when the grid is capped so that every
+    workgroup loops over several boxes of a colour, and for every
+    threads-per-box variant."""
+    wl = make_workload("c2", scale=4, overlap=overlap)
+    steps = [2, 1, 3]
+    ref, _ = _smooth_trace(wl, False, 256, steps)
+    for threads, groups in [(256, 0), (128, 0), (64, 0), (256, 3), (128, 1)]:
+        got, st = _smooth_trace(wl, False, threads, steps, persistent=(True, groups))
+        print("persistent threads", threads, "max_groups", groups, "used", st["smooth_persistent"],
+              "launches", st["n_smooth_launches"], "phases", st["n_smooth_phases"], flush=True)
+        assert st["smooth_persistent"] == 1 and st["n_smooth_launches"] == 1
+        assert st["n_smooth_phases"] == steps[-1] * 2 ** wl.dim
         for (p, fl), (rp, rf) in zip(got, ref):
             assert np.array_equal(p, rp) and np.array_equal(fl, rf)
