@@ -42,10 +42,10 @@ FLUX_TOL = 1e-6
 # hash to the value it was taken with; otherwise the traffic is reported null.
 TRAFFIC = {
     # kernel: (source files, sha256 prefix, fetch KiB, write KiB, workload)
-    "k_smooth_w": (("local_wave.hip",), "532a8d5acc8389da", 4468.1, 158.0, "c2 overlap 4"),
-    "k_local_w": (("local_wave.hip",), "532a8d5acc8389da", 17812.6, 55513.5, "c2 overlap 4"),
-    "k_smooth32": (("local_wave32.hip",), "3c097b55cb1db6d6", 2701.1, 162.0, "c2 overlap 4"),
-    "k_local32": (("local_wave32.hip",), "3c097b55cb1db6d6", 10265.4, 23795.0, "c2 overlap 4"),
+    "k_smooth_w": (("local_wave.hip",), "2c89d52ba5914c9e", 4559.8, 158.0, "c2 overlap 4"),
+    "k_local_w": (("local_wave.hip",), "2c89d52ba5914c9e", 17816.9, 55513.5, "c2 overlap 4"),
+    "k_smooth32": (("local_wave32.hip",), "a36ce2032c49d879", 2779.6, 162.0, "c2 overlap 4"),
+    "k_local32": (("local_wave32.hip",), "a36ce2032c49d879", 10359.8, 23795.0, "c2 overlap 4"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 

@@ -214,45 +214,48 @@ __device__ __forceinline__ void stage_strips(const double* __restrict__ A, const
   }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // One 32 x 32 output tile of a product task (tile = row-major tile index).
+// Each of the four waves computes one 16 x 16 quadrant with FP64 matrix
+// instructions (16 x 16 x 4 per instruction: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] of the k-slice and holds D[4r + l / 16][l % 16] in
+// accumulator element r); two accumulators alternate over the k-slices so
+// that consecutive instructions do not wait on each other.
 __device__ __forceinline__ void gemm_tile(double* pool, const BcrGemm& T, int n, int ld, int tile,
                                           double* smem) {
   double* As = smem;           // n x GT
   double* Bs = smem + n * GT;  // n x GT
   const int ntile = n / GT;
   const int tr0 = (tile / ntile) * GT, tc0 = (tile % ntile) * GT;
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int qr = (wv >> 1) * 16, qc = (wv & 1) * 16;  // quadrant of this wave
+  const int li = ln & 15, lk = ln >> 4;
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int term = 0; term < 2; ++term) {
     const long long ai = term ? T.a2 : T.a1, bi = term ? T.b2 : T.b1;
     if (ai < 0) continue;
     if (term) __syncthreads();
     stage_strips(pool + ai, pool + bi, term ? T.al2 : T.al1, n, ld, tr0, tc0, As, Bs);
     __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < n; ++k) {
-      const double a0 = As[k * GT + ty], a1 = As[k * GT + ty + 16];
-      const double b0 = Bs[k * GT + tx], b1 = Bs[k * GT + tx + 16];
-      acc00 = fma(a0, b0, acc00);
-      acc01 = fma(a0, b1, acc01);
-      acc10 = fma(a1, b0, acc10);
-      acc11 = fma(a1, b1, acc11);
+    const double* ap = As + lk * GT + qr + li;
+    const double* bq = Bs + lk * GT + qc + li;
+#pragma unroll 4
+    for (int k = 0; k < n; k += 8) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k * GT], bq[k * GT], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(k + 4) * GT], bq[(k + 4) * GT], acc1, 0, 0, 0);
     }
   }
   double* C = pool + T.c;
   const double* C0 = T.c0 >= 0 ? pool + T.c0 : nullptr;
-  const long long r_0 = tr0 + ty, r_1 = r_0 + 16;
-  const int c_0 = tc0 + tx, c_1 = c_0 + 16;
-  if (C0) {
-    acc00 += C0[r_0 * ld + c_0];
-    acc01 += C0[r_0 * ld + c_1];
-    acc10 += C0[r_1 * ld + c_0];
-    acc11 += C0[r_1 * ld + c_1];
+  const int col = tc0 + qc + li;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const long long row = tr0 + qr + 4 * r + lk;
+    double v = acc0[r] + acc1[r];
+    if (C0) v += C0[row * ld + col];
+    C[row * ld + col] = v;
   }
-  C[r_0 * ld + c_0] = acc00;
-  C[r_0 * ld + c_1] = acc01;
-  C[r_1 * ld + c_0] = acc10;
-  C[r_1 * ld + c_1] = acc11;
 }
 
 __global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
