@@ -186,11 +186,17 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
 // computes a 2 x 2 set of outputs.
 constexpr int GT = 32, GCH = 16;
 
+// Row stride of the staged A strip: n + 1 doubles, so that the strip's
+// rows start in different banks (row-major writes and the matrix-operand
+// reads, 16 rows at one k, are both free of bank conflicts).
+__device__ __forceinline__ int astride(int n) { return n + 1; }
+
 __device__ __forceinline__ void stage_strips(const double* __restrict__ A, const double* __restrict__ B,
                                              double al, int n, int ld, int tr0, int tc0, double* As,
                                              double* Bs) {
-  // As[k * GT + r] = al * A[tr0 + r][k];  Bs[k * GT + c] = B[k][tc0 + c]
+  // As[r * (n + 1) + k] = al * A[tr0 + r][k];  Bs[k * GT + c] = B[k][tc0 + c]
   const int cnt = GT * n;  // elements per strip
+  const int as = astride(n);
   for (int e0 = 0; e0 < cnt; e0 += 256 * GCH) {
     double va[GCH], vb[GCH];
 #pragma unroll
@@ -207,7 +213,7 @@ __device__ __forceinline__ void stage_strips(const double* __restrict__ A, const
       const int e = e0 + u * 256 + threadIdx.x;
       if (e < cnt) {
         const int ra = e / n, ka = e - (e / n) * n;
-        As[ka * GT + ra] = al * va[u];
+        As[ra * as + ka] = al * va[u];
         Bs[e] = vb[u];
       }
     }
@@ -224,8 +230,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // that consecutive instructions do not wait on each other.
 __device__ __forceinline__ void gemm_tile(double* pool, const BcrGemm& T, int n, int ld, int tile,
                                           double* smem) {
-  double* As = smem;           // n x GT
-  double* Bs = smem + n * GT;  // n x GT
+  double* As = smem;                   // GT x (n + 1)
+  double* Bs = smem + GT * astride(n);  // n x GT
   const int ntile = n / GT;
   const int tr0 = (tile / ntile) * GT, tc0 = (tile % ntile) * GT;
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
@@ -238,12 +244,12 @@ __device__ __forceinline__ void gemm_tile(double* pool, const BcrGemm& T, int n,
     if (term) __syncthreads();
     stage_strips(pool + ai, pool + bi, term ? T.al2 : T.al1, n, ld, tr0, tc0, As, Bs);
     __syncthreads();
-    const double* ap = As + lk * GT + qr + li;
+    const double* ap = As + (qr + li) * astride(n) + lk;
     const double* bq = Bs + lk * GT + qc + li;
 #pragma unroll 4
     for (int k = 0; k < n; k += 8) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k * GT], bq[k * GT], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(k + 4) * GT], bq[(k + 4) * GT], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], bq[k * GT], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k + 4], bq[(k + 4) * GT], acc1, 0, 0, 0);
     }
   }
   double* C = pool + T.c;
@@ -389,7 +395,7 @@ hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n,
   if (ntask <= 0) return hipSuccess;
   if (n % GT || n > kBcrMaxBlock) return hipErrorInvalidValue;
   const int ntile = n / GT;
-  const size_t lds = 2 * sizeof(double) * (size_t)n * GT;
+  const size_t lds = sizeof(double) * ((size_t)GT * (n + 1) + (size_t)n * GT);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_bcr_gemm,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -405,7 +411,7 @@ hipError_t launch_bcr_gemm_gemv(double* pool, double* vec, const BcrGemm* gtasks
   if (ngemm <= 0 && ngemv <= 0) return hipSuccess;
   if (n % GT || n > kBcrMaxBlock || bp % 16) return hipErrorInvalidValue;
   const int ntile = n / GT;
-  const size_t lds = 2 * sizeof(double) * (size_t)n * GT;
+  const size_t lds = sizeof(double) * ((size_t)GT * (n + 1) + (size_t)n * GT);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_bcr_gemm_gemv,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
