@@ -236,16 +236,15 @@ def roofline(wl, form, phases, st):
                 "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic(kern, wl),
                 "work_per_launch": "%.0f bytes" % per_launch,
                 "avg_launch_us": t_smooth_launch * 1e6}
-    # local kernel (basis boxes, particular problems and, in FP64, the
-    # backward factors of the two-ended smoothing sweep, in one launch):
-    # Gauss-Jordan inverse of every line block (nb^3 FMA) and the forward +
-    # backward block products of every right-hand side (2 nb^2 FMA per block)
+    # local kernel (basis boxes and particular problems in one launch):
+    # Gauss-Jordan inverse of every line block (nb^3 FMA; in FP64 the blocks
+    # below the meeting block are eliminated from one end and those above it
+    # from the other, still one inverse per block) and the forward + backward
+    # block products of every right-hand side (2 nb^2 FMA per block)
     flops = 0.0
     for dims, nseed in bx:
         nb, nblk = dims[0], int(np.prod(dims[1:]))
         flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb * nseed
-        if form != "fp32_refine":
-            flops += 2.0 * nblk * nb ** 3  # backward inverses and meeting block
     for _ in range(int(np.prod(wl.ncell)) // int(np.prod(S))):
         nb, nblk = S[0], int(np.prod(S[1:]))
         flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb

@@ -195,6 +195,17 @@ __global__ void k_adj_mean(const double* __restrict__ v, int n, double* __restri
 // --------------------------------------------------------------- smoothing
 constexpr int kAdjNT = 256;
 
+// One right-hand side in s.X solved by one wave with the two-ended sweep of
+// the cached factors (forward inverses below the meeting block, backward
+// inverses above it and Z_m): the same arithmetic as the forward smoothing
+// step, so the reverse pass recomputes the forward state exactly.
+__device__ __forceinline__ void box_solve(const Box& B, const double* Wf, const double* Wt,
+                                          const BoxLds& s, double* z) {
+  double w[RING][HB], zm[HB];
+  wload_block(block_src(Wt, B.nb, B.nblk), B.nblk / 2, zm);
+  sweep_twisted<64>(B, Wf, Wt, s, z, w, zm);
+}
+
 // One colour phase in reverse.  p_in / gf_in: the state before the phase.
 __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restrict__ boxes,
                                                        const int* __restrict__ members,
@@ -202,6 +213,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
                                                        const double* __restrict__ f,
                                                        const double* __restrict__ bcv, double beta,
                                                        const double* __restrict__ fac,
+                                                       const double* __restrict__ fact,
                                                        const double* __restrict__ tcoup,
                                                        const double* __restrict__ p_in,
                                                        const double* __restrict__ gf_in,
@@ -221,7 +233,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
   stage_smooth<NT>(g, B, r, K, p_in, f, gf_in, bcv, tcoup);
   __syncthreads();
   smooth_rhs<NT>(g, B, r, beta, r.b.X);
-  if (tid < 64) sweep1(B, fac + B.fac, r.b, r.b.Z);
+  if (tid < 64) box_solve(B, fac + B.fac, fact + B.fac, r.b, r.b.Z);
   __syncthreads();
   for (int e = tid; e < nc; e += NT) {
     xs[e] = r.b.X[e];
@@ -287,7 +299,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
   // (c) adjoint solve A mu = xbar (A symmetric: cached inverses)
   BoxLds sm = r.b;
   sm.X = mu;
-  if (tid < 64) sweep1(B, fac + B.fac, sm, r.b.Z);
+  if (tid < 64) box_solve(B, fac + B.fac, fact + B.fac, sm, r.b.Z);
   __syncthreads();
   // (d) K terms of the box matrix and right-hand side; lambda_bar of the
   // Robin faces
@@ -455,6 +467,7 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
                                                   const Seed* __restrict__ seeds,
                                                   const double* __restrict__ K, double beta,
                                                   const double* __restrict__ fac,
+                                                  const double* __restrict__ fact,
                                                   const double* __restrict__ X,
                                                   const double* __restrict__ pb,
                                                   const double* __restrict__ tr_u,
@@ -496,9 +509,9 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
     }
   }
   wsync();
-  const double* Wg = fac + B.fac;
-  forward_cached(B, Wg, nrhs, s);
-  backward_cached(B, Wg, nrhs, s);
+  const double* Wf = fac + B.fac;
+  const double* Wt = fact + B.fac;
+  twisted_cached(B, Wf, Wt, nrhs, s);
   wsync();
   for (int e = L; e < nrhs * nc; e += 64) {
     xs[e] = s.X[e];
@@ -567,9 +580,8 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
     }
     wsync();
   }
-  // adjoint solves with the cached inverses
-  forward_cached(B, Wg, nrhs, s);
-  backward_cached(B, Wg, nrhs, s);
+  // adjoint solves with the cached factors (A symmetric)
+  twisted_cached(B, Wf, Wt, nrhs, s);
   wsync();
   box_matrix_adjoint<64>(
       g, B, s, xs, s.X, nrhs, beta, seed_lam, [](int, int) { return 0.0; },
@@ -715,14 +727,14 @@ hipError_t launch_adj_out(const Geo& g, const double* K, const double* p, const 
 
 hipError_t launch_adj_smooth(const Geo& g, const Box* boxes, const int* members, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
-                             const double* fac, const double* tcoup, const double* p_in,
-                             const double* gf_in, double* pb, double* gfb, double* Kb, size_t lds,
-                             hipStream_t s) {
+                             const double* fac, const double* fact, const double* tcoup,
+                             const double* p_in, const double* gf_in, double* pb, double* gfb,
+                             double* Kb, size_t lds, hipStream_t s) {
   if (nmem <= 0) return hipSuccess;
   hipError_t e = lds_attr(k_adj_smooth, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adj_smooth, dim3(nmem), dim3(kAdjNT), lds, s, g, boxes, members, K, f, bcv,
-                     beta, fac, tcoup, p_in, gf_in, pb, gfb, Kb);
+                     beta, fac, fact, tcoup, p_in, gf_in, pb, gfb, Kb);
   return hipGetLastError();
 }
 
@@ -747,15 +759,15 @@ hipError_t launch_adj_moments(const Geo& g, const Iface* ifc, int nifc, const Se
 }
 
 hipError_t launch_adj_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
-                            const double* K, double beta, const double* fac, const double* X,
-                            const double* pb, const double* tr_u, const double* tr_ub,
-                            const double* tr_phib, const double* tr_betab, double* Kb, size_t lds,
-                            hipStream_t s) {
+                            const double* K, double beta, const double* fac, const double* fact,
+                            const double* X, const double* pb, const double* tr_u,
+                            const double* tr_ub, const double* tr_phib, const double* tr_betab,
+                            double* Kb, size_t lds, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
   hipError_t e = lds_attr(k_adj_basis, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_basis, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac, X, pb,
-                     tr_u, tr_ub, tr_phib, tr_betab, Kb);
+  hipLaunchKernelGGL(k_adj_basis, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac, fact,
+                     X, pb, tr_u, tr_ub, tr_phib, tr_betab, Kb);
   return hipGetLastError();
 }
 

@@ -592,7 +592,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
     const Box& P = c->pbox[i];
     if (B.nb > 32 || P.nb > 32) c->wave = false;
     const int bm0 = B.hi[0] - B.lo[0], bm1 = B.hi[1] - B.lo[1];
-    c->lds_basis = std::max(c->lds_basis, wave_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
+    c->lds_basis = std::max(c->lds_basis, wave_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
     c->lds_smooth = std::max(c->lds_smooth, wave_smooth_lds_bytes(bm0, bm1));
     c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1));
     c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0));
@@ -1321,7 +1321,7 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
     const int col = ph % (1 << g.d);
     const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
     HIPCHK(c, launch_adj_smooth(g, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
-                                c->beta_sm, c->fac, c->tco, c->ck_p + ph * np, c->ck_g + ph * ng,
+                                c->beta_sm, c->fac, c->fact, c->tco, c->ck_p + ph * np, c->ck_g + ph * ng,
                                 c->a_pb, c->a_gfb, c->a_Kb, c->lds_adj_smooth, s));
   }
   // MRCM-O assembly
@@ -1355,7 +1355,7 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
                                c->a_nu, c->tr_u, c->tr_beta, c->a_trub, c->a_trphib, c->a_trbetab,
                                c->a_ubarb, c->a_pibarb, s));
   // seeds and particular problems
-  HIPCHK(c, launch_adj_basis(g, c->d_obox, g.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac, c->X,
+  HIPCHK(c, launch_adj_basis(g, c->d_obox, g.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac, c->fact, c->X,
                              c->a_pb, c->tr_u, c->a_trub, c->a_trphib, c->a_trbetab, c->a_Kb,
                              c->lds_adj_basis, s));
   HIPCHK(c, launch_adj_particular(g, c->d_pbox, g.nsub, c->K, c->bcv, c->beta_mbf, c->facp,

@@ -60,46 +60,124 @@ __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double*
 
 // ------------------------------------------------------------------ kernels
 
+// LDS of a basis box: the box arrays with its right-hand sides (the Z
+// scratch of BoxLds serves wave 0), the Z scratch of wave 1, and the forward
+// Schur complement of the meeting block in the block register layout.
+__host__ __device__ inline size_t basis_lds_doubles(int m0, int m1, int nrhs) {
+  return box_lds_doubles(m0, m1, nrhs) + (size_t)nrhs * NBW + 64 * HB + 2;
+}
+
+// Store the nb x nb block held in the register layout w to Wj (row-major).
+__device__ __forceinline__ void store_block(int nb, double* Wj, const double w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    if (r < nb && c < nb) Wj[r * nb + c] = w[i];
+  }
+}
+
 // Steps 1-2: factor the oversampled box, solve every seed, extract
-// u and phi on Gamma_i and the restriction to Omega_i.
+// u and phi on Gamma_i and the restriction to Omega_i.  Two waves solve
+// the block-tridiagonal system from both ends (meeting block m = nblk / 2):
+// wave 0 eliminates blocks 0 .. m-1 (forward inverses W_j into fac), wave 1
+// blocks nblk-1 .. m+1 (backward inverses W'_j = (D_j - t_j W'_{j+1} t_j)^{-1}
+// into fact), each with the forward sweep of every seed fused in; wave 1
+// then inverts Z_m = (S_m - t_m W'_{m+1} t_m)^{-1} (S_m: forward Schur
+// complement of block m, from wave 0), stored at block m of fact, and solves
+// the meeting block; both back-substitute outwards.  The chain of block
+// inverses on one wave is about half as long as a one-ended elimination,
+// and fac / fact are exactly the factors of the two-ended smoothing sweep.
 __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
                                           const double* __restrict__ K, double beta,
-                                          double* __restrict__ fac, double* __restrict__ tcoup,
+                                          double* __restrict__ fac, double* __restrict__ fact,
+                                          double* __restrict__ tcoup,
                                           double* __restrict__ Pk, double* __restrict__ tr_u,
                                           double* __restrict__ tr_phi,
-                                          double* __restrict__ tr_beta, double* dsm, WaveSmem& sm) {
+                                          double* __restrict__ tr_beta, double* dsm, WaveSmem* sm) {
   const int L = lane_id();
+  const int tid = threadIdx.x, wv = tid >> 6;
   const int nrhs = B.nrhs;
   BoxLds s = carve(dsm, B, nrhs);
-  load_box(g, B, K, beta, s);
+  double* Z1 = s.Z + nrhs * NBW;
+  double* Sm = Z1 + nrhs * NBW;
   const int nc = B.ncell;
-  for (int e = L; e < nrhs * nc; e += 64) s.X[e] = 0.0;
-  wsync();
-  for (int k = 0; k < nrhs; ++k) {
-    const Seed sd = seeds[B.seed0 + k];
-    const int a = sd.side >> 1, so = sd.side & 1;
-    const int nf = (a == 0) ? s.m1 : s.m0;
-    #pragma unroll 1
-    for (int t = L; t < nf; t += 64) {
-      int c[3];
-      if (a == 0) { c[0] = so ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
-      else { c[1] = so ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
-      c[2] = 0;
-      const int ox = c[0] + (a == 0 ? (so ? 1 : -1) : 0), oy = c[1] + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, c[0], c[1]);
-      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
-      s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
+  // set-up by wave 0: box arrays, seed right-hand sides, couplings
+  if (wv == 0) {
+    load_box(g, B, K, beta, s);
+    for (int e = L; e < nrhs * nc; e += 64) s.X[e] = 0.0;
+    wsync();
+    for (int k = 0; k < nrhs; ++k) {
+      const Seed sd = seeds[B.seed0 + k];
+      const int a = sd.side >> 1, so = sd.side & 1;
+      const int nf = (a == 0) ? s.m1 : s.m0;
+      #pragma unroll 1
+      for (int t = L; t < nf; t += 64) {
+        int c[3];
+        if (a == 0) { c[0] = so ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
+        else { c[1] = so ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
+        c[2] = 0;
+        const int ox = c[0] + (a == 0 ? (so ? 1 : -1) : 0), oy = c[1] + (a == 1 ? (so ? 1 : -1) : 0);
+        const double kc = kat(s, B, c[0], c[1]);
+        const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+        s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
+      }
+    }
+    for (int e = L; e < nc; e += 64) tcoup[B.scr + e] = s.Tn[e];
+  }
+  __syncthreads();
+  const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
+  double* Wf = fac + B.fac;
+  double* Wt = fact + B.fac;
+  double w[HB];
+#pragma unroll
+  for (int i = 0; i < HB; ++i) w[i] = 0.0;
+  if (wv == 0) {
+    for (int j = 0; j < m; ++j) {
+      wbuild(nb, j, s, w);
+      wgj(nb, sm[0], w);
+      store_block(nb, Wf + (long long)j * nb * nb, w);
+      fwd_step_d(nb, nc, j, j - 1, j > 0, nrhs, s, s.Z, w);
+    }
+    wbuild(nb, m, s, w);  // S_m
+#pragma unroll
+    for (int i = 0; i < HB; ++i) Sm[i * 64 + L] = w[i];
+  } else {
+    for (int j = nblk - 1; j > m; --j) {
+      wbuild_t(nb, j, j < nblk - 1 ? j : -1, s, w);
+      wgj(nb, sm[1], w);
+      store_block(nb, Wt + (long long)j * nb * nb, w);
+      fwd_step_d(nb, nc, j, j + 1, j < nblk - 1, nrhs, s, Z1, w);
     }
   }
-  wsync();
-  double* Wg = fac + B.fac;
-  factor_forward(B, Wg, tcoup + B.scr, nrhs, s, sm);
-  backward_cached(B, Wg, nrhs, s);
+  __syncthreads();
+  if (wv == 1) {
+    // Z_m = (S_m - t_m W'_{m+1} t_m)^{-1}, identity padding kept; w holds
+    // W'_{m+1} when the bottom half is not empty
+    const int c = L & 31, h = L >> 5;
+    const double* Tm = s.Tn + m * nb;
+    const double tc = (m < nblk - 1 && c < nb) ? Tm[c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int r = HB * h + i;
+      const double smi = Sm[i * 64 + L];
+      const double tr = (m < nblk - 1 && r < nb) ? Tm[r] : 0.0;
+      w[i] = (m < nblk - 1 && r < nb && c < nb) ? fma(-tr * tc, w[i], smi) : smi;
+    }
+    wgj(nb, sm[1], w);
+    store_block(nb, Wt + (long long)m * nb * nb, w);
+    mid_step(nb, nc, m, nblk, nrhs, s, Z1, w);
+  }
+  __syncthreads();
+  if (wv == 0) twist_back_cached(B, Wf, nrhs, s, s.Z, false);
+  else twist_back_cached(B, Wt, nrhs, s, Z1, true);
+  __syncthreads();
   int olo[3], ohi[3];
   womega(g, B.sub, olo, ohi);
   const int ncell_o = g.S[0] * g.S[1];
   #pragma unroll 1
-  for (int e = L; e < nrhs * ncell_o; e += 64) {
+  for (int e = tid; e < nrhs * ncell_o; e += 128) {
     const int k = e / ncell_o, t = e % ncell_o;
     Pk[(long long)(B.seed0 + k) * ncell_o + t] =
         s.X[k * nc + bloc(B, s, olo[0] + t % g.S[0], olo[1] + t / g.S[0])];
@@ -109,7 +187,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
     const bool has = wneighbor(g, B.sub, q) >= 0;
     const int a = q >> 1, so = q & 1;
     #pragma unroll 1
-    for (int e = L; e < nrhs * nf; e += 64) {
+    for (int e = tid; e < nrhs * nf; e += 128) {
       const int k = e / nf, t = e % nf;
       const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
       if (!has) {
@@ -180,107 +258,44 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B, const
   }
 }
 
-// Factors of the twisted smoothing sweep for the oversampled box B: the
-// backward inverses W'_j = (D_j - t_j W'_{j+1} t_j)^{-1}, j = nblk-1 .. m+1,
-// and the meeting block Z_m = (S_m - t_m W'_{m+1} t_m)^{-1} with S_m the
-// forward Schur complement of block m (its forward chain is recomputed here
-// with the same arithmetic as the basis factorisation).  Each is stored at
-// its block's place in Wt; the blocks before m are not used.
-__device__ __forceinline__ void twist_box(const Geo& g, const Box& B, const double* __restrict__ K,
-                                          double beta, double* __restrict__ Wt, double* dsm,
-                                          WaveSmem& sm) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-  BoxLds s = carve(dsm, B, 1);
-  load_box(g, B, K, beta, s);
-  wsync();
-  const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
-  double w[HB];
-#pragma unroll
-  for (int i = 0; i < HB; ++i) w[i] = 0.0;
-  for (int j = 0; j <= m; ++j) {
-    wbuild(nb, j, s, w);
-    if (j < m) wgj(nb, sm, w);
-  }
-  double sm_m[HB];
-#pragma unroll
-  for (int i = 0; i < HB; ++i) sm_m[i] = w[i];
-  for (int j = nblk - 1; j > m; --j) {
-    wbuild_t(nb, j, j < nblk - 1 ? j : -1, s, w);
-    wgj(nb, sm, w);
-    double* Wj = Wt + (long long)j * nb * nb;
-#pragma unroll
-    for (int i = 0; i < HB; ++i) {
-      const int r = HB * h + i;
-      if (r < nb && c < nb) Wj[r * nb + c] = w[i];
-    }
-  }
-  if (m < nblk - 1) {
-    // S_m - t_m W'_{m+1} t_m (identity padding kept)
-    const double* Tm = s.Tn + m * nb;
-    const double tc = c < nb ? Tm[c] : 0.0;
-#pragma unroll
-    for (int i = 0; i < HB; ++i) {
-      const int r = HB * h + i;
-      const double tr = r < nb ? Tm[r] : 0.0;
-      w[i] = (r < nb && c < nb) ? fma(-tr * tc, w[i], sm_m[i]) : sm_m[i];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < HB; ++i) w[i] = sm_m[i];
-  }
-  wgj(nb, sm, w);
-  double* Zm = Wt + (long long)m * nb * nb;
-#pragma unroll
-  for (int i = 0; i < HB; ++i) {
-    const int r = HB * h + i;
-    if (r < nb && c < nb) Zm[r * nb + c] = w[i];
-  }
-}
-
-// Steps 1-2 and 4 in one launch.  Workgroups [0, nbox) handle the
-// oversampled boxes (factor, seeds, traces); workgroups [nbox, 2 nbox) handle
-// the particular problems on the subdomains and then, when fact is given,
-// the factors of the twisted smoothing sweep of the same subdomain's
-// oversampled box.  The two sets share nothing, so their waves run side by
-// side instead of one launch after the other.
-__global__ void __launch_bounds__(64) k_local_w(Geo g, const Box* __restrict__ obox,
-                                                const Box* __restrict__ pbox, int nbox,
-                                                const Seed* __restrict__ seeds,
-                                                const double* __restrict__ K,
-                                                const double* __restrict__ f,
-                                                const double* __restrict__ bcv, double beta,
-                                                double* __restrict__ fac,
-                                                double* __restrict__ tcoup,
-                                                double* __restrict__ facp,
-                                                double* __restrict__ tcp,
-                                                double* __restrict__ Pk,
-                                                double* __restrict__ tr_u,
-                                                double* __restrict__ tr_phi,
-                                                double* __restrict__ tr_beta,
-                                                double* __restrict__ pbar,
-                                                double* __restrict__ ubar,
-                                                double* __restrict__ pibar,
-                                                double* __restrict__ fact, int* flags) {
+// Steps 1-2 and 4 in one launch of two-wave workgroups.  Workgroups
+// [0, nbox) handle the oversampled boxes (factors of both ends, seeds,
+// traces); in workgroups [nbox, 2 nbox) wave 0 solves the particular
+// problem of a subdomain (one-ended factorisation of Omega_i) and wave 1
+// has nothing to do.  The two sets share nothing, so their waves run side
+// by side instead of one launch after the other.
+__global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ obox,
+                                                 const Box* __restrict__ pbox, int nbox,
+                                                 const Seed* __restrict__ seeds,
+                                                 const double* __restrict__ K,
+                                                 const double* __restrict__ f,
+                                                 const double* __restrict__ bcv, double beta,
+                                                 double* __restrict__ fac,
+                                                 double* __restrict__ tcoup,
+                                                 double* __restrict__ facp,
+                                                 double* __restrict__ tcp,
+                                                 double* __restrict__ Pk,
+                                                 double* __restrict__ tr_u,
+                                                 double* __restrict__ tr_phi,
+                                                 double* __restrict__ tr_beta,
+                                                 double* __restrict__ pbar,
+                                                 double* __restrict__ ubar,
+                                                 double* __restrict__ pibar,
+                                                 double* __restrict__ fact, int* flags) {
   extern __shared__ __align__(16) double dsm[];
-  __shared__ WaveSmem sm;
-  const int L = lane_id();
-  if (L == 0) sm.flag = 0;
+  __shared__ WaveSmem sm[2];
+  const int L = lane_id(), wv = threadIdx.x >> 6;
+  if (L == 0) sm[wv].flag = 0;
   const int b = blockIdx.x;
   if (b < nbox) {
     const Box B = obox[b];
-    basis_box(g, B, seeds, K, beta, fac, tcoup, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
-  } else {
+    basis_box(g, B, seeds, K, beta, fac, fact, tcoup, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+  } else if (wv == 0) {
     const Box B = pbox[b - nbox];
-    particular_box(g, B, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm);
-    if (fact) {
-      wsync();
-      const Box O = obox[b - nbox];
-      twist_box(g, O, K, beta, fact + O.fac, dsm, sm);
-    }
+    particular_box(g, B, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm[0]);
   }
-  wsync();
-  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
+  __syncthreads();
+  if (threadIdx.x == 0 && (sm[0].flag | sm[1].flag)) atomicOr(flags, sm[0].flag | sm[1].flag);
 }
 
 // Factor blocks a box's smoothing solve needs first (the first ring slots of
@@ -392,6 +407,10 @@ hipError_t set_lds(KF kern, size_t bytes) {
 
 }  // namespace
 
+size_t wave_basis_lds_bytes(int m0, int m1, int nrhs) {
+  return sizeof(double) * basis_lds_doubles(m0, m1, nrhs);
+}
+
 size_t wave_lds_bytes(int m0, int m1, int nrhs) {
   return sizeof(double) * box_lds_doubles(m0, m1, nrhs);
 }
@@ -407,7 +426,8 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
   if (nbox <= 0) return hipSuccess;
   hipError_t e = set_lds(k_local_w, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(64), lds, s, g, obox, pbox, nbox, seeds, K, f,
+  if (!fact) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(128), lds, s, g, obox, pbox, nbox, seeds, K, f,
                      bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar,
                      fact, flags);
   return hipGetLastError();

@@ -109,6 +109,8 @@ hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int
 
 // one-wavefront-per-box 2-D kernels (local_wave.hip), blocks of <= 32 cells
 size_t wave_lds_bytes(int m0, int m1, int nrhs);
+// LDS of a two-wave basis box of k_local_w
+size_t wave_basis_lds_bytes(int m0, int m1, int nrhs);
 size_t wave_smooth_lds_bytes(int m0, int m1);
 // Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox) in one
 // launch of 2 nbox workgroups; lds = the larger of the two boxes' needs.
@@ -200,9 +202,9 @@ hipError_t launch_adj_out(const Geo& g, const double* K, const double* p, const 
                           double* gfb, double* Kb, hipStream_t s);
 hipError_t launch_adj_smooth(const Geo& g, const Box* boxes, const int* members, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
-                             const double* fac, const double* tcoup, const double* p_in,
-                             const double* gf_in, double* pb, double* gfb, double* Kb, size_t lds,
-                             hipStream_t s);
+                             const double* fac, const double* fact, const double* tcoup,
+                             const double* p_in, const double* gf_in, double* pb, double* gfb,
+                             double* Kb, size_t lds, hipStream_t s);
 hipError_t launch_adj_combine(const Geo& g, const int* seed_sub, int nX, const double* X,
                               const double* Pk, const double* tr_u, const double* pb,
                               const double* gfb, double* Xb, double* tr_ub, hipStream_t s);
@@ -212,10 +214,10 @@ hipError_t launch_adj_moments(const Geo& g, const Iface* ifc, int nifc, const Se
                               double* tr_phib, double* tr_betab, double* ubarb, double* pibarb,
                               hipStream_t s);
 hipError_t launch_adj_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
-                            const double* K, double beta, const double* fac, const double* X,
-                            const double* pb, const double* tr_u, const double* tr_ub,
-                            const double* tr_phib, const double* tr_betab, double* Kb, size_t lds,
-                            hipStream_t s);
+                            const double* K, double beta, const double* fac, const double* fact,
+                            const double* X, const double* pb, const double* tr_u,
+                            const double* tr_ub, const double* tr_phib, const double* tr_betab,
+                            double* Kb, size_t lds, hipStream_t s);
 hipError_t launch_adj_particular(const Geo& g, const Box* boxes, int nbox, const double* K,
                                  const double* bcv, double beta, const double* fac,
                                  const double* pbar, const double* pb, const double* ubarb,

@@ -682,28 +682,33 @@ __device__ __forceinline__ double wgemv2(const double w[HB], const double* z) {
   return half_sum(a0 + a1);
 }
 
-// Forward step of block j for all right-hand sides, inverse in w:
-// X_j <- W_j (X_j + t_{j-1} .* X_{j-1}).
-__device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
-                                         const double w[HB]) {
+// Forward step of block j for all right-hand sides, inverse in w, with jp
+// the block eliminated just before j (j - 1 going down the box, j + 1 going
+// up; has_prev false for the first block of a chain):
+// X_j <- W (X_j + t .* X_jp), t the coupling of j and jp (Tn row min(j, jp)).
+// Z: nrhs x NBW doubles of LDS scratch of the calling wave.
+__device__ __forceinline__ void fwd_step_d(int nb, int ncell, int j, int jp, bool has_prev,
+                                           int nrhs, const BoxLds& s, double* Z,
+                                           const double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  const int ti = jp < j ? jp : j;
   #pragma unroll 4
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
     double v = 0.0;
     if (r < nb) {
       v = s.X[k * ncell + j * nb + r];
-      if (j > 0) v += s.Tn[(j - 1) * nb + r] * s.X[k * ncell + (j - 1) * nb + r];
+      if (has_prev) v += s.Tn[ti * nb + r] * s.X[k * ncell + jp * nb + r];
     }
-    s.Z[k * NBW + r] = v;
+    Z[k * NBW + r] = v;
   }
   wsync();
   // four right-hand sides at a time: independent product chains overlap
   for (int k0 = 0; k0 < nrhs; k0 += 4) {
     double y[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, s.Z + min(k0 + q, nrhs - 1) * NBW);
+    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, Z + min(k0 + q, nrhs - 1) * NBW);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (k0 + q < nrhs && h == 0 && c < nb) s.X[(k0 + q) * ncell + j * nb + c] = y[q];
@@ -711,24 +716,67 @@ __device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, con
   wsync();
 }
 
-// Backward step of block j: X_j <- X_j + W_j (t_j .* X_{j+1}).
-__device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
+__device__ __forceinline__ void fwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
                                          const double w[HB]) {
+  fwd_step_d(nb, ncell, j, j - 1, j > 0, nrhs, s, s.Z, w);
+}
+
+// Back-substitution step of block j towards block jn (the block solved just
+// before it): X_j <- X_j + W (t .* X_jn), t the coupling of j and jn.
+__device__ __forceinline__ void bwd_step_d(int nb, int ncell, int j, int jn, int nrhs,
+                                           const BoxLds& s, double* Z, const double w[HB]) {
   const int L = lane_id();
   const int c = L & 31, h = L >> 5;
+  const int ti = jn < j ? jn : j;
   #pragma unroll 4
   for (int e = L; e < nrhs * NBW; e += 64) {
     const int k = e / NBW, r = e % NBW;
-    s.Z[k * NBW + r] = (r < nb) ? s.Tn[j * nb + r] * s.X[k * ncell + (j + 1) * nb + r] : 0.0;
+    Z[k * NBW + r] = (r < nb) ? s.Tn[ti * nb + r] * s.X[k * ncell + jn * nb + r] : 0.0;
   }
   wsync();
   for (int k0 = 0; k0 < nrhs; k0 += 4) {
     double y[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, s.Z + min(k0 + q, nrhs - 1) * NBW);
+    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, Z + min(k0 + q, nrhs - 1) * NBW);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (k0 + q < nrhs && h == 0 && c < nb) s.X[(k0 + q) * ncell + j * nb + c] += y[q];
+  }
+  wsync();
+}
+
+// Backward step of the one-ended solve: X_j <- X_j + W_j (t_j .* X_{j+1}).
+__device__ __forceinline__ void bwd_step(int nb, int ncell, int j, int nrhs, const BoxLds& s,
+                                         const double w[HB]) {
+  bwd_step_d(nb, ncell, j, j + 1, nrhs, s, s.Z, w);
+}
+
+// Meeting block of the two-ended solve, all right-hand sides, Z_m in w:
+// X_m <- Z_m (X_m + t_{m-1} .* X_{m-1} + t_m .* X_{m+1}).
+__device__ __forceinline__ void mid_step(int nb, int ncell, int m, int nblk, int nrhs,
+                                         const BoxLds& s, double* Z, const double w[HB]) {
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+  #pragma unroll 4
+  for (int e = L; e < nrhs * NBW; e += 64) {
+    const int k = e / NBW, r = e % NBW;
+    double v = 0.0;
+    if (r < nb) {
+      const double* X = s.X + k * ncell;
+      v = X[m * nb + r];
+      if (m > 0) v = fma(s.Tn[(m - 1) * nb + r], X[(m - 1) * nb + r], v);
+      if (m + 1 < nblk) v = fma(s.Tn[m * nb + r], X[(m + 1) * nb + r], v);
+    }
+    Z[k * NBW + r] = v;
+  }
+  wsync();
+  for (int k0 = 0; k0 < nrhs; k0 += 4) {
+    double y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = wgemv2(w, Z + min(k0 + q, nrhs - 1) * NBW);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k0 + q < nrhs && h == 0 && c < nb) s.X[(k0 + q) * ncell + m * nb + c] = y[q];
   }
   wsync();
 }
@@ -773,6 +821,75 @@ __device__ __forceinline__ void backward_cached(const Box& B, const double* Wg, 
       }
     }
   }
+}
+
+// Halves of the two-ended solve of all right-hand sides with cached inverses
+// (meeting block m = nblk / 2).  Top: blocks 0 .. m-1 with the forward
+// inverses W_j; bottom: blocks nblk-1 .. m+1 with the backward inverses
+// W'_j = (D_j - t_j W'_{j+1} t_j)^{-1}.  The forward pass of a half runs
+// from its end of the box towards m; the back-substitution from m outwards.
+// The inverses stream from memory RING blocks ahead of their use.
+__device__ __forceinline__ void twist_fwd_cached(const Box& B, const double* Wg, int nrhs,
+                                                 const BoxLds& s, double* Z, bool bottom) {
+  const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
+  const int cnt = bottom ? nblk - 1 - m : m;
+  const int j0 = bottom ? nblk - 1 : 0, dj = bottom ? -1 : 1;
+  if (cnt <= 0) return;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  double w[RING][HB];
+#pragma unroll
+  for (int q = 0; q < RING; ++q)
+    if (q < cnt) wload_block(src, j0 + dj * q, w[q]);
+  for (int t0 = 0; t0 < cnt; t0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int t = t0 + q;
+      if (t < cnt) {
+        const int j = j0 + dj * t;
+        fwd_step_d(nb, B.ncell, j, j - dj, t > 0, nrhs, s, Z, w[q]);
+        if (t + RING < cnt) wload_block(src, j0 + dj * (t + RING), w[q]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void twist_back_cached(const Box& B, const double* Wg, int nrhs,
+                                                  const BoxLds& s, double* Z, bool bottom) {
+  const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
+  const int cnt = bottom ? nblk - 1 - m : m;
+  const int dj = bottom ? 1 : -1;  // direction away from m
+  if (cnt <= 0) return;
+  const BlockSrc<double> src = block_src(Wg, nb, nblk);
+  double w[RING][HB];
+#pragma unroll
+  for (int q = 0; q < RING; ++q)
+    if (q < cnt) wload_block(src, m + dj * (q + 1), w[q]);
+  for (int t0 = 0; t0 < cnt; t0 += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+      const int t = t0 + q;
+      if (t < cnt) {
+        const int j = m + dj * (t + 1);
+        bwd_step_d(nb, B.ncell, j, j - dj, nrhs, s, Z, w[q]);
+        if (t + RING < cnt) wload_block(src, m + dj * (t + RING + 1), w[q]);
+      }
+    }
+  }
+}
+
+// The whole two-ended solve of all right-hand sides in s.X by one wave:
+// Wf holds the forward inverses (blocks < m), Wt the backward inverses
+// (blocks > m) and Z_m at block m.
+__device__ __forceinline__ void twisted_cached(const Box& B, const double* Wf, const double* Wt,
+                                               int nrhs, const BoxLds& s) {
+  const int m = B.nblk / 2;
+  twist_fwd_cached(B, Wf, nrhs, s, s.Z, false);
+  twist_fwd_cached(B, Wt, nrhs, s, s.Z, true);
+  double zm[HB];
+  wload_block(block_src(Wt, B.nb, B.nblk), m, zm);
+  mid_step(B.nb, B.ncell, m, B.nblk, nrhs, s, s.Z, zm);
+  twist_back_cached(B, Wf, nrhs, s, s.Z, false);
+  twist_back_cached(B, Wt, nrhs, s, s.Z, true);
 }
 
 // Forward and backward sweeps of one right-hand side in s.X with the cached
