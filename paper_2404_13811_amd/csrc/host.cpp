@@ -68,6 +68,7 @@ struct mrcm_ctx {
   int* d_seed_off = nullptr;
   Iface* d_ifc = nullptr;
   int* d_members = nullptr;
+  Box* d_obox_col = nullptr;  // oversampled boxes in colour order (members order)
 
   // device workspace
   double *fac = nullptr, *facs = nullptr, *facp = nullptr, *scr = nullptr;
@@ -170,7 +171,7 @@ void drop_graph(mrcm_ctx* c);
 
 void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
-  dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members);
+  dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members); dfree(c->d_obox_col);
   dfree(c->fac); dfree(c->fact); dfree(c->facs); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
   dfree(c->fac32); dfree(c->facp32); dfree(c->d_iters); dfree(c->d_resid);
   dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
@@ -679,6 +680,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->d_seed_off, nsub + 1);
   ALLOC(c->d_ifc, c->ifc.size());
   ALLOC(c->d_members, c->members.size());
+  ALLOC(c->d_obox_col, c->members.size());
   ALLOC(c->fac, c->fac_n);
   ALLOC(c->fact, c->fac_n);
   ALLOC(c->facp, c->facp_n);
@@ -712,6 +714,11 @@ mrcm_status make_plan(mrcm_ctx* c) {
   if (!c->ifc.empty())
     HIPCHK(c, hipMemcpy(c->d_ifc, c->ifc.data(), c->ifc.size() * sizeof(Iface), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_members, c->members.data(), c->members.size() * sizeof(int), hipMemcpyHostToDevice));
+  {
+    std::vector<Box> col(c->members.size());
+    for (size_t i = 0; i < col.size(); ++i) col[i] = c->obox[c->members[i]];
+    HIPCHK(c, hipMemcpy(c->d_obox_col, col.data(), col.size() * sizeof(Box), hipMemcpyHostToDevice));
+  }
 
   // interface solver
   c->use_bcr = false;
@@ -1067,11 +1074,11 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
       ++c->n_ck;
     }
     if (c->prec == MRCM_FP32_REFINE) {
-      HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+      HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
                                   c->beta_sm, c->fac32, p, gflux, c->tol, c->max_refine,
                                   c->d_iters, c->d_resid, c->flags, c->lds32_smooth, nt, s));
     } else if (c->wave) {
-      HIPCHK(c, launch_smooth_w(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
+      HIPCHK(c, launch_smooth_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
                                 c->beta_sm, c->fac, c->fact, c->tco, c->scr, p, gflux,
                                 c->lds_smooth, nt, s));
     } else {
@@ -1218,7 +1225,7 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
     ph.ncol = 1 << c->d;
     for (int col = 0; col <= ph.ncol; ++col) ph.off[col] = c->member_off[col];
     const hipError_t e =
-        launch_smooth_grid(c->geo, c->d_obox, c->d_members, ph, nphase, c->K, c->f, c->bcv,
+        launch_smooth_grid(c->geo, c->d_obox_col, ph, nphase, c->K, c->f, c->bcv,
                            c->beta_sm, c->fac, c->fact, c->tco, c->p, c->gflux, c->lds_smooth,
                            c->smooth_nt, c->persist_groups, s);
     if (e == hipSuccess) {

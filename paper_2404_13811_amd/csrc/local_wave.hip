@@ -334,7 +334,6 @@ __device__ __forceinline__ void smooth_box(const Geo& g, const Box& B, const dou
 // does not depend on NT.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ boxes,
-                                                 const int* __restrict__ members,
                                                  const double* __restrict__ K,
                                                  const double* __restrict__ f,
                                                  const double* __restrict__ bcv, double beta,
@@ -344,7 +343,7 @@ __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ 
                                                  double* __restrict__ p,
                                                  double* __restrict__ gflux) {
   extern __shared__ __align__(16) double dsm[];
-  const Box B = boxes[members[blockIdx.x]];
+  const Box B = boxes[blockIdx.x];
   double w[RING][HB], zm[HB];
   smooth_preload<NT>(B, fac + B.fac, fact + B.fac, w, zm);
   smooth_box<NT>(g, B, K, f, bcv, beta, fac + B.fac, fact + B.fac, tcoup, p, gflux, w, zm, dsm);
@@ -359,7 +358,6 @@ __global__ void __launch_bounds__(NT) k_smooth_w(Geo g, const Box* __restrict__ 
 // not change during smoothing).  Every workgroup passes every barrier.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_smooth_grid(Geo g, const Box* __restrict__ boxes,
-                                                    const int* __restrict__ members,
                                                     SmoothPhases ph, int nphase,
                                                     const double* __restrict__ K,
                                                     const double* __restrict__ f,
@@ -372,7 +370,7 @@ __global__ void __launch_bounds__(NT) k_smooth_grid(Geo g, const Box* __restrict
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   const int G = gridDim.x, b0 = blockIdx.x;
   auto count = [&](int k) { return ph.off[k % ph.ncol + 1] - ph.off[k % ph.ncol]; };
-  auto box_at = [&](int k, int j) { return members[ph.off[k % ph.ncol] + j]; };
+  auto box_at = [&](int k, int j) { return ph.off[k % ph.ncol] + j; };
   auto preload = [&](int bi, double w[RING][HB], double zm[HB]) {
     const Box B = boxes[bi];
     smooth_preload<NT>(B, fac + B.fac, fact + B.fac, w, zm);
@@ -433,7 +431,7 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
   return hipGetLastError();
 }
 
-hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
+hipError_t launch_smooth_w(const Geo& g, const Box* boxes, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* fact, const double* tcoup, double* scr,
                            double* p, double* gflux, size_t lds, int nt, hipStream_t s) {
@@ -444,7 +442,7 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
 #define MRCM_SMOOTH_NT(N)                                                                     \
   e = set_lds(k_smooth_w<N>, lds);                                                            \
   if (e != hipSuccess) return e;                                                              \
-  hipLaunchKernelGGL(k_smooth_w<N>, dim3(nmem), dim3(N), lds, s, g, boxes, members, K, f, bcv, \
+  hipLaunchKernelGGL(k_smooth_w<N>, dim3(nmem), dim3(N), lds, s, g, boxes, K, f, bcv,          \
                      beta, fac, fact, tcoup, p, gflux);
   if (nt == 64) {
     MRCM_SMOOTH_NT(64)
@@ -459,8 +457,7 @@ hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, i
   return hipGetLastError();
 }
 
-hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const int* members,
-                              const SmoothPhases& ph, int nphase, const double* K, const double* f,
+hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const SmoothPhases& ph, int nphase, const double* K, const double* f,
                               const double* bcv, double beta, const double* fac, const double* fact,
                               const double* tcoup, double* p, double* gflux, size_t lds, int nt,
                               int max_groups, hipStream_t s) {
@@ -477,7 +474,7 @@ hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const int* members
   if (!coop) return hipErrorNotSupported;
   Geo gg = g;
   SmoothPhases pp = ph;
-  void* args[] = {&gg, &boxes, &members, &pp, &nphase, &K, &f, &bcv, &beta, &fac, &fact, &tcoup, &p, &gflux};
+  void* args[] = {&gg, &boxes, &pp, &nphase, &K, &f, &bcv, &beta, &fac, &fact, &tcoup, &p, &gflux};
   auto go = [&](auto kern, int N) -> hipError_t {
     hipError_t r = set_lds(kern, lds);
     if (r != hipSuccess) return r;

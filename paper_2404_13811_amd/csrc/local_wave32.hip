@@ -548,7 +548,6 @@ __host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1) {
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_smooth32(Geo g, const Box* __restrict__ boxes,
-                                                 const int* __restrict__ members,
                                                  const double* __restrict__ K,
                                                  const double* __restrict__ f,
                                                  const double* __restrict__ bcv, double beta,
@@ -559,7 +558,7 @@ __global__ void __launch_bounds__(NT) k_smooth32(Geo g, const Box* __restrict__ 
                                                  unsigned long long* resid, int* flags) {
   extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmemF sm;
-  const Box B = boxes[members[blockIdx.x]];
+  const Box B = boxes[blockIdx.x];
   if (threadIdx.x == 0) sm.flag = 0;
   SmoothLds r = carve_smooth(dsm, B);
   const int nc = B.ncell;
@@ -616,7 +615,7 @@ hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int 
   return hipGetLastError();
 }
 
-hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members, int nmem,
+hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
                              const float* fac32, double* p, double* gflux, double tol,
                              int max_refine, int* iters, unsigned long long* resid, int* flags,
@@ -626,7 +625,7 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members,
 #define MRCM_SMOOTH32_NT(N)                                                                     \
   e = set_lds(k_smooth32<N>, lds);                                                              \
   if (e != hipSuccess) return e;                                                                \
-  hipLaunchKernelGGL(k_smooth32<N>, dim3(nmem), dim3(N), lds, s, g, boxes, members, K, f, bcv,  \
+  hipLaunchKernelGGL(k_smooth32<N>, dim3(nmem), dim3(N), lds, s, g, boxes, K, f, bcv,           \
                      beta, fac32, p, gflux, tol, max_refine, iters, resid, flags);
   if (nt == 64) {
     MRCM_SMOOTH32_NT(64)

@@ -122,7 +122,7 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
                           double* ubar, double* pibar, double* fact, int* flags, size_t lds,
                           hipStream_t s);
-hipError_t launch_smooth_w(const Geo& g, const Box* boxes, const int* members, int nmem,
+hipError_t launch_smooth_w(const Geo& g, const Box* boxes, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* fact, const double* tcoup, double* scr,
                            double* p, double* gflux, size_t lds, int nt, hipStream_t s);
@@ -139,8 +139,7 @@ struct SmoothPhases {
 // boxes; hipErrorNotSupported when the device has no cooperative launch,
 // hipErrorCooperativeLaunchTooLarge when not one workgroup fits (nothing is
 // launched in either case)
-hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const int* members,
-                              const SmoothPhases& ph, int nphase, const double* K, const double* f,
+hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const SmoothPhases& ph, int nphase, const double* K, const double* f,
                               const double* bcv, double beta, const double* fac, const double* fact,
                               const double* tcoup, double* p, double* gflux, size_t lds, int nt,
                               int max_groups, hipStream_t s);
@@ -154,7 +153,7 @@ hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int 
                             double* tr_phi, double* tr_beta, double* pbar, double* ubar,
                             double* pibar, double tol, int max_refine, int* iters,
                             unsigned long long* resid, int* flags, size_t lds, hipStream_t s);
-hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, const int* members, int nmem,
+hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
                              const float* fac32, double* p, double* gflux, double tol,
                              int max_refine, int* iters, unsigned long long* resid, int* flags,
