@@ -62,9 +62,9 @@ __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double*
 
 // LDS of a basis box: the box arrays with its right-hand sides (the Z
 // scratch of BoxLds serves wave 0), the Z scratch of wave 1, and the forward
-// Schur complement of the meeting block in the block register layout.
+// Schur complement of the meeting block (nb x nb, nb = m0, row-major).
 __host__ __device__ inline size_t basis_lds_doubles(int m0, int m1, int nrhs) {
-  return box_lds_doubles(m0, m1, nrhs) + (size_t)nrhs * NBW + 64 * HB + 2;
+  return box_lds_doubles(m0, m1, nrhs) + (size_t)nrhs * NBW + (size_t)m0 * m0 + 2;
 }
 
 // Store the nb x nb block held in the register layout w to Wj (row-major).
@@ -141,8 +141,12 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
       fwd_step_d(nb, nc, j, j - 1, j > 0, nrhs, s, s.Z, w);
     }
     wbuild(nb, m, s, w);  // S_m
+    const int c = L & 31, h = L >> 5;
 #pragma unroll
-    for (int i = 0; i < HB; ++i) Sm[i * 64 + L] = w[i];
+    for (int i = 0; i < HB; ++i) {
+      const int r = HB * h + i;
+      if (r < nb && c < nb) Sm[r * nb + c] = w[i];
+    }
   } else {
     for (int j = nblk - 1; j > m; --j) {
       wbuild_t(nb, j, j < nblk - 1 ? j : -1, s, w);
@@ -161,7 +165,8 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
 #pragma unroll
     for (int i = 0; i < HB; ++i) {
       const int r = HB * h + i;
-      const double smi = Sm[i * 64 + L];
+      // identity padding outside the nb x nb block, as wbuild leaves it
+      const double smi = (r < nb && c < nb) ? Sm[r * nb + c] : (r == c ? 1.0 : 0.0);
       const double tr = (m < nblk - 1 && r < nb) ? Tm[r] : 0.0;
       w[i] = (m < nblk - 1 && r < nb && c < nb) ? fma(-tr * tc, w[i], smi) : smi;
     }
