@@ -19,6 +19,8 @@
 #include "mrcm_internal.h"
 #include "pivot4.h"
 
+#include <type_traits>
+
 namespace mrcm {
 namespace {
 
@@ -180,45 +182,8 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
 // C = [C0] + al1 A1 B1 + al2 A2 B2 for a batch of tasks; the operands are
 // n x n matrices at element offsets in the pool with leading dimension ld
 // (whole blocks, or quarters of a block in the two-by-two inverse).  One
-// workgroup of 256 threads per 32 x 32 output tile; the whole 32 x n strip
-// of A (transposed, k-major) and n x 32 strip of B are staged in LDS with
-// all global loads of a chunk in flight before the stores; each thread
-// computes a 2 x 2 set of outputs.
-constexpr int GT = 32, GCH = 16;
-
-// Row stride of the staged A strip: n + 1 doubles, so that the strip's
-// rows start in different banks (row-major writes and the matrix-operand
-// reads, 16 rows at one k, are both free of bank conflicts).
-__device__ __forceinline__ int astride(int n) { return n + 1; }
-
-__device__ __forceinline__ void stage_strips(const double* __restrict__ A, const double* __restrict__ B,
-                                             double al, int n, int ld, int tr0, int tc0, double* As,
-                                             double* Bs) {
-  // As[r * (n + 1) + k] = al * A[tr0 + r][k];  Bs[k * GT + c] = B[k][tc0 + c]
-  const int cnt = GT * n;  // elements per strip
-  const int as = astride(n);
-  for (int e0 = 0; e0 < cnt; e0 += 256 * GCH) {
-    double va[GCH], vb[GCH];
-#pragma unroll
-    for (int u = 0; u < GCH; ++u) {
-      const int e = e0 + u * 256 + threadIdx.x;
-      const bool ok = e < cnt;
-      const int ra = e / n, ka = e - (e / n) * n;  // A row-major: consecutive k
-      const int kb = e >> 5, cb = e & 31;          // B: 32 consecutive columns
-      va[u] = ok ? A[(long long)(tr0 + ra) * ld + ka] : 0.0;
-      vb[u] = ok ? B[(long long)kb * ld + tc0 + cb] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < GCH; ++u) {
-      const int e = e0 + u * 256 + threadIdx.x;
-      if (e < cnt) {
-        const int ra = e / n, ka = e - (e / n) * n;
-        As[ra * as + ka] = al * va[u];
-        Bs[e] = vb[u];
-      }
-    }
-  }
-}
+// workgroup of 256 threads (four waves) per 32 x 32 output tile.
+constexpr int GT = 32;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -228,26 +193,67 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // and B[l / 16][l % 16] of the k-slice and holds D[4r + l / 16][l % 16] in
 // accumulator element r); two accumulators alternate over the k-slices so
 // that consecutive instructions do not wait on each other.
+//
+// The k dimension of every product term is cut into chunks of KC: the A
+// rows of the tile (32 x KC, row-major with stride KC + 1 so that the
+// strip's rows start in different banks) and the B columns (KC x 32) of a
+// chunk are staged in LDS, and the global loads of the next chunk (of this
+// term or the next) are in flight while the matrix instructions run on the
+// current one.  A small KC keeps the LDS of a workgroup small enough for
+// several workgroups per CU.
+template <int KC>
+__host__ __device__ constexpr size_t gemm_lds_doubles() {
+  return (size_t)GT * (KC + 1) + (size_t)KC * GT;
+}
+
+template <int KC>
 __device__ __forceinline__ void gemm_tile(double* pool, const BcrGemm& T, int n, int ld, int tile,
                                           double* smem) {
-  double* As = smem;                   // GT x (n + 1)
-  double* Bs = smem + GT * astride(n);  // n x GT
+  constexpr int NA = GT * KC / 256;  // A (and B) elements per thread per chunk
+  constexpr int AS = KC + 1;
+  double* As = smem;            // GT x (KC + 1)
+  double* Bs = smem + GT * AS;  // KC x GT
   const int ntile = n / GT;
   const int tr0 = (tile / ntile) * GT, tc0 = (tile % ntile) * GT;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, ln = tid & 63;
   const int qr = (wv >> 1) * 16, qc = (wv & 1) * 16;  // quadrant of this wave
   const int li = ln & 15, lk = ln >> 4;
+  const int t0 = T.a1 >= 0 ? 0 : 1;  // first product term present
+  const int nterm = (T.a1 >= 0 ? 1 : 0) + (T.a2 >= 0 ? 1 : 0);
+  const int nch = n / KC, total = nterm * nch;
+  double va[NA], vb[NA];
+  auto load = [&](int c) {
+    const int term = c < nch ? t0 : 1;
+    const int k0 = (c % nch) * KC;
+    const double* A = pool + (term ? T.a2 : T.a1);
+    const double* B = pool + (term ? T.b2 : T.b1);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = u * 256 + tid;
+      const int ra = e / KC, ka = e % KC;  // A row-major: consecutive k
+      const int kb = e >> 5, cb = e & 31;  // B: 32 consecutive columns
+      va[u] = A[(long long)(tr0 + ra) * ld + k0 + ka];
+      vb[u] = B[(long long)(k0 + kb) * ld + tc0 + cb];
+    }
+  };
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int term = 0; term < 2; ++term) {
-    const long long ai = term ? T.a2 : T.a1, bi = term ? T.b2 : T.b1;
-    if (ai < 0) continue;
-    if (term) __syncthreads();
-    stage_strips(pool + ai, pool + bi, term ? T.al2 : T.al1, n, ld, tr0, tc0, As, Bs);
+  if (total > 0) load(0);
+  for (int c = 0; c < total; ++c) {
+    const double al = (c < nch ? t0 : 1) ? T.al2 : T.al1;
+    if (c) __syncthreads();  // the previous chunk's operands are read
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = u * 256 + tid;
+      As[(e / KC) * AS + e % KC] = al * va[u];
+      Bs[e] = vb[u];
+    }
     __syncthreads();
-    const double* ap = As + (qr + li) * astride(n) + lk;
+    if (c + 1 < total) load(c + 1);
+    const double* ap = As + (qr + li) * AS + lk;
     const double* bq = Bs + lk * GT + qc + li;
-#pragma unroll 4
-    for (int k = 0; k < n; k += 8) {
+#pragma unroll
+    for (int k = 0; k < KC; k += 8) {
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], bq[k * GT], acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k + 4], bq[(k + 4) * GT], acc1, 0, 0, 0);
     }
@@ -264,12 +270,13 @@ __device__ __forceinline__ void gemm_tile(double* pool, const BcrGemm& T, int n,
   }
 }
 
+template <int KC>
 __global__ void __launch_bounds__(256) k_bcr_gemm(double* __restrict__ pool,
                                                   const BcrGemm* __restrict__ tasks, int n, int ld) {
   extern __shared__ double smem[];
   const int ntile = n / GT;
   const int task = blockIdx.x / (ntile * ntile);
-  gemm_tile(pool, tasks[task], n, ld, blockIdx.x - task * ntile * ntile, smem);
+  gemm_tile<KC>(pool, tasks[task], n, ld, blockIdx.x - task * ntile * ntile, smem);
 }
 
 // y = [y0] + al1 A1 x1 + al2 A2 x2.  Workgroup (task, group of 16 rows);
@@ -310,6 +317,7 @@ __global__ void __launch_bounds__(256) k_bcr_gemv(const double* __restrict__ poo
 // other, in one launch: workgroups [0, ngblk) are product tiles, the rest
 // row groups of the vector tasks.  The caller guarantees that no vector
 // task reads a block a product task of the same launch writes.
+template <int KC>
 __global__ void __launch_bounds__(256) k_bcr_gemm_gemv(double* pool, double* __restrict__ vec,
                                                        const BcrGemm* __restrict__ gtasks, int ngblk,
                                                        const BcrGemv* __restrict__ vtasks, int n,
@@ -319,7 +327,7 @@ __global__ void __launch_bounds__(256) k_bcr_gemm_gemv(double* pool, double* __r
   if (b < ngblk) {
     const int ntile = n / GT;
     const int task = b / (ntile * ntile);
-    gemm_tile(pool, gtasks[task], n, ld, b - task * ntile * ntile, smem);
+    gemm_tile<KC>(pool, gtasks[task], n, ld, b - task * ntile * ntile, smem);
   } else {
     const int rgs = bp / 16;
     const int i = b - ngblk;
@@ -391,18 +399,35 @@ hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, 
   return hipGetLastError();
 }
 
+// Chunk of the k dimension for products of n x n blocks: whole 128-wide
+// operands when n = 128 (the latency-bound case: one round of loads per
+// term), 64 for larger blocks (several workgroups per CU), else 32.
+template <typename F>
+hipError_t with_chunk(int n, F f) {
+  if (n == 128) return f(std::integral_constant<int, 128>());
+  if (n % 64 == 0) return f(std::integral_constant<int, 64>());
+  return f(std::integral_constant<int, 32>());
+}
+
+template <typename KF>
+hipError_t gemm_lds_attr(KF kern, size_t lds) {
+  if (lds > 64 * 1024)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
 hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n, int ld, hipStream_t s) {
   if (ntask <= 0) return hipSuccess;
   if (n % GT || n > kBcrMaxBlock) return hipErrorInvalidValue;
   const int ntile = n / GT;
-  const size_t lds = sizeof(double) * ((size_t)GT * (n + 1) + (size_t)n * GT);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_bcr_gemm,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return with_chunk(n, [&](auto kc) -> hipError_t {
+    constexpr int KC = decltype(kc)::value;
+    const size_t lds = sizeof(double) * gemm_lds_doubles<KC>();
+    hipError_t e = gemm_lds_attr(k_bcr_gemm<KC>, lds);
     if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_bcr_gemm, dim3(ntask * ntile * ntile), dim3(256), lds, s, pool, tasks, n, ld);
-  return hipGetLastError();
+    hipLaunchKernelGGL(k_bcr_gemm<KC>, dim3(ntask * ntile * ntile), dim3(256), lds, s, pool, tasks, n, ld);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_bcr_gemm_gemv(double* pool, double* vec, const BcrGemm* gtasks, int ngemm,
@@ -411,16 +436,16 @@ hipError_t launch_bcr_gemm_gemv(double* pool, double* vec, const BcrGemm* gtasks
   if (ngemm <= 0 && ngemv <= 0) return hipSuccess;
   if (n % GT || n > kBcrMaxBlock || bp % 16) return hipErrorInvalidValue;
   const int ntile = n / GT;
-  const size_t lds = sizeof(double) * ((size_t)GT * (n + 1) + (size_t)n * GT);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_bcr_gemm_gemv,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   const int ngblk = ngemm * ntile * ntile;
-  hipLaunchKernelGGL(k_bcr_gemm_gemv, dim3(ngblk + ngemv * (bp / 16)), dim3(256), lds, s, pool, vec,
-                     gtasks, ngblk, vtasks, n, ld, bp);
-  return hipGetLastError();
+  return with_chunk(n, [&](auto kc) -> hipError_t {
+    constexpr int KC = decltype(kc)::value;
+    const size_t lds = sizeof(double) * gemm_lds_doubles<KC>();
+    hipError_t e = gemm_lds_attr(k_bcr_gemm_gemv<KC>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bcr_gemm_gemv<KC>, dim3(ngblk + ngemv * (bp / 16)), dim3(256), lds, s, pool,
+                       vec, gtasks, ngblk, vtasks, n, ld, bp);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks, int ntask, int bp,
