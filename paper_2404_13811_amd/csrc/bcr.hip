@@ -50,7 +50,8 @@ constexpr int TR = 4, TC = 8, PB = 4;  // tile rows / columns; pivots per step
 constexpr int kInvThreads = 512;
 
 __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ pool,
-                                                         const long long* __restrict__ offs, int bp,
+                                                         const long long* __restrict__ offs,
+                                                         const int* __restrict__ npiv, int bp,
                                                          int ld, int* flags) {
   __shared__ __align__(16) double rpan[2][PB * kBcrInvMax];  // [m][col] = A[k + m][col]
   __shared__ __align__(16) double cpan[2][kBcrInvMax * PB];  // [row][m] = A[row][k + m]
@@ -75,11 +76,15 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
     }
   }
   bool bad = false;
-  for (int kt = 0; kt < ntc; ++kt) {
+  // pivots beyond the block's own size act on identity padding, which
+  // they leave unchanged: skipped
+  const int kend = npiv[blockIdx.x];
+  for (int kt = 0; kt * TC < kend; ++kt) {
     const bool own_c = tc == kt;
 #pragma unroll
     for (int k2 = 0; k2 < TC; k2 += PB) {
       const int k = kt * TC + k2;
+      if (k >= kend) break;
       const bool own_r = tr == k / TR;
       double* rp = rpan[k2 / PB];
       double* cp = cpan[k2 / PB];
@@ -391,11 +396,12 @@ __global__ void k_bcr_gather(const double* __restrict__ xv, const int* __restric
 
 }  // namespace
 
-hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
+hipError_t launch_bcr_inv(double* pool, const long long* offs, const int* npiv, int nblk, int n,
+                          int ld, int* flags,
                           hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   if (n % TC || n > kBcrInvMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bcr_inv, dim3(nblk), dim3(kInvThreads), 0, s, pool, offs, n, ld, flags);
+  hipLaunchKernelGGL(k_bcr_inv, dim3(nblk), dim3(kInvThreads), 0, s, pool, offs, npiv, n, ld, flags);
   return hipGetLastError();
 }
 

@@ -101,6 +101,7 @@ struct mrcm_ctx {
   int *d_row_lvl = nullptr, *d_row_loc = nullptr, *d_col_lvl = nullptr, *d_col_loc = nullptr;
   int* d_lsize = nullptr;
   long long* d_binv = nullptr;
+  int* d_binvn = nullptr;  // pivots each inverse needs (its layer's size, rounded up to 4)
   BcrGemm* d_bgemm = nullptr;
   BcrGemv* d_bgemv = nullptr;
   double *bpool = nullptr, *bvec = nullptr;
@@ -178,7 +179,7 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
   dfree(c->AB); dfree(c->rhs); dfree(c->X); dfree(c->p); dfree(c->gflux); dfree(c->partial);
   dfree(c->d_row_lvl); dfree(c->d_row_loc); dfree(c->d_col_lvl); dfree(c->d_col_loc);
-  dfree(c->d_lsize); dfree(c->d_binv); dfree(c->d_bgemm); dfree(c->d_bgemv);
+  dfree(c->d_lsize); dfree(c->d_binv); dfree(c->d_binvn); dfree(c->d_bgemm); dfree(c->d_bgemv);
   dfree(c->bpool); dfree(c->bvec);
   dfree(c->p_tune); dfree(c->gflux_tune);
   dfree(c->ck_p); dfree(c->ck_g);
@@ -257,8 +258,8 @@ void family(const mrcm_ctx* c, int q, const int lo[3], const int hi[3], const in
 // layer block is not square or exceeds kBcrMaxBlock.
 bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
               std::vector<int>& col_lvl, std::vector<int>& col_loc, std::vector<int>& lsize,
-              std::vector<long long>& inv, std::vector<BcrGemm>& gemm,
-              std::vector<BcrGemv>& gemv) {
+              std::vector<long long>& inv, std::vector<int>& invn,
+              std::vector<BcrGemm>& gemm, std::vector<BcrGemv>& gemv) {
   const Geo& g = c->geo;
   const int d = c->d, nsub = g.nsub, n = c->nX;
   const int M = g.M[d - 1];
@@ -348,9 +349,16 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
                       const std::vector<int>& s2) {
     const int nb = (int)blk.size();
     if (nb == 0) return;
+    // pivots a block's inverse needs: its layer's size rounded up to the
+    // four pivots of a step (the padding beyond is identity, which a pivot
+    // step leaves unchanged)
+    auto piv = [](int nn) { return nn <= 0 ? 0 : (nn + 3) / 4 * 4; };
     if (bp <= kBcrInvMax) {
       const int o = (int)inv.size();
-      for (int b : blk) inv.push_back(b * bs);
+      for (int b : blk) {
+        inv.push_back(b * bs);
+        invn.push_back(std::min(piv(lsize[b]), bp));
+      }
       op(0, o, nb, bp, bp);
       return;
     }
@@ -362,7 +370,10 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
     auto T1 = [&](int i) { return s1[i] * bs; };
     auto T2 = [&](int i) { return s2[i] * bs; };
     int o = (int)inv.size();
-    for (int i = 0; i < nb; ++i) inv.push_back(A(i));
+    for (int i = 0; i < nb; ++i) {
+      inv.push_back(A(i));
+      invn.push_back(std::min(piv(lsize[blk[i]]), hh));
+    }
     op(0, o, nb, hh, bp);
     o = (int)gemm.size();
     for (int i = 0; i < nb; ++i) {
@@ -374,7 +385,10 @@ bool bcr_plan(mrcm_ctx* c, std::vector<int>& row_lvl, std::vector<int>& row_loc,
     for (int i = 0; i < nb; ++i) gemm.push_back(BcrGemm{D(i), D(i), C(i), T1(i), -1, -1, -1.0, 0.0});
     op(1, o, nb, hh, bp);
     o = (int)inv.size();
-    for (int i = 0; i < nb; ++i) inv.push_back(D(i));
+    for (int i = 0; i < nb; ++i) {
+      inv.push_back(D(i));
+      invn.push_back(std::min(piv(lsize[blk[i]] - hh), hh));
+    }
     op(0, o, nb, hh, bp);
     o = (int)gemm.size();
     for (int i = 0; i < nb; ++i) {
@@ -725,9 +739,10 @@ mrcm_status make_plan(mrcm_ctx* c) {
   if (c->nX > 0 && c->iface_solver != MRCM_IFACE_BAND_LU) {
     std::vector<int> rl, ro, cl, co, ls;
     std::vector<long long> inv;
+    std::vector<int> invn;
     std::vector<BcrGemm> gm;
     std::vector<BcrGemv> gv;
-    const bool ok = bcr_plan(c, rl, ro, cl, co, ls, inv, gm, gv);
+    const bool ok = bcr_plan(c, rl, ro, cl, co, ls, inv, invn, gm, gv);
     if (!ok && c->iface_solver == MRCM_IFACE_BCR)
       return fail(c, MRCM_EINVAL,
                   "block cyclic reduction needs square layer blocks of at most %d unknowns",
@@ -741,6 +756,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
       ALLOC(c->d_col_loc, c->nX);
       ALLOC(c->d_lsize, M);
       ALLOC(c->d_binv, inv.size());
+      ALLOC(c->d_binvn, invn.size());
       ALLOC(c->d_bgemm, gm.size());
       ALLOC(c->d_bgemv, gv.size());
       ALLOC(c->bpool, 5LL * M * bs);
@@ -754,6 +770,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
       HIPCHK(c, up(c->d_col_loc, co.data(), co.size() * sizeof(int)));
       HIPCHK(c, up(c->d_lsize, ls.data(), ls.size() * sizeof(int)));
       HIPCHK(c, up(c->d_binv, inv.data(), inv.size() * sizeof(long long)));
+      HIPCHK(c, up(c->d_binvn, invn.data(), invn.size() * sizeof(int)));
       HIPCHK(c, up(c->d_bgemm, gm.data(), gm.size() * sizeof(BcrGemm)));
       HIPCHK(c, up(c->d_bgemv, gv.data(), gv.size() * sizeof(BcrGemv)));
       c->use_bcr = true;
@@ -768,7 +785,8 @@ mrcm_status run_bcr_ops(mrcm_ctx* c, hipStream_t s) {
   const int bp = c->bcr_bp;
   for (const auto& o : c->bcr_ops) {
     if (o.kind == 0)
-      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, o.cnt, o.n, o.ld, c->flags, s));
+      HIPCHK(c, launch_bcr_inv(c->bpool, c->d_binv + o.off, c->d_binvn + o.off, o.cnt, o.n, o.ld,
+                               c->flags, s));
     else if (o.kind == 1)
       HIPCHK(c, launch_bcr_gemm(c->bpool, c->d_bgemm + o.off, o.cnt, o.n, o.ld, s));
     else if (o.kind == 2)

@@ -177,8 +177,8 @@ hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl
                               const int* row_lvl, const int* row_loc, const int* col_lvl,
                               const int* col_loc, int M, int bp, double* pool, double* vec,
                               const int* lsize, hipStream_t s);
-hipError_t launch_bcr_inv(double* pool, const long long* offs, int nblk, int n, int ld, int* flags,
-                          hipStream_t s);
+hipError_t launch_bcr_inv(double* pool, const long long* offs, const int* npiv, int nblk, int n,
+                          int ld, int* flags, hipStream_t s);
 hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n, int ld, hipStream_t s);
 // independent products and block-vector products of one reduction step in
 // one launch (no vector task may read a block the products write)
