@@ -103,29 +103,29 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
   double* Z1 = s.Z + nrhs * NBW;
   double* Sm = Z1 + nrhs * NBW;
   const int nc = B.ncell;
-  // set-up by wave 0: box arrays, seed right-hand sides, couplings
-  if (wv == 0) {
-    load_box(g, B, K, beta, s);
-    for (int e = L; e < nrhs * nc; e += 64) s.X[e] = 0.0;
-    wsync();
-    for (int k = 0; k < nrhs; ++k) {
-      const Seed sd = seeds[B.seed0 + k];
-      const int a = sd.side >> 1, so = sd.side & 1;
-      const int nf = (a == 0) ? s.m1 : s.m0;
-      #pragma unroll 1
-      for (int t = L; t < nf; t += 64) {
-        int c[3];
-        if (a == 0) { c[0] = so ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
-        else { c[1] = so ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
-        c[2] = 0;
-        const int ox = c[0] + (a == 0 ? (so ? 1 : -1) : 0), oy = c[1] + (a == 1 ? (so ? 1 : -1) : 0);
-        const double kc = kat(s, B, c[0], c[1]);
-        const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
-        s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
-      }
-    }
-    for (int e = L; e < nc; e += 64) tcoup[B.scr + e] = s.Tn[e];
+  // set-up by both waves: box arrays, seed right-hand sides, couplings
+  load_box<128>(g, B, K, beta, s);
+  for (int e = tid; e < nrhs * nc; e += 128) s.X[e] = 0.0;
+  __syncthreads();
+  // T^R times the seed on the cells of its side, all seeds at once
+  const int fs = s.m0 > s.m1 ? s.m0 : s.m1;  // faces of the longest side
+  #pragma unroll 1
+  for (int e = tid; e < nrhs * fs; e += 128) {
+    const int k = e / fs, t = e % fs;
+    const Seed sd = seeds[B.seed0 + k];
+    const int a = sd.side >> 1, so = sd.side & 1;
+    const int nf = (a == 0) ? s.m1 : s.m0;
+    if (t >= nf) continue;
+    int c[3];
+    if (a == 0) { c[0] = so ? B.hi[0] - 1 : B.lo[0]; c[1] = B.lo[1] + t; }
+    else { c[1] = so ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
+    c[2] = 0;
+    const int ox = c[0] + (a == 0 ? (so ? 1 : -1) : 0), oy = c[1] + (a == 1 ? (so ? 1 : -1) : 0);
+    const double kc = kat(s, B, c[0], c[1]);
+    const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+    s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
   }
+  for (int e = tid; e < nc; e += 128) tcoup[B.scr + e] = s.Tn[e];
   __syncthreads();
   const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
   double* Wf = fac + B.fac;

@@ -198,16 +198,16 @@ template <int NT = 64>
 __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta, BoxLds& s);
 
 // Load the K tile and the matrix coefficients of the box into LDS.
+template <int NT = 64>
 __device__ __forceinline__ void load_box(const Geo& g, const Box& B, const double* K, double beta, BoxLds& s) {
-  const int L = lane_id();
   const int W2 = s.m0 + 2, H2 = s.m1 + 2;
-  gather<16>(s.Kt, W2 * H2, [&](int e, double& fill) -> const double* {
+  gather<1024 / NT, NT>(s.Kt, W2 * H2, [&](int e, double& fill) -> const double* {
     const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
     fill = 1.0;
     return (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K + x + g.n[0] * y : nullptr;
   });
-  wsync();
-  coef_box(g, B, beta, s);
+  bsync<NT>();
+  coef_box<NT>(g, B, beta, s);
 }
 
 // Diagonal and couplings of the box matrix from the K tile in LDS.
