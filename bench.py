@@ -102,8 +102,7 @@ def time_solves(wl, precision, steps, warmup, tol, persistent=False):
         m.build_basis(ctx)
         m.solve_interface(ctx)
         m.smooth(ctx, wl.nsmooth)
-        m.get_pressure(ctx, p)
-        m.get_flux(ctx, fl)
+        m.get_solution(ctx, p, fl)
 
     for _ in range(warmup):
         step()

@@ -167,9 +167,10 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* ctx);
 mrcm_status mrcm_smooth(mrcm_ctx* ctx, int nsteps);
 
 /* Execution of the smoothing sweeps (Steps 6-7).  use_graph != 0 (default):
- * one sweep (the 2^dim colour phases) is captured into a HIP graph at the
- * first mrcm_smooth after a configuration change and replayed per step on
- * the context's stream.  threads_per_box: 64, 128 or 256 threads per
+ * the nsteps sweeps of an mrcm_smooth call (nsteps x 2^dim colour phases)
+ * are captured into one HIP graph at the first call with that step count
+ * after a configuration change, and replayed as one launch on the context's
+ * stream.  threads_per_box: 64, 128 or 256 threads per
  * oversampled box, or 0 (default) to time the three on one sweep over a copy
  * of the current state and keep the fastest (done once per configuration,
  * outside the timed region of mrcm_smooth).  The choice does not change the
@@ -199,6 +200,12 @@ mrcm_status mrcm_get_pressure(mrcm_ctx* ctx, double* p_dev);
  * carries the value of the subdomain owning the cell (the normal flux is
  * double-valued there). */
 mrcm_status mrcm_get_flux(mrcm_ctx* ctx, double* flux_dev);
+
+/* Pressure (as mrcm_get_pressure) and face velocities (as mrcm_get_flux) in
+ * one call: both outputs are enqueued before the error flags of the solve
+ * are read, so the stream is synchronised once.  Errors: MRCM_EINVAL (NULL
+ * output), MRCM_ESTATE, and the errors of the solve that produced them. */
+mrcm_status mrcm_get_solution(mrcm_ctx* ctx, double* p_dev, double* flux_dev);
 
 /* Interface unknowns X (n_unknowns values, subdomain-major, seeds of each
  * subdomain in side order), device pointer.  For tests. */

@@ -17,7 +17,7 @@ SYMBOLS = ("mrcm_create", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_
            "mrcm_set_robin", "mrcm_set_smoothing", "mrcm_set_smoothing_persistent",
            "mrcm_set_checkpointing", "mrcm_adjoint",
            "mrcm_set_precision", "mrcm_build_basis", "mrcm_solve_interface", "mrcm_smooth",
-           "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_coefficients", "mrcm_get_stats",
+           "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_solution", "mrcm_get_coefficients", "mrcm_get_stats",
            "mrcm_last_error", "mrcm_destroy")
 
 
@@ -65,6 +65,7 @@ def load():
         "mrcm_smooth": [vp, i],
         "mrcm_get_pressure": [vp, vp],
         "mrcm_get_flux": [vp, vp],
+        "mrcm_get_solution": [vp, vp, vp],
         "mrcm_get_coefficients": [vp, vp],
         "mrcm_get_stats": [vp, ctypes.POINTER(Stats)],
         "mrcm_destroy": [vp],

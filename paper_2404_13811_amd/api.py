@@ -139,6 +139,18 @@ def get_flux(ctx, out=None):
     return out
 
 
+def get_solution(ctx, p_out=None, flux_out=None):
+    """Pressure and face velocities with one stream synchronisation."""
+    n = ctx.ncells
+    if p_out is None:
+        p_out = torch.empty(n, dtype=torch.float64, device="cuda")
+    if flux_out is None:
+        flux_out = torch.empty(n * 2 * ctx.dim, dtype=torch.float64, device="cuda")
+    _check(ctx, "mrcm_get_solution",
+           _lib.load().mrcm_get_solution(ctx.handle, _dev(p_out, n), _dev(flux_out, n * 2 * ctx.dim)))
+    return p_out, flux_out
+
+
 def get_stats(ctx):
     st = _lib.Stats()
     _check(ctx, "mrcm_get_stats", _lib.load().mrcm_get_stats(ctx.handle, ctypes.byref(st)))

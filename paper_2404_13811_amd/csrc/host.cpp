@@ -85,6 +85,7 @@ struct mrcm_ctx {
   double *AB = nullptr, *rhs = nullptr, *X = nullptr;
   double *p = nullptr, *gflux = nullptr, *partial = nullptr;
   int* flags = nullptr;
+  int* flags_host = nullptr;  // pinned copy target of the error flags
 
   // block cyclic reduction of the interface system over the layers of
   // subdomains along the last axis (bcr.hip)
@@ -117,6 +118,7 @@ struct mrcm_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  int graph_steps = 0;  // smoothing steps the captured graph holds
   double* p_tune = nullptr;
   double* gflux_tune = nullptr;
   double ms_autotune = 0.0;
@@ -815,9 +817,10 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
 
 mrcm_status check_flags(mrcm_ctx* c) {
   if (c->checked_epoch == c->epoch) return MRCM_OK;
-  int fl = 0;
+  // one wait: the copy into pinned memory is ordered after the work
+  HIPCHK(c, hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemcpy(&fl, c->flags, sizeof(int), hipMemcpyDeviceToHost));
+  const int fl = *c->flags_host;
   if (!fl) c->checked_epoch = c->epoch;
   if (fl & kFlagBadK) return fail(c, MRCM_EINVAL, "permeability must be finite and positive");
   if (fl & kFlagNotPD) return fail(c, MRCM_ENOTPD, "local factorisation met a non-positive pivot");
@@ -878,6 +881,7 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (e == hipSuccess) e = hipMalloc((void**)&c->f, N * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->flags_host, sizeof(int), hipHostMallocDefault);
   for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   if (e == hipSuccess) e = launch_fill(c->bcv, 0.0, off, c->stream);
   if (e == hipSuccess) e = launch_fill(c->f, 0.0, N, c->stream);
@@ -1151,13 +1155,19 @@ mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
   return MRCM_OK;
 }
 
-// Capture one sweep into a graph (on a private stream), replayed by
-// mrcm_smooth on the context's stream.
-mrcm_status capture_sweep(mrcm_ctx* c) {
-  if (c->graph_exec) return MRCM_OK;
+// Capture nsteps sweeps into one graph (on a private stream), replayed by
+// mrcm_smooth on the context's stream; kept until a call asks for another
+// step count or the configuration changes.
+mrcm_status capture_sweep(mrcm_ctx* c, int nsteps) {
+  if (c->graph_exec && c->graph_steps == nsteps) return MRCM_OK;
+  if (c->graph_exec) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // no replay of the old graph in flight
+    drop_graph(c);
+  }
   if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  mrcm_status st = sweep(c, c->cap_stream, c->smooth_nt, c->p, c->gflux);
+  mrcm_status st = MRCM_OK;
+  for (int k = 0; k < nsteps && !st; ++k) st = sweep(c, c->cap_stream, c->smooth_nt, c->p, c->gflux);
   hipGraph_t gr = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
   if (st) {
@@ -1167,6 +1177,7 @@ mrcm_status capture_sweep(mrcm_ctx* c) {
   HIPCHK(c, e);
   c->graph = gr;
   HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  c->graph_steps = nsteps;
   return MRCM_OK;
 }
 
@@ -1207,7 +1218,7 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
     mrcm_status st = tune_smoothing(c, s);
     if (st) return st;
     if (c->use_graph && !c->ckpt) {
-      st = capture_sweep(c);
+      st = capture_sweep(c, nsteps);
       if (st) return st;
     }
   }
@@ -1254,13 +1265,13 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
       HIPCHK(c, e);
     }
   }
+  if (nsteps > 0 && c->use_graph && !c->ckpt) {
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, s));  // all nsteps sweeps
+    nsteps = 0;
+  }
   for (int step = 0; step < nsteps; ++step) {
-    if (c->use_graph && !c->ckpt) {
-      HIPCHK(c, hipGraphLaunch(c->graph_exec, s));
-    } else {
-      mrcm_status st = sweep(c, s, c->smooth_nt, c->p, c->gflux, c->ckpt);
-      if (st) return st;
-    }
+    mrcm_status st = sweep(c, s, c->smooth_nt, c->p, c->gflux, c->ckpt);
+    if (st) return st;
   }
   c->n_phase += nphase;
   HIPCHK(c, hipEventRecord(c->ev[5], s));
@@ -1281,6 +1292,15 @@ mrcm_status mrcm_get_flux(mrcm_ctx* c, double* flux_dev) {
   if (!c) return MRCM_EINVAL;
   if (!flux_dev) return fail(c, MRCM_EINVAL, "output is NULL");
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  HIPCHK(c, launch_flux_out(c->geo, c->K, c->p, c->gflux, c->bcv, flux_dev, c->stream));
+  return check_flags(c);
+}
+
+mrcm_status mrcm_get_solution(mrcm_ctx* c, double* p_dev, double* flux_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (!p_dev || !flux_dev) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  HIPCHK(c, launch_pressure_out(c->geo, c->p, p_dev, c->partial, c->stream));
   HIPCHK(c, launch_flux_out(c->geo, c->K, c->p, c->gflux, c->bcv, flux_dev, c->stream));
   return check_flags(c);
 }
@@ -1442,6 +1462,7 @@ mrcm_status mrcm_destroy(mrcm_ctx* c) {
   free_plan(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dfree(c->logk); dfree(c->K); dfree(c->f); dfree(c->bcv); dfree(c->flags);
+  if (c->flags_host) (void)hipHostFree(c->flags_host);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;

@@ -212,3 +212,30 @@ def test_persistent_smoothing_agrees_exactly(overlap):
         assert st["n_smooth_phases"] == steps[-1] * 2 ** wl.dim
         for (p, fl), (rp, rf) in zip(got, ref):
             assert np.array_equal(p, rp) and np.array_equal(fl, rf)
+
+
+def test_get_solution_matches_separate_outputs():
+    """mrcm_get_solution gives the pressure and flux of mrcm_get_pressure and
+    mrcm_get_flux, bit for bit, and smoothing calls with changing step
+    counts (each a graph of its own) agree with one call of their sum."""
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    wl = make_workload("c2", scale=4, overlap=2)
+    out = []
+    for steps in ([3], [1, 2]):
+        ctx = m.create(wl.dim, wl.ncell, wl.h)
+        try:
+            api.configure(ctx, wl, "fp64")
+            m.build_basis(ctx)
+            m.solve_interface(ctx)
+            for n in steps:
+                m.smooth(ctx, n)
+            p, fl = m.get_solution(ctx)
+            p2 = m.get_pressure(ctx)
+            fl2 = m.get_flux(ctx)
+            out.append((p.cpu().numpy(), fl.cpu().numpy()))
+            assert np.array_equal(out[-1][0], p2.cpu().numpy())
+            assert np.array_equal(out[-1][1], fl2.cpu().numpy())
+        finally:
+            m.destroy(ctx)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
