@@ -191,6 +191,14 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* ctx, int use_graph, int threads_per_box
  * per-phase form.  Default: off.  Errors: MRCM_EINVAL (max_groups < 0). */
 mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* ctx, int on, int max_groups);
 
+/* Phase timing (default on): HIP events on the context's stream around the
+ * phases of mrcm_build_basis, mrcm_solve_interface and mrcm_smooth, read by
+ * mrcm_get_stats (ms_basis, ms_basis_kernel, ms_interface,
+ * ms_interface_solve, ms_smooth of the last such call made with timing on).
+ * Off, the calls enqueue their kernels only.  Results are unchanged.
+ * Errors: MRCM_EINVAL (ctx NULL). */
+mrcm_status mrcm_set_timing(mrcm_ctx* ctx, int on);
+
 /* Pressure per cell (N values); shifted to zero mean when no side carries a
  * pressure condition. */
 mrcm_status mrcm_get_pressure(mrcm_ctx* ctx, double* p_dev);

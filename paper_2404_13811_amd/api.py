@@ -102,6 +102,10 @@ def set_smoothing_persistent(ctx, on=True, max_groups=0):
            _lib.load().mrcm_set_smoothing_persistent(ctx.handle, int(bool(on)), int(max_groups)))
 
 
+def set_timing(ctx, on=True):
+    _check(ctx, "mrcm_set_timing", _lib.load().mrcm_set_timing(ctx.handle, int(bool(on))))
+
+
 def set_robin(ctx, mode, mbf, smooth_value):
     m = BETA[mode] if isinstance(mode, str) else int(mode)
     _check(ctx, "mrcm_set_robin", _lib.load().mrcm_set_robin(ctx.handle, m, float(mbf), float(smooth_value)))

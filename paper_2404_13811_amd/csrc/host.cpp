@@ -119,6 +119,9 @@ struct mrcm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int graph_steps = 0;  // smoothing steps the captured graph holds
+  // phase timing: events recorded around the phases of each call (the
+  // ms_* fields of mrcm_stats); off, the calls enqueue kernels only
+  bool timing = true;
   double* p_tune = nullptr;
   double* gflux_tune = nullptr;
   double ms_autotune = 0.0;
@@ -1008,36 +1011,36 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
               c->lds32_part > 150 * 1024))
     return fail(c, MRCM_EINVAL, "FP32 refinement is available for 2-D boxes with lines of <= 32 cells");
   hipStream_t s = c->stream;
-  HIPCHK(c, hipEventRecord(c->ev[0], s));
+  if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
   HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
   if (r32) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
-    HIPCHK(c, hipEventRecord(c->ev[8], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_local32_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
                                c->bcv, c->beta_mbf, c->fac32, c->facp32, c->Pk, c->tr_u, c->tr_phi,
                                c->tr_beta, c->pbar, c->ubar, c->pibar, c->tol, c->max_refine,
                                c->d_iters, c->d_resid, c->flags,
                                std::max(c->lds32_basis, c->lds32_part), s));
-    HIPCHK(c, hipEventRecord(c->ev[9], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
   } else if (c->wave) {
-    HIPCHK(c, hipEventRecord(c->ev[8], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_local_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
                              c->bcv, c->beta_mbf, c->fac, c->tco, c->facp, c->tcp, c->Pk, c->tr_u,
                              c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->fact,
                              c->flags, std::max(c->lds_basis, c->lds_part), s));
-    HIPCHK(c, hipEventRecord(c->ev[9], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
   } else {
-    HIPCHK(c, hipEventRecord(c->ev[8], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
                            c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s));
-    HIPCHK(c, hipEventRecord(c->ev[9], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
     HIPCHK(c, launch_particular(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
                                 c->facp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
   }
-  HIPCHK(c, hipEventRecord(c->ev[1], s));
-  c->timed_basis = true;
+  if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], s));
+  c->timed_basis = c->timing;
   c->n_local_solves = c->nX + c->geo.nsub;
   c->state = 1;
   return MRCM_OK;
@@ -1048,7 +1051,7 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   ++c->epoch;
   if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
   hipStream_t s = c->stream;
-  HIPCHK(c, hipEventRecord(c->ev[2], s));
+  if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], s));
   // the reduction reads the row band only; the banded LU also uses the rest
   const long long band = (long long)(c->kl + c->ku + 1) * c->nX;
   HIPCHK(c, launch_fill(c->AB, 0.0, c->use_bcr ? band : (long long)c->ldab * c->nX, s));
@@ -1056,7 +1059,7 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
                            c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab,
                            c->kl, c->ku, c->rhs, s));
   if (c->nX > 0) {
-    HIPCHK(c, hipEventRecord(c->ev[6], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[6], s));
     if (c->use_bcr) {
       mrcm_status st = bcr_solve(c, s);
       if (st) return st;
@@ -1068,12 +1071,12 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
                     c->kl, c->ku);
       HIPCHK(c, e);
     }
-    HIPCHK(c, hipEventRecord(c->ev[7], s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[7], s));
   }
   HIPCHK(c, launch_combine(c->geo, c->d_seed_off, c->X, c->Pk, c->tr_u, c->pbar, c->ubar, c->p,
                            c->gflux, s));
-  HIPCHK(c, hipEventRecord(c->ev[3], s));
-  c->timed_iface = true;
+  if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], s));
+  c->timed_iface = c->timing;
   c->state = 2;
   c->n_ck = 0;
   c->n_phase = 0;
@@ -1197,6 +1200,12 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* c, int use_graph, int threads_per_box) 
   return MRCM_OK;
 }
 
+mrcm_status mrcm_set_timing(mrcm_ctx* c, int on) {
+  if (!c) return MRCM_EINVAL;
+  c->timing = on != 0;
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* c, int on, int max_groups) {
   if (!c) return MRCM_EINVAL;
   if (max_groups < 0) return fail(c, MRCM_EINVAL, "max_groups < 0");
@@ -1245,7 +1254,7 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   }
   const int nphase = nsteps << c->d;
   const bool try_grid = c->persist && c->wave && c->prec != MRCM_FP32_REFINE && !c->ckpt;
-  HIPCHK(c, hipEventRecord(c->ev[4], s));
+  if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], s));
   c->n_smooth_launches = nphase;
   c->n_smooth_phases = nphase;
   c->persist_used = false;
@@ -1274,8 +1283,8 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
     if (st) return st;
   }
   c->n_phase += nphase;
-  HIPCHK(c, hipEventRecord(c->ev[5], s));
-  c->timed_smooth = true;
+  if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], s));
+  c->timed_smooth = c->timing;
   c->n_local_solves += (nphase >> c->d) * c->geo.nsub;
   return MRCM_OK;
 }
