@@ -86,6 +86,7 @@ struct mrcm_ctx {
   double *p = nullptr, *gflux = nullptr, *partial = nullptr;
   int* flags = nullptr;
   int* flags_host = nullptr;  // pinned copy target of the error flags
+  bool flags_zero = false;    // flags cleared by the last check, no work since
 
   // block cyclic reduction of the interface system over the layers of
   // subdomains along the last axis (bcr.hip)
@@ -820,10 +821,13 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
 
 mrcm_status check_flags(mrcm_ctx* c) {
   if (c->checked_epoch == c->epoch) return MRCM_OK;
-  // one wait: the copy into pinned memory is ordered after the work
+  // one wait: the copy into pinned memory is ordered after the work, and
+  // the flags are cleared for the next solve in the same round
   HIPCHK(c, hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const int fl = *c->flags_host;
+  c->flags_zero = true;
   if (!fl) c->checked_epoch = c->epoch;
   if (fl & kFlagBadK) return fail(c, MRCM_EINVAL, "permeability must be finite and positive");
   if (fl & kFlagNotPD) return fail(c, MRCM_ENOTPD, "local factorisation met a non-positive pivot");
@@ -1012,8 +1016,10 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     return fail(c, MRCM_EINVAL, "FP32 refinement is available for 2-D boxes with lines of <= 32 cells");
   hipStream_t s = c->stream;
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
-  HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
-  HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
+  if (!c->flags_zero) HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
+  c->flags_zero = false;
+  // K = exp(log K): inside the local kernel on the FP64 wave path
+  if (r32 || !c->wave) HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
   if (r32) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
@@ -1026,7 +1032,7 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
   } else if (c->wave) {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
-    HIPCHK(c, launch_local_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
+    HIPCHK(c, launch_local_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->logk, c->K, c->f,
                              c->bcv, c->beta_mbf, c->fac, c->tco, c->facp, c->tcp, c->Pk, c->tr_u,
                              c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->fact,
                              c->flags, std::max(c->lds_basis, c->lds_part), s));
@@ -1049,6 +1055,7 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
 mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   if (!c) return MRCM_EINVAL;
   ++c->epoch;
+  c->flags_zero = false;  // new flag-setting work may follow
   if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
   hipStream_t s = c->stream;
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], s));
@@ -1217,6 +1224,7 @@ mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* c, int on, int max_groups) {
 mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   if (!c) return MRCM_EINVAL;
   ++c->epoch;
+  c->flags_zero = false;  // new flag-setting work may follow
   if (c->state < 2) return fail(c, MRCM_ESTATE, "interface not solved");
   if (nsteps < 0) return fail(c, MRCM_EINVAL, "nsteps < 0");
   if (nsteps > 0 && c->beta_sm != c->beta_mbf && !c->facs) {
@@ -1332,6 +1340,7 @@ mrcm_status mrcm_set_checkpointing(mrcm_ctx* c, int on) {
 mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux, double* dJdlogK) {
   if (!c) return MRCM_EINVAL;
   ++c->epoch;
+  c->flags_zero = false;  // new flag-setting work may follow
   if (!dJdlogK) return fail(c, MRCM_EINVAL, "output is NULL");
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution to differentiate");
   if (c->prec != MRCM_FP64 || !c->wave || c->d != 2)

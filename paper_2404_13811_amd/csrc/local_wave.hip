@@ -90,7 +90,7 @@ __device__ __forceinline__ void store_block(int nb, double* Wj, const double w[H
 // inverses on one wave is about half as long as a one-ended elimination,
 // and fac / fact are exactly the factors of the two-ended smoothing sweep.
 __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
-                                          const double* __restrict__ K, double beta,
+                                          const double* __restrict__ logK, double beta,
                                           double* __restrict__ fac, double* __restrict__ fact,
                                           double* __restrict__ tcoup,
                                           double* __restrict__ Pk, double* __restrict__ tr_u,
@@ -103,8 +103,9 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
   double* Z1 = s.Z + nrhs * NBW;
   double* Sm = Z1 + nrhs * NBW;
   const int nc = B.ncell;
-  // set-up by both waves: box arrays, seed right-hand sides, couplings
-  load_box<128>(g, B, K, beta, s);
+  // set-up by both waves: box arrays (K from log K), seed right-hand
+  // sides, couplings
+  load_box<128, true>(g, B, logK, beta, s);
   for (int e = tid; e < nrhs * nc; e += 128) s.X[e] = 0.0;
   __syncthreads();
   // T^R times the seed on the cells of its side, all seeds at once
@@ -224,7 +225,12 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
 }
 
 // Step 4: particular problem on Omega_i with zero Robin data on Gamma_i.
-__device__ __forceinline__ void particular_box(const Geo& g, const Box& B, const double* __restrict__ K,
+// The box is Omega_i itself: it also writes K = exp(log K) of its cells
+// (the subdomains cover the grid once) and flags a K that is not finite
+// and positive.
+__device__ __forceinline__ void particular_box(const Geo& g, const Box& B,
+                                               const double* __restrict__ logK,
+                                               double* __restrict__ K,
                                                const double* __restrict__ f,
                                                const double* __restrict__ bcv, double beta,
                                                double* __restrict__ fac, double* __restrict__ tcoup,
@@ -232,7 +238,13 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B, const
                                                double* __restrict__ pibar, double* dsm, WaveSmem& sm) {
   const int L = lane_id();
   BoxLds s = carve(dsm, B, 1);
-  load_box(g, B, K, beta, s);
+  load_box<64, true>(g, B, logK, beta, s);
+  for (int t = L; t < B.ncell; t += 64) {
+    const int x = B.lo[0] + t % s.m0, y = B.lo[1] + t / s.m0;
+    const double k = kat(s, B, x, y);
+    if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
+    K[x + g.n[0] * y] = k;
+  }
   physical_rhs(g, B, s, f, bcv, s.X);
   wsync();
   double* Wg = fac + B.fac;
@@ -272,7 +284,8 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B, const
 __global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ obox,
                                                  const Box* __restrict__ pbox, int nbox,
                                                  const Seed* __restrict__ seeds,
-                                                 const double* __restrict__ K,
+                                                 const double* __restrict__ logK,
+                                                 double* __restrict__ K,
                                                  const double* __restrict__ f,
                                                  const double* __restrict__ bcv, double beta,
                                                  double* __restrict__ fac,
@@ -294,10 +307,10 @@ __global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ 
   const int b = blockIdx.x;
   if (b < nbox) {
     const Box B = obox[b];
-    basis_box(g, B, seeds, K, beta, fac, fact, tcoup, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+    basis_box(g, B, seeds, logK, beta, fac, fact, tcoup, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
   } else if (wv == 0) {
     const Box B = pbox[b - nbox];
-    particular_box(g, B, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm[0]);
+    particular_box(g, B, logK, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm[0]);
   }
   __syncthreads();
   if (threadIdx.x == 0 && (sm[0].flag | sm[1].flag)) atomicOr(flags, sm[0].flag | sm[1].flag);
@@ -421,7 +434,8 @@ size_t wave_lds_bytes(int m0, int m1, int nrhs) {
 size_t wave_smooth_lds_bytes(int m0, int m1) { return sizeof(double) * smooth_lds_doubles(m0, m1); }
 
 hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
-                          const Seed* seeds, const double* K, const double* f, const double* bcv,
+                          const Seed* seeds, const double* logK, double* K, const double* f,
+                          const double* bcv,
                           double beta, double* fac, double* tcoup, double* facp, double* tcp,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
                           double* ubar, double* pibar, double* fact, int* flags, size_t lds,
@@ -430,7 +444,7 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
   hipError_t e = set_lds(k_local_w, lds);
   if (e != hipSuccess) return e;
   if (!fact) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(128), lds, s, g, obox, pbox, nbox, seeds, K, f,
+  hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(128), lds, s, g, obox, pbox, nbox, seeds, logK, K, f,
                      bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar,
                      fact, flags);
   return hipGetLastError();

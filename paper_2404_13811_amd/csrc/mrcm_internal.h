@@ -114,10 +114,13 @@ size_t wave_basis_lds_bytes(int m0, int m1, int nrhs);
 size_t wave_smooth_lds_bytes(int m0, int m1);
 // Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox) in one
 // launch of 2 nbox workgroups; lds = the larger of the two boxes' needs.
-// fact (may be null): factors of the twisted smoothing sweep, same layout
-// as fac.
+// The kernel reads log K and writes K = exp(log K) (each subdomain its own
+// cells; kFlagBadK where K is not finite and positive).  fac: forward
+// inverses below the meeting block of every oversampled box; fact (not
+// null): backward inverses above it and the meeting block, same layout.
 hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
-                          const Seed* seeds, const double* K, const double* f, const double* bcv,
+                          const Seed* seeds, const double* logK, double* K, const double* f,
+                          const double* bcv,
                           double beta, double* fac, double* tcoup, double* facp, double* tcp,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
                           double* ubar, double* pibar, double* fact, int* flags, size_t lds,

@@ -198,14 +198,20 @@ template <int NT = 64>
 __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta, BoxLds& s);
 
 // Load the K tile and the matrix coefficients of the box into LDS.
-template <int NT = 64>
+// With LOG, K points to log K and the tile is exponentiated in LDS (cells
+// outside the domain read log K = 0, i.e. K = 1, as without).
+template <int NT = 64, bool LOG = false>
 __device__ __forceinline__ void load_box(const Geo& g, const Box& B, const double* K, double beta, BoxLds& s) {
   const int W2 = s.m0 + 2, H2 = s.m1 + 2;
   gather<1024 / NT, NT>(s.Kt, W2 * H2, [&](int e, double& fill) -> const double* {
     const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
-    fill = 1.0;
+    fill = LOG ? 0.0 : 1.0;
     return (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K + x + g.n[0] * y : nullptr;
   });
+  if (LOG) {
+    bsync<NT>();
+    for (int e = threadIdx.x % NT; e < W2 * H2; e += NT) s.Kt[e] = exp(s.Kt[e]);
+  }
   bsync<NT>();
   coef_box<NT>(g, B, beta, s);
 }
