@@ -32,16 +32,19 @@ namespace {
 // with P = A[K][K],
 //   A[K][j] <- P^{-1} A[K][j],   A[i][K] <- -A[i][K] P^{-1},
 //   A[K][K] <- P^{-1},           A[i][j] <- A[i][j] - A[i][K] P^{-1} A[K][j],
-// which equals four scalar pivot steps.  The pivot rows of a step are one
-// tile row (16 threads of one wave) and the pivot columns half a tile
-// column, so few LDS store instructions publish them.  One step:
-//   1. the owners of rows K and of columns K publish them (barrier);
+// which equals four scalar pivot steps.  Thread 16 tr + tc holds tile
+// (tr, tc), so a tile row is one row of 16 lanes of a wave.  The pivot rows
+// of a step are one tile row and the pivot columns half a tile column.  One
+// step:
+//   1. the owners of rows K publish them to LDS (barrier);
 //   2. threads t < n factor the 4 x 4 block P (closed form, no exchange)
 //      and form column t of R = P^{-1} A~[K][:], where A~ has unit vectors
 //      in the columns K (barrier);
 //   3. every thread applies the rank-4 update A[i][j] <- A[i][j] -
 //      A[i][K] R[:, j] to its tile (zero base in the columns K) and the
-//      owners of rows K take R.
+//      owners of rows K take R.  A[i][K] of a tile row is held by one lane
+//      of the same 16-lane row (the owner of the pivot columns), and row
+//      broadcasts hand it to the other 15: the columns never go through LDS.
 // The LDS buffers alternate between steps, so two barriers per four
 // pivots.  R is stored in 16-byte pieces interleaved over the tile columns
 // so that the update reads are free of bank conflicts.  Two waves per SIMD
@@ -49,20 +52,52 @@ namespace {
 constexpr int TR = 4, TC = 8, PB = 4;  // tile rows / columns; pivots per step
 constexpr int kInvThreads = 512;
 
+// cv[i][m] = w[i][K2 + m] of lane KT of this lane's row of 16 lanes
+template <int KT, int K2>
+__device__ __forceinline__ void bcast_cols(const double w[TR][TC], double cv[TR][PB]) {
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int m = 0; m < PB; ++m) {
+      const long long u = __builtin_bit_cast(long long, w[i][K2 + m]);
+      const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffLL), 0x150 + KT, 0xF, 0xF, false);
+      const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x150 + KT, 0xF, 0xF, false);
+      cv[i][m] = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+    }
+}
+
+template <int K2>
+__device__ __forceinline__ void bcast_cols(int kt, const double w[TR][TC], double cv[TR][PB]) {
+  switch (kt) {
+#define MRCM_BC(N) \
+  case N:          \
+    bcast_cols<N, K2>(w, cv); \
+    break;
+    MRCM_BC(0) MRCM_BC(1) MRCM_BC(2) MRCM_BC(3) MRCM_BC(4) MRCM_BC(5) MRCM_BC(6) MRCM_BC(7)
+    MRCM_BC(8) MRCM_BC(9) MRCM_BC(10) MRCM_BC(11) MRCM_BC(12) MRCM_BC(13) MRCM_BC(14) MRCM_BC(15)
+#undef MRCM_BC
+    default:
+      break;
+  }
+}
+
 __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ pool,
                                                          const long long* __restrict__ offs,
                                                          const int* __restrict__ npiv, int bp,
                                                          int ld, int* flags) {
   __shared__ __align__(16) double rpan[2][PB * kBcrInvMax];  // [m][col] = A[k + m][col]
-  __shared__ __align__(16) double cpan[2][kBcrInvMax * PB];  // [row][m] = A[row][k + m]
   __shared__ __align__(16) double rpp[2][PB * kBcrInvMax];   // R, interleaved pieces
   double* A = pool + offs[blockIdx.x];
   const int ntr = bp / TR, ntc = bp / TC;  // tiles per column / per row
   const int t = threadIdx.x;
-  const bool act = t < ntr * ntc;
-  const int tr = act ? t / ntc : -1, tc = act ? t - (t / ntc) * ntc : -1;
+  const int tr = t >> 4, tc = t & 15;
+  const bool act = tr < ntr && tc < ntc;
   const int r0 = tr * TR, c0 = tc * TC;
   double w[TR][TC];
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int j = 0; j < TC; ++j) w[i][j] = 0.0;
   if (act) {
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
@@ -87,7 +122,6 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
       if (k >= kend) break;
       const bool own_r = tr == k / TR;
       double* rp = rpan[k2 / PB];
-      double* cp = cpan[k2 / PB];
       double* rq = rpp[k2 / PB];
       if (own_r) {
 #pragma unroll
@@ -95,14 +129,6 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
           double2* d = reinterpret_cast<double2*>(rp + m * kBcrInvMax + c0);
 #pragma unroll
           for (int jj = 0; jj < TC / 2; ++jj) d[jj] = make_double2(w[m][2 * jj], w[m][2 * jj + 1]);
-        }
-      }
-      if (own_c) {
-#pragma unroll
-        for (int i = 0; i < TR; ++i) {
-          double2* d = reinterpret_cast<double2*>(cp + (r0 + i) * PB);
-          d[0] = make_double2(w[i][k2], w[i][k2 + 1]);
-          d[1] = make_double2(w[i][k2 + 2], w[i][k2 + 3]);
         }
       }
       __syncthreads();
@@ -128,8 +154,11 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
         for (int m = 0; m < PB; ++m) rq[((m * (TC / 2) + jj) * ntc + tq) * 2 + e] = v[m];
       }
       __syncthreads();
-      if (act) {
+      {
+        // every lane takes part in the row broadcasts
         double rv[PB][TC], cv[TR][PB];
+        if (k2 == 0) bcast_cols<0>(kt, w, cv);
+        else bcast_cols<PB>(kt, w, cv);
         const double2* q2 = reinterpret_cast<const double2*>(rq);
 #pragma unroll
         for (int m = 0; m < PB; ++m)
@@ -139,15 +168,6 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
             rv[m][2 * jj] = x.x;
             rv[m][2 * jj + 1] = x.y;
           }
-#pragma unroll
-        for (int i = 0; i < TR; ++i) {
-          const double2* s2 = reinterpret_cast<const double2*>(cp + (r0 + i) * PB);
-          const double2 a = s2[0], b = s2[1];
-          cv[i][0] = a.x;
-          cv[i][1] = a.y;
-          cv[i][2] = b.x;
-          cv[i][3] = b.y;
-        }
         if (own_c) {
 #pragma unroll
           for (int i = 0; i < TR; ++i)
