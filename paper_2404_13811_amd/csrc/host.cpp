@@ -625,7 +625,8 @@ mrcm_status make_plan(mrcm_ctx* c) {
       c->lds_adj_part = std::max(c->lds_adj_part, adj_part_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1]));
     }
   }
-  if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024) c->wave = false;
+  if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024 || 2 * c->lds_part + 16 > 150 * 1024)
+    c->wave = false;
 
   // interfaces and their test functions
   c->ifc.clear();
@@ -1035,7 +1036,7 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     HIPCHK(c, launch_local_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->logk, c->K, c->f,
                              c->bcv, c->beta_mbf, c->fac, c->tco, c->facp, c->tcp, c->Pk, c->tr_u,
                              c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->fact,
-                             c->flags, std::max(c->lds_basis, c->lds_part), s));
+                             c->flags, std::max(c->lds_basis, 2 * c->lds_part + 16), c->lds_part, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
   } else {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));

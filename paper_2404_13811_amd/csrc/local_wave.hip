@@ -277,9 +277,9 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B,
 
 // Steps 1-2 and 4 in one launch of two-wave workgroups.  Workgroups
 // [0, nbox) handle the oversampled boxes (factors of both ends, seeds,
-// traces); in workgroups [nbox, 2 nbox) wave 0 solves the particular
-// problem of a subdomain (one-ended factorisation of Omega_i) and wave 1
-// has nothing to do.  The two sets share nothing, so their waves run side
+// traces); in the workgroups after them each of the first npart waves
+// solves the particular problem of one subdomain (one-ended factorisation
+// of Omega_i), in its own part_ld doubles of LDS.  The two sets share nothing, so their waves run side
 // by side instead of one launch after the other.
 __global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ obox,
                                                  const Box* __restrict__ pbox, int nbox,
@@ -299,7 +299,8 @@ __global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ 
                                                  double* __restrict__ pbar,
                                                  double* __restrict__ ubar,
                                                  double* __restrict__ pibar,
-                                                 double* __restrict__ fact, int* flags) {
+                                                 double* __restrict__ fact, int npart,
+                                                 int part_ld, int* flags) {
   extern __shared__ __align__(16) double dsm[];
   __shared__ WaveSmem sm[2];
   const int L = lane_id(), wv = threadIdx.x >> 6;
@@ -308,9 +309,15 @@ __global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ 
   if (b < nbox) {
     const Box B = obox[b];
     basis_box(g, B, seeds, logK, beta, fac, fact, tcoup, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
-  } else if (wv == 0) {
-    const Box B = pbox[b - nbox];
-    particular_box(g, B, logK, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar, dsm, sm[0]);
+  } else {
+    // npart (1 or 2) subdomains per workgroup, one per wave, each in its own
+    // part_ld doubles of LDS
+    const int pi = npart * (b - nbox) + wv;
+    if (wv < npart && pi < nbox) {
+      const Box B = pbox[pi];
+      particular_box(g, B, logK, K, f, bcv, beta, facp, tcp, pbar, ubar, pibar,
+                     dsm + (size_t)wv * part_ld, sm[wv]);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0 && (sm[0].flag | sm[1].flag)) atomicOr(flags, sm[0].flag | sm[1].flag);
@@ -439,14 +446,25 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
                           double beta, double* fac, double* tcoup, double* facp, double* tcp,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
                           double* ubar, double* pibar, double* fact, int* flags, size_t lds,
-                          hipStream_t s) {
+                          size_t lds_part, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
   hipError_t e = set_lds(k_local_w, lds);
   if (e != hipSuccess) return e;
   if (!fact) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_local_w, dim3(2 * nbox), dim3(128), lds, s, g, obox, pbox, nbox, seeds, logK, K, f,
-                     bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar,
-                     fact, flags);
+  // Two subdomains per workgroup when the boxes outnumber the CUs several
+  // times over (the launch is throughput-bound and a second wave per
+  // workgroup costs no LDS); one when every box has a CU of its own and
+  // the basis workgroups' latency decides.
+  int dev = 0, ncu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int part_ld = (int)((lds_part / sizeof(double) + 1) / 2 * 2);  // 16-byte aligned waves
+  const int npart = (nbox > 2 * ncu && (size_t)2 * part_ld * sizeof(double) <= lds) ? 2 : 1;
+  if ((size_t)part_ld * sizeof(double) > lds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_local_w, dim3(nbox + (nbox + npart - 1) / npart), dim3(128), lds, s, g, obox,
+                     pbox, nbox, seeds, logK, K, f, bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u,
+                     tr_phi, tr_beta, pbar, ubar, pibar, fact, npart, part_ld, flags);
   return hipGetLastError();
 }
 

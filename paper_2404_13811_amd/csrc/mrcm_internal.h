@@ -112,8 +112,10 @@ size_t wave_lds_bytes(int m0, int m1, int nrhs);
 // LDS of a two-wave basis box of k_local_w
 size_t wave_basis_lds_bytes(int m0, int m1, int nrhs);
 size_t wave_smooth_lds_bytes(int m0, int m1);
-// Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox) in one
-// launch of 2 nbox workgroups; lds = the larger of the two boxes' needs.
+// Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox, one
+// or two per workgroup) in one launch; lds_part = LDS of one subdomain box,
+// lds >= the basis boxes' need and lds_part (two per workgroup when lds
+// holds two and there are more than twice as many boxes as CUs).
 // The kernel reads log K and writes K = exp(log K) (each subdomain its own
 // cells; kFlagBadK where K is not finite and positive).  fac: forward
 // inverses below the meeting block of every oversampled box; fact (not
@@ -124,7 +126,7 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
                           double beta, double* fac, double* tcoup, double* facp, double* tcp,
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
                           double* ubar, double* pibar, double* fact, int* flags, size_t lds,
-                          hipStream_t s);
+                          size_t lds_part, hipStream_t s);
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* fact, const double* tcoup, double* scr,
