@@ -218,14 +218,16 @@ def roofline(wl, form, phases, st):
     S = wl.sub
     if dom == "smooth":
         # algorithmic bytes of one colour phase, averaged over the colours:
-        # cached block inverses (once per solve) + block couplings, K and p
-        # with a one-cell halo, f; written: p on Omega_i and its Gamma fluxes
+        # cached block inverses (once per solve; FP64: symmetric, lower
+        # triangles) + block couplings, K and p with a one-cell halo, f;
+        # written: p on Omega_i and its Gamma fluxes
         total = 0.0
         for dims, _ in bx:
             nb, nblk = dims[0], int(np.prod(dims[1:]))
             ncb = nb * nblk
             halo = int(np.prod([d + 2 for d in dims]))
-            total += solves * nblk * nb * nb * word + ncb * 8 + 2 * halo * 8 + ncb * 8
+            blk = nb * nb if form == "fp32_refine" else nb * (nb + 1) // 2
+            total += solves * nblk * blk * word + ncb * 8 + 2 * halo * 8 + ncb * 8
             total += int(np.prod(S)) * 8 + 2 * wl.dim * int(np.prod(S[1:])) * 8
         # every box is solved once per sweep of 2^d colour phases; a launch
         # runs one phase, or all phases of the call in the persistent form

@@ -1443,6 +1443,13 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   out->n_local_solves = c->n_local_solves;
   out->bytes_factor = (double)(c->fac_n + c->facp_n) *
                       (c->prec == MRCM_FP32_REFINE ? sizeof(float) : sizeof(double));
+  if (c->wave && c->prec != MRCM_FP32_REFINE) {
+    // one symmetric inverse per block, stored as its lower triangle
+    double n = 0.0;
+    for (const Box& B : c->obox) n += (double)B.nblk * B.nb * (B.nb + 1) / 2;
+    for (const Box& B : c->pbox) n += (double)B.nblk * B.nb * (B.nb + 1) / 2;
+    out->bytes_factor = n * sizeof(double);
+  }
   if (c->plan_valid && c->prec == MRCM_FP32_REFINE) {
     int it = 0;
     unsigned long long rb = 0;

@@ -34,11 +34,27 @@ using namespace wave;
 
 
 
+// Store the nb x nb block held in the register layout w to Wj.
+__device__ __forceinline__ void store_block(int nb, double* Wj, const double w[HB]) {
+  // lower triangle, row-major (the layout block_src reads)
+  const int L = lane_id();
+  const int c = L & 31, h = L >> 5;
+#pragma unroll
+  for (int i = 0; i < HB; ++i) {
+    const int r = HB * h + i;
+    if (r < nb && c <= r) Wj[r * (r + 1) / 2 + c] = w[i];
+  }
+}
+
+// Block j of the cached FP64 factors of a box
+__device__ __forceinline__ double* fblock(double* Wg, int nb, int j) {
+  return Wg + (long long)j * block_elems<double>(nb);
+}
+
 // Factorisation fused with the forward sweep; inverses to Wg, couplings to Tg.
 __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double* Tg, int nrhs, const BoxLds& s,
                                WaveSmem& sm) {
   const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
   const int nb = B.nb;
   for (int e = L; e < B.ncell; e += 64) Tg[e] = s.Tn[e];
   double w[HB];
@@ -47,12 +63,7 @@ __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double*
   for (int j = 0; j < B.nblk; ++j) {
     wbuild(nb, j, s, w);
     wgj(nb, sm, w);
-    double* Wj = Wg + (long long)j * nb * nb;
-#pragma unroll
-    for (int i = 0; i < HB; ++i) {
-      const int r = HB * h + i;
-      if (r < nb && c < nb) Wj[r * nb + c] = w[i];
-    }
+    store_block(nb, fblock(Wg, nb, j), w);
     fwd_step(nb, B.ncell, j, nrhs, s, w);
   }
 }
@@ -65,17 +76,6 @@ __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double*
 // Schur complement of the meeting block (nb x nb, nb = m0, row-major).
 __host__ __device__ inline size_t basis_lds_doubles(int m0, int m1, int nrhs) {
   return box_lds_doubles(m0, m1, nrhs) + (size_t)nrhs * NBW + (size_t)m0 * m0 + 2;
-}
-
-// Store the nb x nb block held in the register layout w to Wj (row-major).
-__device__ __forceinline__ void store_block(int nb, double* Wj, const double w[HB]) {
-  const int L = lane_id();
-  const int c = L & 31, h = L >> 5;
-#pragma unroll
-  for (int i = 0; i < HB; ++i) {
-    const int r = HB * h + i;
-    if (r < nb && c < nb) Wj[r * nb + c] = w[i];
-  }
 }
 
 // Steps 1-2: factor the oversampled box, solve every seed, extract
@@ -138,7 +138,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
     for (int j = 0; j < m; ++j) {
       wbuild(nb, j, s, w);
       wgj(nb, sm[0], w);
-      store_block(nb, Wf + (long long)j * nb * nb, w);
+      store_block(nb, fblock(Wf, nb, j), w);
       fwd_step_d(nb, nc, j, j - 1, j > 0, nrhs, s, s.Z, w);
     }
     wbuild(nb, m, s, w);  // S_m
@@ -152,7 +152,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
     for (int j = nblk - 1; j > m; --j) {
       wbuild_t(nb, j, j < nblk - 1 ? j : -1, s, w);
       wgj(nb, sm[1], w);
-      store_block(nb, Wt + (long long)j * nb * nb, w);
+      store_block(nb, fblock(Wt, nb, j), w);
       fwd_step_d(nb, nc, j, j + 1, j < nblk - 1, nrhs, s, Z1, w);
     }
   }
@@ -172,7 +172,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
       w[i] = (m < nblk - 1 && r < nb && c < nb) ? fma(-tr * tc, w[i], smi) : smi;
     }
     wgj(nb, sm[1], w);
-    store_block(nb, Wt + (long long)m * nb * nb, w);
+    store_block(nb, fblock(Wt, nb, m), w);
     mid_step(nb, nc, m, nblk, nrhs, s, Z1, w);
   }
   __syncthreads();

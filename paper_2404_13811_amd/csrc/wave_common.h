@@ -81,11 +81,21 @@ __device__ __forceinline__ float half_sum_f(float v) {
   return __int_as_float(a[0]) + __int_as_float(a[1]);
 }
 
-// Cached block inverses of one box (nblk row-major nb x nb blocks) read
-// through a buffer resource: per lane the byte offsets of its 16 entries
-// (row 16h + i, column c) within a block, and the buffer size for the padding
-// entries, which the range check turns into zeros; the block index goes into
-// the scalar offset.
+// Cached block inverses of one box read through a buffer resource: per lane
+// the byte offsets of its 16 entries (row 16h + i, column c) within a block,
+// and the buffer size for the padding entries, which the range check turns
+// into zeros; the block index goes into the scalar offset.  FP64 blocks are
+// the inverses of symmetric Schur complements and are stored as their lower
+// triangle, row-major (entry (r, c), r >= c, at r (r + 1) / 2 + c; both
+// (r, c) and (c, r) read it): half the bytes of a full block.  FP32 blocks
+// are stored whole (nb x nb row-major).
+template <typename T>
+__host__ __device__ constexpr bool packed_blocks() { return sizeof(T) == 8; }
+
+template <typename T>
+__host__ __device__ inline int block_elems(int nb) {
+  return packed_blocks<T>() ? nb * (nb + 1) / 2 : nb * nb;
+}
 template <typename T>
 struct BlockSrc {
   __amdgpu_buffer_rsrc_t rs;
@@ -102,15 +112,18 @@ __device__ __forceinline__ BlockSrc<T> block_src(const T* Wg, int nb, int nblk) 
   const unsigned plo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)pa);
   const unsigned phi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(pa >> 32));
   T* pu = reinterpret_cast<T*>(((unsigned long long)phi << 32) | plo);
-  const int bytes = __builtin_amdgcn_readfirstlane(nblk * nb * nb * (int)sizeof(T));
+  const int bsz = block_elems<T>(nb);
+  const int bytes = __builtin_amdgcn_readfirstlane(nblk * bsz * (int)sizeof(T));
   b.rs = __builtin_amdgcn_make_buffer_rsrc(pu, (short)0, bytes, 0x00020000);
   const int c = threadIdx.x & 31, h = (threadIdx.x >> 5) & 1;
 #pragma unroll
   for (int i = 0; i < HB; ++i) {
     const int r = HB * h + i;
-    b.off[i] = (r < nb && c < nb) ? (r * nb + c) * (int)sizeof(T) : bytes;
+    const int hi = r > c ? r : c, lo = r > c ? c : r;
+    const int idx = packed_blocks<T>() ? hi * (hi + 1) / 2 + lo : r * nb + c;
+    b.off[i] = (r < nb && c < nb) ? idx * (int)sizeof(T) : bytes;
   }
-  b.bbytes = __builtin_amdgcn_readfirstlane(nb * nb * (int)sizeof(T));
+  b.bbytes = __builtin_amdgcn_readfirstlane(bsz * (int)sizeof(T));
   return b;
 }
 
