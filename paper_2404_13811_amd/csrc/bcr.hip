@@ -360,39 +360,11 @@ __global__ void __launch_bounds__(256) k_bcr_gemm_gemv(double* pool, double* __r
   }
 }
 
-// Scatter the interface system assembled in band form into the dense
-// layer blocks: row-band RB (row i, column c at RB[i*(kl+ku+1) + c-i+kl]),
-// right-hand side rhs; row_lvl/row_loc and col_lvl/col_loc map an equation
-// and an unknown to its layer and position; padding gets the identity.
-__global__ void k_bcr_scatter(const double* __restrict__ RB, const double* __restrict__ rhs, int n,
-                              int kl, int ku, const int* __restrict__ row_lvl,
-                              const int* __restrict__ row_loc, const int* __restrict__ col_lvl,
-                              const int* __restrict__ col_loc, int M, int bp,
-                              double* __restrict__ pool, double* __restrict__ vec) {
-  const int W = kl + ku + 1;
-  const long long bs = (long long)bp * bp;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)n * W) return;
-  const int i = (int)(e / W), t = (int)(e - (long long)i * W);
-  const int c = i - kl + t;
-  const int li = row_lvl[i], ri = row_loc[i];
-  if (t == 0) vec[(long long)li * bp + ri] = rhs[i];
-  if (c < 0 || c >= n) return;
-  const double v = RB[e];
-  if (v == 0.0) return;
-  const int lc = col_lvl[c], rc = col_loc[c];
-  int kind;
-  if (lc == li) kind = 0;
-  else if (lc == li - 1) kind = 1;
-  else kind = 2;  // lc == li + 1 (block tridiagonal by construction)
-  pool[(long long)(kind * M + li) * bs + (long long)ri * bp + rc] = v;
-}
-
 // Initial state of the reduction in one pass: the 3M blocks [D | L | U] of
 // the pool zero except the identity on the padded diagonal of every D
 // block (rows and columns past the layer's size), and the M right-hand-side
-// vectors zero.  The scatter then writes the nonzeros of the system, none
-// of which fall in the padding.
+// vectors zero.  The interface moments are then written straight into
+// these blocks, none of them in the padding.
 __global__ void k_bcr_init(double* __restrict__ pool, double* __restrict__ vec,
                            const int* __restrict__ lsize, int M, int bp) {
   const long long bs = (long long)bp * bp;
@@ -479,17 +451,6 @@ hipError_t launch_bcr_gemv(const double* pool, double* vec, const BcrGemv* tasks
   if (ntask <= 0) return hipSuccess;
   if (bp % 16) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_bcr_gemv, dim3(ntask, bp / 16), dim3(256), 0, s, pool, vec, tasks, bp);
-  return hipGetLastError();
-}
-
-hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl, int ku,
-                              const int* row_lvl, const int* row_loc, const int* col_lvl,
-                              const int* col_loc, int M, int bp, double* pool, double* vec,
-                              const int* lsize, hipStream_t s) {
-  const long long tot = (long long)n * (kl + ku + 1);
-  (void)lsize;
-  hipLaunchKernelGGL(k_bcr_scatter, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, RB, rhs, n,
-                     kl, ku, row_lvl, row_loc, col_lvl, col_loc, M, bp, pool, vec);
   return hipGetLastError();
 }
 

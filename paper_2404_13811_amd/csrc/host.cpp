@@ -809,9 +809,8 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
   const int M = c->bcr_M, bp = c->bcr_bp;
   const long long bs = (long long)bp * bp;
   (void)bs;
-  HIPCHK(c, launch_bcr_init(c->bpool, c->bvec, c->d_lsize, M, bp, s));
-  HIPCHK(c, launch_bcr_scatter(c->AB, c->rhs, c->nX, c->kl, c->ku, c->d_row_lvl, c->d_row_loc,
-                               c->d_col_lvl, c->d_col_loc, M, bp, c->bpool, c->bvec, c->d_lsize, s));
+  // blocks and right-hand sides are in place (set up and filled by
+  // mrcm_solve_interface before the moments)
   {
     mrcm_status st = run_bcr_ops(c, s);
     if (st) return st;
@@ -1060,12 +1059,28 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
   hipStream_t s = c->stream;
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], s));
-  // the reduction reads the row band only; the banded LU also uses the rest
-  const long long band = (long long)(c->kl + c->ku + 1) * c->nX;
-  HIPCHK(c, launch_fill(c->AB, 0.0, c->use_bcr ? band : (long long)c->ldab * c->nX, s));
-  HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis, c->d_seed_off,
-                           c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar, c->AB, c->ldab,
-                           c->kl, c->ku, c->rhs, s));
+  if (c->use_bcr && c->nX > 0) {
+    // moments straight into the reduction's layer blocks (set up first:
+    // zero blocks and vectors, identity on the padding)
+    HIPCHK(c, launch_bcr_init(c->bpool, c->bvec, c->d_lsize, c->bcr_M, c->bcr_bp, s));
+    BcrMap bm;
+    bm.row_lvl = c->d_row_lvl;
+    bm.row_loc = c->d_row_loc;
+    bm.col_lvl = c->d_col_lvl;
+    bm.col_loc = c->d_col_loc;
+    bm.M = c->bcr_M;
+    bm.bp = c->bcr_bp;
+    bm.pool = c->bpool;
+    bm.vec = c->bvec;
+    HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis,
+                             c->d_seed_off, c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar,
+                             c->AB, c->ldab, c->kl, c->ku, c->rhs, s, &bm));
+  } else {
+    HIPCHK(c, launch_fill(c->AB, 0.0, (long long)c->ldab * c->nX, s));
+    HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis,
+                             c->d_seed_off, c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar,
+                             c->AB, c->ldab, c->kl, c->ku, c->rhs, s));
+  }
   if (c->nX > 0) {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[6], s));
     if (c->use_bcr) {

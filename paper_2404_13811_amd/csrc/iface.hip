@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256) k_moments(Geo g, const Iface* __restrict_
                                                  const double* __restrict__ ubar,
                                                  const double* __restrict__ pibar,
                                                  double* __restrict__ AB, int ldab, int kl, int ku,
-                                                 double* __restrict__ rhs) {
+                                                 double* __restrict__ rhs, BcrMap bm) {
   const Iface F = ifc[blockIdx.x];
   const int rr = blockIdx.y;
   const int nrow = 2 * F.nbasis;
@@ -113,9 +113,20 @@ __global__ void __launch_bounds__(256) k_moments(Geo g, const Iface* __restrict_
     if (valid && lg == 0) {
       if (e < ni + nj) {
         if (g.neumann && row == 0) acc = (col == 0) ? 1.0 : 0.0;
-        AB[(long long)row * (kl + ku + 1) + (col - row + kl)] = acc;
+        if (bm.pool) {
+          // straight into the reduction's layer blocks: D, L or U of the
+          // equation's layer (block tridiagonal by construction)
+          const int li = bm.row_lvl[row], lc = bm.col_lvl[col];
+          const int kb = lc == li ? 0 : (lc == li - 1 ? 1 : 2);
+          bm.pool[(long long)(kb * bm.M + li) * bm.bp * bm.bp + (long long)bm.row_loc[row] * bm.bp +
+                  bm.col_loc[col]] = acc;
+        } else {
+          AB[(long long)row * (kl + ku + 1) + (col - row + kl)] = acc;
+        }
       } else {
-        rhs[row] = (g.neumann && row == 0) ? 0.0 : -acc;
+        const double v = (g.neumann && row == 0) ? 0.0 : -acc;
+        if (bm.pool) bm.vec[(long long)bm.row_lvl[row] * bm.bp + bm.row_loc[row]] = v;
+        else rhs[row] = v;
       }
     }
   }
@@ -672,10 +683,12 @@ __global__ void k_combine_u(Geo g, const int* __restrict__ seed_off, const doubl
 hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, int nrow_max, const Seed* basis,
                           const int* seed_off, const double* tr_u, const double* tr_phi,
                           const double* tr_beta, const double* ubar, const double* pibar,
-                          double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s) {
+                          double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s,
+                          const BcrMap* bm) {
   if (nifc <= 0 || nrow_max <= 0) return hipSuccess;
+  const BcrMap m = bm ? *bm : BcrMap{};
   hipLaunchKernelGGL(k_moments, dim3(nifc, nrow_max), dim3(256), 0, s, g, ifc, basis, seed_off, tr_u,
-                     tr_phi, tr_beta, ubar, pibar, AB, ldab, kl, ku, rhs);
+                     tr_phi, tr_beta, ubar, pibar, AB, ldab, kl, ku, rhs, m);
   return hipGetLastError();
 }
 

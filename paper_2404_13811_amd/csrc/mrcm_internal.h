@@ -165,10 +165,24 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, int nmem,
                              size_t lds, int nt, hipStream_t s);
 
 // interface system (iface.hip)
+// Where the moments go when the interface system is solved by block cyclic
+// reduction: equation row / unknown col to (layer, position), the layer
+// blocks [D | L | U] (M layers, bp x bp each) and right-hand sides.  pool
+// NULL: the row band AB and rhs.
+struct BcrMap {
+  const int* row_lvl = nullptr;
+  const int* row_loc = nullptr;
+  const int* col_lvl = nullptr;
+  const int* col_loc = nullptr;
+  int M = 0, bp = 0;
+  double* pool = nullptr;
+  double* vec = nullptr;
+};
 hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, int nrow_max, const Seed* basis,
                           const int* seed_off, const double* tr_u, const double* tr_phi,
                           const double* tr_beta, const double* ubar, const double* pibar,
-                          double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s);
+                          double* AB, int ldab, int kl, int ku, double* rhs, hipStream_t s,
+                          const BcrMap* bm = nullptr);
 hipError_t launch_bandlu_solve(double* AB, int ldab, int n, int kl, int ku, double* rhs,
                                double* x, int* ipiv, int* flags, hipStream_t s);
 hipError_t launch_combine(const Geo& g, const int* seed_off, const double* X, const double* Pk,
@@ -178,10 +192,6 @@ hipError_t launch_combine(const Geo& g, const int* seed_off, const double* X, co
 // block cyclic reduction of the interface system (bcr.hip)
 constexpr int kBcrMaxBlock = 256;  // layer block (two-by-two inverse above kBcrInvMax)
 constexpr int kBcrInvMax = 128;    // largest block one Gauss-Jordan workgroup inverts
-hipError_t launch_bcr_scatter(const double* RB, const double* rhs, int n, int kl, int ku,
-                              const int* row_lvl, const int* row_loc, const int* col_lvl,
-                              const int* col_loc, int M, int bp, double* pool, double* vec,
-                              const int* lsize, hipStream_t s);
 hipError_t launch_bcr_inv(double* pool, const long long* offs, const int* npiv, int nblk, int n,
                           int ld, int* flags, hipStream_t s);
 hipError_t launch_bcr_gemm(double* pool, const BcrGemm* tasks, int ntask, int n, int ld, hipStream_t s);
