@@ -1333,8 +1333,8 @@ mrcm_status mrcm_get_solution(mrcm_ctx* c, double* p_dev, double* flux_dev) {
   if (!c) return MRCM_EINVAL;
   if (!p_dev || !flux_dev) return fail(c, MRCM_EINVAL, "output is NULL");
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
-  HIPCHK(c, launch_pressure_out(c->geo, c->p, p_dev, c->partial, c->stream));
-  HIPCHK(c, launch_flux_out(c->geo, c->K, c->p, c->gflux, c->bcv, flux_dev, c->stream));
+  HIPCHK(c, launch_solution_out(c->geo, c->K, c->p, c->gflux, c->bcv, p_dev, flux_dev, c->partial,
+                                c->stream));
   return check_flags(c);
 }
 

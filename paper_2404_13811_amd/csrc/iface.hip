@@ -649,33 +649,33 @@ __global__ void __launch_bounds__(BT) k_bandlu_blocked(const double* __restrict_
 }
 
 // MRCM-O assembly: p = pbar + sum_k X_k P_k on each Omega_i and Gamma fluxes
-// u = ubar + sum_k X_k u_k (equations eq:addu, eq:addp, eq:uhatphat).
-__global__ void k_combine_p(Geo g, const int* __restrict__ seed_off, const double* __restrict__ X,
-                            const double* __restrict__ Pk, const double* __restrict__ pbar,
-                            double* __restrict__ p) {
-  const int ncell_o = g.S[0] * g.S[1] * (g.d == 3 ? g.S[2] : 1);
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)g.nsub * ncell_o) return;
-  const int sub = (int)(e / ncell_o), t = (int)(e % ncell_o);
-  double v = pbar[e];
-  for (int k = seed_off[sub]; k < seed_off[sub + 1]; ++k) v += X[k] * Pk[(long long)k * ncell_o + t];
-  int lo[3], hi[3];
-  omega_box(g, sub, lo, hi);
-  const int c0 = lo[0] + t % g.S[0];
-  const int c1 = lo[1] + (t / g.S[0]) % g.S[1];
-  const int c2 = (g.d == 3) ? lo[2] + t / (g.S[0] * g.S[1]) : 0;
-  p[c0 + g.n[0] * (c1 + g.n[1] * c2)] = v;
-}
-
-__global__ void k_combine_u(Geo g, const int* __restrict__ seed_off, const double* __restrict__ X,
-                            const double* __restrict__ tr_u, const double* __restrict__ ubar,
-                            double* __restrict__ gflux) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)g.nsub * g.gstride) return;
-  const int sub = (int)(e / g.gstride), t = (int)(e % g.gstride);
-  double v = ubar[e];
-  for (int k = seed_off[sub]; k < seed_off[sub + 1]; ++k) v += X[k] * tr_u[(long long)k * g.gstride + t];
-  gflux[e] = v;
+// u = ubar + sum_k X_k u_k (equations eq:addu, eq:addp, eq:uhatphat), one
+// launch: workgroups [0, nbp) the cells, the rest the Gamma faces.
+__global__ void k_combine(Geo g, const int* __restrict__ seed_off, const double* __restrict__ X,
+                          const double* __restrict__ Pk, const double* __restrict__ pbar,
+                          double* __restrict__ p, const double* __restrict__ tr_u,
+                          const double* __restrict__ ubar, double* __restrict__ gflux, int nbp) {
+  if ((int)blockIdx.x < nbp) {
+    const int ncell_o = g.S[0] * g.S[1] * (g.d == 3 ? g.S[2] : 1);
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)g.nsub * ncell_o) return;
+    const int sub = (int)(e / ncell_o), t = (int)(e % ncell_o);
+    double v = pbar[e];
+    for (int k = seed_off[sub]; k < seed_off[sub + 1]; ++k) v += X[k] * Pk[(long long)k * ncell_o + t];
+    int lo[3], hi[3];
+    omega_box(g, sub, lo, hi);
+    const int c0 = lo[0] + t % g.S[0];
+    const int c1 = lo[1] + (t / g.S[0]) % g.S[1];
+    const int c2 = (g.d == 3) ? lo[2] + t / (g.S[0] * g.S[1]) : 0;
+    p[c0 + g.n[0] * (c1 + g.n[1] * c2)] = v;
+  } else {
+    const long long e = (long long)(blockIdx.x - nbp) * blockDim.x + threadIdx.x;
+    if (e >= (long long)g.nsub * g.gstride) return;
+    const int sub = (int)(e / g.gstride), t = (int)(e % g.gstride);
+    double v = ubar[e];
+    for (int k = seed_off[sub]; k < seed_off[sub + 1]; ++k) v += X[k] * tr_u[(long long)k * g.gstride + t];
+    gflux[e] = v;
+  }
 }
 
 }  // namespace
@@ -727,11 +727,11 @@ hipError_t launch_combine(const Geo& g, const int* seed_off, const double* X, co
                           double* gflux, hipStream_t s) {
   const int ncell_o = g.S[0] * g.S[1] * (g.d == 3 ? g.S[2] : 1);
   const long long n1 = (long long)g.nsub * ncell_o;
-  hipLaunchKernelGGL(k_combine_p, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, g, seed_off,
-                     X, Pk, pbar, p);
   const long long n2 = (long long)g.nsub * g.gstride;
-  hipLaunchKernelGGL(k_combine_u, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, g, seed_off,
-                     X, tr_u, ubar, gflux);
+  const int nbp = (int)((n1 + 255) / 256), nbu = (int)((n2 + 255) / 256);
+  if (nbp + nbu == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)(nbp + nbu)), dim3(256), 0, s, g, seed_off, X, Pk, pbar,
+                     p, tr_u, ubar, gflux, nbp);
   return hipGetLastError();
 }
 

@@ -247,6 +247,11 @@ hipError_t launch_bcr_gather_t(const double* xv, const int* row_lvl, const int* 
 // outputs (outputs.hip)
 hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,
                                hipStream_t s);
+// pressure (shifted to zero mean for pure-Neumann problems) and face
+// velocities: two launches instead of three
+hipError_t launch_solution_out(const Geo& g, const double* K, const double* p, const double* gflux,
+                               const double* bcv, double* p_out, double* flux_out, double* partial,
+                               hipStream_t s);
 hipError_t launch_flux_out(const Geo& g, const double* K, const double* p, const double* gflux,
                            const double* bcv, double* out, hipStream_t s);
 

@@ -8,18 +8,23 @@ namespace {
 
 constexpr int RED = 256;
 
-// Deterministic two-pass mean: fixed partition into blocks, fixed tree.
-__global__ void k_partial_sum(const double* __restrict__ p, int n, double* __restrict__ partial) {
+// Deterministic two-pass mean: fixed partition into npart blocks, fixed tree.
+__device__ __forceinline__ void partial_sum(const double* __restrict__ p, int n, int b, int npart,
+                                            double* __restrict__ partial) {
   __shared__ double s[RED];
   double acc = 0.0;
-  for (int i = blockIdx.x * RED + threadIdx.x; i < n; i += gridDim.x * RED) acc += p[i];
+  for (int i = b * RED + threadIdx.x; i < n; i += npart * RED) acc += p[i];
   s[threadIdx.x] = acc;
   __syncthreads();
   for (int off = RED / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+  if (threadIdx.x == 0) partial[b] = s[0];
+}
+
+__global__ void k_partial_sum(const double* __restrict__ p, int n, double* __restrict__ partial) {
+  partial_sum(p, n, blockIdx.x, gridDim.x, partial);
 }
 
 __global__ void k_shift_copy(const double* __restrict__ p, int n, const double* __restrict__ partial,
@@ -36,10 +41,12 @@ __global__ void k_shift_copy(const double* __restrict__ p, int n, const double* 
   if (i < n) out[i] = p[i] - mean;
 }
 
-__global__ void k_flux_out(Geo g, const double* __restrict__ K, const double* __restrict__ p,
-                           const double* __restrict__ gflux, const double* __restrict__ bcv,
-                           double* __restrict__ out) {
-  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void flux_out(const Geo& g, const double* __restrict__ K,
+                                         const double* __restrict__ p,
+                                         const double* __restrict__ gflux,
+                                         const double* __restrict__ bcv, double* __restrict__ out,
+                                         int b) {
+  const int ci = b * blockDim.x + threadIdx.x;
   if (ci >= g.ncells) return;
   int c[3];
   c[0] = ci % g.n[0];
@@ -74,6 +81,22 @@ __global__ void k_flux_out(Geo g, const double* __restrict__ K, const double* __
     }
 }
 
+__global__ void k_flux_out(Geo g, const double* __restrict__ K, const double* __restrict__ p,
+                           const double* __restrict__ gflux, const double* __restrict__ bcv,
+                           double* __restrict__ out) {
+  flux_out(g, K, p, gflux, bcv, out, blockIdx.x);
+}
+
+// Flux output and the partial sums of the pressure mean in one launch:
+// workgroups [0, npart) the sums (npart = 0: no mean), the rest the fluxes.
+__global__ void k_flux_partial(Geo g, const double* __restrict__ K, const double* __restrict__ p,
+                               const double* __restrict__ gflux, const double* __restrict__ bcv,
+                               double* __restrict__ out, int npart, double* __restrict__ partial) {
+  const int b = blockIdx.x;
+  if (b < npart) partial_sum(p, g.ncells, b, npart, partial);
+  else flux_out(g, K, p, gflux, bcv, out, b - npart);
+}
+
 }  // namespace
 
 hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,
@@ -84,6 +107,18 @@ hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, doubl
     hipLaunchKernelGGL(k_partial_sum, dim3(npart), dim3(RED), 0, s, p, n, partial);
   hipLaunchKernelGGL(k_shift_copy, dim3((n + 255) / 256), dim3(256), 0, s, p, n, partial, npart,
                      g.neumann, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_solution_out(const Geo& g, const double* K, const double* p, const double* gflux,
+                               const double* bcv, double* p_out, double* flux_out, double* partial,
+                               hipStream_t s) {
+  const int n = g.ncells;
+  const int npart = g.neumann ? 64 : 0;
+  hipLaunchKernelGGL(k_flux_partial, dim3(npart + (n + 255) / 256), dim3(256), 0, s, g, K, p, gflux,
+                     bcv, flux_out, npart, partial);
+  hipLaunchKernelGGL(k_shift_copy, dim3((n + 255) / 256), dim3(256), 0, s, p, n, partial, 64,
+                     g.neumann, p_out);
   return hipGetLastError();
 }
 
