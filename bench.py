@@ -42,10 +42,10 @@ FLUX_TOL = 1e-6
 # hash to the value it was taken with; otherwise the traffic is reported null.
 TRAFFIC = {
     # kernel: (source files, sha256 prefix, fetch KiB, write KiB, workload)
-    "k_smooth_w": (("local_wave.hip",), "d4fa6496d717bb66", 4560.2, 158.0, "c2 overlap 4"),
-    "k_local_w": (("local_wave.hip",), "d4fa6496d717bb66", 18023.5, 43006.5, "c2 overlap 4"),
-    "k_smooth32": (("local_wave32.hip",), "edbadfaf6da51d6f", 2774.6, 162.0, "c2 overlap 4"),
-    "k_local32": (("local_wave32.hip",), "edbadfaf6da51d6f", 10233.7, 23795.0, "c2 overlap 4"),
+    "k_smooth_w": (("local_wave.hip",), "78f5ab5cf02d28dd", 3011.9, 158.0, "c2 overlap 4"),
+    "k_local_w": (("local_wave.hip",), "78f5ab5cf02d28dd", 10485.2, 26700.0, "c2 overlap 4"),
+    "k_smooth32": (("local_wave32.hip",), "6175ad10e30a35af", 2774.6, 162.0, "c2 overlap 4"),
+    "k_local32": (("local_wave32.hip",), "6175ad10e30a35af", 10283.9, 23795.0, "c2 overlap 4"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
