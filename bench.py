@@ -174,6 +174,63 @@ def time_adjoint(wl, reps):
             "gradient_over_forward": round(ta / tf, 3)}
 
 
+def time_batch(members, reps):
+    """The c5 batch: every member's forward solve (with checkpoints) and
+    gradient, one context and one stream per member, deferred errors (no
+    call waits for the device; one mrcm_wait per member ends the batch).
+    Device wall time per batch, inputs resident."""
+    import numpy as np
+    import torch
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    from inputs import make_workload
+    wls = [make_workload("c5", member=k) for k in range(members)]
+    nx, ny = wls[0].ncell
+    N = nx * ny
+    obs = torch.as_tensor(np.arange(0, N, N // 16)[:16], device="cuda")
+    fw = torch.zeros(N, 4, dtype=torch.float64, device="cuda")
+    fw[torch.arange(nx - 1, N, nx, device="cuda"), 1] = wls[0].h
+    fw = fw.reshape(-1)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in wls]
+    ctxs, outs = [], []
+    for wl, s in zip(wls, streams):
+        with torch.cuda.stream(s):
+            ctx = m.create(wl.dim, wl.ncell, wl.h)
+            api.configure(ctx, wl, "fp64")
+            m.set_checkpointing(ctx, True)
+            m.set_timing(ctx, False)
+            m.set_deferred_errors(ctx, True)
+            p = torch.empty(N, dtype=torch.float64, device="cuda")
+            fl = torch.empty(N * 4, dtype=torch.float64, device="cuda")
+            dJdp = torch.zeros(N, dtype=torch.float64, device="cuda")
+            grad = torch.empty(N, dtype=torch.float64, device="cuda")
+        ctxs.append(ctx)
+        outs.append((p, fl, dJdp, grad))
+    torch.cuda.synchronize()
+    t = 0.0
+    for r in range(reps + 1):
+        t0 = time.perf_counter()
+        for ctx, wl, s, (p, fl, dJdp, grad) in zip(ctxs, wls, streams, outs):
+            with torch.cuda.stream(s):
+                m.build_basis(ctx)
+                m.solve_interface(ctx)
+                m.smooth(ctx, wl.nsmooth)
+                m.get_solution(ctx, p, fl)
+                dJdp[obs] = p[obs] - 0.1
+                m.adjoint(ctx, dJdp, fw, grad)
+        for ctx in ctxs:
+            m.wait(ctx)
+        torch.cuda.synchronize()
+        if r:  # the first round builds the plans and allocates
+            t += (time.perf_counter() - t0) / reps
+    for ctx in ctxs:
+        m.destroy(ctx)
+    return {"members": members, "streams": members, "ms_per_batch": round(t * 1e3, 3),
+            "ms_per_member": round(t * 1e3 / members, 4),
+            "fine_cells_per_s_forward_and_gradient": members * N / t}
+
+
 def boxes(wl):
     """Oversampled boxes (cells per axis), seeds per box, subdomain cells."""
     import numpy as np
@@ -329,6 +386,8 @@ def main():
         return d
 
     adj = None if args.no_extra else time_adjoint(make_workload("c5"), max(3, args.steps // 4))
+    if adj is not None:
+        adj["batch"] = time_batch(32, 3)
     extra = {}
     if not args.no_extra and args.workload == "c2":
         for l in (0, 2, 4):

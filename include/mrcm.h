@@ -199,6 +199,26 @@ mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* ctx, int on, int max_groups)
  * Errors: MRCM_EINVAL (ctx NULL). */
 mrcm_status mrcm_set_timing(mrcm_ctx* ctx, int on);
 
+/* Deferred errors (default off), for callers that keep several contexts
+ * busy at once, each on its own stream (a batch of independent problems).
+ * Off, every call that produces results (mrcm_get_pressure, mrcm_get_flux,
+ * mrcm_get_solution, mrcm_adjoint) ends by reading the device error flags,
+ * which synchronises the context's stream.  On, those calls only enqueue
+ * their work and return MRCM_OK; the flags stay set on the device across
+ * calls (mrcm_build_basis no longer clears them) until mrcm_wait reads them.
+ * Results written since the last mrcm_wait are valid only if it returns
+ * MRCM_OK.  Switching off reads the flags as mrcm_wait does and returns its
+ * status.  Host-side argument and state errors are still returned at once.
+ * Errors: MRCM_EINVAL (ctx NULL). */
+mrcm_status mrcm_set_deferred_errors(mrcm_ctx* ctx, int on);
+
+/* Waits for the work enqueued on the context's stream, then reads and clears
+ * the device error flags: MRCM_OK, or the device-side error of any call made
+ * since the last read (MRCM_EINVAL for a non-finite or non-positive
+ * permeability, MRCM_ENOTPD, MRCM_ESINGULAR, MRCM_ENOCONV), with
+ * mrcm_last_error describing it.  Works in either error mode. */
+mrcm_status mrcm_wait(mrcm_ctx* ctx);
+
 /* Pressure per cell (N values); shifted to zero mean when no side carries a
  * pressure condition. */
 mrcm_status mrcm_get_pressure(mrcm_ctx* ctx, double* p_dev);

@@ -15,7 +15,7 @@ STATUS = {0: "MRCM_OK", 1: "MRCM_EINVAL", 2: "MRCM_ENOMEM", 3: "MRCM_EDEVICE", 4
 SYMBOLS = ("mrcm_create", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_bc",
            "mrcm_set_partition", "mrcm_set_interface_space", "mrcm_set_interface_solver",
            "mrcm_set_robin", "mrcm_set_smoothing", "mrcm_set_smoothing_persistent",
-           "mrcm_set_timing", "mrcm_set_checkpointing", "mrcm_adjoint",
+           "mrcm_set_timing", "mrcm_set_deferred_errors", "mrcm_wait", "mrcm_set_checkpointing", "mrcm_adjoint",
            "mrcm_set_precision", "mrcm_build_basis", "mrcm_solve_interface", "mrcm_smooth",
            "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_solution", "mrcm_get_coefficients", "mrcm_get_stats",
            "mrcm_last_error", "mrcm_destroy")
@@ -58,6 +58,8 @@ def load():
         "mrcm_set_smoothing": [vp, i, i],
         "mrcm_set_smoothing_persistent": [vp, i, i],
         "mrcm_set_timing": [vp, i],
+        "mrcm_set_deferred_errors": [vp, i],
+        "mrcm_wait": [vp],
         "mrcm_set_checkpointing": [vp, i],
         "mrcm_adjoint": [vp, vp, vp, vp],
         "mrcm_set_precision": [vp, i, d, i],

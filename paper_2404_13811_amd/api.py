@@ -106,6 +106,17 @@ def set_timing(ctx, on=True):
     _check(ctx, "mrcm_set_timing", _lib.load().mrcm_set_timing(ctx.handle, int(bool(on))))
 
 
+def set_deferred_errors(ctx, on=True):
+    """Calls stop synchronising to read device errors; ``wait`` reads them."""
+    _check(ctx, "mrcm_set_deferred_errors",
+           _lib.load().mrcm_set_deferred_errors(ctx.handle, int(bool(on))))
+
+
+def wait(ctx):
+    """Synchronise the context's stream and raise on any device-side error."""
+    _check(ctx, "mrcm_wait", _lib.load().mrcm_wait(ctx.handle))
+
+
 def set_robin(ctx, mode, mbf, smooth_value):
     m = BETA[mode] if isinstance(mode, str) else int(mode)
     _check(ctx, "mrcm_set_robin", _lib.load().mrcm_set_robin(ctx.handle, m, float(mbf), float(smooth_value)))

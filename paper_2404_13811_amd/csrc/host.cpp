@@ -123,6 +123,7 @@ struct mrcm_ctx {
   // phase timing: events recorded around the phases of each call (the
   // ms_* fields of mrcm_stats); off, the calls enqueue kernels only
   bool timing = true;
+  bool deferred = false;      // error flags read by mrcm_wait only
   double* p_tune = nullptr;
   double* gflux_tune = nullptr;
   double ms_autotune = 0.0;
@@ -819,8 +820,8 @@ mrcm_status bcr_solve(mrcm_ctx* c, hipStream_t s) {
   return MRCM_OK;
 }
 
-mrcm_status check_flags(mrcm_ctx* c) {
-  if (c->checked_epoch == c->epoch) return MRCM_OK;
+// Reads and clears the device error flags after the work enqueued so far.
+mrcm_status read_flags(mrcm_ctx* c) {
   // one wait: the copy into pinned memory is ordered after the work, and
   // the flags are cleared for the next solve in the same round
   HIPCHK(c, hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -834,6 +835,14 @@ mrcm_status check_flags(mrcm_ctx* c) {
   if (fl & kFlagSingular) return fail(c, MRCM_ESINGULAR, "interface system is singular");
   if (fl & kFlagNoConv) return fail(c, MRCM_ENOCONV, "iterative refinement did not converge");
   return MRCM_OK;
+}
+
+// End of a call that may report device-side errors: with deferred errors the
+// flags stay set on the device until mrcm_wait reads them.
+mrcm_status check_flags(mrcm_ctx* c) {
+  if (c->deferred) return MRCM_OK;
+  if (c->checked_epoch == c->epoch) return MRCM_OK;
+  return read_flags(c);
 }
 
 void drop_graph(mrcm_ctx* c) {
@@ -1016,7 +1025,9 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     return fail(c, MRCM_EINVAL, "FP32 refinement is available for 2-D boxes with lines of <= 32 cells");
   hipStream_t s = c->stream;
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
-  if (!c->flags_zero) HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
+  // a new solve clears the flags of the last one, unless they wait for
+  // mrcm_wait (deferred errors)
+  if (!c->flags_zero && !c->deferred) HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   c->flags_zero = false;
   // K = exp(log K): inside the local kernel on the FP64 wave path
   if (r32 || !c->wave) HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
@@ -1227,6 +1238,21 @@ mrcm_status mrcm_set_timing(mrcm_ctx* c, int on) {
   if (!c) return MRCM_EINVAL;
   c->timing = on != 0;
   return MRCM_OK;
+}
+
+mrcm_status mrcm_set_deferred_errors(mrcm_ctx* c, int on) {
+  if (!c) return MRCM_EINVAL;
+  if (c->deferred && !on) {
+    c->deferred = false;
+    return read_flags(c);  // what the deferred calls left
+  }
+  c->deferred = on != 0;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_wait(mrcm_ctx* c) {
+  if (!c) return MRCM_EINVAL;
+  return read_flags(c);
 }
 
 mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* c, int on, int max_groups) {
