@@ -143,3 +143,34 @@ def test_deferred_error_reported_by_wait_of_its_member():
     finally:
         for ctx in ctxs:
             m.destroy(ctx)
+
+
+def test_back_to_back_deferred_solves_equal_a_synchronous_solve():
+    """The benchmark's timed form (c2 at full size, overlap 4, linear spaces):
+    solves enqueued back to back with one mrcm_wait at the end give the
+    pressure and flux of a solve that waits for its own error read-back."""
+    import torch
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    wl = make_workload("c2")
+    ctx = m.create(wl.dim, wl.ncell, wl.h)
+    try:
+        api.configure(ctx, wl, "fp64")
+
+        def solve():
+            m.build_basis(ctx)
+            m.solve_interface(ctx)
+            m.smooth(ctx, wl.nsmooth)
+            return m.get_solution(ctx)
+
+        p0, f0 = solve()
+        p0, f0 = p0.cpu().numpy(), f0.cpu().numpy()
+        m.set_deferred_errors(ctx, True)
+        outs = [solve() for _ in range(3)]
+        m.wait(ctx)
+        m.set_deferred_errors(ctx, False)
+        for p, fl in outs:
+            assert np.array_equal(p.cpu().numpy(), p0)
+            assert np.array_equal(fl.cpu().numpy(), f0)
+    finally:
+        m.destroy(ctx)
