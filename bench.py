@@ -120,12 +120,16 @@ def time_solves(wl, precision, steps, warmup, tol, persistent=False):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     m.set_deferred_errors(ctx, False)
-    # one solve at a time: each ends with its own error read-back
-    t0 = time.perf_counter()
+    # one solve at a time: each ends with its own error read-back (a stream
+    # synchronisation), so each solve's wall time is its own
+    each = []
     for _ in range(steps):
+        t1 = time.perf_counter()
         step()
+        each.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
-    dt_sync = (time.perf_counter() - t0) / steps
+    dt_sync = sum(each) / steps
+    each.sort()
     m.set_timing(ctx, True)
     # phase and kernel times from the library's HIP events (recorded on the
     # context's stream) over separate solves: get_stats synchronises, so it
@@ -140,6 +144,8 @@ def time_solves(wl, precision, steps, warmup, tol, persistent=False):
             phases[k] += st[k] / nrep
     st = m.get_stats(ctx)
     st["ms_per_solve_synchronous"] = dt_sync * 1e3
+    st["ms_synchronous_median_min_max"] = [round(each[len(each) // 2] * 1e3, 4),
+                                           round(each[0] * 1e3, 4), round(each[-1] * 1e3, 4)]
     m.destroy(ctx)
     return dt, phases, st, p.cpu().numpy(), fl.cpu().numpy()
 
@@ -310,24 +316,44 @@ def roofline(wl, form, phases, st):
                 "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic(kern, wl),
                 "work_per_launch": "%.0f bytes" % per_launch,
                 "avg_launch_us": t_smooth_launch * 1e6}
-    # local kernel (basis boxes and particular problems in one launch):
-    # Gauss-Jordan inverse of every line block (nb^3 FMA; in FP64 the blocks
-    # below the meeting block are eliminated from one end and those above it
-    # from the other, still one inverse per block) and the forward + backward
-    # block products of every right-hand side (2 nb^2 FMA per block)
+    return local_roofline(wl, form, phases, st)
+
+
+def local_roofline(wl, form, phases, st):
+    """Roofline of the local kernel (basis boxes and particular problems in
+    one launch), against the FP64 (or FP32) peak: executed flops of the
+    block-dense elimination, and the band-factor flops of the method."""
+    import numpy as np
+    bx = boxes(wl)
+    solves = max(st["refine_max_iters"], 1) if form == "fp32_refine" else 1
+    t_basis = phases["ms_basis_kernel"] * 1e-3
+    S = wl.sub
+    # executed: Gauss-Jordan inverse of every line block (nb^3 FMA; in FP64
+    # the blocks below the meeting block are eliminated from one end and
+    # those above it from the other, still one inverse per block) and the
+    # forward + backward block products of every right-hand side (2 nb^2 FMA
+    # per block).  Band (algorithmic): n b^2 flops per factor, 4 n b per
+    # right-hand side solve, with n the cells of the box and b = nb its
+    # half-bandwidth in line order.
     flops = 0.0
+    band = 0.0
     for dims, nseed in bx:
         nb, nblk = dims[0], int(np.prod(dims[1:]))
         flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb * nseed
+        n = nb * nblk
+        band += n * nb * nb + solves * 4.0 * n * nb * nseed
     for _ in range(int(np.prod(wl.ncell)) // int(np.prod(S))):
         nb, nblk = S[0], int(np.prod(S[1:]))
         flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb
+        n = nb * nblk
+        band += n * nb * nb + solves * 4.0 * n * nb
     achieved = flops / t_basis
     peak = PEAK_FP32 if form == "fp32_refine" else PEAK_FP64
     kern = "k_local32" if form == "fp32_refine" else "k_local_w"
     return {"kernel": kern, "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic(kern, wl),
-            "work_per_launch": "%.0f flop" % flops, "avg_launch_us": t_basis * 1e6}
+            "work_per_launch": "%.0f flop" % flops, "avg_launch_us": t_basis * 1e6,
+            "band_flop_per_launch": band, "frac_band_algorithmic": band / t_basis / peak}
 
 
 def calibrate_copy():
@@ -391,7 +417,11 @@ def main():
     def form_summary(f, form):
         d = {"value": wl.ncells / f["dt"], "ms_per_step": f["dt"] * 1e3,
              "ms_per_solve_synchronous": round(f["stats"]["ms_per_solve_synchronous"], 4),
-             "phases_ms": {k: round(v, 4) for k, v in f["phases"].items()}}
+             "ms_synchronous_median_min_max": f["stats"]["ms_synchronous_median_min_max"],
+             "phases_ms": {k: round(v, 4) for k, v in f["phases"].items()},
+             "interface_share": round(f["phases"]["ms_interface"] / (f["dt"] * 1e3), 3),
+             "one_time_ms": {"smoothing_autotune": round(f["stats"]["ms_autotune"], 3)},
+             "roofline_local": local_roofline(wl, form, f["phases"], f["stats"])}
         if form == "fp32_refine":
             d["refine"] = {"tol": args.tol, "max_fp32_solves": f["stats"]["refine_max_iters"],
                            "max_backward_error": f["stats"]["refine_max_resid"]}
