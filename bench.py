@@ -400,7 +400,8 @@ def main():
         tcpu = float(np.median(times))
         cpu = {"value": wl.ncells / tcpu, "unit": "fine cells/s", "cores": 1, "kind": "oracle",
                "sample": "median of %d full oracle solves of the benchmark workload "
-                         "(%.2f s each, one thread)" % (len(times), tcpu)}
+                         "(%.2f s each, one thread; host has %s logical CPUs)"
+                         % (len(times), tcpu, os.cpu_count())}
         rp, rf = ref.pressure(), ref.flux().ravel()
         for f in forms.values():
             f["err"] = {"flux_rel_l2": float(np.linalg.norm(f["fl"] - rf) / np.linalg.norm(rf)),
