@@ -4,6 +4,7 @@ Arrays are torch tensors on the GPU, float64, contiguous; the library copies
 inputs and writes outputs on the current torch stream.
 """
 import ctypes
+import weakref
 
 import torch
 
@@ -207,16 +208,17 @@ class _SolveFn(torch.autograd.Function):
         except Exception:
             destroy(ctx)
             raise
+        # the context keeps the factors and checkpoints every backward call
+        # reads (the graph may be differentiated more than once); it is
+        # released with the graph, not at interpreter exit
         actx.mrcm = ctx
+        fin = weakref.finalize(ctx, _lib.load().mrcm_destroy, ctx.handle)
+        fin.atexit = False
         return p, fl
 
     @staticmethod
     def backward(actx, gp, gfl):
-        ctx = actx.mrcm
-        try:
-            g = adjoint(ctx, gp, gfl)
-        finally:
-            destroy(ctx)
+        g = adjoint(actx.mrcm, gp, gfl)
         return g, None, None
 
 

@@ -127,3 +127,26 @@ def test_autograd_function_uses_the_device_adjoint():
     J.backward()
     _, g = _gpu_grad(wl, 2)
     assert np.allclose(lk.grad.cpu().numpy(), g, rtol=1e-12, atol=1e-14 * np.abs(g).max())
+
+
+def test_gradcheck_on_a_16x16_grid():
+    """torch.autograd.gradcheck of the differentiable solve (device forward,
+    device adjoint) on a 16 x 16 grid: J = misfit at 16 cells + outflow."""
+    import torch
+    import paper_2404_13811_amd as m
+    wl = make_workload("c1", scale=4).with_(sub=(4, 4), overlap=2, beta_mode="alpha", beta_mbf=1.0,
+                                             beta_smooth=1.0)
+    assert tuple(wl.ncell) == (16, 16)
+    obs, d, fw = _weights(wl)
+    obs_t = torch.as_tensor(obs, device="cuda")
+    d_t = torch.as_tensor(d, device="cuda")
+    fw_t = torch.as_tensor(fw.ravel(), device="cuda")
+
+    def J(lk):
+        p, fl = m.solve_differentiable(lk, wl, nsmooth=2)
+        return 0.5 * ((p[obs_t] - d_t) ** 2).sum() + (fw_t * fl).sum()
+
+    lk = torch.tensor(wl.logk.ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+    # the adjoint sums the overlapping boxes' contributions with atomic adds,
+    # so two backward calls agree to rounding, not bit for bit
+    assert torch.autograd.gradcheck(J, (lk,), eps=1e-6, atol=1e-7, rtol=1e-5, nondet_tol=1e-12)
