@@ -27,6 +27,10 @@ CASES = {
     "neumann_wells_l2": lambda: make_workload("c2", scale=8, overlap=2),
     "neumann_wells_l0": lambda: make_workload("c2", scale=8, overlap=0),
     "beta_const": lambda: make_workload("c1", scale=2),
+    # Algorithm 1, Step 6: smoothing boxes factored with their own parameter
+    "alpha_distinct_small_l2": lambda: _small(space="const", overlap=2, beta_mbf=1e-2),
+    "alpha_distinct_large_l0": lambda: _small(space="linear", overlap=0, beta_mbf=1e2),
+    "alpha_distinct_wells_l3": lambda: make_workload("c2", scale=8, overlap=3).with_(beta_mbf=1e2),
 }
 
 

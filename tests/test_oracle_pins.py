@@ -60,8 +60,10 @@ def test_tpfa_equals_explicit_rt0_mixed_with_all_face_types():
     # Robin velocities agree too
     u_rob = box.robin_velocity(p_box, 0, lam)
     idx = [k for k, (c, a, s, nb) in enumerate(faces) if a == 0 and s == 0 and nb < 0]
-    assert np.allclose(u_rob, -u_mix[idx], rtol=1e-11, atol=1e-12) or \
-        np.allclose(u_rob, u_mix[idx], rtol=1e-11, atol=1e-12)
+    # both are the velocity along the outward normal of the box (Section 2:
+    # u.n on the boundary with n exterior), so they agree in sign as well
+    assert np.allclose(u_rob, u_mix[idx], rtol=1e-11, atol=1e-12)
+    assert np.abs(u_rob).max() > 1e-3
 
 
 def test_fine_solution_converges_second_order_to_analytic():
@@ -242,6 +244,66 @@ def test_smoothing_is_reentrant():
     a.smooth(1)
     b = mrcm.solve(wl, nsmooth=3)
     assert np.array_equal(a.pressure(), b.pressure())
+
+
+# ------------------------------------------- smoothing with its own Robin parameter
+# Algorithm 1, Step 6: when the smoothing Robin parameter differs from the one
+# of the basis functions, the oversampled boxes are factored again with it
+# (Section 3 item 3 allows any positive alpha); Step 7 then uses those boxes.
+@pytest.mark.parametrize("overlap", [0, 2, 3])
+@pytest.mark.parametrize("alpha_mbf", [1e-2, 1e2])
+def test_fine_solution_is_a_fixed_point_of_smoothing_with_distinct_alpha(overlap, alpha_mbf):
+    """Robin data taken from the fine solution reproduce it whatever the
+    smoothing parameter, provided the box solve and the data use the same
+    beta: a box built with the basis parameter but fed data formed with the
+    smoothing one (or the reverse) leaves the fine solution."""
+    wl = _small(overlap=overlap, beta_mbf=alpha_mbf, beta_smooth=1.0)
+    s = _mrcm_o(wl)
+    assert not s.same_beta
+    pf, ff = mrcm.fine(wl)
+    s.p = pf.copy()
+    for i in range(s.part.nsub):
+        lo, hi = s.part.omega(i)
+        for side in s.part.gamma_sides(i):
+            c = s.grid.flat(tpfa.box_coords(lo, hi)[tpfa.side_local(lo, hi, side)])
+            s.gflux[i][side] = ff[c, side]
+    s.smooth(2)
+    assert rel_l2(s.pressure(), pf) < 1e-12
+    assert rel_l2(s.flux(), ff) < 1e-12
+
+
+@pytest.mark.parametrize("overlap", [0, 2])
+@pytest.mark.parametrize("alpha_mbf", [1e-2, 1e2])
+def test_distinct_alpha_smoothing_uses_the_smoothing_parameter_only(overlap, alpha_mbf):
+    """From one and the same state, smoothing with alpha_sm = 1 gives the
+    same iterates whether the basis was built with alpha_mbf = alpha_sm or
+    not: Steps 6-7 depend on the smoothing parameter alone."""
+    a = _mrcm_o(_small(overlap=overlap, beta_mbf=alpha_mbf, beta_smooth=1.0))
+    b = _mrcm_o(_small(overlap=overlap, beta_mbf=1.0, beta_smooth=1.0))
+    assert rel_l2(a.pressure(), b.pressure()) > 1e-6   # MRCM-O differs with alpha_mbf
+    b.p = a.p.copy()
+    b.gflux = [{q: v.copy() for q, v in fl.items()} for fl in a.gflux]
+    a.smooth(2)
+    b.smooth(2)
+    assert rel_l2(a.pressure(), b.pressure()) < 1e-12
+    assert rel_l2(a.flux(), b.flux()) < 1e-12
+
+
+@pytest.mark.parametrize("alpha_mbf", [1e-2, 1e2])
+def test_smoothing_error_decreases_with_alpha_sm_one(alpha_mbf):
+    """Section 5's parameter study: basis functions with alpha_mbf far from
+    one, smoothing with alpha_sm = 1; each step brings the solution closer
+    to the fine one."""
+    wl = _small(overlap=2, beta_mbf=alpha_mbf, beta_smooth=1.0)
+    s = mrcm.solve(wl, nsmooth=0)
+    pf, ff = mrcm.fine(wl)
+    errs = []
+    for _ in range(5):
+        errs.append((rel_l2(s.pressure(), pf), rel_l2(s.flux(), ff)))
+        s.smooth(1)
+    for k in range(4):
+        assert errs[k + 1][0] < errs[k][0] and errs[k + 1][1] < errs[k][1]
+    assert errs[-1][1] < 0.2 * errs[0][1]
 
 
 # --------------------------------------------------------------- conservation
