@@ -139,7 +139,8 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
 #pragma unroll
           for (int j = 0; j < PB; ++j) P[m][j] = rp[m * kBcrInvMax + k + j];
         const PivBlock<double> q = piv_block(P);
-        bad |= !(q.d0 != 0.0 && q.da != 0.0 && q.s0 != 0.0 && q.ds != 0.0);
+        // a zero, infinite or NaN pivot: the elimination has broken down
+        bad |= !(piv_usable(q.d0) && piv_usable(q.da) && piv_usable(q.s0) && piv_usable(q.ds));
         const int ck = t - k;
         const bool pc = ck >= 0 && ck < PB;
         double r[PB], v[PB];

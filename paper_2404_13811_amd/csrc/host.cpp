@@ -1415,7 +1415,9 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
     HIPCHK(c, hipMalloc((void**)&c->d_seed_sub, nX * sizeof(int)));
     HIPCHK(c, hipMemcpy(c->d_seed_sub, ss.data(), nX * sizeof(int), hipMemcpyHostToDevice));
   }
-  HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
+  // the flags are not cleared here: they may still hold an error of the
+  // forward solve that no call has read yet (deferred errors, or no output
+  // call since it), which this call or mrcm_wait must report
   // outputs
   HIPCHK(c, launch_fill(c->a_gfb, 0.0, (long long)ng, s));
   HIPCHK(c, launch_adj_out(g, c->K, c->p, c->bcv, dJdp, dJdflux, c->a_mean, c->a_pb, c->a_gfb,

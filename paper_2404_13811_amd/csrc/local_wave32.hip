@@ -361,14 +361,17 @@ __device__ __forceinline__ int refine(const Geo& g, const Box& B, const BoxR& R,
         if (loc + nb < nc) { const double t = R.b.Tn[loc] * x[loc + nb]; ax -= t; aa += fabs(t); }
         const double r = bv - ax;
         const double den = aa + fabs(bv);
-        if (den > 0.0) om = fmax(om, fabs(r) / den);
+        // a non-finite residual or iterate never counts as converged (fmax
+        // would drop a NaN ratio)
+        if (!(r - r == 0.0 && den - den == 0.0)) om = INFINITY;
+        else if (den > 0.0) om = fmax(om, fabs(r) / den);
         R.Wf[(size_t)k * nc + loc] = (float)(R.sd[loc] * r);
       }
       omega = fmax(omega, wave_max(om));
     }
     wsync();
     if (it > 0 && omega <= tol) break;
-    if (it > max_refine) {
+    if (it > max_refine || !(omega <= 1e300)) {
       if (L == 0) sm.flag |= kFlagNoConv;
       break;
     }

@@ -21,6 +21,12 @@ __device__ __forceinline__ double pivot_rcp(double x) {
 }
 __device__ __forceinline__ float pivot_rcp(float x) { return 1.0f / x; }
 
+// a pivot the elimination can divide by: finite and non-zero
+template <typename T>
+__device__ __forceinline__ bool piv_usable(T x) {
+  return x == x && x != T(0) && x - x == T(0);
+}
+
 template <typename T>
 struct PivBlock {
   T ai[2][2], E[2][2], e[2][2], si[2][2];

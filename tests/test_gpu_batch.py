@@ -124,7 +124,9 @@ def test_deferred_error_reported_by_wait_of_its_member():
         first = [(p.cpu().numpy(), fl.cpu().numpy()) for p, fl, _ in first]
         with torch.cuda.stream(streams[1]):
             m.set_permeability(ctxs[1], bad)
-        second = batch(1)  # the member with the bad field skips the adjoint
+        # every member runs its adjoint too, the bad one included: the
+        # adjoint must leave the forward solve's unread error flag in place
+        second = batch(-1)
         m.wait(ctxs[0])
         with pytest.raises(m.MRCMError) as err:
             m.wait(ctxs[1])

@@ -44,3 +44,37 @@ def test_bad_permeability_reported_then_cleared(precision):
         assert np.array_equal(p0, p1) and np.array_equal(f0, f1)
     finally:
         m.destroy(ctx)
+
+
+def test_forward_error_reported_by_the_adjoint_call():
+    """A forward solve whose output was never read leaves its device error
+    flag set; the adjoint call that follows reads it (it must not clear
+    it), so the gradient of a solve with a bad permeability is refused."""
+    import torch
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    wl = make_workload("c5", scale=4)
+    good = torch.as_tensor(wl.logk.ravel(), dtype=torch.float64, device="cuda").contiguous()
+    bad = good.clone()
+    bad[11] = float("nan")
+    ctx = m.create(wl.dim, wl.ncell, wl.h)
+    try:
+        api.configure(ctx, wl, "fp64")
+        m.set_checkpointing(ctx, True)
+        m.set_permeability(ctx, bad)
+        m.build_basis(ctx)
+        m.solve_interface(ctx)
+        m.smooth(ctx, 2)
+        dJdp = torch.ones(wl.ncells, dtype=torch.float64, device="cuda")
+        with pytest.raises(m.MRCMError) as err:
+            m.adjoint(ctx, dJdp, None)
+        assert err.value.status == 1  # MRCM_EINVAL
+        # the error was read: a clean solve and gradient follow
+        m.set_permeability(ctx, good)
+        m.build_basis(ctx)
+        m.solve_interface(ctx)
+        m.smooth(ctx, 2)
+        g = m.adjoint(ctx, dJdp, None)
+        assert bool(torch.isfinite(g).all())
+    finally:
+        m.destroy(ctx)
