@@ -145,8 +145,13 @@ mrcm_status mrcm_set_interface_space(mrcm_ctx* ctx, mrcm_space space);
  * blocks are not square or exceed 256 unknowns. */
 mrcm_status mrcm_set_interface_solver(mrcm_ctx* ctx, mrcm_iface_solver solver);
 
-/* Robin parameters of the basis functions and of the smoothing steps
- * (Algorithm 1: Step 6 is needed only when they differ). Values > 0. */
+/* Robin parameters of the basis functions (Algorithm 1, Steps 1-2, and the
+ * particular problems of Step 4) and of the smoothing steps (Steps 6-7;
+ * Section 3 allows any positive value).  Values > 0.  When they differ,
+ * mrcm_build_basis also runs Step 6: every oversampled box is factored a
+ * second time with the smoothing parameter, and mrcm_smooth uses those
+ * factors (one more set of cached factors in device memory).  The adjoint
+ * needs equal values. */
 mrcm_status mrcm_set_robin(mrcm_ctx* ctx, mrcm_beta_mode mode, double mbf, double smooth);
 
 /* Precision of the local factorisations and solves.  tol > 0 and

@@ -73,6 +73,12 @@ struct mrcm_ctx {
   // device workspace
   double *fac = nullptr, *facs = nullptr, *facp = nullptr, *scr = nullptr;
   double* fact = nullptr;  // twisted-sweep factors (backward inverses, meeting block), fac layout
+  // Algorithm 1, Step 6: factors of the oversampled boxes with the smoothing
+  // Robin parameter when it differs from the basis one (facs / facts, or
+  // fac32s in the FP32 form), built by mrcm_build_basis
+  double* facts = nullptr;
+  float* fac32s = nullptr;
+  size_t lds_factor = 0;
   double *tco = nullptr, *tcp = nullptr;  // block couplings of the boxes / subdomains
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
   size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
@@ -180,7 +186,7 @@ void drop_graph(mrcm_ctx* c);
 void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
   dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members); dfree(c->d_obox_col);
-  dfree(c->fac); dfree(c->fact); dfree(c->facs); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
+  dfree(c->fac); dfree(c->fact); dfree(c->facs); dfree(c->facts); dfree(c->fac32s); dfree(c->facp); dfree(c->scr); dfree(c->tco); dfree(c->tcp);
   dfree(c->fac32); dfree(c->facp32); dfree(c->d_iters); dfree(c->d_resid);
   dfree(c->Pk); dfree(c->tr_u); dfree(c->tr_phi); dfree(c->tr_beta);
   dfree(c->pbar); dfree(c->ubar); dfree(c->pibar);
@@ -607,7 +613,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   c->scro_n = scr;
   c->scrp_n = scrp;
   c->wave = c->d == 2;
-  c->lds_basis = c->lds_part = c->lds_smooth = 0;
+  c->lds_basis = c->lds_part = c->lds_smooth = c->lds_factor = 0;
   c->lds_adj_smooth = c->lds_adj_basis = c->lds_adj_part = 0;
   for (int i = 0; i < nsub; ++i) {
     const Box& B = c->obox[i];
@@ -615,6 +621,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
     if (B.nb > 32 || P.nb > 32) c->wave = false;
     const int bm0 = B.hi[0] - B.lo[0], bm1 = B.hi[1] - B.lo[1];
     c->lds_basis = std::max(c->lds_basis, wave_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
+    c->lds_factor = std::max(c->lds_factor, wave_basis_lds_bytes(bm0, bm1, 0));
     c->lds_smooth = std::max(c->lds_smooth, wave_smooth_lds_bytes(bm0, bm1));
     c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1));
     c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0));
@@ -899,6 +906,9 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->flags_host, sizeof(int), hipHostMallocDefault);
   for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  // the error flags start clear: with deferred errors no later call clears
+  // them before the first mrcm_wait
+  if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
   if (e == hipSuccess) e = launch_fill(c->bcv, 0.0, off, c->stream);
   if (e == hipSuccess) e = launch_fill(c->f, 0.0, N, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -906,6 +916,7 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
     mrcm_destroy(c);
     return e == hipErrorOutOfMemory ? MRCM_ENOMEM : MRCM_EDEVICE;
   }
+  c->flags_zero = true;
   *out = c;
   return MRCM_OK;
 }
@@ -1056,6 +1067,28 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     HIPCHK(c, launch_particular(c->geo, c->d_pbox, c->geo.nsub, c->K, c->f, c->bcv, c->beta_mbf,
                                 c->facp, c->scr, c->pbar, c->ubar, c->pibar, c->flags, s));
   }
+  if (c->beta_sm != c->beta_mbf) {
+    // Step 6: the smoothing Robin parameter differs, so the oversampled
+    // boxes are factored once more with it
+    auto grow = [&](auto*& ptr, long long count) -> hipError_t {
+      if (ptr) return hipSuccess;
+      return hipMalloc((void**)&ptr, std::max<long long>(count, 1) * sizeof(*ptr));
+    };
+    if (r32) {
+      HIPCHK(c, grow(c->fac32s, c->fac_n));
+      HIPCHK(c, launch_factor32_w(c->geo, c->d_obox, c->geo.nsub, c->K, c->beta_sm, c->fac32s,
+                                  c->d_iters, c->d_resid, c->flags, c->lds32_basis, s));
+    } else if (c->wave) {
+      HIPCHK(c, grow(c->facs, c->fac_n));
+      HIPCHK(c, grow(c->facts, c->fac_n));
+      HIPCHK(c, launch_factor_w(c->geo, c->d_obox, c->geo.nsub, c->logk, c->beta_sm, c->facs,
+                                c->facts, c->flags, c->lds_factor, s));
+    } else {
+      HIPCHK(c, grow(c->facs, c->fac_n));
+      HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_sm, c->facs,
+                             c->scr, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, c->flags, s, 1));
+    }
+  }
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], s));
   c->timed_basis = c->timing;
   c->n_local_solves = c->nX + c->geo.nsub;
@@ -1132,18 +1165,21 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
       HIPCHK(c, hipMemcpyAsync(c->ck_g + c->n_ck * ng, gflux, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
       ++c->n_ck;
     }
+    const bool own = c->beta_sm != c->beta_mbf;  // Step 6 factors
     if (c->prec == MRCM_FP32_REFINE) {
       HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
-                                  c->beta_sm, c->fac32, p, gflux, c->tol, c->max_refine,
-                                  c->d_iters, c->d_resid, c->flags, c->lds32_smooth, nt, s));
+                                  c->beta_sm, own ? c->fac32s : c->fac32, p, gflux, c->tol,
+                                  c->max_refine, c->d_iters, c->d_resid, c->flags,
+                                  c->lds32_smooth, nt, s));
     } else if (c->wave) {
       HIPCHK(c, launch_smooth_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
-                                c->beta_sm, c->fac, c->fact, c->tco, c->scr, p, gflux,
-                                c->lds_smooth, nt, s));
+                                c->beta_sm, own ? c->facs : c->fac, own ? c->facts : c->fact,
+                                c->tco, c->scr, p, gflux, c->lds_smooth, nt, s));
     } else {
       HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
-                              c->beta_sm, c->fac, nullptr, nullptr, c->scr, p, gflux, c->prec,
-                              c->tol, c->max_refine, nullptr, nullptr, c->flags, s));
+                              c->beta_sm, own ? c->facs : c->fac, nullptr, nullptr, c->scr, p,
+                              gflux, c->prec, c->tol, c->max_refine, nullptr, nullptr, c->flags,
+                              s));
     }
   }
   return MRCM_OK;
@@ -1269,9 +1305,6 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
   c->flags_zero = false;  // new flag-setting work may follow
   if (c->state < 2) return fail(c, MRCM_ESTATE, "interface not solved");
   if (nsteps < 0) return fail(c, MRCM_EINVAL, "nsteps < 0");
-  if (nsteps > 0 && c->beta_sm != c->beta_mbf && !c->facs) {
-    return fail(c, MRCM_EINVAL, "distinct smoothing Robin parameter not available yet");
-  }
   hipStream_t s = c->stream;
   if (nsteps > 0) {
     mrcm_status st = tune_smoothing(c, s);
@@ -1313,9 +1346,10 @@ mrcm_status mrcm_smooth(mrcm_ctx* c, int nsteps) {
     ph.ncol = 1 << c->d;
     for (int col = 0; col <= ph.ncol; ++col) ph.off[col] = c->member_off[col];
     const hipError_t e =
-        launch_smooth_grid(c->geo, c->d_obox_col, ph, nphase, c->K, c->f, c->bcv,
-                           c->beta_sm, c->fac, c->fact, c->tco, c->p, c->gflux, c->lds_smooth,
-                           c->smooth_nt, c->persist_groups, s);
+        launch_smooth_grid(c->geo, c->d_obox_col, ph, nphase, c->K, c->f, c->bcv, c->beta_sm,
+                           c->beta_sm != c->beta_mbf ? c->facs : c->fac,
+                           c->beta_sm != c->beta_mbf ? c->facts : c->fact, c->tco, c->p,
+                           c->gflux, c->lds_smooth, c->smooth_nt, c->persist_groups, s);
     if (e == hipSuccess) {
       c->persist_used = true;
       c->n_smooth_launches = 1;

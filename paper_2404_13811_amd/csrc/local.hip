@@ -312,11 +312,14 @@ __global__ void __launch_bounds__(NT) k_basis(Geo g, const Box* __restrict__ box
                                               double* __restrict__ fac, double* __restrict__ scr,
                                               double* __restrict__ Pk, double* __restrict__ tr_u,
                                               double* __restrict__ tr_phi,
-                                              double* __restrict__ tr_beta, int* flags) {
+                                              double* __restrict__ tr_beta, int* flags,
+                                              int factor_only) {
   __shared__ LocalSmem sm;
   const Box B = boxes[blockIdx.x];
   if (threadIdx.x == 0) sm.flag = 0;
-  const int nrhs = B.nrhs;
+  // factor_only (Algorithm 1, Step 6): the factor with the smoothing Robin
+  // parameter, no right-hand side
+  const int nrhs = factor_only ? 0 : B.nrhs;
   double* S = scr + B.scr;
   // right-hand sides: T^R * seed on the seed's side
   for (long long e = threadIdx.x; e < (long long)nrhs * B.ncell; e += NT) S[e] = 0.0;
@@ -586,10 +589,10 @@ hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s) {
 hipError_t launch_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                         const double* K, double beta, double* fac, double* scr, double* Pk,
                         double* tr_u, double* tr_phi, double* tr_beta, int* flags,
-                        hipStream_t s) {
+                        hipStream_t s, int factor_only) {
   if (nbox <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_basis, dim3(nbox), dim3(NT), 0, s, g, boxes, seeds, K, beta, fac, scr, Pk,
-                     tr_u, tr_phi, tr_beta, flags);
+                     tr_u, tr_phi, tr_beta, flags, factor_only);
   return hipGetLastError();
 }
 

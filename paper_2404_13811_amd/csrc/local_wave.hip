@@ -89,6 +89,10 @@ __host__ __device__ inline size_t basis_lds_doubles(int m0, int m1, int nrhs) {
 // the meeting block; both back-substitute outwards.  The chain of block
 // inverses on one wave is about half as long as a one-ended elimination,
 // and fac / fact are exactly the factors of the two-ended smoothing sweep.
+// FO (factor only, Algorithm 1 Step 6): the box is factored with the
+// smoothing Robin parameter and nothing else is solved or written (the
+// block couplings do not depend on beta and are shared with Step 1).
+template <bool FO = false>
 __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
                                           const double* __restrict__ logK, double beta,
                                           double* __restrict__ fac, double* __restrict__ fact,
@@ -98,7 +102,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
                                           double* __restrict__ tr_beta, double* dsm, WaveSmem* sm) {
   const int L = lane_id();
   const int tid = threadIdx.x, wv = tid >> 6;
-  const int nrhs = B.nrhs;
+  const int nrhs = FO ? 0 : B.nrhs;
   BoxLds s = carve(dsm, B, nrhs);
   double* Z1 = s.Z + nrhs * NBW;
   double* Sm = Z1 + nrhs * NBW;
@@ -126,7 +130,8 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
     const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
     s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
   }
-  for (int e = tid; e < nc; e += 128) tcoup[B.scr + e] = s.Tn[e];
+  if (!FO)
+    for (int e = tid; e < nc; e += 128) tcoup[B.scr + e] = s.Tn[e];
   __syncthreads();
   const int nb = B.nb, nblk = B.nblk, m = nblk / 2;
   double* Wf = fac + B.fac;
@@ -173,8 +178,9 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
     }
     wgj(nb, sm[1], w);
     store_block(nb, fblock(Wt, nb, m), w);
-    mid_step(nb, nc, m, nblk, nrhs, s, Z1, w);
+    if (!FO) mid_step(nb, nc, m, nblk, nrhs, s, Z1, w);
   }
+  if (FO) return;
   __syncthreads();
   if (wv == 0) twist_back_cached(B, Wf, nrhs, s, s.Z, false);
   else twist_back_cached(B, Wt, nrhs, s, Z1, true);
@@ -323,6 +329,24 @@ __global__ void __launch_bounds__(128) k_local_w(Geo g, const Box* __restrict__ 
   if (threadIdx.x == 0 && (sm[0].flag | sm[1].flag)) atomicOr(flags, sm[0].flag | sm[1].flag);
 }
 
+// Algorithm 1, Step 6: the oversampled boxes factored again with the
+// smoothing Robin parameter (when it differs from the basis one), two waves
+// per box as in k_local_w, into their own forward / backward inverses.
+__global__ void __launch_bounds__(128) k_factor_w(Geo g, const Box* __restrict__ obox,
+                                                  const double* __restrict__ logK, double beta,
+                                                  double* __restrict__ fac,
+                                                  double* __restrict__ fact, int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmem sm[2];
+  const int L = lane_id(), wv = threadIdx.x >> 6;
+  if (L == 0) sm[wv].flag = 0;
+  const Box B = obox[blockIdx.x];
+  basis_box<true>(g, B, nullptr, logK, beta, fac, fact, nullptr, nullptr, nullptr, nullptr,
+                  nullptr, dsm, sm);
+  __syncthreads();
+  if (threadIdx.x == 0 && (sm[0].flag | sm[1].flag)) atomicOr(flags, sm[0].flag | sm[1].flag);
+}
+
 // Factor blocks a box's smoothing solve needs first (the first ring slots of
 // both halves on waves 0 and 1, the meeting block on wave 0): constant data,
 // loaded early so that their memory latency overlaps other work.
@@ -465,6 +489,18 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
   hipLaunchKernelGGL(k_local_w, dim3(nbox + (nbox + npart - 1) / npart), dim3(128), lds, s, g, obox,
                      pbox, nbox, seeds, logK, K, f, bcv, beta, fac, tcoup, facp, tcp, Pk, tr_u,
                      tr_phi, tr_beta, pbar, ubar, pibar, fact, npart, part_ld, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_w(const Geo& g, const Box* obox, int nbox, const double* logK,
+                           double beta, double* fac, double* fact, int* flags, size_t lds,
+                           hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  if (!fac || !fact) return hipErrorInvalidValue;
+  hipError_t e = set_lds(k_factor_w, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_factor_w, dim3(nbox), dim3(128), lds, s, g, obox, logK, beta, fac, fact,
+                     flags);
   return hipGetLastError();
 }
 

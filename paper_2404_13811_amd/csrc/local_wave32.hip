@@ -544,6 +544,25 @@ __global__ void __launch_bounds__(64) k_local32(Geo g, const Box* __restrict__ o
   if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
+// Algorithm 1, Step 6 in the FP32 form: the oversampled boxes factored
+// again (FP32, diagonally scaled) with the smoothing Robin parameter; no
+// right-hand side is solved.
+__global__ void __launch_bounds__(64) k_factor32(Geo g, const Box* __restrict__ obox,
+                                                 const double* __restrict__ K, double beta,
+                                                 float* __restrict__ fac32, int* iters,
+                                                 unsigned long long* resid, int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmemF sm;
+  const int L = lane_id();
+  if (L == 0) sm.flag = 0;
+  Box B = obox[blockIdx.x];
+  B.nrhs = 0;
+  basis32_box(g, B, nullptr, K, beta, fac32, nullptr, nullptr, nullptr, nullptr, 1.0, 0, iters,
+              resid, dsm, sm);
+  wsync();
+  if (L == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
 __host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1) {
   const size_t nc = (size_t)m0 * m1;
   return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW + 4);
@@ -615,6 +634,17 @@ hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int 
   hipLaunchKernelGGL(k_local32, dim3(2 * nbox), dim3(64), lds, s, g, obox, pbox, nbox, seeds, K, f,
                      bcv, beta, fac32, facp32, Pk, tr_u, tr_phi, tr_beta, pbar, ubar, pibar, tol,
                      max_refine, iters, resid, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor32_w(const Geo& g, const Box* obox, int nbox, const double* K, double beta,
+                             float* fac32, int* iters, unsigned long long* resid, int* flags,
+                             size_t lds, hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = set_lds(k_factor32, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_factor32, dim3(nbox), dim3(64), lds, s, g, obox, K, beta, fac32, iters,
+                     resid, flags);
   return hipGetLastError();
 }
 

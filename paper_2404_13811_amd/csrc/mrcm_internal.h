@@ -80,10 +80,12 @@ struct BcrGemv {
 hipError_t launch_exp(const double* logk, double* K, int n, int* flags, hipStream_t s);
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
 hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s);
+// factor_only != 0: factor the boxes with beta and solve nothing (Algorithm
+// 1, Step 6: the smoothing factor when its Robin parameter differs)
 hipError_t launch_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                         const double* K, double beta, double* fac, double* scr,
                         double* Pk, double* tr_u, double* tr_phi, double* tr_beta,
-                        int* flags, hipStream_t s);
+                        int* flags, hipStream_t s, int factor_only = 0);
 hipError_t launch_particular(const Geo& g, const Box* boxes, int nbox, const double* K,
                              const double* f, const double* bcv, double beta, double* fac,
                              double* scr, double* pbar, double* ubar, double* pibar,
@@ -127,6 +129,13 @@ hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nb
                           double* Pk, double* tr_u, double* tr_phi, double* tr_beta, double* pbar,
                           double* ubar, double* pibar, double* fact, int* flags, size_t lds,
                           size_t lds_part, hipStream_t s);
+// Algorithm 1, Step 6: the oversampled boxes factored again with the
+// smoothing Robin parameter into fac (forward inverses) and fact (backward
+// inverses, meeting block), the layout k_local_w writes; lds as its basis
+// boxes with no right-hand side
+hipError_t launch_factor_w(const Geo& g, const Box* obox, int nbox, const double* logK,
+                           double beta, double* fac, double* fact, int* flags, size_t lds,
+                           hipStream_t s);
 hipError_t launch_smooth_w(const Geo& g, const Box* boxes, int nmem,
                            const double* K, const double* f, const double* bcv, double beta,
                            const double* fac, const double* fact, const double* tcoup, double* scr,
@@ -158,6 +167,11 @@ hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int 
                             double* tr_phi, double* tr_beta, double* pbar, double* ubar,
                             double* pibar, double tol, int max_refine, int* iters,
                             unsigned long long* resid, int* flags, size_t lds, hipStream_t s);
+// Step 6 in the FP32 form: FP32 factors of the scaled oversampled boxes
+// with the smoothing Robin parameter (K must hold exp(log K))
+hipError_t launch_factor32_w(const Geo& g, const Box* obox, int nbox, const double* K, double beta,
+                             float* fac32, int* iters, unsigned long long* resid, int* flags,
+                             size_t lds, hipStream_t s);
 hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
                              const float* fac32, double* p, double* gflux, double tol,

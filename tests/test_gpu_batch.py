@@ -176,3 +176,30 @@ def test_back_to_back_deferred_solves_equal_a_synchronous_solve():
             assert np.array_equal(fl.cpu().numpy(), f0)
     finally:
         m.destroy(ctx)
+
+
+def test_deferred_errors_from_the_first_call_of_a_new_context():
+    """A context whose first solve runs with deferred errors reports only
+    its own errors: its device flags start clear, whatever the memory it
+    was given held before (here: device memory filled with all bits set and
+    handed back to the driver just before the context is created)."""
+    import torch
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    wl = make_workload("c5", scale=4)
+    for _ in range(3):
+        junk = torch.full((1 << 24,), -1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+        torch.cuda.empty_cache()
+        ctx = m.create(wl.dim, wl.ncell, wl.h)
+        try:
+            api.configure(ctx, wl, "fp64")
+            m.set_deferred_errors(ctx, True)
+            m.build_basis(ctx)
+            m.solve_interface(ctx)
+            m.smooth(ctx, 2)
+            m.get_solution(ctx)
+            m.wait(ctx)
+        finally:
+            m.destroy(ctx)

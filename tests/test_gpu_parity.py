@@ -150,6 +150,12 @@ def test_fp32_refine_c2_full(overlap):
     _check32(make_workload("c2", overlap=overlap))
 
 
+def test_fp32_refine_c3_full():
+    """The channel workload at full size (1024 x 1024, contrast 1e4) in the
+    FP32 + refinement form, against the oracle: flux within 1e-6."""
+    _check32(make_workload("c3"))
+
+
 # ------------------------------------------------- smoothing execution forms
 def _smooth_trace(wl, use_graph, threads, steps, precision="fp64", persistent=None):
     """Pressure and flux after each mrcm_smooth call (eager reads between
