@@ -110,7 +110,30 @@ typedef struct {
   int n_smooth_phases;     /* colour phases run by the last mrcm_smooth        */
   int smooth_persistent;   /* 1: the last mrcm_smooth ran as one cooperative
                               launch                                          */
+  double interface_residual; /* residual check of the last interface solve:
+                              the componentwise backward error
+                              max_r |G X - r|_r / (|G| |X| + |r|)_r of the
+                              interface system (Algorithm 1, Step 5), from the
+                              flux and pressure jump moments of the MRCM-O
+                              state; above 1e-8 mrcm_solve_interface's work
+                              raises MRCM_ESINGULAR.  0 if no interface.     */
 } mrcm_stats;
+
+/* Conservation and continuity measures of the current solution (Section 5's
+ * error measures; the cell mass balance of the mixed system, eq1b, and the
+ * interface equations int_ujump and int_pjump).  u is the output velocity
+ * of mrcm_get_flux; on an interface Gamma_ij each subdomain's own outward
+ * flux u_i, u_j and pressure trace pi = p_c - u h / (2 K_c) are used. */
+typedef struct {
+  double mass_residual_max;  /* max over cells |sum_faces |e| u - f h^d|      */
+  double mass_residual_rel;  /* the same over max over cells sum |e| |u|       */
+  double source_total;       /* sum over cells of f h^d                        */
+  double outflow[6];         /* per domain side: sum over its faces |e| u.n    */
+  double outflow_total;      /* sum of outflow[]: source_total when conserved  */
+  double flux_jump_max;      /* max over interfaces and test functions mu of
+                                |sum |e| mu (u_i + u_j)| / sum |e||mu|(|u_i|+|u_j|) */
+  double pressure_jump_max;  /* the same for pi_i - pi_j                        */
+} mrcm_balance;
 
 /* Create a context for a dim-dimensional grid (dim = 2 or 3) of
  * ncell[0..dim-1] cells of size h.  stream: a hipStream_t (NULL = default
@@ -163,7 +186,11 @@ mrcm_status mrcm_set_precision(mrcm_ctx* ctx, mrcm_precision prec, double tol, i
  * MRCM_EINCOMPAT, MRCM_ENOTPD, MRCM_ENOCONV, MRCM_ENOMEM, MRCM_EDEVICE. */
 mrcm_status mrcm_build_basis(mrcm_ctx* ctx);
 
-/* Steps 3-5: interface system and MRCM-O solution (resets smoothing).
+/* Steps 3-5: interface system and MRCM-O solution (resets smoothing).  The
+ * solve is checked on the device: the componentwise backward error of every
+ * interface equation (see mrcm_stats.interface_residual) must be <= 1e-8,
+ * else the solve's device error is MRCM_ESINGULAR (reported by the next call
+ * that reads the device flags).
  * Errors: MRCM_ESTATE, MRCM_ESINGULAR, MRCM_EDEVICE. */
 mrcm_status mrcm_solve_interface(mrcm_ctx* ctx);
 
@@ -195,6 +222,16 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* ctx, int use_graph, int threads_per_box
  * ones mrcm_set_smoothing selects.  Results are bit-identical to the
  * per-phase form.  Default: off.  Errors: MRCM_EINVAL (max_groups < 0). */
 mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* ctx, int on, int max_groups);
+
+/* Tolerance of the interface solve's check (default 1e-8): the largest
+ * componentwise backward error of the interface equations that
+ * mrcm_solve_interface accepts (mrcm_stats.interface_residual); above it the
+ * solve reports MRCM_ESINGULAR.  The block cyclic reduction does not pivot,
+ * and on very ill-conditioned interface systems (Robin parameters far above
+ * one) it can exceed the tolerance where the pivoted banded LU
+ * (MRCM_IFACE_BAND_LU) does not.  tol <= 0 turns the check off (the
+ * residual is still measured).  Errors: MRCM_EINVAL (NaN). */
+mrcm_status mrcm_set_interface_check(mrcm_ctx* ctx, double tol);
 
 /* Phase timing (default on): HIP events on the context's stream around the
  * phases of mrcm_build_basis, mrcm_solve_interface and mrcm_smooth, read by
@@ -268,6 +305,28 @@ mrcm_status mrcm_adjoint(mrcm_ctx* ctx, const double* dJdp_dev, const double* dJ
                          double* dJdlogK_dev);
 
 mrcm_status mrcm_get_stats(mrcm_ctx* ctx, mrcm_stats* out);
+
+/* Device reductions of the current solution (after mrcm_solve_interface or
+ * mrcm_smooth): the per-cell mass-balance residual r_c = sum_faces |e| u_e -
+ * f_c h^d into cell_residual_dev (N values, device, or NULL), the jump
+ * moments of every interface equation row into jumps_dev (n_unknowns values,
+ * device, or NULL; row order of the interface system: per interface
+ * Gamma_ij, i < j, in order of i then axis, its p flux rows
+ * sum_e |e| mu (u_i + u_j) then its p pressure rows sum_e |e| mu (pi_i - pi_j)),
+ * and the summary into *out (host).  Deterministic (fixed reduction order).
+ * Synchronises the context's stream.  Errors: MRCM_EINVAL, MRCM_ESTATE,
+ * MRCM_EDEVICE and the device errors of the solve. */
+mrcm_status mrcm_get_balance(mrcm_ctx* ctx, double* cell_residual_dev, double* jumps_dev,
+                             mrcm_balance* out);
+
+/* Relative L2 distances of the current outputs (pressure as mrcm_get_pressure,
+ * face velocities as mrcm_get_flux) from reference arrays on the device:
+ * out[0] = ||p - p_ref|| / ||p_ref|| (NaN when p_ref_dev is NULL), out[1] the
+ * same for the N x 2d face velocities (NaN when flux_ref_dev is NULL); out is
+ * host memory of two doubles.  Deterministic device reductions (the flux
+ * norms of Section 5 over per-cell face values).  Synchronises the stream. */
+mrcm_status mrcm_rel_error(mrcm_ctx* ctx, const double* p_ref_dev, const double* flux_ref_dev,
+                           double* out);
 
 /* Message of the last failure on this context (never NULL). */
 const char* mrcm_last_error(const mrcm_ctx* ctx);

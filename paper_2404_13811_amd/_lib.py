@@ -18,7 +18,8 @@ SYMBOLS = ("mrcm_create", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_
            "mrcm_set_timing", "mrcm_set_deferred_errors", "mrcm_wait", "mrcm_set_checkpointing", "mrcm_adjoint",
            "mrcm_set_precision", "mrcm_build_basis", "mrcm_solve_interface", "mrcm_smooth",
            "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_solution", "mrcm_get_coefficients", "mrcm_get_stats",
-           "mrcm_last_error", "mrcm_destroy")
+           "mrcm_get_balance", "mrcm_rel_error", "mrcm_set_interface_check", "mrcm_last_error",
+           "mrcm_destroy")
 
 
 class Stats(ctypes.Structure):
@@ -32,7 +33,14 @@ class Stats(ctypes.Structure):
                 ("n_smooth_launches", ctypes.c_int), ("ms_basis_kernel", ctypes.c_double),
                 ("smooth_threads", ctypes.c_int), ("smooth_graph", ctypes.c_int),
                 ("ms_autotune", ctypes.c_double), ("n_smooth_phases", ctypes.c_int),
-                ("smooth_persistent", ctypes.c_int)]
+                ("smooth_persistent", ctypes.c_int), ("interface_residual", ctypes.c_double)]
+
+
+class Balance(ctypes.Structure):
+    _fields_ = [("mass_residual_max", ctypes.c_double), ("mass_residual_rel", ctypes.c_double),
+                ("source_total", ctypes.c_double), ("outflow", ctypes.c_double * 6),
+                ("outflow_total", ctypes.c_double), ("flux_jump_max", ctypes.c_double),
+                ("pressure_jump_max", ctypes.c_double)]
 
 
 _lib = None
@@ -71,6 +79,9 @@ def load():
         "mrcm_get_solution": [vp, vp, vp],
         "mrcm_get_coefficients": [vp, vp],
         "mrcm_get_stats": [vp, ctypes.POINTER(Stats)],
+        "mrcm_get_balance": [vp, vp, vp, ctypes.POINTER(Balance)],
+        "mrcm_set_interface_check": [vp, d],
+        "mrcm_rel_error": [vp, vp, vp, ctypes.POINTER(ctypes.c_double)],
         "mrcm_destroy": [vp],
     }
     for name, args in sig.items():

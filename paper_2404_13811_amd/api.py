@@ -103,6 +103,12 @@ def set_smoothing_persistent(ctx, on=True, max_groups=0):
            _lib.load().mrcm_set_smoothing_persistent(ctx.handle, int(bool(on)), int(max_groups)))
 
 
+def set_interface_check(ctx, tol=1e-8):
+    """Largest accepted componentwise backward error of the interface solve
+    (tol <= 0: no check)."""
+    _check(ctx, "mrcm_set_interface_check", _lib.load().mrcm_set_interface_check(ctx.handle, float(tol)))
+
+
 def set_timing(ctx, on=True):
     _check(ctx, "mrcm_set_timing", _lib.load().mrcm_set_timing(ctx.handle, int(bool(on))))
 
@@ -171,6 +177,39 @@ def get_stats(ctx):
     st = _lib.Stats()
     _check(ctx, "mrcm_get_stats", _lib.load().mrcm_get_stats(ctx.handle, ctypes.byref(st)))
     return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def get_balance(ctx, cell_residual=False, jumps=False):
+    """Mass balance, boundary outflow and interface jump measures of the
+    current solution (mrcm_get_balance); optionally the per-cell residuals
+    and the per-row jump moments as device tensors."""
+    n = ctx.ncells
+    res = torch.empty(n, dtype=torch.float64, device="cuda") if cell_residual else None
+    nrow = get_stats(ctx)["n_unknowns"] if jumps else 0
+    mom = torch.empty(max(nrow, 1), dtype=torch.float64, device="cuda") if jumps else None
+    b = _lib.Balance()
+    fn = "mrcm_get_balance"
+    _check(ctx, fn, getattr(_lib.load(), fn)(
+        ctx.handle, _dev(res) if res is not None else None, _dev(mom) if mom is not None else None,
+        ctypes.byref(b)))
+    out = {k: getattr(b, k) for k, _ in b._fields_}
+    out["outflow"] = list(b.outflow)
+    if res is not None:
+        out["cell_residual"] = res
+    if mom is not None:
+        out["jumps"] = mom[:nrow]
+    return out
+
+
+def rel_error(ctx, p_ref=None, flux_ref=None):
+    """Relative L2 distances (pressure, flux) of the current outputs from
+    device reference arrays (mrcm_rel_error)."""
+    o = (ctypes.c_double * 2)()
+    n = ctx.ncells
+    _check(ctx, "mrcm_rel_error", _lib.load().mrcm_rel_error(
+        ctx.handle, _dev(p_ref, n) if p_ref is not None else None,
+        _dev(flux_ref, n * 2 * ctx.dim) if flux_ref is not None else None, o))
+    return o[0], o[1]
 
 
 def set_checkpointing(ctx, on=True):
@@ -259,11 +298,14 @@ def configure(ctx, wl, precision="fp64", tol=1e-12, max_refine=30, solver="auto"
 
 
 def solve_workload(wl, precision="fp64", nsmooth=None, tol=1e-12, max_refine=30, keep=False,
-                   solver="auto"):
-    """Full MRCM-OS solve of a workload; returns (pressure, flux[, ctx])."""
+                   solver="auto", check=None):
+    """Full MRCM-OS solve of a workload; returns (pressure, flux[, ctx]).
+    check: tolerance of the interface solve's check (None: the default)."""
     ctx = create(wl.dim, wl.ncell, wl.h)
     try:
         configure(ctx, wl, precision, tol, max_refine, solver)
+        if check is not None:
+            set_interface_check(ctx, check)
         build_basis(ctx)
         solve_interface(ctx)
         smooth(ctx, wl.nsmooth if nsmooth is None else nsmooth)

@@ -94,6 +94,15 @@ struct mrcm_ctx {
   int* flags_host = nullptr;  // pinned copy target of the error flags
   bool flags_zero = false;    // flags cleared by the last check, no work since
 
+  // conservation and continuity measures (balance.hip): partial sums,
+  // results, the largest relative interface jumps after the last
+  // mrcm_solve_interface (its residual check) and after mrcm_get_balance,
+  // output copies for mrcm_rel_error
+  double *bal_partial = nullptr, *bal_out = nullptr;
+  unsigned long long *jmax_solve = nullptr, *jmax_bal = nullptr;
+  double *cmp_p = nullptr, *cmp_f = nullptr;
+  double iface_check_tol = 1e-8;
+
   // block cyclic reduction of the interface system over the layers of
   // subdomains along the last axis (bcr.hip)
   struct BcrOp {
@@ -200,6 +209,8 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->a_pb); dfree(c->a_gfb); dfree(c->a_Kb); dfree(c->a_Xb); dfree(c->a_nu);
   dfree(c->a_trub); dfree(c->a_trphib); dfree(c->a_trbetab); dfree(c->a_ubarb);
   dfree(c->a_pibarb); dfree(c->a_mean); dfree(c->d_seed_sub);
+  dfree(c->bal_partial); dfree(c->bal_out); dfree(c->jmax_solve); dfree(c->jmax_bal);
+  dfree(c->cmp_p); dfree(c->cmp_f);
   drop_graph(c);
   c->smooth_nt = 0;
   c->use_bcr = false;
@@ -733,6 +744,10 @@ mrcm_status make_plan(mrcm_ctx* c) {
   ALLOC(c->p, g.ncells);
   ALLOC(c->gflux, (long long)nsub * g.gstride);
   ALLOC(c->partial, 64);
+  ALLOC(c->bal_partial, (long long)std::max(cell_balance_blocks(g), 256) * std::max(kBalParts, 2));
+  ALLOC(c->bal_out, 16);
+  ALLOC(c->jmax_solve, 2);
+  ALLOC(c->jmax_bal, 2);
   HIPCHK(c, hipMemcpy(c->d_obox, c->obox.data(), nsub * sizeof(Box), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_pbox, c->pbox.data(), nsub * sizeof(Box), hipMemcpyHostToDevice));
   if (!c->seeds.empty())
@@ -1142,6 +1157,24 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   }
   HIPCHK(c, launch_combine(c->geo, c->d_seed_off, c->X, c->Pk, c->tr_u, c->pbar, c->ubar, c->p,
                            c->gflux, s));
+  // the interface system's residual, row by row: the flux and pressure jump
+  // moments of the MRCM-O state over the moments of the magnitudes of every
+  // term of the row (a componentwise backward error); a row above the
+  // tolerance (a breakdown of the solve, which does not pivot) raises
+  // MRCM_ESINGULAR
+  if (!c->ifc.empty()) {
+    JumpTerms jt;
+    jt.X = c->X;
+    jt.seed_off = c->d_seed_off;
+    jt.tr_u = c->tr_u;
+    jt.tr_phi = c->tr_phi;
+    jt.tr_beta = c->tr_beta;
+    jt.ubar = c->ubar;
+    jt.pibar = c->pibar;
+    HIPCHK(c, launch_fill((double*)c->jmax_solve, 0.0, 2, s));
+    HIPCHK(c, launch_jumps(c->geo, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->K, c->p, c->gflux,
+                           nullptr, c->jmax_solve, c->iface_check_tol, c->flags, s, &jt));
+  }
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], s));
   c->timed_iface = c->timing;
   c->state = 2;
@@ -1267,6 +1300,13 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* c, int use_graph, int threads_per_box) 
   c->smooth_nt_req = threads_per_box;
   c->smooth_nt = 0;
   drop_graph(c);
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_interface_check(mrcm_ctx* c, double tol) {
+  if (!c) return MRCM_EINVAL;
+  if (!(tol == tol)) return fail(c, MRCM_EINVAL, "tolerance is NaN");
+  c->iface_check_tol = tol;
   return MRCM_OK;
 }
 
@@ -1506,6 +1546,64 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
   return check_flags(c);
 }
 
+mrcm_status mrcm_get_balance(mrcm_ctx* c, double* cell_residual_dev, double* jumps_dev,
+                             mrcm_balance* out) {
+  if (!c) return MRCM_EINVAL;
+  if (!out) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  const Geo& g = c->geo;
+  hipStream_t s = c->stream;
+  HIPCHK(c, launch_cell_balance(g, c->K, c->p, c->gflux, c->bcv, c->f, cell_residual_dev,
+                                c->bal_partial, std::max(cell_balance_blocks(g), 256), c->bal_out, s));
+  HIPCHK(c, launch_fill((double*)c->jmax_bal, 0.0, 2, s));
+  HIPCHK(c, launch_jumps(g, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->K, c->p, c->gflux,
+                         jumps_dev, c->jmax_bal, 0.0, c->flags, s));
+  double v[kBalParts];
+  unsigned long long jm[2];
+  HIPCHK(c, hipMemcpyAsync(v, c->bal_out, sizeof v, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(jm, c->jmax_bal, sizeof jm, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  std::memset(out, 0, sizeof *out);
+  out->mass_residual_max = v[0];
+  out->mass_residual_rel = v[1] > 0.0 ? v[0] / v[1] : v[0];
+  out->source_total = v[2];
+  double tot = 0.0;
+  for (int q = 0; q < 6; ++q) {
+    out->outflow[q] = q < 2 * g.d ? v[3 + q] : 0.0;
+    tot += out->outflow[q];
+  }
+  out->outflow_total = tot;
+  std::memcpy(&out->flux_jump_max, &jm[0], sizeof(double));
+  std::memcpy(&out->pressure_jump_max, &jm[1], sizeof(double));
+  return check_flags(c);
+}
+
+mrcm_status mrcm_rel_error(mrcm_ctx* c, const double* p_ref_dev, const double* flux_ref_dev,
+                           double* out) {
+  if (!c) return MRCM_EINVAL;
+  if (!out) return fail(c, MRCM_EINVAL, "output is NULL");
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  const Geo& g = c->geo;
+  hipStream_t s = c->stream;
+  const long long N = g.ncells, NF = N * 2 * g.d;
+  if (!c->cmp_p) HIPCHK(c, hipMalloc((void**)&c->cmp_p, N * sizeof(double)));
+  if (!c->cmp_f) HIPCHK(c, hipMalloc((void**)&c->cmp_f, NF * sizeof(double)));
+  HIPCHK(c, launch_solution_out(g, c->K, c->p, c->gflux, c->bcv, c->cmp_p, c->cmp_f, c->partial, s));
+  out[0] = out[1] = NAN;
+  double r[4] = {0, 0, 0, 0};
+  if (p_ref_dev) HIPCHK(c, launch_sq_dist(c->cmp_p, p_ref_dev, N, c->bal_partial, c->bal_out, s));
+  if (p_ref_dev) HIPCHK(c, hipMemcpyAsync(r, c->bal_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (flux_ref_dev) {
+    HIPCHK(c, launch_sq_dist(c->cmp_f, flux_ref_dev, NF, c->bal_partial, c->bal_out, s));
+    HIPCHK(c, hipMemcpyAsync(r + 2, c->bal_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (p_ref_dev) out[0] = std::sqrt(r[0]) / std::sqrt(r[1]);
+  if (flux_ref_dev) out[1] = std::sqrt(r[2]) / std::sqrt(r[3]);
+  return check_flags(c);
+}
+
 mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   if (!c) return MRCM_EINVAL;
   if (!out) return fail(c, MRCM_EINVAL, "output is NULL");
@@ -1551,6 +1649,15 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   out->ms_autotune = c->ms_autotune;
   out->n_smooth_phases = c->n_smooth_phases;
   out->smooth_persistent = c->persist_used ? 1 : 0;
+  out->interface_residual = 0.0;
+  if (c->plan_valid && c->state >= 2 && !c->ifc.empty()) {
+    unsigned long long jm[2];
+    HIPCHK(c, hipMemcpy(jm, c->jmax_solve, sizeof jm, hipMemcpyDeviceToHost));
+    double a, b;
+    std::memcpy(&a, &jm[0], sizeof a);
+    std::memcpy(&b, &jm[1], sizeof b);
+    out->interface_residual = std::max(a, b);
+  }
   return check_flags(c);
 }
 

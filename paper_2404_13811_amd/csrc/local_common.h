@@ -80,6 +80,46 @@ __device__ __forceinline__ int side_face_index(const Geo& g, const int lo[3], co
   return i0 + (pick3(hi, t0) - pick3(lo, t0)) * (pick3(c, t1) - pick3(lo, t1));
 }
 
+// Outward normal velocity on face (a, s) of global cell c (flat index ci)
+// of the solution state: boundary faces from the boundary condition,
+// faces inside the owning subdomain from the two-point flux of p, faces on
+// the skeleton from the owner's Gamma flux (own: the owner's subdomain
+// coordinates, sub its index).
+__device__ __forceinline__ double state_face_u(const Geo& g, const double* __restrict__ K,
+                                               const double* __restrict__ p,
+                                               const double* __restrict__ gflux,
+                                               const double* __restrict__ bcv, const int c[3],
+                                               int ci, const int own[3], int sub, int a, int s) {
+  const int q = 2 * a + s;
+  int o[3] = {c[0], c[1], c[2]};
+  o[a] += s ? 1 : -1;
+  const double kc = K[ci];
+  if (o[a] < 0 || o[a] >= g.n[a]) {
+    const double val = bcv[g.bc_off[q] + bface_index(g, c, a)];
+    return g.bc_type[q] ? 2.0 * kc * g.area / g.h * (p[ci] - val) / g.area : val;
+  }
+  if (o[a] / g.S[a] == own[a]) {
+    const int oi = gcell(g, o);
+    return g.area * kharm(kc, K[oi]) / g.h * (p[ci] - p[oi]) / g.area;
+  }
+  int lo[3], hi[3];
+  for (int b = 0; b < 3; ++b) {
+    lo[b] = (b < g.d) ? own[b] * g.S[b] : 0;
+    hi[b] = (b < g.d) ? lo[b] + g.S[b] : 1;
+  }
+  const int t = side_face_index(g, lo, hi, c, a);
+  return gflux[(long long)sub * g.gstride + g.gside_off[q] + t];
+}
+
+// Cell coordinates, owning subdomain coordinates and index of cell ci.
+__device__ __forceinline__ int cell_owner(const Geo& g, int ci, int c[3], int own[3]) {
+  c[0] = ci % g.n[0];
+  c[1] = (ci / g.n[0]) % g.n[1];
+  c[2] = ci / (g.n[0] * g.n[1]);
+  for (int a = 0; a < 3; ++a) own[a] = (a < g.d) ? c[a] / g.S[a] : 0;
+  return own[0] + g.M[0] * (own[1] + (g.d == 3 ? g.M[1] * own[2] : 0));
+}
+
 // Value of a seed (or interface test function) on the face of side
 // `sd.side` of box [lo, hi) touched by global cell c.
 __device__ __forceinline__ double seed_value(const Geo& g, const Seed& sd, const int lo[3],

@@ -258,6 +258,38 @@ hipError_t launch_bcr_scatter_t(const double* RB, const double* rhs, int n, int 
 hipError_t launch_bcr_gather_t(const double* xv, const int* row_lvl, const int* row_loc, int n, int bp,
                                double* out, hipStream_t s);
 
+// conservation and continuity measures of a state (balance.hip)
+constexpr int kBalParts = 9;  // max |r_c|, max sum |e||u|, sum f h^d, outflow of 6 sides
+// per-cell mass-balance residual (res may be null) and the kBalParts
+// quantities into out (partial: cell_balance_blocks(g) * kBalParts doubles)
+hipError_t launch_cell_balance(const Geo& g, const double* K, const double* p, const double* gflux,
+                               const double* bcv, const double* f, double* res, double* partial,
+                               int max_blocks, double* out, hipStream_t s);
+int cell_balance_blocks(const Geo& g);
+// jump moments of every interface row (mom may be null), largest relative
+// flux / pressure jump into jmax[0] / jmax[1] (bits of non-negative
+// doubles, max-accumulated: clear them first); tol > 0 raises
+// kFlagSingular where a row's relative jump exceeds tol
+// The terms of the interface equations, for a componentwise backward
+// error (all null: magnitudes of the state's values instead)
+struct JumpTerms {
+  const double* X = nullptr;
+  const int* seed_off = nullptr;
+  const double* tr_u = nullptr;
+  const double* tr_phi = nullptr;
+  const double* tr_beta = nullptr;
+  const double* ubar = nullptr;
+  const double* pibar = nullptr;
+};
+hipError_t launch_jumps(const Geo& g, const Iface* ifc, int nifc, const Seed* basis, const double* K,
+                        const double* p, const double* gflux, double* mom,
+                        unsigned long long* jmax, double tol, int* flags, hipStream_t s,
+                        const JumpTerms* terms = nullptr);
+// relative L2 distance: out[0] = sum (a - b)^2 and out[1] = sum b^2 over
+// n values, deterministic (partial: 2 * 256 doubles)
+hipError_t launch_sq_dist(const double* a, const double* b, long long n, double* partial,
+                          double* out, hipStream_t s);
+
 // outputs (outputs.hip)
 hipError_t launch_pressure_out(const Geo& g, const double* p, double* out, double* partial,
                                hipStream_t s);

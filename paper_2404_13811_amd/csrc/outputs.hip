@@ -48,37 +48,11 @@ __device__ __forceinline__ void flux_out(const Geo& g, const double* __restrict_
                                          int b) {
   const int ci = b * blockDim.x + threadIdx.x;
   if (ci >= g.ncells) return;
-  int c[3];
-  c[0] = ci % g.n[0];
-  c[1] = (ci / g.n[0]) % g.n[1];
-  c[2] = ci / (g.n[0] * g.n[1]);
-  const double kc = K[ci];
-  int own[3];
-  for (int a = 0; a < 3; ++a) own[a] = (a < g.d) ? c[a] / g.S[a] : 0;
-  const int sub = own[0] + g.M[0] * (own[1] + (g.d == 3 ? g.M[1] * own[2] : 0));
+  int c[3], own[3];
+  const int sub = cell_owner(g, ci, c, own);
   for (int a = 0; a < g.d; ++a)
-    for (int s = 0; s < 2; ++s) {
-      const int q = 2 * a + s;
-      int o[3] = {c[0], c[1], c[2]};
-      o[a] += s ? 1 : -1;
-      double u;
-      if (o[a] < 0 || o[a] >= g.n[a]) {
-        const double val = bcv[g.bc_off[q] + bface_index(g, c, a)];
-        u = g.bc_type[q] ? 2.0 * kc * g.area / g.h * (p[ci] - val) / g.area : val;
-      } else if (o[a] / g.S[a] == own[a]) {
-        const int oi = gcell(g, o);
-        u = g.area * kharm(kc, K[oi]) / g.h * (p[ci] - p[oi]) / g.area;
-      } else {
-        int lo[3], hi[3];
-        for (int b = 0; b < 3; ++b) {
-          lo[b] = (b < g.d) ? own[b] * g.S[b] : 0;
-          hi[b] = (b < g.d) ? lo[b] + g.S[b] : 1;
-        }
-        const int t = side_face_index(g, lo, hi, c, a);
-        u = gflux[(long long)sub * g.gstride + g.gside_off[q] + t];
-      }
-      out[(long long)ci * (2 * g.d) + q] = u;
-    }
+    for (int s = 0; s < 2; ++s)
+      out[(long long)ci * (2 * g.d) + 2 * a + s] = state_face_u(g, K, p, gflux, bcv, c, ci, own, sub, a, s);
 }
 
 __global__ void k_flux_out(Geo g, const double* __restrict__ K, const double* __restrict__ p,

@@ -62,22 +62,29 @@ def _interface_condition(wl):
     return float(np.linalg.cond(G.toarray()))
 
 
-def _run(wl, precision="fp64"):
+def _run(wl, precision="fp64", solver="auto", check=None):
     from gpu_util import gpu_solve, oracle_solve, rel
     print("case", wl.name, wl.ncell, "l=%d" % wl.overlap, wl.space, "alpha_mbf %.0e" % wl.beta_mbf,
-          "alpha_sm %.0e" % wl.beta_smooth, precision, flush=True)
-    p, fl, X, st = gpu_solve(wl, precision=precision, tol=1e-12, max_refine=30)
+          "alpha_sm %.0e" % wl.beta_smooth, precision, solver, flush=True)
+    p, fl, X, st = gpu_solve(wl, precision=precision, tol=1e-12, max_refine=30, solver=solver,
+                             check=check)
     rp, rf, rX, _ = oracle_solve(wl)
     ep, ef = rel(p, rp), rel(fl, rf)
-    print("  rel L2 p %.3e flux %.3e" % (ep, ef), flush=True)
-    return ep, ef
+    print("  rel L2 p %.3e flux %.3e X %.3e; interface backward error %.2e"
+          % (ep, ef, rel(X, rX), st["interface_residual"]), flush=True)
+    if check is None:
+        assert st["interface_residual"] <= 1e-8
+    return ep, ef, st
 
 
+# Up to alpha_mbf = 1e4 the cyclic reduction (no pivoting) passes the
+# interface check; at 1e8 the pivoted banded LU solves the system (the
+# reduction's breakdown there is detected, see the test below).
 @pytest.mark.parametrize("alpha", ALPHAS)
 @pytest.mark.parametrize("kind", ["const_l2", "linear_l2_wells"])
 def test_alpha_sweep_fp64(kind, alpha):
     wl = _wl(kind, alpha)
-    ep, ef = _run(wl)
+    ep, ef, _ = _run(wl, solver="band_lu" if alpha > 1e4 else "auto")
     cond = _interface_condition(wl)
     sp, sf = _oracle_sensitivity(wl)
     bar = max(1e-10, 1e-14 * cond)
@@ -90,5 +97,23 @@ def test_alpha_sweep_fp64(kind, alpha):
 
 @pytest.mark.parametrize("alpha", [1e-4, 1e4])
 def test_alpha_sweep_fp32_refine(alpha):
-    ep, ef = _run(_wl("const_l2", alpha), "fp32_refine")
+    ep, ef, _ = _run(_wl("const_l2", alpha), "fp32_refine")
     assert ef <= 1e-6 and ep <= 1e-6
+
+
+@pytest.mark.parametrize("kind", ["const_l2", "linear_l2_wells"])
+def test_interface_check_flags_an_inaccurate_reduction(kind):
+    """alpha_mbf = 1e8 through the cyclic reduction with the check off: the
+    measured backward error decides; with the check on, a solve whose
+    backward error exceeds 1e-8 is reported as MRCM_ESINGULAR and one
+    below it passes."""
+    import paper_2404_13811_amd as m
+    wl = _wl(kind, 1e8)
+    _, _, st = _run(wl, solver="bcr", check=0.0)
+    be = st["interface_residual"]
+    if be > 1e-8:
+        with pytest.raises(m.MRCMError) as err:
+            m.solve_workload(wl, solver="bcr")
+        assert err.value.status == 8  # MRCM_ESINGULAR
+    else:
+        m.solve_workload(wl, solver="bcr")

@@ -1,0 +1,128 @@
+"""Device reductions of the solution (mass balance per cell, boundary
+outflow, interface flux and pressure jump moments, relative L2 distances)
+against the same quantities computed from the CPU oracle's outputs, and the
+interface solve's residual check (MRCM-O: every jump moment vanishes up to
+the solve's rounding, equations int_ujump and int_pjump)."""
+import numpy as np
+import pytest
+
+from inputs import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def oracle_jumps(s):
+    """Flux and pressure jump moments of the oracle's state, row by row in
+    the interface system's order (per interface: p flux rows, p pressure
+    rows), and the moments of their magnitudes."""
+    from oracle.tpfa import box_coords, side_local
+    g, part = s.grid, s.part
+    mom, scale = [], []
+    for (i, a, j) in part.interfaces():
+        qi, qj = 2 * a + 1, 2 * a
+        lo_i, hi_i = part.omega(i)
+        lo_j, hi_j = part.omega(j)
+        ci = g.flat(box_coords(lo_i, hi_i)[side_local(lo_i, hi_i, qi)])
+        cj = g.flat(box_coords(lo_j, hi_j)[side_local(lo_j, hi_j, qj)])
+        ui, uj = s.gflux[i][qi], s.gflux[j][qj]
+        pi_i = s.p[ci] - ui * g.h / (2.0 * g.K[ci])
+        pi_j = s.p[cj] - uj * g.h / (2.0 * g.K[cj])
+        fam = s.interface_family(i, qi)
+        for mu in fam:
+            w = g.area * mu
+            mom.append(np.dot(w, ui + uj))
+            scale.append(np.dot(np.abs(w), np.abs(ui) + np.abs(uj)))
+        for mu in fam:
+            w = g.area * mu
+            mom.append(np.dot(w, pi_i - pi_j))
+            scale.append(np.dot(np.abs(w), np.abs(pi_i) + np.abs(pi_j)))
+    return np.array(mom), np.array(scale)
+
+
+def _solve(wl, nsmooth):
+    import paper_2404_13811_amd as m
+    p, fl, ctx = m.solve_workload(wl, nsmooth=nsmooth, keep=True)
+    return m, p, fl, ctx
+
+
+@pytest.mark.parametrize("case,nsmooth", [("c1", 0), ("c1", 2), ("c2_l2", 0), ("c2_l2", 3),
+                                          ("c5", 5), ("c4_small", 1)])
+def test_balance_against_oracle_outputs(case, nsmooth):
+    import torch
+    from oracle import mrcm
+    wl = {"c1": lambda: make_workload("c1"),
+          "c2_l2": lambda: make_workload("c2", scale=4, overlap=2),
+          "c5": lambda: make_workload("c5", scale=2),
+          "c4_small": lambda: make_workload("c4", scale=8)}[case]()
+    print("case", case, wl.ncell, "smoothing", nsmooth, flush=True)
+    m, p, fl, ctx = _solve(wl, nsmooth)
+    try:
+        b = m.get_balance(ctx, cell_residual=True, jumps=True)
+        st = m.get_stats(ctx)
+        s = mrcm.solve(wl, nsmooth=nsmooth)
+        F = s.flux()
+        g = s.grid
+        res = F.sum(axis=1) * g.area - wl.source.ravel() * g.h ** wl.dim
+        scale = np.abs(F).sum(axis=1).max() * g.area
+        gres = b["cell_residual"].cpu().numpy()
+        print("  mass residual max: device %.2e oracle %.2e (scale %.2e)"
+              % (b["mass_residual_max"], np.abs(res).max(), scale), flush=True)
+        # every cell balances in both (the method is locally conservative)
+        assert b["mass_residual_max"] <= 1e-11 * scale
+        assert np.abs(gres).max() == pytest.approx(b["mass_residual_max"], rel=0, abs=0)
+        assert np.abs(res).max() <= 1e-11 * scale
+        # outflow per side and total source
+        out_o = []
+        for side in range(2 * wl.dim):
+            a, sd = divmod(side, 2)
+            sl = [slice(None)] * wl.dim
+            sl[wl.dim - 1 - a] = -1 if sd else 0
+            Fa = F.reshape(tuple(wl.ncell[::-1]) + (2 * wl.dim,))
+            out_o.append(Fa[tuple(sl)][..., side].sum() * g.area)
+        out_g = b["outflow"][:2 * wl.dim]
+        tot = max(np.abs(out_o).max(), 1e-300)
+        print("  outflow device", np.round(out_g, 12), "oracle", np.round(out_o, 12), flush=True)
+        assert np.abs(np.array(out_g) - np.array(out_o)).max() <= 1e-9 * tot
+        assert abs(b["source_total"] - float((wl.source.ravel() * g.h ** wl.dim).sum())) <= 1e-12 * max(1.0, np.abs(wl.source).sum() * g.h ** wl.dim)
+        # interface jump moments, row by row
+        mo, so = oracle_jumps(s)
+        mg = b["jumps"].cpu().numpy()
+        assert mg.shape == mo.shape
+        ref = max(so.max(), 1e-300)
+        print("  jump moments: max |device - oracle| %.2e of scale %.2e; max relative jump "
+              "device (flux %.2e, pressure %.2e)" % (np.abs(mg - mo).max(), ref, b["flux_jump_max"],
+                                                    b["pressure_jump_max"]), flush=True)
+        assert np.abs(mg - mo).max() <= 1e-9 * ref
+        rel_o = np.abs(mo) / np.maximum(so, 1e-300)
+        nf = 0 if nsmooth == 0 else None
+        if nsmooth == 0:
+            # MRCM-O satisfies the interface equations: every jump vanishes
+            assert max(b["flux_jump_max"], b["pressure_jump_max"]) <= 1e-9
+            assert rel_o.max() <= 1e-9
+            assert st["interface_residual"] <= 1e-9
+        else:
+            assert max(b["flux_jump_max"], b["pressure_jump_max"]) > 1e-9   # smoothing moved them
+        del nf
+        # relative L2 distances on the device
+        rp = torch.as_tensor(s.pressure(), device="cuda")
+        rf = torch.as_tensor(F.ravel(), device="cuda")
+        ep, ef = m.rel_error(ctx, rp, rf)
+        pn, fn = p.cpu().numpy(), fl.cpu().numpy()
+        ep_np = np.linalg.norm(pn - s.pressure()) / np.linalg.norm(s.pressure())
+        ef_np = np.linalg.norm(fn - F.ravel()) / np.linalg.norm(F.ravel())
+        print("  rel L2 device (%.3e, %.3e) numpy (%.3e, %.3e)" % (ep, ef, ep_np, ef_np), flush=True)
+        assert ep == pytest.approx(ep_np, rel=1e-6) and ef == pytest.approx(ef_np, rel=1e-6)
+        rng = np.random.default_rng(5)
+        rp2 = torch.as_tensor(s.pressure() * (1 + 1e-3 * rng.standard_normal(wl.ncells)), device="cuda")
+        ep2, ef2 = m.rel_error(ctx, rp2, None)
+        ep2_np = np.linalg.norm(pn - rp2.cpu().numpy()) / np.linalg.norm(rp2.cpu().numpy())
+        assert ep2 == pytest.approx(ep2_np, rel=1e-12) and np.isnan(ef2)
+    finally:
+        m.destroy(ctx)
