@@ -319,6 +319,19 @@ mrcm_status mrcm_get_stats(mrcm_ctx* ctx, mrcm_stats* out);
 mrcm_status mrcm_get_balance(mrcm_ctx* ctx, double* cell_residual_dev, double* jumps_dev,
                              mrcm_balance* out);
 
+/* mrcm_get_balance for callers that cannot allocate device memory (code
+ * between HIP graph captures, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results, bit for bit, with the partial sums and
+ * maxima in a static device array of 65536 doubles instead of the
+ * context's workspace; the call makes no allocation of any kind.  Limit:
+ * grids of at most 1,863,424 cells (MRCM_EINVAL beyond).  The array is one
+ * per GPU, shared by every context on it and kept until the process ends:
+ * calls that overlap in time on one GPU (on different streams or threads)
+ * race on it and must be serialised by the caller.  Synchronises the
+ * context's stream.  Errors: as mrcm_get_balance. */
+mrcm_status mrcm_get_balance_static(mrcm_ctx* ctx, double* cell_residual_dev, double* jumps_dev,
+                                    mrcm_balance* out);
+
 /* Relative L2 distances of the current outputs (pressure as mrcm_get_pressure,
  * face velocities as mrcm_get_flux) from reference arrays on the device:
  * out[0] = ||p - p_ref|| / ||p_ref|| (NaN when p_ref_dev is NULL), out[1] the

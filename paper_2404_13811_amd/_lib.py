@@ -18,7 +18,7 @@ SYMBOLS = ("mrcm_create", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_
            "mrcm_set_timing", "mrcm_set_deferred_errors", "mrcm_wait", "mrcm_set_checkpointing", "mrcm_adjoint",
            "mrcm_set_precision", "mrcm_build_basis", "mrcm_solve_interface", "mrcm_smooth",
            "mrcm_get_pressure", "mrcm_get_flux", "mrcm_get_solution", "mrcm_get_coefficients", "mrcm_get_stats",
-           "mrcm_get_balance", "mrcm_rel_error", "mrcm_set_interface_check", "mrcm_last_error",
+           "mrcm_get_balance", "mrcm_get_balance_static", "mrcm_rel_error", "mrcm_set_interface_check", "mrcm_last_error",
            "mrcm_destroy")
 
 
@@ -80,6 +80,7 @@ def load():
         "mrcm_get_coefficients": [vp, vp],
         "mrcm_get_stats": [vp, ctypes.POINTER(Stats)],
         "mrcm_get_balance": [vp, vp, vp, ctypes.POINTER(Balance)],
+        "mrcm_get_balance_static": [vp, vp, vp, ctypes.POINTER(Balance)],
         "mrcm_set_interface_check": [vp, d],
         "mrcm_rel_error": [vp, vp, vp, ctypes.POINTER(ctypes.c_double)],
         "mrcm_destroy": [vp],

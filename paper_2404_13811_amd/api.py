@@ -179,16 +179,17 @@ def get_stats(ctx):
     return {k: getattr(st, k) for k, _ in st._fields_}
 
 
-def get_balance(ctx, cell_residual=False, jumps=False):
+def get_balance(ctx, cell_residual=False, jumps=False, static=False):
     """Mass balance, boundary outflow and interface jump measures of the
-    current solution (mrcm_get_balance); optionally the per-cell residuals
-    and the per-row jump moments as device tensors."""
+    current solution (mrcm_get_balance, or mrcm_get_balance_static with
+    static=True); optionally the per-cell residuals and the per-row jump
+    moments as device tensors (allocated here, outside the C call)."""
     n = ctx.ncells
     res = torch.empty(n, dtype=torch.float64, device="cuda") if cell_residual else None
     nrow = get_stats(ctx)["n_unknowns"] if jumps else 0
     mom = torch.empty(max(nrow, 1), dtype=torch.float64, device="cuda") if jumps else None
     b = _lib.Balance()
-    fn = "mrcm_get_balance"
+    fn = "mrcm_get_balance_static" if static else "mrcm_get_balance"
     _check(ctx, fn, getattr(_lib.load(), fn)(
         ctx.handle, _dev(res) if res is not None else None, _dev(mom) if mom is not None else None,
         ctypes.byref(b)))
@@ -199,6 +200,11 @@ def get_balance(ctx, cell_residual=False, jumps=False):
     if mom is not None:
         out["jumps"] = mom[:nrow]
     return out
+
+
+def get_balance_static(ctx, cell_residual=False, jumps=False):
+    """mrcm_get_balance_static: get_balance with no allocation in the call."""
+    return get_balance(ctx, cell_residual, jumps, static=True)
 
 
 def rel_error(ctx, p_ref=None, flux_ref=None):

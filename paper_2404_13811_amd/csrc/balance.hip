@@ -20,6 +20,8 @@
 // non-negative doubles, whose order is the order of the values.
 #include "local_common.h"
 
+#include <mutex>
+
 namespace mrcm {
 namespace {
 
@@ -262,6 +264,33 @@ hipError_t launch_sq_dist(const double* a, const double* b, long long n, double*
   hipLaunchKernelGGL(k_sq_dist, dim3(nb), dim3(RB), 0, s, a, b, n, partial);
   hipLaunchKernelGGL(k_sq_dist_final, dim3(1), dim3(64), 0, s, partial, nb, out);
   return hipGetLastError();
+}
+
+// Scratch of mrcm_get_balance_static: a file-scope device array (one copy
+// per GPU, held until the process ends), so that the call allocates
+// nothing.  Host code never passes the array's name to a kernel: it uses the
+// device address hipGetSymbolAddress returns, kept per device.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+std::mutex scratch_mu;
+double* scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(double** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = p;
+  }
+  *ptr = scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_cell_balance(const Geo& g, const double* K, const double* p, const double* gflux,

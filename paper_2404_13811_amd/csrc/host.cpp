@@ -92,6 +92,7 @@ struct mrcm_ctx {
   double *p = nullptr, *gflux = nullptr, *partial = nullptr;
   int* flags = nullptr;
   int* flags_host = nullptr;  // pinned copy target of the error flags
+  double* stage_host = nullptr;  // pinned copy target of small results (16 doubles)
   bool flags_zero = false;    // flags cleared by the last check, no work since
 
   // conservation and continuity measures (balance.hip): partial sums,
@@ -920,6 +921,7 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->flags_host, sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->stage_host, 16 * sizeof(double), hipHostMallocDefault);
   for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   // the error flags start clear: with deferred errors no later call clears
   // them before the first mrcm_wait
@@ -1578,6 +1580,51 @@ mrcm_status mrcm_get_balance(mrcm_ctx* c, double* cell_residual_dev, double* jum
   return check_flags(c);
 }
 
+mrcm_status mrcm_get_balance_static(mrcm_ctx* c, double* cell_residual_dev, double* jumps_dev,
+                                    mrcm_balance* out) {
+  if (!c) return MRCM_EINVAL;
+  if (!out) return fail(c, MRCM_EINVAL, "output is NULL");
+  // scratch layout: jump maxima (2), results (16), partial sums of the
+  // 256-cell workgroups
+  const long long ncells = (long long)c->n[0] * c->n[1] * c->n[2];
+  const long long need = 18 + (ncells + 255) / 256 * kBalParts;
+  if (need > kStaticScratchDoubles)
+    return fail(c, MRCM_EINVAL,
+                "grid of %lld cells needs %lld doubles of static scratch, more than the %d available "
+                "(at most %d cells)", ncells, need, kStaticScratchDoubles,
+                (kStaticScratchDoubles - 18) / kBalParts * 256);
+  if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution yet");
+  const Geo& g = c->geo;
+  double* sc = nullptr;
+  HIPCHK(c, static_scratch(&sc));
+  hipStream_t s = c->stream;
+  unsigned long long* jm = reinterpret_cast<unsigned long long*>(sc);
+  double* res = sc + 2;
+  double* part = sc + 18;
+  HIPCHK(c, launch_cell_balance(g, c->K, c->p, c->gflux, c->bcv, c->f, cell_residual_dev, part,
+                                cell_balance_blocks(g), res, s));
+  HIPCHK(c, launch_fill(sc, 0.0, 2, s));  // the maxima start at zero
+  HIPCHK(c, launch_jumps(g, c->d_ifc, (int)c->ifc.size(), c->d_basis, c->K, c->p, c->gflux,
+                         jumps_dev, jm, 0.0, c->flags, s));
+  HIPCHK(c, hipMemcpyAsync(c->stage_host, sc, (2 + kBalParts) * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const double* v = c->stage_host + 2;
+  std::memset(out, 0, sizeof *out);
+  out->mass_residual_max = v[0];
+  out->mass_residual_rel = v[1] > 0.0 ? v[0] / v[1] : v[0];
+  out->source_total = v[2];
+  double tot = 0.0;
+  for (int q = 0; q < 6; ++q) {
+    out->outflow[q] = q < 2 * g.d ? v[3 + q] : 0.0;
+    tot += out->outflow[q];
+  }
+  out->outflow_total = tot;
+  std::memcpy(&out->flux_jump_max, c->stage_host, sizeof(double));
+  std::memcpy(&out->pressure_jump_max, c->stage_host + 1, sizeof(double));
+  return check_flags(c);
+}
+
 mrcm_status mrcm_rel_error(mrcm_ctx* c, const double* p_ref_dev, const double* flux_ref_dev,
                            double* out) {
   if (!c) return MRCM_EINVAL;
@@ -1673,6 +1720,7 @@ mrcm_status mrcm_destroy(mrcm_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dfree(c->logk); dfree(c->K); dfree(c->f); dfree(c->bcv); dfree(c->flags);
   if (c->flags_host) (void)hipHostFree(c->flags_host);
+  if (c->stage_host) (void)hipHostFree(c->stage_host);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;

@@ -285,6 +285,12 @@ hipError_t launch_jumps(const Geo& g, const Iface* ifc, int nifc, const Seed* ba
                         const double* p, const double* gflux, double* mom,
                         unsigned long long* jmax, double tol, int* flags, hipStream_t s,
                         const JumpTerms* terms = nullptr);
+// Device address of the static scratch array of mrcm_get_balance_static
+// on the current device (kStaticScratchDoubles doubles; looked up once per
+// device, then cached)
+constexpr int kStaticScratchDoubles = 1 << 16;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(double** ptr);
 // relative L2 distance: out[0] = sum (a - b)^2 and out[1] = sum b^2 over
 // n values, deterministic (partial: 2 * 256 doubles)
 hipError_t launch_sq_dist(const double* a, const double* b, long long n, double* partial,
