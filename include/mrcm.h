@@ -87,8 +87,25 @@ typedef enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 } mrcm_bc_type;
  * flux equations of an interface assigned to its lower-indexed subdomain and
  * the pressure equations to the higher one (square layer blocks, block
  * tridiagonal system), dense block inverses without pivoting; needs layer
- * blocks of at most 256 unknowns.  AUTO: BCR when it applies, else BAND_LU. */
-typedef enum { MRCM_IFACE_AUTO = 0, MRCM_IFACE_BAND_LU = 1, MRCM_IFACE_BCR = 2 } mrcm_iface_solver;
+ * blocks of at most 256 unknowns.  AUTO: BCR when it applies, else LAYERED
+ * on 3-D grids, else BAND_LU;
+ * BAND_LU also when the basis Robin parameter is alpha > 1e4 (MRCM_BETA_ALPHA),
+ * where the reduction without pivoting loses accuracy (measured: backward
+ * error 1e-9 at alpha = 1e4, breakdown from 1e6 on). */
+typedef enum {
+  MRCM_IFACE_AUTO = 0,
+  MRCM_IFACE_BAND_LU = 1,
+  MRCM_IFACE_BCR = 2,
+  /* 3-D grids: two-level reduction.  Outer layers of subdomains along the
+   * axis with the most subdomains; the block tridiagonal system of every
+   * outer layer (over inner layers of one row of subdomains, blocks of at
+   * most 256 unknowns) is reduced for all layers at once with its couplings
+   * to the neighbouring layers as extra right-hand sides; the reduced system
+   * over the gaps between outer layers (one dense block per gap) is solved by
+   * block cyclic reduction with recursive two-by-two block inverses.  Exact
+   * elimination, no pivoting. */
+  MRCM_IFACE_LAYERED = 3
+} mrcm_iface_solver;
 
 typedef struct {
   int n_subdomains;        /* m                                              */
@@ -101,7 +118,7 @@ typedef struct {
   double ms_basis, ms_interface, ms_smooth;  /* device time of the last calls */
   double bytes_factor;     /* bytes of cached local factors                  */
   double ms_interface_solve; /* device time of the interface factor + solve  */
-  int interface_solver;    /* MRCM_IFACE_BAND_LU or MRCM_IFACE_BCR in use      */
+  int interface_solver;    /* MRCM_IFACE_BAND_LU, _BCR or _LAYERED in use      */
   int n_smooth_launches;   /* colour-phase launches of the last mrcm_smooth    */
   double ms_basis_kernel;  /* device time of the seed-solve kernel alone       */
   int smooth_threads;      /* threads per box of the smoothing kernels         */
@@ -115,8 +132,9 @@ typedef struct {
                               max_r |G X - r|_r / (|G| |X| + |r|)_r of the
                               interface system (Algorithm 1, Step 5), from the
                               flux and pressure jump moments of the MRCM-O
-                              state; above 1e-8 mrcm_solve_interface's work
-                              raises MRCM_ESINGULAR.  0 if no interface.     */
+                              state; above the check tolerance (default 1e-5,
+                              mrcm_set_interface_check) the solve raises
+                              MRCM_ESINGULAR.  0 if no interface.            */
 } mrcm_stats;
 
 /* Conservation and continuity measures of the current solution (Section 5's
@@ -188,9 +206,9 @@ mrcm_status mrcm_build_basis(mrcm_ctx* ctx);
 
 /* Steps 3-5: interface system and MRCM-O solution (resets smoothing).  The
  * solve is checked on the device: the componentwise backward error of every
- * interface equation (see mrcm_stats.interface_residual) must be <= 1e-8,
- * else the solve's device error is MRCM_ESINGULAR (reported by the next call
- * that reads the device flags).
+ * interface equation (see mrcm_stats.interface_residual) must not exceed
+ * the check tolerance (default 1e-5), else the solve's device error is
+ * MRCM_ESINGULAR (reported by the next call that reads the device flags).
  * Errors: MRCM_ESTATE, MRCM_ESINGULAR, MRCM_EDEVICE. */
 mrcm_status mrcm_solve_interface(mrcm_ctx* ctx);
 
@@ -223,7 +241,7 @@ mrcm_status mrcm_set_smoothing(mrcm_ctx* ctx, int use_graph, int threads_per_box
  * per-phase form.  Default: off.  Errors: MRCM_EINVAL (max_groups < 0). */
 mrcm_status mrcm_set_smoothing_persistent(mrcm_ctx* ctx, int on, int max_groups);
 
-/* Tolerance of the interface solve's check (default 1e-8): the largest
+/* Tolerance of the interface solve's check (default 1e-5): the largest
  * componentwise backward error of the interface equations that
  * mrcm_solve_interface accepts (mrcm_stats.interface_residual); above it the
  * solve reports MRCM_ESINGULAR.  The block cyclic reduction does not pivot,

@@ -13,7 +13,7 @@ from . import _lib
 SPACE = {"const": 0, "linear": 1, "fine": 2}
 PRECISION = {"fp64": 0, "fp32_refine": 1}
 BETA = {"alpha": 0, "const": 1}
-IFACE_SOLVER = {"auto": 0, "band_lu": 1, "bcr": 2}
+IFACE_SOLVER = {"auto": 0, "band_lu": 1, "bcr": 2, "layered": 3}
 BC = {"N": 0, "D": 1}
 
 
@@ -103,7 +103,7 @@ def set_smoothing_persistent(ctx, on=True, max_groups=0):
            _lib.load().mrcm_set_smoothing_persistent(ctx.handle, int(bool(on)), int(max_groups)))
 
 
-def set_interface_check(ctx, tol=1e-8):
+def set_interface_check(ctx, tol=1e-5):
     """Largest accepted componentwise backward error of the interface solve
     (tol <= 0: no check)."""
     _check(ctx, "mrcm_set_interface_check", _lib.load().mrcm_set_interface_check(ctx.handle, float(tol)))

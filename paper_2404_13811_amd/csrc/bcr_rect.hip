@@ -1,0 +1,205 @@
+// Kernels of the two-level interface solver (3-D grids of subdomains whose
+// layers are too large for one dense block): batched products of
+// rectangular blocks on FP64 MFMA, the assembly of the reduced system over
+// the gaps between outer layers from the inner solutions, and the final
+// back substitution into the interface unknowns.  The block elimination
+// itself (inverses, square products, block-vector products) reuses the
+// cyclic-reduction kernels of bcr.hip.
+#include "mrcm_internal.h"
+
+namespace mrcm {
+namespace {
+
+constexpr int RT = 32;  // output tile
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int KC>
+constexpr size_t rect_lds_doubles() {
+  return (size_t)RT * (KC + 1) + (size_t)KC * RT;
+}
+
+// One 32 x 32 tile of C = [C0] + al1 A1 B1 [+ al2 A2 B2] (A: m x k with
+// leading dimension lda, B: k x n with ldb, C and C0: m x n with ldc; all
+// offsets into one base array).  Four waves, a 16 x 16 quadrant each, on
+// FP64 16 x 16 x 4 matrix instructions (lane l: A[l % 16][l / 16],
+// B[l / 16][l % 16], result element r at row 4r + l / 16, column l % 16);
+// k in chunks of KC staged in LDS with the next chunk's loads in flight.
+template <int KC>
+__device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const RectShape& S,
+                                          int tile, double* smem) {
+  constexpr int NA = RT * KC / 256;
+  constexpr int AS = KC + 1;
+  double* As = smem;
+  double* Bs = smem + RT * AS;
+  const int ntc = S.n / RT;
+  const int tr0 = (tile / ntc) * RT, tc0 = (tile % ntc) * RT;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, ln = tid & 63;
+  const int qr = (wv >> 1) * 16, qc = (wv & 1) * 16;
+  const int li = ln & 15, lk = ln >> 4;
+  const int t0 = T.a1 >= 0 ? 0 : 1;
+  const int nterm = (T.a1 >= 0 ? 1 : 0) + (T.a2 >= 0 ? 1 : 0);
+  const int nch = S.k / KC, total = nterm * nch;
+  double va[NA], vb[NA];
+  auto load = [&](int c) {
+    const int term = c < nch ? t0 : 1;
+    const int k0 = (c % nch) * KC;
+    const double* A = base + (term ? T.a2 : T.a1);
+    const double* B = base + (term ? T.b2 : T.b1);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = u * 256 + tid;
+      const int ra = e / KC, ka = e % KC;
+      const int kb = e >> 5, cb = e & 31;
+      va[u] = A[(long long)(tr0 + ra) * S.lda + k0 + ka];
+      vb[u] = B[(long long)(k0 + kb) * S.ldb + tc0 + cb];
+    }
+  };
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  if (total > 0) load(0);
+  for (int c = 0; c < total; ++c) {
+    const double al = (c < nch ? t0 : 1) ? T.al2 : T.al1;
+    if (c) __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = u * 256 + tid;
+      As[(e / KC) * AS + e % KC] = al * va[u];
+      Bs[e] = vb[u];
+    }
+    __syncthreads();
+    if (c + 1 < total) load(c + 1);
+    const double* ap = As + (qr + li) * AS + lk;
+    const double* bq = Bs + lk * RT + qc + li;
+#pragma unroll
+    for (int k = 0; k < KC; k += 8) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], bq[k * RT], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k + 4], bq[(k + 4) * RT], acc1, 0, 0, 0);
+    }
+  }
+  double* C = base + T.c;
+  const double* C0 = T.c0 >= 0 ? base + T.c0 : nullptr;
+  const int col = tc0 + qc + li;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const long long row = tr0 + qr + 4 * r + lk;
+    double v = acc0[r] + acc1[r];
+    if (C0) v += C0[row * S.ldc + col];
+    C[row * S.ldc + col] = v;
+  }
+}
+
+template <int KC>
+__global__ void __launch_bounds__(256) k_rect_gemm(double* __restrict__ base,
+                                                   const BcrGemm* __restrict__ tasks,
+                                                   RectShape S) {
+  extern __shared__ double smem[];
+  const int per = (S.m / RT) * (S.n / RT);
+  const int task = blockIdx.x / per;
+  rect_tile<KC>(base, tasks[task], S, blockIdx.x - task * per, smem);
+}
+
+// base[0, n) = 0; then (second kernel) base[ones[i]] = 1 for the listed
+// offsets (identity blocks and padding, unit right-hand-side columns).
+__global__ void k_fill_zero(double* __restrict__ base, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) base[e] = 0.0;
+}
+__global__ void k_set_ones(double* __restrict__ base, const long long* __restrict__ ones, long long nones) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nones) base[ones[e]] = 1.0;
+}
+
+// Rows of the reduced system: row q of reduced row set `set` is the sum
+// over its cross entries (value at base[cval], row position ypos in the
+// stacked inner solution of its source layer) of value * that solution
+// row; column c of the result goes to base[dst[set] + map(c)], where the
+// column map sends column 0 to the right-hand side and the coupling
+// columns to their reduced blocks.  One workgroup per (row, column chunk).
+__global__ void __launch_bounds__(256) k_lsc_outer_rows(double* __restrict__ base,
+                                                        const LscRow* __restrict__ rows,
+                                                        const long long* __restrict__ ypos,
+                                                        int nrow, int ncol, int width) {
+  const int q = blockIdx.x;
+  if (q >= nrow) return;
+  const LscRow R = rows[q];
+  for (int c = blockIdx.y * blockDim.x + threadIdx.x; c < ncol; c += gridDim.y * blockDim.x) {
+    double acc = 0.0;
+    for (int e = 0; e < width; ++e) {
+      const long long yp = ypos[R.yidx + e];
+      if (yp < 0) continue;
+      acc = fma(base[R.cval + e], base[R.ybase + yp * R.ldy + c], acc);
+    }
+    long long d;
+    if (c == 0) d = R.rhs;
+    else if (c < R.c1) d = R.dst0 >= 0 ? R.dst0 + (c - 1) : -1;
+    else if (c < R.c2) d = R.dst1 >= 0 ? R.dst1 + (c - R.c1) : -1;
+    else d = -1;
+    if (d >= 0) base[d] = acc;
+  }
+}
+
+// X[col] = y[col] - sum_j Y^L[col][j] s[j] - sum_j Y^U[col][j] t[j] for
+// every interface unknown (one wave each): its inner solution row against
+// the reduced solution of the gaps on both sides of its layer.
+__global__ void __launch_bounds__(256) k_lsc_back(const double* __restrict__ base,
+                                                  const LscCol* __restrict__ cols, int n,
+                                                  double* __restrict__ X) {
+  const int wg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int L = threadIdx.x & 63;
+  if (wg >= n) return;
+  const LscCol C = cols[wg];
+  const double* y = base + C.xrow;
+  double acc = 0.0;
+  if (C.sofs >= 0)
+    for (int j = L; j < C.ml; j += 64) acc = fma(y[1 + j], base[C.sofs + j], acc);
+  if (C.tofs >= 0)
+    for (int j = L; j < C.mu; j += 64) acc = fma(y[1 + C.ml + j], base[C.tofs + j], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (L == 0) X[wg] = y[0] - acc;
+}
+
+}  // namespace
+
+hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
+                            hipStream_t s) {
+  if (ntask <= 0) return hipSuccess;
+  if (S.m % RT || S.n % RT || S.k % 32 || S.m <= 0 || S.n <= 0 || S.k <= 0) return hipErrorInvalidValue;
+  const int per = (S.m / RT) * (S.n / RT);
+  if ((long long)ntask * per > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (S.k % 64 == 0) {
+    const size_t lds = sizeof(double) * rect_lds_doubles<64>();
+    hipLaunchKernelGGL(k_rect_gemm<64>, dim3(ntask * per), dim3(256), lds, s, base, tasks, S);
+  } else {
+    const size_t lds = sizeof(double) * rect_lds_doubles<32>();
+    hipLaunchKernelGGL(k_rect_gemm<32>, dim3(ntask * per), dim3(256), lds, s, base, tasks, S);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,
+                            hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n);
+  if (nones > 0)
+    hipLaunchKernelGGL(k_set_ones, dim3((unsigned)((nones + 255) / 256)), dim3(256), 0, s, base, ones,
+                       nones);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos, int nrow,
+                                 int ncol, int width, hipStream_t s) {
+  if (nrow <= 0) return hipSuccess;
+  const int chunks = (ncol + 255) / 256;
+  hipLaunchKernelGGL(k_lsc_outer_rows, dim3(nrow, chunks), dim3(256), 0, s, base, rows, ypos, nrow,
+                     ncol, width);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsc_back(const double* base, const LscCol* cols, int n, double* X, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lsc_back, dim3((n + 3) / 4), dim3(256), 0, s, base, cols, n, X);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

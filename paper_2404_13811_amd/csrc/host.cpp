@@ -102,7 +102,7 @@ struct mrcm_ctx {
   double *bal_partial = nullptr, *bal_out = nullptr;
   unsigned long long *jmax_solve = nullptr, *jmax_bal = nullptr;
   double *cmp_p = nullptr, *cmp_f = nullptr;
-  double iface_check_tol = 1e-8;
+  double iface_check_tol = 1e-5;
 
   // block cyclic reduction of the interface system over the layers of
   // subdomains along the last axis (bcr.hip)
@@ -114,6 +114,10 @@ struct mrcm_ctx {
     int off2 = 0, cnt2 = 0;
   };
   bool use_bcr = false;
+  // two-level solver (iface_lsc.cpp) for 3-D grids whose layers exceed the
+  // cyclic reduction's block
+  Lsc* lsc = nullptr;
+  bool use_lsc = false;
   int bcr_M = 0, bcr_bp = 0;
   std::vector<BcrOp> bcr_ops;
   int *d_row_lvl = nullptr, *d_row_loc = nullptr, *d_col_lvl = nullptr, *d_col_loc = nullptr;
@@ -193,6 +197,15 @@ void dfree(T*& p) {
 
 void drop_graph(mrcm_ctx* c);
 
+// MRCM_IFACE_AUTO takes the pivoted banded LU instead of the cyclic
+// reduction (which does not pivot) for basis Robin parameters alpha above
+// 1e4: measured on the device, the reduction's componentwise backward error
+// grows from 1e-15 at alpha = 1 to 1e-9 at 1e4 and breaks down (5e-3 to 1)
+// from 1e6 on, where the banded LU stays below 1e-6.
+bool auto_prefers_lu(const mrcm_ctx* c) {
+  return c->beta_mode == MRCM_BETA_ALPHA && c->beta_mbf > 1e4;
+}
+
 void free_plan(mrcm_ctx* c) {
   dfree(c->d_obox); dfree(c->d_pbox); dfree(c->d_seeds); dfree(c->d_basis);
   dfree(c->d_seed_off); dfree(c->d_ifc); dfree(c->d_members); dfree(c->d_obox_col);
@@ -214,6 +227,9 @@ void free_plan(mrcm_ctx* c) {
   dfree(c->cmp_p); dfree(c->cmp_f);
   drop_graph(c);
   c->smooth_nt = 0;
+  lsc_destroy(c->lsc);
+  c->lsc = nullptr;
+  c->use_lsc = false;
   c->use_bcr = false;
   c->bcr_ops.clear();
   c->plan_valid = false;
@@ -767,7 +783,9 @@ mrcm_status make_plan(mrcm_ctx* c) {
 
   // interface solver
   c->use_bcr = false;
-  if (c->nX > 0 && c->iface_solver != MRCM_IFACE_BAND_LU) {
+  const bool try_bcr = c->iface_solver == MRCM_IFACE_BCR ||
+                       (c->iface_solver == MRCM_IFACE_AUTO && !auto_prefers_lu(c));
+  if (c->nX > 0 && try_bcr) {
     std::vector<int> rl, ro, cl, co, ls;
     std::vector<long long> inv;
     std::vector<int> invn;
@@ -806,6 +824,29 @@ mrcm_status make_plan(mrcm_ctx* c) {
       HIPCHK(c, up(c->d_bgemv, gv.data(), gv.size() * sizeof(BcrGemv)));
       c->use_bcr = true;
     }
+  }
+  // 3-D: the two-level reduction when the cyclic reduction's layer blocks
+  // are too large (or when asked for)
+  const bool try_lsc = c->iface_solver == MRCM_IFACE_LAYERED ||
+                       (c->iface_solver == MRCM_IFACE_AUTO && !c->use_bcr && !auto_prefers_lu(c));
+  if (c->nX > 0 && c->d == 3 && try_lsc) {
+    std::vector<int> per_side((size_t)nsub * 6, 0);
+    for (int i = 0; i < nsub; ++i)
+      for (int k = c->seed_off[i]; k < c->seed_off[i + 1]; ++k) ++per_side[(size_t)i * 6 + c->seeds[k].side];
+    std::string why;
+    hipError_t he = hipSuccess;
+    c->lsc = lsc_create(g, c->ifc, c->seed_off, per_side, c->nX, &why, &he);
+    if (!c->lsc) {
+      if (he != hipSuccess)
+        return fail(c, he == hipErrorOutOfMemory ? MRCM_ENOMEM : MRCM_EDEVICE, "two-level plan: %s",
+                    why.c_str());
+      if (c->iface_solver == MRCM_IFACE_LAYERED)
+        return fail(c, MRCM_EINVAL, "two-level interface solver: %s", why.c_str());
+    } else {
+      c->use_lsc = true;
+    }
+  } else if (c->iface_solver == MRCM_IFACE_LAYERED && c->nX > 0) {
+    return fail(c, MRCM_EINVAL, "the two-level interface solver needs a 3-D grid");
   }
 #undef ALLOC
   c->plan_valid = true;
@@ -1000,7 +1041,7 @@ mrcm_status mrcm_set_partition(mrcm_ctx* c, const int* sub, int overlap) {
 
 mrcm_status mrcm_set_interface_solver(mrcm_ctx* c, mrcm_iface_solver solver) {
   if (!c) return MRCM_EINVAL;
-  if (solver < MRCM_IFACE_AUTO || solver > MRCM_IFACE_BCR) return fail(c, MRCM_EINVAL, "bad interface solver");
+  if (solver < MRCM_IFACE_AUTO || solver > MRCM_IFACE_LAYERED) return fail(c, MRCM_EINVAL, "bad interface solver");
   c->iface_solver = solver;
   invalidate(c, true);
   return MRCM_OK;
@@ -1019,10 +1060,12 @@ mrcm_status mrcm_set_robin(mrcm_ctx* c, mrcm_beta_mode mode, double mbf, double 
   if (mode != MRCM_BETA_ALPHA && mode != MRCM_BETA_CONST) return fail(c, MRCM_EINVAL, "bad beta mode");
   if (!(mbf > 0.0) || !(smooth > 0.0) || !std::isfinite(mbf) || !std::isfinite(smooth))
     return fail(c, MRCM_EINVAL, "Robin parameters must be positive and finite");
+  const bool lu0 = auto_prefers_lu(c);
   c->beta_mode = mode;
   c->beta_mbf = mbf;
   c->beta_sm = smooth;
-  invalidate(c, false);
+  // the automatic interface solver may change with the parameter
+  invalidate(c, c->iface_solver == MRCM_IFACE_AUTO && lu0 != auto_prefers_lu(c));
   return MRCM_OK;
 }
 
@@ -1120,7 +1163,15 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   if (c->state < 1) return fail(c, MRCM_ESTATE, "basis not built");
   hipStream_t s = c->stream;
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], s));
-  if (c->use_bcr && c->nX > 0) {
+  if (c->use_lsc && c->nX > 0) {
+    // moments straight into the two-level solver's inner blocks and outer
+    // coupling rows (set up first: zeros, identity padding, unit columns)
+    HIPCHK(c, lsc_prepare(c->lsc, s));
+    const BcrMap bm = lsc_map(c->lsc);
+    HIPCHK(c, launch_moments(c->geo, c->d_ifc, (int)c->ifc.size(), c->mom_rows, c->d_basis,
+                             c->d_seed_off, c->tr_u, c->tr_phi, c->tr_beta, c->ubar, c->pibar,
+                             c->AB, c->ldab, c->kl, c->ku, c->rhs, s, &bm));
+  } else if (c->use_bcr && c->nX > 0) {
     // moments straight into the reduction's layer blocks (set up first:
     // zero blocks and vectors, identity on the padding)
     HIPCHK(c, launch_bcr_init(c->bpool, c->bvec, c->d_lsize, c->bcr_M, c->bcr_bp, s));
@@ -1144,7 +1195,9 @@ mrcm_status mrcm_solve_interface(mrcm_ctx* c) {
   }
   if (c->nX > 0) {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[6], s));
-    if (c->use_bcr) {
+    if (c->use_lsc) {
+      HIPCHK(c, lsc_solve(c->lsc, c->X, c->flags, s));
+    } else if (c->use_bcr) {
       mrcm_status st = bcr_solve(c, s);
       if (st) return st;
     } else {
@@ -1661,7 +1714,7 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
   out->n_unknowns = c->nX;
   out->band_kl = c->kl;
   out->band_ku = c->ku;
-  out->interface_solver = c->use_bcr ? MRCM_IFACE_BCR : MRCM_IFACE_BAND_LU;
+  out->interface_solver = c->use_lsc ? MRCM_IFACE_LAYERED : (c->use_bcr ? MRCM_IFACE_BCR : MRCM_IFACE_BAND_LU);
   out->n_local_solves = c->n_local_solves;
   out->bytes_factor = (double)(c->fac_n + c->facp_n) *
                       (c->prec == MRCM_FP32_REFINE ? sizeof(float) : sizeof(double));

@@ -113,7 +113,10 @@ __global__ void __launch_bounds__(256) k_moments(Geo g, const Iface* __restrict_
     if (valid && lg == 0) {
       if (e < ni + nj) {
         if (g.neumann && row == 0) acc = (col == 0) ? 1.0 : 0.0;
-        if (bm.pool) {
+        if (bm.dst) {
+          const long long d = bm.dst[(long long)row * bm.dstw + e];
+          if (d >= 0) bm.pool[d] = acc;
+        } else if (bm.pool) {
           // straight into the reduction's layer blocks: D, L or U of the
           // equation's layer (block tridiagonal by construction)
           const int li = bm.row_lvl[row], lc = bm.col_lvl[col];
@@ -125,7 +128,8 @@ __global__ void __launch_bounds__(256) k_moments(Geo g, const Iface* __restrict_
         }
       } else {
         const double v = (g.neumann && row == 0) ? 0.0 : -acc;
-        if (bm.pool) bm.vec[(long long)bm.row_lvl[row] * bm.bp + bm.row_loc[row]] = v;
+        if (bm.dst) bm.pool[bm.rdst[row]] = v;
+        else if (bm.pool) bm.vec[(long long)bm.row_lvl[row] * bm.bp + bm.row_loc[row]] = v;
         else rhs[row] = v;
       }
     }

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <string>
+#include <vector>
 
 namespace mrcm {
 
@@ -183,6 +185,10 @@ hipError_t launch_smooth32_w(const Geo& g, const Box* boxes, int nmem,
 // reduction: equation row / unknown col to (layer, position), the layer
 // blocks [D | L | U] (M layers, bp x bp each) and right-hand sides.  pool
 // NULL: the row band AB and rhs.
+// With dst set (the two-level solver), entry e of equation row `row` (e
+// counting the seeds of the lower subdomain, then those of the higher one)
+// goes to pool[dst[row * dstw + e]] (skipped where < 0) and the row's
+// right-hand side to pool[rdst[row]].
 struct BcrMap {
   const int* row_lvl = nullptr;
   const int* row_loc = nullptr;
@@ -191,6 +197,9 @@ struct BcrMap {
   int M = 0, bp = 0;
   double* pool = nullptr;
   double* vec = nullptr;
+  const long long* dst = nullptr;
+  const long long* rdst = nullptr;
+  int dstw = 0;
 };
 hipError_t launch_moments(const Geo& g, const Iface* ifc, int nifc, int nrow_max, const Seed* basis,
                           const int* seed_off, const double* tr_u, const double* tr_phi,
@@ -220,6 +229,55 @@ hipError_t launch_bcr_gather(const double* xv, const int* col_lvl, const int* co
                              double* X, hipStream_t s);
 // zero pool and right-hand sides, identity on the padded diagonals of D
 hipError_t launch_bcr_init(double* pool, double* vec, const int* lsize, int M, int bp, hipStream_t s);
+
+// two-level interface solver (bcr_rect.hip, iface_lsc.cpp)
+struct RectShape {
+  int m, n, k;       // C: m x n, A: m x k, B: k x n (multiples of 32)
+  int lda, ldb, ldc;
+};
+// C = [C0] + al1 A1 B1 [+ al2 A2 B2], offsets into one base array (BcrGemm)
+hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
+                            hipStream_t s);
+// base[0, n) = 0, then base[ones[i]] = 1
+hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,
+                            hipStream_t s);
+// One row of the reduced (gap) system: its cross entries (values at
+// base[cval + e], stacked-solution rows ypos[yidx + e], < 0: none) applied
+// to the inner solution of its source layer (base[ybase + row * ldy + c]);
+// column 0 to base[rhs], columns [1, c1) to base[dst0 + c - 1], columns
+// [c1, c2) to base[dst1 + c - c1] (dst < 0: dropped).
+struct LscRow {
+  long long cval, yidx, ybase, rhs, dst0, dst1;
+  int c1, c2, ldy, pad;
+};
+hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos, int nrow,
+                                 int ncol, int width, hipStream_t s);
+// Back substitution of one interface unknown: its inner solution row at
+// base[xrow] (y, then ml coupling columns of s, then mu of t) against the
+// reduced solution (s at base[sofs], t at base[tofs]; < 0: none).
+struct LscCol {
+  long long xrow, sofs, tofs;
+  int ml, mu;
+};
+hipError_t launch_lsc_back(const double* base, const LscCol* cols, int n, double* X, hipStream_t s);
+
+// The two-level solver's plan and device state (iface_lsc.cpp).  seeds_per_side:
+// per subdomain and side (6 entries each) its number of seeds.  Returns
+// null with *err (and *herr for a failed HIP call) when the grid does not
+// suit it.
+struct Lsc;
+Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<int>& seed_off,
+                const std::vector<int>& seeds_per_side, int nX, std::string* err, hipError_t* herr);
+void lsc_destroy(Lsc* L);
+// zero the workspace and set its identity and unit entries (before the moments)
+hipError_t lsc_prepare(Lsc* L, hipStream_t s);
+// where the moments of the interface equations go
+BcrMap lsc_map(const Lsc* L);
+// inner reductions, reduced system, back substitution into X
+hipError_t lsc_solve(Lsc* L, double* X, int* flags, hipStream_t s);
+double lsc_bytes(const Lsc* L);
+// S, Mi, inner block, right-hand sides, gaps, gap block
+void lsc_shape(const Lsc* L, int* out);
 
 // adjoint (adjoint.hip): reverse mode of the 2-D FP64 path
 size_t adj_smooth_lds_bytes(int m0, int m1);

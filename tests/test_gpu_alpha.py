@@ -8,8 +8,10 @@ system is well conditioned.  Large alpha_mbf makes the interface system
 ill-conditioned (condition numbers 1e5 at 1e4, 1e9 to 3e10 at 1e8, measured
 on the oracle's own matrix): a direct FP64 solve then carries a forward
 error of order cond(G) times the unit roundoff, so the bar becomes
-max(1e-10, 1e-14 cond(G)), a backward error of 1e-14 (about 50 ulps: the
-device's cyclic reduction does not pivot) propagated through the system."""
+max(1e-10, 1e-14 cond(G)), a backward error of 1e-14 (about 50 ulps)
+propagated through the system.  Above alpha_mbf = 1e4 the library's
+automatic choice is the pivoted banded LU: the cyclic reduction, which does
+not pivot, breaks down there, and its check reports it."""
 import numpy as np
 import pytest
 
@@ -73,18 +75,19 @@ def _run(wl, precision="fp64", solver="auto", check=None):
     print("  rel L2 p %.3e flux %.3e X %.3e; interface backward error %.2e"
           % (ep, ef, rel(X, rX), st["interface_residual"]), flush=True)
     if check is None:
-        assert st["interface_residual"] <= 1e-8
+        assert st["interface_residual"] <= 1e-5
     return ep, ef, st
 
 
-# Up to alpha_mbf = 1e4 the cyclic reduction (no pivoting) passes the
-# interface check; at 1e8 the pivoted banded LU solves the system (the
-# reduction's breakdown there is detected, see the test below).
+# The library's automatic interface solver: the cyclic reduction up to
+# alpha_mbf = 1e4, the pivoted banded LU above (the reduction's breakdown
+# there is detected, see the test below).
 @pytest.mark.parametrize("alpha", ALPHAS)
 @pytest.mark.parametrize("kind", ["const_l2", "linear_l2_wells"])
 def test_alpha_sweep_fp64(kind, alpha):
     wl = _wl(kind, alpha)
-    ep, ef, _ = _run(wl, solver="band_lu" if alpha > 1e4 else "auto")
+    ep, ef, st = _run(wl)
+    assert st["interface_solver"] == (1 if alpha > 1e4 else 2)
     cond = _interface_condition(wl)
     sp, sf = _oracle_sensitivity(wl)
     bar = max(1e-10, 1e-14 * cond)
@@ -105,13 +108,14 @@ def test_alpha_sweep_fp32_refine(alpha):
 def test_interface_check_flags_an_inaccurate_reduction(kind):
     """alpha_mbf = 1e8 through the cyclic reduction with the check off: the
     measured backward error decides; with the check on, a solve whose
-    backward error exceeds 1e-8 is reported as MRCM_ESINGULAR and one
-    below it passes."""
+    backward error exceeds the default tolerance (1e-5) is reported as
+    MRCM_ESINGULAR and one below it passes."""
     import paper_2404_13811_amd as m
     wl = _wl(kind, 1e8)
     _, _, st = _run(wl, solver="bcr", check=0.0)
     be = st["interface_residual"]
-    if be > 1e-8:
+    print("  cyclic reduction at alpha_mbf 1e8: backward error %.2e" % be, flush=True)
+    if be > 1e-5:
         with pytest.raises(m.MRCMError) as err:
             m.solve_workload(wl, solver="bcr")
         assert err.value.status == 8  # MRCM_ESINGULAR
