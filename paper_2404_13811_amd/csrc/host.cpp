@@ -81,6 +81,8 @@ struct mrcm_ctx {
   size_t lds_factor = 0;
   double *tco = nullptr, *tcp = nullptr;  // block couplings of the boxes / subdomains
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
+  bool d3 = false;                        // 3-D boxes with plane blocks of <= 64 cells
+  size_t lds3_basis = 0, lds3_part = 0, lds3_smooth = 0;
   size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
   size_t lds32_basis = 0, lds32_part = 0, lds32_smooth = 0;
   float *fac32 = nullptr, *facp32 = nullptr;
@@ -663,6 +665,21 @@ mrcm_status make_plan(mrcm_ctx* c) {
   }
   if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024 || 2 * c->lds_part + 16 > 150 * 1024)
     c->wave = false;
+  // 3-D boxes: one wave per box with plane blocks of at most 64 cells
+  c->d3 = c->d == 3;
+  c->lds3_basis = c->lds3_part = c->lds3_smooth = 0;
+  for (int i = 0; i < nsub && c->d3; ++i) {
+    const Box& B = c->obox[i];
+    const Box& P = c->pbox[i];
+    if (B.nb > 64 || P.nb > 64) c->d3 = false;
+    const int m[3] = {B.hi[0] - B.lo[0], B.hi[1] - B.lo[1], B.hi[2] - B.lo[2]};
+    c->lds3_basis = std::max(c->lds3_basis, box3_lds_bytes(m[0], m[1], m[2], std::max(B.nrhs, 1)));
+    c->lds3_smooth = std::max(c->lds3_smooth, box3_lds_bytes(m[0], m[1], m[2], 1));
+    c->lds3_part = std::max(c->lds3_part, box3_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1],
+                                                         P.hi[2] - P.lo[2], 1));
+  }
+  if (c->lds3_basis > 150 * 1024 || c->lds3_smooth > 150 * 1024 || c->lds3_part > 150 * 1024)
+    c->d3 = false;
 
   // interfaces and their test functions
   c->ifc.clear();
@@ -1100,8 +1117,8 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   // mrcm_wait (deferred errors)
   if (!c->flags_zero && !c->deferred) HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   c->flags_zero = false;
-  // K = exp(log K): inside the local kernel on the FP64 wave path
-  if (r32 || !c->wave) HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
+  // K = exp(log K): inside the local kernels on the FP64 wave and 3-D paths
+  if (r32 || !(c->wave || c->d3)) HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
   if (r32) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
@@ -1119,6 +1136,14 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
                              c->tr_phi, c->tr_beta, c->pbar, c->ubar, c->pibar, c->fact,
                              c->flags, std::max(c->lds_basis, 2 * c->lds_part + 16), c->lds_part, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
+  } else if (c->d3) {
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
+    HIPCHK(c, launch_basis3(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->logk, c->beta_mbf, c->fac,
+                            c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 0, c->flags, c->lds3_basis, s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
+    HIPCHK(c, launch_particular3(c->geo, c->d_pbox, c->geo.nsub, c->logk, c->K, c->f, c->bcv,
+                                 c->beta_mbf, c->facp, c->pbar, c->ubar, c->pibar, c->flags,
+                                 c->lds3_part, s));
   } else {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
@@ -1143,6 +1168,11 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
       HIPCHK(c, grow(c->facts, c->fac_n));
       HIPCHK(c, launch_factor_w(c->geo, c->d_obox, c->geo.nsub, c->logk, c->beta_sm, c->facs,
                                 c->facts, c->flags, c->lds_factor, s));
+    } else if (c->d3) {
+      HIPCHK(c, grow(c->facs, c->fac_n));
+      HIPCHK(c, launch_basis3(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->logk, c->beta_sm,
+                              c->facs, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 1, c->flags,
+                              c->lds3_basis, s));
     } else {
       HIPCHK(c, grow(c->facs, c->fac_n));
       HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_sm, c->facs,
@@ -1263,6 +1293,9 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
       HIPCHK(c, launch_smooth_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
                                 c->beta_sm, own ? c->facs : c->fac, own ? c->facts : c->fact,
                                 c->tco, c->scr, p, gflux, c->lds_smooth, nt, s));
+    } else if (c->d3) {
+      HIPCHK(c, launch_smooth3(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv, c->beta_sm,
+                               own ? c->facs : c->fac, p, gflux, c->lds3_smooth, s));
     } else {
       HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
                               c->beta_sm, own ? c->facs : c->fac, nullptr, nullptr, c->scr, p,

@@ -1,0 +1,727 @@
+// One-wavefront-per-box kernels for 3-D local problems whose plane blocks
+// have at most 64 cells (boxes of up to 8 x 8 cells per plane): Steps 1-2
+// (factor of the oversampled box with the seed solves fused into its
+// forward sweep, traces on Gamma_i, basis functions on Omega_i), Step 4
+// (particular problems), Step 6 (factor only) and one colour phase of the
+// smoothing sweep (Steps 6-7).
+//
+// A box is ordered x fastest; a block is one plane of cells (same z), so
+// the matrix is block tridiagonal with dense plane blocks D_j (the x and y
+// couplings of the plane) and diagonal couplings between planes.  The
+// factor is the sequence of block inverses W_j = S_j^{-1} of the block
+// LDL^T recurrence S_j = D_j - t_{j-1} W_{j-1} t_{j-1} (t: plane couplings),
+// computed in registers by Gauss-Jordan elimination with four pivots per
+// step: lane c holds column c of the 64 x 64 block (rows 0..63 in 64
+// registers), the four pivot rows and the four pivot columns of a step are
+// exchanged through LDS, and every lane applies the rank-4 update to its
+// column.  The inverses are symmetric, so lane r also holds row r of W_j,
+// and a block-vector product y = W_j z is one 64-term dot product per lane
+// with z read from LDS (no cross-lane sum).  Solves:
+//   forward   z_j = W_j (b_j + t_{j-1} .* z_{j-1})
+//   backward  x_j = z_j + W_j (t_j .* x_{j+1}).
+// The inverses are stored whole (nb x nb, row-major) in the layout the
+// other 3-D kernels read.
+#include "local_common.h"
+#include "pivot4.h"
+
+namespace mrcm {
+namespace {
+
+constexpr int P3 = 64;   // plane block (padded with the identity)
+constexpr int G3 = 4;    // pivots per Gauss-Jordan step
+
+__device__ __forceinline__ int lane3() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ void wsync3() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Pivot rows of one step (two alternating buffers) and the flag.
+struct __align__(16) Gj3 {
+  double rowb[2][P3 * G3];  // rowb[c * 4 + m] = A[k + m][c]
+  double rows[2][P3 * G3];  // the same, negated for c < k: A[c][k + m]
+  int flag;
+};
+
+// LDS of one box.
+struct Box3 {
+  double* Kt;  // (m0 + 2)(m1 + 2)(m2 + 2) permeabilities, one-cell halo
+  double* Dg;  // ncell diagonal
+  double* Tz;  // ncell coupling to the next plane (0 on the last plane)
+  double* X;   // nrhs x ncell right-hand sides / solutions
+  double* Z;   // nrhs x 64 staging of one block
+  int m0, m1, m2, nc;
+};
+
+__host__ __device__ inline size_t box3_doubles(int m0, int m1, int m2, int nrhs) {
+  const size_t nc = (size_t)m0 * m1 * m2;
+  return (size_t)(m0 + 2) * (m1 + 2) * (m2 + 2) + 2 * nc + (size_t)nrhs * nc + (size_t)nrhs * P3 + 4;
+}
+
+__device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs) {
+  Box3 s;
+  s.m0 = B.hi[0] - B.lo[0];
+  s.m1 = B.hi[1] - B.lo[1];
+  s.m2 = B.hi[2] - B.lo[2];
+  s.nc = s.m0 * s.m1 * s.m2;
+  s.Kt = base;
+  s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2);
+  s.Tz = s.Dg + s.nc;
+  s.X = s.Tz + s.nc;
+  double* z = s.X + (size_t)nrhs * s.nc;
+  // 16-byte alignment for the paired reads of Z
+  const long long off = z - base;
+  s.Z = base + ((off + 1) & ~1LL);
+  return s;
+}
+
+__device__ __forceinline__ double k3(const Box3& s, const Box& B, int x, int y, int z) {
+  return s.Kt[((z - B.lo[2] + 1) * (s.m1 + 2) + (y - B.lo[1] + 1)) * (s.m0 + 2) + (x - B.lo[0] + 1)];
+}
+
+__device__ __forceinline__ double rcp3(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// K tile (log K when LOG: exponentiated here) and the diagonal and plane
+// couplings of the box matrix.
+template <bool LOG>
+__device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const double* Kg, double beta,
+                                          Box3& s) {
+  const int L = lane3();
+  const int W0 = s.m0 + 2, W1 = s.m1 + 2, W2 = s.m2 + 2;
+  const int nt = W0 * W1 * W2;
+  for (int e0 = 0; e0 < nt; e0 += 64 * 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * 64 + L;
+      const int x = B.lo[0] - 1 + e % W0, y = B.lo[1] - 1 + (e / W0) % W1, z = B.lo[2] - 1 + e / (W0 * W1);
+      const bool in = e < nt && x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2];
+      v[u] = in ? Kg[x + g.n[0] * (y + g.n[1] * z)] : (LOG ? 0.0 : 1.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * 64 + L;
+      if (e < nt) s.Kt[e] = LOG ? exp(v[u]) : v[u];
+    }
+  }
+  wsync3();
+  const double ih = rcp3(g.h);
+  for (int loc = L; loc < s.nc; loc += 64) {
+    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + (loc / s.m0) % s.m1, z = B.lo[2] + loc / (s.m0 * s.m1);
+    const int c[3] = {x, y, z};
+    const double kc = k3(s, B, x, y, z);
+    double diag = 0.0, tz = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        int o[3] = {x, y, z};
+        o[a] += sd ? 1 : -1;
+        if (o[a] < 0 || o[a] >= g.n[a]) {
+          if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area * ih;
+          continue;
+        }
+        const double ko = k3(s, B, o[0], o[1], o[2]);
+        const bool inside = o[a] >= B.lo[a] && o[a] < B.hi[a];
+        if (inside) {
+          const double T = g.area * 2.0 * kc * ko * rcp3(kc + ko) * ih;
+          diag += T;
+          if (a == 2 && sd) tz = T;
+        } else {
+          const double bt = robin_beta(g, a, kc, ko, beta);
+          diag += robin_T(g, kc, bt);
+        }
+      }
+    (void)c;
+    s.Dg[loc] = diag;
+    s.Tz[loc] = tz;
+  }
+  wsync3();
+}
+
+// In-plane coupling between plane cells a and a + dx (dx = 1: x, m0: y) of
+// plane j, from the K tile (0 when the neighbour is outside the box).
+__device__ __forceinline__ double tplane(const Geo& g, const Box& B, const Box3& s, int j, int a, int axis) {
+  const int x = B.lo[0] + a % s.m0, y = B.lo[1] + a / s.m0, z = B.lo[2] + j;
+  const int ox = x + (axis == 0), oy = y + (axis == 1);
+  if (ox >= B.hi[0] || oy >= B.hi[1]) return 0.0;
+  const double kc = k3(s, B, x, y, z), ko = k3(s, B, ox, oy, z);
+  return g.area * 2.0 * kc * ko * rcp3(kc + ko) * rcp3(g.h);
+}
+
+// S_j (column c of lane c) = D_j - t_{j-1} W_{j-1} t_{j-1}, w holding
+// W_{j-1} on entry when j > 0; identity outside the nb x nb block.
+__device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s, int j, double w[P3]) {
+  const int c = lane3();
+  const int nb = s.m0 * s.m1, m0 = s.m0;
+  const bool cin = c < nb;
+  const int cc = cin ? c : 0;
+  const double dc = s.Dg[j * nb + cc];
+  const double txm = (cin && cc % m0 > 0) ? tplane(g, B, s, j, cc - 1, 0) : 0.0;
+  const double txp = cin ? tplane(g, B, s, j, cc, 0) : 0.0;
+  const double tym = (cin && cc >= m0) ? tplane(g, B, s, j, cc - m0, 1) : 0.0;
+  const double typ = cin ? tplane(g, B, s, j, cc, 1) : 0.0;
+  const double* tp = s.Tz + (j > 0 ? j - 1 : 0) * nb;
+  const double tcp = (j > 0 && cin) ? tp[cc] : 0.0;
+#pragma unroll
+  for (int i = 0; i < P3; ++i) {
+    // sums of selects: with one-cell-wide planes (m0 = 1) the x and y
+    // neighbours of the block numbering coincide
+    double v = (i == c) ? dc : 0.0;
+    v -= (i == c - 1) ? txm : 0.0;
+    v -= (i == c + 1) ? txp : 0.0;
+    v -= (i == c - m0) ? tym : 0.0;
+    v -= (i == c + m0) ? typ : 0.0;
+    if (j > 0 && i < nb) v = fma(-tp[i] * tcp, w[i], v);
+    w[i] = (i < nb && cin) ? v : (i == c ? 1.0 : 0.0);
+  }
+}
+
+// In-place Gauss-Jordan inverse of the block (column c in lane c), four
+// pivots per step, no pivoting (the Schur complements are SPD).  The
+// pivot columns are not exchanged: for a symmetric matrix under in-place
+// Gauss-Jordan, column k + m equals row k + m on the rows not yet
+// eliminated and its negative on the rows already eliminated (i < k); each
+// lane publishes its pivot-row values twice, as they are (the pivot block
+// and the right-hand side of its own column) and with that sign (the
+// column entries of its row), so the update needs no exchange of columns
+// and no sign logic.  The step index is a template parameter: every
+// register index is a compile-time constant.
+template <int K>
+__device__ __forceinline__ void gj3_step(Gj3& sm, double w[P3], bool& bad) {
+  const int c = lane3();
+  double* rb = sm.rowb[(K / G3) & 1];
+  double* rs = sm.rows[(K / G3) & 1];
+  const int ck = c - K;
+  const bool pc = ck >= 0 && ck < G3;
+  const double sg = c < K ? -1.0 : 1.0;
+  *reinterpret_cast<double2*>(rb + c * G3) = make_double2(w[K], w[K + 1]);
+  *reinterpret_cast<double2*>(rb + c * G3 + 2) = make_double2(w[K + 2], w[K + 3]);
+  *reinterpret_cast<double2*>(rs + c * G3) = make_double2(sg * w[K], sg * w[K + 1]);
+  *reinterpret_cast<double2*>(rs + c * G3 + 2) = make_double2(sg * w[K + 2], sg * w[K + 3]);
+  wsync3();
+  double P[G3][G3], r[G3], v[G3];
+#pragma unroll
+  for (int j = 0; j < G3; ++j)
+#pragma unroll
+    for (int m = 0; m < G3; ++m) P[m][j] = rb[(K + j) * G3 + m];
+#pragma unroll
+  for (int m = 0; m < G3; ++m) r[m] = pc ? (ck == m ? 1.0 : 0.0) : rb[c * G3 + m];
+  const PivBlock<double> q = piv_block(P);
+  bad |= !(q.d0 > 0.0 && q.da > 0.0 && q.s0 > 0.0 && q.ds > 0.0);
+  piv_apply(q, r, v);
+#pragma unroll
+  for (int i = 0; i < P3; ++i) {
+    const double2 c01 = *reinterpret_cast<const double2*>(rs + i * G3);
+    const double2 c23 = *reinterpret_cast<const double2*>(rs + i * G3 + 2);
+    double acc = pc ? 0.0 : w[i];
+    acc = fma(-c01.x, v[0], acc);
+    acc = fma(-c01.y, v[1], acc);
+    acc = fma(-c23.x, v[2], acc);
+    acc = fma(-c23.y, v[3], acc);
+    w[i] = acc;
+  }
+#pragma unroll
+  for (int m = 0; m < G3; ++m) w[K + m] = v[m];
+}
+
+template <int K>
+__device__ __forceinline__ void gj3_steps(int nb, Gj3& sm, double w[P3], bool& bad) {
+  if constexpr (K < P3) {
+    if (K < nb) {
+      gj3_step<K>(sm, w, bad);
+      gj3_steps<K + G3>(nb, sm, w, bad);
+    }
+  }
+}
+
+__device__ __forceinline__ void gj3(int nb, Gj3& sm, double w[P3]) {
+  bool bad = false;
+  gj3_steps<0>(nb, sm, w, bad);
+  if (bad && lane3() == 0) sm.flag |= kFlagNotPD;
+  wsync3();
+}
+
+// y = W z for the staged vector z (64 values in LDS): lane r's dot product
+// of its row of W with z.
+__device__ __forceinline__ double wdot(const double w[P3], const double* z) {
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < P3; i += 2) {
+    const double2 zz = *reinterpret_cast<const double2*>(z + i);
+    a0 = fma(w[i], zz.x, a0);
+    a1 = fma(w[i + 1], zz.y, a1);
+  }
+  return a0 + a1;
+}
+
+// Forward step of block j for all right-hand sides (W_j in w).
+__device__ __forceinline__ void fwd3(const Box3& s, int nb, int j, int nrhs, const double w[P3]) {
+  const int L = lane3();
+  for (int k = 0; k < nrhs; ++k) {
+    double v = 0.0;
+    if (L < nb) {
+      v = s.X[k * s.nc + j * nb + L];
+      if (j > 0) v = fma(s.Tz[(j - 1) * nb + L], s.X[k * s.nc + (j - 1) * nb + L], v);
+    }
+    s.Z[k * P3 + L] = v;
+  }
+  wsync3();
+  for (int k = 0; k < nrhs; ++k) {
+    const double y = wdot(w, s.Z + k * P3);
+    if (L < nb) s.X[k * s.nc + j * nb + L] = y;
+  }
+  wsync3();
+}
+
+// Backward step of block j (W_j in w): x_j += W_j (t_j .* x_{j+1}).
+__device__ __forceinline__ void bwd3(const Box3& s, int nb, int j, int nrhs, const double w[P3]) {
+  const int L = lane3();
+  for (int k = 0; k < nrhs; ++k)
+    s.Z[k * P3 + L] = L < nb ? s.Tz[j * nb + L] * s.X[k * s.nc + (j + 1) * nb + L] : 0.0;
+  wsync3();
+  for (int k = 0; k < nrhs; ++k) {
+    const double y = wdot(w, s.Z + k * P3);
+    if (L < nb) s.X[k * s.nc + j * nb + L] += y;
+  }
+  wsync3();
+}
+
+// Row r (lane r) of the cached symmetric inverse W_j: column r of it.
+__device__ __forceinline__ void load3(const double* Wj, int nb, double w[P3]) {
+  const int r = lane3();
+#pragma unroll
+  for (int i = 0; i < P3; ++i) w[i] = (i < nb && r < nb) ? Wj[i * nb + r] : (i == r ? 1.0 : 0.0);
+}
+
+__device__ __forceinline__ void store3(double* Wj, int nb, const double w[P3]) {
+  const int c = lane3();
+#pragma unroll
+  for (int i = 0; i < P3; ++i)
+    if (i < nb && c < nb) Wj[i * nb + c] = w[i];
+}
+
+// Factor of the box fused with the forward sweep of nrhs right-hand sides
+// already in X; inverses to Wg.
+__device__ __forceinline__ void factor3(const Geo& g, const Box& B, const Box3& s, double* Wg, int nrhs,
+                                        Gj3& sm) {
+  const int nb = s.m0 * s.m1;
+  double w[P3];
+#pragma unroll
+  for (int i = 0; i < P3; ++i) w[i] = 0.0;
+  for (int j = 0; j < s.m2; ++j) {
+    build3(g, B, s, j, w);
+    gj3(nb, sm, w);
+    store3(Wg + (long long)j * nb * nb, nb, w);
+    if (nrhs > 0) fwd3(s, nb, j, nrhs, w);
+  }
+}
+
+__device__ __forceinline__ void backward3(const Box3& s, const double* Wg, int nrhs) {
+  const int nb = s.m0 * s.m1;
+  double w[P3];
+  for (int j = s.m2 - 2; j >= 0; --j) {
+    load3(Wg + (long long)j * nb * nb, nb, w);
+    bwd3(s, nb, j, nrhs, w);
+  }
+}
+
+__device__ __forceinline__ int bloc3(const Box& B, const Box3& s, const int c[3]) {
+  return (c[0] - B.lo[0]) + s.m0 * ((c[1] - B.lo[1]) + s.m1 * (c[2] - B.lo[2]));
+}
+
+__device__ __forceinline__ void omega3(const Geo& g, int sub, int lo[3], int hi[3]) {
+  int r = sub;
+  for (int a = 0; a < 3; ++a) {
+    const int ia = r % g.M[a];
+    r /= g.M[a];
+    lo[a] = ia * g.S[a];
+    hi[a] = lo[a] + g.S[a];
+  }
+}
+
+__device__ __forceinline__ int nbr3(const Geo& g, int sub, int q) {
+  const int a = q >> 1, sd = q & 1;
+  int stride = 1;
+  for (int b = 0; b < a; ++b) stride *= g.M[b];
+  const int ia = (sub / stride) % g.M[a];
+  const int t = ia + (sd ? 1 : -1);
+  if (t < 0 || t >= g.M[a]) return -1;
+  return sub + (sd ? stride : -stride);
+}
+
+__device__ __forceinline__ void face3(const int lo[3], const int hi[3], int q, int t, int c[3]) {
+  const int a = q >> 1, sd = q & 1;
+  int r = t;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (b == a) {
+      c[b] = sd ? hi[b] - 1 : lo[b];
+    } else {
+      const int m = hi[b] - lo[b];
+      c[b] = lo[b] + r % m;
+      r /= m;
+    }
+  }
+}
+
+__device__ __forceinline__ bool inbox3(const Box& B, const int c[3]) {
+  return c[0] >= B.lo[0] && c[0] < B.hi[0] && c[1] >= B.lo[1] && c[1] < B.hi[1] && c[2] >= B.lo[2] &&
+         c[2] < B.hi[2];
+}
+
+// Steps 1-2 on an oversampled box (FO: Step 6, the factor alone).
+template <bool FO>
+__device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
+                                       const double* __restrict__ logK, double beta,
+                                       double* __restrict__ fac, double* __restrict__ Pk,
+                                       double* __restrict__ tr_u, double* __restrict__ tr_phi,
+                                       double* __restrict__ tr_beta, double* dsm, Gj3& sm) {
+  const int L = lane3();
+  const int nrhs = FO ? 0 : B.nrhs;
+  Box3 s = carve3(dsm, B, nrhs);
+  load_box3<true>(g, B, logK, beta, s);
+  for (int e = L; e < nrhs * s.nc; e += 64) s.X[e] = 0.0;
+  wsync3();
+  // T^R times the seed on the cells of its side
+  for (int k = 0; k < nrhs; ++k) {
+    const Seed sd = seeds[B.seed0 + k];
+    const int a = sd.side >> 1, so = sd.side & 1;
+    int nf = 1;
+    for (int b = 0; b < 3; ++b)
+      if (b != a) nf *= B.hi[b] - B.lo[b];
+    for (int t = L; t < nf; t += 64) {
+      int c[3];
+      face3(B.lo, B.hi, sd.side, t, c);
+      int o[3] = {c[0], c[1], c[2]};
+      o[a] += so ? 1 : -1;
+      const double kc = k3(s, B, c[0], c[1], c[2]);
+      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2]), beta);
+      s.X[k * s.nc + bloc3(B, s, c)] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
+    }
+  }
+  wsync3();
+  double* Wg = fac + B.fac;
+  factor3(g, B, s, Wg, nrhs, sm);
+  if (FO) return;
+  backward3(s, Wg, nrhs);
+  int olo[3], ohi[3];
+  omega3(g, B.sub, olo, ohi);
+  const int ncell_o = g.S[0] * g.S[1] * g.S[2];
+  for (int e = L; e < nrhs * ncell_o; e += 64) {
+    const int k = e / ncell_o, t = e % ncell_o;
+    const int c[3] = {olo[0] + t % g.S[0], olo[1] + (t / g.S[0]) % g.S[1], olo[2] + t / (g.S[0] * g.S[1])};
+    Pk[(long long)(B.seed0 + k) * ncell_o + t] = s.X[k * s.nc + bloc3(B, s, c)];
+  }
+  for (int q = 0; q < 6; ++q) {
+    const int a = q >> 1, so = q & 1;
+    int nf = 1;
+    for (int b = 0; b < 3; ++b)
+      if (b != a) nf *= g.S[b];
+    const bool has = nbr3(g, B.sub, q) >= 0;
+    for (int e = L; e < nrhs * nf; e += 64) {
+      const int k = e / nf, t = e % nf;
+      const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
+      if (!has) {
+        tr_u[oidx] = 0.0;
+        tr_phi[oidx] = 0.0;
+        continue;
+      }
+      int c[3];
+      face3(olo, ohi, q, t, c);
+      int o[3] = {c[0], c[1], c[2]};
+      o[a] += so ? 1 : -1;
+      const double kc = k3(s, B, c[0], c[1], c[2]), ko = k3(s, B, o[0], o[1], o[2]);
+      const double Pc = s.X[k * s.nc + bloc3(B, s, c)];
+      const double bt = robin_beta(g, a, kc, ko, beta);
+      double u;
+      if (inbox3(B, o)) {
+        u = g.area * kharm(kc, ko) / g.h * (Pc - s.X[k * s.nc + bloc3(B, s, o)]) / g.area;
+      } else {
+        const Seed sd = seeds[B.seed0 + k];
+        const double lam = (sd.side == q) ? seed_value(g, sd, B.lo, B.hi, c) : 0.0;
+        u = robin_T(g, kc, bt) * (Pc - lam) / g.area;
+      }
+      const double pi = Pc - u * g.h / (2.0 * kc);
+      tr_u[oidx] = u;
+      tr_phi[oidx] = -bt * u + pi;
+      if (k == 0) tr_beta[(long long)B.sub * g.gstride + g.gside_off[q] + t] = bt;
+    }
+  }
+}
+
+// Right-hand side of the physical data (source, boundary conditions).
+__device__ __forceinline__ void physical3(const Geo& g, const Box& B, const Box3& s,
+                                          const double* __restrict__ f,
+                                          const double* __restrict__ bcv, double* X) {
+  const int L = lane3();
+  for (int loc = L; loc < s.nc; loc += 64) {
+    const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
+    const int ci = gcell(g, c);
+    double b = f[ci] * g.vol;
+    const double kc = k3(s, B, c[0], c[1], c[2]);
+    for (int a = 0; a < 3; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int t = c[a] + (sd ? 1 : -1);
+        if (t >= 0 && t < g.n[a]) continue;
+        const int side = 2 * a + sd;
+        const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
+        if (g.bc_type[side]) b += 2.0 * kc * g.area / g.h * val;
+        else b -= g.area * val;
+      }
+    X[loc] = b;
+  }
+}
+
+// Step 4 on a subdomain: K = exp(log K) of its cells (the subdomains cover
+// the grid once; a K that is not finite and positive is flagged).
+__device__ __forceinline__ void particular3(const Geo& g, const Box& B,
+                                            const double* __restrict__ logK, double* __restrict__ K,
+                                            const double* __restrict__ f,
+                                            const double* __restrict__ bcv, double beta,
+                                            double* __restrict__ fac, double* __restrict__ pbar,
+                                            double* __restrict__ ubar, double* __restrict__ pibar,
+                                            double* dsm, Gj3& sm) {
+  const int L = lane3();
+  Box3 s = carve3(dsm, B, 1);
+  load_box3<true>(g, B, logK, beta, s);
+  for (int loc = L; loc < s.nc; loc += 64) {
+    const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
+    const double k = k3(s, B, c[0], c[1], c[2]);
+    if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
+    K[gcell(g, c)] = k;
+  }
+  physical3(g, B, s, f, bcv, s.X);
+  wsync3();
+  double* Wg = fac + B.fac;
+  factor3(g, B, s, Wg, 1, sm);
+  backward3(s, Wg, 1);
+  for (int t = L; t < s.nc; t += 64) pbar[(long long)B.sub * s.nc + t] = s.X[t];
+  for (int q = 0; q < 6; ++q) {
+    const int a = q >> 1, so = q & 1;
+    int nf = 1;
+    for (int b = 0; b < 3; ++b)
+      if (b != a) nf *= g.S[b];
+    const bool has = nbr3(g, B.sub, q) >= 0;
+    for (int t = L; t < nf; t += 64) {
+      const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
+      if (!has) {
+        ubar[oidx] = 0.0;
+        pibar[oidx] = 0.0;
+        continue;
+      }
+      int c[3];
+      face3(B.lo, B.hi, q, t, c);
+      int o[3] = {c[0], c[1], c[2]};
+      o[a] += so ? 1 : -1;
+      const double kc = k3(s, B, c[0], c[1], c[2]);
+      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2]), beta);
+      const double u = robin_T(g, kc, bt) * s.X[bloc3(B, s, c)] / g.area;
+      ubar[oidx] = u;
+      pibar[oidx] = bt * u;
+    }
+  }
+}
+
+// Robin data lambda on face (a, sd) of box cell c from the current state
+// (Section 3 item 3): from the two-point flux across the face when the
+// outside cell lies in the neighbouring subdomain's reach (overlap > 0), or
+// from the neighbour's own Gamma flux and trace (overlap 0).
+__device__ __forceinline__ double lambda3(const Geo& g, const Box& B, const Box3& s,
+                                          const double* __restrict__ p,
+                                          const double* __restrict__ gflux, double beta,
+                                          const int c[3], int a, int sd) {
+  int o[3] = {c[0], c[1], c[2]};
+  o[a] += sd ? 1 : -1;
+  const double kc = k3(s, B, c[0], c[1], c[2]), ko = k3(s, B, o[0], o[1], o[2]);
+  const double bt = robin_beta(g, a, kc, ko, beta);
+  const int ci = gcell(g, c), oi = gcell(g, o);
+  if (g.l > 0) {
+    const double u = g.area * kharm(kc, ko) / g.h * (p[ci] - p[oi]) / g.area;
+    const double pi = p[ci] - u * g.h / (2.0 * kc);
+    return -bt * u + pi;
+  }
+  const int q = 2 * a + sd;
+  const int j = nbr3(g, B.sub, q);
+  int jlo[3], jhi[3];
+  omega3(g, j, jlo, jhi);
+  const int t = side_face_index(g, jlo, jhi, o, a);
+  const double uj = gflux[(long long)j * g.gstride + g.gside_off[q ^ 1] + t];
+  const double pij = p[oi] - uj * g.h / (2.0 * ko);
+  return bt * uj + pij;
+}
+
+// Steps 6-7 for one box: right-hand side from the state, solve with the
+// cached inverses, p on Omega_i and Omega_i's Gamma fluxes.
+__device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double* __restrict__ K,
+                                        const double* __restrict__ f,
+                                        const double* __restrict__ bcv, double beta,
+                                        const double* __restrict__ fac, double* p, double* gflux,
+                                        double* dsm) {
+  const int L = lane3();
+  Box3 s = carve3(dsm, B, 1);
+  load_box3<false>(g, B, K, beta, s);
+  physical3(g, B, s, f, bcv, s.X);
+  wsync3();
+  for (int loc = L; loc < s.nc; loc += 64) {
+    const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
+    double add = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int o = c[a] + (sd ? 1 : -1);
+        if (o < 0 || o >= g.n[a] || (o >= B.lo[a] && o < B.hi[a])) continue;
+        int oc[3] = {c[0], c[1], c[2]};
+        oc[a] = o;
+        const double kc = k3(s, B, c[0], c[1], c[2]);
+        const double bt = robin_beta(g, a, kc, k3(s, B, oc[0], oc[1], oc[2]), beta);
+        add += robin_T(g, kc, bt) * lambda3(g, B, s, p, gflux, beta, c, a, sd);
+      }
+    s.X[loc] += add;
+  }
+  wsync3();
+  const int nb = s.m0 * s.m1;
+  const double* Wg = fac + B.fac;
+  double w[P3];
+  for (int j = 0; j < s.m2; ++j) {
+    load3(Wg + (long long)j * nb * nb, nb, w);
+    fwd3(s, nb, j, 1, w);
+  }
+  backward3(s, Wg, 1);
+  // Gamma fluxes of Omega_i (before p changes: with overlap 0 they read lambda)
+  int olo[3], ohi[3];
+  omega3(g, B.sub, olo, ohi);
+  for (int q = 0; q < 6; ++q) {
+    if (nbr3(g, B.sub, q) < 0) continue;
+    const int a = q >> 1, sd = q & 1;
+    int nf = 1;
+    for (int b = 0; b < 3; ++b)
+      if (b != a) nf *= g.S[b];
+    for (int t = L; t < nf; t += 64) {
+      int c[3];
+      face3(olo, ohi, q, t, c);
+      int o[3] = {c[0], c[1], c[2]};
+      o[a] += sd ? 1 : -1;
+      const double kc = k3(s, B, c[0], c[1], c[2]), ko = k3(s, B, o[0], o[1], o[2]);
+      const double xc = s.X[bloc3(B, s, c)];
+      double u;
+      if (inbox3(B, o)) {
+        u = g.area * kharm(kc, ko) / g.h * (xc - s.X[bloc3(B, s, o)]) / g.area;
+      } else {
+        const double lam = lambda3(g, B, s, p, gflux, beta, c, a, sd);
+        u = robin_T(g, kc, robin_beta(g, a, kc, ko, beta)) * (xc - lam) / g.area;
+      }
+      gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
+    }
+  }
+  wsync3();
+  const int ncell_o = g.S[0] * g.S[1] * g.S[2];
+  for (int t = L; t < ncell_o; t += 64) {
+    const int c[3] = {olo[0] + t % g.S[0], olo[1] + (t / g.S[0]) % g.S[1], olo[2] + t / (g.S[0] * g.S[1])};
+    p[gcell(g, c)] = s.X[bloc3(B, s, c)];
+  }
+}
+
+__global__ void __launch_bounds__(64) k_basis3(Geo g, const Box* __restrict__ boxes,
+                                               const Seed* __restrict__ seeds,
+                                               const double* __restrict__ logK, double beta,
+                                               double* __restrict__ fac, double* __restrict__ Pk,
+                                               double* __restrict__ tr_u, double* __restrict__ tr_phi,
+                                               double* __restrict__ tr_beta, int factor_only,
+                                               int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ Gj3 sm;
+  if (threadIdx.x == 0) sm.flag = 0;
+  const Box B = boxes[blockIdx.x];
+  if (factor_only)
+    basis3<true>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+  else
+    basis3<false>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+  wsync3();
+  if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+__global__ void __launch_bounds__(64) k_particular3(Geo g, const Box* __restrict__ boxes,
+                                                    const double* __restrict__ logK,
+                                                    double* __restrict__ K,
+                                                    const double* __restrict__ f,
+                                                    const double* __restrict__ bcv, double beta,
+                                                    double* __restrict__ fac,
+                                                    double* __restrict__ pbar,
+                                                    double* __restrict__ ubar,
+                                                    double* __restrict__ pibar, int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ Gj3 sm;
+  if (threadIdx.x == 0) sm.flag = 0;
+  wsync3();
+  const Box B = boxes[blockIdx.x];
+  particular3(g, B, logK, K, f, bcv, beta, fac, pbar, ubar, pibar, dsm, sm);
+  wsync3();
+  if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+__global__ void __launch_bounds__(64) k_smooth3(Geo g, const Box* __restrict__ boxes,
+                                                const double* __restrict__ K,
+                                                const double* __restrict__ f,
+                                                const double* __restrict__ bcv, double beta,
+                                                const double* __restrict__ fac,
+                                                double* __restrict__ p, double* __restrict__ gflux) {
+  extern __shared__ __align__(16) double dsm[];
+  const Box B = boxes[blockIdx.x];
+  smooth3(g, B, K, f, bcv, beta, fac, p, gflux, dsm);
+}
+
+template <typename KF>
+hipError_t lds_attr3(KF kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs) {
+  return sizeof(double) * box3_doubles(m0, m1, m2, nrhs);
+}
+
+hipError_t launch_basis3(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
+                         const double* logK, double beta, double* fac, double* Pk, double* tr_u,
+                         double* tr_phi, double* tr_beta, int factor_only, int* flags, size_t lds,
+                         hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = lds_attr3(k_basis3, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_basis3, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, logK, beta, fac, Pk, tr_u,
+                     tr_phi, tr_beta, factor_only, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_particular3(const Geo& g, const Box* boxes, int nbox, const double* logK, double* K,
+                              const double* f, const double* bcv, double beta, double* fac,
+                              double* pbar, double* ubar, double* pibar, int* flags, size_t lds,
+                              hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = lds_attr3(k_particular3, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_particular3, dim3(nbox), dim3(64), lds, s, g, boxes, logK, K, f, bcv, beta, fac,
+                     pbar, ubar, pibar, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double* K, const double* f,
+                          const double* bcv, double beta, const double* fac, double* p, double* gflux,
+                          size_t lds, hipStream_t s) {
+  if (nmem <= 0) return hipSuccess;
+  hipError_t e = lds_attr3(k_smooth3, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_smooth3, dim3(nmem), dim3(64), lds, s, g, boxes, K, f, bcv, beta, fac, p, gflux);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm
