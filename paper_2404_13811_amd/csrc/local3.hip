@@ -217,16 +217,35 @@ __device__ __forceinline__ void gj3_step(Gj3& sm, double w[P3], bool& bad) {
   const PivBlock<double> q = piv_block(P);
   bad |= !(q.d0 > 0.0 && q.da > 0.0 && q.s0 > 0.0 && q.ds > 0.0);
   piv_apply(q, r, v);
+  // rows in groups of RG, the next group's column entries read while the
+  // current group is updated (two register stages)
+  constexpr int RG = 8;
+  double2 cbuf[2][RG][2];
 #pragma unroll
-  for (int i = 0; i < P3; ++i) {
-    const double2 c01 = *reinterpret_cast<const double2*>(rs + i * G3);
-    const double2 c23 = *reinterpret_cast<const double2*>(rs + i * G3 + 2);
-    double acc = pc ? 0.0 : w[i];
-    acc = fma(-c01.x, v[0], acc);
-    acc = fma(-c01.y, v[1], acc);
-    acc = fma(-c23.x, v[2], acc);
-    acc = fma(-c23.y, v[3], acc);
-    w[i] = acc;
+  for (int u = 0; u < RG; ++u) {
+    cbuf[0][u][0] = *reinterpret_cast<const double2*>(rs + u * G3);
+    cbuf[0][u][1] = *reinterpret_cast<const double2*>(rs + u * G3 + 2);
+  }
+#pragma unroll
+  for (int g0 = 0; g0 < P3; g0 += RG) {
+    const int st = (g0 / RG) & 1;
+    if (g0 + RG < P3) {
+#pragma unroll
+      for (int u = 0; u < RG; ++u) {
+        cbuf[st ^ 1][u][0] = *reinterpret_cast<const double2*>(rs + (g0 + RG + u) * G3);
+        cbuf[st ^ 1][u][1] = *reinterpret_cast<const double2*>(rs + (g0 + RG + u) * G3 + 2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+      const int i = g0 + u;
+      double acc = pc ? 0.0 : w[i];
+      acc = fma(-cbuf[st][u][0].x, v[0], acc);
+      acc = fma(-cbuf[st][u][0].y, v[1], acc);
+      acc = fma(-cbuf[st][u][1].x, v[2], acc);
+      acc = fma(-cbuf[st][u][1].y, v[3], acc);
+      w[i] = acc;
+    }
   }
 #pragma unroll
   for (int m = 0; m < G3; ++m) w[K + m] = v[m];
