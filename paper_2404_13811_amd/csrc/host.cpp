@@ -83,6 +83,7 @@ struct mrcm_ctx {
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
   bool d3 = false;                        // 3-D boxes with plane blocks of <= 64 cells
   size_t lds3_basis = 0, lds3_part = 0, lds3_smooth = 0;
+  int nw3_box = 4, nw3_part = 4;  // wavefronts per 3-D box (oversampled, subdomain)
   size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
   size_t lds32_basis = 0, lds32_part = 0, lds32_smooth = 0;
   float *fac32 = nullptr, *facp32 = nullptr;
@@ -668,10 +669,13 @@ mrcm_status make_plan(mrcm_ctx* c) {
   // 3-D boxes: one wave per box with plane blocks of at most 64 cells
   c->d3 = c->d == 3;
   c->lds3_basis = c->lds3_part = c->lds3_smooth = 0;
+  int nb3_box = 1, nb3_part = 1;
   for (int i = 0; i < nsub && c->d3; ++i) {
     const Box& B = c->obox[i];
     const Box& P = c->pbox[i];
     if (B.nb > 64 || P.nb > 64) c->d3 = false;
+    nb3_box = std::max(nb3_box, B.nb);
+    nb3_part = std::max(nb3_part, P.nb);
     const int m[3] = {B.hi[0] - B.lo[0], B.hi[1] - B.lo[1], B.hi[2] - B.lo[2]};
     c->lds3_basis = std::max(c->lds3_basis, box3_lds_bytes(m[0], m[1], m[2], std::max(B.nrhs, 1)));
     c->lds3_smooth = std::max(c->lds3_smooth, box3_lds_bytes(m[0], m[1], m[2], 1));
@@ -680,6 +684,8 @@ mrcm_status make_plan(mrcm_ctx* c) {
   }
   if (c->lds3_basis > 150 * 1024 || c->lds3_smooth > 150 * 1024 || c->lds3_part > 150 * 1024)
     c->d3 = false;
+  c->nw3_box = box3_waves(nb3_box);
+  c->nw3_part = box3_waves(nb3_part);
 
   // interfaces and their test functions
   c->ifc.clear();
@@ -1139,11 +1145,11 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   } else if (c->d3) {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis3(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->logk, c->beta_mbf, c->fac,
-                            c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 0, c->flags, c->lds3_basis, s));
+                            c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 0, c->flags, c->lds3_basis, c->nw3_box, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
     HIPCHK(c, launch_particular3(c->geo, c->d_pbox, c->geo.nsub, c->logk, c->K, c->f, c->bcv,
                                  c->beta_mbf, c->facp, c->pbar, c->ubar, c->pibar, c->flags,
-                                 c->lds3_part, s));
+                                 c->lds3_part, c->nw3_part, s));
   } else {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac,
@@ -1172,7 +1178,7 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
       HIPCHK(c, grow(c->facs, c->fac_n));
       HIPCHK(c, launch_basis3(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->logk, c->beta_sm,
                               c->facs, c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 1, c->flags,
-                              c->lds3_basis, s));
+                              c->lds3_basis, c->nw3_box, s));
     } else {
       HIPCHK(c, grow(c->facs, c->fac_n));
       HIPCHK(c, launch_basis(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->K, c->beta_sm, c->facs,
@@ -1295,7 +1301,7 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
                                 c->tco, c->scr, p, gflux, c->lds_smooth, nt, s));
     } else if (c->d3) {
       HIPCHK(c, launch_smooth3(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv, c->beta_sm,
-                               own ? c->facs : c->fac, p, gflux, c->lds3_smooth, s));
+                               own ? c->facs : c->fac, p, gflux, c->lds3_smooth, c->nw3_box, s));
     } else {
       HIPCHK(c, launch_smooth(c->geo, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
                               c->beta_sm, own ? c->facs : c->fac, nullptr, nullptr, c->scr, p,

@@ -1,48 +1,66 @@
-// One-wavefront-per-box kernels for 3-D local problems whose plane blocks
-// have at most 64 cells (boxes of up to 8 x 8 cells per plane): Steps 1-2
-// (factor of the oversampled box with the seed solves fused into its
-// forward sweep, traces on Gamma_i, basis functions on Omega_i), Step 4
-// (particular problems), Step 6 (factor only) and one colour phase of the
-// smoothing sweep (Steps 6-7).
+// Kernels for 3-D local problems whose plane blocks have at most 64 cells
+// (boxes of up to 8 x 8 cells per plane): Steps 1-2 (factor of the
+// oversampled box with the seed solves fused into its forward sweep, traces
+// on Gamma_i, basis functions on Omega_i), Step 4 (particular problems),
+// Step 6 (factor only) and one colour phase of the smoothing sweep
+// (Steps 6-7).
 //
 // A box is ordered x fastest; a block is one plane of cells (same z), so
 // the matrix is block tridiagonal with dense plane blocks D_j (the x and y
 // couplings of the plane) and diagonal couplings between planes.  The
 // factor is the sequence of block inverses W_j = S_j^{-1} of the block
-// LDL^T recurrence S_j = D_j - t_{j-1} W_{j-1} t_{j-1} (t: plane couplings),
-// computed in registers by Gauss-Jordan elimination with four pivots per
-// step: lane c holds column c of the 64 x 64 block (rows 0..63 in 64
-// registers), the four pivot rows and the four pivot columns of a step are
-// exchanged through LDS, and every lane applies the rank-4 update to its
-// column.  The inverses are symmetric, so lane r also holds row r of W_j,
-// and a block-vector product y = W_j z is one 64-term dot product per lane
-// with z read from LDS (no cross-lane sum).  Solves:
+// LDL^T recurrence S_j = D_j - t_{j-1} W_{j-1} t_{j-1} (t: plane couplings).
+// One workgroup of NW wavefronts works on one box: lane c of wave v holds
+// rows 16v .. 16v + 15 of column c of the 64 x 64 block (padded with the
+// identity) in 16 registers, so a box of 64-cell planes spreads its block
+// over four waves (four SIMDs) and smaller planes take fewer.  W_j is
+// computed in place by Gauss-Jordan elimination with four pivots per step:
+// the wave holding the pivot rows publishes them through LDS, and every
+// lane applies the rank-4 update to its 16 entries.  The inverses are
+// symmetric, so lane c also holds entries 16v .. 16v + 15 of row c, and a
+// block-vector product y = W_j z is a 16-term partial dot product per lane
+// (z read from LDS) summed over the waves through LDS.  Solves:
 //   forward   z_j = W_j (b_j + t_{j-1} .* z_{j-1})
 //   backward  x_j = z_j + W_j (t_j .* x_{j+1}).
-// The inverses are stored whole (nb x nb, row-major) in the layout the
-// other 3-D kernels read.
+// The inverses are stored whole (nb x nb, row-major), the layout the
+// smoothing kernel reads back.
 #include "local_common.h"
 #include "pivot4.h"
 
 namespace mrcm {
 namespace {
 
-constexpr int P3 = 64;   // plane block (padded with the identity)
+constexpr int P3 = 64;   // lanes: columns of the padded plane block
+constexpr int R3 = 16;   // rows of the block per lane
 constexpr int G3 = 4;    // pivots per Gauss-Jordan step
 
 __device__ __forceinline__ int lane3() { return threadIdx.x & 63; }
+// wave index as a scalar, so that branches on it are uniform
+__device__ __forceinline__ int wave3() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-__device__ __forceinline__ void wsync3() {
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-  __builtin_amdgcn_wave_barrier();
+// LDS ordering between the lanes of the box: within one wave a wait for the
+// LDS counter is enough; several waves meet at the workgroup barrier.
+template <int NW>
+__device__ __forceinline__ void bsync() {
+  if constexpr (NW == 1) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
 }
 
-// Pivot rows of one step (two alternating buffers) and the flag.
+// Pivot rows of one step (two alternating buffers) and the flag.  The
+// buffers also hold the per-wave partial sums of the block-vector products
+// (4 right-hand sides x NW waves x 64 lanes <= 1024 values), which never
+// overlap an elimination.
 struct __align__(16) Gj3 {
   double rowb[2][P3 * G3];  // rowb[c * 4 + m] = A[k + m][c]
   double rows[2][P3 * G3];  // the same, negated for c < k: A[c][k + m]
   int flag;
 };
+
+__device__ __forceinline__ double* partials3(Gj3& sm) { return &sm.rowb[0][0]; }
 
 // LDS of one box.
 struct Box3 {
@@ -90,32 +108,32 @@ __device__ __forceinline__ double rcp3(double x) {
 
 // K tile (log K when LOG: exponentiated here) and the diagonal and plane
 // couplings of the box matrix.
-template <bool LOG>
+template <int NW, bool LOG>
 __device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const double* Kg, double beta,
                                           Box3& s) {
-  const int L = lane3();
+  constexpr int NT = 64 * NW;
+  const int tid = threadIdx.x;
   const int W0 = s.m0 + 2, W1 = s.m1 + 2, W2 = s.m2 + 2;
   const int nt = W0 * W1 * W2;
-  for (int e0 = 0; e0 < nt; e0 += 64 * 4) {
+  for (int e0 = 0; e0 < nt; e0 += NT * 4) {
     double v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * 64 + L;
+      const int e = e0 + u * NT + tid;
       const int x = B.lo[0] - 1 + e % W0, y = B.lo[1] - 1 + (e / W0) % W1, z = B.lo[2] - 1 + e / (W0 * W1);
       const bool in = e < nt && x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2];
       v[u] = in ? Kg[x + g.n[0] * (y + g.n[1] * z)] : (LOG ? 0.0 : 1.0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * 64 + L;
+      const int e = e0 + u * NT + tid;
       if (e < nt) s.Kt[e] = LOG ? exp(v[u]) : v[u];
     }
   }
-  wsync3();
+  bsync<NW>();
   const double ih = rcp3(g.h);
-  for (int loc = L; loc < s.nc; loc += 64) {
+  for (int loc = tid; loc < s.nc; loc += NT) {
     const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + (loc / s.m0) % s.m1, z = B.lo[2] + loc / (s.m0 * s.m1);
-    const int c[3] = {x, y, z};
     const double kc = k3(s, B, x, y, z);
     double diag = 0.0, tz = 0.0;
 #pragma unroll
@@ -139,11 +157,10 @@ __device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const doub
           diag += robin_T(g, kc, bt);
         }
       }
-    (void)c;
     s.Dg[loc] = diag;
     s.Tz[loc] = tz;
   }
-  wsync3();
+  bsync<NW>();
 }
 
 // In-plane coupling between plane cells a and a + dx (dx = 1: x, m0: y) of
@@ -156,10 +173,11 @@ __device__ __forceinline__ double tplane(const Geo& g, const Box& B, const Box3&
   return g.area * 2.0 * kc * ko * rcp3(kc + ko) * rcp3(g.h);
 }
 
-// S_j (column c of lane c) = D_j - t_{j-1} W_{j-1} t_{j-1}, w holding
-// W_{j-1} on entry when j > 0; identity outside the nb x nb block.
-__device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s, int j, double w[P3]) {
+// S_j = D_j - t_{j-1} W_{j-1} t_{j-1} (the lane's 16 entries of column c),
+// w holding W_{j-1} on entry when j > 0; identity outside the nb x nb block.
+__device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s, int j, double w[R3]) {
   const int c = lane3();
+  const int r0 = R3 * wave3();
   const int nb = s.m0 * s.m1, m0 = s.m0;
   const bool cin = c < nb;
   const int cc = cin ? c : 0;
@@ -171,7 +189,8 @@ __device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s
   const double* tp = s.Tz + (j > 0 ? j - 1 : 0) * nb;
   const double tcp = (j > 0 && cin) ? tp[cc] : 0.0;
 #pragma unroll
-  for (int i = 0; i < P3; ++i) {
+  for (int ii = 0; ii < R3; ++ii) {
+    const int i = r0 + ii;
     // sums of selects: with one-cell-wide planes (m0 = 1) the x and y
     // neighbours of the block numbering coincide
     double v = (i == c) ? dc : 0.0;
@@ -179,112 +198,172 @@ __device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s
     v -= (i == c + 1) ? txp : 0.0;
     v -= (i == c - m0) ? tym : 0.0;
     v -= (i == c + m0) ? typ : 0.0;
-    if (j > 0 && i < nb) v = fma(-tp[i] * tcp, w[i], v);
-    w[i] = (i < nb && cin) ? v : (i == c ? 1.0 : 0.0);
+    if (j > 0 && i < nb) v = fma(-tp[i] * tcp, w[ii], v);
+    w[ii] = (i < nb && cin) ? v : (i == c ? 1.0 : 0.0);
   }
 }
 
-// In-place Gauss-Jordan inverse of the block (column c in lane c), four
-// pivots per step, no pivoting (the Schur complements are SPD).  The
-// pivot columns are not exchanged: for a symmetric matrix under in-place
-// Gauss-Jordan, column k + m equals row k + m on the rows not yet
-// eliminated and its negative on the rows already eliminated (i < k); each
-// lane publishes its pivot-row values twice, as they are (the pivot block
-// and the right-hand side of its own column) and with that sign (the
-// column entries of its row), so the update needs no exchange of columns
-// and no sign logic.  The step index is a template parameter: every
-// register index is a compile-time constant.
-template <int K>
-__device__ __forceinline__ void gj3_step(Gj3& sm, double w[P3], bool& bad) {
+// In-place Gauss-Jordan inverse of the block, four pivots per step, no
+// pivoting (the Schur complements are SPD).  The pivot columns are not
+// exchanged: for a symmetric matrix under in-place Gauss-Jordan, column
+// k + m equals row k + m on the rows not yet eliminated and its negative
+// on the rows already eliminated (i < k).  The wave holding rows k .. k + 3
+// publishes them twice, as they are (the pivot block and the right-hand
+// side of each lane's column) and with that sign (the column entries of
+// every row), so the update needs no exchange of columns and no sign
+// logic.  The step index is a template parameter: every register index is
+// a compile-time constant.  One barrier per step: a buffer is rewritten two
+// steps later, after every wave has passed the barrier in between.
+template <int NW, int K>
+__device__ __forceinline__ void gj3_step(Gj3& sm, double w[R3], bool& bad) {
+  constexpr int OWN = K / R3, RI = K % R3;
   const int c = lane3();
+  const int wv = wave3();
   double* rb = sm.rowb[(K / G3) & 1];
   double* rs = sm.rows[(K / G3) & 1];
   const int ck = c - K;
   const bool pc = ck >= 0 && ck < G3;
-  const double sg = c < K ? -1.0 : 1.0;
-  *reinterpret_cast<double2*>(rb + c * G3) = make_double2(w[K], w[K + 1]);
-  *reinterpret_cast<double2*>(rb + c * G3 + 2) = make_double2(w[K + 2], w[K + 3]);
-  *reinterpret_cast<double2*>(rs + c * G3) = make_double2(sg * w[K], sg * w[K + 1]);
-  *reinterpret_cast<double2*>(rs + c * G3 + 2) = make_double2(sg * w[K + 2], sg * w[K + 3]);
-  wsync3();
+  // the pivot columns start from zero: a bit mask, not a branch per row
+  const unsigned long long keep = pc ? 0ull : ~0ull;
+  if (wv == OWN) {
+    const double sg = c < K ? -1.0 : 1.0;
+    *reinterpret_cast<double2*>(rb + c * G3) = make_double2(w[RI], w[RI + 1]);
+    *reinterpret_cast<double2*>(rb + c * G3 + 2) = make_double2(w[RI + 2], w[RI + 3]);
+    *reinterpret_cast<double2*>(rs + c * G3) = make_double2(sg * w[RI], sg * w[RI + 1]);
+    *reinterpret_cast<double2*>(rs + c * G3 + 2) = make_double2(sg * w[RI + 2], sg * w[RI + 3]);
+  }
+  bsync<NW>();
   double P[G3][G3], r[G3], v[G3];
 #pragma unroll
   for (int j = 0; j < G3; ++j)
 #pragma unroll
     for (int m = 0; m < G3; ++m) P[m][j] = rb[(K + j) * G3 + m];
-#pragma unroll
-  for (int m = 0; m < G3; ++m) r[m] = pc ? (ck == m ? 1.0 : 0.0) : rb[c * G3 + m];
+  {
+    const double2 r01 = *reinterpret_cast<const double2*>(rb + c * G3);
+    const double2 r23 = *reinterpret_cast<const double2*>(rb + c * G3 + 2);
+    r[0] = pc ? (ck == 0 ? 1.0 : 0.0) : r01.x;
+    r[1] = pc ? (ck == 1 ? 1.0 : 0.0) : r01.y;
+    r[2] = pc ? (ck == 2 ? 1.0 : 0.0) : r23.x;
+    r[3] = pc ? (ck == 3 ? 1.0 : 0.0) : r23.y;
+  }
   const PivBlock<double> q = piv_block(P);
   bad |= !(q.d0 > 0.0 && q.da > 0.0 && q.s0 > 0.0 && q.ds > 0.0);
   piv_apply(q, r, v);
-  // rows in groups of RG, the next group's column entries read while the
-  // current group is updated (two register stages)
-  constexpr int RG = 8;
-  double2 cbuf[2][RG][2];
+  // the lane's rows in groups of RG, the next group's column entries read
+  // while the current group is updated
+  constexpr int RG = 4;
+  const double* rw = rs + R3 * wv * G3;
+  double2 cb[2][RG][2];
 #pragma unroll
   for (int u = 0; u < RG; ++u) {
-    cbuf[0][u][0] = *reinterpret_cast<const double2*>(rs + u * G3);
-    cbuf[0][u][1] = *reinterpret_cast<const double2*>(rs + u * G3 + 2);
+    cb[0][u][0] = *reinterpret_cast<const double2*>(rw + u * G3);
+    cb[0][u][1] = *reinterpret_cast<const double2*>(rw + u * G3 + 2);
   }
 #pragma unroll
-  for (int g0 = 0; g0 < P3; g0 += RG) {
+  for (int g0 = 0; g0 < R3; g0 += RG) {
     const int st = (g0 / RG) & 1;
-    if (g0 + RG < P3) {
+    if (g0 + RG < R3) {
 #pragma unroll
       for (int u = 0; u < RG; ++u) {
-        cbuf[st ^ 1][u][0] = *reinterpret_cast<const double2*>(rs + (g0 + RG + u) * G3);
-        cbuf[st ^ 1][u][1] = *reinterpret_cast<const double2*>(rs + (g0 + RG + u) * G3 + 2);
+        cb[st ^ 1][u][0] = *reinterpret_cast<const double2*>(rw + (g0 + RG + u) * G3);
+        cb[st ^ 1][u][1] = *reinterpret_cast<const double2*>(rw + (g0 + RG + u) * G3 + 2);
       }
     }
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
-      const int i = g0 + u;
-      double acc = pc ? 0.0 : w[i];
-      acc = fma(-cbuf[st][u][0].x, v[0], acc);
-      acc = fma(-cbuf[st][u][0].y, v[1], acc);
-      acc = fma(-cbuf[st][u][1].x, v[2], acc);
-      acc = fma(-cbuf[st][u][1].y, v[3], acc);
-      w[i] = acc;
+      const int ii = g0 + u;
+      double acc = __longlong_as_double(__double_as_longlong(w[ii]) & keep);
+      acc = fma(-cb[st][u][0].x, v[0], acc);
+      acc = fma(-cb[st][u][0].y, v[1], acc);
+      acc = fma(-cb[st][u][1].x, v[2], acc);
+      acc = fma(-cb[st][u][1].y, v[3], acc);
+      w[ii] = acc;
     }
   }
+  if (wv == OWN) {
 #pragma unroll
-  for (int m = 0; m < G3; ++m) w[K + m] = v[m];
+    for (int m = 0; m < G3; ++m) w[RI + m] = v[m];
+  }
 }
 
-template <int K>
-__device__ __forceinline__ void gj3_steps(int nb, Gj3& sm, double w[P3], bool& bad) {
-  if constexpr (K < P3) {
+template <int NW, int K>
+__device__ __forceinline__ void gj3_steps(int nb, Gj3& sm, double w[R3], bool& bad) {
+  if constexpr (K < R3 * NW) {
     if (K < nb) {
-      gj3_step<K>(sm, w, bad);
-      gj3_steps<K + G3>(nb, sm, w, bad);
+      gj3_step<NW, K>(sm, w, bad);
+      gj3_steps<NW, K + G3>(nb, sm, w, bad);
     }
   }
 }
 
-__device__ __forceinline__ void gj3(int nb, Gj3& sm, double w[P3]) {
+template <int NW>
+__device__ __forceinline__ void gj3(int nb, Gj3& sm, double w[R3]) {
   bool bad = false;
-  gj3_steps<0>(nb, sm, w, bad);
-  if (bad && lane3() == 0) sm.flag |= kFlagNotPD;
-  wsync3();
+  gj3_steps<NW, 0>(nb, sm, w, bad);
+  // every wave computed the same pivot blocks
+  if (bad && threadIdx.x == 0) sm.flag |= kFlagNotPD;
+  bsync<NW>();
 }
 
-// y = W z for the staged vector z (64 values in LDS): lane r's dot product
-// of its row of W with z.
-__device__ __forceinline__ double wdot(const double w[P3], const double* z) {
+// The lane's share of y = W z for the staged vector z (64 values in LDS):
+// the 16-term partial dot product of its entries of row c with z.
+__device__ __forceinline__ double wdot3(const double w[R3], const double* z) {
+  const double* zw = z + R3 * wave3();
   double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-  for (int i = 0; i < P3; i += 2) {
-    const double2 zz = *reinterpret_cast<const double2*>(z + i);
-    a0 = fma(w[i], zz.x, a0);
-    a1 = fma(w[i + 1], zz.y, a1);
+  for (int ii = 0; ii < R3; ii += 2) {
+    const double2 zz = *reinterpret_cast<const double2*>(zw + ii);
+    a0 = fma(w[ii], zz.x, a0);
+    a1 = fma(w[ii + 1], zz.y, a1);
   }
   return a0 + a1;
 }
 
+// Y[k][c] (+)= (W Z_k)[c] for the nrhs vectors staged in Z (k-th at Z + 64k),
+// Y[k] at Y + k * ystride; the partial sums of the waves are added through
+// LDS in a fixed order, four right-hand sides at a time.
+template <int NW, bool ACC>
+__device__ __forceinline__ void wmul3(const Box3& s, Gj3& sm, int nb, int nrhs, const double w[R3],
+                                      double* Y, int ystride) {
+  constexpr int NT = 64 * NW;
+  const int c = lane3();
+  if constexpr (NW == 1) {
+    for (int k = 0; k < nrhs; ++k) {
+      const double y = wdot3(w, s.Z + k * P3);
+      if (c < nb) {
+        if (ACC) Y[k * ystride + c] += y;
+        else Y[k * ystride + c] = y;
+      }
+    }
+    bsync<NW>();
+  } else {
+    double* pt = partials3(sm);
+    const int wv = wave3();
+    for (int k0 = 0; k0 < nrhs; k0 += 4) {
+      const int cnt = min(4, nrhs - k0);
+      for (int kk = 0; kk < cnt; ++kk) pt[(kk * NW + wv) * P3 + c] = wdot3(w, s.Z + (k0 + kk) * P3);
+      bsync<NW>();
+      for (int e = threadIdx.x; e < cnt * P3; e += NT) {
+        const int kk = e / P3, L = e % P3;
+        double y = 0.0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) y += pt[(kk * NW + u) * P3 + L];
+        if (L < nb) {
+          if (ACC) Y[(k0 + kk) * ystride + L] += y;
+          else Y[(k0 + kk) * ystride + L] = y;
+        }
+      }
+      bsync<NW>();
+    }
+  }
+}
+
 // Forward step of block j for all right-hand sides (W_j in w).
-__device__ __forceinline__ void fwd3(const Box3& s, int nb, int j, int nrhs, const double w[P3]) {
-  const int L = lane3();
-  for (int k = 0; k < nrhs; ++k) {
+template <int NW>
+__device__ __forceinline__ void fwd3(const Box3& s, Gj3& sm, int nb, int j, int nrhs, const double w[R3]) {
+  constexpr int NT = 64 * NW;
+  for (int e = threadIdx.x; e < nrhs * P3; e += NT) {
+    const int k = e / P3, L = e % P3;
     double v = 0.0;
     if (L < nb) {
       v = s.X[k * s.nc + j * nb + L];
@@ -292,63 +371,66 @@ __device__ __forceinline__ void fwd3(const Box3& s, int nb, int j, int nrhs, con
     }
     s.Z[k * P3 + L] = v;
   }
-  wsync3();
-  for (int k = 0; k < nrhs; ++k) {
-    const double y = wdot(w, s.Z + k * P3);
-    if (L < nb) s.X[k * s.nc + j * nb + L] = y;
-  }
-  wsync3();
+  bsync<NW>();
+  wmul3<NW, false>(s, sm, nb, nrhs, w, s.X + j * nb, s.nc);
 }
 
 // Backward step of block j (W_j in w): x_j += W_j (t_j .* x_{j+1}).
-__device__ __forceinline__ void bwd3(const Box3& s, int nb, int j, int nrhs, const double w[P3]) {
-  const int L = lane3();
-  for (int k = 0; k < nrhs; ++k)
+template <int NW>
+__device__ __forceinline__ void bwd3(const Box3& s, Gj3& sm, int nb, int j, int nrhs, const double w[R3]) {
+  constexpr int NT = 64 * NW;
+  for (int e = threadIdx.x; e < nrhs * P3; e += NT) {
+    const int k = e / P3, L = e % P3;
     s.Z[k * P3 + L] = L < nb ? s.Tz[j * nb + L] * s.X[k * s.nc + (j + 1) * nb + L] : 0.0;
-  wsync3();
-  for (int k = 0; k < nrhs; ++k) {
-    const double y = wdot(w, s.Z + k * P3);
-    if (L < nb) s.X[k * s.nc + j * nb + L] += y;
   }
-  wsync3();
+  bsync<NW>();
+  wmul3<NW, true>(s, sm, nb, nrhs, w, s.X + j * nb, s.nc);
 }
 
-// Row r (lane r) of the cached symmetric inverse W_j: column r of it.
-__device__ __forceinline__ void load3(const double* Wj, int nb, double w[P3]) {
-  const int r = lane3();
+// The lane's entries of the cached symmetric inverse W_j (rows 16v .. of
+// column c; coalesced along the rows).
+__device__ __forceinline__ void load3(const double* Wj, int nb, double w[R3]) {
+  const int c = lane3(), r0 = R3 * wave3();
 #pragma unroll
-  for (int i = 0; i < P3; ++i) w[i] = (i < nb && r < nb) ? Wj[i * nb + r] : (i == r ? 1.0 : 0.0);
+  for (int ii = 0; ii < R3; ++ii) {
+    const int i = r0 + ii;
+    w[ii] = (i < nb && c < nb) ? Wj[i * nb + c] : (i == c ? 1.0 : 0.0);
+  }
 }
 
-__device__ __forceinline__ void store3(double* Wj, int nb, const double w[P3]) {
-  const int c = lane3();
+__device__ __forceinline__ void store3(double* Wj, int nb, const double w[R3]) {
+  const int c = lane3(), r0 = R3 * wave3();
 #pragma unroll
-  for (int i = 0; i < P3; ++i)
-    if (i < nb && c < nb) Wj[i * nb + c] = w[i];
+  for (int ii = 0; ii < R3; ++ii) {
+    const int i = r0 + ii;
+    if (i < nb && c < nb) Wj[i * nb + c] = w[ii];
+  }
 }
 
 // Factor of the box fused with the forward sweep of nrhs right-hand sides
 // already in X; inverses to Wg.
+template <int NW>
 __device__ __forceinline__ void factor3(const Geo& g, const Box& B, const Box3& s, double* Wg, int nrhs,
                                         Gj3& sm) {
   const int nb = s.m0 * s.m1;
-  double w[P3];
+  double w[R3];
 #pragma unroll
-  for (int i = 0; i < P3; ++i) w[i] = 0.0;
+  for (int i = 0; i < R3; ++i) w[i] = 0.0;
   for (int j = 0; j < s.m2; ++j) {
     build3(g, B, s, j, w);
-    gj3(nb, sm, w);
+    gj3<NW>(nb, sm, w);
     store3(Wg + (long long)j * nb * nb, nb, w);
-    if (nrhs > 0) fwd3(s, nb, j, nrhs, w);
+    if (nrhs > 0) fwd3<NW>(s, sm, nb, j, nrhs, w);
   }
 }
 
-__device__ __forceinline__ void backward3(const Box3& s, const double* Wg, int nrhs) {
+template <int NW>
+__device__ __forceinline__ void backward3(const Box3& s, Gj3& sm, const double* Wg, int nrhs) {
   const int nb = s.m0 * s.m1;
-  double w[P3];
+  double w[R3];
   for (int j = s.m2 - 2; j >= 0; --j) {
     load3(Wg + (long long)j * nb * nb, nb, w);
-    bwd3(s, nb, j, nrhs, w);
+    bwd3<NW>(s, sm, nb, j, nrhs, w);
   }
 }
 
@@ -397,18 +479,19 @@ __device__ __forceinline__ bool inbox3(const Box& B, const int c[3]) {
 }
 
 // Steps 1-2 on an oversampled box (FO: Step 6, the factor alone).
-template <bool FO>
+template <int NW, bool FO>
 __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
                                        const double* __restrict__ logK, double beta,
                                        double* __restrict__ fac, double* __restrict__ Pk,
                                        double* __restrict__ tr_u, double* __restrict__ tr_phi,
                                        double* __restrict__ tr_beta, double* dsm, Gj3& sm) {
-  const int L = lane3();
+  constexpr int NT = 64 * NW;
+  const int tid = threadIdx.x;
   const int nrhs = FO ? 0 : B.nrhs;
   Box3 s = carve3(dsm, B, nrhs);
-  load_box3<true>(g, B, logK, beta, s);
-  for (int e = L; e < nrhs * s.nc; e += 64) s.X[e] = 0.0;
-  wsync3();
+  load_box3<NW, true>(g, B, logK, beta, s);
+  for (int e = tid; e < nrhs * s.nc; e += NT) s.X[e] = 0.0;
+  bsync<NW>();
   // T^R times the seed on the cells of its side
   for (int k = 0; k < nrhs; ++k) {
     const Seed sd = seeds[B.seed0 + k];
@@ -416,7 +499,7 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
     int nf = 1;
     for (int b = 0; b < 3; ++b)
       if (b != a) nf *= B.hi[b] - B.lo[b];
-    for (int t = L; t < nf; t += 64) {
+    for (int t = tid; t < nf; t += NT) {
       int c[3];
       face3(B.lo, B.hi, sd.side, t, c);
       int o[3] = {c[0], c[1], c[2]};
@@ -426,15 +509,15 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
       s.X[k * s.nc + bloc3(B, s, c)] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
     }
   }
-  wsync3();
+  bsync<NW>();
   double* Wg = fac + B.fac;
-  factor3(g, B, s, Wg, nrhs, sm);
+  factor3<NW>(g, B, s, Wg, nrhs, sm);
   if (FO) return;
-  backward3(s, Wg, nrhs);
+  backward3<NW>(s, sm, Wg, nrhs);
   int olo[3], ohi[3];
   omega3(g, B.sub, olo, ohi);
   const int ncell_o = g.S[0] * g.S[1] * g.S[2];
-  for (int e = L; e < nrhs * ncell_o; e += 64) {
+  for (int e = tid; e < nrhs * ncell_o; e += NT) {
     const int k = e / ncell_o, t = e % ncell_o;
     const int c[3] = {olo[0] + t % g.S[0], olo[1] + (t / g.S[0]) % g.S[1], olo[2] + t / (g.S[0] * g.S[1])};
     Pk[(long long)(B.seed0 + k) * ncell_o + t] = s.X[k * s.nc + bloc3(B, s, c)];
@@ -445,7 +528,7 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
     for (int b = 0; b < 3; ++b)
       if (b != a) nf *= g.S[b];
     const bool has = nbr3(g, B.sub, q) >= 0;
-    for (int e = L; e < nrhs * nf; e += 64) {
+    for (int e = tid; e < nrhs * nf; e += NT) {
       const int k = e / nf, t = e % nf;
       const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
       if (!has) {
@@ -477,11 +560,11 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
 }
 
 // Right-hand side of the physical data (source, boundary conditions).
+template <int NW>
 __device__ __forceinline__ void physical3(const Geo& g, const Box& B, const Box3& s,
                                           const double* __restrict__ f,
                                           const double* __restrict__ bcv, double* X) {
-  const int L = lane3();
-  for (int loc = L; loc < s.nc; loc += 64) {
+  for (int loc = threadIdx.x; loc < s.nc; loc += 64 * NW) {
     const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
     const int ci = gcell(g, c);
     double b = f[ci] * g.vol;
@@ -501,6 +584,7 @@ __device__ __forceinline__ void physical3(const Geo& g, const Box& B, const Box3
 
 // Step 4 on a subdomain: K = exp(log K) of its cells (the subdomains cover
 // the grid once; a K that is not finite and positive is flagged).
+template <int NW>
 __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
                                             const double* __restrict__ logK, double* __restrict__ K,
                                             const double* __restrict__ f,
@@ -508,28 +592,29 @@ __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
                                             double* __restrict__ fac, double* __restrict__ pbar,
                                             double* __restrict__ ubar, double* __restrict__ pibar,
                                             double* dsm, Gj3& sm) {
-  const int L = lane3();
+  constexpr int NT = 64 * NW;
+  const int tid = threadIdx.x;
   Box3 s = carve3(dsm, B, 1);
-  load_box3<true>(g, B, logK, beta, s);
-  for (int loc = L; loc < s.nc; loc += 64) {
+  load_box3<NW, true>(g, B, logK, beta, s);
+  for (int loc = tid; loc < s.nc; loc += NT) {
     const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
     const double k = k3(s, B, c[0], c[1], c[2]);
     if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
     K[gcell(g, c)] = k;
   }
-  physical3(g, B, s, f, bcv, s.X);
-  wsync3();
+  physical3<NW>(g, B, s, f, bcv, s.X);
+  bsync<NW>();
   double* Wg = fac + B.fac;
-  factor3(g, B, s, Wg, 1, sm);
-  backward3(s, Wg, 1);
-  for (int t = L; t < s.nc; t += 64) pbar[(long long)B.sub * s.nc + t] = s.X[t];
+  factor3<NW>(g, B, s, Wg, 1, sm);
+  backward3<NW>(s, sm, Wg, 1);
+  for (int t = tid; t < s.nc; t += NT) pbar[(long long)B.sub * s.nc + t] = s.X[t];
   for (int q = 0; q < 6; ++q) {
     const int a = q >> 1, so = q & 1;
     int nf = 1;
     for (int b = 0; b < 3; ++b)
       if (b != a) nf *= g.S[b];
     const bool has = nbr3(g, B.sub, q) >= 0;
-    for (int t = L; t < nf; t += 64) {
+    for (int t = tid; t < nf; t += NT) {
       const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
       if (!has) {
         ubar[oidx] = 0.0;
@@ -579,17 +664,19 @@ __device__ __forceinline__ double lambda3(const Geo& g, const Box& B, const Box3
 
 // Steps 6-7 for one box: right-hand side from the state, solve with the
 // cached inverses, p on Omega_i and Omega_i's Gamma fluxes.
+template <int NW>
 __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double* __restrict__ K,
                                         const double* __restrict__ f,
                                         const double* __restrict__ bcv, double beta,
                                         const double* __restrict__ fac, double* p, double* gflux,
-                                        double* dsm) {
-  const int L = lane3();
+                                        double* dsm, Gj3& sm) {
+  constexpr int NT = 64 * NW;
+  const int tid = threadIdx.x;
   Box3 s = carve3(dsm, B, 1);
-  load_box3<false>(g, B, K, beta, s);
-  physical3(g, B, s, f, bcv, s.X);
-  wsync3();
-  for (int loc = L; loc < s.nc; loc += 64) {
+  load_box3<NW, false>(g, B, K, beta, s);
+  physical3<NW>(g, B, s, f, bcv, s.X);
+  bsync<NW>();
+  for (int loc = tid; loc < s.nc; loc += NT) {
     const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
     double add = 0.0;
     for (int a = 0; a < 3; ++a)
@@ -604,15 +691,15 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
       }
     s.X[loc] += add;
   }
-  wsync3();
+  bsync<NW>();
   const int nb = s.m0 * s.m1;
   const double* Wg = fac + B.fac;
-  double w[P3];
+  double w[R3];
   for (int j = 0; j < s.m2; ++j) {
     load3(Wg + (long long)j * nb * nb, nb, w);
-    fwd3(s, nb, j, 1, w);
+    fwd3<NW>(s, sm, nb, j, 1, w);
   }
-  backward3(s, Wg, 1);
+  backward3<NW>(s, sm, Wg, 1);
   // Gamma fluxes of Omega_i (before p changes: with overlap 0 they read lambda)
   int olo[3], ohi[3];
   omega3(g, B.sub, olo, ohi);
@@ -622,7 +709,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
     int nf = 1;
     for (int b = 0; b < 3; ++b)
       if (b != a) nf *= g.S[b];
-    for (int t = L; t < nf; t += 64) {
+    for (int t = tid; t < nf; t += NT) {
       int c[3];
       face3(olo, ohi, q, t, c);
       int o[3] = {c[0], c[1], c[2]};
@@ -639,61 +726,70 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
       gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
     }
   }
-  wsync3();
+  // every Robin datum of the box has been read before p is written
+  bsync<NW>();
   const int ncell_o = g.S[0] * g.S[1] * g.S[2];
-  for (int t = L; t < ncell_o; t += 64) {
+  for (int t = tid; t < ncell_o; t += NT) {
     const int c[3] = {olo[0] + t % g.S[0], olo[1] + (t / g.S[0]) % g.S[1], olo[2] + t / (g.S[0] * g.S[1])};
     p[gcell(g, c)] = s.X[bloc3(B, s, c)];
   }
 }
 
-__global__ void __launch_bounds__(64) k_basis3(Geo g, const Box* __restrict__ boxes,
-                                               const Seed* __restrict__ seeds,
-                                               const double* __restrict__ logK, double beta,
-                                               double* __restrict__ fac, double* __restrict__ Pk,
-                                               double* __restrict__ tr_u, double* __restrict__ tr_phi,
-                                               double* __restrict__ tr_beta, int factor_only,
-                                               int* flags) {
+// Register budget for three resident boxes per CU (their LDS allows no
+// more): at most 168 registers per lane.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_basis3(Geo g, const Box* __restrict__ boxes,
+                                                    const Seed* __restrict__ seeds,
+                                                    const double* __restrict__ logK, double beta,
+                                                    double* __restrict__ fac, double* __restrict__ Pk,
+                                                    double* __restrict__ tr_u,
+                                                    double* __restrict__ tr_phi,
+                                                    double* __restrict__ tr_beta, int factor_only,
+                                                    int* flags) {
   extern __shared__ __align__(16) double dsm[];
   __shared__ Gj3 sm;
   if (threadIdx.x == 0) sm.flag = 0;
+  bsync<NW>();
   const Box B = boxes[blockIdx.x];
   if (factor_only)
-    basis3<true>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+    basis3<NW, true>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
   else
-    basis3<false>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
-  wsync3();
+    basis3<NW, false>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+  bsync<NW>();
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-__global__ void __launch_bounds__(64) k_particular3(Geo g, const Box* __restrict__ boxes,
-                                                    const double* __restrict__ logK,
-                                                    double* __restrict__ K,
-                                                    const double* __restrict__ f,
-                                                    const double* __restrict__ bcv, double beta,
-                                                    double* __restrict__ fac,
-                                                    double* __restrict__ pbar,
-                                                    double* __restrict__ ubar,
-                                                    double* __restrict__ pibar, int* flags) {
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_particular3(Geo g, const Box* __restrict__ boxes,
+                                                         const double* __restrict__ logK,
+                                                         double* __restrict__ K,
+                                                         const double* __restrict__ f,
+                                                         const double* __restrict__ bcv, double beta,
+                                                         double* __restrict__ fac,
+                                                         double* __restrict__ pbar,
+                                                         double* __restrict__ ubar,
+                                                         double* __restrict__ pibar, int* flags) {
   extern __shared__ __align__(16) double dsm[];
   __shared__ Gj3 sm;
   if (threadIdx.x == 0) sm.flag = 0;
-  wsync3();
+  bsync<NW>();
   const Box B = boxes[blockIdx.x];
-  particular3(g, B, logK, K, f, bcv, beta, fac, pbar, ubar, pibar, dsm, sm);
-  wsync3();
+  particular3<NW>(g, B, logK, K, f, bcv, beta, fac, pbar, ubar, pibar, dsm, sm);
+  bsync<NW>();
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-__global__ void __launch_bounds__(64) k_smooth3(Geo g, const Box* __restrict__ boxes,
-                                                const double* __restrict__ K,
-                                                const double* __restrict__ f,
-                                                const double* __restrict__ bcv, double beta,
-                                                const double* __restrict__ fac,
-                                                double* __restrict__ p, double* __restrict__ gflux) {
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_smooth3(Geo g, const Box* __restrict__ boxes,
+                                                     const double* __restrict__ K,
+                                                     const double* __restrict__ f,
+                                                     const double* __restrict__ bcv, double beta,
+                                                     const double* __restrict__ fac,
+                                                     double* __restrict__ p, double* __restrict__ gflux) {
   extern __shared__ __align__(16) double dsm[];
+  __shared__ Gj3 sm;
   const Box B = boxes[blockIdx.x];
-  smooth3(g, B, K, f, bcv, beta, fac, p, gflux, dsm);
+  smooth3<NW>(g, B, K, f, bcv, beta, fac, p, gflux, dsm, sm);
 }
 
 template <typename KF>
@@ -709,38 +805,63 @@ size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs) {
   return sizeof(double) * box3_doubles(m0, m1, m2, nrhs);
 }
 
+int box3_waves(int nb) { return nb <= R3 ? 1 : nb <= 2 * R3 ? 2 : 4; }
+
+#define MRCM_NW_SWITCH(nw, CALL)      \
+  switch (nw) {                       \
+    case 1: CALL(1); break;           \
+    case 2: CALL(2); break;           \
+    case 4: CALL(4); break;           \
+    default: return hipErrorInvalidValue; \
+  }
+
 hipError_t launch_basis3(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                          const double* logK, double beta, double* fac, double* Pk, double* tr_u,
                          double* tr_phi, double* tr_beta, int factor_only, int* flags, size_t lds,
-                         hipStream_t s) {
+                         int nw, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
-  hipError_t e = lds_attr3(k_basis3, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_basis3, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, logK, beta, fac, Pk, tr_u,
-                     tr_phi, tr_beta, factor_only, flags);
+  hipError_t e = hipSuccess;
+#define MRCM_CALL(NW)                                                                                 \
+  e = lds_attr3(k_basis3<NW>, lds);                                                                   \
+  if (e != hipSuccess) return e;                                                                      \
+  hipLaunchKernelGGL(k_basis3<NW>, dim3(nbox), dim3(64 * NW), lds, s, g, boxes, seeds, logK, beta, fac, \
+                     Pk, tr_u, tr_phi, tr_beta, factor_only, flags)
+  MRCM_NW_SWITCH(nw, MRCM_CALL)
+#undef MRCM_CALL
   return hipGetLastError();
 }
 
 hipError_t launch_particular3(const Geo& g, const Box* boxes, int nbox, const double* logK, double* K,
                               const double* f, const double* bcv, double beta, double* fac,
-                              double* pbar, double* ubar, double* pibar, int* flags, size_t lds,
+                              double* pbar, double* ubar, double* pibar, int* flags, size_t lds, int nw,
                               hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
-  hipError_t e = lds_attr3(k_particular3, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_particular3, dim3(nbox), dim3(64), lds, s, g, boxes, logK, K, f, bcv, beta, fac,
-                     pbar, ubar, pibar, flags);
+  hipError_t e = hipSuccess;
+#define MRCM_CALL(NW)                                                                                \
+  e = lds_attr3(k_particular3<NW>, lds);                                                             \
+  if (e != hipSuccess) return e;                                                                     \
+  hipLaunchKernelGGL(k_particular3<NW>, dim3(nbox), dim3(64 * NW), lds, s, g, boxes, logK, K, f, bcv, \
+                     beta, fac, pbar, ubar, pibar, flags)
+  MRCM_NW_SWITCH(nw, MRCM_CALL)
+#undef MRCM_CALL
   return hipGetLastError();
 }
 
 hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double* K, const double* f,
                           const double* bcv, double beta, const double* fac, double* p, double* gflux,
-                          size_t lds, hipStream_t s) {
+                          size_t lds, int nw, hipStream_t s) {
   if (nmem <= 0) return hipSuccess;
-  hipError_t e = lds_attr3(k_smooth3, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_smooth3, dim3(nmem), dim3(64), lds, s, g, boxes, K, f, bcv, beta, fac, p, gflux);
+  hipError_t e = hipSuccess;
+#define MRCM_CALL(NW)                                                                                   \
+  e = lds_attr3(k_smooth3<NW>, lds);                                                                    \
+  if (e != hipSuccess) return e;                                                                        \
+  hipLaunchKernelGGL(k_smooth3<NW>, dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv, beta, fac, p, \
+                     gflux)
+  MRCM_NW_SWITCH(nw, MRCM_CALL)
+#undef MRCM_CALL
   return hipGetLastError();
 }
+
+#undef MRCM_NW_SWITCH
 
 }  // namespace mrcm

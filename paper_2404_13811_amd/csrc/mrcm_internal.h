@@ -162,21 +162,23 @@ hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const SmoothPhases
 
 // one-wavefront-per-box 3-D kernels (local3.hip), plane blocks of <= 64 cells
 size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs);
+// wavefronts per box for plane blocks of nb cells (1, 2 or 4)
+int box3_waves(int nb);
 // Steps 1-2 (factor_only: Step 6) on oversampled boxes; reads log K
 hipError_t launch_basis3(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                          const double* logK, double beta, double* fac, double* Pk, double* tr_u,
                          double* tr_phi, double* tr_beta, int factor_only, int* flags, size_t lds,
-                         hipStream_t s);
+                         int nw, hipStream_t s);
 // Step 4 on the subdomains; writes K = exp(log K) (kFlagBadK where not
 // finite and positive)
 hipError_t launch_particular3(const Geo& g, const Box* boxes, int nbox, const double* logK, double* K,
                               const double* f, const double* bcv, double beta, double* fac,
-                              double* pbar, double* ubar, double* pibar, int* flags, size_t lds,
+                              double* pbar, double* ubar, double* pibar, int* flags, size_t lds, int nw,
                               hipStream_t s);
 // one colour phase of the smoothing sweep (boxes in colour order)
 hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double* K, const double* f,
                           const double* bcv, double beta, const double* fac, double* p, double* gflux,
-                          size_t lds, hipStream_t s);
+                          size_t lds, int nw, hipStream_t s);
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);
