@@ -35,6 +35,16 @@ constexpr int R3 = 16;   // rows of the block per lane
 constexpr int G3 = 4;    // pivots per Gauss-Jordan step
 
 __device__ __forceinline__ int lane3() { return threadIdx.x & 63; }
+
+// The lane index recomputed where it is used: the unrolled elimination
+// steps would otherwise each get lane-dependent constants (pivot-column
+// masks, unit right-hand sides) computed up front and kept in scratch
+// memory for the whole elimination.
+__device__ __forceinline__ int lane3_here() {
+  int v;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+  return v;
+}
 // wave index as a scalar, so that branches on it are uniform
 __device__ __forceinline__ int wave3() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
@@ -217,7 +227,7 @@ __device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s
 template <int NW, int K>
 __device__ __forceinline__ void gj3_step(Gj3& sm, double w[R3], bool& bad) {
   constexpr int OWN = K / R3, RI = K % R3;
-  const int c = lane3();
+  const int c = lane3_here();
   const int wv = wave3();
   double* rb = sm.rowb[(K / G3) & 1];
   double* rs = sm.rows[(K / G3) & 1];
