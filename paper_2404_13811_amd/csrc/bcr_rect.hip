@@ -10,38 +10,41 @@
 namespace mrcm {
 namespace {
 
-constexpr int RT = 32;  // output tile
-
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <int KC>
+template <int TM, int TN, int KC>
 constexpr size_t rect_lds_doubles() {
-  return (size_t)RT * (KC + 1) + (size_t)KC * RT;
+  return (size_t)TM * (KC + 1) + (size_t)KC * TN;
 }
 
-// One 32 x 32 tile of C = [C0] + al1 A1 B1 [+ al2 A2 B2] (A: m x k with
+// One TM x TN tile of C = [C0] + al1 A1 B1 [+ al2 A2 B2] (A: m x k with
 // leading dimension lda, B: k x n with ldb, C and C0: m x n with ldc; all
-// offsets into one base array).  Four waves, a 16 x 16 quadrant each, on
-// FP64 16 x 16 x 4 matrix instructions (lane l: A[l % 16][l / 16],
-// B[l / 16][l % 16], result element r at row 4r + l / 16, column l % 16);
-// k in chunks of KC staged in LDS with the next chunk's loads in flight.
-template <int KC>
+// offsets into one base array).  Four waves in a 2 x 2 arrangement, each a
+// (TM/2) x (TN/2) quadrant of 16 x 16 blocks on FP64 16 x 16 x 4 matrix
+// instructions (lane l: A[l % 16][l / 16], B[l / 16][l % 16], result element
+// r at row 4r + l / 16, column l % 16); k in chunks of KC staged in LDS with
+// the next chunk's loads in flight.  A wave of a 64 x 64 tile reuses each
+// operand it reads from LDS for two instructions.
+template <int TM, int TN, int KC>
 __device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const RectShape& S,
                                           int tile, double* smem) {
-  constexpr int NA = RT * KC / 256;
+  constexpr int NA = TM * KC / 256, NB = KC * TN / 256;
   constexpr int AS = KC + 1;
+  constexpr int BM = TM / 32, BN = TN / 32;  // 16 x 16 blocks per wave
+  // one block per wave: two accumulators on alternate k steps
+  constexpr int NACC = BM * BN == 1 ? 2 : 1;
   double* As = smem;
-  double* Bs = smem + RT * AS;
-  const int ntc = S.n / RT;
-  const int tr0 = (tile / ntc) * RT, tc0 = (tile % ntc) * RT;
+  double* Bs = smem + TM * AS;
+  const int ntc = S.n / TN;
+  const int tr0 = (tile / ntc) * TM, tc0 = (tile % ntc) * TN;
   const int tid = threadIdx.x;
   const int wv = tid >> 6, ln = tid & 63;
-  const int qr = (wv >> 1) * 16, qc = (wv & 1) * 16;
+  const int qr = (wv >> 1) * (TM / 2), qc = (wv & 1) * (TN / 2);
   const int li = ln & 15, lk = ln >> 4;
   const int t0 = T.a1 >= 0 ? 0 : 1;
   const int nterm = (T.a1 >= 0 ? 1 : 0) + (T.a2 >= 0 ? 1 : 0);
   const int nch = S.k / KC, total = nterm * nch;
-  double va[NA], vb[NA];
+  double va[NA], vb[NB];
   auto load = [&](int c) {
     const int term = c < nch ? t0 : 1;
     const int k0 = (c % nch) * KC;
@@ -50,13 +53,21 @@ __device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const 
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int e = u * 256 + tid;
-      const int ra = e / KC, ka = e % KC;
-      const int kb = e >> 5, cb = e & 31;
-      va[u] = A[(long long)(tr0 + ra) * S.lda + k0 + ka];
-      vb[u] = B[(long long)(k0 + kb) * S.ldb + tc0 + cb];
+      va[u] = A[(long long)(tr0 + e / KC) * S.lda + k0 + e % KC];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = u * 256 + tid;
+      vb[u] = B[(long long)(k0 + e / TN) * S.ldb + tc0 + e % TN];
     }
   };
-  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  dbl4 acc[NACC][BM][BN];
+#pragma unroll
+  for (int h = 0; h < NACC; ++h)
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) acc[h][i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   if (total > 0) load(0);
   for (int c = 0; c < total; ++c) {
     const double al = (c < nch ? t0 : 1) ? T.al2 : T.al1;
@@ -65,38 +76,52 @@ __device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const 
     for (int u = 0; u < NA; ++u) {
       const int e = u * 256 + tid;
       As[(e / KC) * AS + e % KC] = al * va[u];
-      Bs[e] = vb[u];
     }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) Bs[u * 256 + tid] = vb[u];
     __syncthreads();
     if (c + 1 < total) load(c + 1);
-    const double* ap = As + (qr + li) * AS + lk;
-    const double* bq = Bs + lk * RT + qc + li;
 #pragma unroll
-    for (int k = 0; k < KC; k += 8) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], bq[k * RT], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k + 4], bq[(k + 4) * RT], acc1, 0, 0, 0);
+    for (int k = 0; k < KC; k += 4) {
+      double a[BM], b[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) a[i] = As[(qr + 16 * i + li) * AS + k + lk];
+#pragma unroll
+      for (int j = 0; j < BN; ++j) b[j] = Bs[(k + lk) * TN + qc + 16 * j + li];
+      const int h = NACC == 2 ? (k / 4) & 1 : 0;
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          acc[h][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[h][i][j], 0, 0, 0);
     }
   }
   double* C = base + T.c;
   const double* C0 = T.c0 >= 0 ? base + T.c0 : nullptr;
-  const int col = tc0 + qc + li;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const long long row = tr0 + qr + 4 * r + lk;
-    double v = acc0[r] + acc1[r];
-    if (C0) v += C0[row * S.ldc + col];
-    C[row * S.ldc + col] = v;
-  }
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      const int col = tc0 + qc + 16 * j + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long row = tr0 + qr + 16 * i + 4 * r + lk;
+        double v = acc[0][i][j][r];
+        if (NACC == 2) v += acc[NACC - 1][i][j][r];
+        if (C0) v += C0[row * S.ldc + col];
+        C[row * S.ldc + col] = v;
+      }
+    }
 }
 
-template <int KC>
+template <int TM, int TN, int KC>
 __global__ void __launch_bounds__(256) k_rect_gemm(double* __restrict__ base,
                                                    const BcrGemm* __restrict__ tasks,
                                                    RectShape S) {
   extern __shared__ double smem[];
-  const int per = (S.m / RT) * (S.n / RT);
+  const int per = (S.m / TM) * (S.n / TN);
   const int task = blockIdx.x / per;
-  rect_tile<KC>(base, tasks[task], S, blockIdx.x - task * per, smem);
+  rect_tile<TM, TN, KC>(base, tasks[task], S, blockIdx.x - task * per, smem);
 }
 
 // base[0, n) = 0; then (second kernel) base[ones[i]] = 1 for the listed
@@ -161,20 +186,31 @@ __global__ void __launch_bounds__(256) k_lsc_back(const double* __restrict__ bas
 
 }  // namespace
 
+namespace {
+template <int TM, int TN, int KC>
+hipError_t rect_launch(double* base, const BcrGemm* tasks, int ntask, const RectShape& S, hipStream_t s) {
+  const long long per = (long long)(S.m / TM) * (S.n / TN);
+  if ((long long)ntask * per > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * rect_lds_doubles<TM, TN, KC>();
+  hipLaunchKernelGGL((k_rect_gemm<TM, TN, KC>), dim3((unsigned)(ntask * per)), dim3(256), lds, s, base,
+                     tasks, S);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
                             hipStream_t s) {
   if (ntask <= 0) return hipSuccess;
-  if (S.m % RT || S.n % RT || S.k % 32 || S.m <= 0 || S.n <= 0 || S.k <= 0) return hipErrorInvalidValue;
-  const int per = (S.m / RT) * (S.n / RT);
-  if ((long long)ntask * per > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (S.k % 64 == 0) {
-    const size_t lds = sizeof(double) * rect_lds_doubles<64>();
-    hipLaunchKernelGGL(k_rect_gemm<64>, dim3(ntask * per), dim3(256), lds, s, base, tasks, S);
-  } else {
-    const size_t lds = sizeof(double) * rect_lds_doubles<32>();
-    hipLaunchKernelGGL(k_rect_gemm<32>, dim3(ntask * per), dim3(256), lds, s, base, tasks, S);
-  }
-  return hipGetLastError();
+  if (S.m % 32 || S.n % 32 || S.k % 32 || S.m <= 0 || S.n <= 0 || S.k <= 0) return hipErrorInvalidValue;
+  // 64 x 64 tiles where they divide the product and still give every CU two
+  // workgroups (half the operand traffic per multiply-add of 32 x 32 tiles);
+  // 32 x 32 tiles otherwise.  Measured on the 3-D workload's reduced
+  // system: 128 x 128 tiles (one workgroup per CU) and 96 x 96 tiles for the
+  // inner products were no faster.
+  if (S.m % 64 == 0 && S.n % 64 == 0 && (long long)ntask * (S.m / 64) * (S.n / 64) >= 512)
+    return rect_launch<64, 64, 32>(base, tasks, ntask, S, s);
+  if (S.k % 64 == 0) return rect_launch<32, 32, 64>(base, tasks, ntask, S, s);
+  return rect_launch<32, 32, 32>(base, tasks, ntask, S, s);
 }
 
 hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,
