@@ -167,47 +167,61 @@ __global__ void __launch_bounds__(64) k_jumps(Geo g, const Iface* __restrict__ i
     if (b != F.axis) nf *= g.S[b];
   const long long bi = (long long)F.i * g.gstride + g.gside_off[qi];
   const long long bj = (long long)F.j * g.gstride + g.gside_off[qj];
+  // lanes in NG groups of nf faces when the faces of a side divide the wave:
+  // group q takes the seeds q, q + NG, ... of the two sides (all loads of a
+  // lane independent), group 0 also the jump itself and the particular
+  // solution's terms; otherwise one group strides over the faces
+  const int NG = (nf <= 64 && 64 % nf == 0) ? 64 / nf : 1;
+  const int grp = NG > 1 ? L / nf : 0;
+  const int tl = NG > 1 ? L % nf : L;
+  const int tstep = NG > 1 ? nf : 64;
+  const int ni = tr.X ? tr.seed_off[F.i + 1] - tr.seed_off[F.i] : 0;
+  const int nseed = tr.X ? ni + tr.seed_off[F.j + 1] - tr.seed_off[F.j] : 0;
   double worst[2] = {0.0, 0.0};
   for (int rr = 0; rr < 2 * F.nbasis; ++rr) {
     const int kind = rr / F.nbasis;  // 0 flux, 1 pressure
     const Seed mu = basis[F.basis0 + rr % F.nbasis];
     double m = 0.0, sc = 0.0;
-    for (int t = L; t < nf; t += 64) {
-      int ci[3], cj[3];
+    for (int t = tl; t < nf; t += tstep) {
+      int ci[3];
       side_cell(ilo, ihi, qi, t, ci);
-      side_cell(jlo, jhi, qj, t, cj);
       const double w = g.area * seed_value(g, mu, ilo, ihi, ci);
-      const double ui = gflux[bi + t], uj = gflux[bj + t];
-      double a, b;
-      if (kind == 0) {
-        a = ui;
-        b = uj;
-        m += w * (a + b);
-      } else {
-        const int ii = gcell(g, ci), jj = gcell(g, cj);
-        a = p[ii] - ui * g.h / (2.0 * K[ii]);
-        b = p[jj] - uj * g.h / (2.0 * K[jj]);
-        m += w * (a - b);
+      double a = 0.0, b = 0.0;
+      if (grp == 0) {
+        const double ui = gflux[bi + t], uj = gflux[bj + t];
+        if (kind == 0) {
+          a = ui;
+          b = uj;
+          m += w * (a + b);
+        } else {
+          int cj[3];
+          side_cell(jlo, jhi, qj, t, cj);
+          const int ii = gcell(g, ci), jj = gcell(g, cj);
+          a = p[ii] - ui * g.h / (2.0 * K[ii]);
+          b = p[jj] - uj * g.h / (2.0 * K[jj]);
+          m += w * (a - b);
+        }
       }
       if (tr.X) {
         // every term of the row: the seeds' traces times |X|, the particular
         // solution's trace
         double mag = 0.0;
-        for (int side = 0; side < 2; ++side) {
+        if (grp == 0)
+          mag = fabs(kind == 0 ? tr.ubar[bi + t] : tr.pibar[bi + t]) +
+                fabs(kind == 0 ? tr.ubar[bj + t] : tr.pibar[bj + t]);
+        for (int e = grp; e < nseed; e += NG) {
+          const int side = e >= ni;
           const int sub = side ? F.j : F.i;
-          const long long ob = side ? bj : bi;
+          const int k = tr.seed_off[sub] + (side ? e - ni : e);
           const long long so = (side ? g.gside_off[qj] : g.gside_off[qi]) + t;
-          mag += fabs(kind == 0 ? tr.ubar[ob + t] : tr.pibar[ob + t]);
-          for (int k = tr.seed_off[sub]; k < tr.seed_off[sub + 1]; ++k) {
-            const long long e = (long long)k * g.gstride + so;
-            const double v = kind == 0 ? tr.tr_u[e]
-                                       : tr.tr_beta[(long long)sub * g.gstride + so] * tr.tr_u[e] +
-                                             tr.tr_phi[e];
-            mag += fabs(tr.X[k] * v);
-          }
+          const long long ek = (long long)k * g.gstride + so;
+          const double v = kind == 0 ? tr.tr_u[ek]
+                                     : tr.tr_beta[(long long)sub * g.gstride + so] * tr.tr_u[ek] +
+                                           tr.tr_phi[ek];
+          mag += fabs(tr.X[k] * v);
         }
         sc += fabs(w) * mag;
-      } else {
+      } else if (grp == 0) {
         sc += fabs(w) * (fabs(a) + fabs(b));
       }
     }
