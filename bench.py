@@ -5,19 +5,23 @@ local factorisations and seed solves, particular solves, interface system
 assembly and solve, MRCM-O assembly, N_s smoothing sweeps, pressure and flux
 written to device buffers), with the permeability already resident in HBM.
 
-Workload (default, the largest that runs on one GPU with its oracle in
-minutes): 1024 x 1024 cells, 64 x 64 subdomains of 16 x 16 cells, overlap 4
-(oversampled boxes truncated at the boundary, uneven sizes), piecewise-
-constant interface spaces, binary channel permeability (contrast 1e4),
-p = 1 / 0 on the x sides, alpha = 1, ten smoothing steps.  The 256 x 256
-Gaussian-field workload with piecewise-linear spaces and wells is timed
-beside it, and the batch/adjoint workload (32 fields of 256 x 256).
+Workload (default, the largest single-GPU configuration): the 3-D grid of
+64 x 224 x 80 cells, 4 x 4 x 4-cell subdomains (17,920) with overlap 2
+(8^3-cell oversampled boxes, truncated at the boundary), piecewise-constant
+interface spaces (102,848 interface unknowns), layered log-normal
+permeability (contrast up to 1e6), p = 1 / 0 on the y sides, three smoothing
+steps.  Its flux and pressure are checked against the CPU oracle's solution
+at 4096 seeded sample cells (tests/golden/c4_full_samples.npz, written by the
+oracle); the full oracle solve takes minutes.  Beside it: the 1024 x 1024
+channel workload (64 x 64 subdomains, overlap 4, ten smoothing steps) in
+both precision forms with its full oracle check, the 256 x 256 Gaussian
+workload, and the batch/adjoint workload (32 fields of 256 x 256).
 
-Both precision forms are timed on the same workload: FP32 factors with FP64
-iterative refinement, and FP64.  Each is compared with the CPU FP64 oracle
-(relative L2 of flux and pressure).  The headline value is the faster form
-among those whose flux error is <= 1e-6; when no form was checked or none
-meets it, the value is null and ``target_met`` is false.
+Both precision forms are timed where the library has them (FP32 factors with
+FP64 refinement exist for 2-D boxes only): FP32 with FP64 iterative
+refinement, and FP64.  The headline value is the faster form among those
+whose flux error is <= 1e-6; when no form was checked or none meets it, the
+value is null and ``target_met`` is false.
 """
 import argparse
 import hashlib
@@ -37,6 +41,8 @@ PEAK_HBM = 8.0e12        # B/s
 PEAK_FP64 = 78.6e12      # FLOP/s, vector (= matrix) FP64
 PEAK_FP32 = 157.3e12     # FLOP/s, vector FP32
 FLUX_TOL = 1e-6
+SOLVERS = {1: "band_lu", 2: "block_cyclic_reduction", 3: "two_level_layered_reduction"}
+GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_full_samples.npz")
 
 # HBM bytes per launch of a kernel on a workload, from two rocprofv3 counter
 # passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each counter is
@@ -81,7 +87,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--workload", default="c4")
     ap.add_argument("--overlap", type=int, default=None)
     ap.add_argument("--precision", default="best", choices=["best", "fp64", "fp32_refine"])
     ap.add_argument("--tol", type=float, default=None,
@@ -298,12 +304,19 @@ def boxes(wl):
     return out
 
 
+def block_cells(dims):
+    """Cells of one block of a box: a line (2-D) or a plane (3-D); the
+    half-bandwidth of the box matrix in that ordering."""
+    import numpy as np
+    return int(np.prod(dims[:-1]))
+
+
 def band_bytes(dims, word=8):
-    """Bytes of the band factor of one box in line order: n (b + 1) words,
-    n the cells of the box, b = cells of one line (its half-bandwidth)."""
+    """Bytes of the band factor of one box in block order: n (b + 1) words,
+    n the cells of the box, b = cells of one block (its half-bandwidth)."""
     import numpy as np
     n = int(np.prod(dims))
-    return n * (dims[0] + 1) * word
+    return n * (block_cells(dims) + 1) * word
 
 
 def smoothing_roofline(wl, form, phases, st):
@@ -322,18 +335,21 @@ def smoothing_roofline(wl, form, phases, st):
     per_phase = (factor + state) / 2 ** wl.dim
     per_launch = per_phase * phases_per_launch
     achieved = per_launch / t_launch
-    # what the kernel itself reads: the symmetric block inverses of the
-    # line blocks stored as lower triangles (FP64) or whole (FP32)
+    # what the kernel itself reads: the symmetric block inverses, stored as
+    # lower triangles (2-D FP64) or whole (FP32, and the 3-D plane blocks,
+    # read twice: forward and backward sweep)
     stored = 0
     for dims, _, _ in bx:
-        nb = dims[0]
-        nblk = 1
-        for v in dims[1:]:
-            nblk *= v
+        nb, nblk = block_cells(dims), dims[-1]
+        if wl.dim == 3:
+            stored += (2 * nblk - 1) * nb * nb * word
+            continue
         blk = nb * nb if form == "fp32_refine" else nb * (nb + 1) // 2
         stored += nblk * blk * word * solves
     kern = "k_smooth32" if form == "fp32_refine" else "k_smooth_w"
-    if st["smooth_persistent"]:
+    if wl.dim == 3:
+        kern = "k_smooth3"
+    elif st["smooth_persistent"]:
         kern = "k_smooth_grid"
     return {"kernel": kern, "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
             "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic(kern, wl),
@@ -357,16 +373,22 @@ def local_roofline(wl, form, phases, st):
     flops = 0.0
     band = 0.0
     for dims, nseed, _ in bx:
-        nb, nblk = dims[0], int(np.prod(dims[1:]))
+        nb, nblk = block_cells(dims), dims[-1]
         flops += 2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb * nseed
         n = nb * nblk
         band += n * nb * nb + solves * 4.0 * n * nb * nseed
     nsub = int(np.prod(wl.ncell)) // int(np.prod(S))
-    nb, nblk = S[0], int(np.prod(S[1:]))
-    flops += nsub * (2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb)
-    band += nsub * (nb * nblk * nb * nb + solves * 4.0 * nb * nblk * nb)
+    nb, nblk = block_cells(S), S[-1]
+    part = nsub * (2.0 * nblk * nb ** 3 + solves * 4.0 * nblk * nb * nb)
+    part_band = nsub * (nb * nblk * nb * nb + solves * 4.0 * nb * nblk * nb)
+    if wl.dim == 2:
+        # one launch holds the basis boxes and the particular problems
+        flops += part
+        band += part_band
     peak = PEAK_FP32 if form == "fp32_refine" else PEAK_FP64
     kern = "k_local32" if form == "fp32_refine" else "k_local_w"
+    if wl.dim == 3:
+        kern = "k_basis3"
     return {"kernel": kern, "bound": "alu", "achieved": band / t_basis / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": band / t_basis / peak, "traffic": traffic(kern, wl),
             "band_flop_per_launch": band, "executed_flop_per_launch": flops,
@@ -376,7 +398,7 @@ def local_roofline(wl, form, phases, st):
 def interface_entry(wl, phases, st, dt):
     """The interface solve (Algorithm 1, Step 5), reported on its own."""
     return {"unknowns": st["n_unknowns"],
-            "solver": {1: "band_lu", 2: "block_cyclic_reduction"}.get(st["interface_solver"]),
+            "solver": SOLVERS.get(st["interface_solver"]),
             "ms_assembly_and_solve": round(phases["ms_interface"], 4),
             "ms_solve": round(phases["ms_interface_solve"], 4),
             "share_of_solve": round(phases["ms_interface"] / (dt * 1e3), 3)}
@@ -412,7 +434,8 @@ def cpu_baseline(wl, procs, t_full):
     recipe; aggregate cells per wall second.  The single-process time of the
     full workload (t_full, measured for the error check) is reported beside."""
     import multiprocessing as mp
-    P = procs or os.cpu_count() or 1
+    # the CPUs this process may run on, at most 16 (one GPU's share of a node)
+    P = procs or min(len(os.sched_getaffinity(0)), 16) or 1
     scale = 2 if wl.name in ("c3", "c2", "c5", "c1") else 4
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(P) as pool:
@@ -420,13 +443,96 @@ def cpu_baseline(wl, procs, t_full):
     wall = time.perf_counter() - t
     cells = sum(r[0] for r in res)
     per = sorted(r[1] for r in res)
-    return {"value": cells / wall, "unit": "fine cells/s", "cores": P, "kind": "oracle",
-            "sample": "%d concurrent oracle solves (one thread each) of the %s recipe at half the "
-                      "subdomains per axis (%d cells each, %.1f-%.1f s per solve, %.1f s wall); "
-                      "host has %s logical CPUs" % (P, wl.name, res[0][0], per[0], per[-1], wall,
-                                                    os.cpu_count()),
-            "single_process_full_workload": {"value": wl.ncells / t_full if t_full else None,
-                                             "seconds": t_full, "cores": 1}}
+    out = {"value": cells / wall, "unit": "fine cells/s", "cores": P, "kind": "oracle",
+           "sample": "%d concurrent oracle solves (one thread each) of the %s recipe at 1/%d of the "
+                     "subdomains per axis (%d cells each, %.1f-%.1f s per solve, %.1f s wall); "
+                     "host has %s logical CPUs" % (P, wl.name, scale, res[0][0], per[0], per[-1], wall,
+                                                   os.cpu_count())}
+    if t_full:
+        out["single_process_full_workload"] = {"value": wl.ncells / t_full, "seconds": t_full,
+                                               "cores": 1}
+    return out
+
+
+def sampled_check(wl, p, fl):
+    """Relative L2 errors at the oracle's stored sample cells of the full 3-D
+    workload (pressure and the six face velocities of each sampled cell)."""
+    import numpy as np
+    ref = np.load(GOLDEN_C4)
+    if int(ref["ncells"]) != wl.ncells:
+        return None
+    cells = ref["cells"]
+    f = fl.reshape(wl.ncells, 2 * wl.dim)
+    return {"flux_rel_l2": float(np.linalg.norm(f[cells] - ref["flux"]) / np.linalg.norm(ref["flux"])),
+            "pressure_rel_l2": float(np.linalg.norm(p[cells] - ref["pressure"]) /
+                                     np.linalg.norm(ref["pressure"])),
+            "over": "%d oracle sample cells (pressure and %d face velocities each)"
+                    % (len(cells), 2 * wl.dim)}
+
+
+def full_check(wl, forms):
+    """The oracle's full solve of the workload against each timed form;
+    returns its single-process time."""
+    import numpy as np
+    from oracle import mrcm as oracle_mrcm
+    t = time.perf_counter()
+    ref = oracle_mrcm.solve(wl)
+    t_full = time.perf_counter() - t
+    rp, rf = ref.pressure(), ref.flux().ravel()
+    for f in forms.values():
+        if "dt" in f:
+            f["err"] = {"flux_rel_l2": float(np.linalg.norm(f["fl"] - rf) / np.linalg.norm(rf)),
+                        "pressure_rel_l2": float(np.linalg.norm(f["p"] - rp) / np.linalg.norm(rp)),
+                        "over": "all cells"}
+    print("oracle %s: %.1f s" % (wl.name, t_full), file=sys.stderr, flush=True)
+    return t_full
+
+
+def time_forms(wl, args, steps_all):
+    """Both precision forms on one workload (a form the library refuses for
+    this workload is recorded with the library's message)."""
+    import paper_2404_13811_amd as m
+    forms = {}
+    for form in ("fp32_refine", "fp64"):
+        steps = steps_all if args.precision in ("best", form) else max(3, steps_all // 2)
+        try:
+            dt, ph, st, p, fl = time_solves(wl, form, steps, args.warmup, args.tol,
+                                            args.smoothing == "persistent")
+        except m.MRCMError as e:
+            forms[form] = {"unavailable": str(e)}
+            print("%s %s: not available (%s)" % (wl.name, form, e), file=sys.stderr, flush=True)
+            continue
+        forms[form] = {"dt": dt, "phases": ph, "stats": st, "p": p, "fl": fl, "steps": steps}
+        print("timed %s %s: %.3f ms per solve" % (wl.name, form, dt * 1e3), file=sys.stderr,
+              flush=True)
+    return forms
+
+
+def form_summary(wl, f, form, args):
+    if "dt" not in f:
+        return {"available": False, "reason": f["unavailable"]}
+    d = {"value": wl.ncells / f["dt"], "ms_per_step": f["dt"] * 1e3,
+         "target_met": f["target_met"],
+         "ms_per_solve_synchronous": round(f["stats"]["ms_per_solve_synchronous"], 4),
+         "ms_synchronous_median_min_max": f["stats"]["ms_synchronous_median_min_max"],
+         "phases_ms": {k: round(v, 4) for k, v in f["phases"].items()},
+         "interface": interface_entry(wl, f["phases"], f["stats"], f["dt"]),
+         "interface_backward_error": f["stats"]["interface_residual"],
+         "one_time_ms": {"smoothing_autotune": round(f["stats"]["ms_autotune"], 3)},
+         "roofline_smoothing": smoothing_roofline(wl, form, f["phases"], f["stats"]),
+         "roofline_local": local_roofline(wl, form, f["phases"], f["stats"])}
+    if form == "fp32_refine":
+        d["refine"] = {"tol": args.tol if args.tol is not None else DEFAULT_TOL,
+                       "max_fp32_solves": f["stats"]["refine_max_iters"],
+                       "max_backward_error": f["stats"]["refine_max_resid"]}
+    if "err" in f:
+        d["err_vs_oracle"] = f["err"]
+    return d
+
+
+def describe(name, w):
+    return "%s: %s cells, subdomains %s, overlap %d, %s spaces, %d smoothing steps" % (
+        name, "x".join(map(str, w.ncell)), "x".join(map(str, w.sub)), w.overlap, w.space, w.nsmooth)
 
 
 def main():
@@ -438,76 +544,63 @@ def main():
         print("bench.py runs on one GPU only: this MRCM-OS path has no multi-GPU form "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     from inputs import make_workload
     wl = make_workload(args.workload, overlap=args.overlap)
-    forms = {}
-    for form in ("fp32_refine", "fp64"):
-        steps = args.steps if args.precision in ("best", form) else max(3, args.steps // 2)
-        dt, ph, st, p, fl = time_solves(wl, form, steps, args.warmup, args.tol,
-                                        args.smoothing == "persistent")
-        forms[form] = {"dt": dt, "phases": ph, "stats": st, "p": p, "fl": fl, "steps": steps}
-        print("timed %s %s: %.3f ms per solve" % (wl.name, form, dt * 1e3), file=sys.stderr,
-              flush=True)
+    forms = time_forms(wl, args, args.steps)
+    if not any("dt" in f for f in forms.values()):
+        print("no precision form runs on %s" % wl.name, file=sys.stderr)
+        sys.exit(1)
     t_full = None
-    if not args.no_cpu_baseline:
-        from oracle import mrcm as oracle_mrcm
-        t = time.perf_counter()
-        ref = oracle_mrcm.solve(wl)
-        t_full = time.perf_counter() - t
-        rp, rf = ref.pressure(), ref.flux().ravel()
+    sampled = wl.name == "c4" and args.overlap is None
+    if sampled:
+        # the full 3-D oracle solve takes minutes: its stored samples
         for f in forms.values():
-            f["err"] = {"flux_rel_l2": float(np.linalg.norm(f["fl"] - rf) / np.linalg.norm(rf)),
-                        "pressure_rel_l2": float(np.linalg.norm(f["p"] - rp) / np.linalg.norm(rp))}
-        print("oracle %s: %.1f s" % (wl.name, t_full), file=sys.stderr, flush=True)
+            if "dt" in f:
+                e = sampled_check(wl, f["p"], f["fl"])
+                if e is not None:
+                    f["err"] = e
+    elif not args.no_cpu_baseline:
+        t_full = full_check(wl, forms)
     for f in forms.values():
         f["target_met"] = "err" in f and f["err"]["flux_rel_l2"] <= FLUX_TOL
+    run = [k for k, f in forms.items() if "dt" in f]
     if args.precision == "best":
-        ok = [k for k, f in forms.items() if f["target_met"]]
-        head = min(ok or forms, key=lambda k: forms[k]["dt"])
+        ok = [k for k in run if forms[k]["target_met"]]
+        head = min(ok or run, key=lambda k: forms[k]["dt"])
     else:
         head = args.precision
-    other = "fp64" if head == "fp32_refine" else "fp32_refine"
-    H, O = forms[head], forms[other]
+        if head not in run:
+            print("%s is not available on %s" % (head, wl.name), file=sys.stderr)
+            sys.exit(1)
+    H = forms[head]
     st = H["stats"]
-
-    def form_summary(f, form):
-        d = {"value": wl.ncells / f["dt"], "ms_per_step": f["dt"] * 1e3,
-             "target_met": f["target_met"],
-             "ms_per_solve_synchronous": round(f["stats"]["ms_per_solve_synchronous"], 4),
-             "ms_synchronous_median_min_max": f["stats"]["ms_synchronous_median_min_max"],
-             "phases_ms": {k: round(v, 4) for k, v in f["phases"].items()},
-             "interface": interface_entry(wl, f["phases"], f["stats"], f["dt"]),
-             "one_time_ms": {"smoothing_autotune": round(f["stats"]["ms_autotune"], 3)},
-             "roofline_smoothing": smoothing_roofline(wl, form, f["phases"], f["stats"]),
-             "roofline_local": local_roofline(wl, form, f["phases"], f["stats"])}
-        if form == "fp32_refine":
-            d["refine"] = {"tol": args.tol if args.tol is not None else DEFAULT_TOL,
-                           "max_fp32_solves": f["stats"]["refine_max_iters"],
-                           "max_backward_error": f["stats"]["refine_max_resid"]}
-        if "err" in f:
-            d["err_vs_oracle"] = f["err"]
-        return d
 
     others = {}
     if not args.no_extra:
-        for name in ("c2",):
+        for name in ("c3", "c2"):
             if name == args.workload:
                 continue
             w2 = make_workload(name)
+            f2 = time_forms(w2, args, max(3, args.steps // 2))
+            if name == "c3" and not args.no_cpu_baseline:
+                full_check(w2, f2)
             o2 = {}
-            for form in ("fp64", "fp32_refine"):
-                d3, ph3, st3, _, _ = time_solves(w2, form, max(3, args.steps // 2), 2, args.tol)
-                o2[form] = {"ms_per_step": round(d3 * 1e3, 4), "value": w2.ncells / d3,
-                            "interface": interface_entry(w2, ph3, st3, d3),
-                            **{k: round(v, 4) for k, v in ph3.items()}}
-            others["%s: %s cells, subdomains %s, overlap %d, %s spaces, %d smoothing steps" % (
-                name, "x".join(map(str, w2.ncell)), "x".join(map(str, w2.sub)), w2.overlap,
-                w2.space, w2.nsmooth)] = o2
+            for form, f in f2.items():
+                if "dt" in f:
+                    f["target_met"] = "err" in f and f["err"]["flux_rel_l2"] <= FLUX_TOL
+                o2[form] = form_summary(w2, f, form, args)
+            others[describe(name, w2)] = o2
         adj = time_adjoint(make_workload("c5"), max(3, args.steps // 4))
         adj["batch"] = time_batch(32, 3)
         others["adjoint"] = adj
     met = H["target_met"]
+    # the roofline of the kernel with the largest share of the solve: the
+    # local kernel (factor + seed solves) or the smoothing kernel
+    loc = local_roofline(wl, head, H["phases"], st)
+    smo = smoothing_roofline(wl, head, H["phases"], st)
+    t_loc = H["phases"]["ms_basis_kernel"]
+    t_smo = H["phases"]["ms_smooth"]
+    roof = loc if t_loc >= t_smo else smo
     line = {
         "metric": "fine cells/s per MRCM-OS solve, FP32+refine vs FP64, at flux err <=1e-6",
         "value": wl.ncells / H["dt"] if met else None,
@@ -522,19 +615,18 @@ def main():
         "dtype": "f32+f64" if head == "fp32_refine" else "f64",
         "data": "synthetic",
         "target_met": met,
-        "config": {"workload": "%s: %s cells, subdomains %s, overlap %d, %s spaces, %d smoothing steps"
-                   % (args.workload, "x".join(map(str, wl.ncell)), "x".join(map(str, wl.sub)),
-                      wl.overlap, wl.space, wl.nsmooth),
+        "config": {"workload": describe(args.workload, wl),
                    "smoothing": "one cooperative launch per call" if st["smooth_persistent"]
                    else "graph of per-colour launches",
                    "solves": "back to back, device errors read once per timed loop; "
                              "ms_per_solve_synchronous: each solve waits for its own",
                    "precision": head, "interface_unknowns": st["n_unknowns"],
-                   "interface_solver": {1: "band_lu", 2: "block_cyclic_reduction"}[st["interface_solver"]]},
-        head: form_summary(H, head),
-        other: form_summary(O, other),
+                   "interface_solver": SOLVERS.get(st["interface_solver"]),
+                   "oracle_check": "stored oracle samples" if sampled else "full oracle solve"},
+        "forms": {k: form_summary(wl, f, k, args) for k, f in forms.items()},
         "other_workloads": others,
-        "roofline": smoothing_roofline(wl, head, H["phases"], st),
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": roof,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_procs, t_full)
