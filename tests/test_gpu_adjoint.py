@@ -82,6 +82,13 @@ CASES = {
     # same cells in the box right-hand sides and their adjoints
     "thin_rows_l0": (lambda: _small(space="const", overlap=0, sub=(8, 1)), 2),
     "thin_rows_l1": (lambda: _small(space="const", overlap=1, sub=(8, 2)), 2),
+    # 64 x 64 cells, 4 x 4 subdomains of 16 x 16 (the first recipe at full
+    # size, alpha = 1)
+    "grid64_sub4x4": (lambda: make_workload("c1").with_(beta_mode="alpha", beta_mbf=1.0,
+                                                         beta_smooth=1.0), 2),
+    # one full member of the batch workload: 256 x 256 cells, 16 x 16
+    # subdomains, overlap 2, five smoothing steps (about 30 s on the CPU)
+    "batch_member_256": (lambda: make_workload("c5"), 5),
 }
 
 
