@@ -219,9 +219,9 @@ def time_adjoint(wl, reps):
 
 def time_batch(members, reps):
     """The batch of fields: every member's forward solve (with checkpoints)
-    and gradient, one context and one stream per member, deferred errors (no
-    call waits for the device; one mrcm_wait per member ends the batch).
-    Device wall time per batch, inputs resident."""
+    and gradient.  Two forms, device wall time per batch, inputs resident:
+    one batched context (mrcm_create_batched: one launch per stage for all
+    members), and one context and stream per member with deferred errors."""
     import numpy as np
     import torch
     import paper_2404_13811_amd as m
@@ -230,48 +230,84 @@ def time_batch(members, reps):
     wls = [make_workload("c5", member=k) for k in range(members)]
     nx, ny = wls[0].ncell
     N = nx * ny
-    obs = torch.as_tensor(np.arange(0, N, N // 16)[:16], device="cuda")
-    fw = torch.zeros(N, 4, dtype=torch.float64, device="cuda")
-    fw[torch.arange(nx - 1, N, nx, device="cuda"), 1] = wls[0].h
-    fw = fw.reshape(-1)
+
+    def weights(nmem):
+        obs = torch.as_tensor(np.concatenate([k * N + np.arange(0, N, N // 16)[:16] for k in range(nmem)]),
+                              device="cuda")
+        fw = torch.zeros(nmem * N, 4, dtype=torch.float64, device="cuda")
+        cells = torch.arange(nmem * N, device="cuda")
+        fw[cells[cells % nx == nx - 1], 1] = wls[0].h
+        return obs, fw.reshape(-1)
+
+    # one batched context
+    ctx = m.create_batched(2, wls[0].ncell, wls[0].h, members)
+    m.configure_batch(ctx, wls, "fp64")
+    m.set_checkpointing(ctx, True)
+    m.set_timing(ctx, False)
+    obs_b, fw_b = weights(members)
+    p = torch.empty(members * N, dtype=torch.float64, device="cuda")
+    fl = torch.empty(members * N * 4, dtype=torch.float64, device="cuda")
+    dJdp = torch.zeros(members * N, dtype=torch.float64, device="cuda")
+    grad = torch.empty(members * N, dtype=torch.float64, device="cuda")
+    tb = 0.0
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.build_basis(ctx)
+        m.solve_interface(ctx)
+        m.smooth(ctx, wls[0].nsmooth)
+        m.get_solution(ctx, p, fl)
+        dJdp[obs_b] = p[obs_b] - 0.1
+        m.adjoint(ctx, dJdp, fw_b, grad)
+        torch.cuda.synchronize()
+        if r:  # the first round builds the plan and allocates
+            tb += (time.perf_counter() - t0) / reps
+    m.destroy(ctx)
+
+    # one context and stream per member
+    obs, fw = weights(1)
     torch.cuda.synchronize()
     streams = [torch.cuda.Stream() for _ in wls]
     ctxs, outs = [], []
     for wl, s in zip(wls, streams):
         with torch.cuda.stream(s):
-            ctx = m.create(wl.dim, wl.ncell, wl.h)
-            api.configure(ctx, wl, "fp64")
-            m.set_checkpointing(ctx, True)
-            m.set_timing(ctx, False)
-            m.set_deferred_errors(ctx, True)
-            p = torch.empty(N, dtype=torch.float64, device="cuda")
-            fl = torch.empty(N * 4, dtype=torch.float64, device="cuda")
-            dJdp = torch.zeros(N, dtype=torch.float64, device="cuda")
-            grad = torch.empty(N, dtype=torch.float64, device="cuda")
-        ctxs.append(ctx)
-        outs.append((p, fl, dJdp, grad))
+            c = m.create(wl.dim, wl.ncell, wl.h)
+            api.configure(c, wl, "fp64")
+            m.set_checkpointing(c, True)
+            m.set_timing(c, False)
+            m.set_deferred_errors(c, True)
+            pk = torch.empty(N, dtype=torch.float64, device="cuda")
+            flk = torch.empty(N * 4, dtype=torch.float64, device="cuda")
+            dk = torch.zeros(N, dtype=torch.float64, device="cuda")
+            gk = torch.empty(N, dtype=torch.float64, device="cuda")
+        ctxs.append(c)
+        outs.append((pk, flk, dk, gk))
     torch.cuda.synchronize()
     t = 0.0
     for r in range(reps + 1):
         t0 = time.perf_counter()
-        for ctx, wl, s, (p, fl, dJdp, grad) in zip(ctxs, wls, streams, outs):
+        for c, wl, s, (pk, flk, dk, gk) in zip(ctxs, wls, streams, outs):
             with torch.cuda.stream(s):
-                m.build_basis(ctx)
-                m.solve_interface(ctx)
-                m.smooth(ctx, wl.nsmooth)
-                m.get_solution(ctx, p, fl)
-                dJdp[obs] = p[obs] - 0.1
-                m.adjoint(ctx, dJdp, fw, grad)
-        for ctx in ctxs:
-            m.wait(ctx)
+                m.build_basis(c)
+                m.solve_interface(c)
+                m.smooth(c, wl.nsmooth)
+                m.get_solution(c, pk, flk)
+                dk[obs] = pk[obs] - 0.1
+                m.adjoint(c, dk, fw, gk)
+        for c in ctxs:
+            m.wait(c)
         torch.cuda.synchronize()
-        if r:  # the first round builds the plans and allocates
+        if r:
             t += (time.perf_counter() - t0) / reps
-    for ctx in ctxs:
-        m.destroy(ctx)
-    return {"members": members, "streams": members, "ms_per_batch": round(t * 1e3, 3),
-            "ms_per_member": round(t * 1e3 / members, 4),
-            "fine_cells_per_s_forward_and_gradient": members * N / t}
+    for c in ctxs:
+        m.destroy(c)
+    return {"members": members,
+            "batched_context": {"ms_per_batch": round(tb * 1e3, 3),
+                                "ms_per_member": round(tb * 1e3 / members, 4),
+                                "fine_cells_per_s_forward_and_gradient": members * N / tb},
+            "contexts_on_streams": {"streams": members, "ms_per_batch": round(t * 1e3, 3),
+                                    "ms_per_member": round(t * 1e3 / members, 4),
+                                    "fine_cells_per_s_forward_and_gradient": members * N / t}}
 
 
 def boxes(wl):
@@ -436,7 +472,7 @@ def cpu_baseline(wl, procs, t_full):
     import multiprocessing as mp
     # the CPUs this process may run on, at most 16 (one GPU's share of a node)
     P = procs or min(len(os.sched_getaffinity(0)), 16) or 1
-    scale = 2 if wl.name in ("c3", "c2", "c5", "c1") else 4
+    scale = 2
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(P) as pool:
         res = pool.map(_oracle_sample, [(wl.name, scale)] * P)

@@ -160,6 +160,33 @@ typedef struct {
  * MRCM_EDEVICE. */
 mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_ctx** out);
 
+/* A batch of nbatch independent 2-D problems that share the grid
+ * (ncell[0] x ncell[1] cells of size h) and every setting of the context
+ * (partition, spaces, Robin parameters, precision, solver) but not the data:
+ * each member has its own log K, source and boundary values.  Every stage
+ * runs the whole batch at once: one launch of the local kernels over all
+ * members' boxes, one launch per colour phase of the smoothing sweep, one
+ * interface solve (the members' systems are independent blocks of it, the
+ * MRCM-OS of Algorithm 1 applied to each member; every step but Step 5 is
+ * per subdomain, Section 4), one adjoint.
+ * Layout: member-major everywhere.  Per-cell arrays (log K, f, pressure,
+ * gradients) hold nbatch * ncell[0] * ncell[1] values, member m's cells at
+ * m * ncell[0] * ncell[1] (x fastest within a member); per-face fluxes
+ * 4 values per cell in the same order; the boundary values of the x sides
+ * (sides 0, 1) nbatch * ncell[1] values and of the y sides (2, 3)
+ * nbatch * ncell[0], member after member.  Equivalently the members are
+ * stacked along y into one grid of ncell[0] x nbatch * ncell[1] cells that
+ * is cut between members: no cell, box or interface couples two members.
+ * Interface unknowns (mrcm_get_coefficients) follow the members in order.
+ * Requires dim = 2, nbatch >= 1, a pressure (Dirichlet) boundary on some
+ * side (mrcm_build_basis: MRCM_EINVAL otherwise, the members would need
+ * their own gauge) and ncell[1] a multiple of the subdomain size along y
+ * (mrcm_set_partition: MRCM_EINVAL).  mrcm_get_balance and mrcm_rel_error
+ * report over the whole batch.  Errors as mrcm_create, and MRCM_EINVAL for
+ * dim != 2 with nbatch > 1 or nbatch < 1. */
+mrcm_status mrcm_create_batched(int dim, const int* ncell, double h, int nbatch, void* stream,
+                                mrcm_ctx** out);
+
 /* log K per cell (N values, x fastest; paper eq1a, scalar K).  Copied.
  * Errors: MRCM_EINVAL on NULL; non-finite values are detected at
  * mrcm_build_basis (MRCM_EINVAL). */

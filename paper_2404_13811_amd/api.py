@@ -6,6 +6,7 @@ inputs and writes outputs on the current torch stream.
 import ctypes
 import weakref
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -24,10 +25,13 @@ class MRCMError(RuntimeError):
 
 
 class Context:
-    def __init__(self, handle, dim, ncell):
+    def __init__(self, handle, dim, ncell, nbatch=1):
         self.handle = handle
         self.dim = dim
+        # cells per axis of the (stacked) grid: a batch stacks its members
+        # along y
         self.ncell = tuple(ncell)
+        self.nbatch = nbatch
 
     @property
     def ncells(self):
@@ -63,6 +67,39 @@ def create(dim, ncell, h, stream=None):
     if st != 0:
         raise MRCMError("mrcm_create", st, "")
     return Context(out, dim, ncell)
+
+
+def create_batched(dim, ncell, h, nbatch, stream=None):
+    """A batch of nbatch 2-D problems on one grid (mrcm_create_batched)."""
+    lib = _lib.load()
+    arr = (ctypes.c_int * 3)(*(list(ncell) + [1] * (3 - len(ncell))))
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    out = ctypes.c_void_p()
+    st = lib.mrcm_create_batched(int(dim), arr, float(h), int(nbatch), ctypes.c_void_p(s),
+                                 ctypes.byref(out))
+    if st != 0:
+        raise MRCMError("mrcm_create_batched", st, "")
+    return Context(out, dim, (ncell[0], ncell[1] * nbatch), nbatch)
+
+
+def configure_batch(ctx, members, precision="fp64", tol=1e-12, max_refine=30, solver="auto"):
+    """Pass the workload records of a batch (same grid, partition, spaces,
+    Robin parameters and boundary types) through the set_* calls, member
+    after member."""
+    dev = "cuda"
+    w0 = members[0]
+    cat = lambda arrs: torch.as_tensor(np.concatenate([np.ravel(a) for a in arrs]),
+                                       dtype=torch.float64, device=dev).contiguous()
+    set_permeability(ctx, cat([w.logk for w in members]))
+    src = [w.source for w in members]
+    set_source(ctx, cat(src) if any(np.any(a) for a in src) else None)
+    for side, kind in enumerate(w0.bc_type):
+        set_bc(ctx, side, kind, cat([w.bc_value[side] for w in members]))
+    set_partition(ctx, w0.sub, w0.overlap)
+    set_interface_space(ctx, w0.space)
+    set_robin(ctx, w0.beta_mode, w0.beta_mbf, w0.beta_smooth)
+    set_precision(ctx, precision, tol, max_refine)
+    set_interface_solver(ctx, solver)
 
 
 def set_permeability(ctx, logk):

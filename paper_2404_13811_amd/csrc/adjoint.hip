@@ -107,7 +107,7 @@ __device__ __forceinline__ void box_matrix_adjoint(const Geo& g, const Box& B, c
     const int ox = gx + (a == 0 ? (sd ? 1 : -1) : 0), oy = gy + (a == 1 ? (sd ? 1 : -1) : 0);
     const int c = xl + m0 * yl;
     const double kc = kat(s, B, gx, gy);
-    const bool dom = (a == 0 ? ox : oy) < 0 || (a == 0 ? ox : oy) >= g.n[a];
+    const bool dom = off_domain(g, a, a == 0 ? gx : gy, a == 0 ? ox : oy);
     if (dom) {
       if (!g.bc_type[q]) continue;
       const double gv = gval(q, t);
@@ -150,10 +150,11 @@ __global__ void k_adj_out(Geo g, const double* __restrict__ K, const double* __r
       const int a = q >> 1, sd = q & 1;
       const int ox = cx + (a == 0 ? (sd ? 1 : -1) : 0), oy = cy + (a == 1 ? (sd ? 1 : -1) : 0);
       const double ub = dJdf[(long long)ci * 4 + q];
-      if (a == 0 ? (ox < 0 || ox >= g.n[0]) : (oy < 0 || oy >= g.n[1])) {
+      if (off_domain(g, a, a == 0 ? cx : cy, a == 0 ? ox : oy)) {
         if (g.bc_type[q]) {
           const int off = q == 0 ? g.bc_off[0] : q == 1 ? g.bc_off[1] : q == 2 ? g.bc_off[2] : g.bc_off[3];
-          const double val = bcv[off + (a == 0 ? cy : cx)];
+          const int c3[3] = {cx, cy, 0};
+          const double val = bcv[off + bface_index(g, c3, a)];
           vp += ub * 2.0 * kc / g.h;
           vk += ub * 2.0 * (pc - val) / g.h;
         }
@@ -252,7 +253,6 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
     pb[ci] = 0.0;
   }
   __syncthreads();
-  const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
   // one pass per side of Omega_i: with a subdomain one cell thick along a,
   // both sides of that axis add to the same cells
 #pragma unroll 1
@@ -260,8 +260,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
     const int a = q >> 1, so = q & 1;
     const int nf = a == 0 ? g.S[1] : g.S[0];
     for (int t = tid; t < nf; t += NT) {
-      const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
-      if (!has) continue;
+      if (wneighbor(g, B.sub, q) < 0) continue;
       int cx, cy;
       wgface(olo, ohi, q, t, cx, cy);
       const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
@@ -528,7 +527,6 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
     s.X[k * nc + bloc(B, s, cx, cy)] += X[B.seed0 + k] * pb[cx + g.n[0] * cy];
   }
   wsync();
-  const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
   // one pass per side of Omega_i: with a subdomain one cell thick along a,
   // both sides of that axis add to the same cells
   for (int q = 0; q < 4; ++q) {
@@ -536,8 +534,7 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
     const int nf = a == 0 ? g.S[1] : g.S[0];
     for (int e = L; e < nrhs * nf; e += 64) {
       const int k = e / nf, t = e % nf;
-      const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
-      if (!has) continue;
+      if (wneighbor(g, B.sub, q) < 0) continue;
       const int go = q == 0 ? g.gside_off[0] : q == 1 ? g.gside_off[1] : q == 2 ? g.gside_off[2] : g.gside_off[3];
       const long long tf = (long long)(B.seed0 + k) * g.gstride + go + t;
       const long long bf = (long long)B.sub * g.gstride + go + t;
@@ -617,9 +614,10 @@ __global__ void __launch_bounds__(64) k_adj_particular(Geo g, const Box* __restr
     const int cx = a == 0 ? (sd ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
     const int cy = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
     const int o = (a == 0 ? cx : cy) + (sd ? 1 : -1);
-    const bool dom = o < 0 || o >= g.n[a];
+    const bool dom = off_domain(g, a, a == 0 ? cx : cy, o);
     const int off = q == 0 ? g.bc_off[0] : q == 1 ? g.bc_off[1] : q == 2 ? g.bc_off[2] : g.bc_off[3];
-    bc[u] = dom ? bcv[off + (a == 0 ? cy : cx)] : 0.0;
+    const int c3[3] = {cx, cy, 0};
+    bc[u] = dom ? bcv[off + bface_index(g, c3, a)] : 0.0;
   }
   for (int e = L; e < nc; e += 64) {
     xs[e] = pbar[(long long)B.sub * nc + e];
@@ -627,13 +625,11 @@ __global__ void __launch_bounds__(64) k_adj_particular(Geo g, const Box* __restr
     s.X[e] = pb[cx + g.n[0] * cy];
   }
   wsync();
-  const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
   for (int q = 0; q < 4; ++q) {  // one pass per side, as above
     const int a = q >> 1, so = q & 1;
     const int nf = a == 0 ? g.S[1] : g.S[0];
     for (int t = L; t < nf; t += 64) {
-      const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
-      if (!has) continue;
+      if (wneighbor(g, B.sub, q) < 0) continue;
       const int go = q == 0 ? g.gside_off[0] : q == 1 ? g.gside_off[1] : q == 2 ? g.gside_off[2] : g.gside_off[3];
       const long long bf = (long long)B.sub * g.gstride + go + t;
       int cx, cy;

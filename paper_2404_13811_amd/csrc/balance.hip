@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(RB) k_cell_balance(Geo g, const double* __rest
         sum += g.area * u;
         ab += g.area * fabs(u);
         const int o = c[a] + (s ? 1 : -1);
-        if (o < 0 || o >= g.n[a]) out[2 * a + s] = g.area * u;
+        if (off_domain(g, a, c[a], o)) out[2 * a + s] = g.area * u;
       }
     src = f[ci] * g.vol;
     r = sum - src;

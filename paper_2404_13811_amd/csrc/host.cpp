@@ -20,6 +20,9 @@ using namespace mrcm;
 struct mrcm_ctx {
   int d = 0;
   int n[3] = {1, 1, 1};
+  // a batch of nbatch 2-D problems on one geometry, stacked along axis 1
+  // (cut cells per member; n[1] = nbatch * cut)
+  int nbatch = 1, cut = 0;
   double h = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -259,7 +262,7 @@ int neighbor(const mrcm_ctx* c, int i, int q) {
   int ic[3];
   sub_coords(c, i, ic);
   const int t = ic[a] + (s ? 1 : -1);
-  if (t < 0 || t >= c->geo.M[a]) return -1;
+  if (off_subgrid(c->geo, a, ic[a], t)) return -1;
   int stride = 1;
   for (int b = 0; b < a; ++b) stride *= c->geo.M[b];
   return i + (s ? stride : -stride);
@@ -582,6 +585,10 @@ mrcm_status make_plan(mrcm_ctx* c) {
   }
   g.gstride = off;
   g.nfaceg = 0;
+  g.cut = c->cut;
+  g.mcut = c->cut > 0 ? c->cut / g.S[1] : 0;
+  if (c->nbatch > 1 && g.neumann)
+    return fail(c, MRCM_EINVAL, "a batch needs a pressure (Dirichlet) boundary: each member would need its own gauge");
 
   const int nsub = g.nsub;
   c->seeds.clear();
@@ -598,6 +605,12 @@ mrcm_status make_plan(mrcm_ctx* c) {
       whi[a] = wlo[a] + g.S[a];
       lo[a] = a < c->d ? std::max(wlo[a] - c->l, 0) : 0;
       hi[a] = a < c->d ? std::min(whi[a] + c->l, g.n[a]) : 1;
+    }
+    if (g.cut > 0) {
+      // a batch member's boxes end at its cuts, as at the domain boundary
+      const int m0 = wlo[1] / g.cut * g.cut;
+      lo[1] = std::max(lo[1], m0);
+      hi[1] = std::min(hi[1], m0 + g.cut);
     }
     c->seed_off[i] = (int)c->seeds.size();
     for (int q = 0; q < 2 * c->d; ++q)
@@ -952,12 +965,24 @@ void invalidate(mrcm_ctx* c, bool geometry) {
 
 extern "C" {
 
-mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_ctx** out) {
+namespace {
+// Boundary values per side: faces x-fastest over the other axes; on the
+// y sides of a batch, member after member.
+int side_values(const mrcm_ctx* c, int side) {
+  int nf = 1;
+  for (int b = 0; b < c->d; ++b)
+    if (b != (side >> 1)) nf *= c->n[b];
+  if ((side >> 1) == 1 && c->cut > 0) nf *= c->nbatch;
+  return nf;
+}
+
+mrcm_status create_ctx(int dim, const int* ncell, double h, int nbatch, void* stream, mrcm_ctx** out) {
   if (!out) return MRCM_EINVAL;
   *out = nullptr;
   if (dim != 2 && dim != 3) return MRCM_EINVAL;
   if (!ncell || !(h > 0.0) || !std::isfinite(h)) return MRCM_EINVAL;
-  long long N = 1;
+  if (nbatch < 1 || (nbatch > 1 && dim != 2)) return MRCM_EINVAL;
+  long long N = nbatch;
   for (int a = 0; a < dim; ++a) {
     if (ncell[a] <= 0) return MRCM_EINVAL;
     N *= ncell[a];
@@ -967,16 +992,17 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   if (!c) return MRCM_ENOMEM;
   c->d = dim;
   for (int a = 0; a < dim; ++a) c->n[a] = ncell[a];
+  if (nbatch > 1) {
+    c->nbatch = nbatch;
+    c->cut = ncell[1];
+    c->n[1] = ncell[1] * nbatch;
+  }
   c->h = h;
   c->stream = (hipStream_t)stream;
-  // boundary value layout: per side, faces x-fastest over the other axes
   int off = 0;
   for (int q = 0; q < 2 * dim; ++q) {
     c->bc_off[q] = off;
-    int nf = 1;
-    for (int b = 0; b < dim; ++b)
-      if (b != (q >> 1)) nf *= ncell[b];
-    off += nf;
+    off += side_values(c, q);
   }
   c->nbcv = off;
   hipError_t e = hipMalloc((void**)&c->logk, N * sizeof(double));
@@ -1000,6 +1026,16 @@ mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_
   c->flags_zero = true;
   *out = c;
   return MRCM_OK;
+}
+}  // namespace
+
+mrcm_status mrcm_create(int dim, const int* ncell, double h, void* stream, mrcm_ctx** out) {
+  return create_ctx(dim, ncell, h, 1, stream, out);
+}
+
+mrcm_status mrcm_create_batched(int dim, const int* ncell, double h, int nbatch, void* stream,
+                                mrcm_ctx** out) {
+  return create_ctx(dim, ncell, h, nbatch, stream, out);
 }
 
 mrcm_status mrcm_set_permeability(mrcm_ctx* c, const double* logk_dev) {
@@ -1029,9 +1065,7 @@ mrcm_status mrcm_set_bc(mrcm_ctx* c, int side, mrcm_bc_type type, const double* 
   if (!c) return MRCM_EINVAL;
   if (side < 0 || side >= 2 * c->d) return fail(c, MRCM_EINVAL, "side %d out of range", side);
   if (type != MRCM_BC_NEUMANN && type != MRCM_BC_DIRICHLET) return fail(c, MRCM_EINVAL, "bad bc type");
-  int nf = 1;
-  for (int b = 0; b < c->d; ++b)
-    if (b != (side >> 1)) nf *= c->n[b];
+  const int nf = side_values(c, side);
   if (val_dev) {
     HIPCHK(c, hipMemcpyAsync(c->bcv + c->bc_off[side], val_dev, nf * sizeof(double),
                              hipMemcpyDeviceToDevice, c->stream));
@@ -1055,6 +1089,9 @@ mrcm_status mrcm_set_partition(mrcm_ctx* c, const int* sub, int overlap) {
   }
   if (overlap < 0 || overlap > smin - 1)
     return fail(c, MRCM_EINVAL, "overlap must satisfy 0 <= l <= min(sub) - 1");
+  if (c->cut > 0 && c->cut % sub[1])
+    return fail(c, MRCM_EINVAL, "batch member: %d cells along y not a multiple of subdomain size %d",
+                c->cut, sub[1]);
   for (int a = 0; a < c->d; ++a) c->S[a] = sub[a];
   c->l = overlap;
   c->have_part = true;

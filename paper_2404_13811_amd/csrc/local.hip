@@ -254,7 +254,7 @@ __device__ __forceinline__ int neighbor_of(const Geo& g, int sub, int q) {
   for (int b = 0; b < a; ++b) stride *= g.M[b];
   ia = (r / stride) % g.M[a];
   const int t = ia + (s ? 1 : -1);
-  if (t < 0 || t >= g.M[a]) return -1;
+  if (off_subgrid(g, a, ia, t)) return -1;
   return sub + (s ? stride : -stride);
 }
 
@@ -415,7 +415,7 @@ __device__ void physical_rhs(const Geo& g, const Box& B, const double* K, const 
     for (int a = 0; a < g.d; ++a)
       for (int s = 0; s < 2; ++s) {
         const int t = c[a] + (s ? 1 : -1);
-        if (t >= 0 && t < g.n[a]) continue;
+        if (!off_domain(g, a, c[a], t)) continue;
         const int side = 2 * a + s;
         const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
         if (g.bc_type[side]) b += 2.0 * K[ci] * g.area / g.h * val;

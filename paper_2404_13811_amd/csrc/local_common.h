@@ -46,7 +46,7 @@ enum { kFaceInterior = 0, kFaceRobin = 1, kFaceDir = 2, kFaceNeu = 3 };
 
 __device__ __forceinline__ int face_kind(const Geo& g, const Box& B, const int c[3], int a, int s) {
   int t = c[a] + (s ? 1 : -1);
-  if (t < 0 || t >= g.n[a]) return g.bc_type[2 * a + s] ? kFaceDir : kFaceNeu;
+  if (off_domain(g, a, c[a], t)) return g.bc_type[2 * a + s] ? kFaceDir : kFaceNeu;
   if (t < B.lo[a] || t >= B.hi[a]) return kFaceRobin;
   return kFaceInterior;
 }
@@ -61,12 +61,14 @@ __device__ __forceinline__ void tangential(int a, int& t0, int& t1) {
   t1 = a == 2 ? 1 : 2;
 }
 
-// Index of a boundary face of domain side (a, s) touched by global cell c.
+// Index of a boundary face of domain side (a, s) touched by global cell c
+// (on the y sides of a batch, member after member).
 __device__ __forceinline__ int bface_index(const Geo& g, const int c[3], int a) {
   int t0, t1;
   tangential(a, t0, t1);
   const int i0 = pick3(c, t0);
-  return g.d == 3 ? i0 + pick3(g.n, t0) * pick3(c, t1) : i0;
+  if (g.d == 3) return i0 + pick3(g.n, t0) * pick3(c, t1);
+  return (a == 1 && g.cut > 0) ? i0 + g.n[0] * (c[1] / g.cut) : i0;
 }
 
 // Index of the face of side q of box [lo, hi) touched by global cell c
@@ -94,7 +96,7 @@ __device__ __forceinline__ double state_face_u(const Geo& g, const double* __res
   int o[3] = {c[0], c[1], c[2]};
   o[a] += s ? 1 : -1;
   const double kc = K[ci];
-  if (o[a] < 0 || o[a] >= g.n[a]) {
+  if (off_domain(g, a, c[a], o[a])) {
     const double val = bcv[g.bc_off[q] + bface_index(g, c, a)];
     return g.bc_type[q] ? 2.0 * kc * g.area / g.h * (p[ci] - val) / g.area : val;
   }

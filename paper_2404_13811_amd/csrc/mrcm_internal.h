@@ -31,8 +31,25 @@ struct Geo {
   int nfaceg;      // faces per Gamma side (S^(d-1)), same for every side when S is cubic
   int gside_off[6];// offset of side q within one subdomain's Gamma-face block
   int gstride;     // faces per subdomain over all 2d sides
+  // batches of 2-D problems: the members are stacked along axis 1, cut
+  // cells (mcut subdomain rows) each; nothing couples cells or subdomains
+  // across a cut, which bounds each member like the domain boundary
+  // (0: one problem)
+  int cut, mcut;
   double h, area, vol;
 };
+
+// Moving from coordinate `from` to `to` along axis a leaves the domain (or
+// the batch member).
+__host__ __device__ inline bool off_domain(const Geo& g, int a, int from, int to) {
+  return to < 0 || to >= g.n[a] || (a == 1 && g.cut > 0 && to / g.cut != from / g.cut);
+}
+
+// The subdomain at coordinate `to` along axis a is no neighbour of the one
+// at `from` (outside the grid of subdomains or across a batch cut).
+__host__ __device__ inline bool off_subgrid(const Geo& g, int a, int from, int to) {
+  return to < 0 || to >= g.M[a] || (a == 1 && g.mcut > 0 && to / g.mcut != from / g.mcut);
+}
 
 // One local box: an oversampled region (basis functions, smoothing) or a
 // subdomain (particular problem).  Cells are ordered x fastest; blocks are

@@ -219,7 +219,7 @@ __device__ __forceinline__ void load_box(const Geo& g, const Box& B, const doubl
   gather<1024 / NT, NT>(s.Kt, W2 * H2, [&](int e, double& fill) -> const double* {
     const int x = B.lo[0] - 1 + e % W2, y = B.lo[1] - 1 + e / W2;
     fill = LOG ? 0.0 : 1.0;
-    return (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1]) ? K + x + g.n[0] * y : nullptr;
+    return (x >= 0 && x < g.n[0] && !off_domain(g, 1, B.lo[1], y)) ? K + x + g.n[0] * y : nullptr;
   });
   if (LOG) {
     bsync<NT>();
@@ -246,7 +246,7 @@ __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta
         const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0);
         const int oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
         const int t = a == 0 ? ox : oy;
-        if (t < 0 || t >= g.n[a]) {
+        if (off_domain(g, a, a == 0 ? x : y, t)) {
           if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area * ih;
           continue;
         }
@@ -398,7 +398,7 @@ __device__ __forceinline__ int wneighbor(const Geo& g, int sub, int q) {
   const int a = q >> 1, sd = q & 1;
   const int ia = (a == 0) ? sub % g.M[0] : sub / g.M[0];
   const int t = ia + (sd ? 1 : -1);
-  if (t < 0 || t >= g.M[a]) return -1;
+  if (off_subgrid(g, a, ia, t)) return -1;
   const int stride = (a == 0) ? 1 : g.M[0];
   return sub + (sd ? stride : -stride);
 }
@@ -428,7 +428,7 @@ __device__ __forceinline__ void physical_rhs(const Geo& g, const Box& B, const B
     for (int a = 0; a < 2; ++a)
       for (int sd = 0; sd < 2; ++sd) {
         const int t = c[a] + (sd ? 1 : -1);
-        if (t >= 0 && t < g.n[a]) continue;
+        if (!off_domain(g, a, c[a], t)) continue;
         const int side = 2 * a + sd;
         const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
         if (g.bc_type[side]) b += 2.0 * kat(s, B, x, y) * g.area / g.h * val;
@@ -518,7 +518,7 @@ __device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const S
   const BoxLds& s = r.b;
   const int m0 = s.m0, m1 = s.m1, W2 = m0 + 2;
   const int nc = m0 * m1, nt = W2 * (m1 + 2), ns = 2 * (m0 + m1);
-  const int n0 = g.n[0], n1 = g.n[1];
+  const int n0 = g.n[0];
   const int lo0 = B.lo[0], lo1 = B.lo[1];
   const double* tg = tcoup ? tcoup + B.scr : nullptr;
   // per side q: a box side on the domain boundary reads its boundary values;
@@ -533,7 +533,7 @@ __device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const S
       const int u = isk ? e : e - nt;
       const int y = lo1 - 1 + u / W2, x = lo0 - 1 + (u - (u / W2) * W2);
       fill = isk ? 1.0 : 0.0;
-      if (x < 0 || x >= n0 || y < 0 || y >= n1) return nullptr;
+      if (x < 0 || x >= n0 || off_domain(g, 1, lo1, y)) return nullptr;
       return (isk ? K : p) + x + n0 * y;
     }
     e -= 2 * nt;
@@ -550,11 +550,12 @@ __device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const S
     const int x = a == 0 ? (sd ? B.hi[0] - 1 : lo0) : lo0 + t;
     const int y = a == 1 ? (sd ? B.hi[1] - 1 : lo1) : lo1 + t;
     const int o = (a == 0 ? x : y) + (sd ? 1 : -1);
-    const bool dom = o < 0 || o >= (a == 0 ? n0 : n1);
+    const bool dom = off_domain(g, a, a == 0 ? x : y, o);
     if (!isgf) {
       if (!dom) return nullptr;
       const int off = q == 0 ? g.bc_off[0] : q == 1 ? g.bc_off[1] : q == 2 ? g.bc_off[2] : g.bc_off[3];
-      return bcv + off + (a == 0 ? y : x);
+      const int c3[3] = {x, y, 0};
+      return bcv + off + bface_index(g, c3, a);
     }
     if (dom || g.l > 0) return nullptr;
     // neighbour across side q and the face's position on its opposite side
@@ -656,9 +657,7 @@ __device__ __forceinline__ void smooth_out(const Geo& g, const Box& B, const Smo
   for (int u = tid; u < 2 * (nfx + nfy); u += NT) {
     const int q = u < 2 * nfx ? (u < nfx ? 0 : 1) : (u < 2 * nfx + nfy ? 2 : 3);
     const int t = u - (q == 0 ? 0 : q == 1 ? nfx : q == 2 ? 2 * nfx : 2 * nfx + nfy);
-    const int ix = B.sub % g.M[0], iy = B.sub / g.M[0];
-    const bool has = q == 0 ? ix > 0 : q == 1 ? ix + 1 < g.M[0] : q == 2 ? iy > 0 : iy + 1 < g.M[1];
-    if (!has) continue;
+    if (wneighbor(g, B.sub, q) < 0) continue;
     const int a = q >> 1, so = q & 1;
     int cx, cy;
     wgface(olo, ohi, q, t, cx, cy);

@@ -1,0 +1,191 @@
+"""Batched contexts (mrcm_create_batched): the members of a batch solved in
+one context against each member solved in a context of its own, members
+against the CPU oracle, the batch's adjoint against the members' adjoints,
+and the calls a batch refuses."""
+import numpy as np
+import pytest
+
+from inputs import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(ctx, nsmooth, dJ=None):
+    import torch
+    import paper_2404_13811_amd as m
+    # the same threads per box in every context: the smoothing kernels'
+    # setup is spread over the box's threads
+    m.set_smoothing(ctx, True, 128)
+    if dJ is not None:
+        m.set_checkpointing(ctx, True)
+    m.build_basis(ctx)
+    m.solve_interface(ctx)
+    m.smooth(ctx, nsmooth)
+    p, fl = m.get_solution(ctx)
+    g = None
+    if dJ is not None:
+        dJdp, dJdf = dJ(p)
+        g = m.adjoint(ctx, dJdp, dJdf).cpu().numpy()
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), fl.cpu().numpy(), g
+
+
+def solve_batch(wls, precision="fp64", dJ=None):
+    import paper_2404_13811_amd as m
+    w0 = wls[0]
+    ctx = m.create_batched(2, w0.ncell, w0.h, len(wls))
+    try:
+        m.configure_batch(ctx, wls, precision)
+        p, fl, g = _run(ctx, w0.nsmooth, dJ)
+        st = m.get_stats(ctx)
+    finally:
+        m.destroy(ctx)
+    n = w0.ncell[0] * w0.ncell[1]
+    return ([p[k * n:(k + 1) * n] for k in range(len(wls))],
+            [fl[k * 4 * n:(k + 1) * 4 * n] for k in range(len(wls))],
+            None if g is None else [g[k * n:(k + 1) * n] for k in range(len(wls))], st)
+
+
+def solve_one(wl, precision="fp64", dJ=None):
+    import paper_2404_13811_amd as m
+    from paper_2404_13811_amd import api
+    ctx = m.create(wl.dim, wl.ncell, wl.h)
+    try:
+        api.configure(ctx, wl, precision)
+        p, fl, g = _run(ctx, wl.nsmooth, dJ)
+    finally:
+        m.destroy(ctx)
+    return p, fl, g
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_batch_of_32_members_is_bit_identical_to_single_solves():
+    """32 full members of the batch workload (256 x 256 cells, 16 x 16
+    subdomains, overlap 2, five smoothing steps) in one context.  Every
+    stage is per box except the interface solve, whose reduction over the
+    stacked layers eliminates each member's 16 layers in the same order as
+    alone (the couplings between members are zero), so the results agree
+    bit for bit."""
+    wls = [make_workload("c5", member=k) for k in range(32)]
+    ps, fls, _, st = solve_batch(wls)
+    assert st["n_subdomains"] == 32 * 256 and st["n_unknowns"] == 32 * 960
+    worst = 0.0
+    for k in range(32):
+        p1, f1, _ = solve_one(wls[k])
+        if not (np.array_equal(ps[k], p1) and np.array_equal(fls[k], f1)):
+            worst = max(worst, _rel(ps[k], p1), _rel(fls[k], f1))
+    print("  32 members: largest relative difference from the single solves %.3e" % worst, flush=True)
+    assert worst == 0.0
+
+
+def test_batch_members_against_the_oracle():
+    """Four members (128 x 128 cells, 8 x 8 subdomains) against the CPU
+    oracle, FP64 to 1e-10."""
+    from oracle import mrcm as oracle_mrcm
+    wls = [make_workload("c5", scale=2, member=k) for k in range(4)]
+    ps, fls, _, _ = solve_batch(wls)
+    for k, wl in enumerate(wls):
+        ref = oracle_mrcm.solve(wl)
+        ep = _rel(ps[k], ref.pressure())
+        ef = _rel(fls[k], ref.flux().ravel())
+        print("  member %d: rel L2 pressure %.3e flux %.3e" % (k, ep, ef), flush=True)
+        assert ep <= 1e-10 and ef <= 1e-10
+
+
+def _members_with_own_boundaries(n, **kw):
+    """Members with their own Dirichlet data on all four sides (so that the
+    y sides' boundary values, stored member after member, matter)."""
+    out = []
+    for k in range(n):
+        wl = make_workload("c1", scale=2, member=0, seed=40 + k).with_(**kw)
+        nx, ny = wl.ncell
+        vals = [np.full(ny, 1.0 + k), np.full(ny, 0.1 * k), np.linspace(0.0, 1.0, nx) * (k + 1),
+                np.linspace(1.0, 0.0, nx)]
+        out.append(wl.with_(bc_type=("D", "D", "D", "D"), bc_value=vals))
+    return out
+
+
+@pytest.mark.parametrize("overlap,space", [(0, "const"), (2, "linear"), (1, "const")])
+def test_batch_of_three_with_their_own_boundary_data(overlap, space):
+    """Three members of 32 x 32 cells with subdomains of 16 x 16 (two
+    layers each: the reduction's tree over the six stacked layers differs
+    from a member's own, so the agreement is to rounding) and member-specific
+    pressure data on all four sides; overlap 0 takes the neighbours' fluxes
+    across cuts-free interfaces only."""
+    wls = _members_with_own_boundaries(3, overlap=overlap, space=space)
+    ps, fls, _, _ = solve_batch(wls)
+    for k, wl in enumerate(wls):
+        p1, f1, _ = solve_one(wl)
+        ep, ef = _rel(ps[k], p1), _rel(fls[k], f1)
+        print("  member %d: rel difference p %.2e flux %.2e" % (k, ep, ef), flush=True)
+        assert ep <= 1e-12 and ef <= 1e-12
+
+
+def test_batch_fp32_refine_equals_single_solves():
+    wls = [make_workload("c5", scale=2, member=k) for k in range(3)]
+    ps, fls, _, st = solve_batch(wls, "fp32_refine")
+    for k, wl in enumerate(wls):
+        p1, f1, _ = solve_one(wl, "fp32_refine")
+        assert _rel(ps[k], p1) <= 1e-12 and _rel(fls[k], f1) <= 1e-12
+
+
+def test_batch_adjoint_equals_the_members_adjoints():
+    """Gradient of J = 1/2 sum_obs (p - 0.1)^2 + outflow of every member,
+    summed over the batch, against each member's own adjoint."""
+    import torch
+    wls = [make_workload("c5", scale=2, member=k) for k in range(4)]
+    nx, ny = wls[0].ncell
+    n = nx * ny
+
+    def dJ_for(nmem):
+        def dJ(p):
+            obs = np.concatenate([k * n + np.arange(0, n, n // 16)[:16] for k in range(nmem)])
+            o = torch.as_tensor(obs, device="cuda")
+            dJdp = torch.zeros_like(p)
+            dJdp[o] = p[o] - 0.1
+            fw = torch.zeros(nmem * n, 4, dtype=torch.float64, device="cuda")
+            cells = torch.arange(nmem * n, device="cuda")
+            fw[cells[cells % nx == nx - 1], 1] = wls[0].h
+            return dJdp, fw.reshape(-1)
+        return dJ
+
+    _, _, gs, _ = solve_batch(wls, dJ=dJ_for(4))
+    for k, wl in enumerate(wls):
+        _, _, g1 = solve_one(wl, dJ=dJ_for(1))
+        e = _rel(gs[k], g1)
+        print("  member %d: gradient rel difference %.2e" % (k, e), flush=True)
+        assert e <= 1e-12
+
+
+def test_batch_refusals():
+    import paper_2404_13811_amd as m
+    with pytest.raises(m.MRCMError):
+        m.create_batched(3, (8, 8, 8), 0.125, 2)
+    with pytest.raises(m.MRCMError):
+        m.create_batched(2, (32, 32), 1.0 / 32, 0)
+    # pure Neumann members would each need their own gauge
+    wls = [make_workload("c2", scale=8, member=0) for _ in range(2)]
+    ctx = m.create_batched(2, wls[0].ncell, wls[0].h, 2)
+    try:
+        m.configure_batch(ctx, wls)
+        with pytest.raises(m.MRCMError):
+            m.build_basis(ctx)
+    finally:
+        m.destroy(ctx)
+    # members' cells along y must hold whole subdomains
+    ctx = m.create_batched(2, (32, 24), 1.0 / 32, 2)
+    try:
+        with pytest.raises(m.MRCMError):
+            m.set_partition(ctx, (16, 16), 2)
+    finally:
+        m.destroy(ctx)
