@@ -52,6 +52,8 @@ GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_full_samples.npz")
 # value it was taken with; otherwise the traffic is reported as null.
 TRAFFIC = {
     # (kernel, workload key): (source files, sha256 prefix, fetch KiB, write KiB)
+    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip",), "d0b2ac9c6b72e60f", 1887617.5, 4380710.0),
+    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip",), "d0b2ac9c6b72e60f", 518748.2, 2727.0),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COMMON_SOURCES = ("wave_common.h", "local_common.h", "mrcm_internal.h", "pivot4.h")
