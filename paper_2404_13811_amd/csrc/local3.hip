@@ -60,17 +60,22 @@ __device__ __forceinline__ void bsync() {
   }
 }
 
-// Pivot rows of one step (two alternating buffers) and the flag.  The
-// buffers also hold the per-wave partial sums of the block-vector products
-// (4 right-hand sides x NW waves x 64 lanes <= 1024 values), which never
-// overlap an elimination.
+// Pivot data of one elimination step (two alternating buffers) and the
+// flag.  vb holds the step's multipliers v_c = P^-1 A[k..k+3][c] of every
+// column c (m-major: lane c reads vb[m][c], no bank conflicts), rs the
+// pivot-column entries A[i][k+m] of every row i (row-major, read as
+// broadcasts), pb the 4 x 4 pivot block on its way to the wave that factors
+// it.  vb and rs also hold the per-wave partial sums of the block-vector
+// products (4 right-hand sides x NW waves x 64 lanes <= 1024 values), which
+// never overlap an elimination.
 struct __align__(16) Gj3 {
-  double rowb[2][P3 * G3];  // rowb[c * 4 + m] = A[k + m][c]
-  double rows[2][P3 * G3];  // the same, negated for c < k: A[c][k + m]
+  double vb[2][G3 * P3];
+  double rs[2][P3 * G3];
+  double pb[2][G3 * G3];
   int flag;
 };
 
-__device__ __forceinline__ double* partials3(Gj3& sm) { return &sm.rowb[0][0]; }
+__device__ __forceinline__ double* partials3(Gj3& sm) { return &sm.vb[0][0]; }
 
 // LDS of one box.
 struct Box3 {
@@ -217,90 +222,114 @@ __device__ __forceinline__ void build3(const Geo& g, const Box& B, const Box3& s
 // pivoting (the Schur complements are SPD).  The pivot columns are not
 // exchanged: for a symmetric matrix under in-place Gauss-Jordan, column
 // k + m equals row k + m on the rows not yet eliminated and its negative
-// on the rows already eliminated (i < k).  The wave holding rows k .. k + 3
-// publishes them twice, as they are (the pivot block and the right-hand
-// side of each lane's column) and with that sign (the column entries of
-// every row), so the update needs no exchange of columns and no sign
-// logic.  The step index is a template parameter: every register index is
-// a compile-time constant.  One barrier per step: a buffer is rewritten two
-// steps later, after every wave has passed the barrier in between.
+// on the rows already eliminated (i < k), so the wave holding rows
+// k .. k + 3 publishes them with that sign as the pivot-column entries of
+// every row.  That wave also factors the 4 x 4 pivot block (closed form)
+// and publishes the multipliers v_c = P^-1 A[k..k+3][c] of every column c
+// (a unit right-hand side for the pivot columns), so the other waves only
+// read v_c and apply the rank-4 update A[i][c] -= sum_m A[i][k+m] v_c[m] to
+// their rows.  Look-ahead: during step k the wave holding rows k + 4 ..
+// k + 7 updates those rows first and publishes step k + 4's pivot data
+// before updating the rest, so one workgroup barrier per step suffices and
+// the pivot factorisation overlaps the other waves' updates.  The step
+// index is a template parameter: every register index is a compile-time
+// constant.
 template <int NW, int K>
-__device__ __forceinline__ void gj3_step(Gj3& sm, double w[R3], bool& bad) {
-  constexpr int OWN = K / R3, RI = K % R3;
+__device__ __forceinline__ void gj3_pivot(int nb, Gj3& sm, double w[R3], bool& bad) {
+  // publish step K's pivot data (the calling wave holds rows K .. K + 3)
+  constexpr int RI = K % R3;
   const int c = lane3_here();
-  const int wv = wave3();
-  double* rb = sm.rowb[(K / G3) & 1];
-  double* rs = sm.rows[(K / G3) & 1];
   const int ck = c - K;
   const bool pc = ck >= 0 && ck < G3;
-  // the pivot columns start from zero: a bit mask, not a branch per row
-  const unsigned long long keep = pc ? 0ull : ~0ull;
-  if (wv == OWN) {
-    const double sg = c < K ? -1.0 : 1.0;
-    *reinterpret_cast<double2*>(rb + c * G3) = make_double2(w[RI], w[RI + 1]);
-    *reinterpret_cast<double2*>(rb + c * G3 + 2) = make_double2(w[RI + 2], w[RI + 3]);
-    *reinterpret_cast<double2*>(rs + c * G3) = make_double2(sg * w[RI], sg * w[RI + 1]);
-    *reinterpret_cast<double2*>(rs + c * G3 + 2) = make_double2(sg * w[RI + 2], sg * w[RI + 3]);
+  double* vb = sm.vb[(K / G3) & 1];
+  double* rs = sm.rs[(K / G3) & 1];
+  double* pb = sm.pb[(K / G3) & 1];
+  if (pc) {
+    *reinterpret_cast<double2*>(pb + ck * G3) = make_double2(w[RI], w[RI + 1]);
+    *reinterpret_cast<double2*>(pb + ck * G3 + 2) = make_double2(w[RI + 2], w[RI + 3]);
   }
-  bsync<NW>();
+  const double sg = c < K ? -1.0 : 1.0;
+  *reinterpret_cast<double2*>(rs + c * G3) = make_double2(sg * w[RI], sg * w[RI + 1]);
+  *reinterpret_cast<double2*>(rs + c * G3 + 2) = make_double2(sg * w[RI + 2], sg * w[RI + 3]);
+  bsync<1>();  // the pivot block is read back by this wave only
   double P[G3][G3], r[G3], v[G3];
 #pragma unroll
   for (int j = 0; j < G3; ++j)
 #pragma unroll
-    for (int m = 0; m < G3; ++m) P[m][j] = rb[(K + j) * G3 + m];
-  {
-    const double2 r01 = *reinterpret_cast<const double2*>(rb + c * G3);
-    const double2 r23 = *reinterpret_cast<const double2*>(rb + c * G3 + 2);
-    r[0] = pc ? (ck == 0 ? 1.0 : 0.0) : r01.x;
-    r[1] = pc ? (ck == 1 ? 1.0 : 0.0) : r01.y;
-    r[2] = pc ? (ck == 2 ? 1.0 : 0.0) : r23.x;
-    r[3] = pc ? (ck == 3 ? 1.0 : 0.0) : r23.y;
+    for (int m = 0; m < G3; ++m) P[m][j] = pb[j * G3 + m];
+#pragma unroll
+  for (int m = 0; m < G3; ++m) {
+    // select values, not addresses (a select between the address of a
+    // constant and of w[] would keep w out of registers)
+    const double wm = w[RI + m];
+    const double unit = ck == m ? 1.0 : 0.0;
+    r[m] = pc ? unit : wm;
   }
   const PivBlock<double> q = piv_block(P);
   bad |= !(q.d0 > 0.0 && q.da > 0.0 && q.s0 > 0.0 && q.ds > 0.0);
   piv_apply(q, r, v);
-  // the lane's rows in groups of RG, the next group's column entries read
-  // while the current group is updated
-  constexpr int RG = 4;
-  const double* rw = rs + R3 * wv * G3;
-  double2 cb[2][RG][2];
 #pragma unroll
-  for (int u = 0; u < RG; ++u) {
-    cb[0][u][0] = *reinterpret_cast<const double2*>(rw + u * G3);
-    cb[0][u][1] = *reinterpret_cast<const double2*>(rw + u * G3 + 2);
+  for (int m = 0; m < G3; ++m) vb[m * P3 + c] = v[m];
+  (void)nb;
+}
+
+// rows [R0, R1) of the lane's 16: A[i][c] = (pivot column ? 0 : A[i][c]) -
+// sum_m rs[i][m] v[m]
+template <int R0, int R1>
+__device__ __forceinline__ void gj3_rows(const double* rw, unsigned long long keep, const double v[G3],
+                                         double w[R3]) {
+#pragma unroll
+  for (int ii = R0; ii < R1; ++ii) {
+    const double2 c01 = *reinterpret_cast<const double2*>(rw + ii * G3);
+    const double2 c23 = *reinterpret_cast<const double2*>(rw + ii * G3 + 2);
+    double acc = __longlong_as_double(__double_as_longlong(w[ii]) & keep);
+    acc = fma(-c01.x, v[0], acc);
+    acc = fma(-c01.y, v[1], acc);
+    acc = fma(-c23.x, v[2], acc);
+    acc = fma(-c23.y, v[3], acc);
+    w[ii] = acc;
   }
+}
+
+template <int NW, int K>
+__device__ __forceinline__ void gj3_step(int nb, Gj3& sm, double w[R3], bool& bad) {
+  constexpr int OWN = K / R3, RI = K % R3;
+  constexpr int KN = K + G3, OWNN = KN / R3, RIN = KN % R3;
+  const int c = lane3_here();
+  const int wv = wave3();
+  const double* vb = sm.vb[(K / G3) & 1];
+  const double* rw = sm.rs[(K / G3) & 1] + R3 * wv * G3;
+  const int ck = c - K;
+  const bool pc = ck >= 0 && ck < G3;
+  // the pivot columns start from zero: a bit mask, not a branch per row
+  const unsigned long long keep = pc ? 0ull : ~0ull;
+  double v[G3];
 #pragma unroll
-  for (int g0 = 0; g0 < R3; g0 += RG) {
-    const int st = (g0 / RG) & 1;
-    if (g0 + RG < R3) {
-#pragma unroll
-      for (int u = 0; u < RG; ++u) {
-        cb[st ^ 1][u][0] = *reinterpret_cast<const double2*>(rw + (g0 + RG + u) * G3);
-        cb[st ^ 1][u][1] = *reinterpret_cast<const double2*>(rw + (g0 + RG + u) * G3 + 2);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RG; ++u) {
-      const int ii = g0 + u;
-      double acc = __longlong_as_double(__double_as_longlong(w[ii]) & keep);
-      acc = fma(-cb[st][u][0].x, v[0], acc);
-      acc = fma(-cb[st][u][0].y, v[1], acc);
-      acc = fma(-cb[st][u][1].x, v[2], acc);
-      acc = fma(-cb[st][u][1].y, v[3], acc);
-      w[ii] = acc;
-    }
+  for (int m = 0; m < G3; ++m) v[m] = vb[m * P3 + c];
+  if constexpr (KN < R3 * NW) {
+    // look-ahead: every wave updates the rows at the next pivot rows' place
+    // first (the order of the rows does not matter otherwise); the wave
+    // that holds them then publishes the next step's pivot data before it
+    // updates the rest
+    gj3_rows<RIN, RIN + G3>(rw, keep, v, w);
+    if (KN < nb && wv == OWNN) gj3_pivot<NW, KN>(nb, sm, w, bad);
+    gj3_rows<0, RIN>(rw, keep, v, w);
+    gj3_rows<RIN + G3, R3>(rw, keep, v, w);
+  } else {
+    gj3_rows<0, R3>(rw, keep, v, w);
   }
   if (wv == OWN) {
 #pragma unroll
     for (int m = 0; m < G3; ++m) w[RI + m] = v[m];
   }
+  bsync<NW>();
 }
 
 template <int NW, int K>
 __device__ __forceinline__ void gj3_steps(int nb, Gj3& sm, double w[R3], bool& bad) {
   if constexpr (K < R3 * NW) {
     if (K < nb) {
-      gj3_step<NW, K>(sm, w, bad);
+      gj3_step<NW, K>(nb, sm, w, bad);
       gj3_steps<NW, K + G3>(nb, sm, w, bad);
     }
   }
@@ -309,9 +338,10 @@ __device__ __forceinline__ void gj3_steps(int nb, Gj3& sm, double w[R3], bool& b
 template <int NW>
 __device__ __forceinline__ void gj3(int nb, Gj3& sm, double w[R3]) {
   bool bad = false;
+  if (wave3() == 0) gj3_pivot<NW, 0>(nb, sm, w, bad);
+  bsync<NW>();
   gj3_steps<NW, 0>(nb, sm, w, bad);
-  // every wave computed the same pivot blocks
-  if (bad && threadIdx.x == 0) sm.flag |= kFlagNotPD;
+  if (bad && lane3() == 0) atomicOr(&sm.flag, kFlagNotPD);
   bsync<NW>();
 }
 
