@@ -148,16 +148,13 @@ __global__ void k_cell_balance_final(const double* __restrict__ partial, int nb,
 // is then the row's componentwise backward error |G X - r| / (|G||X| + |r|)
 // of the interface solve, which cancellation in an ill-conditioned system
 // does not inflate.
-__global__ void __launch_bounds__(64) k_jumps(Geo g, const Iface* __restrict__ ifc,
-                                              const Seed* __restrict__ basis,
-                                              const double* __restrict__ K,
-                                              const double* __restrict__ p,
-                                              const double* __restrict__ gflux,
-                                              double* __restrict__ mom,
-                                              unsigned long long* __restrict__ jmax, double tol,
-                                              int* flags, JumpTerms tr) {
-  const Iface F = ifc[blockIdx.x];
-  const int L = threadIdx.x;
+// The measures of one interface by one wave; the row maxima are returned
+// to lane 0's worst[].
+__device__ __forceinline__ void jumps_one(const Geo& g, const Iface F, const Seed* __restrict__ basis,
+                                          const double* __restrict__ K, const double* __restrict__ p,
+                                          const double* __restrict__ gflux, double* __restrict__ mom,
+                                          const JumpTerms& tr, double worst[2]) {
+  const int L = threadIdx.x & 63;
   const int qi = 2 * F.axis + 1, qj = 2 * F.axis;
   int ilo[3], ihi[3], jlo[3], jhi[3];
   iface_box(g, F.i, ilo, ihi);
@@ -177,7 +174,6 @@ __global__ void __launch_bounds__(64) k_jumps(Geo g, const Iface* __restrict__ i
   const int tstep = NG > 1 ? nf : 64;
   const int ni = tr.X ? tr.seed_off[F.i + 1] - tr.seed_off[F.i] : 0;
   const int nseed = tr.X ? ni + tr.seed_off[F.j + 1] - tr.seed_off[F.j] : 0;
-  double worst[2] = {0.0, 0.0};
   for (int rr = 0; rr < 2 * F.nbasis; ++rr) {
     const int kind = rr / F.nbasis;  // 0 flux, 1 pressure
     const Seed mu = basis[F.basis0 + rr % F.nbasis];
@@ -236,10 +232,39 @@ __global__ void __launch_bounds__(64) k_jumps(Geo g, const Iface* __restrict__ i
     // a NaN ratio counts as the worst
     worst[kind] = (ratio == ratio) ? fmax(worst[kind], ratio) : INFINITY;
   }
-  if (L == 0) {
-    atomicMax(&jmax[0], dbits(worst[0]));
-    atomicMax(&jmax[1], dbits(worst[1]));
-    if (tol > 0.0 && !(fmax(worst[0], worst[1]) <= tol)) atomicOr(flags, kFlagSingular);
+}
+
+// Four waves per workgroup, each taking interfaces in a grid-stride loop;
+// the workgroup's maxima go out with one atomic pair (atomics of every
+// interface on the same two words serialise in L2).
+__global__ void __launch_bounds__(256) k_jumps(Geo g, const Iface* __restrict__ ifc, int nifc,
+                                               const Seed* __restrict__ basis,
+                                               const double* __restrict__ K,
+                                               const double* __restrict__ p,
+                                               const double* __restrict__ gflux,
+                                               double* __restrict__ mom,
+                                               unsigned long long* __restrict__ jmax, double tol,
+                                               int* flags, JumpTerms tr) {
+  __shared__ double wmax[4][2];
+  const int wv = threadIdx.x >> 6;
+  double worst[2] = {0.0, 0.0};
+  for (int f = blockIdx.x * 4 + wv; f < nifc; f += gridDim.x * 4)
+    jumps_one(g, ifc[f], basis, K, p, gflux, mom, tr, worst);
+  if ((threadIdx.x & 63) == 0) {
+    wmax[wv][0] = worst[0];
+    wmax[wv][1] = worst[1];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double w0 = 0.0, w1 = 0.0;
+    for (int u = 0; u < 4; ++u) {
+      // a NaN or infinite ratio wins
+      w0 = (wmax[u][0] == wmax[u][0]) ? fmax(w0, wmax[u][0]) : INFINITY;
+      w1 = (wmax[u][1] == wmax[u][1]) ? fmax(w1, wmax[u][1]) : INFINITY;
+    }
+    atomicMax(&jmax[0], dbits(w0));
+    atomicMax(&jmax[1], dbits(w1));
+    if (tol > 0.0 && !(fmax(w0, w1) <= tol)) atomicOr(flags, kFlagSingular);
   }
 }
 
@@ -326,7 +351,8 @@ hipError_t launch_jumps(const Geo& g, const Iface* ifc, int nifc, const Seed* ba
   if (nifc <= 0) return hipSuccess;
   JumpTerms tr{};
   if (terms) tr = *terms;
-  hipLaunchKernelGGL(k_jumps, dim3(nifc), dim3(64), 0, s, g, ifc, basis, K, p, gflux, mom, jmax,
+  const int nblk = std::min((nifc + 3) / 4, 2048);
+  hipLaunchKernelGGL(k_jumps, dim3(nblk), dim3(256), 0, s, g, ifc, nifc, basis, K, p, gflux, mom, jmax,
                      tol, flags, tr);
   return hipGetLastError();
 }
