@@ -124,6 +124,26 @@ __global__ void __launch_bounds__(256) k_rect_gemm(double* __restrict__ base,
   rect_tile<TM, TN, KC>(base, tasks[task], S, blockIdx.x - task * per, smem);
 }
 
+// Two independent groups of products of different shapes (and the same k)
+// in one launch: the first na * (tiles of SA) workgroups take group A.
+template <int TM, int TN, int KC>
+__global__ void __launch_bounds__(256) k_rect_gemm2(double* __restrict__ base,
+                                                    const BcrGemm* __restrict__ ta, int na, RectShape SA,
+                                                    const BcrGemm* __restrict__ tb, RectShape SB) {
+  extern __shared__ double smem[];
+  const int pa = (SA.m / TM) * (SA.n / TN);
+  int b = blockIdx.x;
+  if (b < na * pa) {
+    const int task = b / pa;
+    rect_tile<TM, TN, KC>(base, ta[task], SA, b - task * pa, smem);
+  } else {
+    b -= na * pa;
+    const int pb = (SB.m / TM) * (SB.n / TN);
+    const int task = b / pb;
+    rect_tile<TM, TN, KC>(base, tb[task], SB, b - task * pb, smem);
+  }
+}
+
 // base[0, n) = 0; then (second kernel) base[ones[i]] = 1 for the listed
 // offsets (identity blocks and padding, unit right-hand-side columns).
 __global__ void k_fill_zero(double* __restrict__ base, long long n) {
@@ -211,6 +231,33 @@ hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const
     return rect_launch<64, 64, 32>(base, tasks, ntask, S, s);
   if (S.k % 64 == 0) return rect_launch<32, 32, 64>(base, tasks, ntask, S, s);
   return rect_launch<32, 32, 32>(base, tasks, ntask, S, s);
+}
+
+namespace {
+template <int TM, int TN, int KC>
+hipError_t rect_launch2(double* base, const BcrGemm* ta, int na, const RectShape& SA, const BcrGemm* tb,
+                        int nb, const RectShape& SB, hipStream_t s) {
+  const long long n = (long long)na * (SA.m / TM) * (SA.n / TN) + (long long)nb * (SB.m / TM) * (SB.n / TN);
+  if (n > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * rect_lds_doubles<TM, TN, KC>();
+  hipLaunchKernelGGL((k_rect_gemm2<TM, TN, KC>), dim3((unsigned)n), dim3(256), lds, s, base, ta, na, SA, tb,
+                     SB);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_rect_gemm2(double* base, const BcrGemm* ta, int na, const RectShape& SA,
+                             const BcrGemm* tb, int nb, const RectShape& SB, hipStream_t s) {
+  if (na <= 0) return launch_rect_gemm(base, tb, nb, SB, s);
+  if (nb <= 0) return launch_rect_gemm(base, ta, na, SA, s);
+  for (const RectShape* S : {&SA, &SB})
+    if (S->m % 32 || S->n % 32 || S->k % 32 || S->m <= 0 || S->n <= 0 || S->k <= 0) return hipErrorInvalidValue;
+  if (SA.k != SB.k) return hipErrorInvalidValue;
+  const long long t64 = (long long)na * (SA.m / 64) * (SA.n / 64) + (long long)nb * (SB.m / 64) * (SB.n / 64);
+  if (SA.m % 64 == 0 && SA.n % 64 == 0 && SB.m % 64 == 0 && SB.n % 64 == 0 && t64 >= 512)
+    return rect_launch2<64, 64, 32>(base, ta, na, SA, tb, nb, SB, s);
+  if (SA.k % 64 == 0) return rect_launch2<32, 32, 64>(base, ta, na, SA, tb, nb, SB, s);
+  return rect_launch2<32, 32, 32>(base, ta, na, SA, tb, nb, SB, s);
 }
 
 hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,

@@ -166,10 +166,13 @@ std::vector<SOp> schedule(int Ml) {
 
 // One launch of the solver.
 struct LscLaunch {
-  int kind;  // 0 inverses, 1 rectangular products, 2 block-vector products (outer)
+  int kind;  // 0 inverses, 1 rectangular products, 2 block-vector products (outer),
+             // 3 two independent groups of products (second: off2, cnt2, shape2)
   int off, cnt;
   int n, ld;        // inverses
   RectShape shape;  // products
+  int off2, cnt2;
+  RectShape shape2;
 };
 
 struct Lsc {
@@ -227,6 +230,25 @@ struct Builder {
     rect.insert(rect.end(), t.begin(), t.end());
     L.push_back(o);
   }
+  void prod2(std::vector<LscLaunch>& L, const std::vector<BcrGemm>& ta, const RectShape& sa,
+             const std::vector<BcrGemm>& tb, const RectShape& sb) {
+    if (ta.empty() || tb.empty()) {
+      prod(L, ta, sa);
+      prod(L, tb, sb);
+      return;
+    }
+    LscLaunch o{};
+    o.kind = 3;
+    o.off = (int)rect.size();
+    o.cnt = (int)ta.size();
+    o.shape = sa;
+    rect.insert(rect.end(), ta.begin(), ta.end());
+    o.off2 = (int)rect.size();
+    o.cnt2 = (int)tb.size();
+    o.shape2 = sb;
+    rect.insert(rect.end(), tb.begin(), tb.end());
+    L.push_back(o);
+  }
   void vec(std::vector<LscLaunch>& L, const std::vector<BcrGemv>& t) {
     if (t.empty()) return;
     LscLaunch o{};
@@ -261,22 +283,21 @@ struct Builder {
       T2.push_back(scr[i] + so + (long long)n1 * n2);
     }
     rinv(L, A, scr, n1, ld, so2);
-    std::vector<BcrGemm> t;
+    // T1 = A' B and T2 = C A' are independent: one launch
+    std::vector<BcrGemm> t, u;
     for (size_t i = 0; i < blk.size(); ++i) t.push_back(BcrGemm{T1[i], -1, A[i], B[i], -1, -1, 1.0, 0.0});
-    prod(L, t, RectShape{n1, n2, n1, ld, ld, n2});
-    t.clear();
-    for (size_t i = 0; i < blk.size(); ++i) t.push_back(BcrGemm{T2[i], -1, C[i], A[i], -1, -1, 1.0, 0.0});
-    prod(L, t, RectShape{n2, n1, n1, ld, ld, n1});
+    for (size_t i = 0; i < blk.size(); ++i) u.push_back(BcrGemm{T2[i], -1, C[i], A[i], -1, -1, 1.0, 0.0});
+    prod2(L, t, RectShape{n1, n2, n1, ld, ld, n2}, u, RectShape{n2, n1, n1, ld, ld, n1});
     t.clear();
     for (size_t i = 0; i < blk.size(); ++i) t.push_back(BcrGemm{D[i], D[i], C[i], T1[i], -1, -1, -1.0, 0.0});
     prod(L, t, RectShape{n2, n2, n1, ld, n2, ld});
     rinv(L, D, scr, n2, ld, so2);
+    // B' = -T1 S^-1 and C' = -S^-1 T2 likewise
     t.clear();
+    u.clear();
     for (size_t i = 0; i < blk.size(); ++i) t.push_back(BcrGemm{B[i], -1, T1[i], D[i], -1, -1, -1.0, 0.0});
-    prod(L, t, RectShape{n1, n2, n2, n2, ld, ld});
-    t.clear();
-    for (size_t i = 0; i < blk.size(); ++i) t.push_back(BcrGemm{C[i], -1, D[i], T2[i], -1, -1, -1.0, 0.0});
-    prod(L, t, RectShape{n2, n1, n2, ld, n1, ld});
+    for (size_t i = 0; i < blk.size(); ++i) u.push_back(BcrGemm{C[i], -1, D[i], T2[i], -1, -1, -1.0, 0.0});
+    prod2(L, t, RectShape{n1, n2, n2, n2, ld, ld}, u, RectShape{n2, n1, n2, ld, n1, ld});
     t.clear();
     for (size_t i = 0; i < blk.size(); ++i) t.push_back(BcrGemm{A[i], A[i], B[i], T2[i], -1, -1, -1.0, 0.0});
     prod(L, t, RectShape{n1, n1, n2, ld, n1, ld});
@@ -664,6 +685,9 @@ hipError_t run(Lsc* L, const std::vector<LscLaunch>& ops, int* flags, hipStream_
       e = launch_bcr_inv(L->buf, L->d_offs + o.off, L->d_npiv + o.off, o.cnt, o.n, o.ld, flags, s);
     else if (o.kind == 1)
       e = launch_rect_gemm(L->buf, L->d_rect + o.off, o.cnt, o.shape, s);
+    else if (o.kind == 3)
+      e = launch_rect_gemm2(L->buf, L->d_rect + o.off, o.cnt, o.shape, L->d_rect + o.off2, o.cnt2,
+                            o.shape2, s);
     else
       e = launch_bcr_gemv(L->buf + L->P_out, L->buf + L->V_out, L->d_gemv + o.off, o.cnt, L->bo, s);
     if (e != hipSuccess) return e;

@@ -275,6 +275,9 @@ struct RectShape {
 // C = [C0] + al1 A1 B1 [+ al2 A2 B2], offsets into one base array (BcrGemm)
 hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
                             hipStream_t s);
+// two independent groups of products with the same k in one launch
+hipError_t launch_rect_gemm2(double* base, const BcrGemm* ta, int na, const RectShape& SA,
+                             const BcrGemm* tb, int nb, const RectShape& SB, hipStream_t s);
 // base[0, n) = 0, then base[ones[i]] = 1
 hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,
                             hipStream_t s);
