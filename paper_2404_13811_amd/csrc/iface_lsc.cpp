@@ -202,6 +202,16 @@ struct Lsc {
 
 namespace {
 
+// Leading part of an n x n block (n > kBcrInvMax) in the recursive
+// two-by-two inverse: the largest kBcrInvMax * 2^j below n, so that the
+// leading part splits into whole leaves and the recursion takes as few
+// dependent launches as it can (640 = 512 + 128: five leaves of 128).
+int rinv_split(int n) {
+  int n1 = kBcrInvMax;
+  while (2 * n1 < n) n1 *= 2;
+  return n1;
+}
+
 struct Builder {
   std::vector<long long> offs;
   std::vector<int> npiv;
@@ -270,7 +280,7 @@ struct Builder {
       inv(L, blk, n, ld);
       return;
     }
-    const int n1 = n / 2 > kBcrInvMax ? (int)up32(n / 2) : kBcrInvMax;
+    const int n1 = rinv_split(n);
     const int n2 = n - n1;
     const long long so2 = so + 2LL * n1 * n2;
     std::vector<long long> A, B, C, D, T1, T2;
@@ -307,7 +317,7 @@ struct Builder {
 // Scratch doubles the recursive inverse of an n x n block needs.
 long long rinv_scratch(int n) {
   if (n <= kBcrInvMax) return 0;
-  const int n1 = n / 2 > kBcrInvMax ? (int)up32(n / 2) : kBcrInvMax;
+  const int n1 = rinv_split(n);
   const int n2 = n - n1;
   return 2LL * n1 * n2 + std::max(rinv_scratch(n1), rinv_scratch(n2));
 }
