@@ -339,13 +339,19 @@ mrcm_status mrcm_set_checkpointing(mrcm_ctx* ctx, int on);
  * vector-Jacobian product of the whole discrete map (basis, particular
  * problems, interface system, MRCM-O assembly, smoothing sweeps, outputs),
  * computed on the device by the reverse of each step: adjoint local solves
- * with the cached FP64 factors (the local matrices are symmetric), the
+ * with the cached factors (the local matrices are symmetric), the
  * transposed interface system by the same cyclic reduction, the smoothing
- * phases in reverse order recomputed from the checkpoints.  Device pointers.
- * Requirements: MRCM_FP64, 2-D boxes whose lines have <= 32 cells, the block
- * cyclic reduction interface solver, equal Robin parameters in both stages,
+ * phases in reverse order recomputed from the checkpoints.  The local
+ * solves take the precision of the forward solve: with MRCM_FP32_REFINE,
+ * the cached FP32 factors refined in FP64 to the same tolerance (and the
+ * same iteration limit, MRCM_ENOCONV when it is reached), every forward box
+ * solution recomputed by the forward pass's own refinement; the interface
+ * system stays FP64.  Device pointers.
+ * Requirements: 2-D boxes whose lines have <= 32 cells, the block cyclic
+ * reduction interface solver, equal Robin parameters in both stages,
  * checkpointing on for every smoothing step since the last
- * mrcm_solve_interface.  Errors: MRCM_EINVAL, MRCM_ESTATE, MRCM_EDEVICE. */
+ * mrcm_solve_interface.  Errors: MRCM_EINVAL, MRCM_ESTATE, MRCM_ENOCONV,
+ * MRCM_EDEVICE. */
 mrcm_status mrcm_adjoint(mrcm_ctx* ctx, const double* dJdp_dev, const double* dJdflux_dev,
                          double* dJdlogK_dev);
 

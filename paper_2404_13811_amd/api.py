@@ -276,10 +276,10 @@ class _SolveFn(torch.autograd.Function):
     """(pressure, flux) = MRCM-OS(log K); backward = mrcm_adjoint."""
 
     @staticmethod
-    def forward(actx, logk, wl, nsmooth):
+    def forward(actx, logk, wl, nsmooth, precision):
         ctx = create(wl.dim, wl.ncell, wl.h)
         try:
-            configure(ctx, wl, "fp64")
+            configure(ctx, wl, precision)
             set_permeability(ctx, logk.detach().to(device="cuda", dtype=torch.float64).contiguous())
             set_checkpointing(ctx, True)
             build_basis(ctx)
@@ -301,14 +301,15 @@ class _SolveFn(torch.autograd.Function):
     @staticmethod
     def backward(actx, gp, gfl):
         g = adjoint(actx.mrcm, gp, gfl)
-        return g, None, None
+        return g, None, None, None
 
 
-def solve_differentiable(logk, wl, nsmooth=None):
+def solve_differentiable(logk, wl, nsmooth=None, precision="fp64"):
     """MRCM-OS pressure and face velocities as differentiable functions of
     log K (a CUDA float64 tensor of N values); the gradient runs the device
-    adjoint.  The workload record supplies everything else."""
-    return _SolveFn.apply(logk, wl, nsmooth)
+    adjoint in the forward solve's precision ("fp64" or "fp32_refine").  The
+    workload record supplies everything else."""
+    return _SolveFn.apply(logk, wl, nsmooth, precision)
 
 
 def get_coefficients(ctx, out=None):

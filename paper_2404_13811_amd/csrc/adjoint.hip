@@ -1,6 +1,7 @@
 // Reverse mode of the MRCM-OS map log K -> (pressure, face velocities) on
-// the 2-D one-wave-per-box path (FP64): the vector-Jacobian product
-// dJ/dlog K for given dJ/dp and dJ/d(face velocity).
+// the 2-D one-wave-per-box path: the vector-Jacobian product dJ/dlog K for
+// given dJ/dp and dJ/d(face velocity), in the FP64 form or the FP32 form
+// with FP64 refinement (the precision of the forward solve).
 //
 // The forward steps are replayed in reverse order (Algorithm 1 backwards):
 //   outputs -> smoothing phases (last first; Section 3) -> MRCM-O assembly
@@ -8,7 +9,10 @@
 //   transposed) -> moments -> basis seeds and particular problems (eq.
 //   informed_space, eq111dbar-eq122dbar).
 // Every local system A(K) x = b(K, lambda) is symmetric, so its adjoint
-// system A mu = xbar reuses the cached block inverses; the K-dependence of
+// system A mu = xbar reuses the cached block inverses (in the FP32 form:
+// the cached FP32 inverses of the scaled matrix, refined in FP64 to the
+// forward solve's tolerance, and every forward box solution recomputed by
+// the same refinement as the forward pass); the K-dependence of
 // A and b enters through the per-face coefficients
 //   interior face  T   = |e| K_H / h                 Tbar   = -(mu_c - mu_o)(x_c - x_o)
 //   Robin face     T^R = |e| / (h / (2 K_c) + beta)  T^Rbar = mu_c (lambda - x_c)
@@ -17,7 +21,7 @@
 // smoothing phase is kept by the forward pass (checkpoints); each phase's
 // box solutions are recomputed from them.  Per-cell gradients accumulate
 // with atomic adds (boxes overlap).
-#include "wave_common.h"
+#include "wave32_common.h"
 
 namespace mrcm {
 namespace {
@@ -196,6 +200,16 @@ __global__ void k_adj_mean(const double* __restrict__ v, int n, double* __restri
 // --------------------------------------------------------------- smoothing
 constexpr int kAdjNT = 256;
 
+// Doubles before the adjoint's own arrays in the FP32 forms' LDS: the FP32
+// smoothing box (carve_smooth + carve_smooth_r), a refinement box of nrhs
+// right-hand sides (carve_r), each rounded up to 16 bytes.
+__host__ __device__ inline size_t adj_smooth32_off(int m0, int m1) {
+  return (smooth32_lds_bytes(m0, m1) + 15) / 16 * 2;
+}
+__host__ __device__ inline size_t adj_box32_off(int m0, int m1, int nrhs) {
+  return (boxr_bytes(m0, m1, nrhs, nrhs) + 15) / 16 * 2;
+}
+
 // One right-hand side in s.X solved by one wave with the two-ended sweep of
 // the cached factors (forward inverses below the meeting block, backward
 // inverses above it and Z_m): the same arithmetic as the forward smoothing
@@ -208,6 +222,9 @@ __device__ __forceinline__ void box_solve(const Box& B, const double* Wf, const 
 }
 
 // One colour phase in reverse.  p_in / gf_in: the state before the phase.
+// F32: the FP32 form (fac, fact and tcoup unused; the FP32 factors and the
+// refinement settings in rf).
+template <bool F32>
 __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restrict__ boxes,
                                                        const int* __restrict__ members,
                                                        const double* __restrict__ K,
@@ -215,7 +232,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
                                                        const double* __restrict__ bcv, double beta,
                                                        const double* __restrict__ fac,
                                                        const double* __restrict__ fact,
-                                                       const double* __restrict__ tcoup,
+                                                       const double* __restrict__ tcoup, Adj32 rf,
                                                        const double* __restrict__ p_in,
                                                        const double* __restrict__ gf_in,
                                                        double* __restrict__ pb,
@@ -223,18 +240,36 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
                                                        double* __restrict__ Kb) {
   constexpr int NT = kAdjNT;
   extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmemF sm32;
   const Box B = boxes[members[blockIdx.x]];
   SmoothLds r = carve_smooth(dsm, B);
   const int m0 = r.b.m0, m1 = r.b.m1, nc = m0 * m1, ns = 2 * (m0 + m1);
-  double* xs = dsm + smooth_lds_doubles(m0, m1);  // forward solution
+  BoxR R{};
+  if (F32) R = carve_smooth_r(dsm, r);
+  double* xs = dsm + (F32 ? adj_smooth32_off(m0, m1) : smooth_lds_doubles(m0, m1));  // forward solution
   double* mu = xs + nc;                             // adjoint right-hand side / solution
   double* lb = mu + nc;                             // lambda_bar per box-side face
   const int tid = threadIdx.x;
-  // (a) forward solution of this box from the checkpointed state
-  stage_smooth<NT>(g, B, r, K, p_in, f, gf_in, bcv, tcoup);
-  __syncthreads();
-  smooth_rhs<NT>(g, B, r, beta, r.b.X);
-  if (tid < 64) box_solve(B, fac + B.fac, fact + B.fac, r.b, r.b.Z);
+  if (F32 && tid == 0) sm32.flag = 0;
+  // (a) forward solution of this box from the checkpointed state (the
+  // forward smoothing step's arithmetic)
+  if (F32) {
+    stage_smooth<NT>(g, B, r, K, p_in, f, gf_in, bcv, nullptr);
+    __syncthreads();
+    smooth_rhs<NT>(g, B, r, beta, R.Bv);
+    coef_box<NT>(g, B, beta, R.b);
+    scale_box<NT>(B, R);
+    if (tid < 64) {
+      double om = 0.0;
+      const int it = refine<true>(g, B, R, rf.fac + B.fac, 1, nullptr, beta, rf.tol, rf.max_refine, om, sm32);
+      record_refine(it, om, rf.iters, rf.resid);
+    }
+  } else {
+    stage_smooth<NT>(g, B, r, K, p_in, f, gf_in, bcv, tcoup);
+    __syncthreads();
+    smooth_rhs<NT>(g, B, r, beta, r.b.X);
+    if (tid < 64) box_solve(B, fac + B.fac, fact + B.fac, r.b, r.b.Z);
+  }
   __syncthreads();
   for (int e = tid; e < nc; e += NT) {
     xs[e] = r.b.X[e];
@@ -296,9 +331,21 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
     __syncthreads();
   }
   // (c) adjoint solve A mu = xbar (A symmetric: cached inverses)
-  BoxLds sm = r.b;
-  sm.X = mu;
-  if (tid < 64) box_solve(B, fac + B.fac, fact + B.fac, sm, r.b.Z);
+  if (F32) {
+    for (int e = tid; e < nc; e += NT) R.Bv[e] = mu[e];
+    __syncthreads();
+    if (tid < 64) {
+      double om = 0.0;
+      const int it = refine<true>(g, B, R, rf.fac + B.fac, 1, nullptr, beta, rf.tol, rf.max_refine, om, sm32);
+      record_refine(it, om, rf.iters, rf.resid);
+    }
+    __syncthreads();
+    for (int e = tid; e < nc; e += NT) mu[e] = R.b.X[e];
+  } else {
+    BoxLds sm = r.b;
+    sm.X = mu;
+    if (tid < 64) box_solve(B, fac + B.fac, fact + B.fac, sm, r.b.Z);
+  }
   __syncthreads();
   // (d) K terms of the box matrix and right-hand side; lambda_bar of the
   // Robin faces
@@ -354,6 +401,10 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
       kadd(Kb, g, cx, cy, lbar * uj * rd.dbt_c);
       (void)ci;
     }
+  }
+  if (F32) {
+    __syncthreads();
+    if (tid == 0 && sm32.flag) atomicOr(rf.flags, sm32.flag);
   }
 }
 
@@ -461,12 +512,14 @@ __global__ void k_adj_moments(Geo g, const Iface* __restrict__ ifc, const Seed* 
 // ------------------------------------------------------------ seeds (basis)
 // Per oversampled box: recompute the seed solutions P_k, form their adjoint
 // right-hand sides (Omega_i restriction and Gamma traces u, phi, beta),
-// solve with the cached inverses and accumulate the K terms.
+// solve with the cached inverses and accumulate the K terms.  F32: the
+// FP32 form (fac and fact unused).
+template <bool F32>
 __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__ boxes,
                                                   const Seed* __restrict__ seeds,
                                                   const double* __restrict__ K, double beta,
                                                   const double* __restrict__ fac,
-                                                  const double* __restrict__ fact,
+                                                  const double* __restrict__ fact, Adj32 rf,
                                                   const double* __restrict__ X,
                                                   const double* __restrict__ pb,
                                                   const double* __restrict__ tr_u,
@@ -475,16 +528,24 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
                                                   const double* __restrict__ tr_betab,
                                                   double* __restrict__ Kb) {
   extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmemF sm32;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
   const int nrhs = B.nrhs;
-  BoxLds s = carve(dsm, B, nrhs);
+  BoxR R{};
+  BoxLds s;
+  double* xs;  // nrhs x nc forward solutions
+  if (F32) {
+    R = carve_r(dsm, B, max(nrhs, 1), max(nrhs, 1));
+    s = R.b;
+    xs = dsm + adj_box32_off(s.m0, s.m1, max(nrhs, 1));
+  } else {
+    s = carve(dsm, B, nrhs);
+    xs = dsm + box_lds_doubles(s.m0, s.m1, nrhs);
+  }
   const int nc = B.ncell;
-  double* xs = dsm + box_lds_doubles(s.m0, s.m1, nrhs);  // nrhs x nc forward solutions
+  if (F32 && L == 0) sm32.flag = 0;
   load_box(g, B, K, beta, s);
-  // seed right-hand sides (T^R times the seed on its side)
-  for (int e = L; e < nrhs * nc; e += 64) s.X[e] = 0.0;
-  wsync();
   auto seed_lam = [&](int k, int q, int t) -> double {
     const Seed sd = seeds[B.seed0 + k];
     if (sd.side != q) return 0.0;
@@ -495,22 +556,35 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
     c[2] = 0;
     return seed_value(g, sd, B.lo, B.hi, c);
   };
-  for (int k = 0; k < nrhs; ++k) {
-    const Seed sd = seeds[B.seed0 + k];
-    const int a = sd.side >> 1, so = sd.side & 1;
-    const int nf = a == 0 ? s.m1 : s.m0;
-    for (int t = L; t < nf; t += 64) {
-      const int cx = a == 0 ? (so ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
-      const int cy = a == 1 ? (so ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
-      const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
-      const RobinD rd = robin_d(g, a, kat(s, B, cx, cy), kat(s, B, ox, oy), beta);
-      s.X[k * nc + bloc(B, s, cx, cy)] = rd.TR * seed_lam(k, sd.side, t);
-    }
-  }
-  wsync();
   const double* Wf = fac + B.fac;
   const double* Wt = fact + B.fac;
-  twisted_cached(B, Wf, Wt, nrhs, s);
+  if (F32) {
+    // the forward basis kernel's refinement of the seed problems
+    scale_box(B, R);
+    if (nrhs > 0) {
+      double om = 0.0;
+      const int it = refine<false>(g, B, R, rf.fac + B.fac, nrhs, seeds, beta, rf.tol, rf.max_refine, om, sm32);
+      record_refine(it, om, rf.iters, rf.resid);
+    }
+  } else {
+    // seed right-hand sides (T^R times the seed on its side)
+    for (int e = L; e < nrhs * nc; e += 64) s.X[e] = 0.0;
+    wsync();
+    for (int k = 0; k < nrhs; ++k) {
+      const Seed sd = seeds[B.seed0 + k];
+      const int a = sd.side >> 1, so = sd.side & 1;
+      const int nf = a == 0 ? s.m1 : s.m0;
+      for (int t = L; t < nf; t += 64) {
+        const int cx = a == 0 ? (so ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
+        const int cy = a == 1 ? (so ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
+        const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
+        const RobinD rd = robin_d(g, a, kat(s, B, cx, cy), kat(s, B, ox, oy), beta);
+        s.X[k * nc + bloc(B, s, cx, cy)] = rd.TR * seed_lam(k, sd.side, t);
+      }
+    }
+    wsync();
+    twisted_cached(B, Wf, Wt, nrhs, s);
+  }
   wsync();
   for (int e = L; e < nrhs * nc; e += 64) {
     xs[e] = s.X[e];
@@ -578,34 +652,62 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
     wsync();
   }
   // adjoint solves with the cached factors (A symmetric)
-  twisted_cached(B, Wf, Wt, nrhs, s);
+  if (F32) {
+    for (int e = L; e < nrhs * nc; e += 64) R.Bv[e] = s.X[e];
+    wsync();
+    if (nrhs > 0) {
+      double om = 0.0;
+      const int it = refine<false>(g, B, R, rf.fac + B.fac, nrhs, nullptr, beta, rf.tol, rf.max_refine, om, sm32);
+      record_refine(it, om, rf.iters, rf.resid);
+    }
+  } else {
+    twisted_cached(B, Wf, Wt, nrhs, s);
+  }
   wsync();
   box_matrix_adjoint<64>(
       g, B, s, xs, s.X, nrhs, beta, seed_lam, [](int, int) { return 0.0; },
       [](int, int, int, double) {}, Kb);
+  if (F32) {
+    wsync();
+    if (L == 0 && sm32.flag) atomicOr(rf.flags, sm32.flag);
+  }
 }
 
 // --------------------------------------------------------------- particular
 // Per subdomain: the particular solution pbar is stored; its adjoint
 // right-hand side collects pb on Omega_i and the Gamma traces ubar, pibar.
+// F32: the FP32 form (fac unused).
+template <bool F32>
 __global__ void __launch_bounds__(64) k_adj_particular(Geo g, const Box* __restrict__ boxes,
                                                        const double* __restrict__ K,
                                                        const double* __restrict__ bcv, double beta,
-                                                       const double* __restrict__ fac,
+                                                       const double* __restrict__ fac, Adj32 rf,
                                                        const double* __restrict__ pbar,
                                                        const double* __restrict__ pb,
                                                        const double* __restrict__ ubarb,
                                                        const double* __restrict__ pibarb,
                                                        double* __restrict__ Kb) {
   extern __shared__ __align__(16) double dsm[];
+  __shared__ WaveSmemF sm32;
   const Box B = boxes[blockIdx.x];
   const int L = lane_id();
-  BoxLds s = carve(dsm, B, 1);
+  BoxR R{};
+  BoxLds s;
+  double* xs;
+  if (F32) {
+    R = carve_r(dsm, B, 1, 1);
+    s = R.b;
+    xs = dsm + adj_box32_off(s.m0, s.m1, 1);
+  } else {
+    s = carve(dsm, B, 1);
+    // the single-right-hand-side sweep stages through 2 x NBW doubles at s.Z
+    xs = dsm + box_lds_doubles(s.m0, s.m1, 1) + NBW;
+  }
   const int nc = B.ncell;
-  // the single-right-hand-side sweep stages through 2 x NBW doubles at s.Z
-  double* xs = dsm + box_lds_doubles(s.m0, s.m1, 1) + NBW;
   double* bc = xs + nc;  // boundary value per box-side face
+  if (F32 && L == 0) sm32.flag = 0;
   load_box(g, B, K, beta, s);
+  if (F32) scale_box(B, R);
   const int m0 = s.m0, m1 = s.m1, ns = 2 * (m0 + m1);
   for (int u = L; u < ns; u += 64) {
     const int q = u < 2 * m1 ? (u < m1 ? 0 : 1) : (u < 2 * m1 + m0 ? 2 : 3);
@@ -650,10 +752,22 @@ __global__ void __launch_bounds__(64) k_adj_particular(Geo g, const Box* __restr
     }
     wsync();
   }
-  sweep1(B, fac + B.fac, s, s.Z);
+  if (F32) {
+    for (int e = L; e < nc; e += 64) R.Bv[e] = s.X[e];
+    wsync();
+    double om = 0.0;
+    const int it = refine<true>(g, B, R, rf.fac + B.fac, 1, nullptr, beta, rf.tol, rf.max_refine, om, sm32);
+    record_refine(it, om, rf.iters, rf.resid);
+  } else {
+    sweep1(B, fac + B.fac, s, s.Z);
+  }
   box_matrix_adjoint<64>(
       g, B, s, xs, s.X, 1, beta, [](int, int, int) { return 0.0; },
       [&](int q, int t) { return bc[side_off(s, q) + t]; }, [](int, int, int, double) {}, Kb);
+  if (F32) {
+    wsync();
+    if (L == 0 && sm32.flag) atomicOr(rf.flags, sm32.flag);
+  }
 }
 
 __global__ void k_adj_logk(const double* __restrict__ K, const double* __restrict__ Kb, int n,
@@ -693,16 +807,19 @@ __global__ void k_bcr_gather_t(const double* __restrict__ xv, const int* __restr
 
 }  // namespace
 
-size_t adj_smooth_lds_bytes(int m0, int m1) {
-  return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * (size_t)m0 * m1 + 2 * (size_t)(m0 + m1));
+size_t adj_smooth_lds_bytes(int m0, int m1, bool f32) {
+  const size_t own = 2 * (size_t)m0 * m1 + 2 * (size_t)(m0 + m1);
+  return sizeof(double) * ((f32 ? adj_smooth32_off(m0, m1) : smooth_lds_doubles(m0, m1)) + own);
 }
 
-size_t adj_basis_lds_bytes(int m0, int m1, int nrhs) {
-  return sizeof(double) * (box_lds_doubles(m0, m1, nrhs) + (size_t)nrhs * m0 * m1);
+size_t adj_basis_lds_bytes(int m0, int m1, int nrhs, bool f32) {
+  const size_t own = (size_t)nrhs * m0 * m1;
+  return sizeof(double) * ((f32 ? adj_box32_off(m0, m1, nrhs) : box_lds_doubles(m0, m1, nrhs)) + own);
 }
 
-size_t adj_part_lds_bytes(int m0, int m1) {
-  return sizeof(double) * (box_lds_doubles(m0, m1, 1) + NBW + (size_t)m0 * m1 + 2 * (size_t)(m0 + m1));
+size_t adj_part_lds_bytes(int m0, int m1, bool f32) {
+  const size_t own = (size_t)m0 * m1 + 2 * (size_t)(m0 + m1);
+  return sizeof(double) * ((f32 ? adj_box32_off(m0, m1, 1) : box_lds_doubles(m0, m1, 1) + NBW) + own);
 }
 
 template <typename KF>
@@ -724,13 +841,22 @@ hipError_t launch_adj_out(const Geo& g, const double* K, const double* p, const 
 hipError_t launch_adj_smooth(const Geo& g, const Box* boxes, const int* members, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
                              const double* fac, const double* fact, const double* tcoup,
-                             const double* p_in, const double* gf_in, double* pb, double* gfb,
-                             double* Kb, size_t lds, hipStream_t s) {
+                             const Adj32* f32, const double* p_in, const double* gf_in, double* pb,
+                             double* gfb, double* Kb, size_t lds, hipStream_t s) {
   if (nmem <= 0) return hipSuccess;
-  hipError_t e = lds_attr(k_adj_smooth, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_smooth, dim3(nmem), dim3(kAdjNT), lds, s, g, boxes, members, K, f, bcv,
-                     beta, fac, fact, tcoup, p_in, gf_in, pb, gfb, Kb);
+  const Adj32 rf = f32 ? *f32 : Adj32{};
+  hipError_t e;
+  if (f32) {
+    e = lds_attr(k_adj_smooth<true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_smooth<true>, dim3(nmem), dim3(kAdjNT), lds, s, g, boxes, members, K, f,
+                       bcv, beta, fac, fact, tcoup, rf, p_in, gf_in, pb, gfb, Kb);
+  } else {
+    e = lds_attr(k_adj_smooth<false>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_smooth<false>, dim3(nmem), dim3(kAdjNT), lds, s, g, boxes, members, K, f,
+                       bcv, beta, fac, fact, tcoup, rf, p_in, gf_in, pb, gfb, Kb);
+  }
   return hipGetLastError();
 }
 
@@ -756,26 +882,44 @@ hipError_t launch_adj_moments(const Geo& g, const Iface* ifc, int nifc, const Se
 
 hipError_t launch_adj_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                             const double* K, double beta, const double* fac, const double* fact,
-                            const double* X, const double* pb, const double* tr_u,
+                            const Adj32* f32, const double* X, const double* pb, const double* tr_u,
                             const double* tr_ub, const double* tr_phib, const double* tr_betab,
                             double* Kb, size_t lds, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
-  hipError_t e = lds_attr(k_adj_basis, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_basis, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac, fact,
-                     X, pb, tr_u, tr_ub, tr_phib, tr_betab, Kb);
+  const Adj32 rf = f32 ? *f32 : Adj32{};
+  hipError_t e;
+  if (f32) {
+    e = lds_attr(k_adj_basis<true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_basis<true>, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac,
+                       fact, rf, X, pb, tr_u, tr_ub, tr_phib, tr_betab, Kb);
+  } else {
+    e = lds_attr(k_adj_basis<false>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_basis<false>, dim3(nbox), dim3(64), lds, s, g, boxes, seeds, K, beta, fac,
+                       fact, rf, X, pb, tr_u, tr_ub, tr_phib, tr_betab, Kb);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_particular(const Geo& g, const Box* boxes, int nbox, const double* K,
-                                 const double* bcv, double beta, const double* fac,
+                                 const double* bcv, double beta, const double* fac, const Adj32* f32,
                                  const double* pbar, const double* pb, const double* ubarb,
                                  const double* pibarb, double* Kb, size_t lds, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
-  hipError_t e = lds_attr(k_adj_particular, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_particular, dim3(nbox), dim3(64), lds, s, g, boxes, K, bcv, beta, fac, pbar,
-                     pb, ubarb, pibarb, Kb);
+  const Adj32 rf = f32 ? *f32 : Adj32{};
+  hipError_t e;
+  if (f32) {
+    e = lds_attr(k_adj_particular<true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_particular<true>, dim3(nbox), dim3(64), lds, s, g, boxes, K, bcv, beta, fac,
+                       rf, pbar, pb, ubarb, pibarb, Kb);
+  } else {
+    e = lds_attr(k_adj_particular<false>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_particular<false>, dim3(nbox), dim3(64), lds, s, g, boxes, K, bcv, beta, fac,
+                       rf, pbar, pb, ubarb, pibarb, Kb);
+  }
   return hipGetLastError();
 }
 

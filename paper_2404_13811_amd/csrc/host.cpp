@@ -166,6 +166,7 @@ struct mrcm_ctx {
   double *a_pibarb = nullptr, *a_mean = nullptr;
   int* d_seed_sub = nullptr;
   size_t lds_adj_smooth = 0, lds_adj_basis = 0, lds_adj_part = 0;
+  size_t lds_adj32_smooth = 0, lds_adj32_basis = 0, lds_adj32_part = 0;
 
   hipEvent_t ev[12] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -659,6 +660,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   c->wave = c->d == 2;
   c->lds_basis = c->lds_part = c->lds_smooth = c->lds_factor = 0;
   c->lds_adj_smooth = c->lds_adj_basis = c->lds_adj_part = 0;
+  c->lds_adj32_smooth = c->lds_adj32_basis = c->lds_adj32_part = 0;
   for (int i = 0; i < nsub; ++i) {
     const Box& B = c->obox[i];
     const Box& P = c->pbox[i];
@@ -672,9 +674,14 @@ mrcm_status make_plan(mrcm_ctx* c) {
     c->lds32_smooth = std::max(c->lds32_smooth, wave32_smooth_lds_bytes(bm0, bm1));
     c->lds32_part = std::max(c->lds32_part, wave32_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, 1));
     if (c->d == 2) {
-      c->lds_adj_smooth = std::max(c->lds_adj_smooth, adj_smooth_lds_bytes(bm0, bm1));
-      c->lds_adj_basis = std::max(c->lds_adj_basis, adj_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
-      c->lds_adj_part = std::max(c->lds_adj_part, adj_part_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1]));
+      for (int f32 = 0; f32 < 2; ++f32) {
+        size_t& ls = f32 ? c->lds_adj32_smooth : c->lds_adj_smooth;
+        size_t& lb = f32 ? c->lds_adj32_basis : c->lds_adj_basis;
+        size_t& lp = f32 ? c->lds_adj32_part : c->lds_adj_part;
+        ls = std::max(ls, adj_smooth_lds_bytes(bm0, bm1, f32));
+        lb = std::max(lb, adj_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), f32));
+        lp = std::max(lp, adj_part_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], f32));
+      }
     }
   }
   if (c->lds_basis > 150 * 1024 || c->lds_smooth > 150 * 1024 || 2 * c->lds_part + 16 > 150 * 1024)
@@ -1590,13 +1597,18 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
   c->flags_zero = false;  // new flag-setting work may follow
   if (!dJdlogK) return fail(c, MRCM_EINVAL, "output is NULL");
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution to differentiate");
-  if (c->prec != MRCM_FP64 || !c->wave || c->d != 2)
-    return fail(c, MRCM_EINVAL, "the adjoint needs the FP64 path on 2-D boxes with lines of <= 32 cells");
+  if (!c->wave || c->d != 2)
+    return fail(c, MRCM_EINVAL, "the adjoint needs 2-D boxes with lines of <= 32 cells");
   if (!c->use_bcr)
     return fail(c, MRCM_EINVAL, "the adjoint needs the block-cyclic-reduction interface solver");
   if (c->n_ck != c->n_phase)
     return fail(c, MRCM_ESTATE, "smoothing ran without checkpointing (call mrcm_set_checkpointing first)");
-  if (c->lds_adj_basis > 150 * 1024 || c->lds_adj_smooth > 150 * 1024 || c->lds_adj_part > 150 * 1024)
+  // the precision of the forward solve: FP64, or FP32 with FP64 refinement
+  const bool r32 = c->prec == MRCM_FP32_REFINE;
+  const size_t lds_sm = r32 ? c->lds_adj32_smooth : c->lds_adj_smooth;
+  const size_t lds_bs = r32 ? c->lds_adj32_basis : c->lds_adj_basis;
+  const size_t lds_pt = r32 ? c->lds_adj32_part : c->lds_adj_part;
+  if (lds_bs > 150 * 1024 || lds_sm > 150 * 1024 || lds_pt > 150 * 1024)
     return fail(c, MRCM_EINVAL, "too many seeds per box for the adjoint kernels");
   if (c->beta_sm != c->beta_mbf)
     return fail(c, MRCM_EINVAL, "the adjoint needs equal Robin parameters in both stages");
@@ -1627,14 +1639,19 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
   HIPCHK(c, launch_fill(c->a_gfb, 0.0, (long long)ng, s));
   HIPCHK(c, launch_adj_out(g, c->K, c->p, c->bcv, dJdp, dJdflux, c->a_mean, c->a_pb, c->a_gfb,
                            c->a_Kb, s));
+  // FP32 form: cached FP32 factors of the seed / smoothing boxes (equal
+  // Robin parameters: one set) and of the particular boxes
+  const Adj32 a32 = {c->fac32, c->tol, c->max_refine, c->d_iters, c->d_resid, c->flags};
+  const Adj32 a32p = {c->facp32, c->tol, c->max_refine, c->d_iters, c->d_resid, c->flags};
   // smoothing phases, last first
   const size_t np = N;
   for (int ph = c->n_ck - 1; ph >= 0; --ph) {
     const int col = ph % (1 << g.d);
     const int m0 = c->member_off[col], m1 = c->member_off[col + 1];
     HIPCHK(c, launch_adj_smooth(g, c->d_obox, c->d_members + m0, m1 - m0, c->K, c->f, c->bcv,
-                                c->beta_sm, c->fac, c->fact, c->tco, c->ck_p + ph * np, c->ck_g + ph * ng,
-                                c->a_pb, c->a_gfb, c->a_Kb, c->lds_adj_smooth, s));
+                                c->beta_sm, c->fac, c->fact, c->tco, r32 ? &a32 : nullptr,
+                                c->ck_p + ph * np, c->ck_g + ph * ng, c->a_pb, c->a_gfb, c->a_Kb,
+                                lds_sm, s));
   }
   // MRCM-O assembly
   HIPCHK(c, launch_adj_combine(g, c->d_seed_sub, c->nX, c->X, c->Pk, c->tr_u, c->a_pb, c->a_gfb,
@@ -1667,12 +1684,12 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
                                c->a_nu, c->tr_u, c->tr_beta, c->a_trub, c->a_trphib, c->a_trbetab,
                                c->a_ubarb, c->a_pibarb, s));
   // seeds and particular problems
-  HIPCHK(c, launch_adj_basis(g, c->d_obox, g.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac, c->fact, c->X,
-                             c->a_pb, c->tr_u, c->a_trub, c->a_trphib, c->a_trbetab, c->a_Kb,
-                             c->lds_adj_basis, s));
+  HIPCHK(c, launch_adj_basis(g, c->d_obox, g.nsub, c->d_seeds, c->K, c->beta_mbf, c->fac, c->fact,
+                             r32 ? &a32 : nullptr, c->X, c->a_pb, c->tr_u, c->a_trub, c->a_trphib,
+                             c->a_trbetab, c->a_Kb, lds_bs, s));
   HIPCHK(c, launch_adj_particular(g, c->d_pbox, g.nsub, c->K, c->bcv, c->beta_mbf, c->facp,
-                                  c->pbar, c->a_pb, c->a_ubarb, c->a_pibarb, c->a_Kb,
-                                  c->lds_adj_part, s));
+                                  r32 ? &a32p : nullptr, c->pbar, c->a_pb, c->a_ubarb, c->a_pibarb,
+                                  c->a_Kb, lds_pt, s));
   HIPCHK(c, launch_adj_logk(c->K, c->a_Kb, g.ncells, dJdlogK, s));
   return check_flags(c);
 }

@@ -319,18 +319,28 @@ double lsc_bytes(const Lsc* L);
 // S, Mi, inner block, right-hand sides, gaps, gap block
 void lsc_shape(const Lsc* L, int* out);
 
-// adjoint (adjoint.hip): reverse mode of the 2-D FP64 path
-size_t adj_smooth_lds_bytes(int m0, int m1);
-size_t adj_basis_lds_bytes(int m0, int m1, int nrhs);
-size_t adj_part_lds_bytes(int m0, int m1);
+// adjoint (adjoint.hip): reverse mode of the 2-D one-wave-per-box path.
+// The FP32 form takes its cached FP32 factors of the scaled matrices and
+// refinement settings from an Adj32 (launchers: null for the FP64 form).
+struct Adj32 {
+  const float* fac;  // FP32 block inverses (smoothing / seed boxes, or particular boxes)
+  double tol;
+  int max_refine;
+  int* iters;
+  unsigned long long* resid;
+  int* flags;
+};
+size_t adj_smooth_lds_bytes(int m0, int m1, bool f32);
+size_t adj_basis_lds_bytes(int m0, int m1, int nrhs, bool f32);
+size_t adj_part_lds_bytes(int m0, int m1, bool f32);
 hipError_t launch_adj_out(const Geo& g, const double* K, const double* p, const double* bcv,
                           const double* dJdp, const double* dJdf, double* meanp, double* pb,
                           double* gfb, double* Kb, hipStream_t s);
 hipError_t launch_adj_smooth(const Geo& g, const Box* boxes, const int* members, int nmem,
                              const double* K, const double* f, const double* bcv, double beta,
                              const double* fac, const double* fact, const double* tcoup,
-                             const double* p_in, const double* gf_in, double* pb, double* gfb,
-                             double* Kb, size_t lds, hipStream_t s);
+                             const Adj32* f32, const double* p_in, const double* gf_in, double* pb,
+                             double* gfb, double* Kb, size_t lds, hipStream_t s);
 hipError_t launch_adj_combine(const Geo& g, const int* seed_sub, int nX, const double* X,
                               const double* Pk, const double* tr_u, const double* pb,
                               const double* gfb, double* Xb, double* tr_ub, hipStream_t s);
@@ -341,11 +351,11 @@ hipError_t launch_adj_moments(const Geo& g, const Iface* ifc, int nifc, const Se
                               hipStream_t s);
 hipError_t launch_adj_basis(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
                             const double* K, double beta, const double* fac, const double* fact,
-                            const double* X, const double* pb, const double* tr_u,
+                            const Adj32* f32, const double* X, const double* pb, const double* tr_u,
                             const double* tr_ub, const double* tr_phib, const double* tr_betab,
                             double* Kb, size_t lds, hipStream_t s);
 hipError_t launch_adj_particular(const Geo& g, const Box* boxes, int nbox, const double* K,
-                                 const double* bcv, double beta, const double* fac,
+                                 const double* bcv, double beta, const double* fac, const Adj32* f32,
                                  const double* pbar, const double* pb, const double* ubarb,
                                  const double* pibarb, double* Kb, size_t lds, hipStream_t s);
 hipError_t launch_adj_logk(const double* K, const double* Kb, int n, double* out, hipStream_t s);

@@ -1,6 +1,8 @@
 """Device adjoint (mrcm_adjoint) against the CPU FP64 adjoint of the
 differentiable oracle (relative L2 <= 1e-8) and against central finite
-differences of the device forward map (relative 1e-4)."""
+differences of the device forward map (relative 1e-4); the FP32+refine form
+(FP32 local factors, every local solve refined in FP64 to a componentwise
+backward error of 1e-12) against the same oracle gradient."""
 import numpy as np
 import pytest
 
@@ -33,14 +35,14 @@ def _weights(wl, n_obs=16):
     return obs, d, fw
 
 
-def _gpu_grad(wl, nsmooth):
+def _gpu_grad(wl, nsmooth, precision="fp64"):
     import torch
     import paper_2404_13811_amd as m
     from paper_2404_13811_amd import api
     obs, d, fw = _weights(wl)
     ctx = m.create(wl.dim, wl.ncell, wl.h)
     try:
-        api.configure(ctx, wl, "fp64")
+        api.configure(ctx, wl, precision)
         m.set_checkpointing(ctx, True)
         m.build_basis(ctx)
         m.solve_interface(ctx)
@@ -104,6 +106,43 @@ def test_adjoint_matches_cpu_adjoint(case):
     assert err <= 1e-8
 
 
+# the FP32+refine form on the cases whose boxes its kernels take (2-D lines
+# of at most 32 cells): Dirichlet and pure Neumann, overlaps 0 to 3, both
+# interface spaces, thin subdomains, and a full batch member
+FP32_CASES = ["const_l2_dirichlet", "linear_l0", "linear_l3", "neumann_wells_l2", "beta_const",
+              "no_smoothing", "thin_rows_l0", "grid64_sub4x4", "batch_member_256"]
+
+
+@pytest.mark.parametrize("case", FP32_CASES)
+def test_fp32_refine_adjoint_matches_cpu_adjoint(case):
+    """Every local solve is refined to a componentwise backward error of
+    1e-12, so the FP32+refine map stays within about 1e-10 of the FP64 map
+    (measured: J within 3e-10 and the gradient within 2e-9 on the full batch
+    member, which amplifies most through its five smoothing steps); bars:
+    J 1e-8 and gradient 1e-7 relative, well inside the 1e-6 that the
+    FP32+refine form is held to."""
+    mk, ns = CASES[case]
+    wl = mk()
+    Jg, g = _gpu_grad(wl, ns, "fp32_refine")
+    Jo, go = _oracle_grad(wl, ns)
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(case, "fp32_refine J %.12e vs %.12e  gradient rel L2 %.3e" % (Jg, Jo, err), flush=True)
+    assert abs(Jg - Jo) <= 1e-8 * abs(Jo)
+    assert err <= 1e-7
+
+
+def test_fp32_refine_adjoint_equals_fp64_adjoint_c5():
+    """Full member of the batch workload: the two precision forms' device
+    gradients against each other."""
+    wl = make_workload("c5")
+    J64, g64 = _gpu_grad(wl, wl.nsmooth, "fp64")
+    J32, g32 = _gpu_grad(wl, wl.nsmooth, "fp32_refine")
+    err = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    print("c5 member: J fp64 %.12e fp32_refine %.12e; gradient rel L2 %.3e" % (J64, J32, err), flush=True)
+    assert abs(J32 - J64) <= 1e-8 * abs(J64)
+    assert err <= 1e-7
+
+
 def test_adjoint_matches_finite_differences_c5():
     """Full-size member of the batch workload (256 x 256, 16 x 16 subdomains,
     overlap 2, 5 smoothing steps): directional derivative of J along a random
@@ -133,6 +172,20 @@ def test_autograd_function_uses_the_device_adjoint():
         + (torch.as_tensor(fw.ravel(), device="cuda") * fl).sum()
     J.backward()
     _, g = _gpu_grad(wl, 2)
+    assert np.allclose(lk.grad.cpu().numpy(), g, rtol=1e-12, atol=1e-14 * np.abs(g).max())
+
+
+def test_autograd_function_fp32_refine():
+    import torch
+    import paper_2404_13811_amd as m
+    wl = _small(space="const", overlap=2)
+    obs, d, fw = _weights(wl)
+    lk = torch.tensor(wl.logk.ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+    p, fl = m.solve_differentiable(lk, wl, nsmooth=2, precision="fp32_refine")
+    J = 0.5 * ((p[torch.as_tensor(obs, device="cuda")] - torch.as_tensor(d, device="cuda")) ** 2).sum() \
+        + (torch.as_tensor(fw.ravel(), device="cuda") * fl).sum()
+    J.backward()
+    _, g = _gpu_grad(wl, 2, "fp32_refine")
     assert np.allclose(lk.grad.cpu().numpy(), g, rtol=1e-12, atol=1e-14 * np.abs(g).max())
 
 

@@ -139,9 +139,11 @@ def test_batch_fp32_refine_equals_single_solves():
         assert _rel(ps[k], p1) <= 1e-12 and _rel(fls[k], f1) <= 1e-12
 
 
-def test_batch_adjoint_equals_the_members_adjoints():
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batch_adjoint_equals_the_members_adjoints(precision):
     """Gradient of J = 1/2 sum_obs (p - 0.1)^2 + outflow of every member,
-    summed over the batch, against each member's own adjoint."""
+    summed over the batch, against each member's own adjoint (both precision
+    forms)."""
     import torch
     wls = [make_workload("c5", scale=2, member=k) for k in range(4)]
     nx, ny = wls[0].ncell
@@ -159,9 +161,9 @@ def test_batch_adjoint_equals_the_members_adjoints():
             return dJdp, fw.reshape(-1)
         return dJ
 
-    _, _, gs, _ = solve_batch(wls, dJ=dJ_for(4))
+    _, _, gs, _ = solve_batch(wls, precision, dJ=dJ_for(4))
     for k, wl in enumerate(wls):
-        _, _, g1 = solve_one(wl, dJ=dJ_for(1))
+        _, _, g1 = solve_one(wl, precision, dJ=dJ_for(1))
         e = _rel(gs[k], g1)
         print("  member %d: gradient rel difference %.2e" % (k, e), flush=True)
         assert e <= 1e-12
