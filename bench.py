@@ -175,10 +175,11 @@ def time_solves(wl, precision, steps, warmup, tol, persistent=False):
     return dt, phases, st, p.cpu().numpy(), fl.cpu().numpy()
 
 
-def time_adjoint(wl, reps):
+def time_adjoint(wl, reps, precision="fp64"):
     """Forward solve with checkpointing plus mrcm_adjoint (dJ/dlog K of the
     outflow through the +x side plus a misfit at 16 cells) on one member of
-    the batch workload; device wall time per call."""
+    the batch workload, in the given precision form; device wall time per
+    call."""
     import numpy as np
     import torch
     import paper_2404_13811_amd as m
@@ -190,7 +191,7 @@ def time_adjoint(wl, reps):
     fw[torch.arange(nx - 1, N, nx, device="cuda"), 1] = wl.h
     fw = fw.reshape(-1)
     ctx = m.create(wl.dim, wl.ncell, wl.h)
-    api.configure(ctx, wl, "fp64")
+    api.configure(ctx, wl, precision)
     m.set_checkpointing(ctx, True)
     grad = torch.empty(N, dtype=torch.float64, device="cuda")
     tf = ta = 0.0
@@ -219,11 +220,12 @@ def time_adjoint(wl, reps):
             "gradient_over_forward": round(ta / tf, 3)}
 
 
-def time_batch(members, reps):
+def time_batch(members, reps, precision="fp64", streams=True):
     """The batch of fields: every member's forward solve (with checkpoints)
-    and gradient.  Two forms, device wall time per batch, inputs resident:
-    one batched context (mrcm_create_batched: one launch per stage for all
-    members), and one context and stream per member with deferred errors."""
+    and gradient in the given precision form.  Device wall time per batch,
+    inputs resident: one batched context (mrcm_create_batched: one launch
+    per stage for all members), and (streams) one context and stream per
+    member with deferred errors."""
     import numpy as np
     import torch
     import paper_2404_13811_amd as m
@@ -243,7 +245,7 @@ def time_batch(members, reps):
 
     # one batched context
     ctx = m.create_batched(2, wls[0].ncell, wls[0].h, members)
-    m.configure_batch(ctx, wls, "fp64")
+    m.configure_batch(ctx, wls, precision)
     m.set_checkpointing(ctx, True)
     m.set_timing(ctx, False)
     obs_b, fw_b = weights(members)
@@ -265,6 +267,12 @@ def time_batch(members, reps):
         if r:  # the first round builds the plan and allocates
             tb += (time.perf_counter() - t0) / reps
     m.destroy(ctx)
+    out = {"members": members, "precision": precision,
+           "batched_context": {"ms_per_batch": round(tb * 1e3, 3),
+                               "ms_per_member": round(tb * 1e3 / members, 4),
+                               "fine_cells_per_s_forward_and_gradient": members * N / tb}}
+    if not streams:
+        return out
 
     # one context and stream per member
     obs, fw = weights(1)
@@ -274,7 +282,7 @@ def time_batch(members, reps):
     for wl, s in zip(wls, streams):
         with torch.cuda.stream(s):
             c = m.create(wl.dim, wl.ncell, wl.h)
-            api.configure(c, wl, "fp64")
+            api.configure(c, wl, precision)
             m.set_checkpointing(c, True)
             m.set_timing(c, False)
             m.set_deferred_errors(c, True)
@@ -303,13 +311,10 @@ def time_batch(members, reps):
             t += (time.perf_counter() - t0) / reps
     for c in ctxs:
         m.destroy(c)
-    return {"members": members,
-            "batched_context": {"ms_per_batch": round(tb * 1e3, 3),
-                                "ms_per_member": round(tb * 1e3 / members, 4),
-                                "fine_cells_per_s_forward_and_gradient": members * N / tb},
-            "contexts_on_streams": {"streams": members, "ms_per_batch": round(t * 1e3, 3),
-                                    "ms_per_member": round(t * 1e3 / members, 4),
-                                    "fine_cells_per_s_forward_and_gradient": members * N / t}}
+    out["contexts_on_streams"] = {"streams": members, "ms_per_batch": round(t * 1e3, 3),
+                                  "ms_per_member": round(t * 1e3 / members, 4),
+                                  "fine_cells_per_s_forward_and_gradient": members * N / t}
+    return out
 
 
 def boxes(wl):
@@ -629,7 +634,9 @@ def main():
                 o2[form] = form_summary(w2, f, form, args)
             others[describe(name, w2)] = o2
         adj = time_adjoint(make_workload("c5"), max(3, args.steps // 4))
+        adj["fp32_refine"] = time_adjoint(make_workload("c5"), max(3, args.steps // 4), "fp32_refine")
         adj["batch"] = time_batch(32, 3)
+        adj["batch_fp32_refine"] = time_batch(32, 3, "fp32_refine", streams=False)
         others["adjoint"] = adj
     met = H["target_met"]
     # the roofline of the kernel with the largest share of the solve: the

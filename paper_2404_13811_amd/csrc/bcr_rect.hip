@@ -7,6 +7,8 @@
 // cyclic-reduction kernels of bcr.hip.
 #include "mrcm_internal.h"
 
+#include <algorithm>
+
 namespace mrcm {
 namespace {
 
@@ -26,8 +28,8 @@ constexpr size_t rect_lds_doubles() {
 // the next chunk's loads in flight.  A wave of a 64 x 64 tile reuses each
 // operand it reads from LDS for two instructions.
 template <int TM, int TN, int KC>
-__device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const RectShape& S,
-                                          int tile, double* smem) {
+__device__ __forceinline__ void rect_tile_at(double* base, const BcrGemm& T, const RectShape& S,
+                                             int tr0, int tc0, double* smem) {
   constexpr int NA = TM * KC / 256, NB = KC * TN / 256;
   constexpr int AS = KC + 1;
   constexpr int BM = TM / 32, BN = TN / 32;  // 16 x 16 blocks per wave
@@ -35,8 +37,6 @@ __device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const 
   constexpr int NACC = BM * BN == 1 ? 2 : 1;
   double* As = smem;
   double* Bs = smem + TM * AS;
-  const int ntc = S.n / TN;
-  const int tr0 = (tile / ntc) * TM, tc0 = (tile % ntc) * TN;
   const int tid = threadIdx.x;
   const int wv = tid >> 6, ln = tid & 63;
   const int qr = (wv >> 1) * (TM / 2), qc = (wv & 1) * (TN / 2);
@@ -115,6 +115,39 @@ __device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const 
 }
 
 template <int TM, int TN, int KC>
+__device__ __forceinline__ void rect_tile(double* base, const BcrGemm& T, const RectShape& S,
+                                          int tile, double* smem) {
+  const int ntc = S.n / TN;
+  rect_tile_at<TM, TN, KC>(base, T, S, (tile / ntc) * TM, (tile % ntc) * TN, smem);
+}
+
+// Products restricted to their column windows: workgroup (task, row tile,
+// j) takes the task's j-th window tile, or returns when the window has
+// fewer than j + 1 tiles (the whole workgroup, before any barrier).
+template <int TM, int TN, int KC>
+__global__ void __launch_bounds__(256) k_rect_gemm_win(double* __restrict__ base,
+                                                       const BcrGemm* __restrict__ tasks, RectShape S,
+                                                       int maxnt) {
+  extern __shared__ double smem[];
+  const int per = (S.m / TM) * maxnt;
+  const int task = blockIdx.x / per;
+  const int loc = blockIdx.x - task * per;
+  const int i = loc / maxnt, j = loc - i * maxnt;
+  const BcrGemm T = tasks[task];
+  int t0 = 0, t1 = S.n / TN, tx = -1;
+  if (T.wc1 > 0) {
+    t0 = T.wc0 / TN;
+    t1 = min((T.wc1 + TN - 1) / TN, S.n / TN);
+    tx = T.wcx >= 0 ? T.wcx / TN : -1;
+    if (tx >= t0 && tx < t1) tx = -1;
+  }
+  const int cnt = (t1 - t0) + (tx >= 0 ? 1 : 0);
+  if (j >= cnt) return;
+  const int ct = j < t1 - t0 ? t0 + j : tx;
+  rect_tile_at<TM, TN, KC>(base, T, S, i * TM, ct * TN, smem);
+}
+
+template <int TM, int TN, int KC>
 __global__ void __launch_bounds__(256) k_rect_gemm(double* __restrict__ base,
                                                    const BcrGemm* __restrict__ tasks,
                                                    RectShape S) {
@@ -164,23 +197,26 @@ __global__ void k_set_ones(double* __restrict__ base, const long long* __restric
 __global__ void __launch_bounds__(256) k_lsc_outer_rows(double* __restrict__ base,
                                                         const LscRow* __restrict__ rows,
                                                         const long long* __restrict__ ypos,
-                                                        int nrow, int ncol, int width) {
+                                                        const int* __restrict__ cmap, int nrow,
+                                                        int ncol, int width) {
   const int q = blockIdx.x;
   if (q >= nrow) return;
   const LscRow R = rows[q];
   for (int c = blockIdx.y * blockDim.x + threadIdx.x; c < ncol; c += gridDim.y * blockDim.x) {
+    const int code = cmap[R.cm + c];
+    long long d;
+    if (code == -2) d = R.rhs;
+    else if (code < 0) d = -1;
+    else if (code < R.ml) d = R.dst0 >= 0 ? R.dst0 + code : -1;
+    else d = R.dst1 >= 0 ? R.dst1 + (code - R.ml) : -1;
+    if (d < 0) continue;
     double acc = 0.0;
     for (int e = 0; e < width; ++e) {
       const long long yp = ypos[R.yidx + e];
       if (yp < 0) continue;
       acc = fma(base[R.cval + e], base[R.ybase + yp * R.ldy + c], acc);
     }
-    long long d;
-    if (c == 0) d = R.rhs;
-    else if (c < R.c1) d = R.dst0 >= 0 ? R.dst0 + (c - 1) : -1;
-    else if (c < R.c2) d = R.dst1 >= 0 ? R.dst1 + (c - R.c1) : -1;
-    else d = -1;
-    if (d >= 0) base[d] = acc;
+    base[d] = acc;
   }
 }
 
@@ -188,20 +224,30 @@ __global__ void __launch_bounds__(256) k_lsc_outer_rows(double* __restrict__ bas
 // every interface unknown (one wave each): its inner solution row against
 // the reduced solution of the gaps on both sides of its layer.
 __global__ void __launch_bounds__(256) k_lsc_back(const double* __restrict__ base,
-                                                  const LscCol* __restrict__ cols, int n,
+                                                  const LscCol* __restrict__ cols,
+                                                  const int* __restrict__ cmap, int n, int ncol,
                                                   double* __restrict__ X) {
   const int wg = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int L = threadIdx.x & 63;
   if (wg >= n) return;
   const LscCol C = cols[wg];
   const double* y = base + C.xrow;
-  double acc = 0.0;
-  if (C.sofs >= 0)
-    for (int j = L; j < C.ml; j += 64) acc = fma(y[1 + j], base[C.sofs + j], acc);
-  if (C.tofs >= 0)
-    for (int j = L; j < C.mu; j += 64) acc = fma(y[1 + C.ml + j], base[C.tofs + j], acc);
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (L == 0) X[wg] = y[0] - acc;
+  double acc = 0.0, rhs = 0.0;
+  for (int c = L; c < ncol; c += 64) {
+    const int code = cmap[C.cm + c];
+    if (code == -2) {
+      rhs = y[c];
+    } else if (code >= 0) {
+      const long long o = code < C.ml ? (C.sofs >= 0 ? C.sofs + code : -1)
+                                      : (C.tofs >= 0 ? C.tofs + (code - C.ml) : -1);
+      if (o >= 0) acc = fma(y[c], base[o], acc);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    acc += __shfl_xor(acc, off);
+    rhs += __shfl_xor(rhs, off);  // one lane holds it: exact
+  }
+  if (L == 0) X[wg] = rhs - acc;
 }
 
 }  // namespace
@@ -231,6 +277,25 @@ hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const
     return rect_launch<64, 64, 32>(base, tasks, ntask, S, s);
   if (S.k % 64 == 0) return rect_launch<32, 32, 64>(base, tasks, ntask, S, s);
   return rect_launch<32, 32, 32>(base, tasks, ntask, S, s);
+}
+
+hipError_t launch_rect_gemm_win(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
+                                int maxnt, hipStream_t s) {
+  if (ntask <= 0) return hipSuccess;
+  if (S.m % 32 || S.n % 32 || S.k % 32 || S.m <= 0 || S.n <= 0 || S.k <= 0) return hipErrorInvalidValue;
+  maxnt = std::max(1, std::min(maxnt, S.n / 32));
+  const long long n = (long long)ntask * (S.m / 32) * maxnt;
+  if (n > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (S.k % 64 == 0) {
+    const size_t lds = sizeof(double) * rect_lds_doubles<32, 32, 64>();
+    hipLaunchKernelGGL((k_rect_gemm_win<32, 32, 64>), dim3((unsigned)n), dim3(256), lds, s, base, tasks, S,
+                       maxnt);
+  } else {
+    const size_t lds = sizeof(double) * rect_lds_doubles<32, 32, 32>();
+    hipLaunchKernelGGL((k_rect_gemm_win<32, 32, 32>), dim3((unsigned)n), dim3(256), lds, s, base, tasks, S,
+                       maxnt);
+  }
+  return hipGetLastError();
 }
 
 namespace {
@@ -270,18 +335,19 @@ hipError_t launch_fill_ones(double* base, long long n, const long long* ones, lo
   return hipGetLastError();
 }
 
-hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos, int nrow,
-                                 int ncol, int width, hipStream_t s) {
+hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos,
+                                 const int* cmap, int nrow, int ncol, int width, hipStream_t s) {
   if (nrow <= 0) return hipSuccess;
   const int chunks = (ncol + 255) / 256;
-  hipLaunchKernelGGL(k_lsc_outer_rows, dim3(nrow, chunks), dim3(256), 0, s, base, rows, ypos, nrow,
-                     ncol, width);
+  hipLaunchKernelGGL(k_lsc_outer_rows, dim3(nrow, chunks), dim3(256), 0, s, base, rows, ypos, cmap,
+                     nrow, ncol, width);
   return hipGetLastError();
 }
 
-hipError_t launch_lsc_back(const double* base, const LscCol* cols, int n, double* X, hipStream_t s) {
+hipError_t launch_lsc_back(const double* base, const LscCol* cols, const int* cmap, int n, int ncol,
+                           double* X, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lsc_back, dim3((n + 3) / 4), dim3(256), 0, s, base, cols, n, X);
+  hipLaunchKernelGGL(k_lsc_back, dim3((n + 3) / 4), dim3(256), 0, s, base, cols, cmap, n, ncol, X);
   return hipGetLastError();
 }
 

@@ -26,6 +26,15 @@
 // The algebra is exact (no approximation is added to the direct solve):
 // the reduced system is the Schur complement of the interface system onto
 // the couplings between outer layers.
+//
+// Columns of [r_k | P_L^T | P_U^T]: the coupling columns of each inner
+// layer z side by side (its lower, then its upper couplings), the
+// right-hand side last.  The unit column of a coupling row of inner layer z
+// is zero outside layer z, so in the forward pass of the inner reduction a
+// vector block depends only on the inner layers it has gathered: the
+// block-vector products of that pass run over the column window of those
+// layers (plus the right-hand side) and skip the columns that are still
+// zero.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -167,8 +176,10 @@ std::vector<SOp> schedule(int Ml) {
 // One launch of the solver.
 struct LscLaunch {
   int kind;  // 0 inverses, 1 rectangular products, 2 block-vector products (outer),
-             // 3 two independent groups of products (second: off2, cnt2, shape2)
+             // 3 two independent groups of products (second: off2, cnt2, shape2),
+             // 4 rectangular products over their column windows (at most wmax tiles)
   int off, cnt;
+  int wmax;
   int n, ld;        // inverses
   RectShape shape;  // products
   int off2, cnt2;
@@ -196,6 +207,7 @@ struct Lsc {
   int nrows = 0;
   LscCol* d_cols = nullptr;
   int ncols = 0;
+  int* d_cmap = nullptr;  // per outer layer: code of every inner-solution column
   // launches: inner phase, outer phase
   std::vector<LscLaunch> inner, outer;
 };
@@ -237,6 +249,18 @@ struct Builder {
     o.off = (int)rect.size();
     o.cnt = (int)t.size();
     o.shape = sh;
+    rect.insert(rect.end(), t.begin(), t.end());
+    L.push_back(o);
+  }
+  // products over column windows (wmax: most 32-column tiles of a window)
+  void prodw(std::vector<LscLaunch>& L, const std::vector<BcrGemm>& t, const RectShape& sh, int wmax) {
+    if (t.empty()) return;
+    LscLaunch o{};
+    o.kind = 4;
+    o.off = (int)rect.size();
+    o.cnt = (int)t.size();
+    o.shape = sh;
+    o.wmax = wmax;
     rect.insert(rect.end(), t.begin(), t.end());
     L.push_back(o);
   }
@@ -339,7 +363,7 @@ void lsc_destroy(Lsc* L) {
     p = nullptr;
   };
   f(L->buf); f(L->d_dst); f(L->d_rdst); f(L->d_ones); f(L->d_offs); f(L->d_npiv);
-  f(L->d_rect); f(L->d_gemv); f(L->d_rows); f(L->d_ypos); f(L->d_cols);
+  f(L->d_rect); f(L->d_gemv); f(L->d_rows); f(L->d_ypos); f(L->d_cols); f(L->d_cmap);
   delete L;
 }
 
@@ -461,6 +485,36 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
   }
   L.nc = (int)up32(1 + mlu);
   L.ncol = 1 + mlu;
+  // inner-solution columns per outer layer k: for every inner layer z its
+  // lower then its upper coupling rows, the right-hand side last (column
+  // RC); zc0 / zc1: the column range of inner layer z
+  const int RC = mlu;
+  std::vector<std::vector<int>> colL(L.S), colU(L.S);
+  std::vector<int> zc0((size_t)L.S * L.Mi, 0), zc1((size_t)L.S * L.Mi, 0);
+  std::vector<int> cmap((size_t)L.S * L.ncol, -1);
+  for (int k = 0; k < L.S; ++k) {
+    colL[k].assign(RLr[k].size(), -1);
+    colU[k].assign(RUr[k].size(), -1);
+    const int mLk = (int)RLr[k].size();
+    int next = 0;
+    for (int z = 0; z < L.Mi; ++z) {
+      zc0[(size_t)k * L.Mi + z] = next;
+      for (size_t jq = 0; jq < RLr[k].size(); ++jq)
+        if (row_z[RLr[k][jq]] == z) {
+          colL[k][jq] = next;
+          cmap[(size_t)k * L.ncol + next] = (int)jq;
+          ++next;
+        }
+      for (size_t jq = 0; jq < RUr[k].size(); ++jq)
+        if (row_z[RUr[k][jq]] == z) {
+          colU[k][jq] = next;
+          cmap[(size_t)k * L.ncol + next] = mLk + (int)jq;
+          ++next;
+        }
+      zc1[(size_t)k * L.Mi + z] = next;
+    }
+    cmap[(size_t)k * L.ncol + RC] = -2;
+  }
   L.bo = (int)up32(std::max(mgap, 32));
   const long long bsi = (long long)L.bpi * L.bpi, bso = (long long)L.bo * L.bo;
   // regions (each a multiple of 32 doubles)
@@ -497,7 +551,7 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
     for (int rr = 0; rr < 2 * F.nbasis; ++rr) {
       const int row = F.row0 + rr;
       const int k = row_sys[row], zr = row_z[row];
-      rdst[row] = L.R_in + ((long long)k * 3 * L.Mi + zr) * L.bpi * L.nc + (long long)row_loc[row] * L.nc;
+      rdst[row] = L.R_in + ((long long)k * 3 * L.Mi + zr) * L.bpi * L.nc + (long long)row_loc[row] * L.nc + RC;
       for (int e = 0; e < ni + nj; ++e) {
         const int col = e < ni ? seed_off[F.i] + e : seed_off[F.j] + (e - ni);
         const int kc = col_sys[col], zc = col_z[col];
@@ -531,16 +585,15 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
     for (int z = 0; z < L.Mi; ++z)
       for (int p = lsz[(size_t)k * L.Mi + z]; p < L.bpi; ++p)
         ones.push_back(L.P_in + ((long long)k * 5 * L.Mi + z) * bsi + (long long)p * L.bpi + p);
-    const int mL = (int)RLr[k].size();
     for (size_t jq = 0; jq < RLr[k].size(); ++jq) {
       const int r = RLr[k][jq];
       ones.push_back(L.R_in + ((long long)k * 3 * L.Mi + row_z[r]) * L.bpi * L.nc +
-                     (long long)row_loc[r] * L.nc + 1 + (long long)jq);
+                     (long long)row_loc[r] * L.nc + colL[k][jq]);
     }
     for (size_t jq = 0; jq < RUr[k].size(); ++jq) {
       const int r = RUr[k][jq];
       ones.push_back(L.R_in + ((long long)k * 3 * L.Mi + row_z[r]) * L.bpi * L.nc +
-                     (long long)row_loc[r] * L.nc + 1 + mL + (long long)jq);
+                     (long long)row_loc[r] * L.nc + colU[k][jq]);
     }
   }
   for (int gi = 0; gi < L.ng; ++gi)
@@ -563,8 +616,8 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
       R.ybase = ybase(gi);
       R.ldy = L.nc;
       R.rhs = L.V_out + (long long)gi * L.bo + pr;
-      R.c1 = 1 + mLg;
-      R.c2 = 1 + mLg + mU;
+      R.cm = gi * L.ncol;
+      R.ml = mLg;
       R.dst0 = gi > 0 ? L.P_out + (long long)(Ml + gi) * bso + (long long)pr * L.bo + (long long)RUr[gi - 1].size() : -1;
       R.dst1 = L.P_out + (long long)gi * bso + (long long)pr * L.bo;
       rows.push_back(R);
@@ -578,8 +631,8 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
       R.ybase = ybase(gi + 1);
       R.ldy = L.nc;
       R.rhs = L.V_out + (long long)gi * L.bo + q;
-      R.c1 = 1 + mL1;
-      R.c2 = 1 + mL1 + mU1;
+      R.cm = (gi + 1) * L.ncol;
+      R.ml = mL1;
       R.dst0 = L.P_out + (long long)gi * bso + (long long)q * L.bo + mU;
       R.dst1 = gi + 1 < L.ng ? L.P_out + (long long)(2 * Ml + gi) * bso + (long long)q * L.bo : -1;
       rows.push_back(R);
@@ -596,6 +649,7 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
     C.mu = (int)RUr[k].size();
     C.sofs = k > 0 ? L.V_out + (long long)(2 * Ml + k - 1) * L.bo + (long long)RUr[k - 1].size() : -1;
     C.tofs = k < L.Mo - 1 ? L.V_out + (long long)(2 * Ml + k) * L.bo : -1;
+    C.cm = k * L.ncol;
     cols[c] = C;
   }
   L.ncols = nX;
@@ -605,6 +659,10 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
     const std::vector<SOp> ops = schedule(L.Mi);
     auto pb = [&](int sys, int slot) { return L.P_in + ((long long)sys * 5 * L.Mi + slot) * bsi; };
     auto rb = [&](int sys, int slot) { return L.R_in + ((long long)sys * 3 * L.Mi + slot) * L.bpi * L.nc; };
+    // inner layers gathered by each vector slot (r_k: layer k; a product's
+    // output: the union over its inputs), so its window of columns
+    std::vector<int> slo(3 * L.Mi, L.Mi), shi(3 * L.Mi, -1);
+    for (int k = 0; k < L.Mi; ++k) slo[k] = shi[k] = k;
     for (const SOp& o : ops) {
       if (o.kind == 0) {
         std::vector<long long> blk, scr;
@@ -616,17 +674,52 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
         B.rinv(L.inner, blk, scr, L.bpi, L.bpi, 0);
         continue;
       }
+      // windows of this op's vector outputs (inputs are never outputs of
+      // the same op)
+      std::vector<int> vlo(o.vec.size()), vhi(o.vec.size());
+      for (size_t q = 0; q < o.vec.size(); ++q) {
+        const SProd& t = o.vec[q];
+        int lo = L.Mi, hi = -1;
+        for (int in : {t.c0, t.b1, t.b2})
+          if (in >= 0) {
+            lo = std::min(lo, slo[in]);
+            hi = std::max(hi, shi[in]);
+          }
+        vlo[q] = lo;
+        vhi[q] = hi;
+      }
       std::vector<BcrGemm> p, v;
+      int wmax = 1;
       for (int sys = 0; sys < L.S; ++sys) {
         for (const SProd& t : o.prod)
           p.push_back(BcrGemm{pb(sys, t.c), t.c0 >= 0 ? pb(sys, t.c0) : -1, pb(sys, t.a1), pb(sys, t.b1),
                               t.a2 >= 0 ? pb(sys, t.a2) : -1, t.a2 >= 0 ? pb(sys, t.b2) : -1, t.al1, t.al2});
-        for (const SProd& t : o.vec)
-          v.push_back(BcrGemm{rb(sys, t.c), t.c0 >= 0 ? rb(sys, t.c0) : -1, pb(sys, t.a1), rb(sys, t.b1),
-                              t.a2 >= 0 ? pb(sys, t.a2) : -1, t.a2 >= 0 ? rb(sys, t.b2) : -1, t.al1, t.al2});
+        for (size_t q = 0; q < o.vec.size(); ++q) {
+          const SProd& t = o.vec[q];
+          BcrGemm G{rb(sys, t.c), t.c0 >= 0 ? rb(sys, t.c0) : -1, pb(sys, t.a1), rb(sys, t.b1),
+                    t.a2 >= 0 ? pb(sys, t.a2) : -1, t.a2 >= 0 ? rb(sys, t.b2) : -1, t.al1, t.al2};
+          if (vhi[q] >= vlo[q] && !(vlo[q] == 0 && vhi[q] == L.Mi - 1)) {
+            G.wc0 = zc0[(size_t)sys * L.Mi + vlo[q]];
+            G.wc1 = zc1[(size_t)sys * L.Mi + vhi[q]];
+            G.wcx = RC;
+            // tiles: the window rounded out to 32 columns, and the tile of
+            // the right-hand side
+            const int t0 = G.wc0 / 32, t1 = (G.wc1 + 31) / 32, tx = RC / 32;
+            wmax = std::max(wmax, std::max(t1 - t0, 0) + ((tx >= t0 && tx < t1) ? 0 : 1));
+          } else {
+            wmax = L.nc / 32;
+          }
+          v.push_back(G);
+        }
       }
+      for (size_t q = 0; q < o.vec.size(); ++q) {
+        slo[o.vec[q].c] = vlo[q];
+        shi[o.vec[q].c] = vhi[q];
+      }
+      const RectShape vs{L.bpi, L.nc, L.bpi, L.bpi, L.nc, L.nc};
       B.prod(L.inner, p, RectShape{L.bpi, L.bpi, L.bpi, L.bpi, L.bpi, L.bpi});
-      B.prod(L.inner, v, RectShape{L.bpi, L.nc, L.bpi, L.bpi, L.nc, L.nc});
+      if (wmax < L.nc / 32) B.prodw(L.inner, v, vs, wmax);
+      else B.prod(L.inner, v, vs);
     }
   }
   // reduced system over the gaps
@@ -665,6 +758,7 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
   if (e == hipSuccess) e = upload(L.d_rows, rows);
   if (e == hipSuccess) e = upload(L.d_ypos, ypos);
   if (e == hipSuccess) e = upload(L.d_cols, cols);
+  if (e == hipSuccess) e = upload(L.d_cmap, cmap);
   if (e != hipSuccess) {
     *herr = e;
     if (err) *err = hipGetErrorString(e);
@@ -698,6 +792,8 @@ hipError_t run(Lsc* L, const std::vector<LscLaunch>& ops, int* flags, hipStream_
     else if (o.kind == 3)
       e = launch_rect_gemm2(L->buf, L->d_rect + o.off, o.cnt, o.shape, L->d_rect + o.off2, o.cnt2,
                             o.shape2, s);
+    else if (o.kind == 4)
+      e = launch_rect_gemm_win(L->buf, L->d_rect + o.off, o.cnt, o.shape, o.wmax, s);
     else
       e = launch_bcr_gemv(L->buf + L->P_out, L->buf + L->V_out, L->d_gemv + o.off, o.cnt, L->bo, s);
     if (e != hipSuccess) return e;
@@ -709,9 +805,9 @@ hipError_t run(Lsc* L, const std::vector<LscLaunch>& ops, int* flags, hipStream_
 hipError_t lsc_solve(Lsc* L, double* X, int* flags, hipStream_t s) {
   hipError_t e = run(L, L->inner, flags, s);
   if (e == hipSuccess)
-    e = launch_lsc_outer_rows(L->buf, L->d_rows, L->d_ypos, L->nrows, L->ncol, L->wc, s);
+    e = launch_lsc_outer_rows(L->buf, L->d_rows, L->d_ypos, L->d_cmap, L->nrows, L->ncol, L->wc, s);
   if (e == hipSuccess) e = run(L, L->outer, flags, s);
-  if (e == hipSuccess) e = launch_lsc_back(L->buf, L->d_cols, L->ncols, X, s);
+  if (e == hipSuccess) e = launch_lsc_back(L->buf, L->d_cols, L->d_cmap, L->ncols, L->ncol, X, s);
   return e;
 }
 

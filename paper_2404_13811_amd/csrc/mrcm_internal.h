@@ -87,6 +87,10 @@ struct Iface {
 struct BcrGemm {
   long long c, c0, a1, b1, a2, b2;
   double al1, al2;
+  // column window of a windowed rectangular product (launch_rect_gemm_win):
+  // columns [wc0, wc1) and column wcx (< 0: none) of C, rounded out to
+  // whole tiles; the other columns are neither read from B nor written
+  int wc0 = 0, wc1 = 0, wcx = -1, pad = 0;
 };
 // Vector form: vector y := [vector y0] + al1 * block a1 * vector x1 [+ ...].
 struct BcrGemv {
@@ -275,6 +279,10 @@ struct RectShape {
 // C = [C0] + al1 A1 B1 [+ al2 A2 B2], offsets into one base array (BcrGemm)
 hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
                             hipStream_t s);
+// products restricted to their column windows (32-column tiles); maxnt:
+// the largest number of column tiles of a task's window
+hipError_t launch_rect_gemm_win(double* base, const BcrGemm* tasks, int ntask, const RectShape& S,
+                                int maxnt, hipStream_t s);
 // two independent groups of products with the same k in one launch
 hipError_t launch_rect_gemm2(double* base, const BcrGemm* ta, int na, const RectShape& SA,
                              const BcrGemm* tb, int nb, const RectShape& SB, hipStream_t s);
@@ -286,20 +294,25 @@ hipError_t launch_fill_ones(double* base, long long n, const long long* ones, lo
 // to the inner solution of its source layer (base[ybase + row * ldy + c]);
 // column 0 to base[rhs], columns [1, c1) to base[dst0 + c - 1], columns
 // [c1, c2) to base[dst1 + c - c1] (dst < 0: dropped).
+// Columns of the inner solutions: cmap[cm + c] for column c of the source
+// layer: -2 the right-hand side, j in [0, ml) the j-th lower coupling (to
+// dst0 + j), ml + j the j-th upper coupling (to dst1 + j), -1 unused.
 struct LscRow {
   long long cval, yidx, ybase, rhs, dst0, dst1;
-  int c1, c2, ldy, pad;
+  int cm, ml, ldy, pad;
 };
-hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos, int nrow,
-                                 int ncol, int width, hipStream_t s);
+hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos,
+                                 const int* cmap, int nrow, int ncol, int width, hipStream_t s);
 // Back substitution of one interface unknown: its inner solution row at
-// base[xrow] (y, then ml coupling columns of s, then mu of t) against the
-// reduced solution (s at base[sofs], t at base[tofs]; < 0: none).
+// base[xrow] (columns mapped by cmap[cm + c] as above: the right-hand side,
+// the ml couplings of s, the mu of t) against the reduced solution (s at
+// base[sofs], t at base[tofs]; < 0: none).
 struct LscCol {
   long long xrow, sofs, tofs;
-  int ml, mu;
+  int ml, mu, cm, pad;
 };
-hipError_t launch_lsc_back(const double* base, const LscCol* cols, int n, double* X, hipStream_t s);
+hipError_t launch_lsc_back(const double* base, const LscCol* cols, const int* cmap, int n, int ncol,
+                           double* X, hipStream_t s);
 
 // The two-level solver's plan and device state (iface_lsc.cpp).  seeds_per_side:
 // per subdomain and side (6 entries each) its number of seeds.  Returns
