@@ -179,9 +179,12 @@ __global__ void __launch_bounds__(256) k_rect_gemm2(double* __restrict__ base,
 
 // base[0, n) = 0; then (second kernel) base[ones[i]] = 1 for the listed
 // offsets (identity blocks and padding, unit right-hand-side columns).
-__global__ void k_fill_zero(double* __restrict__ base, long long n) {
+// zero nrep runs of len doubles, stride apart, from base
+__global__ void k_fill_zero(double* __restrict__ base, long long len, long long stride, long long nrep) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) base[e] = 0.0;
+  if (e >= len * nrep) return;
+  const long long r = e / len;
+  base[r * stride + (e - r * len)] = 0.0;
 }
 __global__ void k_set_ones(double* __restrict__ base, const long long* __restrict__ ones, long long nones) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,10 +328,15 @@ hipError_t launch_rect_gemm2(double* base, const BcrGemm* ta, int na, const Rect
   return rect_launch2<32, 32, 32>(base, ta, na, SA, tb, nb, SB, s);
 }
 
-hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,
-                            hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n);
+hipError_t launch_fill_ones(double* base, const ZeroRun* runs, int nruns, const long long* ones,
+                            long long nones, hipStream_t s) {
+  for (int i = 0; i < nruns; ++i) {
+    const ZeroRun& z = runs[i];
+    const long long n = z.len * z.nrep;
+    if (n > 0)
+      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base + z.off,
+                         z.len, z.stride, z.nrep);
+  }
   if (nones > 0)
     hipLaunchKernelGGL(k_set_ones, dim3((unsigned)((nones + 255) / 256)), dim3(256), 0, s, base, ones,
                        nones);

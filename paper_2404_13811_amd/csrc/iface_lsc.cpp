@@ -778,7 +778,21 @@ BcrMap lsc_map(const Lsc* L) {
 }
 
 hipError_t lsc_prepare(Lsc* L, hipStream_t s) {
-  return launch_fill_ones(L->buf, L->total, L->d_ones, L->nones, s);
+  // zeros where the moments scatter (the inner D, L, U blocks and right-hand
+  // sides, the gap blocks D, L, U and right-hand sides) and in the inner g
+  // vectors, which the windowed forward products write only in part; the
+  // F and G blocks, the inner x vectors and the gap g and x vectors are
+  // written whole before they are read (the cross values are read only
+  // where the moments wrote them)
+  const long long bsi = (long long)L->bpi * L->bpi, bso = (long long)L->bo * L->bo;
+  const long long vsi = (long long)L->bpi * L->nc;
+  const ZeroRun runs[4] = {
+      {L->P_in, 3LL * L->Mi * bsi, 5LL * L->Mi * bsi, L->S},
+      {L->R_in, 2LL * L->Mi * vsi, 3LL * L->Mi * vsi, L->S},
+      {L->P_out, 3LL * L->ng * bso, 0, 1},
+      {L->V_out, (long long)L->ng * L->bo, 0, 1},
+  };
+  return launch_fill_ones(L->buf, runs, 4, L->d_ones, L->nones, s);
 }
 
 namespace {

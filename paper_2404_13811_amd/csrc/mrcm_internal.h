@@ -286,17 +286,20 @@ hipError_t launch_rect_gemm_win(double* base, const BcrGemm* tasks, int ntask, c
 // two independent groups of products with the same k in one launch
 hipError_t launch_rect_gemm2(double* base, const BcrGemm* ta, int na, const RectShape& SA,
                              const BcrGemm* tb, int nb, const RectShape& SB, hipStream_t s);
-// base[0, n) = 0, then base[ones[i]] = 1
-hipError_t launch_fill_ones(double* base, long long n, const long long* ones, long long nones,
-                            hipStream_t s);
+// Runs of zeros: nrep runs of len doubles at base + off, off + stride, ...
+// launch_fill_ones: the runs, then base[ones[i]] = 1.
+struct ZeroRun {
+  long long off, len, stride, nrep;
+};
+hipError_t launch_fill_ones(double* base, const ZeroRun* runs, int nruns, const long long* ones,
+                            long long nones, hipStream_t s);
 // One row of the reduced (gap) system: its cross entries (values at
 // base[cval + e], stacked-solution rows ypos[yidx + e], < 0: none) applied
-// to the inner solution of its source layer (base[ybase + row * ldy + c]);
-// column 0 to base[rhs], columns [1, c1) to base[dst0 + c - 1], columns
-// [c1, c2) to base[dst1 + c - c1] (dst < 0: dropped).
-// Columns of the inner solutions: cmap[cm + c] for column c of the source
-// layer: -2 the right-hand side, j in [0, ml) the j-th lower coupling (to
-// dst0 + j), ml + j the j-th upper coupling (to dst1 + j), -1 unused.
+// to the inner solution of its source layer (base[ybase + row * ldy + c]),
+// column c going where cmap[cm + c] sends it: -2 (the right-hand side) to
+// base[rhs], j in [0, ml) (the j-th lower coupling) to base[dst0 + j],
+// ml + j (the j-th upper coupling) to base[dst1 + j]; -1 (unused) and
+// dst < 0 are dropped.
 struct LscRow {
   long long cval, yidx, ybase, rhs, dst0, dst1;
   int cm, ml, ldy, pad;
