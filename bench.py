@@ -52,8 +52,8 @@ GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_full_samples.npz")
 # value it was taken with; otherwise the traffic is reported as null.
 TRAFFIC = {
     # (kernel, workload key): (source files, sha256 prefix, fetch KiB, write KiB)
-    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip",), "d0b2ac9c6b72e60f", 1887617.5, 4380710.0),
-    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip",), "d0b2ac9c6b72e60f", 518748.2, 2727.0),
+    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip",), "7317bad19c0be02c", 1887676.3, 4380710.0),
+    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip",), "7317bad19c0be02c", 518678.0, 2727.0),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COMMON_SOURCES = ("wave_common.h", "local_common.h", "mrcm_internal.h", "pivot4.h")
@@ -630,7 +630,8 @@ def main():
             o2 = {}
             for form, f in f2.items():
                 if "dt" in f:
-                    f["target_met"] = "err" in f and f["err"]["flux_rel_l2"] <= FLUX_TOL
+                    # null: timed only, not checked against the oracle
+                    f["target_met"] = (f["err"]["flux_rel_l2"] <= FLUX_TOL) if "err" in f else None
                 o2[form] = form_summary(w2, f, form, args)
             others[describe(name, w2)] = o2
         adj = time_adjoint(make_workload("c5"), max(3, args.steps // 4))
