@@ -52,6 +52,9 @@ class Workload:
     beta_smooth: float      # alpha (or beta) for the smoothing steps
     nsmooth: int            # number of smoothing steps
     meta: dict = field(default_factory=dict)
+    # diagonal permeability tensor: log K per axis, shape (dim, *ncell[::-1])
+    # (row a: the entry of axis a); None for scalar K (logk)
+    logk_axes: np.ndarray = None
 
     @property
     def ncells(self):
@@ -59,7 +62,18 @@ class Workload:
 
     @property
     def perm(self):
+        """K per cell, or (dim, cells) per axis for a diagonal tensor."""
+        if self.logk_axes is not None:
+            return np.exp(np.asarray(self.logk_axes)).reshape(self.dim, -1)
         return np.exp(self.logk)
+
+    def with_tensor(self, log_ratio):
+        """The same workload with a diagonal tensor: axis a's log K is logk
+        plus log_ratio[a] (an array of the grid's shape, or a number)."""
+        ax = np.stack([np.asarray(self.logk) + np.broadcast_to(np.asarray(r, dtype=np.float64),
+                                                                np.shape(self.logk))
+                       for r in log_ratio])
+        return replace(self, logk_axes=ax)
 
     def with_(self, **kw):
         return replace(self, **kw)

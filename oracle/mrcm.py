@@ -112,7 +112,7 @@ def make_beta(grid, part, mode, value):
     if mode == "const":
         return lambda a, c, o: np.full(np.size(c), float(value))
     if mode == "alpha":
-        return lambda a, c, o: float(value) * part.S[a] * grid.h / grid.k_harmonic(c, o)
+        return lambda a, c, o: float(value) * part.S[a] * grid.h / grid.k_harmonic(c, o, a)
     raise ValueError(mode)
 
 
@@ -165,7 +165,7 @@ class MRCM:
 
     def __init__(self, wl):
         self.wl = wl
-        self.grid = Grid(wl.ncell, wl.h, np.exp(wl.logk))
+        self.grid = Grid(wl.ncell, wl.h, wl.perm)
         self.part = Partition(wl.ncell, wl.sub, wl.overlap)
         self.bc_type = tuple(wl.bc_type)
         self.bc_value = [np.asarray(v, dtype=np.float64) for v in wl.bc_value]
@@ -197,11 +197,11 @@ class MRCM:
             inner = np.array([box.local_of[int(v)] for v in c])
             if all(int(v) in box.local_of for v in c2):
                 outer = np.array([box.local_of[int(v)] for v in c2])
-                u = g.trans(c, c2) * (P[inner] - P[outer]) / g.area
+                u = g.trans(c, c2, a) * (P[inner] - P[outer]) / g.area
             else:
                 # no oversampling: Gamma_i is the Robin side of the box itself
                 u = box.robin_velocity(P, side, lam.get(side, 0.0))
-            pi = P[inner] - u * g.h / (2.0 * g.K[c])
+            pi = P[inner] - u * g.h / (2.0 * g.k(c, a))
             beta = beta_fn(a, c, c2) * np.ones(c.size)
             out[side] = dict(u=u, pi=pi, phi=-beta * u + pi, beta=beta)
         return out
@@ -339,15 +339,16 @@ class MRCM:
         lam = {}
         for side in box.robin_sides:
             e = box.robin[side]
+            a = side // 2
             c = box.gidx[e["local"]]
             o = e["outer"]
             if part.l > 0:
-                u = g.trans(c, o) * (self.p[c] - self.p[o]) / g.area
-                pi = self.p[c] - u * g.h / (2.0 * g.K[c])
+                u = g.trans(c, o, a) * (self.p[c] - self.p[o]) / g.area
+                pi = self.p[c] - u * g.h / (2.0 * g.k(c, a))
             else:
                 j = part.neighbor(i, side)
                 uj = self.gflux[j][side ^ 1]           # neighbour's outward flux
-                pij = self.p[o] - uj * g.h / (2.0 * g.K[o])
+                pij = self.p[o] - uj * g.h / (2.0 * g.k(o, a))
                 u = -uj
                 pi = pij
             lam[side] = -e["beta"] * u + pi
@@ -426,7 +427,7 @@ def solve(wl, nsmooth=None):
 
 def fine(wl):
     """Fine-grid reference solution and its face velocities."""
-    g = Grid(wl.ncell, wl.h, np.exp(wl.logk))
+    g = Grid(wl.ncell, wl.h, wl.perm)
     p = fine_solve(g, wl.bc_type, wl.bc_value, wl.source)
     return p, cell_face_velocity(g, p, wl.bc_type, wl.bc_value)
 

@@ -67,7 +67,7 @@ def mixed_solve(grid, bc_type, bc_value, f, robin=None):
                 val = 0.0
                 for x in verts:
                     val += wq * _rt0_basis_at(x, a, s, h) * _rt0_basis_at(x, b, t, h)
-                Mm[fi, fj] += val * sg * sg2 / grid.K[c]
+                Mm[fi, fj] += val * sg * sg2 / grid.k(c, a)
             # divergence of the basis: outward flux |e| through its own face
             B[c, fi] += sg * grid.area
     robin = robin or {}

@@ -10,6 +10,10 @@ dimensions (face area ``|e| = h^(d-1)``, cell volume ``h^d``):
 * interior face between c and c': ``T_e = |e| K_H / h`` with ``K_H`` the
   harmonic mean of ``K_c`` and ``K_c'``; the outward normal velocity from c is
   ``u_e = T_e (p_c - p_c') / |e|``;
+* a diagonal permeability tensor (Section 2 allows any symmetric positive
+  definite K) enters a face normal to axis a only through its a-th diagonal
+  entry: every ``K_c`` above is then ``K_c^(a)`` of the face's axis, the
+  two-point flux being consistent for a diagonal tensor on a Cartesian grid;
 * Robin face (``-beta u.n + p = lam``, equation genRobin): the face pressure is
   ``pi = lam + beta u``, and with the half-cell relation
   ``u = 2 K_c (p_c - pi) / h`` one gets ``|e| u = T^R (p_c - lam)`` with
@@ -30,11 +34,20 @@ class Grid:
     """Uniform Cartesian grid; cell arrays are flat in x-fastest order."""
 
     def __init__(self, ncell, h, perm):
+        """perm: K per cell (scalar K), or shape (d, cells) / (d, *cells) for
+        a diagonal tensor: row a holds the entry of axis a."""
         self.n = tuple(int(v) for v in ncell)
         self.d = len(self.n)
         self.h = float(h)
-        self.K = np.asarray(perm, dtype=np.float64).ravel()
-        assert self.K.size == int(np.prod(self.n))
+        N = int(np.prod(self.n))
+        k = np.asarray(perm, dtype=np.float64)
+        if k.size == N:
+            self.Ka = np.tile(k.ravel(), (self.d, 1))
+            self.isotropic = True
+        else:
+            assert k.size == self.d * N
+            self.Ka = np.ascontiguousarray(k.reshape(self.d, N))
+            self.isotropic = False
         self.stride = tuple(int(np.prod(self.n[:a])) for a in range(self.d))
         self.area = self.h ** (self.d - 1)
         self.vol = self.h ** self.d
@@ -54,17 +67,22 @@ class Grid:
             out.append((flat // self.stride[a]) % self.n[a])
         return np.stack(out, axis=-1)
 
-    def k_harmonic(self, c, c2):
-        k1 = self.K[c]
-        k2 = self.K[c2]
+    def k(self, c, a):
+        """K of cells c in the direction of axis a."""
+        return self.Ka[a][c]
+
+    def k_harmonic(self, c, c2, a):
+        k1 = self.Ka[a][c]
+        k2 = self.Ka[a][c2]
         return 2.0 * k1 * k2 / (k1 + k2)
 
-    def trans(self, c, c2):
-        """Interior face transmissibility |e| K_H / h."""
-        return self.area * self.k_harmonic(c, c2) / self.h
+    def trans(self, c, c2, a):
+        """Transmissibility |e| K_H / h of the faces normal to axis a between
+        cells c and c2."""
+        return self.area * self.k_harmonic(c, c2, a) / self.h
 
-    def half_trans(self, c):
-        return 2.0 * self.K[c] * self.area / self.h
+    def half_trans(self, c, a):
+        return 2.0 * self.Ka[a][c] * self.area / self.h
 
 
 def box_coords(lo, hi):
@@ -131,7 +149,7 @@ class BoxProblem:
             # interior faces inside the box along axis a
             sel = np.nonzero(loc[:, a] < m[a] - 1)[0]
             nb = sel + int(np.prod(m[:a]))
-            T = grid.trans(self.gidx[sel], self.gidx[nb])
+            T = grid.trans(self.gidx[sel], self.gidx[nb], a)
             rows += [sel, nb]
             cols += [nb, sel]
             vals += [-T, -T]
@@ -144,7 +162,7 @@ class BoxProblem:
                 on_boundary = (s == 0 and self.lo[a] == 0) or (s == 1 and self.hi[a] == grid.n[a])
                 if on_boundary:
                     typ = bc_type[side]
-                    coef = grid.half_trans(gc) if typ == "D" else np.zeros(lc.size)
+                    coef = grid.half_trans(gc, a) if typ == "D" else np.zeros(lc.size)
                     if typ == "D":
                         np.add.at(diag, lc, coef)
                     self.bcf[side] = dict(local=lc, face=boundary_face_index(grid, self.coords[lc], side),
@@ -154,7 +172,7 @@ class BoxProblem:
                     oc[:, a] += -1 if s == 0 else 1
                     og = grid.flat(oc)
                     beta = np.asarray(beta_fn(a, gc, og), dtype=np.float64) * np.ones(lc.size)
-                    TR = grid.area / (grid.h / (2.0 * grid.K[gc]) + beta)
+                    TR = grid.area / (grid.h / (2.0 * grid.k(gc, a)) + beta)
                     np.add.at(diag, lc, TR)
                     self.robin[side] = dict(local=lc, outer=og, beta=beta, TR=TR)
         rows.append(np.arange(nloc))
@@ -251,12 +269,12 @@ def cell_face_velocity(grid, p, bc_type, bc_value, face_override=None):
             inside = (nbc[:, a] >= 0) & (nbc[:, a] < grid.n[a])
             cin = allc[inside]
             cn = grid.flat(nbc[inside])
-            out[cin, side] = grid.trans(cin, cn) * (p[cin] - p[cn]) / grid.area
+            out[cin, side] = grid.trans(cin, cn, a) * (p[cin] - p[cn]) / grid.area
             cb = allc[~inside]
             face = boundary_face_index(grid, co[cb], side)
             val = np.asarray(bc_value[side])[face]
             if bc_type[side] == "D":
-                out[cb, side] = grid.half_trans(cb) * (p[cb] - val) / grid.area
+                out[cb, side] = grid.half_trans(cb, a) * (p[cb] - val) / grid.area
             else:
                 out[cb, side] = val
             if face_override is not None:

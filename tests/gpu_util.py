@@ -27,6 +27,9 @@ _CACHE = {}
 def _key(wl, nsmooth):
     import hashlib
     h = hashlib.sha256(np.ascontiguousarray(wl.logk).tobytes())
+    if wl.logk_axes is not None:
+        h.update(b"tensor")
+        h.update(np.ascontiguousarray(wl.logk_axes).tobytes())
     h.update(np.ascontiguousarray(wl.source).tobytes())
     for v in wl.bc_value:
         h.update(np.ascontiguousarray(v).tobytes())

@@ -32,8 +32,8 @@ def oracle_jumps(s):
         ci = g.flat(box_coords(lo_i, hi_i)[side_local(lo_i, hi_i, qi)])
         cj = g.flat(box_coords(lo_j, hi_j)[side_local(lo_j, hi_j, qj)])
         ui, uj = s.gflux[i][qi], s.gflux[j][qj]
-        pi_i = s.p[ci] - ui * g.h / (2.0 * g.K[ci])
-        pi_j = s.p[cj] - uj * g.h / (2.0 * g.K[cj])
+        pi_i = s.p[ci] - ui * g.h / (2.0 * g.k(ci, a))
+        pi_j = s.p[cj] - uj * g.h / (2.0 * g.k(cj, a))
         fam = s.interface_family(i, qi)
         for mu in fam:
             w = g.area * mu
