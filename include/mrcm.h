@@ -192,6 +192,20 @@ mrcm_status mrcm_create_batched(int dim, const int* ncell, double h, int nbatch,
  * mrcm_build_basis (MRCM_EINVAL). */
 mrcm_status mrcm_set_permeability(mrcm_ctx* ctx, const double* logk_dev);
 
+/* Diagonal permeability tensor K = diag(K_x, K_y[, K_z]) per cell (paper
+ * Section 2: eq1a with K symmetric positive definite): log K as dim x N
+ * values, component-major (the dim components of axis 0, then axis 1, ...;
+ * each x fastest; for a batch, each component over all members in order).
+ * On the two-point flux a face normal to axis a sees only K_a: in its
+ * transmissibility, its Robin and Dirichlet coefficients, beta = alpha H /
+ * (K_a)_H and the half-cell pressure trace.  Copied; replaces a scalar K
+ * and is replaced by mrcm_set_permeability.  Every forward path takes it;
+ * mrcm_adjoint refuses it (MRCM_EINVAL: the gradient is with respect to a
+ * scalar log K).  The box layouts hold one permeability tile per
+ * component, so 3-D boxes need 2 more halo tiles of LDS.  Errors as
+ * mrcm_set_permeability. */
+mrcm_status mrcm_set_permeability_diag(mrcm_ctx* ctx, const double* logk_dev);
+
 /* Source density f per cell (eq1b; N values) or NULL for f = 0.  Copied. */
 mrcm_status mrcm_set_source(mrcm_ctx* ctx, const double* f_dev);
 

@@ -12,7 +12,8 @@ LIBPATH = os.path.join(HERE, "libmrcm.so")
 STATUS = {0: "MRCM_OK", 1: "MRCM_EINVAL", 2: "MRCM_ENOMEM", 3: "MRCM_EDEVICE", 4: "MRCM_ESTATE",
           5: "MRCM_ENOTPD", 6: "MRCM_ENOCONV", 7: "MRCM_EINCOMPAT", 8: "MRCM_ESINGULAR"}
 
-SYMBOLS = ("mrcm_create", "mrcm_create_batched", "mrcm_set_permeability", "mrcm_set_source", "mrcm_set_bc",
+SYMBOLS = ("mrcm_create", "mrcm_create_batched", "mrcm_set_permeability", "mrcm_set_permeability_diag",
+           "mrcm_set_source", "mrcm_set_bc",
            "mrcm_set_partition", "mrcm_set_interface_space", "mrcm_set_interface_solver",
            "mrcm_set_robin", "mrcm_set_smoothing", "mrcm_set_smoothing_persistent",
            "mrcm_set_timing", "mrcm_set_deferred_errors", "mrcm_wait", "mrcm_set_checkpointing", "mrcm_adjoint",
@@ -58,6 +59,7 @@ def load():
         "mrcm_create": [i, ip, d, vp, ctypes.POINTER(vp)],
         "mrcm_create_batched": [i, ip, d, i, vp, ctypes.POINTER(vp)],
         "mrcm_set_permeability": [vp, vp],
+        "mrcm_set_permeability_diag": [vp, vp],
         "mrcm_set_source": [vp, vp],
         "mrcm_set_bc": [vp, i, i, vp],
         "mrcm_set_partition": [vp, ip, i],

@@ -90,7 +90,12 @@ def configure_batch(ctx, members, precision="fp64", tol=1e-12, max_refine=30, so
     w0 = members[0]
     cat = lambda arrs: torch.as_tensor(np.concatenate([np.ravel(a) for a in arrs]),
                                        dtype=torch.float64, device=dev).contiguous()
-    set_permeability(ctx, cat([w.logk for w in members]))
+    if any(w.logk_axes is not None for w in members):
+        ax = [np.asarray(w.logk_axes if w.logk_axes is not None else
+                         np.stack([w.logk] * w.dim)).reshape(w.dim, -1) for w in members]
+        _set_k(ctx, None, np.concatenate(ax, axis=1), dev)
+    else:
+        set_permeability(ctx, cat([w.logk for w in members]))
     src = [w.source for w in members]
     set_source(ctx, cat(src) if any(np.any(a) for a in src) else None)
     for side, kind in enumerate(w0.bc_type):
@@ -104,6 +109,22 @@ def configure_batch(ctx, members, precision="fp64", tol=1e-12, max_refine=30, so
 
 def set_permeability(ctx, logk):
     _check(ctx, "mrcm_set_permeability", _lib.load().mrcm_set_permeability(ctx.handle, _dev(logk, ctx.ncells)))
+
+
+def set_permeability_diag(ctx, logk_axes):
+    """Diagonal tensor: log K as dim x N values, component-major."""
+    _check(ctx, "mrcm_set_permeability_diag",
+           _lib.load().mrcm_set_permeability_diag(ctx.handle, _dev(logk_axes, ctx.dim * ctx.ncells)))
+
+
+def _set_k(ctx, logk, logk_axes, dev):
+    """log K of one workload, or of a batch's members stacked member after
+    member (a tensor: each component over all members in order)."""
+    if logk_axes is None:
+        set_permeability(ctx, torch.as_tensor(np.ravel(logk), dtype=torch.float64, device=dev).contiguous())
+    else:
+        set_permeability_diag(ctx, torch.as_tensor(np.ravel(logk_axes), dtype=torch.float64,
+                                                   device=dev).contiguous())
 
 
 def set_source(ctx, f):
@@ -329,7 +350,7 @@ def destroy(ctx):
 def configure(ctx, wl, precision="fp64", tol=1e-12, max_refine=30, solver="auto"):
     """Pass a workload record (inputs.Workload) through the set_* calls."""
     dev = "cuda"
-    set_permeability(ctx, torch.as_tensor(wl.logk.ravel(), dtype=torch.float64, device=dev).contiguous())
+    _set_k(ctx, wl.logk, wl.logk_axes, dev)
     src = wl.source.ravel()
     set_source(ctx, torch.as_tensor(src, dtype=torch.float64, device=dev).contiguous() if src.any() else None)
     for side, (kind, vals) in enumerate(zip(wl.bc_type, wl.bc_value)):

@@ -1,5 +1,5 @@
-// Reverse mode of the MRCM-OS map log K -> (pressure, face velocities) on
-// the 2-D one-wave-per-box path: the vector-Jacobian product dJ/dlog K for
+// Reverse mode of the MRCM-OS map log K -> (pressure, face velocities), K
+// scalar, on the 2-D one-wave-per-box path: the vector-Jacobian product dJ/dlog K for
 // given dJ/dp and dJ/d(face velocity), in the FP64 form or the FP32 form
 // with FP64 refinement (the precision of the forward solve).
 //
@@ -94,7 +94,7 @@ __device__ __forceinline__ void box_matrix_adjoint(const Geo& g, const Box& B, c
     for (int k = 0; k < nrhs; ++k)
       tb -= (mu[k * nc + c] - mu[k * nc + o]) * (x[k * nc + c] - x[k * nc + o]);
     const int gx = B.lo[0] + xl, gy = B.lo[1] + yl;
-    const Dkh kk = dkh(kat(s, B, gx, gy), kat(s, B, gx + (a == 0), gy + (a == 1)));
+    const Dkh kk = dkh(kat(s, B, gx, gy, a), kat(s, B, gx + (a == 0), gy + (a == 1), a));
     const double f = tb * g.area / g.h;
     kadd(Kb, g, gx, gy, f * kk.da);
     kadd(Kb, g, gx + (a == 0), gy + (a == 1), f * kk.db);
@@ -110,7 +110,7 @@ __device__ __forceinline__ void box_matrix_adjoint(const Geo& g, const Box& B, c
     const int gx = B.lo[0] + xl, gy = B.lo[1] + yl;
     const int ox = gx + (a == 0 ? (sd ? 1 : -1) : 0), oy = gy + (a == 1 ? (sd ? 1 : -1) : 0);
     const int c = xl + m0 * yl;
-    const double kc = kat(s, B, gx, gy);
+    const double kc = kat(s, B, gx, gy, a);
     const bool dom = off_domain(g, a, a == 0 ? gx : gy, a == 0 ? ox : oy);
     if (dom) {
       if (!g.bc_type[q]) continue;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void box_matrix_adjoint(const Geo& g, const Box& B, c
       kadd(Kb, g, gx, gy, db * 2.0 * g.area / g.h);
       continue;
     }
-    const RobinD r = robin_d(g, a, kc, kat(s, B, ox, oy), beta);
+    const RobinD r = robin_d(g, a, kc, kat(s, B, ox, oy, a), beta);
     double trb = 0.0;
     for (int k = 0; k < nrhs; ++k) {
       const double m = mu[k * nc + c];
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
       const double ub = *gp;
       *gp = 0.0;
       if (ub == 0.0) continue;
-      const double kc = kat(r.b, B, cx, cy), ko = kat(r.b, B, ox, oy);
+      const double kc = kat(r.b, B, cx, cy, a), ko = kat(r.b, B, ox, oy, a);
       const int c = bloc(B, r.b, cx, cy);
       if (win_box(B, ox, oy)) {
         const int o = bloc(B, r.b, ox, oy);
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
         const int cx = a == 0 ? (sd ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
         const int cy = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
         const int ox = cx + (a == 0 ? (sd ? 1 : -1) : 0), oy = cy + (a == 1 ? (sd ? 1 : -1) : 0);
-        const RobinD rd = robin_d(g, a, kat(r.b, B, cx, cy), kat(r.b, B, ox, oy), beta);
+        const RobinD rd = robin_d(g, a, kat(r.b, B, cx, cy, a), kat(r.b, B, ox, oy, a), beta);
         return lambda_s(g, B, r, rd.bt, cx, cy, a, sd);
       },
       [&](int q, int t) { return r.BC[side_off(r.b, q) + t]; },
@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_smooth(Geo g, const Box* __restr
     const int cy = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
     const int ox = cx + (a == 0 ? (sd ? 1 : -1) : 0), oy = cy + (a == 1 ? (sd ? 1 : -1) : 0);
     const int ti = tile_at(r.b, B, cx, cy), to = tile_at(r.b, B, ox, oy);
-    const double kc = r.b.Kt[ti], ko = r.b.Kt[to];
+    const double kc = ktile(r.b, a)[ti], ko = ktile(r.b, a)[to];
     const RobinD rd = robin_d(g, a, kc, ko, beta);
     const int ci = cx + g.n[0] * cy, oi = ox + g.n[0] * oy;
     if (g.l > 0) {
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
         const int cx = a == 0 ? (so ? B.hi[0] - 1 : B.lo[0]) : B.lo[0] + t;
         const int cy = a == 1 ? (so ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
         const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
-        const RobinD rd = robin_d(g, a, kat(s, B, cx, cy), kat(s, B, ox, oy), beta);
+        const RobinD rd = robin_d(g, a, kat(s, B, cx, cy, a), kat(s, B, ox, oy, a), beta);
         s.X[k * nc + bloc(B, s, cx, cy)] = rd.TR * seed_lam(k, sd.side, t);
       }
     }
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(64) k_adj_basis(Geo g, const Box* __restrict__
       int cx, cy;
       wgface(olo, ohi, q, t, cx, cy);
       const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, cx, cy), ko = kat(s, B, ox, oy);
+      const double kc = kat(s, B, cx, cy, a), ko = kat(s, B, ox, oy, a);
       const RobinD rd = robin_d(g, a, kc, ko, beta);
       const int c = bloc(B, s, cx, cy);
       const double xc = xs[k * nc + c];
@@ -737,7 +737,7 @@ __global__ void __launch_bounds__(64) k_adj_particular(Geo g, const Box* __restr
       int cx, cy;
       wgface(B.lo, B.hi, q, t, cx, cy);
       const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, cx, cy), ko = kat(s, B, ox, oy);
+      const double kc = kat(s, B, cx, cy, a), ko = kat(s, B, ox, oy, a);
       const RobinD rd = robin_d(g, a, kc, ko, beta);
       const int c = bloc(B, s, cx, cy);
       // ubar = T^R pbar_c / |e|, pibar = beta ubar

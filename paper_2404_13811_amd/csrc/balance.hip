@@ -156,6 +156,7 @@ __device__ __forceinline__ void jumps_one(const Geo& g, const Iface F, const See
                                           const JumpTerms& tr, double worst[2]) {
   const int L = threadIdx.x & 63;
   const int qi = 2 * F.axis + 1, qj = 2 * F.axis;
+  K += kaxis(g, F.axis);  // the entry normal to the interface
   int ilo[3], ihi[3], jlo[3], jhi[3];
   iface_box(g, F.i, ilo, ihi);
   iface_box(g, F.j, jlo, jhi);

@@ -43,7 +43,8 @@ struct mrcm_ctx {
   bool plan_valid = false;
 
   // inputs (device)
-  double* logk = nullptr;
+  double* logk = nullptr;  // log K: N values, or d x N (diagonal tensor, component-major)
+  int kcomp = 1;           // permeability entries per cell
   double* K = nullptr;
   double* f = nullptr;
   bool have_f = false;
@@ -559,6 +560,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   g.area = std::pow(c->h, c->d - 1);
   g.vol = std::pow(c->h, c->d);
   g.beta_mode = c->beta_mode == MRCM_BETA_CONST ? 1 : 0;
+  g.kc = c->kcomp;
   g.ncells = 1;
   g.nsub = 1;
   g.neumann = 1;
@@ -666,13 +668,14 @@ mrcm_status make_plan(mrcm_ctx* c) {
     const Box& P = c->pbox[i];
     if (B.nb > 32 || P.nb > 32) c->wave = false;
     const int bm0 = B.hi[0] - B.lo[0], bm1 = B.hi[1] - B.lo[1];
-    c->lds_basis = std::max(c->lds_basis, wave_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1)));
-    c->lds_factor = std::max(c->lds_factor, wave_basis_lds_bytes(bm0, bm1, 0));
-    c->lds_smooth = std::max(c->lds_smooth, wave_smooth_lds_bytes(bm0, bm1));
-    c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1));
-    c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0));
-    c->lds32_smooth = std::max(c->lds32_smooth, wave32_smooth_lds_bytes(bm0, bm1));
-    c->lds32_part = std::max(c->lds32_part, wave32_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, 1));
+    const int kc = c->kcomp;
+    c->lds_basis = std::max(c->lds_basis, wave_basis_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), kc));
+    c->lds_factor = std::max(c->lds_factor, wave_basis_lds_bytes(bm0, bm1, 0, kc));
+    c->lds_smooth = std::max(c->lds_smooth, wave_smooth_lds_bytes(bm0, bm1, kc));
+    c->lds_part = std::max(c->lds_part, wave_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, kc));
+    c->lds32_basis = std::max(c->lds32_basis, wave32_lds_bytes(bm0, bm1, std::max(B.nrhs, 1), 0, kc));
+    c->lds32_smooth = std::max(c->lds32_smooth, wave32_smooth_lds_bytes(bm0, bm1, kc));
+    c->lds32_part = std::max(c->lds32_part, wave32_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], 1, 1, kc));
     if (c->d == 2) {
       for (int f32 = 0; f32 < 2; ++f32) {
         size_t& ls = f32 ? c->lds_adj32_smooth : c->lds_adj_smooth;
@@ -697,10 +700,11 @@ mrcm_status make_plan(mrcm_ctx* c) {
     nb3_box = std::max(nb3_box, B.nb);
     nb3_part = std::max(nb3_part, P.nb);
     const int m[3] = {B.hi[0] - B.lo[0], B.hi[1] - B.lo[1], B.hi[2] - B.lo[2]};
-    c->lds3_basis = std::max(c->lds3_basis, box3_lds_bytes(m[0], m[1], m[2], std::max(B.nrhs, 1)));
-    c->lds3_smooth = std::max(c->lds3_smooth, box3_lds_bytes(m[0], m[1], m[2], 1));
+    const int kc = c->kcomp;
+    c->lds3_basis = std::max(c->lds3_basis, box3_lds_bytes(m[0], m[1], m[2], std::max(B.nrhs, 1), kc));
+    c->lds3_smooth = std::max(c->lds3_smooth, box3_lds_bytes(m[0], m[1], m[2], 1, kc));
     c->lds3_part = std::max(c->lds3_part, box3_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1],
-                                                         P.hi[2] - P.lo[2], 1));
+                                                         P.hi[2] - P.lo[2], 1, kc));
   }
   if (c->lds3_basis > 150 * 1024 || c->lds3_smooth > 150 * 1024 || c->lds3_part > 150 * 1024)
     c->d3 = false;
@@ -1012,8 +1016,9 @@ mrcm_status create_ctx(int dim, const int* ncell, double h, int nbatch, void* st
     off += side_values(c, q);
   }
   c->nbcv = off;
-  hipError_t e = hipMalloc((void**)&c->logk, N * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&c->K, N * sizeof(double));
+  // room for a diagonal tensor's d entries per cell
+  hipError_t e = hipMalloc((void**)&c->logk, (size_t)dim * N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->K, (size_t)dim * N * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->f, N * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->bcv, off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&c->flags, sizeof(int));
@@ -1051,7 +1056,21 @@ mrcm_status mrcm_set_permeability(mrcm_ctx* c, const double* logk_dev) {
   const long long N = (long long)c->n[0] * c->n[1] * c->n[2];
   HIPCHK(c, hipMemcpyAsync(c->logk, logk_dev, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   c->have_k = true;
-  invalidate(c, false);
+  // the box layouts hold one permeability tile per entry of a cell
+  invalidate(c, c->kcomp != 1);
+  c->kcomp = 1;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_set_permeability_diag(mrcm_ctx* c, const double* logk_dev) {
+  if (!c) return MRCM_EINVAL;
+  if (!logk_dev) return fail(c, MRCM_EINVAL, "logk is NULL");
+  const long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+  HIPCHK(c, hipMemcpyAsync(c->logk, logk_dev, (size_t)c->d * N * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  c->have_k = true;
+  invalidate(c, c->kcomp != c->d);
+  c->kcomp = c->d;
   return MRCM_OK;
 }
 
@@ -1168,7 +1187,8 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
   if (!c->flags_zero && !c->deferred) HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   c->flags_zero = false;
   // K = exp(log K): inside the local kernels on the FP64 wave and 3-D paths
-  if (r32 || !(c->wave || c->d3)) HIPCHK(c, launch_exp(c->logk, c->K, c->geo.ncells, c->flags, s));
+  if (r32 || !(c->wave || c->d3))
+    HIPCHK(c, launch_exp(c->logk, c->K, c->kcomp * c->geo.ncells, c->flags, s));
   if (r32) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
@@ -1599,6 +1619,7 @@ mrcm_status mrcm_adjoint(mrcm_ctx* c, const double* dJdp, const double* dJdflux,
   if (c->state < 2) return fail(c, MRCM_ESTATE, "no solution to differentiate");
   if (!c->wave || c->d != 2)
     return fail(c, MRCM_EINVAL, "the adjoint needs 2-D boxes with lines of <= 32 cells");
+  if (c->kcomp != 1) return fail(c, MRCM_EINVAL, "the adjoint needs a scalar permeability");
   if (!c->use_bcr)
     return fail(c, MRCM_EINVAL, "the adjoint needs the block-cyclic-reduction interface solver");
   if (c->n_ck != c->n_phase)

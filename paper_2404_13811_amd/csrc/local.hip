@@ -343,8 +343,9 @@ __global__ void __launch_bounds__(NT) k_basis(Geo g, const Box* __restrict__ box
       }
       int o[3] = {c[0], c[1], c[2]};
       o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)];
-      const double bt = robin_beta(g, a, kc, K[gcell(g, o)], beta);
+      const double* Ka = K + kaxis(g, a);
+      const double kc = Ka[gcell(g, c)];
+      const double bt = robin_beta(g, a, kc, Ka[gcell(g, o)], beta);
       S[(long long)k * B.ncell + cell_loc(B, c)] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
     }
   }
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(NT) k_basis(Geo g, const Box* __restrict__ box
       gamma_face_cell(g, olo, ohi, q, t, c);
       o[0] = c[0]; o[1] = c[1]; o[2] = c[2];
       o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)], ko = K[gcell(g, o)];
+      const double kc = K[kaxis(g, a) + gcell(g, c)], ko = K[kaxis(g, a) + gcell(g, o)];
       const double Pc = S[(long long)k * B.ncell + cell_loc(B, c)];
       double u;
       if (in_box(B, o)) {
@@ -418,7 +419,7 @@ __device__ void physical_rhs(const Geo& g, const Box& B, const double* K, const 
         if (!off_domain(g, a, c[a], t)) continue;
         const int side = 2 * a + s;
         const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-        if (g.bc_type[side]) b += 2.0 * K[ci] * g.area / g.h * val;
+        if (g.bc_type[side]) b += 2.0 * K[kaxis(g, a) + ci] * g.area / g.h * val;
         else b -= g.area * val;
       }
     S[loc] = b;
@@ -460,8 +461,9 @@ __global__ void __launch_bounds__(NT) k_particular(Geo g, const Box* __restrict_
       gamma_face_cell(g, B.lo, B.hi, q, t, c);
       o[0] = c[0]; o[1] = c[1]; o[2] = c[2];
       o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)];
-      const double bt = robin_beta(g, a, kc, K[gcell(g, o)], beta);
+      const double* Ka = K + kaxis(g, a);
+      const double kc = Ka[gcell(g, c)];
+      const double bt = robin_beta(g, a, kc, Ka[gcell(g, o)], beta);
       const double u = robin_T(g, kc, bt) * (S[cell_loc(B, c)] - 0.0) / g.area;
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
@@ -479,7 +481,7 @@ __device__ __forceinline__ double smooth_lambda(const Geo& g, const Box& B, cons
   int o[3] = {c[0], c[1], c[2]};
   o[a] += s ? 1 : -1;
   const int ci = gcell(g, c), oi = gcell(g, o);
-  const double kc = K[ci], ko = K[oi];
+  const double kc = K[kaxis(g, a) + ci], ko = K[kaxis(g, a) + oi];
   const double bt = robin_beta(g, a, kc, ko, beta);
   if (g.l > 0) {
     const double u = g.area * kharm(kc, ko) / g.h * (p[ci] - p[oi]) / g.area;
@@ -521,8 +523,8 @@ __global__ void __launch_bounds__(NT) k_smooth(Geo g, const Box* __restrict__ bo
         if (face_kind(g, B, c, a, s) != kFaceRobin) continue;
         int o[3] = {c[0], c[1], c[2]};
         o[a] += s ? 1 : -1;
-        const double kc = K[gcell(g, c)];
-        const double bt = robin_beta(g, a, kc, K[gcell(g, o)], beta);
+        const double kc = K[kaxis(g, a) + gcell(g, c)];
+        const double bt = robin_beta(g, a, kc, K[kaxis(g, a) + gcell(g, o)], beta);
         add += robin_T(g, kc, bt) * smooth_lambda(g, B, K, p, gflux, beta, c, a, s);
       }
     S[loc] += add;
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(NT) k_smooth(Geo g, const Box* __restrict__ bo
       gamma_face_cell(g, olo, ohi, q, t, c);
       o[0] = c[0]; o[1] = c[1]; o[2] = c[2];
       o[a] += s ? 1 : -1;
-      const double kc = K[gcell(g, c)], ko = K[gcell(g, o)];
+      const double kc = K[kaxis(g, a) + gcell(g, c)], ko = K[kaxis(g, a) + gcell(g, o)];
       const double xc = S[cell_loc(B, c)];
       double u;
       if (in_box(B, o)) {

@@ -85,19 +85,32 @@ struct Box3 {
   double* X;   // nrhs x ncell right-hand sides / solutions
   double* Z;   // nrhs x 64 staging of one block
   int m0, m1, m2, nc;
+  // diagonal permeability tensor: halo tiles of the entries of axes 1..,
+  // ktn doubles apart (ktn = 0: scalar K, every axis reads Kt)
+  double* Kx;
+  int ktn;
 };
 
-__host__ __device__ inline size_t box3_doubles(int m0, int m1, int m2, int nrhs) {
-  const size_t nc = (size_t)m0 * m1 * m2;
-  return (size_t)(m0 + 2) * (m1 + 2) * (m2 + 2) + 2 * nc + (size_t)nrhs * nc + (size_t)nrhs * P3 + 4;
+// LDS of those extra tiles (ahead of the box's other arrays; even).
+__host__ __device__ inline size_t kx3_doubles(int kc, int m0, int m1, int m2) {
+  return kc > 1 ? ((size_t)(kc - 1) * (m0 + 2) * (m1 + 2) * (m2 + 2) + 1) / 2 * 2 : 0;
 }
 
-__device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs) {
+__host__ __device__ inline size_t box3_doubles(int m0, int m1, int m2, int nrhs, int kc = 1) {
+  const size_t nc = (size_t)m0 * m1 * m2;
+  return kx3_doubles(kc, m0, m1, m2) + (size_t)(m0 + 2) * (m1 + 2) * (m2 + 2) + 2 * nc +
+         (size_t)nrhs * nc + (size_t)nrhs * P3 + 4;
+}
+
+__device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs, int kc) {
   Box3 s;
   s.m0 = B.hi[0] - B.lo[0];
   s.m1 = B.hi[1] - B.lo[1];
   s.m2 = B.hi[2] - B.lo[2];
   s.nc = s.m0 * s.m1 * s.m2;
+  s.Kx = base;
+  s.ktn = kc > 1 ? (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2) : 0;
+  base += kx3_doubles(kc, s.m0, s.m1, s.m2);
   s.Kt = base;
   s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2);
   s.Tz = s.Dg + s.nc;
@@ -109,8 +122,10 @@ __device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs) {
   return s;
 }
 
-__device__ __forceinline__ double k3(const Box3& s, const Box& B, int x, int y, int z) {
-  return s.Kt[((z - B.lo[2] + 1) * (s.m1 + 2) + (y - B.lo[1] + 1)) * (s.m0 + 2) + (x - B.lo[0] + 1)];
+// K along axis a at global cell (x, y, z) of the box or its halo.
+__device__ __forceinline__ double k3(const Box3& s, const Box& B, int x, int y, int z, int a) {
+  const double* t = (a > 0 && s.ktn) ? s.Kx + (a - 1) * s.ktn : s.Kt;
+  return t[((z - B.lo[2] + 1) * (s.m1 + 2) + (y - B.lo[1] + 1)) * (s.m0 + 2) + (x - B.lo[0] + 1)];
 }
 
 __device__ __forceinline__ double rcp3(double x) {
@@ -145,14 +160,22 @@ __device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const doub
       if (e < nt) s.Kt[e] = LOG ? exp(v[u]) : v[u];
     }
   }
+  // the other axes' entries of a diagonal tensor
+  for (int e = tid; e < (s.ktn ? (g.kc - 1) * nt : 0); e += NT) {
+    const int ax = 1 + e / nt, u = e - (ax - 1) * nt;
+    const int x = B.lo[0] - 1 + u % W0, y = B.lo[1] - 1 + (u / W0) % W1, z = B.lo[2] - 1 + u / (W0 * W1);
+    const bool in = x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2];
+    const double v = in ? Kg[kaxis(g, ax) + x + g.n[0] * (y + g.n[1] * z)] : (LOG ? 0.0 : 1.0);
+    s.Kx[e] = LOG ? exp(v) : v;
+  }
   bsync<NW>();
   const double ih = rcp3(g.h);
   for (int loc = tid; loc < s.nc; loc += NT) {
     const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + (loc / s.m0) % s.m1, z = B.lo[2] + loc / (s.m0 * s.m1);
-    const double kc = k3(s, B, x, y, z);
     double diag = 0.0, tz = 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
+      const double kc = k3(s, B, x, y, z, a);
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         int o[3] = {x, y, z};
@@ -161,7 +184,7 @@ __device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const doub
           if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area * ih;
           continue;
         }
-        const double ko = k3(s, B, o[0], o[1], o[2]);
+        const double ko = k3(s, B, o[0], o[1], o[2], a);
         const bool inside = o[a] >= B.lo[a] && o[a] < B.hi[a];
         if (inside) {
           const double T = g.area * 2.0 * kc * ko * rcp3(kc + ko) * ih;
@@ -172,6 +195,7 @@ __device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const doub
           diag += robin_T(g, kc, bt);
         }
       }
+    }
     s.Dg[loc] = diag;
     s.Tz[loc] = tz;
   }
@@ -184,7 +208,7 @@ __device__ __forceinline__ double tplane(const Geo& g, const Box& B, const Box3&
   const int x = B.lo[0] + a % s.m0, y = B.lo[1] + a / s.m0, z = B.lo[2] + j;
   const int ox = x + (axis == 0), oy = y + (axis == 1);
   if (ox >= B.hi[0] || oy >= B.hi[1]) return 0.0;
-  const double kc = k3(s, B, x, y, z), ko = k3(s, B, ox, oy, z);
+  const double kc = k3(s, B, x, y, z, axis), ko = k3(s, B, ox, oy, z, axis);
   return g.area * 2.0 * kc * ko * rcp3(kc + ko) * rcp3(g.h);
 }
 
@@ -528,7 +552,7 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
   const int nrhs = FO ? 0 : B.nrhs;
-  Box3 s = carve3(dsm, B, nrhs);
+  Box3 s = carve3(dsm, B, nrhs, g.kc);
   load_box3<NW, true>(g, B, logK, beta, s);
   for (int e = tid; e < nrhs * s.nc; e += NT) s.X[e] = 0.0;
   bsync<NW>();
@@ -544,8 +568,8 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
       face3(B.lo, B.hi, sd.side, t, c);
       int o[3] = {c[0], c[1], c[2]};
       o[a] += so ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2]);
-      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2]), beta);
+      const double kc = k3(s, B, c[0], c[1], c[2], a);
+      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2], a), beta);
       s.X[k * s.nc + bloc3(B, s, c)] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
     }
   }
@@ -580,7 +604,7 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
       face3(olo, ohi, q, t, c);
       int o[3] = {c[0], c[1], c[2]};
       o[a] += so ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2]), ko = k3(s, B, o[0], o[1], o[2]);
+      const double kc = k3(s, B, c[0], c[1], c[2], a), ko = k3(s, B, o[0], o[1], o[2], a);
       const double Pc = s.X[k * s.nc + bloc3(B, s, c)];
       const double bt = robin_beta(g, a, kc, ko, beta);
       double u;
@@ -608,14 +632,13 @@ __device__ __forceinline__ void physical3(const Geo& g, const Box& B, const Box3
     const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
     const int ci = gcell(g, c);
     double b = f[ci] * g.vol;
-    const double kc = k3(s, B, c[0], c[1], c[2]);
     for (int a = 0; a < 3; ++a)
       for (int sd = 0; sd < 2; ++sd) {
         const int t = c[a] + (sd ? 1 : -1);
         if (t >= 0 && t < g.n[a]) continue;
         const int side = 2 * a + sd;
         const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-        if (g.bc_type[side]) b += 2.0 * kc * g.area / g.h * val;
+        if (g.bc_type[side]) b += 2.0 * k3(s, B, c[0], c[1], c[2], a) * g.area / g.h * val;
         else b -= g.area * val;
       }
     X[loc] = b;
@@ -634,13 +657,15 @@ __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
                                             double* dsm, Gj3& sm) {
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
-  Box3 s = carve3(dsm, B, 1);
+  Box3 s = carve3(dsm, B, 1, g.kc);
   load_box3<NW, true>(g, B, logK, beta, s);
   for (int loc = tid; loc < s.nc; loc += NT) {
     const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
-    const double k = k3(s, B, c[0], c[1], c[2]);
-    if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
-    K[gcell(g, c)] = k;
+    for (int a = 0; a < g.kc; ++a) {
+      const double k = k3(s, B, c[0], c[1], c[2], a);
+      if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
+      K[kaxis(g, a) + gcell(g, c)] = k;
+    }
   }
   physical3<NW>(g, B, s, f, bcv, s.X);
   bsync<NW>();
@@ -665,8 +690,8 @@ __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
       face3(B.lo, B.hi, q, t, c);
       int o[3] = {c[0], c[1], c[2]};
       o[a] += so ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2]);
-      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2]), beta);
+      const double kc = k3(s, B, c[0], c[1], c[2], a);
+      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2], a), beta);
       const double u = robin_T(g, kc, bt) * s.X[bloc3(B, s, c)] / g.area;
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
@@ -684,7 +709,7 @@ __device__ __forceinline__ double lambda3(const Geo& g, const Box& B, const Box3
                                           const int c[3], int a, int sd) {
   int o[3] = {c[0], c[1], c[2]};
   o[a] += sd ? 1 : -1;
-  const double kc = k3(s, B, c[0], c[1], c[2]), ko = k3(s, B, o[0], o[1], o[2]);
+  const double kc = k3(s, B, c[0], c[1], c[2], a), ko = k3(s, B, o[0], o[1], o[2], a);
   const double bt = robin_beta(g, a, kc, ko, beta);
   const int ci = gcell(g, c), oi = gcell(g, o);
   if (g.l > 0) {
@@ -712,7 +737,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
                                         double* dsm, Gj3& sm) {
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
-  Box3 s = carve3(dsm, B, 1);
+  Box3 s = carve3(dsm, B, 1, g.kc);
   load_box3<NW, false>(g, B, K, beta, s);
   physical3<NW>(g, B, s, f, bcv, s.X);
   bsync<NW>();
@@ -725,8 +750,8 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
         if (o < 0 || o >= g.n[a] || (o >= B.lo[a] && o < B.hi[a])) continue;
         int oc[3] = {c[0], c[1], c[2]};
         oc[a] = o;
-        const double kc = k3(s, B, c[0], c[1], c[2]);
-        const double bt = robin_beta(g, a, kc, k3(s, B, oc[0], oc[1], oc[2]), beta);
+        const double kc = k3(s, B, c[0], c[1], c[2], a);
+        const double bt = robin_beta(g, a, kc, k3(s, B, oc[0], oc[1], oc[2], a), beta);
         add += robin_T(g, kc, bt) * lambda3(g, B, s, p, gflux, beta, c, a, sd);
       }
     s.X[loc] += add;
@@ -754,7 +779,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
       face3(olo, ohi, q, t, c);
       int o[3] = {c[0], c[1], c[2]};
       o[a] += sd ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2]), ko = k3(s, B, o[0], o[1], o[2]);
+      const double kc = k3(s, B, c[0], c[1], c[2], a), ko = k3(s, B, o[0], o[1], o[2], a);
       const double xc = s.X[bloc3(B, s, c)];
       double u;
       if (inbox3(B, o)) {
@@ -841,8 +866,8 @@ hipError_t lds_attr3(KF kern, size_t bytes) {
 
 }  // namespace
 
-size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs) {
-  return sizeof(double) * box3_doubles(m0, m1, m2, nrhs);
+size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs, int kc) {
+  return sizeof(double) * box3_doubles(m0, m1, m2, nrhs, kc);
 }
 
 int box3_waves(int nb) { return nb <= R3 ? 1 : nb <= 2 * R3 ? 2 : 4; }

@@ -7,7 +7,8 @@
 //   Robin face      |e| u = T^R (p_c - lam), T^R = |e| / (h / (2 K_c) + beta)
 //   Dirichlet face  |e| u = 2 K_c |e| / h (p_c - g)
 //   Neumann face    |e| u = |e| z
-// and mass balance per cell gives A p = b.  Cells of a box are numbered x
+// (with a diagonal permeability tensor, K of a face normal to axis a is the
+// entry of axis a) and mass balance per cell gives A p = b.  Cells of a box are numbered x
 // fastest; the dense blocks of the block-tridiagonal matrix are the cells
 // sharing the last-axis coordinate (lines in 2-D, planes in 3-D).
 #pragma once
@@ -95,6 +96,7 @@ __device__ __forceinline__ double state_face_u(const Geo& g, const double* __res
   const int q = 2 * a + s;
   int o[3] = {c[0], c[1], c[2]};
   o[a] += s ? 1 : -1;
+  K += kaxis(g, a);
   const double kc = K[ci];
   if (off_domain(g, a, c[a], o[a])) {
     const double val = bcv[g.bc_off[q] + bface_index(g, c, a)];
@@ -149,18 +151,19 @@ __device__ __forceinline__ CellCoef cell_coef(const Geo& g, const Box& B, const 
   r.diag = 0.0;
   r.tp[0] = r.tp[1] = r.tp[2] = 0.0;
   const int ci = gcell(g, c);
-  const double kc = K[ci];
   for (int a = 0; a < g.d; ++a) {
+    const double* Ka = K + kaxis(g, a);
+    const double kc = Ka[ci];
     for (int s = 0; s < 2; ++s) {
       int o[3] = {c[0], c[1], c[2]};
       o[a] += s ? 1 : -1;
       const int kind = face_kind(g, B, c, a, s);
       if (kind == kFaceInterior) {
-        const double T = g.area * kharm(kc, K[gcell(g, o)]) / g.h;
+        const double T = g.area * kharm(kc, Ka[gcell(g, o)]) / g.h;
         r.diag += T;
         if (s) r.tp[a] = T;
       } else if (kind == kFaceRobin) {
-        const double b = robin_beta(g, a, kc, K[gcell(g, o)], beta);
+        const double b = robin_beta(g, a, kc, Ka[gcell(g, o)], beta);
         r.diag += robin_T(g, kc, b);
       } else if (kind == kFaceDir) {
         r.diag += 2.0 * kc * g.area / g.h;

@@ -74,8 +74,8 @@ __device__ __forceinline__ void factor_forward(const Box& B, double* Wg, double*
 // LDS of a basis box: the box arrays with its right-hand sides (the Z
 // scratch of BoxLds serves wave 0), the Z scratch of wave 1, and the forward
 // Schur complement of the meeting block (nb x nb, nb = m0, row-major).
-__host__ __device__ inline size_t basis_lds_doubles(int m0, int m1, int nrhs) {
-  return box_lds_doubles(m0, m1, nrhs) + (size_t)nrhs * NBW + (size_t)m0 * m0 + 2;
+__host__ __device__ inline size_t basis_lds_doubles(int m0, int m1, int nrhs, int kc = 1) {
+  return box_lds_doubles(m0, m1, nrhs, kc) + (size_t)nrhs * NBW + (size_t)m0 * m0 + 2;
 }
 
 // Steps 1-2: factor the oversampled box, solve every seed, extract
@@ -103,7 +103,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
   const int L = lane_id();
   const int tid = threadIdx.x, wv = tid >> 6;
   const int nrhs = FO ? 0 : B.nrhs;
-  BoxLds s = carve(dsm, B, nrhs);
+  BoxLds s = carve(dsm, B, nrhs, g.kc);
   double* Z1 = s.Z + nrhs * NBW;
   double* Sm = Z1 + nrhs * NBW;
   const int nc = B.ncell;
@@ -126,8 +126,8 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
     else { c[1] = so ? B.hi[1] - 1 : B.lo[1]; c[0] = B.lo[0] + t; }
     c[2] = 0;
     const int ox = c[0] + (a == 0 ? (so ? 1 : -1) : 0), oy = c[1] + (a == 1 ? (so ? 1 : -1) : 0);
-    const double kc = kat(s, B, c[0], c[1]);
-    const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+    const double kc = kat(s, B, c[0], c[1], a);
+    const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy, a), beta);
     s.X[k * nc + bloc(B, s, c[0], c[1])] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
   }
   if (!FO)
@@ -210,7 +210,7 @@ __device__ __forceinline__ void basis_box(const Geo& g, const Box& B, const Seed
       int x, y;
       wgface(olo, ohi, q, t, x, y);
       const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+      const double kc = kat(s, B, x, y, a), ko = kat(s, B, ox, oy, a);
       const double Pc = s.X[k * nc + bloc(B, s, x, y)];
       const double bt = robin_beta(g, a, kc, ko, beta);
       double u;
@@ -243,13 +243,15 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B,
                                                double* __restrict__ pbar, double* __restrict__ ubar,
                                                double* __restrict__ pibar, double* dsm, WaveSmem& sm) {
   const int L = lane_id();
-  BoxLds s = carve(dsm, B, 1);
+  BoxLds s = carve(dsm, B, 1, g.kc);
   load_box<64, true>(g, B, logK, beta, s);
   for (int t = L; t < B.ncell; t += 64) {
     const int x = B.lo[0] + t % s.m0, y = B.lo[1] + t / s.m0;
-    const double k = kat(s, B, x, y);
-    if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
-    K[x + g.n[0] * y] = k;
+    for (int a = 0; a < g.kc; ++a) {
+      const double k = kat(s, B, x, y, a);
+      if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
+      K[kaxis(g, a) + x + g.n[0] * y] = k;
+    }
   }
   physical_rhs(g, B, s, f, bcv, s.X);
   wsync();
@@ -272,8 +274,8 @@ __device__ __forceinline__ void particular_box(const Geo& g, const Box& B,
       int x, y;
       wgface(B.lo, B.hi, q, t, x, y);
       const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, x, y);
-      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+      const double kc = kat(s, B, x, y, a);
+      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy, a), beta);
       const double u = robin_T(g, kc, bt) * s.X[bloc(B, s, x, y)] / g.area;
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
@@ -369,7 +371,7 @@ __device__ __forceinline__ void smooth_box(const Geo& g, const Box& B, const dou
                                            const double* __restrict__ tcoup, double* p,
                                            double* gflux, double w[RING][HB], const double zm[HB],
                                            double* dsm) {
-  SmoothLds r = carve_smooth(dsm, B);
+  SmoothLds r = carve_smooth(dsm, B, g.kc);
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, tcoup);
   bsync<NT>();
   smooth_rhs<NT>(g, B, r, beta, r.b.X);
@@ -454,15 +456,15 @@ hipError_t set_lds(KF kern, size_t bytes) {
 
 }  // namespace
 
-size_t wave_basis_lds_bytes(int m0, int m1, int nrhs) {
-  return sizeof(double) * basis_lds_doubles(m0, m1, nrhs);
+size_t wave_basis_lds_bytes(int m0, int m1, int nrhs, int kc) {
+  return sizeof(double) * basis_lds_doubles(m0, m1, nrhs, kc);
 }
 
-size_t wave_lds_bytes(int m0, int m1, int nrhs) {
-  return sizeof(double) * box_lds_doubles(m0, m1, nrhs);
+size_t wave_lds_bytes(int m0, int m1, int nrhs, int kc) {
+  return sizeof(double) * box_lds_doubles(m0, m1, nrhs, kc);
 }
 
-size_t wave_smooth_lds_bytes(int m0, int m1) { return sizeof(double) * smooth_lds_doubles(m0, m1); }
+size_t wave_smooth_lds_bytes(int m0, int m1, int kc) { return sizeof(double) * smooth_lds_doubles(m0, m1, kc); }
 
 hipError_t launch_local_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
                           const Seed* seeds, const double* logK, double* K, const double* f,

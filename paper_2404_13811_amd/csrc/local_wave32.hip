@@ -31,7 +31,7 @@ __device__ __forceinline__ void basis32_box(const Geo& g, const Box& B, const Se
                                             WaveSmemF& sm) {
   const int L = lane_id();
   const int nrhs = B.nrhs;
-  BoxR R = carve_r(dsm, B, max(nrhs, 1), 0);
+  BoxR R = carve_r(dsm, B, max(nrhs, 1), 0, g.kc);
   load_box(g, B, K, beta, R.b);
   scale_box(B, R);
   float* Wg = fac32 + B.fac;
@@ -66,7 +66,7 @@ __device__ __forceinline__ void basis32_box(const Geo& g, const Box& B, const Se
       int x, y;
       wgface(olo, ohi, q, t, x, y);
       const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+      const double kc = kat(s, B, x, y, a), ko = kat(s, B, ox, oy, a);
       const double Pc = s.X[k * nc + bloc(B, s, x, y)];
       const double bt = robin_beta(g, a, kc, ko, beta);
       double u;
@@ -96,7 +96,7 @@ __device__ __forceinline__ void particular32_box(const Geo& g, const Box& B, con
                                                  unsigned long long* resid, double* dsm,
                                                  WaveSmemF& sm) {
   const int L = lane_id();
-  BoxR R = carve_r(dsm, B, 1, 1);
+  BoxR R = carve_r(dsm, B, 1, 1, g.kc);
   load_box(g, B, K, beta, R.b);
   scale_box(B, R);
   physical_rhs(g, B, R.b, f, bcv, R.Bv);
@@ -123,8 +123,8 @@ __device__ __forceinline__ void particular32_box(const Geo& g, const Box& B, con
       int x, y;
       wgface(B.lo, B.hi, q, t, x, y);
       const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-      const double kc = kat(s, B, x, y);
-      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy), beta);
+      const double kc = kat(s, B, x, y, a);
+      const double bt = robin_beta(g, a, kc, kat(s, B, ox, oy, a), beta);
       const double u = robin_T(g, kc, bt) * s.X[bloc(B, s, x, y)] / g.area;
       ubar[oidx] = u;
       pibar[oidx] = bt * u;
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(NT) k_smooth32(Geo g, const Box* __restrict__ 
   __shared__ WaveSmemF sm;
   const Box B = boxes[blockIdx.x];
   if (threadIdx.x == 0) sm.flag = 0;
-  SmoothLds r = carve_smooth(dsm, B);
+  SmoothLds r = carve_smooth(dsm, B, g.kc);
   BoxR R = carve_smooth_r(dsm, r);
   stage_smooth<NT>(g, B, r, K, p, f, gflux, bcv, nullptr);
   __syncthreads();
@@ -231,9 +231,11 @@ hipError_t set_lds(KF kern, size_t bytes) {
 
 }  // namespace
 
-size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs) { return boxr_bytes(m0, m1, nrhs, nbrhs); }
+size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs, int kc) {
+  return boxr_bytes(m0, m1, nrhs, nbrhs, kc);
+}
 
-size_t wave32_smooth_lds_bytes(int m0, int m1) { return smooth32_lds_bytes(m0, m1); }
+size_t wave32_smooth_lds_bytes(int m0, int m1, int kc) { return smooth32_lds_bytes(m0, m1, kc); }
 
 hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
                             const Seed* seeds, const double* K, const double* f, const double* bcv,

@@ -36,8 +36,16 @@ struct Geo {
   // across a cut, which bounds each member like the domain boundary
   // (0: one problem)
   int cut, mcut;
+  // permeability entries per cell: 1 (scalar K) or d (diagonal tensor,
+  // component-major: the entry of axis a of cell c at K[a * ncells + c])
+  int kc;
   double h, area, vol;
 };
+
+// Offset of axis a's permeability entries (0 for scalar K).
+__host__ __device__ inline long long kaxis(const Geo& g, int a) {
+  return g.kc > 1 ? (long long)a * g.ncells : 0;
+}
 
 // Moving from coordinate `from` to `to` along axis a leaves the domain (or
 // the batch member).
@@ -133,10 +141,10 @@ hipError_t launch_smooth(const Geo& g, const Box* boxes, const int* members, int
                          int max_refine, int* iters, double* resid, int* flags, hipStream_t s);
 
 // one-wavefront-per-box 2-D kernels (local_wave.hip), blocks of <= 32 cells
-size_t wave_lds_bytes(int m0, int m1, int nrhs);
+size_t wave_lds_bytes(int m0, int m1, int nrhs, int kc);
 // LDS of a two-wave basis box of k_local_w
-size_t wave_basis_lds_bytes(int m0, int m1, int nrhs);
-size_t wave_smooth_lds_bytes(int m0, int m1);
+size_t wave_basis_lds_bytes(int m0, int m1, int nrhs, int kc);
+size_t wave_smooth_lds_bytes(int m0, int m1, int kc);
 // Steps 1-2 (oversampled boxes obox) and Step 4 (subdomain boxes pbox, one
 // or two per workgroup) in one launch; lds_part = LDS of one subdomain box,
 // lds >= the basis boxes' need and lds_part (two per workgroup when lds
@@ -182,7 +190,7 @@ hipError_t launch_smooth_grid(const Geo& g, const Box* boxes, const SmoothPhases
                               int max_groups, hipStream_t s);
 
 // one-wavefront-per-box 3-D kernels (local3.hip), plane blocks of <= 64 cells
-size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs);
+size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs, int kc);
 // wavefronts per box for plane blocks of nb cells (1, 2 or 4)
 int box3_waves(int nb);
 // Steps 1-2 (factor_only: Step 6) on oversampled boxes; reads log K
@@ -202,8 +210,8 @@ hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double
                           size_t lds, int nw, hipStream_t s);
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
-size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs);
-size_t wave32_smooth_lds_bytes(int m0, int m1);
+size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs, int kc);
+size_t wave32_smooth_lds_bytes(int m0, int m1, int kc);
 hipError_t launch_local32_w(const Geo& g, const Box* obox, const Box* pbox, int nbox,
                             const Seed* seeds, const double* K, const double* f, const double* bcv,
                             double beta, float* fac32, float* facp32, double* Pk, double* tr_u,

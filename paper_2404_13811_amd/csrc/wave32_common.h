@@ -26,18 +26,19 @@ struct BoxR {
   float* Zf;    // nrhs x NBW staging
 };
 
-__host__ __device__ inline size_t boxr_bytes(int m0, int m1, int nrhs, int nbrhs) {
+__host__ __device__ inline size_t boxr_bytes(int m0, int m1, int nrhs, int nbrhs, int kc = 1) {
   const size_t nc = (size_t)m0 * m1;
-  const size_t d = (size_t)(m0 + 2) * (m1 + 2) + 3 * nc + nrhs * nc + nc + nbrhs * nc;
+  const size_t d = kx_doubles(kc, m0, m1) + (size_t)(m0 + 2) * (m1 + 2) + 3 * nc + nrhs * nc + nc + nbrhs * nc;
   const size_t f = nrhs * nc + 2 * nc + (size_t)(nrhs < 2 ? 2 : nrhs) * NBW + 4;
   return d * sizeof(double) + f * sizeof(float);
 }
 
-__device__ __forceinline__ BoxR carve_r(double* base, const Box& B, int nrhs, int nbrhs) {
+__device__ __forceinline__ BoxR carve_r(double* base, const Box& B, int nrhs, int nbrhs, int kc = 1) {
   BoxR r;
   r.b.m0 = B.hi[0] - B.lo[0];
   r.b.m1 = B.hi[1] - B.lo[1];
   const int nc = r.b.m0 * r.b.m1;
+  base = attach_kx(r.b, base, kc);
   r.b.Kt = base;
   r.b.Dg = r.b.Kt + (r.b.m0 + 2) * (r.b.m1 + 2);
   r.b.Tx = r.b.Dg + nc;
@@ -319,8 +320,8 @@ __device__ __forceinline__ double seed_rhs(const Geo& g, const Box& B, const Box
   const bool on = (a == 0) ? (x == (so ? B.hi[0] - 1 : B.lo[0])) : (y == (so ? B.hi[1] - 1 : B.lo[1]));
   if (!on) return 0.0;
   const int ox = x + (a == 0 ? (so ? 1 : -1) : 0), oy = y + (a == 1 ? (so ? 1 : -1) : 0);
-  const double kc = kat(R.b, B, x, y);
-  const double bt = robin_beta(g, a, kc, kat(R.b, B, ox, oy), beta);
+  const double kc = kat(R.b, B, x, y, a);
+  const double bt = robin_beta(g, a, kc, kat(R.b, B, ox, oy, a), beta);
   const int c[3] = {x, y, 0};
   return robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
 }
@@ -404,9 +405,9 @@ __device__ __forceinline__ BoxR carve_smooth_r(double* base, const SmoothLds& r)
   return R;
 }
 
-__host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1) {
+__host__ __device__ inline size_t smooth32_lds_bytes(int m0, int m1, int kc = 1) {
   const size_t nc = (size_t)m0 * m1;
-  return sizeof(double) * (smooth_lds_doubles(m0, m1) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW + 4);
+  return sizeof(double) * (smooth_lds_doubles(m0, m1, kc) + 2 * nc) + sizeof(float) * (3 * nc + 2 * NBW + 4);
 }
 
 }  // namespace wave

@@ -34,6 +34,10 @@ struct BoxLds {
   double* X;    // nrhs x ncell right-hand sides / solutions
   double* Z;    // nrhs x NBW staging of one block
   int m0, m1;
+  // diagonal permeability tensor: the halo tiles of the entries of axes
+  // 1.., ktn doubles apart (ktn = 0: scalar K, every axis reads Kt)
+  double* Kx;
+  int ktn;
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -183,16 +187,32 @@ __device__ __forceinline__ void robin_face(const Geo& g, int a, double kc, doubl
   TR = g.area * 2.0 * kc * rcp_d(g.h + 2.0 * kc * bt);
 }
 
-__host__ __device__ inline size_t box_lds_doubles(int m0, int m1, int nrhs) {
-  const int nc = m0 * m1;
-  return (size_t)(m0 + 2) * (m1 + 2) + 3 * (size_t)nc + (size_t)nrhs * nc + (size_t)nrhs * NBW + 2;
+// LDS of the extra permeability tiles of a diagonal tensor with kc entries
+// per cell (axes 1.., one halo tile each), placed ahead of a box's other
+// arrays; 0 for scalar K.  Even, so that what follows keeps its alignment.
+__host__ __device__ inline size_t kx_doubles(int kc, int m0, int m1) {
+  return kc > 1 ? ((size_t)(kc - 1) * (m0 + 2) * (m1 + 2) + 1) / 2 * 2 : 0;
 }
 
-__device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs) {
+// The extra tiles at base; returns where the box's own arrays start.
+__device__ __forceinline__ double* attach_kx(BoxLds& s, double* base, int kc) {
+  s.Kx = base;
+  s.ktn = kc > 1 ? (s.m0 + 2) * (s.m1 + 2) : 0;
+  return base + kx_doubles(kc, s.m0, s.m1);
+}
+
+__host__ __device__ inline size_t box_lds_doubles(int m0, int m1, int nrhs, int kc = 1) {
+  const int nc = m0 * m1;
+  return kx_doubles(kc, m0, m1) + (size_t)(m0 + 2) * (m1 + 2) + 3 * (size_t)nc + (size_t)nrhs * nc +
+         (size_t)nrhs * NBW + 2;
+}
+
+__device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs, int kc = 1) {
   BoxLds s;
   s.m0 = B.hi[0] - B.lo[0];
   s.m1 = B.hi[1] - B.lo[1];
   const int nc = s.m0 * s.m1;
+  base = attach_kx(s, base, kc);
   s.Kt = base;
   s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2);
   s.Tx = s.Dg + nc;
@@ -202,13 +222,38 @@ __device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs) {
   return s;
 }
 
-// K at global cell (x, y), which must lie in the box or its halo.
-__device__ __forceinline__ double kat(const BoxLds& s, const Box& B, int x, int y) {
-  return s.Kt[(y - B.lo[1] + 1) * (s.m0 + 2) + (x - B.lo[0] + 1)];
+// The halo tile of axis a's permeability entries.
+__device__ __forceinline__ const double* ktile(const BoxLds& s, int a) {
+  return (a > 0 && s.ktn) ? s.Kx + (a - 1) * s.ktn : s.Kt;
+}
+
+// K along axis a at global cell (x, y), which must lie in the box or its
+// halo.
+__device__ __forceinline__ double kat(const BoxLds& s, const Box& B, int x, int y, int a) {
+  return ktile(s, a)[(y - B.lo[1] + 1) * (s.m0 + 2) + (x - B.lo[0] + 1)];
 }
 
 template <int NT = 64>
 __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta, BoxLds& s);
+
+// The tiles of the permeability entries of axes 1.. (diagonal tensor), as
+// the Kt tile (LOG: exponentiated here).
+template <int NT, bool LOG>
+__device__ __forceinline__ void load_kx(const Geo& g, const Box& B, const double* K, const BoxLds& s) {
+  if (!s.ktn) return;
+  const int W2 = s.m0 + 2, nt = s.ktn;
+  gather<1024 / NT, NT>(s.Kx, (g.kc - 1) * nt, [&](int e, double& fill) -> const double* {
+    const int a = 1 + e / nt, u = e - (a - 1) * nt;
+    const int x = B.lo[0] - 1 + u % W2, y = B.lo[1] - 1 + u / W2;
+    fill = LOG ? 0.0 : 1.0;
+    return (x >= 0 && x < g.n[0] && !off_domain(g, 1, B.lo[1], y)) ? K + kaxis(g, a) + x + g.n[0] * y
+                                                                   : nullptr;
+  });
+  if (LOG) {
+    bsync<NT>();
+    for (int e = threadIdx.x % NT; e < (g.kc - 1) * nt; e += NT) s.Kx[e] = exp(s.Kx[e]);
+  }
+}
 
 // Load the K tile and the matrix coefficients of the box into LDS.
 // With LOG, K points to log K and the tile is exponentiated in LDS (cells
@@ -221,6 +266,7 @@ __device__ __forceinline__ void load_box(const Geo& g, const Box& B, const doubl
     fill = LOG ? 0.0 : 1.0;
     return (x >= 0 && x < g.n[0] && !off_domain(g, 1, B.lo[1], y)) ? K + x + g.n[0] * y : nullptr;
   });
+  load_kx<NT, LOG>(g, B, K, s);
   if (LOG) {
     bsync<NT>();
     for (int e = threadIdx.x % NT; e < W2 * H2; e += NT) s.Kt[e] = exp(s.Kt[e]);
@@ -237,10 +283,10 @@ __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta
 #pragma unroll 1
   for (int loc = threadIdx.x % NT; loc < nc; loc += NT) {
     const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + loc / s.m0;
-    const double kc = kat(s, B, x, y);
     double diag = 0.0, tx = 0.0, tn = 0.0;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a) {
+      const double kc = kat(s, B, x, y, a);
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0);
@@ -250,7 +296,7 @@ __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta
           if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area * ih;
           continue;
         }
-        const double ko = kat(s, B, ox, oy);
+        const double ko = kat(s, B, ox, oy, a);
         const bool inside = ox >= B.lo[0] && ox < B.hi[0] && oy >= B.lo[1] && oy < B.hi[1];
         if (inside) {
           const double T = g.area * 2.0 * kc * ko * rcp_d(kc + ko) * ih;
@@ -265,6 +311,7 @@ __device__ __forceinline__ void coef_box(const Geo& g, const Box& B, double beta
           diag += TR;
         }
       }
+    }
     s.Dg[loc] = diag;
     s.Tx[loc] = tx;
     s.Tn[loc] = tn;
@@ -431,7 +478,7 @@ __device__ __forceinline__ void physical_rhs(const Geo& g, const Box& B, const B
         if (!off_domain(g, a, c[a], t)) continue;
         const int side = 2 * a + sd;
         const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-        if (g.bc_type[side]) b += 2.0 * kat(s, B, x, y) * g.area / g.h * val;
+        if (g.bc_type[side]) b += 2.0 * kat(s, B, x, y, a) * g.area / g.h * val;
         else b -= g.area * val;
       }
     out[loc] = b;
@@ -445,7 +492,7 @@ __device__ __forceinline__ double wlambda(const Geo& g, const Box& B, const BoxL
                                           int x, int y, int a, int sd) {
   const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
   const int ci = x + g.n[0] * y, oi = ox + g.n[0] * oy;
-  const double kc = kat(s, B, x, y), ko = kat(s, B, ox, oy);
+  const double kc = kat(s, B, x, y, a), ko = kat(s, B, ox, oy, a);
   const double bt = robin_beta(g, a, kc, ko, beta);
   if (g.l > 0) {
     const double u = g.area * kharm(kc, ko) / g.h * (p[ci] - p[oi]) / g.area;
@@ -477,9 +524,9 @@ struct SmoothLds {
   double* BC;  // 2 (m0 + m1): boundary value per face of each box side
 };
 
-__host__ __device__ inline size_t smooth_lds_doubles(int m0, int m1) {
+__host__ __device__ inline size_t smooth_lds_doubles(int m0, int m1, int kc = 1) {
   const size_t nc = (size_t)m0 * m1, nt = (size_t)(m0 + 2) * (m1 + 2);
-  return 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 4 * NBW + 2;
+  return kx_doubles(kc, m0, m1) + 2 * nt + 5 * nc + 4 * (size_t)(m0 + m1) + 4 * NBW + 2;
 }
 
 __device__ __forceinline__ int side_off(const BoxLds& s, int q) {
@@ -487,13 +534,15 @@ __device__ __forceinline__ int side_off(const BoxLds& s, int q) {
   return q == 0 ? 0 : q == 1 ? s.m1 : q == 2 ? 2 * s.m1 : 2 * s.m1 + s.m0;
 }
 
-// Gather order: [Kt | P | F | Tn | GF | BC] contiguous from `base`.
-__device__ __forceinline__ SmoothLds carve_smooth(double* base, const Box& B) {
+// Gather order: [Kt | P | F | Tn | GF | BC] contiguous (after the extra
+// permeability tiles of a tensor).
+__device__ __forceinline__ SmoothLds carve_smooth(double* base, const Box& B, int kc = 1) {
   SmoothLds r;
   BoxLds& s = r.b;
   s.m0 = B.hi[0] - B.lo[0];
   s.m1 = B.hi[1] - B.lo[1];
   const int nc = s.m0 * s.m1, nt = (s.m0 + 2) * (s.m1 + 2), ns = 2 * (s.m0 + s.m1);
+  base = attach_kx(s, base, kc);
   s.Kt = base;
   r.P = s.Kt + nt;
   r.F = r.P + nt;
@@ -564,6 +613,7 @@ __device__ __forceinline__ void stage_smooth(const Geo& g, const Box& B, const S
     const int tj = a == 0 ? y - jsub * g.S[1] : x - isub * g.S[0];
     return gflux + (long long)j * g.gstride + go + tj;
   });
+  load_kx<NT, false>(g, B, K, s);
 }
 
 // K and p at a cell of the box or its halo.
@@ -579,7 +629,7 @@ __device__ __forceinline__ double lambda_s(const Geo& g, const Box& B, const Smo
   const BoxLds& s = r.b;
   const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
   const int ti = tile_at(s, B, x, y), to = tile_at(s, B, ox, oy);
-  const double kc = s.Kt[ti], ko = s.Kt[to];
+  const double kc = ktile(s, a)[ti], ko = ktile(s, a)[to];
   if (g.l > 0) {
     // u = K_H (p_c - p_o) / h, pi = p_c - u h / (2 K_c)
     const double u = 2.0 * kc * ko * rcp_d(kc + ko) * (r.P[ti] - r.P[to]) * rcp_d(g.h);
@@ -611,12 +661,13 @@ __device__ __forceinline__ void smooth_rhs(const Geo& g, const Box& B, const Smo
     const int y = a == 1 ? (sd ? B.hi[1] - 1 : B.lo[1]) : B.lo[1] + t;
     const int c[3] = {x, y, 0};
     const int kind = face_kind(g, B, c, a, sd);
-    const double kc = s.Kt[tile_at(s, B, x, y)];
+    const double* Ka = ktile(s, a);
+    const double kc = Ka[tile_at(s, B, x, y)];
     double add;
     if (kind == kFaceRobin) {
       const int ox = x + (a == 0 ? (sd ? 1 : -1) : 0), oy = y + (a == 1 ? (sd ? 1 : -1) : 0);
       double bt, TR;
-      robin_face(g, a, kc, s.Kt[tile_at(s, B, ox, oy)], beta, bt, TR);
+      robin_face(g, a, kc, Ka[tile_at(s, B, ox, oy)], beta, bt, TR);
       add = TR * lambda_s(g, B, r, bt, x, y, a, sd);
     } else {
       const double val = r.BC[side_off(s, 2 * a + sd) + t];
@@ -662,7 +713,7 @@ __device__ __forceinline__ void smooth_out(const Geo& g, const Box& B, const Smo
     int cx, cy;
     wgface(olo, ohi, q, t, cx, cy);
     const int ox = cx + (a == 0 ? (so ? 1 : -1) : 0), oy = cy + (a == 1 ? (so ? 1 : -1) : 0);
-    const double kc = s.Kt[tile_at(s, B, cx, cy)], ko = s.Kt[tile_at(s, B, ox, oy)];
+    const double kc = ktile(s, a)[tile_at(s, B, cx, cy)], ko = ktile(s, a)[tile_at(s, B, ox, oy)];
     const double xc = x[bloc(B, s, cx, cy)];
     double v;
     if (win_box(B, ox, oy)) {
