@@ -225,32 +225,26 @@ __global__ void __launch_bounds__(256) k_lsc_outer_rows(double* __restrict__ bas
 
 // X[col] = y[col] - sum_j Y^L[col][j] s[j] - sum_j Y^U[col][j] t[j] for
 // every interface unknown (one wave each): its inner solution row against
-// the reduced solution of the gaps on both sides of its layer.
+// the reduced solution of the gaps on both sides of its layer (the j-th
+// coupling's column of the row at icol[C.cm + j], the right-hand side at
+// column rc).
 __global__ void __launch_bounds__(256) k_lsc_back(const double* __restrict__ base,
                                                   const LscCol* __restrict__ cols,
-                                                  const int* __restrict__ cmap, int n, int ncol,
+                                                  const int* __restrict__ icol, int n, int rc,
                                                   double* __restrict__ X) {
   const int wg = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int L = threadIdx.x & 63;
   if (wg >= n) return;
   const LscCol C = cols[wg];
   const double* y = base + C.xrow;
-  double acc = 0.0, rhs = 0.0;
-  for (int c = L; c < ncol; c += 64) {
-    const int code = cmap[C.cm + c];
-    if (code == -2) {
-      rhs = y[c];
-    } else if (code >= 0) {
-      const long long o = code < C.ml ? (C.sofs >= 0 ? C.sofs + code : -1)
-                                      : (C.tofs >= 0 ? C.tofs + (code - C.ml) : -1);
-      if (o >= 0) acc = fma(y[c], base[o], acc);
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    acc += __shfl_xor(acc, off);
-    rhs += __shfl_xor(rhs, off);  // one lane holds it: exact
-  }
-  if (L == 0) X[wg] = rhs - acc;
+  const int* ic = icol + C.cm;
+  double acc = 0.0;
+  if (C.sofs >= 0)
+    for (int j = L; j < C.ml; j += 64) acc = fma(y[ic[j]], base[C.sofs + j], acc);
+  if (C.tofs >= 0)
+    for (int j = L; j < C.mu; j += 64) acc = fma(y[ic[C.ml + j]], base[C.tofs + j], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (L == 0) X[wg] = y[rc] - acc;
 }
 
 }  // namespace
@@ -352,10 +346,10 @@ hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long lo
   return hipGetLastError();
 }
 
-hipError_t launch_lsc_back(const double* base, const LscCol* cols, const int* cmap, int n, int ncol,
+hipError_t launch_lsc_back(const double* base, const LscCol* cols, const int* icol, int n, int rc,
                            double* X, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lsc_back, dim3((n + 3) / 4), dim3(256), 0, s, base, cols, cmap, n, ncol, X);
+  hipLaunchKernelGGL(k_lsc_back, dim3((n + 3) / 4), dim3(256), 0, s, base, cols, icol, n, rc, X);
   return hipGetLastError();
 }
 

@@ -208,6 +208,8 @@ struct Lsc {
   LscCol* d_cols = nullptr;
   int ncols = 0;
   int* d_cmap = nullptr;  // per outer layer: code of every inner-solution column
+  int* d_icol = nullptr;  // per outer layer: column of its j-th coupling (lower, then upper)
+  int rc = 0;             // column of the right-hand side
   // launches: inner phase, outer phase
   std::vector<LscLaunch> inner, outer;
 };
@@ -363,7 +365,7 @@ void lsc_destroy(Lsc* L) {
     p = nullptr;
   };
   f(L->buf); f(L->d_dst); f(L->d_rdst); f(L->d_ones); f(L->d_offs); f(L->d_npiv);
-  f(L->d_rect); f(L->d_gemv); f(L->d_rows); f(L->d_ypos); f(L->d_cols); f(L->d_cmap);
+  f(L->d_rect); f(L->d_gemv); f(L->d_rows); f(L->d_ypos); f(L->d_cols); f(L->d_cmap); f(L->d_icol);
   delete L;
 }
 
@@ -514,6 +516,13 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
       zc1[(size_t)k * L.Mi + z] = next;
     }
     cmap[(size_t)k * L.ncol + RC] = -2;
+  }
+  L.rc = RC;
+  std::vector<int> icol((size_t)L.S * L.ncol, 0);
+  for (int k = 0; k < L.S; ++k) {
+    for (size_t jq = 0; jq < colL[k].size(); ++jq) icol[(size_t)k * L.ncol + jq] = colL[k][jq];
+    for (size_t jq = 0; jq < colU[k].size(); ++jq)
+      icol[(size_t)k * L.ncol + colL[k].size() + jq] = colU[k][jq];
   }
   L.bo = (int)up32(std::max(mgap, 32));
   const long long bsi = (long long)L.bpi * L.bpi, bso = (long long)L.bo * L.bo;
@@ -759,6 +768,7 @@ Lsc* lsc_create(const Geo& g, const std::vector<Iface>& ifc, const std::vector<i
   if (e == hipSuccess) e = upload(L.d_ypos, ypos);
   if (e == hipSuccess) e = upload(L.d_cols, cols);
   if (e == hipSuccess) e = upload(L.d_cmap, cmap);
+  if (e == hipSuccess) e = upload(L.d_icol, icol);
   if (e != hipSuccess) {
     *herr = e;
     if (err) *err = hipGetErrorString(e);
@@ -821,7 +831,7 @@ hipError_t lsc_solve(Lsc* L, double* X, int* flags, hipStream_t s) {
   if (e == hipSuccess)
     e = launch_lsc_outer_rows(L->buf, L->d_rows, L->d_ypos, L->d_cmap, L->nrows, L->ncol, L->wc, s);
   if (e == hipSuccess) e = run(L, L->outer, flags, s);
-  if (e == hipSuccess) e = launch_lsc_back(L->buf, L->d_cols, L->d_cmap, L->ncols, L->ncol, X, s);
+  if (e == hipSuccess) e = launch_lsc_back(L->buf, L->d_cols, L->d_icol, L->ncols, L->rc, X, s);
   return e;
 }
 

@@ -86,9 +86,11 @@ struct Box3 {
   double* Z;   // nrhs x 64 staging of one block
   int m0, m1, m2, nc;
   // diagonal permeability tensor: halo tiles of the entries of axes 1..,
-  // ktn doubles apart (ktn = 0: scalar K, every axis reads Kt)
+  // ktn doubles apart (ktn = 0: scalar K), and the tile each axis reads
+  // (Kt for every axis with scalar K)
   double* Kx;
   int ktn;
+  const double* Ka[2];  // axes 1 and 2
 };
 
 // LDS of those extra tiles (ahead of the box's other arrays; even).
@@ -102,7 +104,11 @@ __host__ __device__ inline size_t box3_doubles(int m0, int m1, int m2, int nrhs,
          (size_t)nrhs * nc + (size_t)nrhs * P3 + 4;
 }
 
+// TS: the tensor form; without it the tiles of axes 1.. are Kt at
+// compile time, and the scalar kernels carry nothing of the tensor.
+template <bool TS>
 __device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs, int kc) {
+  if (!TS) kc = 1;
   Box3 s;
   s.m0 = B.hi[0] - B.lo[0];
   s.m1 = B.hi[1] - B.lo[1];
@@ -112,6 +118,8 @@ __device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs, int
   s.ktn = kc > 1 ? (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2) : 0;
   base += kx3_doubles(kc, s.m0, s.m1, s.m2);
   s.Kt = base;
+  s.Ka[0] = s.ktn ? s.Kx : s.Kt;
+  s.Ka[1] = s.ktn ? s.Kx + s.ktn : s.Kt;
   s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2);
   s.Tz = s.Dg + s.nc;
   s.X = s.Tz + s.nc;
@@ -124,7 +132,7 @@ __device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs, int
 
 // K along axis a at global cell (x, y, z) of the box or its halo.
 __device__ __forceinline__ double k3(const Box3& s, const Box& B, int x, int y, int z, int a) {
-  const double* t = (a > 0 && s.ktn) ? s.Kx + (a - 1) * s.ktn : s.Kt;
+  const double* t = a == 0 ? s.Kt : a == 1 ? s.Ka[0] : s.Ka[1];
   return t[((z - B.lo[2] + 1) * (s.m1 + 2) + (y - B.lo[1] + 1)) * (s.m0 + 2) + (x - B.lo[0] + 1)];
 }
 
@@ -543,7 +551,7 @@ __device__ __forceinline__ bool inbox3(const Box& B, const int c[3]) {
 }
 
 // Steps 1-2 on an oversampled box (FO: Step 6, the factor alone).
-template <int NW, bool FO>
+template <int NW, bool FO, bool TS>
 __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
                                        const double* __restrict__ logK, double beta,
                                        double* __restrict__ fac, double* __restrict__ Pk,
@@ -552,7 +560,7 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
   const int nrhs = FO ? 0 : B.nrhs;
-  Box3 s = carve3(dsm, B, nrhs, g.kc);
+  Box3 s = carve3<TS>(dsm, B, nrhs, g.kc);
   load_box3<NW, true>(g, B, logK, beta, s);
   for (int e = tid; e < nrhs * s.nc; e += NT) s.X[e] = 0.0;
   bsync<NW>();
@@ -647,7 +655,7 @@ __device__ __forceinline__ void physical3(const Geo& g, const Box& B, const Box3
 
 // Step 4 on a subdomain: K = exp(log K) of its cells (the subdomains cover
 // the grid once; a K that is not finite and positive is flagged).
-template <int NW>
+template <int NW, bool TS>
 __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
                                             const double* __restrict__ logK, double* __restrict__ K,
                                             const double* __restrict__ f,
@@ -657,11 +665,11 @@ __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
                                             double* dsm, Gj3& sm) {
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
-  Box3 s = carve3(dsm, B, 1, g.kc);
+  Box3 s = carve3<TS>(dsm, B, 1, g.kc);
   load_box3<NW, true>(g, B, logK, beta, s);
   for (int loc = tid; loc < s.nc; loc += NT) {
     const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
-    for (int a = 0; a < g.kc; ++a) {
+    for (int a = 0; a < (TS ? g.kc : 1); ++a) {
       const double k = k3(s, B, c[0], c[1], c[2], a);
       if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
       K[kaxis(g, a) + gcell(g, c)] = k;
@@ -729,7 +737,7 @@ __device__ __forceinline__ double lambda3(const Geo& g, const Box& B, const Box3
 
 // Steps 6-7 for one box: right-hand side from the state, solve with the
 // cached inverses, p on Omega_i and Omega_i's Gamma fluxes.
-template <int NW>
+template <int NW, bool TS>
 __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double* __restrict__ K,
                                         const double* __restrict__ f,
                                         const double* __restrict__ bcv, double beta,
@@ -737,7 +745,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
                                         double* dsm, Gj3& sm) {
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
-  Box3 s = carve3(dsm, B, 1, g.kc);
+  Box3 s = carve3<TS>(dsm, B, 1, g.kc);
   load_box3<NW, false>(g, B, K, beta, s);
   physical3<NW>(g, B, s, f, bcv, s.X);
   bsync<NW>();
@@ -802,7 +810,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
 
 // Register budget for three resident boxes per CU (their LDS allows no
 // more): at most 168 registers per lane.
-template <int NW>
+template <int NW, bool TS>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_basis3(Geo g, const Box* __restrict__ boxes,
                                                     const Seed* __restrict__ seeds,
                                                     const double* __restrict__ logK, double beta,
@@ -817,14 +825,14 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
   bsync<NW>();
   const Box B = boxes[blockIdx.x];
   if (factor_only)
-    basis3<NW, true>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+    basis3<NW, true, TS>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
   else
-    basis3<NW, false>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
+    basis3<NW, false, TS>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, dsm, sm);
   bsync<NW>();
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-template <int NW>
+template <int NW, bool TS>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_particular3(Geo g, const Box* __restrict__ boxes,
                                                          const double* __restrict__ logK,
                                                          double* __restrict__ K,
@@ -839,12 +847,12 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
   if (threadIdx.x == 0) sm.flag = 0;
   bsync<NW>();
   const Box B = boxes[blockIdx.x];
-  particular3<NW>(g, B, logK, K, f, bcv, beta, fac, pbar, ubar, pibar, dsm, sm);
+  particular3<NW, TS>(g, B, logK, K, f, bcv, beta, fac, pbar, ubar, pibar, dsm, sm);
   bsync<NW>();
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-template <int NW>
+template <int NW, bool TS>
 __global__ void __launch_bounds__(64 * NW) k_smooth3(Geo g, const Box* __restrict__ boxes,
                                                      const double* __restrict__ K,
                                                      const double* __restrict__ f,
@@ -854,7 +862,7 @@ __global__ void __launch_bounds__(64 * NW) k_smooth3(Geo g, const Box* __restric
   extern __shared__ __align__(16) double dsm[];
   __shared__ Gj3 sm;
   const Box B = boxes[blockIdx.x];
-  smooth3<NW>(g, B, K, f, bcv, beta, fac, p, gflux, dsm, sm);
+  smooth3<NW, TS>(g, B, K, f, bcv, beta, fac, p, gflux, dsm, sm);
 }
 
 template <typename KF>
@@ -872,12 +880,22 @@ size_t box3_lds_bytes(int m0, int m1, int m2, int nrhs, int kc) {
 
 int box3_waves(int nb) { return nb <= R3 ? 1 : nb <= 2 * R3 ? 2 : 4; }
 
-#define MRCM_NW_SWITCH(nw, CALL)      \
-  switch (nw) {                       \
-    case 1: CALL(1); break;           \
-    case 2: CALL(2); break;           \
-    case 4: CALL(4); break;           \
-    default: return hipErrorInvalidValue; \
+// waves per box, and the scalar or the tensor form of K
+#define MRCM_NW_SWITCH(nw, CALL)                   \
+  if (g.kc > 1) {                                  \
+    switch (nw) {                                  \
+      case 1: CALL(1, true); break;                \
+      case 2: CALL(2, true); break;                \
+      case 4: CALL(4, true); break;                \
+      default: return hipErrorInvalidValue;        \
+    }                                              \
+  } else {                                         \
+    switch (nw) {                                  \
+      case 1: CALL(1, false); break;               \
+      case 2: CALL(2, false); break;               \
+      case 4: CALL(4, false); break;               \
+      default: return hipErrorInvalidValue;        \
+    }                                              \
   }
 
 hipError_t launch_basis3(const Geo& g, const Box* boxes, int nbox, const Seed* seeds,
@@ -886,10 +904,10 @@ hipError_t launch_basis3(const Geo& g, const Box* boxes, int nbox, const Seed* s
                          int nw, hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
-#define MRCM_CALL(NW)                                                                                 \
-  e = lds_attr3(k_basis3<NW>, lds);                                                                   \
+#define MRCM_CALL(NW, TS)                                                                             \
+  e = lds_attr3(k_basis3<NW, TS>, lds);                                                               \
   if (e != hipSuccess) return e;                                                                      \
-  hipLaunchKernelGGL(k_basis3<NW>, dim3(nbox), dim3(64 * NW), lds, s, g, boxes, seeds, logK, beta, fac, \
+  hipLaunchKernelGGL((k_basis3<NW, TS>), dim3(nbox), dim3(64 * NW), lds, s, g, boxes, seeds, logK, beta, fac, \
                      Pk, tr_u, tr_phi, tr_beta, factor_only, flags)
   MRCM_NW_SWITCH(nw, MRCM_CALL)
 #undef MRCM_CALL
@@ -902,10 +920,10 @@ hipError_t launch_particular3(const Geo& g, const Box* boxes, int nbox, const do
                               hipStream_t s) {
   if (nbox <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
-#define MRCM_CALL(NW)                                                                                \
-  e = lds_attr3(k_particular3<NW>, lds);                                                             \
+#define MRCM_CALL(NW, TS)                                                                            \
+  e = lds_attr3(k_particular3<NW, TS>, lds);                                                         \
   if (e != hipSuccess) return e;                                                                     \
-  hipLaunchKernelGGL(k_particular3<NW>, dim3(nbox), dim3(64 * NW), lds, s, g, boxes, logK, K, f, bcv, \
+  hipLaunchKernelGGL((k_particular3<NW, TS>), dim3(nbox), dim3(64 * NW), lds, s, g, boxes, logK, K, f, bcv, \
                      beta, fac, pbar, ubar, pibar, flags)
   MRCM_NW_SWITCH(nw, MRCM_CALL)
 #undef MRCM_CALL
@@ -917,10 +935,10 @@ hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double
                           size_t lds, int nw, hipStream_t s) {
   if (nmem <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
-#define MRCM_CALL(NW)                                                                                   \
-  e = lds_attr3(k_smooth3<NW>, lds);                                                                    \
+#define MRCM_CALL(NW, TS)                                                                               \
+  e = lds_attr3(k_smooth3<NW, TS>, lds);                                                                \
   if (e != hipSuccess) return e;                                                                        \
-  hipLaunchKernelGGL(k_smooth3<NW>, dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv, beta, fac, p, \
+  hipLaunchKernelGGL((k_smooth3<NW, TS>), dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv, beta, fac, p, \
                      gflux)
   MRCM_NW_SWITCH(nw, MRCM_CALL)
 #undef MRCM_CALL

@@ -315,14 +315,15 @@ struct LscRow {
 hipError_t launch_lsc_outer_rows(double* base, const LscRow* rows, const long long* ypos,
                                  const int* cmap, int nrow, int ncol, int width, hipStream_t s);
 // Back substitution of one interface unknown: its inner solution row at
-// base[xrow] (columns mapped by cmap[cm + c] as above: the right-hand side,
-// the ml couplings of s, the mu of t) against the reduced solution (s at
-// base[sofs], t at base[tofs]; < 0: none).
+// base[xrow] (the column of its layer's j-th coupling at icol[cm + j]: the
+// ml couplings of s, then the mu of t; the right-hand side at column rc)
+// against the reduced solution (s at base[sofs], t at base[tofs]; < 0:
+// none).
 struct LscCol {
   long long xrow, sofs, tofs;
   int ml, mu, cm, pad;
 };
-hipError_t launch_lsc_back(const double* base, const LscCol* cols, const int* cmap, int n, int ncol,
+hipError_t launch_lsc_back(const double* base, const LscCol* cols, const int* icol, int n, int rc,
                            double* X, hipStream_t s);
 
 // The two-level solver's plan and device state (iface_lsc.cpp).  seeds_per_side:

@@ -40,6 +40,7 @@ __device__ __forceinline__ BoxR carve_r(double* base, const Box& B, int nrhs, in
   const int nc = r.b.m0 * r.b.m1;
   base = attach_kx(r.b, base, kc);
   r.b.Kt = base;
+  attach_ky(r.b);
   r.b.Dg = r.b.Kt + (r.b.m0 + 2) * (r.b.m1 + 2);
   r.b.Tx = r.b.Dg + nc;
   r.b.Tn = r.b.Tx + nc;

@@ -35,9 +35,11 @@ struct BoxLds {
   double* Z;    // nrhs x NBW staging of one block
   int m0, m1;
   // diagonal permeability tensor: the halo tiles of the entries of axes
-  // 1.., ktn doubles apart (ktn = 0: scalar K, every axis reads Kt)
+  // 1.., ktn doubles apart (ktn = 0: scalar K), and the tile axis 1 reads
+  // (Kt with scalar K)
   double* Kx;
   int ktn;
+  const double* Ky;
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -201,6 +203,9 @@ __device__ __forceinline__ double* attach_kx(BoxLds& s, double* base, int kc) {
   return base + kx_doubles(kc, s.m0, s.m1);
 }
 
+// After Kt is set: the tile axis 1 reads.
+__device__ __forceinline__ void attach_ky(BoxLds& s) { s.Ky = s.ktn ? s.Kx : s.Kt; }
+
 __host__ __device__ inline size_t box_lds_doubles(int m0, int m1, int nrhs, int kc = 1) {
   const int nc = m0 * m1;
   return kx_doubles(kc, m0, m1) + (size_t)(m0 + 2) * (m1 + 2) + 3 * (size_t)nc + (size_t)nrhs * nc +
@@ -214,6 +219,7 @@ __device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs, in
   const int nc = s.m0 * s.m1;
   base = attach_kx(s, base, kc);
   s.Kt = base;
+  attach_ky(s);
   s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2);
   s.Tx = s.Dg + nc;
   s.Tn = s.Tx + nc;
@@ -223,9 +229,7 @@ __device__ __forceinline__ BoxLds carve(double* base, const Box& B, int nrhs, in
 }
 
 // The halo tile of axis a's permeability entries.
-__device__ __forceinline__ const double* ktile(const BoxLds& s, int a) {
-  return (a > 0 && s.ktn) ? s.Kx + (a - 1) * s.ktn : s.Kt;
-}
+__device__ __forceinline__ const double* ktile(const BoxLds& s, int a) { return a == 0 ? s.Kt : s.Ky; }
 
 // K along axis a at global cell (x, y), which must lie in the box or its
 // halo.
@@ -544,6 +548,7 @@ __device__ __forceinline__ SmoothLds carve_smooth(double* base, const Box& B, in
   const int nc = s.m0 * s.m1, nt = (s.m0 + 2) * (s.m1 + 2), ns = 2 * (s.m0 + s.m1);
   base = attach_kx(s, base, kc);
   s.Kt = base;
+  attach_ky(s);
   r.P = s.Kt + nt;
   r.F = r.P + nt;
   s.Tn = r.F + nc;
