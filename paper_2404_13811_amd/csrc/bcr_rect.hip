@@ -266,12 +266,14 @@ hipError_t launch_rect_gemm(double* base, const BcrGemm* tasks, int ntask, const
   if (ntask <= 0) return hipSuccess;
   if (S.m % 32 || S.n % 32 || S.k % 32 || S.m <= 0 || S.n <= 0 || S.k <= 0) return hipErrorInvalidValue;
   // 64 x 64 tiles where they divide the product and still give every CU two
-  // workgroups (half the operand traffic per multiply-add of 32 x 32 tiles);
-  // 32 x 32 tiles otherwise.  Measured on the 3-D workload's reduced
-  // system: 128 x 128 tiles (one workgroup per CU) and 96 x 96 tiles for the
-  // inner products were no faster.
+  // workgroups (half the operand traffic per multiply-add of 32 x 32 tiles),
+  // with k in chunks of 16 (17 KB of LDS: more resident workgroups per CU
+  // hide more of the operand loads than longer chunks do); 32 x 32 tiles
+  // otherwise.  Measured on the 3-D workload's reduced system: 128 x 128,
+  // 128 x 64 and 64 x 128 tiles, chunks of 32 and 8, and 96 x 96 tiles for
+  // the inner products were no faster.
   if (S.m % 64 == 0 && S.n % 64 == 0 && (long long)ntask * (S.m / 64) * (S.n / 64) >= 512)
-    return rect_launch<64, 64, 32>(base, tasks, ntask, S, s);
+    return rect_launch<64, 64, 16>(base, tasks, ntask, S, s);
   if (S.k % 64 == 0) return rect_launch<32, 32, 64>(base, tasks, ntask, S, s);
   return rect_launch<32, 32, 32>(base, tasks, ntask, S, s);
 }
@@ -317,7 +319,7 @@ hipError_t launch_rect_gemm2(double* base, const BcrGemm* ta, int na, const Rect
   if (SA.k != SB.k) return hipErrorInvalidValue;
   const long long t64 = (long long)na * (SA.m / 64) * (SA.n / 64) + (long long)nb * (SB.m / 64) * (SB.n / 64);
   if (SA.m % 64 == 0 && SA.n % 64 == 0 && SB.m % 64 == 0 && SB.n % 64 == 0 && t64 >= 512)
-    return rect_launch2<64, 64, 32>(base, ta, na, SA, tb, nb, SB, s);
+    return rect_launch2<64, 64, 16>(base, ta, na, SA, tb, nb, SB, s);
   if (SA.k % 64 == 0) return rect_launch2<32, 32, 64>(base, ta, na, SA, tb, nb, SB, s);
   return rect_launch2<32, 32, 32>(base, ta, na, SA, tb, nb, SB, s);
 }
