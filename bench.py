@@ -52,8 +52,8 @@ GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_full_samples.npz")
 # value it was taken with; otherwise the traffic is reported as null.
 TRAFFIC = {
     # (kernel, workload key): (source files, sha256 prefix, fetch KiB, write KiB)
-    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip",), "7317bad19c0be02c", 1887676.3, 4380710.0),
-    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip",), "7317bad19c0be02c", 518678.0, 2727.0),
+    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip",), "b759a61a37d702da", 1887586.8, 4380710.0),
+    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip",), "b759a61a37d702da", 518742.5, 2727.0),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COMMON_SOURCES = ("wave_common.h", "local_common.h", "mrcm_internal.h", "pivot4.h")
