@@ -87,6 +87,8 @@ struct mrcm_ctx {
   bool wave = false;                      // 2-D boxes with blocks of <= 32 cells
   bool d3 = false;                        // 3-D boxes with plane blocks of <= 64 cells
   size_t lds3_basis = 0, lds3_part = 0, lds3_smooth = 0;
+  // the same in the FP32 form (local3f.hip)
+  size_t lds3f_basis = 0, lds3f_part = 0, lds3f_smooth = 0;
   int nw3_box = 4, nw3_part = 4;  // wavefronts per 3-D box (oversampled, subdomain)
   size_t lds_basis = 0, lds_part = 0, lds_smooth = 0;
   size_t lds32_basis = 0, lds32_part = 0, lds32_smooth = 0;
@@ -692,6 +694,7 @@ mrcm_status make_plan(mrcm_ctx* c) {
   // 3-D boxes: one wave per box with plane blocks of at most 64 cells
   c->d3 = c->d == 3;
   c->lds3_basis = c->lds3_part = c->lds3_smooth = 0;
+  c->lds3f_basis = c->lds3f_part = c->lds3f_smooth = 0;
   int nb3_box = 1, nb3_part = 1;
   for (int i = 0; i < nsub && c->d3; ++i) {
     const Box& B = c->obox[i];
@@ -705,6 +708,10 @@ mrcm_status make_plan(mrcm_ctx* c) {
     c->lds3_smooth = std::max(c->lds3_smooth, box3_lds_bytes(m[0], m[1], m[2], 1, kc));
     c->lds3_part = std::max(c->lds3_part, box3_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1],
                                                          P.hi[2] - P.lo[2], 1, kc));
+    c->lds3f_basis = std::max(c->lds3f_basis, box3f_lds_bytes(m[0], m[1], m[2], std::max(B.nrhs, 1), 0, kc));
+    c->lds3f_smooth = std::max(c->lds3f_smooth, box3f_lds_bytes(m[0], m[1], m[2], 1, 1, kc));
+    c->lds3f_part = std::max(c->lds3f_part, box3f_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1],
+                                                            P.hi[2] - P.lo[2], 1, 1, kc));
   }
   if (c->lds3_basis > 150 * 1024 || c->lds3_smooth > 150 * 1024 || c->lds3_part > 150 * 1024)
     c->d3 = false;
@@ -1177,21 +1184,39 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
     if (st) return st;
   }
   const bool r32 = c->prec == MRCM_FP32_REFINE;
-  if (r32 && (!c->wave || c->lds32_basis > 150 * 1024 || c->lds32_smooth > 150 * 1024 ||
-              c->lds32_part > 150 * 1024))
-    return fail(c, MRCM_EINVAL, "FP32 refinement is available for 2-D boxes with lines of <= 32 cells");
+  if (r32 && c->d3 &&
+      (c->lds3f_basis > 150 * 1024 || c->lds3f_smooth > 150 * 1024 || c->lds3f_part > 150 * 1024))
+    return fail(c, MRCM_EINVAL, "FP32 refinement: a 3-D box does not fit the LDS of a workgroup");
+  if (r32 && !c->d3 && (!c->wave || c->lds32_basis > 150 * 1024 || c->lds32_smooth > 150 * 1024 ||
+                        c->lds32_part > 150 * 1024))
+    return fail(c, MRCM_EINVAL,
+                "FP32 refinement is available for 2-D boxes with lines of <= 32 cells and 3-D boxes with "
+                "planes of <= 64 cells");
   hipStream_t s = c->stream;
   if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
   // a new solve clears the flags of the last one, unless they wait for
   // mrcm_wait (deferred errors)
   if (!c->flags_zero && !c->deferred) HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int), s));
   c->flags_zero = false;
-  // K = exp(log K): inside the local kernels on the FP64 wave and 3-D paths
-  if (r32 || !(c->wave || c->d3))
+  // K = exp(log K): inside the local kernels on the FP64 wave path and on
+  // both 3-D paths
+  if ((r32 && !c->d3) || !(c->wave || c->d3))
     HIPCHK(c, launch_exp(c->logk, c->K, c->kcomp * c->geo.ncells, c->flags, s));
   if (r32) {
     HIPCHK(c, hipMemsetAsync(c->d_iters, 0, sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->d_resid, 0, sizeof(unsigned long long), s));
+  }
+  if (r32 && c->d3) {
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
+    HIPCHK(c, launch_basis3f(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->logk, c->beta_mbf, c->fac32,
+                             c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 0, c->tol, c->max_refine, c->d_iters,
+                             c->d_resid, c->flags, c->lds3f_basis, c->nw3_box, s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
+    HIPCHK(c, launch_particular3f(c->geo, c->d_pbox, c->geo.nsub, c->logk, c->K, c->f, c->bcv,
+                                  c->beta_mbf, c->facp32, c->pbar, c->ubar, c->pibar, c->tol,
+                                  c->max_refine, c->d_iters, c->d_resid, c->flags, c->lds3f_part,
+                                  c->nw3_part, s));
+  } else if (r32) {
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
     HIPCHK(c, launch_local32_w(c->geo, c->d_obox, c->d_pbox, c->geo.nsub, c->d_seeds, c->K, c->f,
                                c->bcv, c->beta_mbf, c->fac32, c->facp32, c->Pk, c->tr_u, c->tr_phi,
@@ -1229,7 +1254,12 @@ mrcm_status mrcm_build_basis(mrcm_ctx* c) {
       if (ptr) return hipSuccess;
       return hipMalloc((void**)&ptr, std::max<long long>(count, 1) * sizeof(*ptr));
     };
-    if (r32) {
+    if (r32 && c->d3) {
+      HIPCHK(c, grow(c->fac32s, c->fac_n));
+      HIPCHK(c, launch_basis3f(c->geo, c->d_obox, c->geo.nsub, c->d_seeds, c->logk, c->beta_sm, c->fac32s,
+                               c->Pk, c->tr_u, c->tr_phi, c->tr_beta, 1, c->tol, c->max_refine,
+                               c->d_iters, c->d_resid, c->flags, c->lds3f_basis, c->nw3_box, s));
+    } else if (r32) {
       HIPCHK(c, grow(c->fac32s, c->fac_n));
       HIPCHK(c, launch_factor32_w(c->geo, c->d_obox, c->geo.nsub, c->K, c->beta_sm, c->fac32s,
                                   c->d_iters, c->d_resid, c->flags, c->lds32_basis, s));
@@ -1354,7 +1384,11 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
       ++c->n_ck;
     }
     const bool own = c->beta_sm != c->beta_mbf;  // Step 6 factors
-    if (c->prec == MRCM_FP32_REFINE) {
+    if (c->prec == MRCM_FP32_REFINE && c->d3) {
+      HIPCHK(c, launch_smooth3f(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv, c->beta_sm,
+                                own ? c->fac32s : c->fac32, p, gflux, c->tol, c->max_refine, c->d_iters,
+                                c->d_resid, c->flags, c->lds3f_smooth, c->nw3_box, s));
+    } else if (c->prec == MRCM_FP32_REFINE) {
       HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
                                   c->beta_sm, own ? c->fac32s : c->fac32, p, gflux, c->tol,
                                   c->max_refine, c->d_iters, c->d_resid, c->flags,
@@ -1381,7 +1415,7 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
 // state (the variants give identical results).
 mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
   if (c->smooth_nt) return MRCM_OK;
-  if (c->smooth_nt_req || !(c->wave || c->prec == MRCM_FP32_REFINE)) {
+  if (c->smooth_nt_req || !c->wave) {
     c->smooth_nt = c->smooth_nt_req ? c->smooth_nt_req : 256;
     return MRCM_OK;
   }

@@ -24,41 +24,11 @@
 //   backward  x_j = z_j + W_j (t_j .* x_{j+1}).
 // The inverses are stored whole (nb x nb, row-major), the layout the
 // smoothing kernel reads back.
-#include "local_common.h"
+#include "local3_common.h"
 #include "pivot4.h"
 
 namespace mrcm {
 namespace {
-
-constexpr int P3 = 64;   // lanes: columns of the padded plane block
-constexpr int R3 = 16;   // rows of the block per lane
-constexpr int G3 = 4;    // pivots per Gauss-Jordan step
-
-__device__ __forceinline__ int lane3() { return threadIdx.x & 63; }
-
-// The lane index recomputed where it is used: the unrolled elimination
-// steps would otherwise each get lane-dependent constants (pivot-column
-// masks, unit right-hand sides) computed up front and kept in scratch
-// memory for the whole elimination.
-__device__ __forceinline__ int lane3_here() {
-  int v;
-  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
-  return v;
-}
-// wave index as a scalar, so that branches on it are uniform
-__device__ __forceinline__ int wave3() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// LDS ordering between the lanes of the box: within one wave a wait for the
-// LDS counter is enough; several waves meet at the workgroup barrier.
-template <int NW>
-__device__ __forceinline__ void bsync() {
-  if constexpr (NW == 1) {
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    __builtin_amdgcn_wave_barrier();
-  } else {
-    __syncthreads();
-  }
-}
 
 // Pivot data of one elimination step (two alternating buffers) and the
 // flag.  vb holds the step's multipliers v_c = P^-1 A[k..k+3][c] of every
@@ -76,149 +46,6 @@ struct __align__(16) Gj3 {
 };
 
 __device__ __forceinline__ double* partials3(Gj3& sm) { return &sm.vb[0][0]; }
-
-// LDS of one box.
-struct Box3 {
-  double* Kt;  // (m0 + 2)(m1 + 2)(m2 + 2) permeabilities, one-cell halo
-  double* Dg;  // ncell diagonal
-  double* Tz;  // ncell coupling to the next plane (0 on the last plane)
-  double* X;   // nrhs x ncell right-hand sides / solutions
-  double* Z;   // nrhs x 64 staging of one block
-  int m0, m1, m2, nc;
-  // diagonal permeability tensor: halo tiles of the entries of axes 1..,
-  // ktn doubles apart (ktn = 0: scalar K), and the tile each axis reads
-  // (Kt for every axis with scalar K)
-  double* Kx;
-  int ktn;
-  const double* Ka[2];  // axes 1 and 2
-};
-
-// LDS of those extra tiles (ahead of the box's other arrays; even).
-__host__ __device__ inline size_t kx3_doubles(int kc, int m0, int m1, int m2) {
-  return kc > 1 ? ((size_t)(kc - 1) * (m0 + 2) * (m1 + 2) * (m2 + 2) + 1) / 2 * 2 : 0;
-}
-
-__host__ __device__ inline size_t box3_doubles(int m0, int m1, int m2, int nrhs, int kc = 1) {
-  const size_t nc = (size_t)m0 * m1 * m2;
-  return kx3_doubles(kc, m0, m1, m2) + (size_t)(m0 + 2) * (m1 + 2) * (m2 + 2) + 2 * nc +
-         (size_t)nrhs * nc + (size_t)nrhs * P3 + 4;
-}
-
-// TS: the tensor form; without it the tiles of axes 1.. are Kt at
-// compile time, and the scalar kernels carry nothing of the tensor.
-template <bool TS>
-__device__ __forceinline__ Box3 carve3(double* base, const Box& B, int nrhs, int kc) {
-  if (!TS) kc = 1;
-  Box3 s;
-  s.m0 = B.hi[0] - B.lo[0];
-  s.m1 = B.hi[1] - B.lo[1];
-  s.m2 = B.hi[2] - B.lo[2];
-  s.nc = s.m0 * s.m1 * s.m2;
-  s.Kx = base;
-  s.ktn = kc > 1 ? (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2) : 0;
-  base += kx3_doubles(kc, s.m0, s.m1, s.m2);
-  s.Kt = base;
-  s.Ka[0] = s.ktn ? s.Kx : s.Kt;
-  s.Ka[1] = s.ktn ? s.Kx + s.ktn : s.Kt;
-  s.Dg = s.Kt + (s.m0 + 2) * (s.m1 + 2) * (s.m2 + 2);
-  s.Tz = s.Dg + s.nc;
-  s.X = s.Tz + s.nc;
-  double* z = s.X + (size_t)nrhs * s.nc;
-  // 16-byte alignment for the paired reads of Z
-  const long long off = z - base;
-  s.Z = base + ((off + 1) & ~1LL);
-  return s;
-}
-
-// K along axis a at global cell (x, y, z) of the box or its halo.
-__device__ __forceinline__ double k3(const Box3& s, const Box& B, int x, int y, int z, int a) {
-  const double* t = a == 0 ? s.Kt : a == 1 ? s.Ka[0] : s.Ka[1];
-  return t[((z - B.lo[2] + 1) * (s.m1 + 2) + (y - B.lo[1] + 1)) * (s.m0 + 2) + (x - B.lo[0] + 1)];
-}
-
-__device__ __forceinline__ double rcp3(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-// K tile (log K when LOG: exponentiated here) and the diagonal and plane
-// couplings of the box matrix.
-template <int NW, bool LOG>
-__device__ __forceinline__ void load_box3(const Geo& g, const Box& B, const double* Kg, double beta,
-                                          Box3& s) {
-  constexpr int NT = 64 * NW;
-  const int tid = threadIdx.x;
-  const int W0 = s.m0 + 2, W1 = s.m1 + 2, W2 = s.m2 + 2;
-  const int nt = W0 * W1 * W2;
-  for (int e0 = 0; e0 < nt; e0 += NT * 4) {
-    double v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * NT + tid;
-      const int x = B.lo[0] - 1 + e % W0, y = B.lo[1] - 1 + (e / W0) % W1, z = B.lo[2] - 1 + e / (W0 * W1);
-      const bool in = e < nt && x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2];
-      v[u] = in ? Kg[x + g.n[0] * (y + g.n[1] * z)] : (LOG ? 0.0 : 1.0);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * NT + tid;
-      if (e < nt) s.Kt[e] = LOG ? exp(v[u]) : v[u];
-    }
-  }
-  // the other axes' entries of a diagonal tensor
-  for (int e = tid; e < (s.ktn ? (g.kc - 1) * nt : 0); e += NT) {
-    const int ax = 1 + e / nt, u = e - (ax - 1) * nt;
-    const int x = B.lo[0] - 1 + u % W0, y = B.lo[1] - 1 + (u / W0) % W1, z = B.lo[2] - 1 + u / (W0 * W1);
-    const bool in = x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2];
-    const double v = in ? Kg[kaxis(g, ax) + x + g.n[0] * (y + g.n[1] * z)] : (LOG ? 0.0 : 1.0);
-    s.Kx[e] = LOG ? exp(v) : v;
-  }
-  bsync<NW>();
-  const double ih = rcp3(g.h);
-  for (int loc = tid; loc < s.nc; loc += NT) {
-    const int x = B.lo[0] + loc % s.m0, y = B.lo[1] + (loc / s.m0) % s.m1, z = B.lo[2] + loc / (s.m0 * s.m1);
-    double diag = 0.0, tz = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double kc = k3(s, B, x, y, z, a);
-#pragma unroll
-      for (int sd = 0; sd < 2; ++sd) {
-        int o[3] = {x, y, z};
-        o[a] += sd ? 1 : -1;
-        if (o[a] < 0 || o[a] >= g.n[a]) {
-          if (g.bc_type[2 * a + sd]) diag += 2.0 * kc * g.area * ih;
-          continue;
-        }
-        const double ko = k3(s, B, o[0], o[1], o[2], a);
-        const bool inside = o[a] >= B.lo[a] && o[a] < B.hi[a];
-        if (inside) {
-          const double T = g.area * 2.0 * kc * ko * rcp3(kc + ko) * ih;
-          diag += T;
-          if (a == 2 && sd) tz = T;
-        } else {
-          const double bt = robin_beta(g, a, kc, ko, beta);
-          diag += robin_T(g, kc, bt);
-        }
-      }
-    }
-    s.Dg[loc] = diag;
-    s.Tz[loc] = tz;
-  }
-  bsync<NW>();
-}
-
-// In-plane coupling between plane cells a and a + dx (dx = 1: x, m0: y) of
-// plane j, from the K tile (0 when the neighbour is outside the box).
-__device__ __forceinline__ double tplane(const Geo& g, const Box& B, const Box3& s, int j, int a, int axis) {
-  const int x = B.lo[0] + a % s.m0, y = B.lo[1] + a / s.m0, z = B.lo[2] + j;
-  const int ox = x + (axis == 0), oy = y + (axis == 1);
-  if (ox >= B.hi[0] || oy >= B.hi[1]) return 0.0;
-  const double kc = k3(s, B, x, y, z, axis), ko = k3(s, B, ox, oy, z, axis);
-  return g.area * 2.0 * kc * ko * rcp3(kc + ko) * rcp3(g.h);
-}
 
 // S_j = D_j - t_{j-1} W_{j-1} t_{j-1} (the lane's 16 entries of column c),
 // w holding W_{j-1} on entry when j > 0; identity outside the nb x nb block.
@@ -506,50 +333,6 @@ __device__ __forceinline__ void backward3(const Box3& s, Gj3& sm, const double* 
   }
 }
 
-__device__ __forceinline__ int bloc3(const Box& B, const Box3& s, const int c[3]) {
-  return (c[0] - B.lo[0]) + s.m0 * ((c[1] - B.lo[1]) + s.m1 * (c[2] - B.lo[2]));
-}
-
-__device__ __forceinline__ void omega3(const Geo& g, int sub, int lo[3], int hi[3]) {
-  int r = sub;
-  for (int a = 0; a < 3; ++a) {
-    const int ia = r % g.M[a];
-    r /= g.M[a];
-    lo[a] = ia * g.S[a];
-    hi[a] = lo[a] + g.S[a];
-  }
-}
-
-__device__ __forceinline__ int nbr3(const Geo& g, int sub, int q) {
-  const int a = q >> 1, sd = q & 1;
-  int stride = 1;
-  for (int b = 0; b < a; ++b) stride *= g.M[b];
-  const int ia = (sub / stride) % g.M[a];
-  const int t = ia + (sd ? 1 : -1);
-  if (t < 0 || t >= g.M[a]) return -1;
-  return sub + (sd ? stride : -stride);
-}
-
-__device__ __forceinline__ void face3(const int lo[3], const int hi[3], int q, int t, int c[3]) {
-  const int a = q >> 1, sd = q & 1;
-  int r = t;
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    if (b == a) {
-      c[b] = sd ? hi[b] - 1 : lo[b];
-    } else {
-      const int m = hi[b] - lo[b];
-      c[b] = lo[b] + r % m;
-      r /= m;
-    }
-  }
-}
-
-__device__ __forceinline__ bool inbox3(const Box& B, const int c[3]) {
-  return c[0] >= B.lo[0] && c[0] < B.hi[0] && c[1] >= B.lo[1] && c[1] < B.hi[1] && c[2] >= B.lo[2] &&
-         c[2] < B.hi[2];
-}
-
 // Steps 1-2 on an oversampled box (FO: Step 6, the factor alone).
 template <int NW, bool FO, bool TS>
 __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
@@ -564,93 +347,13 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
   load_box3<NW, true>(g, B, logK, beta, s);
   for (int e = tid; e < nrhs * s.nc; e += NT) s.X[e] = 0.0;
   bsync<NW>();
-  // T^R times the seed on the cells of its side
-  for (int k = 0; k < nrhs; ++k) {
-    const Seed sd = seeds[B.seed0 + k];
-    const int a = sd.side >> 1, so = sd.side & 1;
-    int nf = 1;
-    for (int b = 0; b < 3; ++b)
-      if (b != a) nf *= B.hi[b] - B.lo[b];
-    for (int t = tid; t < nf; t += NT) {
-      int c[3];
-      face3(B.lo, B.hi, sd.side, t, c);
-      int o[3] = {c[0], c[1], c[2]};
-      o[a] += so ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2], a);
-      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2], a), beta);
-      s.X[k * s.nc + bloc3(B, s, c)] = robin_T(g, kc, bt) * seed_value(g, sd, B.lo, B.hi, c);
-    }
-  }
+  seed_rhs3<NW>(g, B, s, seeds, beta, nrhs, s.X);
   bsync<NW>();
   double* Wg = fac + B.fac;
   factor3<NW>(g, B, s, Wg, nrhs, sm);
   if (FO) return;
   backward3<NW>(s, sm, Wg, nrhs);
-  int olo[3], ohi[3];
-  omega3(g, B.sub, olo, ohi);
-  const int ncell_o = g.S[0] * g.S[1] * g.S[2];
-  for (int e = tid; e < nrhs * ncell_o; e += NT) {
-    const int k = e / ncell_o, t = e % ncell_o;
-    const int c[3] = {olo[0] + t % g.S[0], olo[1] + (t / g.S[0]) % g.S[1], olo[2] + t / (g.S[0] * g.S[1])};
-    Pk[(long long)(B.seed0 + k) * ncell_o + t] = s.X[k * s.nc + bloc3(B, s, c)];
-  }
-  for (int q = 0; q < 6; ++q) {
-    const int a = q >> 1, so = q & 1;
-    int nf = 1;
-    for (int b = 0; b < 3; ++b)
-      if (b != a) nf *= g.S[b];
-    const bool has = nbr3(g, B.sub, q) >= 0;
-    for (int e = tid; e < nrhs * nf; e += NT) {
-      const int k = e / nf, t = e % nf;
-      const long long oidx = (long long)(B.seed0 + k) * g.gstride + g.gside_off[q] + t;
-      if (!has) {
-        tr_u[oidx] = 0.0;
-        tr_phi[oidx] = 0.0;
-        continue;
-      }
-      int c[3];
-      face3(olo, ohi, q, t, c);
-      int o[3] = {c[0], c[1], c[2]};
-      o[a] += so ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2], a), ko = k3(s, B, o[0], o[1], o[2], a);
-      const double Pc = s.X[k * s.nc + bloc3(B, s, c)];
-      const double bt = robin_beta(g, a, kc, ko, beta);
-      double u;
-      if (inbox3(B, o)) {
-        u = g.area * kharm(kc, ko) / g.h * (Pc - s.X[k * s.nc + bloc3(B, s, o)]) / g.area;
-      } else {
-        const Seed sd = seeds[B.seed0 + k];
-        const double lam = (sd.side == q) ? seed_value(g, sd, B.lo, B.hi, c) : 0.0;
-        u = robin_T(g, kc, bt) * (Pc - lam) / g.area;
-      }
-      const double pi = Pc - u * g.h / (2.0 * kc);
-      tr_u[oidx] = u;
-      tr_phi[oidx] = -bt * u + pi;
-      if (k == 0) tr_beta[(long long)B.sub * g.gstride + g.gside_off[q] + t] = bt;
-    }
-  }
-}
-
-// Right-hand side of the physical data (source, boundary conditions).
-template <int NW>
-__device__ __forceinline__ void physical3(const Geo& g, const Box& B, const Box3& s,
-                                          const double* __restrict__ f,
-                                          const double* __restrict__ bcv, double* X) {
-  for (int loc = threadIdx.x; loc < s.nc; loc += 64 * NW) {
-    const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
-    const int ci = gcell(g, c);
-    double b = f[ci] * g.vol;
-    for (int a = 0; a < 3; ++a)
-      for (int sd = 0; sd < 2; ++sd) {
-        const int t = c[a] + (sd ? 1 : -1);
-        if (t >= 0 && t < g.n[a]) continue;
-        const int side = 2 * a + sd;
-        const double val = bcv[g.bc_off[side] + bface_index(g, c, a)];
-        if (g.bc_type[side]) b += 2.0 * k3(s, B, c[0], c[1], c[2], a) * g.area / g.h * val;
-        else b -= g.area * val;
-      }
-    X[loc] = b;
-  }
+  basis_out3<NW>(g, B, s, seeds, beta, nrhs, Pk, tr_u, tr_phi, tr_beta);
 }
 
 // Step 4 on a subdomain: K = exp(log K) of its cells (the subdomains cover
@@ -663,76 +366,15 @@ __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
                                             double* __restrict__ fac, double* __restrict__ pbar,
                                             double* __restrict__ ubar, double* __restrict__ pibar,
                                             double* dsm, Gj3& sm) {
-  constexpr int NT = 64 * NW;
-  const int tid = threadIdx.x;
   Box3 s = carve3<TS>(dsm, B, 1, g.kc);
   load_box3<NW, true>(g, B, logK, beta, s);
-  for (int loc = tid; loc < s.nc; loc += NT) {
-    const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
-    for (int a = 0; a < (TS ? g.kc : 1); ++a) {
-      const double k = k3(s, B, c[0], c[1], c[2], a);
-      if (!(k > 0.0) || !isfinite(k)) atomicOr(&sm.flag, kFlagBadK);
-      K[kaxis(g, a) + gcell(g, c)] = k;
-    }
-  }
+  part_k3<NW, TS>(g, B, s, K, sm.flag);
   physical3<NW>(g, B, s, f, bcv, s.X);
   bsync<NW>();
   double* Wg = fac + B.fac;
   factor3<NW>(g, B, s, Wg, 1, sm);
   backward3<NW>(s, sm, Wg, 1);
-  for (int t = tid; t < s.nc; t += NT) pbar[(long long)B.sub * s.nc + t] = s.X[t];
-  for (int q = 0; q < 6; ++q) {
-    const int a = q >> 1, so = q & 1;
-    int nf = 1;
-    for (int b = 0; b < 3; ++b)
-      if (b != a) nf *= g.S[b];
-    const bool has = nbr3(g, B.sub, q) >= 0;
-    for (int t = tid; t < nf; t += NT) {
-      const long long oidx = (long long)B.sub * g.gstride + g.gside_off[q] + t;
-      if (!has) {
-        ubar[oidx] = 0.0;
-        pibar[oidx] = 0.0;
-        continue;
-      }
-      int c[3];
-      face3(B.lo, B.hi, q, t, c);
-      int o[3] = {c[0], c[1], c[2]};
-      o[a] += so ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2], a);
-      const double bt = robin_beta(g, a, kc, k3(s, B, o[0], o[1], o[2], a), beta);
-      const double u = robin_T(g, kc, bt) * s.X[bloc3(B, s, c)] / g.area;
-      ubar[oidx] = u;
-      pibar[oidx] = bt * u;
-    }
-  }
-}
-
-// Robin data lambda on face (a, sd) of box cell c from the current state
-// (Section 3 item 3): from the two-point flux across the face when the
-// outside cell lies in the neighbouring subdomain's reach (overlap > 0), or
-// from the neighbour's own Gamma flux and trace (overlap 0).
-__device__ __forceinline__ double lambda3(const Geo& g, const Box& B, const Box3& s,
-                                          const double* __restrict__ p,
-                                          const double* __restrict__ gflux, double beta,
-                                          const int c[3], int a, int sd) {
-  int o[3] = {c[0], c[1], c[2]};
-  o[a] += sd ? 1 : -1;
-  const double kc = k3(s, B, c[0], c[1], c[2], a), ko = k3(s, B, o[0], o[1], o[2], a);
-  const double bt = robin_beta(g, a, kc, ko, beta);
-  const int ci = gcell(g, c), oi = gcell(g, o);
-  if (g.l > 0) {
-    const double u = g.area * kharm(kc, ko) / g.h * (p[ci] - p[oi]) / g.area;
-    const double pi = p[ci] - u * g.h / (2.0 * kc);
-    return -bt * u + pi;
-  }
-  const int q = 2 * a + sd;
-  const int j = nbr3(g, B.sub, q);
-  int jlo[3], jhi[3];
-  omega3(g, j, jlo, jhi);
-  const int t = side_face_index(g, jlo, jhi, o, a);
-  const double uj = gflux[(long long)j * g.gstride + g.gside_off[q ^ 1] + t];
-  const double pij = p[oi] - uj * g.h / (2.0 * ko);
-  return bt * uj + pij;
+  part_out3<NW>(g, B, s, beta, pbar, ubar, pibar);
 }
 
 // Steps 6-7 for one box: right-hand side from the state, solve with the
@@ -743,27 +385,11 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
                                         const double* __restrict__ bcv, double beta,
                                         const double* __restrict__ fac, double* p, double* gflux,
                                         double* dsm, Gj3& sm) {
-  constexpr int NT = 64 * NW;
-  const int tid = threadIdx.x;
   Box3 s = carve3<TS>(dsm, B, 1, g.kc);
   load_box3<NW, false>(g, B, K, beta, s);
   physical3<NW>(g, B, s, f, bcv, s.X);
   bsync<NW>();
-  for (int loc = tid; loc < s.nc; loc += NT) {
-    const int c[3] = {B.lo[0] + loc % s.m0, B.lo[1] + (loc / s.m0) % s.m1, B.lo[2] + loc / (s.m0 * s.m1)};
-    double add = 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int sd = 0; sd < 2; ++sd) {
-        const int o = c[a] + (sd ? 1 : -1);
-        if (o < 0 || o >= g.n[a] || (o >= B.lo[a] && o < B.hi[a])) continue;
-        int oc[3] = {c[0], c[1], c[2]};
-        oc[a] = o;
-        const double kc = k3(s, B, c[0], c[1], c[2], a);
-        const double bt = robin_beta(g, a, kc, k3(s, B, oc[0], oc[1], oc[2], a), beta);
-        add += robin_T(g, kc, bt) * lambda3(g, B, s, p, gflux, beta, c, a, sd);
-      }
-    s.X[loc] += add;
-  }
+  smooth_rhs3<NW>(g, B, s, p, gflux, beta, s.X);
   bsync<NW>();
   const int nb = s.m0 * s.m1;
   const double* Wg = fac + B.fac;
@@ -773,39 +399,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
     fwd3<NW>(s, sm, nb, j, 1, w);
   }
   backward3<NW>(s, sm, Wg, 1);
-  // Gamma fluxes of Omega_i (before p changes: with overlap 0 they read lambda)
-  int olo[3], ohi[3];
-  omega3(g, B.sub, olo, ohi);
-  for (int q = 0; q < 6; ++q) {
-    if (nbr3(g, B.sub, q) < 0) continue;
-    const int a = q >> 1, sd = q & 1;
-    int nf = 1;
-    for (int b = 0; b < 3; ++b)
-      if (b != a) nf *= g.S[b];
-    for (int t = tid; t < nf; t += NT) {
-      int c[3];
-      face3(olo, ohi, q, t, c);
-      int o[3] = {c[0], c[1], c[2]};
-      o[a] += sd ? 1 : -1;
-      const double kc = k3(s, B, c[0], c[1], c[2], a), ko = k3(s, B, o[0], o[1], o[2], a);
-      const double xc = s.X[bloc3(B, s, c)];
-      double u;
-      if (inbox3(B, o)) {
-        u = g.area * kharm(kc, ko) / g.h * (xc - s.X[bloc3(B, s, o)]) / g.area;
-      } else {
-        const double lam = lambda3(g, B, s, p, gflux, beta, c, a, sd);
-        u = robin_T(g, kc, robin_beta(g, a, kc, ko, beta)) * (xc - lam) / g.area;
-      }
-      gflux[(long long)B.sub * g.gstride + g.gside_off[q] + t] = u;
-    }
-  }
-  // every Robin datum of the box has been read before p is written
-  bsync<NW>();
-  const int ncell_o = g.S[0] * g.S[1] * g.S[2];
-  for (int t = tid; t < ncell_o; t += NT) {
-    const int c[3] = {olo[0] + t % g.S[0], olo[1] + (t / g.S[0]) % g.S[1], olo[2] + t / (g.S[0] * g.S[1])};
-    p[gcell(g, c)] = s.X[bloc3(B, s, c)];
-  }
+  smooth_out3<NW>(g, B, s, p, gflux, beta);
 }
 
 // Register budget for three resident boxes per CU (their LDS allows no

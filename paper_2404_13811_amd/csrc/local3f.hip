@@ -1,0 +1,732 @@
+// Kernels for 3-D local problems in the FP32 form: the plane-block factor
+// of the diagonally scaled box matrix A^ = D^-1/2 A D^-1/2 is formed and
+// applied in FP32, and every local solve is refined in FP64 on the
+// unscaled two-point-flux matrix A:
+//     x = 0;  repeat  r = b - A x (FP64);  x += D^-1/2 solve32(D^-1/2 r)
+// until the componentwise backward error max_c |r_c| / (|A| |x| + |b|)_c
+// is at most tol.  Steps 1-2 (seed solves, traces on Gamma_i, basis
+// functions on Omega_i), Step 4 (particular problems), Step 6 (factor only)
+// and one colour phase of the smoothing sweep (Steps 6-7).
+//
+// Layout as the FP64 kernels (local3.hip): one workgroup of NW wavefronts
+// per box, lane c of wave v holding rows 16v .. 16v + 15 of column c of the
+// padded 64 x 64 plane block, here in FP32; the block LDL^T recurrence
+// S_j = D_j - t_{j-1} W_{j-1} t_{j-1} with W_j = S_j^{-1} formed in place by
+// four-pivot Gauss-Jordan elimination with look-ahead.  What the FP32 form
+// adds: the inverses of the first JC = 8 planes (16 registers each per
+// lane, 128 in all) stay in registers once formed or read, so the back
+// substitution and every refinement sweep read no factor from memory, and
+// a smoothing box reads its stored FP32 inverses once per solve however
+// many refinement sweeps it takes.  Planes beyond the eighth are read back
+// from the stored inverses (nb x nb, row-major FP32).
+#include "local3_common.h"
+#include "pivot4.h"
+
+namespace mrcm {
+namespace {
+
+constexpr int JC = 8;  // plane inverses held in registers
+
+// Pivot data of one elimination step (two alternating buffers), as Gj3 of
+// the FP64 kernels in FP32; vb and rs (1024 floats) also hold the per-wave
+// partial sums of the block-vector products.  red: the waves' maxima of
+// the backward error.
+struct __align__(16) Gj3f {
+  float vb[2][G3 * P3];
+  float rs[2][P3 * G3];
+  float pb[2][G3 * G3];
+  double red[4];
+  int flag;
+};
+
+__device__ __forceinline__ float* partials3f(Gj3f& sm) { return &sm.vb[0][0]; }
+
+// LDS of one box in the FP32 form: the FP64 box (K tile, diagonal, plane
+// couplings; s.X holds the FP64 solutions x, nrhs x ncell), then
+struct Box3F {
+  Box3 s;
+  double* sd;   // ncell: D^-1/2
+  double* Bv;   // ncell right-hand side (particular and smoothing boxes)
+  float* Xf;    // nrhs x ncell: scaled residuals, then the FP32 corrections
+  float* Tzf;   // ncell: scaled couplings to the next plane
+  float* Zf;    // nrhs x 64 staging of one block (16-byte aligned)
+};
+
+__host__ __device__ inline size_t box3f_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc) {
+  const size_t nc = (size_t)m0 * m1 * m2;
+  const size_t d = kx3_doubles(kc, m0, m1, m2) + (size_t)(m0 + 2) * (m1 + 2) * (m2 + 2) + 2 * nc +
+                   (size_t)nrhs * nc + nc + (size_t)nbv * nc;
+  const size_t f = (size_t)nrhs * nc + nc + (size_t)(nrhs < 1 ? 1 : nrhs) * P3 + 4;
+  return d * sizeof(double) + f * sizeof(float) + 16;
+}
+
+template <bool TS>
+__device__ __forceinline__ Box3F carve3f(double* base, const Box& B, int nrhs, int nbv, int kc) {
+  Box3F F;
+  F.s = carve3<TS>(base, B, nrhs, kc);  // F.s.Z (FP64 staging) is not used
+  const int nc = F.s.nc;
+  F.sd = F.s.X + (size_t)nrhs * nc;
+  F.Bv = F.sd + nc;
+  F.Xf = reinterpret_cast<float*>(F.Bv + (size_t)nbv * nc);
+  F.Tzf = F.Xf + (size_t)nrhs * nc;
+  const uintptr_t z = reinterpret_cast<uintptr_t>(F.Tzf + nc);
+  F.Zf = reinterpret_cast<float*>((z + 15) & ~uintptr_t(15));
+  return F;
+}
+
+// D^-1/2 and the scaled plane couplings (after load_box3).
+template <int NW>
+__device__ __forceinline__ void scale3f(const Box3F& F) {
+  constexpr int NT = 64 * NW;
+  const Box3& s = F.s;
+  const int nc = s.nc, nb = s.m0 * s.m1;
+  for (int e = threadIdx.x; e < nc; e += NT) F.sd[e] = rcp3(sqrt(s.Dg[e]));
+  bsync<NW>();
+  for (int e = threadIdx.x; e < nc; e += NT)
+    F.Tzf[e] = e + nb < nc ? (float)(s.Tz[e] * F.sd[e] * F.sd[e + nb]) : 0.0f;
+  bsync<NW>();
+}
+
+// Scaled S_j = D^_j - t^_{j-1} W_{j-1} t^_{j-1} (the lane's 16 entries of
+// column c), w holding W_{j-1} on entry when j > 0; identity outside the
+// nb x nb block.  The couplings are scaled in FP64 and rounded once.
+__device__ __forceinline__ void build3f(const Geo& g, const Box& B, const Box3F& F, int j, float w[R3]) {
+  const Box3& s = F.s;
+  const int c = lane3();
+  const int r0 = R3 * wave3();
+  const int nb = s.m0 * s.m1, m0 = s.m0;
+  const bool cin = c < nb;
+  const int cc = cin ? c : 0;
+  const int xl = cc % m0;
+  const double* sdj = F.sd + j * nb;
+  const double sc = sdj[cc];
+  const float dc = (float)(s.Dg[j * nb + cc] * sc * sc);
+  const float txm = (cin && xl > 0) ? (float)(tplane(g, B, s, j, cc - 1, 0) * sc * sdj[cc - 1]) : 0.0f;
+  const float txp = (cin && xl + 1 < m0) ? (float)(tplane(g, B, s, j, cc, 0) * sc * sdj[cc + 1]) : 0.0f;
+  const float tym = (cin && cc >= m0) ? (float)(tplane(g, B, s, j, cc - m0, 1) * sc * sdj[cc - m0]) : 0.0f;
+  const float typ = (cin && cc + m0 < nb) ? (float)(tplane(g, B, s, j, cc, 1) * sc * sdj[cc + m0]) : 0.0f;
+  const float* tp = F.Tzf + (j > 0 ? j - 1 : 0) * nb;
+  const float tcp = (j > 0 && cin) ? tp[cc] : 0.0f;
+#pragma unroll
+  for (int ii = 0; ii < R3; ++ii) {
+    const int i = r0 + ii;
+    float v = (i == c) ? dc : 0.0f;
+    v -= (i == c - 1) ? txm : 0.0f;
+    v -= (i == c + 1) ? txp : 0.0f;
+    v -= (i == c - m0) ? tym : 0.0f;
+    v -= (i == c + m0) ? typ : 0.0f;
+    if (j > 0 && i < nb) v = fmaf(-tp[i] * tcp, w[ii], v);
+    w[ii] = (i < nb && cin) ? v : (i == c ? 1.0f : 0.0f);
+  }
+}
+
+// Four-pivot Gauss-Jordan inverse with look-ahead in FP32: the steps of
+// gj3_pivot / gj3_rows / gj3_step of the FP64 kernels, on floats.
+template <int NW, int K>
+__device__ __forceinline__ void gj3f_pivot(Gj3f& sm, float w[R3], bool& bad) {
+  constexpr int RI = K % R3;
+  const int c = lane3_here();
+  const int ck = c - K;
+  const bool pc = ck >= 0 && ck < G3;
+  float* vb = sm.vb[(K / G3) & 1];
+  float* rs = sm.rs[(K / G3) & 1];
+  float* pb = sm.pb[(K / G3) & 1];
+  if (pc) *reinterpret_cast<float4*>(pb + ck * G3) = make_float4(w[RI], w[RI + 1], w[RI + 2], w[RI + 3]);
+  const float sg = c < K ? -1.0f : 1.0f;
+  *reinterpret_cast<float4*>(rs + c * G3) =
+      make_float4(sg * w[RI], sg * w[RI + 1], sg * w[RI + 2], sg * w[RI + 3]);
+  bsync<1>();  // the pivot block is read back by this wave only
+  float P[G3][G3], r[G3], v[G3];
+#pragma unroll
+  for (int j = 0; j < G3; ++j)
+#pragma unroll
+    for (int m = 0; m < G3; ++m) P[m][j] = pb[j * G3 + m];
+#pragma unroll
+  for (int m = 0; m < G3; ++m) {
+    const float wm = w[RI + m];
+    const float unit = ck == m ? 1.0f : 0.0f;
+    r[m] = pc ? unit : wm;
+  }
+  const PivBlock<float> q = piv_block(P);
+  bad |= !(q.d0 > 0.0f && q.da > 0.0f && q.s0 > 0.0f && q.ds > 0.0f);
+  piv_apply(q, r, v);
+#pragma unroll
+  for (int m = 0; m < G3; ++m) vb[m * P3 + c] = v[m];
+}
+
+template <int R0, int R1>
+__device__ __forceinline__ void gj3f_rows(const float* rw, unsigned keep, const float v[G3], float w[R3]) {
+#pragma unroll
+  for (int ii = R0; ii < R1; ++ii) {
+    const float4 cr = *reinterpret_cast<const float4*>(rw + ii * G3);
+    float acc = __uint_as_float(__float_as_uint(w[ii]) & keep);
+    acc = fmaf(-cr.x, v[0], acc);
+    acc = fmaf(-cr.y, v[1], acc);
+    acc = fmaf(-cr.z, v[2], acc);
+    acc = fmaf(-cr.w, v[3], acc);
+    w[ii] = acc;
+  }
+}
+
+template <int NW, int K>
+__device__ __forceinline__ void gj3f_step(int nb, Gj3f& sm, float w[R3], bool& bad) {
+  constexpr int OWN = K / R3, RI = K % R3;
+  constexpr int KN = K + G3, OWNN = KN / R3, RIN = KN % R3;
+  const int c = lane3_here();
+  const int wv = wave3();
+  const float* vb = sm.vb[(K / G3) & 1];
+  const float* rw = sm.rs[(K / G3) & 1] + R3 * wv * G3;
+  const int ck = c - K;
+  const bool pc = ck >= 0 && ck < G3;
+  const unsigned keep = pc ? 0u : ~0u;
+  float v[G3];
+#pragma unroll
+  for (int m = 0; m < G3; ++m) v[m] = vb[m * P3 + c];
+  if constexpr (KN < R3 * NW) {
+    gj3f_rows<RIN, RIN + G3>(rw, keep, v, w);
+    if (KN < nb && wv == OWNN) gj3f_pivot<NW, KN>(sm, w, bad);
+    gj3f_rows<0, RIN>(rw, keep, v, w);
+    gj3f_rows<RIN + G3, R3>(rw, keep, v, w);
+  } else {
+    gj3f_rows<0, R3>(rw, keep, v, w);
+  }
+  if (wv == OWN) {
+#pragma unroll
+    for (int m = 0; m < G3; ++m) w[RI + m] = v[m];
+  }
+  bsync<NW>();
+}
+
+template <int NW, int K>
+__device__ __forceinline__ void gj3f_steps(int nb, Gj3f& sm, float w[R3], bool& bad) {
+  if constexpr (K < R3 * NW) {
+    if (K < nb) {
+      gj3f_step<NW, K>(nb, sm, w, bad);
+      gj3f_steps<NW, K + G3>(nb, sm, w, bad);
+    }
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ void gj3f(int nb, Gj3f& sm, float w[R3]) {
+  bool bad = false;
+  if (wave3() == 0) gj3f_pivot<NW, 0>(sm, w, bad);
+  bsync<NW>();
+  gj3f_steps<NW, 0>(nb, sm, w, bad);
+  if (bad && lane3() == 0) atomicOr(&sm.flag, kFlagNotPD);
+  bsync<NW>();
+}
+
+// The lane's 16-term share of y = W z for z staged in LDS.
+__device__ __forceinline__ float wdot3f(const float w[R3], const float* z) {
+  const float* zw = z + R3 * wave3();
+  float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+  for (int ii = 0; ii < R3; ii += 4) {
+    const float4 zz = *reinterpret_cast<const float4*>(zw + ii);
+    a0 = fmaf(w[ii], zz.x, a0);
+    a1 = fmaf(w[ii + 1], zz.y, a1);
+    a0 = fmaf(w[ii + 2], zz.z, a0);
+    a1 = fmaf(w[ii + 3], zz.w, a1);
+  }
+  return a0 + a1;
+}
+
+// Y[k][c] (+)= (W Z_k)[c] for the nrhs vectors staged in Zf; the waves'
+// partial sums added through LDS in a fixed order, four vectors at a time.
+template <int NW, bool ACC>
+__device__ __forceinline__ void wmul3f(const Box3F& F, Gj3f& sm, int nb, int nrhs, const float w[R3],
+                                       float* Y, int ystride) {
+  constexpr int NT = 64 * NW;
+  const int c = lane3();
+  if constexpr (NW == 1) {
+    for (int k = 0; k < nrhs; ++k) {
+      const float y = wdot3f(w, F.Zf + k * P3);
+      if (c < nb) {
+        if (ACC) Y[k * ystride + c] += y;
+        else Y[k * ystride + c] = y;
+      }
+    }
+    bsync<NW>();
+  } else {
+    float* pt = partials3f(sm);
+    const int wv = wave3();
+    for (int k0 = 0; k0 < nrhs; k0 += 4) {
+      const int cnt = min(4, nrhs - k0);
+      for (int kk = 0; kk < cnt; ++kk) pt[(kk * NW + wv) * P3 + c] = wdot3f(w, F.Zf + (k0 + kk) * P3);
+      bsync<NW>();
+      for (int e = threadIdx.x; e < cnt * P3; e += NT) {
+        const int kk = e / P3, L = e % P3;
+        float y = 0.0f;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) y += pt[(kk * NW + u) * P3 + L];
+        if (L < nb) {
+          if (ACC) Y[(k0 + kk) * ystride + L] += y;
+          else Y[(k0 + kk) * ystride + L] = y;
+        }
+      }
+      bsync<NW>();
+    }
+  }
+}
+
+// Forward step of block j on the scaled vectors in Xf: z_j = W_j (r_j +
+// t_{j-1} z_{j-1}).
+template <int NW>
+__device__ __forceinline__ void fwd3f(const Box3F& F, Gj3f& sm, int nb, int j, int nrhs, const float w[R3]) {
+  constexpr int NT = 64 * NW;
+  const int nc = F.s.nc;
+  for (int e = threadIdx.x; e < nrhs * P3; e += NT) {
+    const int k = e / P3, L = e % P3;
+    float v = 0.0f;
+    if (L < nb) {
+      v = F.Xf[k * nc + j * nb + L];
+      if (j > 0) v = fmaf(F.Tzf[(j - 1) * nb + L], F.Xf[k * nc + (j - 1) * nb + L], v);
+    }
+    F.Zf[k * P3 + L] = v;
+  }
+  bsync<NW>();
+  wmul3f<NW, false>(F, sm, nb, nrhs, w, F.Xf + j * nb, nc);
+}
+
+// Backward step of block j: x_j += W_j (t_j .* x_{j+1}).
+template <int NW>
+__device__ __forceinline__ void bwd3f(const Box3F& F, Gj3f& sm, int nb, int j, int nrhs, const float w[R3]) {
+  constexpr int NT = 64 * NW;
+  const int nc = F.s.nc;
+  for (int e = threadIdx.x; e < nrhs * P3; e += NT) {
+    const int k = e / P3, L = e % P3;
+    F.Zf[k * P3 + L] = L < nb ? F.Tzf[j * nb + L] * F.Xf[k * nc + (j + 1) * nb + L] : 0.0f;
+  }
+  bsync<NW>();
+  wmul3f<NW, true>(F, sm, nb, nrhs, w, F.Xf + j * nb, nc);
+}
+
+__device__ __forceinline__ void load3f(const float* Wj, int nb, float w[R3]) {
+  const int c = lane3(), r0 = R3 * wave3();
+#pragma unroll
+  for (int ii = 0; ii < R3; ++ii) {
+    const int i = r0 + ii;
+    w[ii] = (i < nb && c < nb) ? Wj[i * nb + c] : (i == c ? 1.0f : 0.0f);
+  }
+}
+
+__device__ __forceinline__ void store3f(float* Wj, int nb, const float w[R3]) {
+  const int c = lane3(), r0 = R3 * wave3();
+#pragma unroll
+  for (int ii = 0; ii < R3; ++ii) {
+    const int i = r0 + ii;
+    if (i < nb && c < nb) Wj[i * nb + c] = w[ii];
+  }
+}
+
+// Register cache of the plane inverses.  Slots are addressed with
+// compile-time indices only: the sweeps run their first JC planes as an
+// unrolled loop, and a plane formed at a runtime index is written into its
+// slot by selects (a conditional store per slot would be merged into a
+// store through a selected address, which keeps the cache in scratch
+// memory).
+__device__ __forceinline__ void cclear(float wc[JC][R3]) {
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+    for (int ii = 0; ii < R3; ++ii) wc[jj][ii] = 0.0f;
+}
+
+__device__ __forceinline__ void cput(float wc[JC][R3], int j, const float w[R3]) {
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+    for (int ii = 0; ii < R3; ++ii) wc[jj][ii] = jj == j ? w[ii] : wc[jj][ii];
+}
+
+// Factor of the box fused with the forward sweep of the nrhs scaled
+// right-hand sides in Xf; inverses to Wg and to the register cache.
+template <int NW>
+__device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F& F, float* Wg, int nrhs,
+                                         Gj3f& sm, float wc[JC][R3]) {
+  const int nb = F.s.m0 * F.s.m1;
+  float w[R3];
+#pragma unroll
+  for (int i = 0; i < R3; ++i) w[i] = 0.0f;
+  cclear(wc);
+  for (int j = 0; j < F.s.m2; ++j) {
+    build3f(g, B, F, j, w);
+    gj3f<NW>(nb, sm, w);
+    store3f(Wg + (long long)j * nb * nb, nb, w);
+    cput(wc, j, w);
+    if (nrhs > 0) fwd3f<NW>(F, sm, nb, j, nrhs, w);
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ void backward3f(const Box3F& F, Gj3f& sm, const float wc[JC][R3], const float* Wg,
+                                           int nrhs) {
+  const int nb = F.s.m0 * F.s.m1, m2 = F.s.m2;
+  float w[R3];
+  for (int j = m2 - 2; j >= JC; --j) {
+    load3f(Wg + (long long)j * nb * nb, nb, w);
+    bwd3f<NW>(F, sm, nb, j, nrhs, w);
+  }
+#pragma unroll
+  for (int j = JC - 1; j >= 0; --j)
+    if (j <= m2 - 2) bwd3f<NW>(F, sm, nb, j, nrhs, wc[j]);
+}
+
+// Forward sweep with the cached inverses (LOAD: the cache filled from the
+// stored inverses on the way).
+template <int NW, bool LOAD>
+__device__ __forceinline__ void forward3f(const Box3F& F, Gj3f& sm, float wc[JC][R3], const float* Wg,
+                                          int nrhs) {
+  const int nb = F.s.m0 * F.s.m1, m2 = F.s.m2;
+#pragma unroll
+  for (int j = 0; j < JC; ++j)
+    if (j < m2) {
+      if (LOAD) load3f(Wg + (long long)j * nb * nb, nb, wc[j]);
+      fwd3f<NW>(F, sm, nb, j, nrhs, wc[j]);
+    }
+  float w[R3];
+  for (int j = JC; j < m2; ++j) {
+    load3f(Wg + (long long)j * nb * nb, nb, w);
+    fwd3f<NW>(F, sm, nb, j, nrhs, w);
+  }
+}
+
+// Xf <- A^^-1 Xf with the cached inverses.
+template <int NW>
+__device__ __forceinline__ void solve3f(const Box3F& F, Gj3f& sm, float wc[JC][R3], const float* Wg,
+                                        int nrhs) {
+  forward3f<NW, false>(F, sm, wc, Wg, nrhs);
+  backward3f<NW>(F, sm, wc, Wg, nrhs);
+}
+
+// x += D^-1/2 (FP32 correction), for the nrhs solutions.
+template <int NW>
+__device__ __forceinline__ void update3f(const Box3F& F, int nrhs) {
+  const int nc = F.s.nc;
+  for (int e = threadIdx.x; e < nrhs * nc; e += 64 * NW) F.s.X[e] += F.sd[e % nc] * (double)F.Xf[e];
+  bsync<NW>();
+}
+
+__device__ __forceinline__ double wave_max3(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// r = b - A x in FP64 for the nrhs solutions in s.X (b: the seeds' right-
+// hand sides when seeds is given, else Bv), D^-1/2 r into Xf, and the
+// componentwise backward error over the box (the same value on every lane).
+// A residual or iterate that is not finite gives an infinite error.
+template <int NW>
+__device__ __forceinline__ double resid3f(const Geo& g, const Box& B, const Box3F& F,
+                                          const Seed* __restrict__ seeds, double beta, int nrhs,
+                                          Gj3f& sm) {
+  constexpr int NT = 64 * NW;
+  const Box3& s = F.s;
+  const int nc = s.nc, m0 = s.m0, m1 = s.m1, m2 = s.m2, nb = m0 * m1;
+  double om = 0.0;
+  for (int e = threadIdx.x; e < nrhs * nc; e += NT) {
+    const int k = e / nc, loc = e - k * nc;
+    const int xl = loc % m0, yl = (loc / m0) % m1, j = loc / nb, a = loc - j * nb;
+    const double* x = s.X + (size_t)k * nc;
+    double bv;
+    if (seeds) {
+      const Seed sd = seeds[B.seed0 + k];
+      const int c[3] = {B.lo[0] + xl, B.lo[1] + yl, B.lo[2] + j};
+      const int sa = sd.side >> 1;
+      const bool on = pick3(c, sa) == ((sd.side & 1) ? pick3(B.hi, sa) - 1 : pick3(B.lo, sa));
+      bv = on ? seed_face_b3(g, B, s, sd, beta, c) : 0.0;
+    } else {
+      bv = F.Bv[loc];
+    }
+    const double xc = x[loc];
+    double ax = s.Dg[loc] * xc, aa = fabs(ax), t;
+    if (xl > 0) { t = tplane(g, B, s, j, a - 1, 0) * x[loc - 1]; ax -= t; aa += fabs(t); }
+    if (xl + 1 < m0) { t = tplane(g, B, s, j, a, 0) * x[loc + 1]; ax -= t; aa += fabs(t); }
+    if (yl > 0) { t = tplane(g, B, s, j, a - m0, 1) * x[loc - m0]; ax -= t; aa += fabs(t); }
+    if (yl + 1 < m1) { t = tplane(g, B, s, j, a, 1) * x[loc + m0]; ax -= t; aa += fabs(t); }
+    if (j > 0) { t = s.Tz[loc - nb] * x[loc - nb]; ax -= t; aa += fabs(t); }
+    if (j + 1 < m2) { t = s.Tz[loc] * x[loc + nb]; ax -= t; aa += fabs(t); }
+    const double r = bv - ax;
+    const double den = aa + fabs(bv);
+    if (!(r - r == 0.0 && den - den == 0.0)) om = INFINITY;
+    else if (den > 0.0) om = fmax(om, fabs(r) / den);
+    F.Xf[e] = (float)(F.sd[loc] * r);
+  }
+  om = wave_max3(om);
+  if (lane3() == 0) sm.red[wave3()] = om;
+  bsync<NW>();
+  double omega = sm.red[0];
+#pragma unroll
+  for (int u = 1; u < NW; ++u) omega = fmax(omega, sm.red[u]);
+  return omega;
+}
+
+// Refinement after the first FP32 solve (x = D^-1/2 z already in s.X);
+// returns the number of FP32 solves, the final backward error in omega.
+template <int NW>
+__device__ __forceinline__ int refine3f(const Geo& g, const Box& B, const Box3F& F, const float* Wg,
+                                        const Seed* __restrict__ seeds, double beta, int nrhs, double tol,
+                                        int max_refine, Gj3f& sm, float wc[JC][R3], double& omega) {
+  int it = 1;
+  while (true) {
+    omega = resid3f<NW>(g, B, F, seeds, beta, nrhs, sm);
+    if (omega <= tol) break;
+    if (it > max_refine || !(omega <= 1e300)) {
+      if (threadIdx.x == 0) atomicOr(&sm.flag, kFlagNoConv);
+      break;
+    }
+    solve3f<NW>(F, sm, wc, Wg, nrhs);
+    update3f<NW>(F, nrhs);
+    ++it;
+  }
+  return it;
+}
+
+__device__ __forceinline__ void record3f(int it, double omega, int* iters, unsigned long long* resid) {
+  if (threadIdx.x == 0) {
+    atomicMax(iters, it);
+    atomicMax(resid, (unsigned long long)__double_as_longlong(omega));
+  }
+}
+
+// Xf = D^-1/2 b for x = 0 (b in X, or in Bv when FROM_BV), and X = 0.
+template <int NW, bool FROM_BV>
+__device__ __forceinline__ void start3f(const Box3F& F, int nrhs) {
+  const int nc = F.s.nc;
+  for (int e = threadIdx.x; e < nrhs * nc; e += 64 * NW) {
+    const int loc = e % nc;
+    const double b = FROM_BV ? F.Bv[loc] : F.s.X[e];
+    F.Xf[e] = (float)(F.sd[loc] * b);
+    F.s.X[e] = 0.0;
+  }
+  bsync<NW>();
+}
+
+// Steps 1-2 on an oversampled box (FO: Step 6, the factor alone).
+template <int NW, bool FO, bool TS>
+__device__ __forceinline__ void basis3f(const Geo& g, const Box& B, const Seed* __restrict__ seeds,
+                                        const double* __restrict__ logK, double beta, float* __restrict__ fac,
+                                        double* __restrict__ Pk, double* __restrict__ tr_u,
+                                        double* __restrict__ tr_phi, double* __restrict__ tr_beta,
+                                        double tol, int max_refine, int* iters, unsigned long long* resid,
+                                        double* dsm, Gj3f& sm) {
+  constexpr int NT = 64 * NW;
+  const int nrhs = FO ? 0 : B.nrhs;
+  Box3F F = carve3f<TS>(dsm, B, nrhs, 0, g.kc);
+  Box3& s = F.s;
+  load_box3<NW, true>(g, B, logK, beta, s);
+  scale3f<NW>(F);
+  for (int e = threadIdx.x; e < nrhs * s.nc; e += NT) s.X[e] = 0.0;
+  bsync<NW>();
+  seed_rhs3<NW>(g, B, s, seeds, beta, nrhs, s.X);
+  bsync<NW>();
+  start3f<NW, false>(F, nrhs);
+  float* Wg = fac + B.fac;
+  float wc[JC][R3];
+  factor3f<NW>(g, B, F, Wg, nrhs, sm, wc);
+  if (FO) return;
+  backward3f<NW>(F, sm, wc, Wg, nrhs);
+  update3f<NW>(F, nrhs);
+  double omega;
+  const int it = refine3f<NW>(g, B, F, Wg, seeds, beta, nrhs, tol, max_refine, sm, wc, omega);
+  record3f(it, omega, iters, resid);
+  basis_out3<NW>(g, B, s, seeds, beta, nrhs, Pk, tr_u, tr_phi, tr_beta);
+}
+
+// Step 4 on a subdomain; writes K = exp(log K) of its cells.
+template <int NW, bool TS>
+__device__ __forceinline__ void particular3f(const Geo& g, const Box& B, const double* __restrict__ logK,
+                                             double* __restrict__ K, const double* __restrict__ f,
+                                             const double* __restrict__ bcv, double beta,
+                                             float* __restrict__ fac, double* __restrict__ pbar,
+                                             double* __restrict__ ubar, double* __restrict__ pibar,
+                                             double tol, int max_refine, int* iters,
+                                             unsigned long long* resid, double* dsm, Gj3f& sm) {
+  Box3F F = carve3f<TS>(dsm, B, 1, 1, g.kc);
+  Box3& s = F.s;
+  load_box3<NW, true>(g, B, logK, beta, s);
+  part_k3<NW, TS>(g, B, s, K, sm.flag);
+  physical3<NW>(g, B, s, f, bcv, F.Bv);
+  scale3f<NW>(F);
+  start3f<NW, true>(F, 1);
+  float* Wg = fac + B.fac;
+  float wc[JC][R3];
+  factor3f<NW>(g, B, F, Wg, 1, sm, wc);
+  backward3f<NW>(F, sm, wc, Wg, 1);
+  update3f<NW>(F, 1);
+  double omega;
+  const int it = refine3f<NW>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
+  record3f(it, omega, iters, resid);
+  part_out3<NW>(g, B, s, beta, pbar, ubar, pibar);
+}
+
+// Steps 6-7 for one box: right-hand side from the state, FP32 solves with
+// the stored inverses (read once into the register cache), FP64
+// refinement, then p on Omega_i and Omega_i's Gamma fluxes.
+template <int NW, bool TS>
+__device__ __forceinline__ void smooth3f(const Geo& g, const Box& B, const double* __restrict__ K,
+                                         const double* __restrict__ f, const double* __restrict__ bcv,
+                                         double beta, const float* __restrict__ fac, double* p,
+                                         double* gflux, double tol, int max_refine, int* iters,
+                                         unsigned long long* resid, double* dsm, Gj3f& sm) {
+  Box3F F = carve3f<TS>(dsm, B, 1, 1, g.kc);
+  Box3& s = F.s;
+  load_box3<NW, false>(g, B, K, beta, s);
+  physical3<NW>(g, B, s, f, bcv, F.Bv);
+  bsync<NW>();
+  smooth_rhs3<NW>(g, B, s, p, gflux, beta, F.Bv);
+  scale3f<NW>(F);
+  start3f<NW, true>(F, 1);
+  const float* Wg = fac + B.fac;
+  float wc[JC][R3];
+  forward3f<NW, true>(F, sm, wc, Wg, 1);
+  backward3f<NW>(F, sm, wc, Wg, 1);
+  update3f<NW>(F, 1);
+  double omega;
+  const int it = refine3f<NW>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
+  record3f(it, omega, iters, resid);
+  smooth_out3<NW>(g, B, s, p, gflux, beta);
+}
+
+// Two boxes per CU (LDS of a c4 basis box about 61 KB): up to 256
+// registers per lane, the 128 of the plane cache among them.
+template <int NW, bool TS>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+k_basis3f(Geo g, const Box* __restrict__ boxes, const Seed* __restrict__ seeds, const double* __restrict__ logK,
+          double beta, float* __restrict__ fac, double* __restrict__ Pk, double* __restrict__ tr_u,
+          double* __restrict__ tr_phi, double* __restrict__ tr_beta, int factor_only, double tol,
+          int max_refine, int* iters, unsigned long long* resid, int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ Gj3f sm;
+  if (threadIdx.x == 0) sm.flag = 0;
+  bsync<NW>();
+  const Box B = boxes[blockIdx.x];
+  if (factor_only)
+    basis3f<NW, true, TS>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, tol, max_refine, iters,
+                          resid, dsm, sm);
+  else
+    basis3f<NW, false, TS>(g, B, seeds, logK, beta, fac, Pk, tr_u, tr_phi, tr_beta, tol, max_refine, iters,
+                           resid, dsm, sm);
+  bsync<NW>();
+  if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+template <int NW, bool TS>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+k_particular3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ logK, double* __restrict__ K,
+               const double* __restrict__ f, const double* __restrict__ bcv, double beta,
+               float* __restrict__ fac, double* __restrict__ pbar, double* __restrict__ ubar,
+               double* __restrict__ pibar, double tol, int max_refine, int* iters, unsigned long long* resid,
+               int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ Gj3f sm;
+  if (threadIdx.x == 0) sm.flag = 0;
+  bsync<NW>();
+  const Box B = boxes[blockIdx.x];
+  particular3f<NW, TS>(g, B, logK, K, f, bcv, beta, fac, pbar, ubar, pibar, tol, max_refine, iters, resid,
+                       dsm, sm);
+  bsync<NW>();
+  if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+template <int NW, bool TS>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+k_smooth3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ K, const double* __restrict__ f,
+           const double* __restrict__ bcv, double beta, const float* __restrict__ fac, double* __restrict__ p,
+           double* __restrict__ gflux, double tol, int max_refine, int* iters, unsigned long long* resid,
+           int* flags) {
+  extern __shared__ __align__(16) double dsm[];
+  __shared__ Gj3f sm;
+  if (threadIdx.x == 0) sm.flag = 0;
+  bsync<NW>();
+  const Box B = boxes[blockIdx.x];
+  smooth3f<NW, TS>(g, B, K, f, bcv, beta, fac, p, gflux, tol, max_refine, iters, resid, dsm, sm);
+  bsync<NW>();
+  if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
+}
+
+template <typename KF>
+hipError_t lds_attr3f(KF kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t box3f_lds_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc) {
+  return box3f_bytes(m0, m1, m2, nrhs, nbv, kc);
+}
+
+// waves per box, and the scalar or the tensor form of K
+#define MRCM_NW_SWITCH(nw, CALL)                   \
+  if (g.kc > 1) {                                  \
+    switch (nw) {                                  \
+      case 1: CALL(1, true); break;                \
+      case 2: CALL(2, true); break;                \
+      case 4: CALL(4, true); break;                \
+      default: return hipErrorInvalidValue;        \
+    }                                              \
+  } else {                                         \
+    switch (nw) {                                  \
+      case 1: CALL(1, false); break;               \
+      case 2: CALL(2, false); break;               \
+      case 4: CALL(4, false); break;               \
+      default: return hipErrorInvalidValue;        \
+    }                                              \
+  }
+
+hipError_t launch_basis3f(const Geo& g, const Box* boxes, int nbox, const Seed* seeds, const double* logK,
+                          double beta, float* fac32, double* Pk, double* tr_u, double* tr_phi,
+                          double* tr_beta, int factor_only, double tol, int max_refine, int* iters,
+                          unsigned long long* resid, int* flags, size_t lds, int nw, hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+#define MRCM_CALL(NW, TS)                                                                                   \
+  e = lds_attr3f(k_basis3f<NW, TS>, lds);                                                                   \
+  if (e != hipSuccess) return e;                                                                            \
+  hipLaunchKernelGGL((k_basis3f<NW, TS>), dim3(nbox), dim3(64 * NW), lds, s, g, boxes, seeds, logK, beta,   \
+                     fac32, Pk, tr_u, tr_phi, tr_beta, factor_only, tol, max_refine, iters, resid, flags)
+  MRCM_NW_SWITCH(nw, MRCM_CALL)
+#undef MRCM_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_particular3f(const Geo& g, const Box* boxes, int nbox, const double* logK, double* K,
+                               const double* f, const double* bcv, double beta, float* facp32,
+                               double* pbar, double* ubar, double* pibar, double tol, int max_refine,
+                               int* iters, unsigned long long* resid, int* flags, size_t lds, int nw,
+                               hipStream_t s) {
+  if (nbox <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+#define MRCM_CALL(NW, TS)                                                                                   \
+  e = lds_attr3f(k_particular3f<NW, TS>, lds);                                                              \
+  if (e != hipSuccess) return e;                                                                            \
+  hipLaunchKernelGGL((k_particular3f<NW, TS>), dim3(nbox), dim3(64 * NW), lds, s, g, boxes, logK, K, f,     \
+                     bcv, beta, facp32, pbar, ubar, pibar, tol, max_refine, iters, resid, flags)
+  MRCM_NW_SWITCH(nw, MRCM_CALL)
+#undef MRCM_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth3f(const Geo& g, const Box* boxes, int nmem, const double* K, const double* f,
+                           const double* bcv, double beta, const float* fac32, double* p, double* gflux,
+                           double tol, int max_refine, int* iters, unsigned long long* resid, int* flags,
+                           size_t lds, int nw, hipStream_t s) {
+  if (nmem <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+#define MRCM_CALL(NW, TS)                                                                                   \
+  e = lds_attr3f(k_smooth3f<NW, TS>, lds);                                                                  \
+  if (e != hipSuccess) return e;                                                                            \
+  hipLaunchKernelGGL((k_smooth3f<NW, TS>), dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv, beta,    \
+                     fac32, p, gflux, tol, max_refine, iters, resid, flags)
+  MRCM_NW_SWITCH(nw, MRCM_CALL)
+#undef MRCM_CALL
+  return hipGetLastError();
+}
+
+#undef MRCM_NW_SWITCH
+
+}  // namespace mrcm
