@@ -109,7 +109,7 @@ def parse():
     return ap.parse_args()
 
 
-DEFAULT_TOL = 1e-12  # refinement tolerance when --tol is not given
+DEFAULT_TOL = 1e-11
 
 
 def time_solves(wl, precision, steps, warmup, tol, persistent=False):
@@ -365,33 +365,39 @@ def band_bytes(dims, word=8):
 def smoothing_roofline(wl, form, phases, st):
     """Roofline of the smoothing kernel (one colour phase per launch) with
     the algorithmic bytes of the method: per sweep, every oversampled box's
-    band factor read once, plus (8 + 8 + 16 d) bytes per fine cell of state
-    (K, p and the face fluxes), spread over the 2^d colour phases."""
+    band factor read once (however many refinement solves use it), plus
+    (8 + 8 + 16 d) bytes per fine cell of state (K, p and the face fluxes),
+    spread over the 2^d colour phases."""
     bx = boxes(wl)
     word = 4 if form == "fp32_refine" else 8
     solves = max(st["refine_max_iters"], 1) if form == "fp32_refine" else 1
     n_launch = max(st["n_smooth_launches"], 1)
     phases_per_launch = max(st["n_smooth_phases"], 1) / n_launch
     t_launch = phases["ms_smooth"] / n_launch * 1e-3
-    factor = sum(band_bytes(d, word) for d, _, _ in bx) * solves
+    factor = sum(band_bytes(d, word) for d, _, _ in bx)
     state = (16 + 16 * wl.dim) * wl.ncells
     per_phase = (factor + state) / 2 ** wl.dim
     per_launch = per_phase * phases_per_launch
     achieved = per_launch / t_launch
     # what the kernel itself reads: the symmetric block inverses, stored as
-    # lower triangles (2-D FP64) or whole (FP32, and the 3-D plane blocks,
-    # read twice: forward and backward sweep)
+    # lower triangles (2-D FP64) or whole (2-D FP32, once per refinement
+    # solve; the 3-D plane blocks: FP64 read twice, forward and backward
+    # sweep; FP32 read once into registers, planes beyond the eighth once
+    # per sweep)
     stored = 0
     for dims, _, _ in bx:
         nb, nblk = block_cells(dims), dims[-1]
         if wl.dim == 3:
-            stored += (2 * nblk - 1) * nb * nb * word
+            if form == "fp32_refine":
+                stored += (nblk + max(0, nblk - 8) * (2 * solves - 1)) * nb * nb * word
+            else:
+                stored += (2 * nblk - 1) * nb * nb * word
             continue
         blk = nb * nb if form == "fp32_refine" else nb * (nb + 1) // 2
         stored += nblk * blk * word * solves
     kern = "k_smooth32" if form == "fp32_refine" else "k_smooth_w"
     if wl.dim == 3:
-        kern = "k_smooth3"
+        kern = "k_smooth3f" if form == "fp32_refine" else "k_smooth3"
     elif st["smooth_persistent"]:
         kern = "k_smooth_grid"
     return {"kernel": kern, "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
@@ -431,7 +437,7 @@ def local_roofline(wl, form, phases, st):
     peak = PEAK_FP32 if form == "fp32_refine" else PEAK_FP64
     kern = "k_local32" if form == "fp32_refine" else "k_local_w"
     if wl.dim == 3:
-        kern = "k_basis3"
+        kern = "k_basis3f" if form == "fp32_refine" else "k_basis3"
     return {"kernel": kern, "bound": "alu", "achieved": band / t_basis / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": band / t_basis / peak, "traffic": traffic(kern, wl),
             "band_flop_per_launch": band, "executed_flop_per_launch": flops,
@@ -568,6 +574,9 @@ def form_summary(wl, f, form, args):
         d["refine"] = {"tol": args.tol if args.tol is not None else DEFAULT_TOL,
                        "max_fp32_solves": f["stats"]["refine_max_iters"],
                        "max_backward_error": f["stats"]["refine_max_resid"]}
+        if wl.dim == 3:
+            d["smoothing_plane_inverses"] = ("held in registers across the refinement sweeps"
+                                             if f["stats"]["smooth_cached"] else "read by every sweep")
     if "err" in f:
         d["err_vs_oracle"] = f["err"]
     return d

@@ -34,7 +34,8 @@ class Stats(ctypes.Structure):
                 ("n_smooth_launches", ctypes.c_int), ("ms_basis_kernel", ctypes.c_double),
                 ("smooth_threads", ctypes.c_int), ("smooth_graph", ctypes.c_int),
                 ("ms_autotune", ctypes.c_double), ("n_smooth_phases", ctypes.c_int),
-                ("smooth_persistent", ctypes.c_int), ("interface_residual", ctypes.c_double)]
+                ("smooth_persistent", ctypes.c_int), ("interface_residual", ctypes.c_double),
+                ("smooth_cached", ctypes.c_int)]
 
 
 class Balance(ctypes.Structure):

@@ -140,6 +140,9 @@ struct mrcm_ctx {
   // smoothing execution: threads per box (0 = autotune on first use), the
   // chosen value, and the captured sweep graph
   int smooth_nt_req = 0, smooth_nt = 0;
+  // 3-D FP32 smoothing: plane inverses held in registers (1) or read per
+  // sweep (0), chosen by the autotuner
+  int smooth_cached = 1;
   bool use_graph = true;
   // one cooperative launch per mrcm_smooth call (FP64 wave kernels), with
   // at most persist_groups workgroups (0 = as many as fit)
@@ -1387,7 +1390,7 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
     if (c->prec == MRCM_FP32_REFINE && c->d3) {
       HIPCHK(c, launch_smooth3f(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv, c->beta_sm,
                                 own ? c->fac32s : c->fac32, p, gflux, c->tol, c->max_refine, c->d_iters,
-                                c->d_resid, c->flags, c->lds3f_smooth, c->nw3_box, s));
+                                c->d_resid, c->flags, c->lds3f_smooth, c->nw3_box, c->smooth_cached, s));
     } else if (c->prec == MRCM_FP32_REFINE) {
       HIPCHK(c, launch_smooth32_w(c->geo, c->d_obox_col + m0, m1 - m0, c->K, c->f, c->bcv,
                                   c->beta_sm, own ? c->fac32s : c->fac32, p, gflux, c->tol,
@@ -1412,10 +1415,12 @@ mrcm_status sweep(mrcm_ctx* c, hipStream_t s, int nt, double* p, double* gflux, 
 
 // Threads per box of the smoothing kernels: the requested value, or the
 // fastest of 64, 128 and 256 over timed sweeps on copies of the current
-// state (the variants give identical results).
+// state; for 3-D boxes in the FP32 form, whether a box holds its plane
+// inverses in registers (the variants give identical results).
 mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
   if (c->smooth_nt) return MRCM_OK;
-  if (c->smooth_nt_req || !c->wave) {
+  const bool f3 = c->d3 && c->prec == MRCM_FP32_REFINE;
+  if (!f3 && (c->smooth_nt_req || !c->wave)) {
     c->smooth_nt = c->smooth_nt_req ? c->smooth_nt_req : 256;
     return MRCM_OK;
   }
@@ -1426,8 +1431,11 @@ mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
   HIPCHK(c, hipMemcpyAsync(c->gflux_tune, c->gflux, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipEventRecord(c->ev[10], s));
   float best = 0.f;
-  int best_nt = 256;
-  for (int nt : {64, 128, 256}) {
+  int best_nt = 256, best_var = 1;
+  const std::vector<int> cand = f3 ? std::vector<int>{1, 0} : std::vector<int>{64, 128, 256};
+  for (int v : cand) {
+    const int nt = f3 ? 256 : v;
+    if (f3) c->smooth_cached = v;
     mrcm_status st = sweep(c, s, nt, c->p_tune, c->gflux_tune);  // warm-up
     if (st) return st;
     HIPCHK(c, hipEventRecord(c->ev[4], s));
@@ -1439,11 +1447,13 @@ mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
     HIPCHK(c, hipEventSynchronize(c->ev[5]));
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
-    if (nt == 64 || ms < best) {
+    if (v == cand[0] || ms < best) {
       best = ms;
       best_nt = nt;
+      best_var = v;
     }
   }
+  if (f3) c->smooth_cached = best_var;
   HIPCHK(c, hipEventRecord(c->ev[11], s));
   HIPCHK(c, hipEventSynchronize(c->ev[11]));
   float ms = 0.f;
@@ -1893,6 +1903,7 @@ mrcm_status mrcm_get_stats(mrcm_ctx* c, mrcm_stats* out) {
     out->ms_basis_kernel = ms;
   out->n_smooth_launches = c->n_smooth_launches;
   out->smooth_threads = c->smooth_nt;
+  out->smooth_cached = c->d3 && c->prec == MRCM_FP32_REFINE ? c->smooth_cached : 0;
   out->smooth_graph = c->use_graph ? 1 : 0;
   out->ms_autotune = c->ms_autotune;
   out->n_smooth_phases = c->n_smooth_phases;

@@ -234,14 +234,14 @@ __device__ __forceinline__ void wmul3(const Box3& s, Gj3& sm, int nb, int nrhs, 
         else Y[k * ystride + c] = y;
       }
     }
-    bsync<NW>();
+    lsync<NW>();
   } else {
     double* pt = partials3(sm);
     const int wv = wave3();
     for (int k0 = 0; k0 < nrhs; k0 += 4) {
       const int cnt = min(4, nrhs - k0);
       for (int kk = 0; kk < cnt; ++kk) pt[(kk * NW + wv) * P3 + c] = wdot3(w, s.Z + (k0 + kk) * P3);
-      bsync<NW>();
+      lsync<NW>();
       for (int e = threadIdx.x; e < cnt * P3; e += NT) {
         const int kk = e / P3, L = e % P3;
         double y = 0.0;
@@ -252,7 +252,7 @@ __device__ __forceinline__ void wmul3(const Box3& s, Gj3& sm, int nb, int nrhs, 
           else Y[(k0 + kk) * ystride + L] = y;
         }
       }
-      bsync<NW>();
+      lsync<NW>();
     }
   }
 }
@@ -270,7 +270,7 @@ __device__ __forceinline__ void fwd3(const Box3& s, Gj3& sm, int nb, int j, int 
     }
     s.Z[k * P3 + L] = v;
   }
-  bsync<NW>();
+  lsync<NW>();
   wmul3<NW, false>(s, sm, nb, nrhs, w, s.X + j * nb, s.nc);
 }
 
@@ -282,7 +282,7 @@ __device__ __forceinline__ void bwd3(const Box3& s, Gj3& sm, int nb, int j, int 
     const int k = e / P3, L = e % P3;
     s.Z[k * P3 + L] = L < nb ? s.Tz[j * nb + L] * s.X[k * s.nc + (j + 1) * nb + L] : 0.0;
   }
-  bsync<NW>();
+  lsync<NW>();
   wmul3<NW, true>(s, sm, nb, nrhs, w, s.X + j * nb, s.nc);
 }
 
@@ -323,13 +323,20 @@ __device__ __forceinline__ void factor3(const Geo& g, const Box& B, const Box3& 
   }
 }
 
-template <int NW>
+// PF: the next plane's inverse is loaded while the current one is applied
+template <int NW, bool PF>
 __device__ __forceinline__ void backward3(const Box3& s, Gj3& sm, const double* Wg, int nrhs) {
   const int nb = s.m0 * s.m1;
-  double w[R3];
+  double w[R3], wn[R3];
+  if (PF && s.m2 >= 2) load3(Wg + (long long)(s.m2 - 2) * nb * nb, nb, w);
   for (int j = s.m2 - 2; j >= 0; --j) {
-    load3(Wg + (long long)j * nb * nb, nb, w);
+    if (!PF) load3(Wg + (long long)j * nb * nb, nb, w);
+    if (PF && j > 0) load3(Wg + (long long)(j - 1) * nb * nb, nb, wn);
     bwd3<NW>(s, sm, nb, j, nrhs, w);
+    if (PF) {
+#pragma unroll
+      for (int ii = 0; ii < R3; ++ii) w[ii] = wn[ii];
+    }
   }
 }
 
@@ -352,7 +359,7 @@ __device__ __forceinline__ void basis3(const Geo& g, const Box& B, const Seed* _
   double* Wg = fac + B.fac;
   factor3<NW>(g, B, s, Wg, nrhs, sm);
   if (FO) return;
-  backward3<NW>(s, sm, Wg, nrhs);
+  backward3<NW, true>(s, sm, Wg, nrhs);
   basis_out3<NW>(g, B, s, seeds, beta, nrhs, Pk, tr_u, tr_phi, tr_beta);
 }
 
@@ -373,7 +380,7 @@ __device__ __forceinline__ void particular3(const Geo& g, const Box& B,
   bsync<NW>();
   double* Wg = fac + B.fac;
   factor3<NW>(g, B, s, Wg, 1, sm);
-  backward3<NW>(s, sm, Wg, 1);
+  backward3<NW, true>(s, sm, Wg, 1);
   part_out3<NW>(g, B, s, beta, pbar, ubar, pibar);
 }
 
@@ -398,7 +405,7 @@ __device__ __forceinline__ void smooth3(const Geo& g, const Box& B, const double
     load3(Wg + (long long)j * nb * nb, nb, w);
     fwd3<NW>(s, sm, nb, j, 1, w);
   }
-  backward3<NW>(s, sm, Wg, 1);
+  backward3<NW, false>(s, sm, Wg, 1);
   smooth_out3<NW>(g, B, s, p, gflux, beta);
 }
 

@@ -40,6 +40,22 @@ __device__ __forceinline__ void bsync() {
     __syncthreads();
   }
 }
+
+// The same for steps whose exchange between waves is LDS only (the sweep
+// steps): the fences order LDS accesses alone, so global loads issued
+// ahead (the next plane's inverse) stay in flight across the barrier.
+template <int NW>
+__device__ __forceinline__ void lsync() {
+  if constexpr (NW == 1) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  }
+}
+
 // LDS of one box.
 struct Box3 {
   double* Kt;  // (m0 + 2)(m1 + 2)(m2 + 2) permeabilities, one-cell halo

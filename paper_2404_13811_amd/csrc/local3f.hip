@@ -49,14 +49,14 @@ struct Box3F {
   double* Bv;   // ncell right-hand side (particular and smoothing boxes)
   float* Xf;    // nrhs x ncell: scaled residuals, then the FP32 corrections
   float* Tzf;   // ncell: scaled couplings to the next plane
-  float* Zf;    // nrhs x 64 staging of one block (16-byte aligned)
+  float* Zf;    // 2 x nrhs x 64: staged inputs of a sweep step (16-byte aligned)
 };
 
 __host__ __device__ inline size_t box3f_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc) {
   const size_t nc = (size_t)m0 * m1 * m2;
   const size_t d = kx3_doubles(kc, m0, m1, m2) + (size_t)(m0 + 2) * (m1 + 2) * (m2 + 2) + 2 * nc +
                    (size_t)nrhs * nc + nc + (size_t)nbv * nc;
-  const size_t f = (size_t)nrhs * nc + nc + (size_t)(nrhs < 1 ? 1 : nrhs) * P3 + 4;
+  const size_t f = (size_t)nrhs * nc + nc + 2 * (size_t)(nrhs < 1 ? 1 : nrhs) * P3 + 4;
   return d * sizeof(double) + f * sizeof(float) + 16;
 }
 
@@ -217,98 +217,140 @@ __device__ __forceinline__ void gj3f(int nb, Gj3f& sm, float w[R3]) {
   bsync<NW>();
 }
 
-// The lane's 16-term share of y = W z for z staged in LDS.
-__device__ __forceinline__ float wdot3f(const float w[R3], const float* z) {
-  const float* zw = z + R3 * wave3();
+// The sweeps use a second register layout of a plane inverse, row blocks:
+// lane L of wave v holds W_j[r][16q .. 16q + 15] with r = 16v + L / 4 and
+// q = L % 4, so y_r = (W_j z)_r is a 16-term dot product per lane summed
+// over the four lanes of a quad (DPP), with no exchange between waves.
+// Each step of a sweep reads the plane's staged input vector from LDS,
+// writes y into Xf and stages the next plane's input, then meets the other
+// waves at one barrier.  Rows and columns beyond the nb x nb block hold 0.
+__device__ __forceinline__ int rb_row() { return R3 * wave3() + (lane3() >> 2); }
+__device__ __forceinline__ int rb_col() { return R3 * (lane3() & 3); }
+
+__device__ __forceinline__ float quad_sum(float p) {
+  p += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0xB1, 0xF, 0xF, false));  // quad_perm(1,0,3,2)
+  p += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0x4E, 0xF, 0xF, false));  // quad_perm(2,3,0,1)
+  return p;
+}
+
+// The lane's row-block entries of a stored inverse (nb x nb, row-major).
+__device__ __forceinline__ void load_rb(const float* Wj, int nb, float wr[R3]) {
+  const int r = rb_row(), c0 = rb_col();
+  const float* src = Wj + r * nb + c0;
+  if (r < nb && c0 + R3 <= nb && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+#pragma unroll
+    for (int ii = 0; ii < R3; ii += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(src + ii);
+      wr[ii] = v.x;
+      wr[ii + 1] = v.y;
+      wr[ii + 2] = v.z;
+      wr[ii + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int ii = 0; ii < R3; ++ii) wr[ii] = (r < nb && c0 + ii < nb) ? src[ii] : 0.0f;
+  }
+}
+
+// Row blocks from the elimination layout (lane c: W[16v + ii][c]); both
+// layouts give wave v the rows 16v .. 16v + 15, so the exchange stays in
+// the wave: four rounds through a 16 x 16 staging tile T of the wave's own.
+__device__ __forceinline__ void gj_to_rb(const float w[R3], float wr[R3], float* T) {
+  const int c = lane3();
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    if ((c >> 4) == qq) {
+#pragma unroll
+      for (int ii = 0; ii < R3; ++ii) T[ii * R3 + (c & 15)] = w[ii];
+    }
+    bsync<1>();
+    if ((c & 3) == qq) {
+#pragma unroll
+      for (int ii = 0; ii < R3; ii += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(T + (c >> 2) * R3 + ii);
+        wr[ii] = v.x;
+        wr[ii + 1] = v.y;
+        wr[ii + 2] = v.z;
+        wr[ii + 3] = v.w;
+      }
+    }
+    bsync<1>();
+  }
+}
+
+__device__ __forceinline__ float dot16(const float wr[R3], const float* z) {
   float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
   for (int ii = 0; ii < R3; ii += 4) {
-    const float4 zz = *reinterpret_cast<const float4*>(zw + ii);
-    a0 = fmaf(w[ii], zz.x, a0);
-    a1 = fmaf(w[ii + 1], zz.y, a1);
-    a0 = fmaf(w[ii + 2], zz.z, a0);
-    a1 = fmaf(w[ii + 3], zz.w, a1);
+    const float4 zz = *reinterpret_cast<const float4*>(z + ii);
+    a0 = fmaf(wr[ii], zz.x, a0);
+    a1 = fmaf(wr[ii + 1], zz.y, a1);
+    a0 = fmaf(wr[ii + 2], zz.z, a0);
+    a1 = fmaf(wr[ii + 3], zz.w, a1);
   }
   return a0 + a1;
 }
 
-// Y[k][c] (+)= (W Z_k)[c] for the nrhs vectors staged in Zf; the waves'
-// partial sums added through LDS in a fixed order, four vectors at a time.
-template <int NW, bool ACC>
-__device__ __forceinline__ void wmul3f(const Box3F& F, Gj3f& sm, int nb, int nrhs, const float w[R3],
-                                       float* Y, int ystride) {
-  constexpr int NT = 64 * NW;
-  const int c = lane3();
-  if constexpr (NW == 1) {
-    for (int k = 0; k < nrhs; ++k) {
-      const float y = wdot3f(w, F.Zf + k * P3);
-      if (c < nb) {
-        if (ACC) Y[k * ystride + c] += y;
-        else Y[k * ystride + c] = y;
-      }
-    }
-    bsync<NW>();
-  } else {
-    float* pt = partials3f(sm);
-    const int wv = wave3();
-    for (int k0 = 0; k0 < nrhs; k0 += 4) {
-      const int cnt = min(4, nrhs - k0);
-      for (int kk = 0; kk < cnt; ++kk) pt[(kk * NW + wv) * P3 + c] = wdot3f(w, F.Zf + (k0 + kk) * P3);
-      bsync<NW>();
-      for (int e = threadIdx.x; e < cnt * P3; e += NT) {
-        const int kk = e / P3, L = e % P3;
-        float y = 0.0f;
-#pragma unroll
-        for (int u = 0; u < NW; ++u) y += pt[(kk * NW + u) * P3 + L];
-        if (L < nb) {
-          if (ACC) Y[(k0 + kk) * ystride + L] += y;
-          else Y[(k0 + kk) * ystride + L] = y;
-        }
-      }
-      bsync<NW>();
-    }
-  }
-}
+// Staged inputs of plane j: Zb + (j & 1) * nrhs * 64 (two alternating
+// buffers; a step reads one and writes the other).
+__device__ __forceinline__ float* zbuf(const Box3F& F, int j, int nrhs) { return F.Zf + (j & 1) * nrhs * P3; }
 
-// Forward step of block j on the scaled vectors in Xf: z_j = W_j (r_j +
-// t_{j-1} z_{j-1}).
+// Input of plane 0 of a forward sweep from Xf (the scaled right-hand sides).
 template <int NW>
-__device__ __forceinline__ void fwd3f(const Box3F& F, Gj3f& sm, int nb, int j, int nrhs, const float w[R3]) {
-  constexpr int NT = 64 * NW;
-  const int nc = F.s.nc;
-  for (int e = threadIdx.x; e < nrhs * P3; e += NT) {
-    const int k = e / P3, L = e % P3;
-    float v = 0.0f;
-    if (L < nb) {
-      v = F.Xf[k * nc + j * nb + L];
-      if (j > 0) v = fmaf(F.Tzf[(j - 1) * nb + L], F.Xf[k * nc + (j - 1) * nb + L], v);
-    }
-    F.Zf[k * P3 + L] = v;
+__device__ __forceinline__ void stage0_rb(const Box3F& F, int nb, int nrhs) {
+  for (int e = threadIdx.x; e < nrhs * P3; e += 64 * NW) {
+    const int k = e / P3, i = e % P3;
+    F.Zf[e] = i < nb ? F.Xf[k * F.s.nc + i] : 0.0f;
   }
-  bsync<NW>();
-  wmul3f<NW, false>(F, sm, nb, nrhs, w, F.Xf + j * nb, nc);
+  lsync<NW>();
 }
 
-// Backward step of block j: x_j += W_j (t_j .* x_{j+1}).
+// Forward step of plane j: z_j = W_j (r_j + t_{j-1} z_{j-1}) into Xf, and
+// the next plane's input r_{j+1} + t_j z_j, or on the last plane the input
+// t_{j-1} x_j of the backward sweep's first plane (x_j = z_j there).
 template <int NW>
-__device__ __forceinline__ void bwd3f(const Box3F& F, Gj3f& sm, int nb, int j, int nrhs, const float w[R3]) {
-  constexpr int NT = 64 * NW;
-  const int nc = F.s.nc;
-  for (int e = threadIdx.x; e < nrhs * P3; e += NT) {
-    const int k = e / P3, L = e % P3;
-    F.Zf[k * P3 + L] = L < nb ? F.Tzf[j * nb + L] * F.Xf[k * nc + (j + 1) * nb + L] : 0.0f;
+__device__ __forceinline__ void fwd_rb(const Box3F& F, int nb, int j, int nrhs, const float wr[R3]) {
+  const int r = rb_row(), c0 = rb_col(), nc = F.s.nc, m2 = F.s.m2;
+  const bool last = j == m2 - 1;
+  const float* zin = zbuf(F, j, nrhs);
+  float* zout = zbuf(F, j + 1, nrhs);
+  for (int k = 0; k < nrhs; ++k) {
+    float y = c0 < nb ? dot16(wr, zin + k * P3 + c0) : 0.0f;
+    y = quad_sum(y);
+    if (c0 == 0 && r < P3) {
+      float zn = 0.0f;
+      if (r < nb) {
+        F.Xf[k * nc + j * nb + r] = y;
+        if (!last) zn = fmaf(F.Tzf[j * nb + r], y, F.Xf[k * nc + (j + 1) * nb + r]);
+        else if (j > 0) zn = F.Tzf[(j - 1) * nb + r] * y;
+      }
+      zout[k * P3 + r] = zn;
+    }
   }
-  bsync<NW>();
-  wmul3f<NW, true>(F, sm, nb, nrhs, w, F.Xf + j * nb, nc);
+  lsync<NW>();
 }
 
-__device__ __forceinline__ void load3f(const float* Wj, int nb, float w[R3]) {
-  const int c = lane3(), r0 = R3 * wave3();
-#pragma unroll
-  for (int ii = 0; ii < R3; ++ii) {
-    const int i = r0 + ii;
-    w[ii] = (i < nb && c < nb) ? Wj[i * nb + c] : (i == c ? 1.0f : 0.0f);
+// Backward step of plane j: x_j = z_j + W_j (t_j .* x_{j+1}) into Xf, and
+// the input t_{j-1} x_j of plane j - 1.
+template <int NW>
+__device__ __forceinline__ void bwd_rb(const Box3F& F, int nb, int j, int nrhs, const float wr[R3]) {
+  const int r = rb_row(), c0 = rb_col(), nc = F.s.nc;
+  const float* zin = zbuf(F, j, nrhs);
+  float* zout = zbuf(F, j + 1, nrhs);
+  for (int k = 0; k < nrhs; ++k) {
+    float y = c0 < nb ? dot16(wr, zin + k * P3 + c0) : 0.0f;
+    y = quad_sum(y);
+    if (c0 == 0 && r < P3) {
+      float zn = 0.0f;
+      if (r < nb) {
+        const float x = F.Xf[k * nc + j * nb + r] + y;
+        F.Xf[k * nc + j * nb + r] = x;
+        if (j > 0) zn = F.Tzf[(j - 1) * nb + r] * x;
+      }
+      zout[k * P3 + r] = zn;
+    }
   }
+  lsync<NW>();
 }
 
 __device__ __forceinline__ void store3f(float* Wj, int nb, const float w[R3]) {
@@ -320,10 +362,10 @@ __device__ __forceinline__ void store3f(float* Wj, int nb, const float w[R3]) {
   }
 }
 
-// Register cache of the plane inverses.  Slots are addressed with
-// compile-time indices only: the sweeps run their first JC planes as an
-// unrolled loop, and a plane formed at a runtime index is written into its
-// slot by selects (a conditional store per slot would be merged into a
+// Register cache of the plane inverses (row blocks).  Slots are addressed
+// with compile-time indices only: the sweeps run their first JC planes as
+// an unrolled loop, and a plane formed at a runtime index is written into
+// its slot by selects (a conditional store per slot would be merged into a
 // store through a selected address, which keeps the cache in scratch
 // memory).
 __device__ __forceinline__ void cclear(float wc[JC][R3]) {
@@ -341,11 +383,13 @@ __device__ __forceinline__ void cput(float wc[JC][R3], int j, const float w[R3])
 }
 
 // Factor of the box fused with the forward sweep of the nrhs scaled
-// right-hand sides in Xf; inverses to Wg and to the register cache.
+// right-hand sides in Xf (plane 0's input staged); inverses to Wg and, as
+// row blocks, to the register cache.
 template <int NW>
 __device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F& F, float* Wg, int nrhs,
                                          Gj3f& sm, float wc[JC][R3]) {
   const int nb = F.s.m0 * F.s.m1;
+  float* T = partials3f(sm) + R3 * R3 * wave3();
   float w[R3];
 #pragma unroll
   for (int i = 0; i < R3; ++i) w[i] = 0.0f;
@@ -354,50 +398,59 @@ __device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F
     build3f(g, B, F, j, w);
     gj3f<NW>(nb, sm, w);
     store3f(Wg + (long long)j * nb * nb, nb, w);
-    cput(wc, j, w);
-    if (nrhs > 0) fwd3f<NW>(F, sm, nb, j, nrhs, w);
+    if (nrhs > 0) {
+      // the pivot buffers are free until the next plane's elimination,
+      // which starts after the forward step's barrier
+      float wr[R3];
+      gj_to_rb(w, wr, T);
+      cput(wc, j, wr);
+      fwd_rb<NW>(F, nb, j, nrhs, wr);
+    }
   }
 }
 
-template <int NW>
-__device__ __forceinline__ void backward3f(const Box3F& F, Gj3f& sm, const float wc[JC][R3], const float* Wg,
-                                           int nrhs) {
+// JCN: planes taken from the register cache (JC, or 0: every plane read
+// from the stored inverses).
+template <int NW, int JCN = JC>
+__device__ __forceinline__ void backward3f(const Box3F& F, const float wc[JC][R3], const float* Wg, int nrhs) {
   const int nb = F.s.m0 * F.s.m1, m2 = F.s.m2;
-  float w[R3];
-  for (int j = m2 - 2; j >= JC; --j) {
-    load3f(Wg + (long long)j * nb * nb, nb, w);
-    bwd3f<NW>(F, sm, nb, j, nrhs, w);
+  float wr[R3];
+  for (int j = m2 - 2; j >= JCN; --j) {
+    load_rb(Wg + (long long)j * nb * nb, nb, wr);
+    bwd_rb<NW>(F, nb, j, nrhs, wr);
   }
 #pragma unroll
-  for (int j = JC - 1; j >= 0; --j)
-    if (j <= m2 - 2) bwd3f<NW>(F, sm, nb, j, nrhs, wc[j]);
+  for (int j = JCN - 1; j >= 0; --j)
+    if (j <= m2 - 2) bwd_rb<NW>(F, nb, j, nrhs, wc[j]);
 }
 
 // Forward sweep with the cached inverses (LOAD: the cache filled from the
-// stored inverses on the way).
-template <int NW, bool LOAD>
-__device__ __forceinline__ void forward3f(const Box3F& F, Gj3f& sm, float wc[JC][R3], const float* Wg,
-                                          int nrhs) {
+// stored inverses on the way); plane 0's input staged.
+// Filling the cache, loads run one plane ahead of the plane being applied
+// (into the next slot).
+template <int NW, bool LOAD, int JCN = JC>
+__device__ __forceinline__ void forward3f(const Box3F& F, float wc[JC][R3], const float* Wg, int nrhs) {
   const int nb = F.s.m0 * F.s.m1, m2 = F.s.m2;
+  if (LOAD && JCN > 0 && m2 > 0) load_rb(Wg, nb, wc[0]);
 #pragma unroll
-  for (int j = 0; j < JC; ++j)
+  for (int j = 0; j < JCN; ++j)
     if (j < m2) {
-      if (LOAD) load3f(Wg + (long long)j * nb * nb, nb, wc[j]);
-      fwd3f<NW>(F, sm, nb, j, nrhs, wc[j]);
+      if (LOAD && j + 1 < JCN && j + 1 < m2) load_rb(Wg + (long long)(j + 1) * nb * nb, nb, wc[j + 1]);
+      fwd_rb<NW>(F, nb, j, nrhs, wc[j]);
     }
-  float w[R3];
-  for (int j = JC; j < m2; ++j) {
-    load3f(Wg + (long long)j * nb * nb, nb, w);
-    fwd3f<NW>(F, sm, nb, j, nrhs, w);
+  float wr[R3];
+  for (int j = JCN; j < m2; ++j) {
+    load_rb(Wg + (long long)j * nb * nb, nb, wr);
+    fwd_rb<NW>(F, nb, j, nrhs, wr);
   }
 }
 
 // Xf <- A^^-1 Xf with the cached inverses.
-template <int NW>
-__device__ __forceinline__ void solve3f(const Box3F& F, Gj3f& sm, float wc[JC][R3], const float* Wg,
-                                        int nrhs) {
-  forward3f<NW, false>(F, sm, wc, Wg, nrhs);
-  backward3f<NW>(F, sm, wc, Wg, nrhs);
+template <int NW, int JCN = JC>
+__device__ __forceinline__ void solve3f(const Box3F& F, float wc[JC][R3], const float* Wg, int nrhs) {
+  stage0_rb<NW>(F, F.s.m0 * F.s.m1, nrhs);
+  forward3f<NW, false, JCN>(F, wc, Wg, nrhs);
+  backward3f<NW, JCN>(F, wc, Wg, nrhs);
 }
 
 // x += D^-1/2 (FP32 correction), for the nrhs solutions.
@@ -465,7 +518,7 @@ __device__ __forceinline__ double resid3f(const Geo& g, const Box& B, const Box3
 
 // Refinement after the first FP32 solve (x = D^-1/2 z already in s.X);
 // returns the number of FP32 solves, the final backward error in omega.
-template <int NW>
+template <int NW, int JCN = JC>
 __device__ __forceinline__ int refine3f(const Geo& g, const Box& B, const Box3F& F, const float* Wg,
                                         const Seed* __restrict__ seeds, double beta, int nrhs, double tol,
                                         int max_refine, Gj3f& sm, float wc[JC][R3], double& omega) {
@@ -477,7 +530,7 @@ __device__ __forceinline__ int refine3f(const Geo& g, const Box& B, const Box3F&
       if (threadIdx.x == 0) atomicOr(&sm.flag, kFlagNoConv);
       break;
     }
-    solve3f<NW>(F, sm, wc, Wg, nrhs);
+    solve3f<NW, JCN>(F, wc, Wg, nrhs);
     update3f<NW>(F, nrhs);
     ++it;
   }
@@ -523,11 +576,12 @@ __device__ __forceinline__ void basis3f(const Geo& g, const Box& B, const Seed* 
   seed_rhs3<NW>(g, B, s, seeds, beta, nrhs, s.X);
   bsync<NW>();
   start3f<NW, false>(F, nrhs);
+  stage0_rb<NW>(F, s.m0 * s.m1, nrhs);
   float* Wg = fac + B.fac;
   float wc[JC][R3];
   factor3f<NW>(g, B, F, Wg, nrhs, sm, wc);
   if (FO) return;
-  backward3f<NW>(F, sm, wc, Wg, nrhs);
+  backward3f<NW>(F, wc, Wg, nrhs);
   update3f<NW>(F, nrhs);
   double omega;
   const int it = refine3f<NW>(g, B, F, Wg, seeds, beta, nrhs, tol, max_refine, sm, wc, omega);
@@ -551,10 +605,11 @@ __device__ __forceinline__ void particular3f(const Geo& g, const Box& B, const d
   physical3<NW>(g, B, s, f, bcv, F.Bv);
   scale3f<NW>(F);
   start3f<NW, true>(F, 1);
+  stage0_rb<NW>(F, s.m0 * s.m1, 1);
   float* Wg = fac + B.fac;
   float wc[JC][R3];
   factor3f<NW>(g, B, F, Wg, 1, sm, wc);
-  backward3f<NW>(F, sm, wc, Wg, 1);
+  backward3f<NW>(F, wc, Wg, 1);
   update3f<NW>(F, 1);
   double omega;
   const int it = refine3f<NW>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
@@ -565,7 +620,7 @@ __device__ __forceinline__ void particular3f(const Geo& g, const Box& B, const d
 // Steps 6-7 for one box: right-hand side from the state, FP32 solves with
 // the stored inverses (read once into the register cache), FP64
 // refinement, then p on Omega_i and Omega_i's Gamma fluxes.
-template <int NW, bool TS>
+template <int NW, bool TS, int JCN>
 __device__ __forceinline__ void smooth3f(const Geo& g, const Box& B, const double* __restrict__ K,
                                          const double* __restrict__ f, const double* __restrict__ bcv,
                                          double beta, const float* __restrict__ fac, double* p,
@@ -579,13 +634,14 @@ __device__ __forceinline__ void smooth3f(const Geo& g, const Box& B, const doubl
   smooth_rhs3<NW>(g, B, s, p, gflux, beta, F.Bv);
   scale3f<NW>(F);
   start3f<NW, true>(F, 1);
+  stage0_rb<NW>(F, s.m0 * s.m1, 1);
   const float* Wg = fac + B.fac;
   float wc[JC][R3];
-  forward3f<NW, true>(F, sm, wc, Wg, 1);
-  backward3f<NW>(F, sm, wc, Wg, 1);
+  forward3f<NW, true, JCN>(F, wc, Wg, 1);
+  backward3f<NW, JCN>(F, wc, Wg, 1);
   update3f<NW>(F, 1);
   double omega;
-  const int it = refine3f<NW>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
+  const int it = refine3f<NW, JCN>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
   record3f(it, omega, iters, resid);
   smooth_out3<NW>(g, B, s, p, gflux, beta);
 }
@@ -631,8 +687,11 @@ k_particular3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ 
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-template <int NW, bool TS>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+// JCN = JC: the plane inverses read once per solve into registers (two
+// boxes per CU); JCN = 0: read from memory by every sweep, at up to four
+// boxes per CU (LDS of a c4 smoothing box about 33 KB).
+template <int NW, bool TS, int JCN>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(JCN ? 2 : 4)))
 k_smooth3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ K, const double* __restrict__ f,
            const double* __restrict__ bcv, double beta, const float* __restrict__ fac, double* __restrict__ p,
            double* __restrict__ gflux, double tol, int max_refine, int* iters, unsigned long long* resid,
@@ -642,7 +701,7 @@ k_smooth3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ K, c
   if (threadIdx.x == 0) sm.flag = 0;
   bsync<NW>();
   const Box B = boxes[blockIdx.x];
-  smooth3f<NW, TS>(g, B, K, f, bcv, beta, fac, p, gflux, tol, max_refine, iters, resid, dsm, sm);
+  smooth3f<NW, TS, JCN>(g, B, K, f, bcv, beta, fac, p, gflux, tol, max_refine, iters, resid, dsm, sm);
   bsync<NW>();
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
@@ -714,16 +773,23 @@ hipError_t launch_particular3f(const Geo& g, const Box* boxes, int nbox, const d
 hipError_t launch_smooth3f(const Geo& g, const Box* boxes, int nmem, const double* K, const double* f,
                            const double* bcv, double beta, const float* fac32, double* p, double* gflux,
                            double tol, int max_refine, int* iters, unsigned long long* resid, int* flags,
-                           size_t lds, int nw, hipStream_t s) {
+                           size_t lds, int nw, int cached, hipStream_t s) {
   if (nmem <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
-#define MRCM_CALL(NW, TS)                                                                                   \
-  e = lds_attr3f(k_smooth3f<NW, TS>, lds);                                                                  \
+#define MRCM_CALL1(NW, TS, JCN)                                                                             \
+  e = lds_attr3f(k_smooth3f<NW, TS, JCN>, lds);                                                             \
   if (e != hipSuccess) return e;                                                                            \
-  hipLaunchKernelGGL((k_smooth3f<NW, TS>), dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv, beta,    \
-                     fac32, p, gflux, tol, max_refine, iters, resid, flags)
+  hipLaunchKernelGGL((k_smooth3f<NW, TS, JCN>), dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv,     \
+                     beta, fac32, p, gflux, tol, max_refine, iters, resid, flags)
+#define MRCM_CALL(NW, TS)          \
+  if (cached) {                    \
+    MRCM_CALL1(NW, TS, JC);        \
+  } else {                         \
+    MRCM_CALL1(NW, TS, 0);         \
+  }
   MRCM_NW_SWITCH(nw, MRCM_CALL)
 #undef MRCM_CALL
+#undef MRCM_CALL1
   return hipGetLastError();
 }
 

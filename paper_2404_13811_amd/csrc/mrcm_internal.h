@@ -214,7 +214,8 @@ hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double
 // solve to the componentwise backward error tol (at most max_refine + 1
 // FP32 solves; the most taken and the largest final error to iters and
 // resid).  LDS bytes of a box with nrhs solutions and nbv FP64 right-hand
-// sides stored.
+// sides stored.  Smoothing: cached = 1 holds a box's plane inverses in
+// registers across its refinement sweeps, 0 reads them for every sweep.
 size_t box3f_lds_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc);
 hipError_t launch_basis3f(const Geo& g, const Box* boxes, int nbox, const Seed* seeds, const double* logK,
                           double beta, float* fac32, double* Pk, double* tr_u, double* tr_phi,
@@ -228,7 +229,7 @@ hipError_t launch_particular3f(const Geo& g, const Box* boxes, int nbox, const d
 hipError_t launch_smooth3f(const Geo& g, const Box* boxes, int nmem, const double* K, const double* f,
                            const double* bcv, double beta, const float* fac32, double* p, double* gflux,
                            double tol, int max_refine, int* iters, unsigned long long* resid, int* flags,
-                           size_t lds, int nw, hipStream_t s);
+                           size_t lds, int nw, int cached, hipStream_t s);
 
 // FP32 factors with FP64 iterative refinement (local_wave32.hip)
 size_t wave32_lds_bytes(int m0, int m1, int nrhs, int nbrhs, int kc);
