@@ -479,33 +479,41 @@ __device__ __forceinline__ double resid3f(const Geo& g, const Box& B, const Box3
   const Box3& s = F.s;
   const int nc = s.nc, m0 = s.m0, m1 = s.m1, m2 = s.m2, nb = m0 * m1;
   double om = 0.0;
-  for (int e = threadIdx.x; e < nrhs * nc; e += NT) {
-    const int k = e / nc, loc = e - k * nc;
+  // the couplings of a cell once, for all its right-hand sides
+  for (int loc = threadIdx.x; loc < nc; loc += NT) {
     const int xl = loc % m0, yl = (loc / m0) % m1, j = loc / nb, a = loc - j * nb;
-    const double* x = s.X + (size_t)k * nc;
-    double bv;
-    if (seeds) {
-      const Seed sd = seeds[B.seed0 + k];
-      const int c[3] = {B.lo[0] + xl, B.lo[1] + yl, B.lo[2] + j};
-      const int sa = sd.side >> 1;
-      const bool on = pick3(c, sa) == ((sd.side & 1) ? pick3(B.hi, sa) - 1 : pick3(B.lo, sa));
-      bv = on ? seed_face_b3(g, B, s, sd, beta, c) : 0.0;
-    } else {
-      bv = F.Bv[loc];
+    const double dg = s.Dg[loc], sdl = F.sd[loc];
+    const double txm = xl > 0 ? tplane(g, B, s, j, a - 1, 0) : 0.0;
+    const double txp = xl + 1 < m0 ? tplane(g, B, s, j, a, 0) : 0.0;
+    const double tym = yl > 0 ? tplane(g, B, s, j, a - m0, 1) : 0.0;
+    const double typ = yl + 1 < m1 ? tplane(g, B, s, j, a, 1) : 0.0;
+    const double tzm = j > 0 ? s.Tz[loc - nb] : 0.0;
+    const double tzp = j + 1 < m2 ? s.Tz[loc] : 0.0;
+    const int c[3] = {B.lo[0] + xl, B.lo[1] + yl, B.lo[2] + j};
+    for (int k = 0; k < nrhs; ++k) {
+      const double* x = s.X + (size_t)k * nc;
+      double bv;
+      if (seeds) {
+        const Seed sd = seeds[B.seed0 + k];
+        const int sa = sd.side >> 1;
+        const bool on = pick3(c, sa) == ((sd.side & 1) ? pick3(B.hi, sa) - 1 : pick3(B.lo, sa));
+        bv = on ? seed_face_b3(g, B, s, sd, beta, c) : 0.0;
+      } else {
+        bv = F.Bv[loc];
+      }
+      double ax = dg * x[loc], aa = fabs(ax), t;
+      if (xl > 0) { t = txm * x[loc - 1]; ax -= t; aa += fabs(t); }
+      if (xl + 1 < m0) { t = txp * x[loc + 1]; ax -= t; aa += fabs(t); }
+      if (yl > 0) { t = tym * x[loc - m0]; ax -= t; aa += fabs(t); }
+      if (yl + 1 < m1) { t = typ * x[loc + m0]; ax -= t; aa += fabs(t); }
+      if (j > 0) { t = tzm * x[loc - nb]; ax -= t; aa += fabs(t); }
+      if (j + 1 < m2) { t = tzp * x[loc + nb]; ax -= t; aa += fabs(t); }
+      const double r = bv - ax;
+      const double den = aa + fabs(bv);
+      if (!(r - r == 0.0 && den - den == 0.0)) om = INFINITY;
+      else if (den > 0.0) om = fmax(om, fabs(r) / den);
+      F.Xf[k * nc + loc] = (float)(sdl * r);
     }
-    const double xc = x[loc];
-    double ax = s.Dg[loc] * xc, aa = fabs(ax), t;
-    if (xl > 0) { t = tplane(g, B, s, j, a - 1, 0) * x[loc - 1]; ax -= t; aa += fabs(t); }
-    if (xl + 1 < m0) { t = tplane(g, B, s, j, a, 0) * x[loc + 1]; ax -= t; aa += fabs(t); }
-    if (yl > 0) { t = tplane(g, B, s, j, a - m0, 1) * x[loc - m0]; ax -= t; aa += fabs(t); }
-    if (yl + 1 < m1) { t = tplane(g, B, s, j, a, 1) * x[loc + m0]; ax -= t; aa += fabs(t); }
-    if (j > 0) { t = s.Tz[loc - nb] * x[loc - nb]; ax -= t; aa += fabs(t); }
-    if (j + 1 < m2) { t = s.Tz[loc] * x[loc + nb]; ax -= t; aa += fabs(t); }
-    const double r = bv - ax;
-    const double den = aa + fabs(bv);
-    if (!(r - r == 0.0 && den - den == 0.0)) om = INFINITY;
-    else if (den > 0.0) om = fmax(om, fabs(r) / den);
-    F.Xf[e] = (float)(F.sd[loc] * r);
   }
   om = wave_max3(om);
   if (lane3() == 0) sm.red[wave3()] = om;
