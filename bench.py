@@ -592,8 +592,7 @@ def form_summary(wl, f, form, args):
                        "max_fp32_solves": f["stats"]["refine_max_iters"],
                        "max_backward_error": f["stats"]["refine_max_resid"]}
         if wl.dim == 3:
-            d["smoothing_plane_inverses"] = ("held in registers across the refinement sweeps"
-                                             if f["stats"]["smooth_cached"] else "read by every sweep")
+            d["smoothing_planes_in_registers"] = f["stats"]["smooth_cached"]
     if "err" in f:
         d["err_vs_oracle"] = f["err"]
     return d

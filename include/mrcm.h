@@ -135,11 +135,11 @@ typedef struct {
                               state; above the check tolerance (default 1e-5,
                               mrcm_set_interface_check) the solve raises
                               MRCM_ESINGULAR.  0 if no interface.            */
-  int smooth_cached;       /* 3-D boxes in the FP32 form: 1 when a smoothing
-                              box holds its plane inverses in registers
-                              across its refinement sweeps, 0 when every sweep
-                              reads them from memory (the faster of the two,
-                              timed by the autotuner)                         */
+  int smooth_cached;       /* 3-D boxes in the FP32 form: the planes (8, 4 or
+                              0) whose inverses a smoothing box holds in
+                              registers across its refinement sweeps; the
+                              others are read from memory by every sweep
+                              (the fastest variant, timed by the autotuner)   */
 } mrcm_stats;
 
 /* Conservation and continuity measures of the current solution (Section 5's

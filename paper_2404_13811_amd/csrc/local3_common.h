@@ -56,6 +56,158 @@ __device__ __forceinline__ void lsync() {
   }
 }
 
+// Row-block sweeps (both precision forms).  A second register layout of a
+// plane inverse: lane L of wave v holds W_j[r][16q .. 16q + 15] with
+// r = 16v + L / 4 and q = L % 4, so y_r = (W_j z)_r is a 16-term dot
+// product per lane summed over the four lanes of a quad (DPP), with no
+// exchange between waves.  Each step of a sweep reads the plane's staged
+// input vector from LDS, writes y into the solution vectors and stages the
+// next plane's input, then meets the other waves at one barrier (LDS
+// only).  Rows and columns beyond the nb x nb block hold 0.
+__device__ __forceinline__ int rb_row() { return R3 * wave3() + (lane3() >> 2); }
+__device__ __forceinline__ int rb_col() { return R3 * (lane3() & 3); }
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// sum over the quad: quad_perm(1,0,3,2) then quad_perm(2,3,0,1); every
+// lane of the quad gets the same value
+__device__ __forceinline__ float quad_sum(float p) {
+  p += __int_as_float(dpp_i<0xB1>(__float_as_int(p)));
+  p += __int_as_float(dpp_i<0x4E>(__float_as_int(p)));
+  return p;
+}
+
+__device__ __forceinline__ double quad_sum(double p) {
+  p += __hiloint2double(dpp_i<0xB1>(__double2hiint(p)), dpp_i<0xB1>(__double2loint(p)));
+  p += __hiloint2double(dpp_i<0x4E>(__double2hiint(p)), dpp_i<0x4E>(__double2loint(p)));
+  return p;
+}
+
+// 16-byte loads of four floats or two doubles
+template <typename T>
+__device__ __forceinline__ void ld16(const T* src, T* dst) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src);
+    dst[0] = v.x;
+    dst[1] = v.y;
+    dst[2] = v.z;
+    dst[3] = v.w;
+  } else {
+    const double2 v = *reinterpret_cast<const double2*>(src);
+    dst[0] = v.x;
+    dst[1] = v.y;
+  }
+}
+
+// The lane's row-block entries of a stored inverse (nb x nb, row-major).
+template <typename T>
+__device__ __forceinline__ void load_rb(const T* Wj, int nb, T wr[R3]) {
+  constexpr int V = 16 / sizeof(T);
+  const int r = rb_row(), c0 = rb_col();
+  const T* src = Wj + r * nb + c0;
+  if (r < nb && c0 + R3 <= nb && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+#pragma unroll
+    for (int ii = 0; ii < R3; ii += V) ld16(src + ii, wr + ii);
+  } else {
+#pragma unroll
+    for (int ii = 0; ii < R3; ++ii) wr[ii] = (r < nb && c0 + ii < nb) ? src[ii] : T(0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T dot16(const T wr[R3], const T* z) {
+  constexpr int V = 16 / sizeof(T);
+  T a0 = T(0), a1 = T(0);
+#pragma unroll
+  for (int ii = 0; ii < R3; ii += V) {
+    T zz[V];
+    ld16(z + ii, zz);
+#pragma unroll
+    for (int u = 0; u < V; u += 2) {
+      a0 = fma(wr[ii + u], zz[u], a0);
+      a1 = fma(wr[ii + u + 1], zz[u + 1], a1);
+    }
+  }
+  return a0 + a1;
+}
+
+// The vectors a row-block sweep works on: X (nrhs x nc, solved in place),
+// the plane couplings Tz (ncell) and the staged inputs Z (2 x nrhs x 64,
+// 16-byte aligned).
+template <typename T>
+struct RbSweep {
+  T* X;
+  const T* Tz;
+  T* Z;
+  int nc, m2, nrhs;
+};
+
+// Staged inputs of plane j: two alternating buffers; a step reads one and
+// writes the other.
+template <typename T>
+__device__ __forceinline__ T* zbuf(const RbSweep<T>& v, int j) { return v.Z + (j & 1) * v.nrhs * P3; }
+
+// Input of plane 0 of a forward sweep from X (the right-hand sides).
+template <int NW, typename T>
+__device__ __forceinline__ void stage0_rb(const RbSweep<T>& v, int nb) {
+  for (int e = threadIdx.x; e < v.nrhs * P3; e += 64 * NW) {
+    const int k = e / P3, i = e % P3;
+    v.Z[e] = i < nb ? v.X[k * v.nc + i] : T(0);
+  }
+  lsync<NW>();
+}
+
+// Forward step of plane j: z_j = W_j (r_j + t_{j-1} z_{j-1}) into X, and
+// the next plane's input r_{j+1} + t_j z_j, or on the last plane the input
+// t_{j-1} x_j of the backward sweep's first plane (x_j = z_j there).
+template <int NW, typename T>
+__device__ __forceinline__ void fwd_rb(const RbSweep<T>& v, int nb, int j, const T wr[R3]) {
+  const int r = rb_row(), c0 = rb_col(), nc = v.nc;
+  const bool last = j == v.m2 - 1;
+  const T* zin = zbuf(v, j);
+  T* zout = zbuf(v, j + 1);
+  for (int k = 0; k < v.nrhs; ++k) {
+    T y = c0 < nb ? dot16(wr, zin + k * P3 + c0) : T(0);
+    y = quad_sum(y);
+    if (c0 == 0) {
+      T zn = T(0);
+      if (r < nb) {
+        v.X[k * nc + j * nb + r] = y;
+        if (!last) zn = fma(v.Tz[j * nb + r], y, v.X[k * nc + (j + 1) * nb + r]);
+        else if (j > 0) zn = v.Tz[(j - 1) * nb + r] * y;
+      }
+      zout[k * P3 + r] = zn;
+    }
+  }
+  lsync<NW>();
+}
+
+// Backward step of plane j: x_j = z_j + W_j (t_j .* x_{j+1}) into X, and
+// the input t_{j-1} x_j of plane j - 1.
+template <int NW, typename T>
+__device__ __forceinline__ void bwd_rb(const RbSweep<T>& v, int nb, int j, const T wr[R3]) {
+  const int r = rb_row(), c0 = rb_col(), nc = v.nc;
+  const T* zin = zbuf(v, j);
+  T* zout = zbuf(v, j + 1);
+  for (int k = 0; k < v.nrhs; ++k) {
+    T y = c0 < nb ? dot16(wr, zin + k * P3 + c0) : T(0);
+    y = quad_sum(y);
+    if (c0 == 0) {
+      T zn = T(0);
+      if (r < nb) {
+        const T x = v.X[k * nc + j * nb + r] + y;
+        v.X[k * nc + j * nb + r] = x;
+        if (j > 0) zn = v.Tz[(j - 1) * nb + r] * x;
+      }
+      zout[k * P3 + r] = zn;
+    }
+  }
+  lsync<NW>();
+}
+
 // LDS of one box.
 struct Box3 {
   double* Kt;  // (m0 + 2)(m1 + 2)(m2 + 2) permeabilities, one-cell halo

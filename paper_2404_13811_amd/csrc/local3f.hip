@@ -217,41 +217,6 @@ __device__ __forceinline__ void gj3f(int nb, Gj3f& sm, float w[R3]) {
   bsync<NW>();
 }
 
-// The sweeps use a second register layout of a plane inverse, row blocks:
-// lane L of wave v holds W_j[r][16q .. 16q + 15] with r = 16v + L / 4 and
-// q = L % 4, so y_r = (W_j z)_r is a 16-term dot product per lane summed
-// over the four lanes of a quad (DPP), with no exchange between waves.
-// Each step of a sweep reads the plane's staged input vector from LDS,
-// writes y into Xf and stages the next plane's input, then meets the other
-// waves at one barrier.  Rows and columns beyond the nb x nb block hold 0.
-__device__ __forceinline__ int rb_row() { return R3 * wave3() + (lane3() >> 2); }
-__device__ __forceinline__ int rb_col() { return R3 * (lane3() & 3); }
-
-__device__ __forceinline__ float quad_sum(float p) {
-  p += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0xB1, 0xF, 0xF, false));  // quad_perm(1,0,3,2)
-  p += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0x4E, 0xF, 0xF, false));  // quad_perm(2,3,0,1)
-  return p;
-}
-
-// The lane's row-block entries of a stored inverse (nb x nb, row-major).
-__device__ __forceinline__ void load_rb(const float* Wj, int nb, float wr[R3]) {
-  const int r = rb_row(), c0 = rb_col();
-  const float* src = Wj + r * nb + c0;
-  if (r < nb && c0 + R3 <= nb && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-#pragma unroll
-    for (int ii = 0; ii < R3; ii += 4) {
-      const float4 v = *reinterpret_cast<const float4*>(src + ii);
-      wr[ii] = v.x;
-      wr[ii + 1] = v.y;
-      wr[ii + 2] = v.z;
-      wr[ii + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int ii = 0; ii < R3; ++ii) wr[ii] = (r < nb && c0 + ii < nb) ? src[ii] : 0.0f;
-  }
-}
-
 // Row blocks from the elimination layout (lane c: W[16v + ii][c]); both
 // layouts give wave v the rows 16v .. 16v + 15, so the exchange stays in
 // the wave: four rounds through a 16 x 16 staging tile T of the wave's own.
@@ -278,79 +243,10 @@ __device__ __forceinline__ void gj_to_rb(const float w[R3], float wr[R3], float*
   }
 }
 
-__device__ __forceinline__ float dot16(const float wr[R3], const float* z) {
-  float a0 = 0.0f, a1 = 0.0f;
-#pragma unroll
-  for (int ii = 0; ii < R3; ii += 4) {
-    const float4 zz = *reinterpret_cast<const float4*>(z + ii);
-    a0 = fmaf(wr[ii], zz.x, a0);
-    a1 = fmaf(wr[ii + 1], zz.y, a1);
-    a0 = fmaf(wr[ii + 2], zz.z, a0);
-    a1 = fmaf(wr[ii + 3], zz.w, a1);
-  }
-  return a0 + a1;
-}
-
-// Staged inputs of plane j: Zb + (j & 1) * nrhs * 64 (two alternating
-// buffers; a step reads one and writes the other).
-__device__ __forceinline__ float* zbuf(const Box3F& F, int j, int nrhs) { return F.Zf + (j & 1) * nrhs * P3; }
-
-// Input of plane 0 of a forward sweep from Xf (the scaled right-hand sides).
-template <int NW>
-__device__ __forceinline__ void stage0_rb(const Box3F& F, int nb, int nrhs) {
-  for (int e = threadIdx.x; e < nrhs * P3; e += 64 * NW) {
-    const int k = e / P3, i = e % P3;
-    F.Zf[e] = i < nb ? F.Xf[k * F.s.nc + i] : 0.0f;
-  }
-  lsync<NW>();
-}
-
-// Forward step of plane j: z_j = W_j (r_j + t_{j-1} z_{j-1}) into Xf, and
-// the next plane's input r_{j+1} + t_j z_j, or on the last plane the input
-// t_{j-1} x_j of the backward sweep's first plane (x_j = z_j there).
-template <int NW>
-__device__ __forceinline__ void fwd_rb(const Box3F& F, int nb, int j, int nrhs, const float wr[R3]) {
-  const int r = rb_row(), c0 = rb_col(), nc = F.s.nc, m2 = F.s.m2;
-  const bool last = j == m2 - 1;
-  const float* zin = zbuf(F, j, nrhs);
-  float* zout = zbuf(F, j + 1, nrhs);
-  for (int k = 0; k < nrhs; ++k) {
-    float y = c0 < nb ? dot16(wr, zin + k * P3 + c0) : 0.0f;
-    y = quad_sum(y);
-    if (c0 == 0 && r < P3) {
-      float zn = 0.0f;
-      if (r < nb) {
-        F.Xf[k * nc + j * nb + r] = y;
-        if (!last) zn = fmaf(F.Tzf[j * nb + r], y, F.Xf[k * nc + (j + 1) * nb + r]);
-        else if (j > 0) zn = F.Tzf[(j - 1) * nb + r] * y;
-      }
-      zout[k * P3 + r] = zn;
-    }
-  }
-  lsync<NW>();
-}
-
-// Backward step of plane j: x_j = z_j + W_j (t_j .* x_{j+1}) into Xf, and
-// the input t_{j-1} x_j of plane j - 1.
-template <int NW>
-__device__ __forceinline__ void bwd_rb(const Box3F& F, int nb, int j, int nrhs, const float wr[R3]) {
-  const int r = rb_row(), c0 = rb_col(), nc = F.s.nc;
-  const float* zin = zbuf(F, j, nrhs);
-  float* zout = zbuf(F, j + 1, nrhs);
-  for (int k = 0; k < nrhs; ++k) {
-    float y = c0 < nb ? dot16(wr, zin + k * P3 + c0) : 0.0f;
-    y = quad_sum(y);
-    if (c0 == 0 && r < P3) {
-      float zn = 0.0f;
-      if (r < nb) {
-        const float x = F.Xf[k * nc + j * nb + r] + y;
-        F.Xf[k * nc + j * nb + r] = x;
-        if (j > 0) zn = F.Tzf[(j - 1) * nb + r] * x;
-      }
-      zout[k * P3 + r] = zn;
-    }
-  }
-  lsync<NW>();
+// The row-block sweep vectors of a box in the FP32 form: the scaled work
+// vectors Xf, the scaled plane couplings Tzf and the staged inputs Zf.
+__device__ __forceinline__ RbSweep<float> rbv(const Box3F& F, int nrhs) {
+  return RbSweep<float>{F.Xf, F.Tzf, F.Zf, F.s.nc, F.s.m2, nrhs};
 }
 
 __device__ __forceinline__ void store3f(float* Wj, int nb, const float w[R3]) {
@@ -404,7 +300,7 @@ __device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F
       float wr[R3];
       gj_to_rb(w, wr, T);
       cput(wc, j, wr);
-      fwd_rb<NW>(F, nb, j, nrhs, wr);
+      fwd_rb<NW>(rbv(F, nrhs), nb, j, wr);
     }
   }
 }
@@ -417,11 +313,11 @@ __device__ __forceinline__ void backward3f(const Box3F& F, const float wc[JC][R3
   float wr[R3];
   for (int j = m2 - 2; j >= JCN; --j) {
     load_rb(Wg + (long long)j * nb * nb, nb, wr);
-    bwd_rb<NW>(F, nb, j, nrhs, wr);
+    bwd_rb<NW>(rbv(F, nrhs), nb, j, wr);
   }
 #pragma unroll
   for (int j = JCN - 1; j >= 0; --j)
-    if (j <= m2 - 2) bwd_rb<NW>(F, nb, j, nrhs, wc[j]);
+    if (j <= m2 - 2) bwd_rb<NW>(rbv(F, nrhs), nb, j, wc[j]);
 }
 
 // Forward sweep with the cached inverses (LOAD: the cache filled from the
@@ -436,19 +332,19 @@ __device__ __forceinline__ void forward3f(const Box3F& F, float wc[JC][R3], cons
   for (int j = 0; j < JCN; ++j)
     if (j < m2) {
       if (LOAD && j + 1 < JCN && j + 1 < m2) load_rb(Wg + (long long)(j + 1) * nb * nb, nb, wc[j + 1]);
-      fwd_rb<NW>(F, nb, j, nrhs, wc[j]);
+      fwd_rb<NW>(rbv(F, nrhs), nb, j, wc[j]);
     }
   float wr[R3];
   for (int j = JCN; j < m2; ++j) {
     load_rb(Wg + (long long)j * nb * nb, nb, wr);
-    fwd_rb<NW>(F, nb, j, nrhs, wr);
+    fwd_rb<NW>(rbv(F, nrhs), nb, j, wr);
   }
 }
 
 // Xf <- A^^-1 Xf with the cached inverses.
 template <int NW, int JCN = JC>
 __device__ __forceinline__ void solve3f(const Box3F& F, float wc[JC][R3], const float* Wg, int nrhs) {
-  stage0_rb<NW>(F, F.s.m0 * F.s.m1, nrhs);
+  stage0_rb<NW>(rbv(F, nrhs), F.s.m0 * F.s.m1);
   forward3f<NW, false, JCN>(F, wc, Wg, nrhs);
   backward3f<NW, JCN>(F, wc, Wg, nrhs);
 }
@@ -584,7 +480,7 @@ __device__ __forceinline__ void basis3f(const Geo& g, const Box& B, const Seed* 
   seed_rhs3<NW>(g, B, s, seeds, beta, nrhs, s.X);
   bsync<NW>();
   start3f<NW, false>(F, nrhs);
-  stage0_rb<NW>(F, s.m0 * s.m1, nrhs);
+  stage0_rb<NW>(rbv(F, nrhs), s.m0 * s.m1);
   float* Wg = fac + B.fac;
   float wc[JC][R3];
   factor3f<NW>(g, B, F, Wg, nrhs, sm, wc);
@@ -613,7 +509,7 @@ __device__ __forceinline__ void particular3f(const Geo& g, const Box& B, const d
   physical3<NW>(g, B, s, f, bcv, F.Bv);
   scale3f<NW>(F);
   start3f<NW, true>(F, 1);
-  stage0_rb<NW>(F, s.m0 * s.m1, 1);
+  stage0_rb<NW>(rbv(F, 1), s.m0 * s.m1);
   float* Wg = fac + B.fac;
   float wc[JC][R3];
   factor3f<NW>(g, B, F, Wg, 1, sm, wc);
@@ -642,7 +538,7 @@ __device__ __forceinline__ void smooth3f(const Geo& g, const Box& B, const doubl
   smooth_rhs3<NW>(g, B, s, p, gflux, beta, F.Bv);
   scale3f<NW>(F);
   start3f<NW, true>(F, 1);
-  stage0_rb<NW>(F, s.m0 * s.m1, 1);
+  stage0_rb<NW>(rbv(F, 1), s.m0 * s.m1);
   const float* Wg = fac + B.fac;
   float wc[JC][R3];
   forward3f<NW, true, JCN>(F, wc, Wg, 1);
@@ -695,11 +591,12 @@ k_particular3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ 
   if (threadIdx.x == 0 && sm.flag) atomicOr(flags, sm.flag);
 }
 
-// JCN = JC: the plane inverses read once per solve into registers (two
-// boxes per CU); JCN = 0: read from memory by every sweep, at up to four
-// boxes per CU (LDS of a c4 smoothing box about 33 KB).
+// JCN planes' inverses held in registers across the refinement sweeps, the
+// others read from memory by every sweep: JCN = JC (two boxes per CU), JC / 2
+// (three) or 0 (up to four; LDS of a c4 smoothing box about 33 KB).
 template <int NW, bool TS, int JCN>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(JCN ? 2 : 4)))
+__global__ void __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(JCN == JC ? 2 : JCN > 0 ? 3 : 4)))
 k_smooth3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ K, const double* __restrict__ f,
            const double* __restrict__ bcv, double beta, const float* __restrict__ fac, double* __restrict__ p,
            double* __restrict__ gflux, double tol, int max_refine, int* iters, unsigned long long* resid,
@@ -790,8 +687,10 @@ hipError_t launch_smooth3f(const Geo& g, const Box* boxes, int nmem, const doubl
   hipLaunchKernelGGL((k_smooth3f<NW, TS, JCN>), dim3(nmem), dim3(64 * NW), lds, s, g, boxes, K, f, bcv,     \
                      beta, fac32, p, gflux, tol, max_refine, iters, resid, flags)
 #define MRCM_CALL(NW, TS)          \
-  if (cached) {                    \
+  if (cached >= JC) {              \
     MRCM_CALL1(NW, TS, JC);        \
+  } else if (cached > 0) {         \
+    MRCM_CALL1(NW, TS, JC / 2);    \
   } else {                         \
     MRCM_CALL1(NW, TS, 0);         \
   }

@@ -214,8 +214,9 @@ hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double
 // solve to the componentwise backward error tol (at most max_refine + 1
 // FP32 solves; the most taken and the largest final error to iters and
 // resid).  LDS bytes of a box with nrhs solutions and nbv FP64 right-hand
-// sides stored.  Smoothing: cached = 1 holds a box's plane inverses in
-// registers across its refinement sweeps, 0 reads them for every sweep.
+// sides stored.  Smoothing: a box holds the inverses of its first `cached`
+// planes (8, 4 or 0) in registers across its refinement sweeps and reads
+// the others for every sweep.
 size_t box3f_lds_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc);
 hipError_t launch_basis3f(const Geo& g, const Box* boxes, int nbox, const Seed* seeds, const double* logK,
                           double beta, float* fac32, double* Pk, double* tr_u, double* tr_phi,
