@@ -5,7 +5,9 @@ relative L2 error of flux and pressure within 1e-6 (the precision form's
 bound).  Covers the layered Gaussian-field recipe at reduced and at full
 size, linear interface spaces, a smoothing Robin parameter that differs
 from the basis one (Step 6), a diagonal permeability tensor, boxes of more
-planes than the kernels hold in registers, and the no-convergence report."""
+planes than the kernels hold in registers, plane sizes for one, two and
+four waves per box (aligned and unaligned rows), no oversampling, and the
+no-convergence report."""
 import os
 
 import numpy as np
@@ -107,3 +109,13 @@ def test_fp32_refine_3d_reports_no_convergence():
     wl = make_workload("c4", scale=8)
     with pytest.raises(RuntimeError, match="MRCM_ENOCONV"):
         gpu_solve(wl, precision="fp32_refine", tol=1e-15, max_refine=0)
+
+
+@pytest.mark.parametrize("sub,overlap", [((4, 7, 4), 1), ((4, 7, 4), 0), ((4, 4, 4), 0), ((2, 7, 8), 1)])
+def test_fp32_refine_3d_box_shapes(sub, overlap):
+    # planes of 54, 45, 40 cells (rows of the stored inverses not 16-byte
+    # aligned), of 28 (two waves per box) and 16 (one wave), no oversampling
+    # (smoothing data from the neighbours' Gamma fluxes), and boxes whose
+    # oversampling is truncated on both sides of an axis
+    wl = make_workload("c4", scale=8).with_(sub=sub, overlap=overlap, nsmooth=2)
+    _check32(wl)
