@@ -58,9 +58,9 @@ TRAFFIC = {
                                              518490.8, 2727.0),
     ("k_basis3f", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "6ea390ab5f666eab",
                                              68058.3, 2300751.0),
-    # the variant the autotuner picks on this workload: four planes' inverses
-    # held in registers, the other four read by every sweep
-    ("k_smooth3f", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "6ea390ab5f666eab",
+    # the variant with four planes' inverses held in registers (the other
+    # four read by every sweep), which the autotuner picks on this workload
+    ("k_smooth3f<4>", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "6ea390ab5f666eab",
                                               219638.0, 2867.0),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
@@ -415,7 +415,7 @@ def smoothing_roofline(wl, form, phases, st):
         stored += nblk * blk * word * solves
     kern = "k_smooth32" if form == "fp32_refine" else "k_smooth_w"
     if wl.dim == 3:
-        kern = "k_smooth3f" if form == "fp32_refine" else "k_smooth3"
+        kern = "k_smooth3f<%d>" % st["smooth_cached"] if form == "fp32_refine" else "k_smooth3"
     elif st["smooth_persistent"]:
         kern = "k_smooth_grid"
     return {"kernel": kern, "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
