@@ -12,13 +12,16 @@
 // per box, lane c of wave v holding rows 16v .. 16v + 15 of column c of the
 // padded 64 x 64 plane block, here in FP32; the block LDL^T recurrence
 // S_j = D_j - t_{j-1} W_{j-1} t_{j-1} with W_j = S_j^{-1} formed in place by
-// four-pivot Gauss-Jordan elimination with look-ahead.  What the FP32 form
-// adds: the inverses of the first JC = 8 planes (16 registers each per
-// lane, 128 in all) stay in registers once formed or read, so the back
-// substitution and every refinement sweep read no factor from memory, and
-// a smoothing box reads its stored FP32 inverses once per solve however
-// many refinement sweeps it takes.  Planes beyond the eighth are read back
-// from the stored inverses (nb x nb, row-major FP32).
+// four-pivot Gauss-Jordan elimination with look-ahead.  The sweeps run on
+// row blocks of the inverses (local3_common.h: one quad-reduced dot
+// product per lane, one barrier per plane step).  What the FP32 form adds:
+// the basis kernel converts each new inverse to row blocks within its wave
+// and holds the first JC = 8 planes' (16 registers each per lane, 128 in
+// all), so the back substitution and every refinement sweep read no factor
+// from memory; a smoothing box holds 8, 4 or 0 planes' inverses (the
+// autotuner's choice) across its refinement sweeps and reads the others in
+// every sweep.  Inverses not held are read from the stored ones (nb x nb,
+// row-major FP32).
 #include "local3_common.h"
 #include "pivot4.h"
 
