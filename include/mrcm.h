@@ -135,8 +135,8 @@ typedef struct {
                               state; above the check tolerance (default 1e-5,
                               mrcm_set_interface_check) the solve raises
                               MRCM_ESINGULAR.  0 if no interface.            */
-  int smooth_cached;       /* 3-D boxes in the FP32 form: the planes (8, 4 or
-                              0) whose inverses a smoothing box holds in
+  int smooth_cached;       /* 3-D boxes in the FP32 form: the planes (8, 4, 2
+                              or 0) whose inverses a smoothing box holds in
                               registers across its refinement sweeps; the
                               others are read from memory by every sweep
                               (the fastest variant, timed by the autotuner)   */

@@ -141,7 +141,7 @@ struct mrcm_ctx {
   // chosen value, and the captured sweep graph
   int smooth_nt_req = 0, smooth_nt = 0;
   // 3-D FP32 smoothing: planes whose inverses a box holds in registers
-  // across its refinement sweeps (8, 4 or 0), chosen by the autotuner
+  // across its refinement sweeps (8, 4, 2 or 0), chosen by the autotuner
   int smooth_cached = 8;
   bool use_graph = true;
   // one cooperative launch per mrcm_smooth call (FP64 wave kernels), with
@@ -1432,7 +1432,7 @@ mrcm_status tune_smoothing(mrcm_ctx* c, hipStream_t s) {
   HIPCHK(c, hipEventRecord(c->ev[10], s));
   float best = 0.f;
   int best_nt = 256, best_var = 8;
-  const std::vector<int> cand = f3 ? std::vector<int>{8, 4, 0} : std::vector<int>{64, 128, 256};
+  const std::vector<int> cand = f3 ? std::vector<int>{8, 4, 2, 0} : std::vector<int>{64, 128, 256};
   for (int v : cand) {
     const int nt = f3 ? 256 : v;
     if (f3) c->smooth_cached = v;

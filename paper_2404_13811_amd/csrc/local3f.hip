@@ -595,11 +595,11 @@ k_particular3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ 
 }
 
 // JCN planes' inverses held in registers across the refinement sweeps, the
-// others read from memory by every sweep: JCN = JC (two boxes per CU), JC / 2
-// (three) or 0 (up to four; LDS of a c4 smoothing box about 33 KB).
+// others read from memory by every sweep: JCN = 8 (two boxes per CU), 4
+// (three), 2 or 0 (four; LDS of a c4 smoothing box about 33 KB).
 template <int NW, bool TS, int JCN>
 __global__ void __launch_bounds__(64 * NW)
-__attribute__((amdgpu_waves_per_eu(JCN == JC ? 2 : JCN > 0 ? 3 : 4)))
+__attribute__((amdgpu_waves_per_eu(JCN == JC ? 2 : JCN > 2 ? 3 : 4)))
 k_smooth3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ K, const double* __restrict__ f,
            const double* __restrict__ bcv, double beta, const float* __restrict__ fac, double* __restrict__ p,
            double* __restrict__ gflux, double tol, int max_refine, int* iters, unsigned long long* resid,
@@ -692,8 +692,10 @@ hipError_t launch_smooth3f(const Geo& g, const Box* boxes, int nmem, const doubl
 #define MRCM_CALL(NW, TS)          \
   if (cached >= JC) {              \
     MRCM_CALL1(NW, TS, JC);        \
+  } else if (cached >= 4) {        \
+    MRCM_CALL1(NW, TS, 4);         \
   } else if (cached > 0) {         \
-    MRCM_CALL1(NW, TS, JC / 2);    \
+    MRCM_CALL1(NW, TS, 2);         \
   } else {                         \
     MRCM_CALL1(NW, TS, 0);         \
   }

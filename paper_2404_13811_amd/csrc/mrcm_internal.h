@@ -215,7 +215,7 @@ hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double
 // FP32 solves; the most taken and the largest final error to iters and
 // resid).  LDS bytes of a box with nrhs solutions and nbv FP64 right-hand
 // sides stored.  Smoothing: a box holds the inverses of its first `cached`
-// planes (8, 4 or 0) in registers across its refinement sweeps and reads
+// planes (8, 4, 2 or 0) in registers across its refinement sweeps and reads
 // the others for every sweep.
 size_t box3f_lds_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc);
 hipError_t launch_basis3f(const Geo& g, const Box* boxes, int nbox, const Seed* seeds, const double* logK,
