@@ -75,7 +75,9 @@ typedef enum { MRCM_BETA_ALPHA = 0, MRCM_BETA_CONST = 1 } mrcm_beta_mode;
  * iterative refinement with the residual r = b - A x evaluated from K in
  * FP64 until the componentwise backward error max_c |r_c| / (|A||x| + |b|)_c
  * is <= tol (at most max_refine corrections; MRCM_ENOCONV otherwise).
- * Available for 2-D boxes whose lines have at most 32 cells. */
+ * Available for 2-D boxes whose lines have at most 32 cells and for 3-D
+ * boxes whose planes have at most 64 cells (otherwise mrcm_build_basis
+ * returns MRCM_EINVAL). */
 typedef enum { MRCM_FP64 = 0, MRCM_FP32_REFINE = 1 } mrcm_precision;
 
 typedef enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 } mrcm_bc_type;
@@ -270,7 +272,10 @@ mrcm_status mrcm_smooth(mrcm_ctx* ctx, int nsteps);
  * oversampled box, or 0 (default) to time the three on one sweep over a copy
  * of the current state and keep the fastest (done once per configuration,
  * outside the timed region of mrcm_smooth).  The choice does not change the
- * results.  Errors: MRCM_EINVAL. */
+ * results.  3-D boxes take one to four waves by their plane size and ignore
+ * threads_per_box; in the FP32 form the autotuner instead times how many
+ * planes' inverses a box holds in registers (mrcm_stats.smooth_cached).
+ * Errors: MRCM_EINVAL. */
 mrcm_status mrcm_set_smoothing(mrcm_ctx* ctx, int use_graph, int threads_per_box);
 
 /* Persistent form of the smoothing sweeps (Steps 6-7, Algorithm 1's loop
