@@ -553,7 +553,8 @@ __device__ __forceinline__ void smooth3f(const Geo& g, const Box& B, const doubl
   smooth_out3<NW>(g, B, s, p, gflux, beta);
 }
 
-// Two boxes per CU (LDS of a c4 basis box about 61 KB): up to 256
+// Two boxes per CU (LDS of an 8 x 8 x 8 basis box with six seeds about
+// 66 KB with its pivot buffers): up to 256
 // registers per lane, the 128 of the plane cache among them.
 template <int NW, bool TS>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
@@ -596,7 +597,7 @@ k_particular3f(Geo g, const Box* __restrict__ boxes, const double* __restrict__ 
 
 // JCN planes' inverses held in registers across the refinement sweeps, the
 // others read from memory by every sweep: JCN = 8 (two boxes per CU), 4
-// (three), 2 or 0 (four; LDS of a c4 smoothing box about 33 KB).
+// (three), 2 or 0 (four; LDS of an 8 x 8 x 8 smoothing box about 33 KB).
 template <int NW, bool TS, int JCN>
 __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(JCN == JC ? 2 : JCN > 2 ? 3 : 4)))
