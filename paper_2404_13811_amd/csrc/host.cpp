@@ -711,7 +711,8 @@ mrcm_status make_plan(mrcm_ctx* c) {
     c->lds3_smooth = std::max(c->lds3_smooth, box3_lds_bytes(m[0], m[1], m[2], 1, kc));
     c->lds3_part = std::max(c->lds3_part, box3_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1],
                                                          P.hi[2] - P.lo[2], 1, kc));
-    c->lds3f_basis = std::max(c->lds3f_basis, box3f_lds_bytes(m[0], m[1], m[2], std::max(B.nrhs, 1), 0, kc));
+    c->lds3f_basis = std::max(c->lds3f_basis, box3f_lds_bytes(m[0], m[1], m[2],
+                                                              std::min(std::max(B.nrhs, 1), kSeedBatch3f), 0, kc));
     c->lds3f_smooth = std::max(c->lds3f_smooth, box3f_lds_bytes(m[0], m[1], m[2], 1, 1, kc));
     c->lds3f_part = std::max(c->lds3f_part, box3f_lds_bytes(P.hi[0] - P.lo[0], P.hi[1] - P.lo[1],
                                                             P.hi[2] - P.lo[2], 1, 1, kc));

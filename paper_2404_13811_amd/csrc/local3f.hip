@@ -28,7 +28,8 @@
 namespace mrcm {
 namespace {
 
-constexpr int JC = 8;  // plane inverses held in registers
+constexpr int JC = 8;   // plane inverses held in registers (most)
+constexpr int JCB = 2;  // those the basis kernel holds (three boxes per CU)
 
 // Pivot data of one elimination step (two alternating buffers), as Gj3 of
 // the FP64 kernels in FP32; vb and rs (1024 floats) also hold the per-wave
@@ -474,26 +475,39 @@ __device__ __forceinline__ void basis3f(const Geo& g, const Box& B, const Seed* 
                                         double* dsm, Gj3f& sm) {
   constexpr int NT = 64 * NW;
   const int nrhs = FO ? 0 : B.nrhs;
-  Box3F F = carve3f<TS>(dsm, B, nrhs, 0, g.kc);
+  // the seeds in batches of at most kSeedBatch3f (the LDS of one batch's
+  // FP64 solutions and FP32 work vectors), after the factor
+  const int nbat = nrhs < kSeedBatch3f ? nrhs : kSeedBatch3f;
+  Box3F F = carve3f<TS>(dsm, B, nbat, 0, g.kc);
   Box3& s = F.s;
   load_box3<NW, true>(g, B, logK, beta, s);
   scale3f<NW>(F);
-  for (int e = threadIdx.x; e < nrhs * s.nc; e += NT) s.X[e] = 0.0;
-  bsync<NW>();
-  seed_rhs3<NW>(g, B, s, seeds, beta, nrhs, s.X);
-  bsync<NW>();
-  start3f<NW, false>(F, nrhs);
-  stage0_rb<NW>(rbv(F, nrhs), s.m0 * s.m1);
   float* Wg = fac + B.fac;
   float wc[JC][R3];
-  factor3f<NW>(g, B, F, Wg, nrhs, sm, wc);
+  factor3f<NW>(g, B, F, Wg, 0, sm, wc);
   if (FO) return;
-  backward3f<NW>(F, wc, Wg, nrhs);
-  update3f<NW>(F, nrhs);
-  double omega;
-  const int it = refine3f<NW>(g, B, F, Wg, seeds, beta, nrhs, tol, max_refine, sm, wc, omega);
-  record3f(it, omega, iters, resid);
-  basis_out3<NW>(g, B, s, seeds, beta, nrhs, Pk, tr_u, tr_phi, tr_beta);
+  // the first JCB planes' inverses as row blocks in registers
+  const int nb = s.m0 * s.m1;
+#pragma unroll
+  for (int j = 0; j < JCB; ++j)
+    if (j < s.m2) load_rb(Wg + (long long)j * nb * nb, nb, wc[j]);
+  for (int b0 = 0; b0 < nrhs; b0 += kSeedBatch3f) {
+    const int nr = min(kSeedBatch3f, nrhs - b0);
+    Box Bb = B;  // seeds b0 .. b0 + nr - 1
+    Bb.seed0 += b0;
+    for (int e = threadIdx.x; e < nr * s.nc; e += NT) s.X[e] = 0.0;
+    bsync<NW>();
+    seed_rhs3<NW>(g, Bb, s, seeds, beta, nr, s.X);
+    bsync<NW>();
+    start3f<NW, false>(F, nr);
+    solve3f<NW, JCB>(F, wc, Wg, nr);
+    update3f<NW>(F, nr);
+    double omega;
+    const int it = refine3f<NW, JCB>(g, Bb, F, Wg, seeds, beta, nr, tol, max_refine, sm, wc, omega);
+    record3f(it, omega, iters, resid);
+    basis_out3<NW>(g, Bb, s, seeds, beta, nr, Pk, tr_u, tr_phi, tr_beta);
+    bsync<NW>();  // X is read by the outputs before the next batch clears it
+  }
 }
 
 // Step 4 on a subdomain; writes K = exp(log K) of its cells.
@@ -553,11 +567,10 @@ __device__ __forceinline__ void smooth3f(const Geo& g, const Box& B, const doubl
   smooth_out3<NW>(g, B, s, p, gflux, beta);
 }
 
-// Two boxes per CU (LDS of an 8 x 8 x 8 basis box with six seeds about
-// 66 KB with its pivot buffers): up to 256
-// registers per lane, the 128 of the plane cache among them.
+// Three boxes per CU (LDS of an 8 x 8 x 8 basis box with a batch of three
+// seeds about 48 KB with its pivot buffers): up to 168 registers per lane.
 template <int NW, bool TS>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)))
 k_basis3f(Geo g, const Box* __restrict__ boxes, const Seed* __restrict__ seeds, const double* __restrict__ logK,
           double beta, float* __restrict__ fac, double* __restrict__ Pk, double* __restrict__ tr_u,
           double* __restrict__ tr_phi, double* __restrict__ tr_beta, int factor_only, double tol,

@@ -218,6 +218,8 @@ hipError_t launch_smooth3(const Geo& g, const Box* boxes, int nmem, const double
 // planes (8, 4, 2 or 0) in registers across its refinement sweeps and reads
 // the others for every sweep.
 size_t box3f_lds_bytes(int m0, int m1, int m2, int nrhs, int nbv, int kc);
+// seeds an FP32 basis box solves at a time (after its factor)
+constexpr int kSeedBatch3f = 3;
 hipError_t launch_basis3f(const Geo& g, const Box* boxes, int nbox, const Seed* seeds, const double* logK,
                           double beta, float* fac32, double* Pk, double* tr_u, double* tr_phi,
                           double* tr_beta, int factor_only, double tol, int max_refine, int* iters,
