@@ -268,24 +268,26 @@ __device__ __forceinline__ void store3f(float* Wj, int nb, const float w[R3]) {
 // its slot by selects (a conditional store per slot would be merged into a
 // store through a selected address, which keeps the cache in scratch
 // memory).
+template <int JCN>
 __device__ __forceinline__ void cclear(float wc[JC][R3]) {
 #pragma unroll
-  for (int jj = 0; jj < JC; ++jj)
+  for (int jj = 0; jj < JCN; ++jj)
 #pragma unroll
     for (int ii = 0; ii < R3; ++ii) wc[jj][ii] = 0.0f;
 }
 
+template <int JCN>
 __device__ __forceinline__ void cput(float wc[JC][R3], int j, const float w[R3]) {
 #pragma unroll
-  for (int jj = 0; jj < JC; ++jj)
+  for (int jj = 0; jj < JCN; ++jj)
 #pragma unroll
     for (int ii = 0; ii < R3; ++ii) wc[jj][ii] = jj == j ? w[ii] : wc[jj][ii];
 }
 
 // Factor of the box fused with the forward sweep of the nrhs scaled
 // right-hand sides in Xf (plane 0's input staged); inverses to Wg and, as
-// row blocks, to the register cache.
-template <int NW>
+// row blocks, those of the first JCN planes to the register cache.
+template <int NW, int JCN>
 __device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F& F, float* Wg, int nrhs,
                                          Gj3f& sm, float wc[JC][R3]) {
   const int nb = F.s.m0 * F.s.m1;
@@ -293,7 +295,7 @@ __device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F
   float w[R3];
 #pragma unroll
   for (int i = 0; i < R3; ++i) w[i] = 0.0f;
-  cclear(wc);
+  cclear<JCN>(wc);
   for (int j = 0; j < F.s.m2; ++j) {
     build3f(g, B, F, j, w);
     gj3f<NW>(nb, sm, w);
@@ -303,7 +305,7 @@ __device__ __forceinline__ void factor3f(const Geo& g, const Box& B, const Box3F
       // which starts after the forward step's barrier
       float wr[R3];
       gj_to_rb(w, wr, T);
-      cput(wc, j, wr);
+      cput<JCN>(wc, j, wr);
       fwd_rb<NW>(rbv(F, nrhs), nb, j, wr);
     }
   }
@@ -484,9 +486,13 @@ __device__ __forceinline__ void basis3f(const Geo& g, const Box& B, const Seed* 
   scale3f<NW>(F);
   float* Wg = fac + B.fac;
   float wc[JC][R3];
-  factor3f<NW>(g, B, F, Wg, 0, sm, wc);
+  factor3f<NW, 0>(g, B, F, Wg, 0, sm, wc);
   if (FO) return;
-  // the first JCB planes' inverses as row blocks in registers
+  // the first JCB planes' inverses as row blocks in registers (a forward
+  // sweep fused with the factor needs more registers than three boxes per
+  // CU leave, and was slower); the barrier orders the last plane's stores
+  // before the reads of other waves
+  bsync<NW>();
   const int nb = s.m0 * s.m1;
 #pragma unroll
   for (int j = 0; j < JCB; ++j)
@@ -528,12 +534,12 @@ __device__ __forceinline__ void particular3f(const Geo& g, const Box& B, const d
   start3f<NW, true>(F, 1);
   stage0_rb<NW>(rbv(F, 1), s.m0 * s.m1);
   float* Wg = fac + B.fac;
-  float wc[JC][R3];
-  factor3f<NW>(g, B, F, Wg, 1, sm, wc);
-  backward3f<NW>(F, wc, Wg, 1);
+  float wc[JC][R3];  // not used: a subdomain's few small planes are read back
+  factor3f<NW, 0>(g, B, F, Wg, 1, sm, wc);
+  backward3f<NW, 0>(F, wc, Wg, 1);
   update3f<NW>(F, 1);
   double omega;
-  const int it = refine3f<NW>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
+  const int it = refine3f<NW, 0>(g, B, F, Wg, nullptr, beta, 1, tol, max_refine, sm, wc, omega);
   record3f(it, omega, iters, resid);
   part_out3<NW>(g, B, s, beta, pbar, ubar, pibar);
 }
