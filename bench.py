@@ -52,16 +52,16 @@ GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_full_samples.npz")
 # value it was taken with; otherwise the traffic is reported as null.
 TRAFFIC = {
     # (kernel, workload key): (source files, sha256 prefix, fetch KiB, write KiB)
-    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip", "local3_common.h"), "2f2631aab327e556",
-                                            1886502.6, 4380710.0),
-    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip", "local3_common.h"), "2f2631aab327e556",
-                                             518490.8, 2727.0),
-    ("k_basis3f", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "c253c5016f97c1a0",
-                                             68598.0, 2300751.0),
+    ("k_basis3", "c4:64x224x80:l2:const"): (("local3.hip", "local3_common.h"), "b3b558db75c0f9cc",
+                                            1886612.6, 4380710.0),
+    ("k_smooth3", "c4:64x224x80:l2:const"): (("local3.hip", "local3_common.h"), "b3b558db75c0f9cc",
+                                             518853.0, 2727.0),
+    ("k_basis3f", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "69366ae71dae8439",
+                                             2898127.0, 2314650.4),
     # the variant with two planes' inverses held in registers (the others
     # read by every sweep), which the autotuner picks on this workload
-    ("k_smooth3f<2>", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "c253c5016f97c1a0",
-                                                 343020.0, 2867.0),
+    ("k_smooth3f<2>", "c4:64x224x80:l2:const"): (("local3f.hip", "local3_common.h"), "69366ae71dae8439",
+                                                 342802.5, 2867.0),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COMMON_SOURCES = ("wave_common.h", "local_common.h", "mrcm_internal.h", "pivot4.h")
