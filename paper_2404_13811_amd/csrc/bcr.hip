@@ -35,20 +35,22 @@ namespace {
 // which equals four scalar pivot steps.  Thread 16 tr + tc holds tile
 // (tr, tc), so a tile row is one row of 16 lanes of a wave.  The pivot rows
 // of a step are one tile row and the pivot columns half a tile column.  One
-// step:
-//   1. the owners of rows K publish them to LDS (barrier);
-//   2. threads t < n factor the 4 x 4 block P (closed form, no exchange)
-//      and form column t of R = P^{-1} A~[K][:], where A~ has unit vectors
-//      in the columns K (barrier);
-//   3. every thread applies the rank-4 update A[i][j] <- A[i][j] -
+// step, with R = P^{-1} A~[K][:] (A~ with unit vectors in the columns K)
+// already in LDS:
+//   1. every thread applies the rank-4 update A[i][j] <- A[i][j] -
 //      A[i][K] R[:, j] to its tile (zero base in the columns K) and the
 //      owners of rows K take R.  A[i][K] of a tile row is held by one lane
 //      of the same 16-lane row (the owner of the pivot columns), and row
-//      broadcasts hand it to the other 15: the columns never go through LDS.
-// The LDS buffers alternate between steps, so two barriers per four
-// pivots.  R is stored in 16-byte pieces interleaved over the tile columns
-// so that the update reads are free of bank conflicts.  Two waves per SIMD
-// hide each other's LDS latency.
+//      broadcasts hand it to the other 15: the columns never go through LDS;
+//   2. look-ahead: the wave that holds the next step's pivot rows runs its
+//      update at raised priority, publishes those rows to LDS, factors the
+//      next 4 x 4 pivot block (closed form, redundantly in every lane) and
+//      forms the next R, two columns per lane, while the other waves are
+//      still updating;
+//   3. one barrier.
+// R alternates between two LDS buffers.  It is stored in 16-byte pieces
+// interleaved over the tile columns so that the update reads are free of
+// bank conflicts.  Two waves per SIMD hide each other's LDS latency.
 constexpr int TR = 4, TC = 8, PB = 4;  // tile rows / columns; pivots per step
 constexpr int kInvThreads = 512;
 
@@ -81,11 +83,61 @@ __device__ __forceinline__ void bcast_cols(int kt, const double w[TR][TC], doubl
   }
 }
 
+// R = P^{-1} A~[K][:] of step st (pivots K = 4 st .. 4 st + 3, A~ with
+// unit vectors in the columns K), formed by the one wave that holds the
+// pivot rows (tile row st): its 16 lanes of that tile row publish the rows
+// to rp, then every lane of the wave forms two columns of R into rq (the
+// interleaved pieces the update reads).  Returns whether the pivot block
+// is unusable (zero, infinite or NaN pivot).
+__device__ __forceinline__ bool form_r(int st, int t, int tr, int bp, int ntc, int c0,
+                                       const double w[TR][TC], double* rp, double* rq) {
+  if (tr == st) {
+#pragma unroll
+    for (int m = 0; m < PB; ++m) {
+      double2* d = reinterpret_cast<double2*>(rp + m * kBcrInvMax + c0);
+#pragma unroll
+      for (int jj = 0; jj < TC / 2; ++jj) d[jj] = make_double2(w[m][2 * jj], w[m][2 * jj + 1]);
+    }
+  }
+  // the rows are read by other lanes of the same wave: LDS stores complete
+  // before the loads below
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  const int k = st * PB;
+  double P[PB][PB];
+#pragma unroll
+  for (int m = 0; m < PB; ++m)
+#pragma unroll
+    for (int j = 0; j < PB; ++j) P[m][j] = rp[m * kBcrInvMax + k + j];
+  const PivBlock<double> q = piv_block(P);
+  const bool bad = !(piv_usable(q.d0) && piv_usable(q.da) && piv_usable(q.s0) && piv_usable(q.ds));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = (t & 63) + 64 * h;
+    if (col < bp) {
+      const int ck = col - k;
+      const bool pc = ck >= 0 && ck < PB;
+      double r[PB], v[PB];
+      // unit vector in the pivot columns, formed arithmetically (a select
+      // on a load becomes a branch with its own LDS wait)
+#pragma unroll
+      for (int m = 0; m < PB; ++m)
+        r[m] = fma(rp[m * kBcrInvMax + col], pc ? 0.0 : 1.0, (pc && ck == m) ? 1.0 : 0.0);
+      piv_apply(q, r, v);
+      const int tq = col / TC, jj = (col % TC) / 2, e = col & 1;
+#pragma unroll
+      for (int m = 0; m < PB; ++m) rq[((m * (TC / 2) + jj) * ntc + tq) * 2 + e] = v[m];
+    }
+  }
+  return bad;
+}
+
 __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ pool,
                                                          const long long* __restrict__ offs,
                                                          const int* __restrict__ npiv, int bp,
                                                          int ld, int* flags) {
-  __shared__ __align__(16) double rpan[2][PB * kBcrInvMax];  // [m][col] = A[k + m][col]
+  __shared__ __align__(16) double rpan[PB * kBcrInvMax];     // [m][col] = A[k + m][col]
   __shared__ __align__(16) double rpp[2][PB * kBcrInvMax];   // R, interleaved pieces
   double* A = pool + offs[blockIdx.x];
   const int ntr = bp / TR, ntc = bp / TC;  // tiles per column / per row
@@ -110,57 +162,31 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
       }
     }
   }
-  bool bad = false;
   // pivots beyond the block's own size act on identity padding, which
   // they leave unchanged: skipped
   const int kend = npiv[blockIdx.x];
+  const int nstep = (kend + PB - 1) / PB;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // holds tile rows 4 wv .. 4 wv + 3
+  bool bad = false;
+  if (nstep > 0 && wv == 0) bad |= form_r(0, t, tr, bp, ntc, c0, w, rpan, rpp[0]);
+  __syncthreads();
   for (int kt = 0; kt * TC < kend; ++kt) {
     const bool own_c = tc == kt;
 #pragma unroll
     for (int k2 = 0; k2 < TC; k2 += PB) {
-      const int k = kt * TC + k2;
-      if (k >= kend) break;
-      const bool own_r = tr == k / TR;
-      double* rp = rpan[k2 / PB];
-      double* rq = rpp[k2 / PB];
-      if (own_r) {
-#pragma unroll
-        for (int m = 0; m < PB; ++m) {
-          double2* d = reinterpret_cast<double2*>(rp + m * kBcrInvMax + c0);
-#pragma unroll
-          for (int jj = 0; jj < TC / 2; ++jj) d[jj] = make_double2(w[m][2 * jj], w[m][2 * jj + 1]);
-        }
-      }
-      __syncthreads();
-      if (t < bp) {
-        double P[PB][PB];
-#pragma unroll
-        for (int m = 0; m < PB; ++m)
-#pragma unroll
-          for (int j = 0; j < PB; ++j) P[m][j] = rp[m * kBcrInvMax + k + j];
-        const PivBlock<double> q = piv_block(P);
-        // a zero, infinite or NaN pivot: the elimination has broken down
-        bad |= !(piv_usable(q.d0) && piv_usable(q.da) && piv_usable(q.s0) && piv_usable(q.ds));
-        const int ck = t - k;
-        const bool pc = ck >= 0 && ck < PB;
-        double r[PB], v[PB];
-        // unit vector in the pivot columns, formed arithmetically (a select
-        // on a load becomes a branch with its own LDS wait)
-#pragma unroll
-        for (int m = 0; m < PB; ++m)
-          r[m] = fma(rp[m * kBcrInvMax + t], pc ? 0.0 : 1.0, (pc && ck == m) ? 1.0 : 0.0);
-        piv_apply(q, r, v);
-        const int tq = t / TC, jj = (t % TC) / 2, e = t & 1;
-#pragma unroll
-        for (int m = 0; m < PB; ++m) rq[((m * (TC / 2) + jj) * ntc + tq) * 2 + e] = v[m];
-      }
-      __syncthreads();
+      const int st = kt * (TC / PB) + k2 / PB;  // step: pivots 4 st .. 4 st + 3
+      if (st >= nstep) break;
+      const bool own_r = tr == st;
+      // the wave that holds the next step's pivot rows updates first, then
+      // forms that step's R while the other waves finish this update
+      const bool ahead = st + 1 < nstep && wv == (st + 1) / (64 / 16);
+      if (ahead) __builtin_amdgcn_s_setprio(2);
       {
         // every lane takes part in the row broadcasts
         double rv[PB][TC], cv[TR][PB];
         if (k2 == 0) bcast_cols<0>(kt, w, cv);
         else bcast_cols<PB>(kt, w, cv);
-        const double2* q2 = reinterpret_cast<const double2*>(rq);
+        const double2* q2 = reinterpret_cast<const double2*>(rpp[st & 1]);
 #pragma unroll
         for (int m = 0; m < PB; ++m)
 #pragma unroll
@@ -191,6 +217,11 @@ __global__ void __launch_bounds__(kInvThreads) k_bcr_inv(double* __restrict__ po
             for (int j = 0; j < TC; ++j) w[m][j] = rv[m][j];
         }
       }
+      if (ahead) {
+        bad |= form_r(st + 1, t, tr, bp, ntc, c0, w, rpan, rpp[(st + 1) & 1]);
+        __builtin_amdgcn_s_setprio(0);
+      }
+      __syncthreads();
     }
   }
   if (act) {

@@ -161,12 +161,18 @@ def test_batch_adjoint_equals_the_members_adjoints(precision):
             return dJdp, fw.reshape(-1)
         return dJ
 
+    # FP64: the same arithmetic in both; FP32 + refinement: every box solve
+    # stops once its componentwise backward error is below 1e-12, so a
+    # rounding-level difference upstream can cost or save one refinement
+    # step of a box, which the interface system's conditioning carries into
+    # the gradient above the rounding level
+    bound = 1e-12 if precision == "fp64" else 1e-10
     _, _, gs, _ = solve_batch(wls, precision, dJ=dJ_for(4))
     for k, wl in enumerate(wls):
         _, _, g1 = solve_one(wl, precision, dJ=dJ_for(1))
         e = _rel(gs[k], g1)
         print("  member %d: gradient rel difference %.2e" % (k, e), flush=True)
-        assert e <= 1e-12
+        assert e <= bound
 
 
 def test_batch_refusals():
